@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This package builds block-banded Markov generators and start vectors.  It holds
+none of the staircase method's arithmetic: only random draws, masks, and the
+generator's defining convention that each row of Q sums to zero.
+"""
+from .chains import (  # noqa: F401
+    BlockGenerator,
+    qbd,
+    banded,
+    birth_death,
+    planted_reversible,
+    served_stream,
+    positive_start,
+    config_seed,
+)
