@@ -1,0 +1,187 @@
+"""Benchmark: HBM GB/s per staircase sweep on one MI355X.
+
+Workload (default): level-dependent QBD generator, 4096 levels x block size 64
+(N = 262144), FP64, stair type 1, synthetic seeded rates.  A step is one
+sweep of Algorithm 2 (phase A + phase B + normalisation and change), run on
+the device-resident iterate.  value = algorithmic bytes of one sweep / mean
+sweep time.
+
+Prints one JSON line.  Options:
+  --gpus N        only 1 is supported (one GPU per run)
+  --steps K       timed sweeps (default 200)
+  --warmup W      untimed sweeps first (default 20)
+  --no-cpu        skip the CPU oracle baseline
+  --ttr           also time the solve to ||Q^T pi||_1 <= 1e-12, FP64 vs mixed
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("stc_kernels.hip", "stc_runtime.cpp", "stc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2302_07551_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per phase-A launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    entry = rec.get(workload)
+    if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_baseline(gen, budget_s: float = 12.0):
+    """The oracle's C/OpenMP Algorithm 2 sweep on the host cores (FP64)."""
+    import numpy as np
+    from oracle import csweep
+    threads = len(os.sched_getaffinity(0))
+    cs = csweep.CSweep(gen.blocks, gen.sizes, gen.b, 1, threads=threads)
+    x = np.full((gen.L, gen.m), 1.0 / gen.N)
+    z = np.empty_like(x)
+    for _ in range(2):
+        cs.sweep(x, z)
+        x, z = z, x
+    n, t0 = 0, time.perf_counter()
+    while True:
+        cs.sweep(x, z)
+        x, z = z, x
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 2000:
+            break
+    return el / n, n, cs.threads
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ttr", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+
+    torch.cuda.set_device(0)
+    L, m = 4096, 64
+    workload = f"qbd_L{L}_m{m}_fp64"
+    t0 = time.perf_counter()
+    gen = synth.qbd(L, m, synth.config_seed(1))
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    solver = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64", stair_type=1)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"# generated in {t_gen:.1f}s, setup in {t_setup:.2f}s, arena "
+          f"{solver.footprint / 2**20:.0f} MiB", file=sys.stderr, flush=True)
+
+    solver.load(None)
+    solver.sweeps(args.warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.sweeps(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+
+    # per-launch device times of the two phase kernels (HIP events on the
+    # library's stream around every launch)
+    ms_a, ms_b, ms_sw = stc.stc_profile_sweeps(solver.h, args.steps)
+    bytes_a, bytes_b = stc.stc_phase_bytes(solver.h)
+    bytes_sweep = bytes_a + bytes_b
+    value = bytes_sweep / (ms_per_step * 1e-3) / 1e9
+    achieved = bytes_a / (ms_a * 1e-3) / 1e9
+    traffic = measured_traffic(workload)
+
+    line = {
+        "metric": "HBM GB/s per staircase sweep",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "levels": L, "block": m, "N": L * m,
+                   "stair_type": 1, "bytes_per_sweep": bytes_sweep,
+                   "seed": synth.config_seed(1)},
+        "roofline": {"bound": "hbm", "kernel": "phase A sweep kernel",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": bytes_a, "ms_per_launch": round(ms_a, 5)},
+        "phase_b": {"ms_per_launch": round(ms_b, 5), "bytes_per_launch": bytes_b,
+                    "GB/s": round(bytes_b / (ms_b * 1e-3) / 1e9, 1)},
+        "sweeps_per_s": round(1e3 / ms_per_step, 1),
+    }
+
+    if args.ttr:
+        line["time_to_residual"] = time_to_residual(gen)
+
+    if not args.no_cpu:
+        sec, n, threads = cpu_baseline(gen)
+        line["cpu_baseline"] = {"value": round(bytes_sweep / sec / 1e9, 2), "unit": "GB/s",
+                                "cores": threads, "kind": "oracle",
+                                "sample": f"{n} FP64 sweeps of the same workload by the C/OpenMP "
+                                          f"oracle sweep ({sec * 1e3:.1f} ms each)"}
+    solver.close()
+    print(json.dumps(line), flush=True)
+
+
+def time_to_residual(gen, tol=1e-12):
+    import numpy as np
+    import torch
+    from oracle import level_reduction
+    from paper_2302_07551_amd import Solver
+    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec, stop="residual",
+                   check_every=50, switch_tol=1e-6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pi, info = s.solve(tol=tol, maxit=200000)
+        dt = time.perf_counter() - t0
+        out[prec] = {"seconds": round(dt, 4), "iters": info["iters"],
+                     "iters_fp32": info["iters_fp32"], "residual": info["residual_1"],
+                     "err_vs_direct": float(np.abs(pi - ref).sum())}
+        s.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()

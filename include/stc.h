@@ -1,0 +1,182 @@
+/*
+ * stc.h - C ABI of the block staircase-splitting solver for the stationary
+ * vector of a continuous-time Markov chain on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (eq. (1), section 1): given the generator Q of an irreducible chain
+ * (off-diagonal rates >= 0, every row sums to 0), find pi with
+ *     Q^T pi = 0,   pi >= 0,   e^T pi = 1.
+ * Method (section 2): the normalised power-type iteration of eq. (mainsch)
+ * for the regular splitting Q^T = M - N in which M is a stair matrix (type 1
+ * or 2), implemented as in Algorithm 2.  One sweep has two parallel steps:
+ * "phase A" solves the diagonal-only block rows independently; "phase B"
+ * solves the stair rows from the freshly computed neighbours; then the sweep
+ * normalises and measures ||x^(k+1) - x^(k)||_1.
+ *
+ * Levels: the states are grouped into L levels (the block partition of Q^T,
+ * section 2), level i holding n_i <= m states; equal sizes with a smaller
+ * last level is the paper's choice (section 3).  The generator is block
+ * banded with block bandwidth b (1 = block tridiagonal / QBD, 2 = block
+ * pentadiagonal).
+ *
+ * Conventions for every entry point:
+ *   - Status codes only; nothing throws across this interface.  After any
+ *     status other than STC_OK, stc_last_error() returns a message for the
+ *     calling thread.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Host arrays passed in are only read during the call (the caller may
+ *     free them afterwards) unless stated otherwise.
+ *   - All device memory the library uses lives inside the caller's arena
+ *     (stc_options.arena); the library allocates no device memory.
+ *   - Vectors of length N = sum n_i are compact (level after level), FP64.
+ *     Arguments marked "where" say whether a vector pointer is host memory
+ *     (STC_MEM_HOST) or device memory on the handle's GPU (STC_MEM_DEVICE).
+ */
+#ifndef STC_H
+#define STC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STC_OK = 0,
+    STC_EINVAL = 1,      /* bad argument: sizes, null pointer, x0 with a negative,
+                            non-finite or all-zero entry set, unsupported m      */
+    STC_ENOTGEN = 2,     /* not a generator: negative or non-finite off-diagonal
+                            rate, or a row that does not sum to 0               */
+    STC_ESINGULAR = 3,   /* a diagonal block Q_ii is singular (states of a level
+                            that can never leave it), so M is not invertible    */
+    STC_EDEGENERATE = 4, /* a sweep produced e^T z <= 0 or a non-finite sum      */
+    STC_EMAXIT = 5,      /* maxit sweeps without meeting tol; the last iterate
+                            and its figures are still returned                  */
+    STC_ENOMEM = 6,      /* the arena is smaller than stc_footprint_bytes()     */
+    STC_EDEVICE = 7      /* a HIP runtime call or kernel launch failed           */
+} stc_status;
+
+enum { STC_FP64 = 0, STC_FP32 = 1, STC_MIXED = 2 };   /* stc_options.precision */
+enum { STC_STOP_DIFF = 0, STC_STOP_RESIDUAL = 1 };     /* stc_options.stop      */
+enum { STC_MEM_HOST = 0, STC_MEM_DEVICE = 1 };         /* "where" arguments     */
+
+/* The block generator (section 2 block partition).  blocks is a host array
+ * [L][2b+1][m][m], row-major: blocks[i][d+b] holds Q_{i,i+d} (rows = states
+ * of level i, columns = states of level i+d) padded with zeros to m x m.
+ * Slots with i+d outside [0, L) are ignored, as is the padding. */
+typedef struct {
+    int32_t L;                   /* levels, >= 2                                    */
+    int32_t m;                   /* block size: max states per level, 1..128       */
+    int32_t b;                   /* block bandwidth, 1 or 2                        */
+    const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */
+    const double *blocks;        /* host, see above                                */
+    int32_t recompute_diagonal;  /* 1: diag(Q_ii) := -(row sum of its off-diagonal
+                                    rates); 0: use the given diagonal, which must
+                                    make every row sum to 0                        */
+} stc_generator;
+
+typedef struct {
+    int32_t precision;    /* STC_FP64: FP64 blocks and sweeps.
+                             STC_FP32: FP32 blocks and sweeps, FP64 sums.
+                             STC_MIXED: FP32 sweeps until the change falls below
+                             switch_tol, then FP64 sweeps to tol.             */
+    int32_t stair_type;   /* 1: M = M1 (phase A = even 0-based levels);
+                             2: M = M2 (phase A = odd 0-based levels)         */
+    int32_t stop;         /* STC_STOP_DIFF: ||x^(k) - x^(k-1)||_1 <= tol
+                             (the stopping test of section 3);
+                             STC_STOP_RESIDUAL: ||Q^T x^(k)||_1 <= tol        */
+    int32_t check_every;  /* sweeps queued between host checks (>= 1).  The
+                             change test runs on the device after every
+                             sweep, so it stops at the exact sweep; the
+                             residual test runs every check_every sweeps.    */
+    double switch_tol;    /* STC_MIXED: FP32 -> FP64 switch threshold on the
+                             change (<= 0: 1e-6)                              */
+    void *stream;         /* hipStream_t used for every launch (NULL: null
+                             stream)                                          */
+    void *arena;          /* device memory owned by the caller, 256-byte
+                             aligned, on the current device                  */
+    size_t arena_bytes;   /* its size, >= stc_footprint_bytes()              */
+} stc_options;
+
+typedef struct {
+    double residual_1;    /* ||Q^T pi||_1 of the returned pi, FP64            */
+    double diff_1;        /* ||x^(k) - x^(k-1)||_1 at the returned sweep k    */
+    int64_t iters;        /* k: sweeps that produced the returned pi          */
+    int64_t iters_fp32;   /* of which in FP32 (STC_FP32 / STC_MIXED)          */
+    int32_t status;       /* same value as the call's return code             */
+} stc_result;
+
+typedef struct stc_handle stc_handle;
+
+/* Device bytes the handle needs for this generator and these options
+ * (arena sub-allocation of every block copy, inverse, iterate and scratch).
+ * Returns 0 for invalid arguments.  Used for admission decisions. */
+size_t stc_footprint_bytes(const stc_generator *gen, const stc_options *opt);
+
+/* Validate Q on the host, copy its blocks to the arena in the sweep's layout
+ * and invert every diagonal block on the device: W_i = (-Q_ii)^{-1}, the
+ * inverse of the diagonal block of M applied in both parallel steps of
+ * Algorithm 2 (section 2).  FP32 copies are rounded from the FP64 ones.
+ * Errors: STC_EINVAL, STC_ENOTGEN, STC_ESINGULAR, STC_ENOMEM, STC_EDEVICE.
+ * On success *out owns no device memory of its own; it must be destroyed
+ * before the arena is freed. */
+stc_status stc_setup(const stc_generator *gen, const stc_options *opt, stc_handle **out);
+
+/* Algorithm 2 (section 2) with the stopping test of section 3: start from
+ * x0 / e^T x0 (x0 NULL: e/N), sweep until the stop quantity is <= tol or
+ * maxit sweeps were done, and write the last iterate to pi (length N).
+ * x0 and pi are host or device memory per "where".  Returns STC_OK,
+ * STC_EMAXIT (pi and res still filled), STC_EDEGENERATE, STC_EINVAL,
+ * STC_EDEVICE.  res may be NULL. */
+stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
+                     double *pi, stc_result *res, int32_t where);
+
+/* One sweep of Algorithm 2 from x (normalised first): z = M^{-1} N x,
+ * normalised, and *diff_1 = ||z - x/e^T x||_1.  In STC_FP32 / STC_MIXED the
+ * sweep runs in FP32.  x and z are host or device memory per "where"; z may
+ * not alias x. */
+stc_status stc_step(stc_handle *h, const double *x, double *z, double *diff_1, int32_t where);
+
+/* ||Q^T x||_1 in FP64 (eq. (1)), x as given (not normalised). */
+stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t where);
+
+/* Device-resident sweeps: run nsweeps sweeps of Algorithm 2 on the handle's
+ * current iterate without host synchronisation (the iterate is the one left by
+ * the previous stc_solve / stc_step / stc_load on this handle).  diffs (host,
+ * may be NULL) receives the change of every sweep but the last, after an
+ * implicit synchronisation. */
+stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs);
+
+/* Measurement form of stc_sweeps: the same sweeps, with a HIP event recorded
+ * on the handle's stream before and after every phase launch.  Returns the
+ * mean device time per launch of phase A and of phase B and the mean time of
+ * a whole sweep, in milliseconds (any pointer may be NULL). */
+stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_phase_a,
+                              double *ms_phase_b, double *ms_sweep);
+
+/* Algorithmic HBM bytes of one launch of phase A and of phase B for this
+ * handle's current precision: every stored block the phase reads once, the
+ * vector segments it reads once and the segments it writes once. */
+stc_status stc_phase_bytes(stc_handle *h, double *bytes_phase_a, double *bytes_phase_b);
+
+/* Set the handle's current iterate to x / e^T x (host or device memory). */
+stc_status stc_load(stc_handle *h, const double *x, int32_t where);
+
+/* Per-handle figures after stc_sweeps: sweeps done since
+ * the last load, whether the device stop test fired, the last known change. */
+stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *diff_1);
+
+/* Copy the handle's current (or stopped) iterate, normalised, to pi. */
+stc_status stc_store(stc_handle *h, double *pi, int32_t where);
+
+/* Release the handle (the arena stays with the caller). */
+void stc_destroy(stc_handle *h);
+
+const char *stc_status_string(stc_status s);
+const char *stc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STC_H */

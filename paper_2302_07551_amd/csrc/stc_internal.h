@@ -1,0 +1,75 @@
+// Internal declarations shared by the host runtime (stc_runtime.cpp) and the
+// device kernels (stc_kernels.hip) of the staircase solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace stc {
+
+// Device-side solver state of one chain (lives in the arena).
+// Ring slots are indexed by the sweep number s modulo kRing:
+//   inv_sigma[s] = 1 / e^T W_s   (W_s: unnormalised output of sweep s,
+//                                 W_0 = the loaded start vector)
+//   diff[s]      = ||x^(s) - x^(s-1)||_1 with x^(s) = W_s * inv_sigma[s]
+constexpr int kRing = 4096;
+constexpr int kRingMask = kRing - 1;
+
+struct DevState {
+    double inv_sigma[kRing];
+    double diff[kRing];
+    double residual;          // last residual evaluation
+    double x_sum;             // e^T of the last loaded vector
+    int stop_flag;            // 1: no further sweep may change the iterate
+    int status;               // 0 ok, 1 degenerate sum, 2 bad start vector
+    long long stop_sweep;     // sweep whose change met the device test
+    long long last_sweep;     // last sweep whose phase B finished
+    int bad_blocks;           // singular diagonal blocks found by the inverse
+    int pad_;
+};
+
+enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2 };
+
+// One launch of a half-sweep (phase A or phase B) of one chain.
+struct SweepLaunch {
+    const void *blk;      // T [L][2b+1][MP][MP] gather-oriented blocks
+    const void *w_old;    // T [L][MP]  W_{s-1}
+    const void *w_older;  // T [L][MP]  W_{s-2}  (change of sweep s-1)
+    void *w_new;          // T [L][MP]  W_s
+    double *part_sum;     // per-workgroup partial e^T W_s
+    double *part_diff;    // per-workgroup partial change
+    DevState *st;
+    int L;
+    int parity;           // first level of this phase
+    int slot0;            // first partial slot used by this launch
+    int nslots;           // total slots of both phases
+    long long s;          // sweep being produced (>= 1)
+};
+
+// Host-visible launchers (stc_kernels.hip).  Each returns a hipError_t.
+int supported_mp(int m);   // padded block size for m, or 0
+int phase_groups(int precision_bytes, int MP, int L, int parity);
+hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b,
+                              const SweepLaunch &a, hipStream_t stream);
+hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
+                                 DevState *st, long long s, double tol, hipStream_t stream);
+hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, double *blk,
+                         int L, DevState *st, hipStream_t stream);
+hipError_t launch_cast_blocks(const double *src, float *dst, size_t n, hipStream_t stream);
+hipError_t launch_load(int precision_bytes, int MP, const double *x, const long long *off,
+                       const int *sizes, int L, void *w0, double *part, int nparts,
+                       DevState *st, int state_slot, hipStream_t stream);
+hipError_t launch_store(int precision_bytes, int MP, const void *w, const long long *off,
+                        const int *sizes, int L, DevState *st, long long slot, double *x,
+                        hipStream_t stream);
+hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
+                           const double *diag64, const void *w, int L, DevState *st,
+                           long long slot, double *part, hipStream_t stream);
+hipError_t launch_diff(int precision_bytes, int MP, const void *w, const void *w_prev,
+                       int L, DevState *st, long long s, double *part, hipStream_t stream);
+hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t stream);
+hipError_t launch_reset_state(DevState *st, hipStream_t stream);
+int reduce_groups(int MP, int L);
+
+}  // namespace stc

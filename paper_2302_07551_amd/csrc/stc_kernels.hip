@@ -1,0 +1,671 @@
+// Device kernels of the block staircase-splitting solver (gfx950).
+//
+// One sweep of Algorithm 2 (section 2) is two launches:
+//   phase A: every diagonal-only level i (independent):
+//              r_i = sum_{k != i} A_{i,k} x_k         (old iterate)
+//              z_i = W_i r_i,  W_i = (-A_{i,i})^{-1}
+//   phase B: every stair level i, from the fresh phase-A neighbours:
+//              r_i = sum_{k = i+-1} A_{i,k} z_k + sum_{|k-i| >= 2} A_{i,k} x_k
+//              z_i = W_i r_i
+// followed by the normalisation z / e^T z and the change ||z - x||_1.  Here
+// A = Q^T, so A_{i,k} v = Q_{k,i}^T v; every product is a non-negative block
+// times a non-negative vector (no cancellation).
+//
+// Layout in HBM (per chain):
+//   blk [L][2b+1][MP][MP]  level-major, so one level's blocks are contiguous.
+//                          Slot d+b, d != 0, holds Q_{i+d,i} row-major (rows =
+//                          states of level i+d, columns = states of level i);
+//                          slot b holds (-Q_ii)^{-1} row-major.  The product
+//                          with a vector is a column gather: y[j] = sum_r
+//                          B[r][j] v[r], so lanes run along a row and every
+//                          load is a contiguous 16-byte piece of one row.
+//   W   [L][MP]            iterates, zero padded.
+//
+// Normalisation is lazy: the sweep producing W_s reads W_{s-1} scaled by
+// 1/e^T W_{s-1} (a device scalar) and writes fixed-order per-workgroup
+// partial sums of its output and of the change of the previous sweep,
+// ||x^(s-1) - x^(s-2)||_1.  A one-workgroup finalize kernel then forms
+// e^T W_s and that change in a fixed order (the result does not depend on
+// scheduling) and applies the device-side stopping test.  No workgroup waits
+// on another and no kernel needs a device-wide fence: the kernel boundaries
+// order the three launches of a sweep.
+#include <math.h>
+
+#include "stc_internal.h"
+
+namespace stc {
+
+constexpr int kWG = 256;
+
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    typedef double __attribute__((ext_vector_type(2))) type;
+};
+template <>
+struct Vec16<float> {
+    typedef float __attribute__((ext_vector_type(4))) type;
+};
+
+// Thread geometry of one level ("team"): CT lanes span a block row with
+// 16-byte loads, R row groups split the rows, LPW levels share a workgroup.
+template <typename T, int MP>
+struct Tile {
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr int CT = MP / VEC;
+    static constexpr int TS = (CT * 8 <= kWG) ? CT * 8 : kWG;
+    static constexpr int R = TS / CT;
+    static constexpr int RPT = MP / R;
+    static constexpr int LPW = kWG / TS;
+    static constexpr int PF = RPT < 8 ? RPT : 8;   // W_i rows prefetched per thread
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fixed-order workgroup sum (every thread gets the same value).
+__device__ inline double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWG / 64; ++j) t += sh[j];
+    return t;
+}
+
+__device__ inline double block_max(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = sh[0];
+#pragma unroll
+    for (int j = 1; j < kWG / 64; ++j) t = fmax(t, sh[j]);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// half-sweep
+// ---------------------------------------------------------------------------
+template <typename T, int MP, int B, bool PHB>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
+    using TL = Tile<T, MP>;
+    using VT = typename Vec16<T>::type;
+    constexpr int NB = 2 * B + 1;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
+                  LPW = TL::LPW, PF = TL::PF;
+    constexpr size_t BS = (size_t)MP * MP;
+    __shared__ T red[LPW][R][MP];
+    __shared__ T rv[LPW][MP];
+    __shared__ double sh[kWG / 64];
+
+    const DevState *st = a.st;
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    const int i = a.parity + 2 * (blockIdx.x * LPW + team);
+    const bool active = i < a.L;
+    const int ic = active ? i : a.parity;   // a valid level for idle teams
+    const T *w_old = (const T *)a.w_old;
+    T *w_new = (T *)a.w_new;
+    const T *base = (const T *)a.blk + (size_t)ic * NB * BS;
+    const double inv_old = st->inv_sigma[(a.s - 1) & kRingMask];
+    const T sc = (T)inv_old;
+
+    // r_i: gather of the off-diagonal blocks of block row i of A.  The loop
+    // has no branches, so all block loads of the level are in flight at once;
+    // a neighbour outside [0, L) has an all-zero stored block and weight 0.
+    VT acc = (VT)(T)0;
+#pragma unroll
+    for (int d = -B; d <= B; ++d) {
+        if (d == 0) continue;
+        const int k = ic + d;
+        const bool in = (k >= 0) && (k < a.L);
+        const bool fresh = PHB && (d == 1 || d == -1);
+        const T *v = (fresh ? (const T *)w_new : w_old) + (size_t)(in ? k : ic) * MP;
+        const T vs = in ? (fresh ? (T)1 : sc) : (T)0;
+        const T *gb = base + (size_t)(d + B) * BS + c * VEC;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int row = g + R * q;
+            const VT blkv = *(const VT *)(gb + (size_t)row * MP);
+            acc += blkv * (v[row] * vs);
+        }
+    }
+    // rows of W_i fetched before the reduction, so they stream meanwhile
+    VT vpre[PF];
+    const T *wb = base + (size_t)B * BS + c * VEC;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) vpre[q] = *(const VT *)(wb + (size_t)(g + R * q) * MP);
+
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc[e];
+    __syncthreads();
+    if (tt < MP) {
+        T r = 0;
+#pragma unroll
+        for (int gg = 0; gg < R; ++gg) r += red[team][gg][tt];
+        rv[team][tt] = r;
+    }
+    __syncthreads();
+
+    // z_i = W_i r_i
+    VT acc2 = (VT)(T)0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int row = g + R * q;
+        const VT wv = (q < PF) ? vpre[q < PF ? q : 0] : *(const VT *)(wb + (size_t)row * MP);
+        acc2 += wv * rv[team][row];
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc2[e];
+    __syncthreads();
+
+    // a sweep queued after the device stopping test fired changes nothing
+    const bool live = st->stop_flag == 0;
+    double zs = 0.0, dd = 0.0;
+    if (live && active && tt < MP) {
+        T z = 0;
+#pragma unroll
+        for (int gg = 0; gg < R; ++gg) z += red[team][gg][tt];
+        w_new[(size_t)i * MP + tt] = z;
+        zs = (double)z;
+        if (a.s >= 2) {
+            const double inv_older = st->inv_sigma[(a.s - 2) & kRingMask];
+            const T *w_older = (const T *)a.w_older;
+            dd = fabs((double)w_old[(size_t)i * MP + tt] * inv_old -
+                      (double)w_older[(size_t)i * MP + tt] * inv_older);
+        }
+    }
+    const double S = block_sum(zs, sh);
+    const double D = block_sum(dd, sh);
+    if (live && tid == 0) {
+        a.part_sum[a.slot0 + blockIdx.x] = S;
+        a.part_diff[a.slot0 + blockIdx.x] = D;
+    }
+}
+
+// One workgroup: e^T W_s and the change of sweep s-1 from the partials of
+// both phases (fixed order), then the device stopping test.
+__global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
+                                                         const double *part_diff, int nslots,
+                                                         DevState *st, long long s, double tol) {
+    __shared__ double sh[kWG / 64];
+    if (st->stop_flag) return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = threadIdx.x; j < nslots; j += kWG) {
+        s1 += part_sum[j];
+        s2 += part_diff[j];
+    }
+    s1 = block_sum(s1, sh);
+    s2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        st->last_sweep = s;
+        if (!(s1 > 0.0) || !isfinite(s1)) {
+            st->status = kDevDegenerate;
+            st->stop_flag = 1;
+            st->stop_sweep = s - 1;
+        } else {
+            st->inv_sigma[s & kRingMask] = 1.0 / s1;
+        }
+        if (s >= 2) {
+            st->diff[(s - 1) & kRingMask] = s2;
+            if (tol > 0.0 && s2 <= tol && !st->stop_flag) {
+                st->stop_flag = 1;
+                st->stop_sweep = s - 1;
+            }
+        }
+    }
+}
+
+// One workgroup: fixed-order sum (and max) of per-group partials for the
+// residual, change and load kernels.
+enum ReduceMode { kReduceResidual = 0, kReduceDiff = 1, kReduceLoad = 2 };
+
+__global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int mode,
+                                                 DevState *st, long long slot) {
+    __shared__ double sh[kWG / 64];
+    const int stride = (mode == kReduceLoad) ? 2 : 1;
+    double t = 0.0, b = 0.0;
+    for (int j = threadIdx.x; j < n; j += kWG) {
+        t += part[stride * j];
+        if (mode == kReduceLoad) b = fmax(b, part[2 * j + 1]);
+    }
+    t = block_sum(t, sh);
+    if (mode == kReduceLoad) b = block_max(b, sh);
+    if (threadIdx.x != 0) return;
+    if (mode == kReduceResidual) {
+        st->residual = t;
+    } else if (mode == kReduceDiff) {
+        st->diff[slot & kRingMask] = t;
+    } else {
+        st->x_sum = t;
+        // slot < 0: a raw vector for the residual, no start-vector checks
+        if (slot >= 0) {
+            if (b > 0.0 || !(t > 0.0) || !isfinite(t)) {
+                st->status = kDevBadStart;
+                st->inv_sigma[slot & kRingMask] = 0.0;
+            } else {
+                st->inv_sigma[slot & kRingMask] = 1.0 / t;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// residual ||Q^T x||_1 in FP64: (Q^T x)_i = sum_{d != 0} Q_{i+d,i}^T x_{i+d} + Q_ii^T x_i
+// ---------------------------------------------------------------------------
+template <typename T, int MP, int B>
+__global__ __launch_bounds__(kWG) void k_residual(const double *blk, const double *diag,
+                                                   const T *w, int L, const DevState *st,
+                                                   long long slot, double *part) {
+    using TL = Tile<double, MP>;
+    using VT = typename Vec16<double>::type;
+    constexpr int NB = 2 * B + 1;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
+                  LPW = TL::LPW;
+    constexpr size_t BS = (size_t)MP * MP;
+    __shared__ double red[LPW][R][MP];
+    __shared__ double sh[kWG / 64];
+
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    const int i = blockIdx.x * LPW + team;
+    const bool active = i < L;
+    const double inv = slot < 0 ? 1.0 : st->inv_sigma[slot & kRingMask];
+
+    VT acc = (VT)0.0;
+    if (active) {
+#pragma unroll
+        for (int d = -B; d <= B; ++d) {
+            const int k = i + d;
+            if (k < 0 || k >= L) continue;
+            const T *v = w + (size_t)k * MP;
+            const double *gb = (d == 0 ? diag + (size_t)i * BS
+                                       : blk + ((size_t)i * NB + (d + B)) * BS) + c * VEC;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int row = g + R * q;
+                const VT bv = *(const VT *)(gb + (size_t)row * MP);
+                acc += bv * ((double)v[row] * inv);
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc[e];
+    __syncthreads();
+    double r = 0.0;
+    if (active && tt < MP) {
+        double t = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < R; ++gg) t += red[team][gg][tt];
+        r = fabs(t);
+    }
+    const double S = block_sum(r, sh);
+    if (tid == 0) part[blockIdx.x] = S;
+}
+
+// ---------------------------------------------------------------------------
+// change ||x^(s) - x^(s-1)||_1 of one sweep (used when the run ends at maxit)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, size_t n,
+                                               const DevState *st, long long s, double *part) {
+    __shared__ double sh[kWG / 64];
+    const double inv = st->inv_sigma[s & kRingMask];
+    const double invp = st->inv_sigma[(s - 1) & kRingMask];
+    double d = 0.0;
+    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG)
+        d += fabs((double)w[j] * inv - (double)wp[j] * invp);
+    d = block_sum(d, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
+}
+
+// ---------------------------------------------------------------------------
+// compact FP64 vector -> padded iterate W (type T); partial sums and a flag
+// for negative or non-finite entries (k_reduce then records 1/e^T W)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_load(const double *x, const long long *off,
+                                               const int *sizes, int L, int MP, T *w,
+                                               double *part, int slot) {
+    __shared__ double sh[kWG / 64];
+    const size_t n = (size_t)L * MP;
+    double s = 0.0, bad = 0.0;
+    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG) {
+        const int lev = (int)(j / MP), col = (int)(j - (size_t)lev * MP);
+        double v = 0.0;
+        if (col < sizes[lev]) v = x[off[lev] + col];
+        if (!isfinite(v) || (slot >= 0 && !(v >= 0.0))) {
+            bad = 1.0;
+            v = 0.0;
+        }
+        const T t = (T)v;
+        w[j] = t;
+        s += (double)t;
+    }
+    s = block_sum(s, sh);
+    bad = block_max(bad, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s;
+        part[2 * blockIdx.x + 1] = bad;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_store(const T *w, const long long *off, const int *sizes,
+                                                int L, int MP, const DevState *st, long long slot,
+                                                double *x) {
+    const double inv = st->inv_sigma[slot & kRingMask];
+    const size_t n = (size_t)L * MP;
+    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG) {
+        const int lev = (int)(j / MP), col = (int)(j - (size_t)lev * MP);
+        if (col < sizes[lev]) x[off[lev] + col] = (double)w[j] * inv;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_cast(const double *src, float *dst, size_t n) {
+    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG)
+        dst[j] = (float)src[j];
+}
+
+__global__ __launch_bounds__(kWG) void k_widen(const float *src, double *dst, size_t n) {
+    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG)
+        dst[j] = (double)src[j];
+}
+
+__global__ void k_reset(DevState *st) {
+    if (threadIdx.x == 0) {
+        st->stop_flag = 0;
+        st->status = kDevOk;
+        st->stop_sweep = -1;
+        st->last_sweep = 0;
+        st->residual = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// W_i = (-Q_ii)^{-1} by Gauss-Jordan elimination in LDS, one level per group.
+// -Q_ii is a diagonally dominant M-matrix (its rows sum to the rate leaving
+// the level), so no pivoting is needed and every pivot is positive; a pivot
+// that is not clearly positive marks the block singular.  Padding rows and
+// columns are carried as an identity and written back as zeros.
+// ---------------------------------------------------------------------------
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_invert(const double *diag, const int *sizes,
+                                                 double *blk, int NB, int B, DevState *st) {
+    constexpr int LD = MP + 1;
+    __shared__ double a[MP * LD];
+    __shared__ double colk[MP];
+    __shared__ double rowk[MP];
+    __shared__ int bad;
+    const int i = blockIdx.x;
+    const int n = sizes[i];
+    const double *Q = diag + (size_t)i * MP * MP;
+    if (threadIdx.x == 0) bad = 0;
+    for (int idx = threadIdx.x; idx < MP * MP; idx += kWG) {
+        const int r = idx / MP, c = idx - r * MP;
+        double v;
+        if (r < n && c < n) v = -Q[idx];
+        else v = (r == c) ? 1.0 : 0.0;
+        a[r * LD + c] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < MP; ++k) {
+        const double p = a[k * LD + k];
+        if (threadIdx.x < MP) {
+            colk[threadIdx.x] = a[threadIdx.x * LD + k];
+            rowk[threadIdx.x] = a[k * LD + threadIdx.x];
+        }
+        if (threadIdx.x == 0) {
+            // relative to the row's total rate, which equals the original diagonal
+            // up to the eliminated part; a non-positive or vanishing pivot means the
+            // level has a closed set of states
+            double scale = 0.0;
+            for (int c = k; c < MP; ++c) scale += fabs(a[k * LD + c]);
+            if (!(p > 1e-13 * scale) || !isfinite(p)) bad = 1;
+        }
+        __syncthreads();
+        const double pinv = 1.0 / p;
+        for (int idx = threadIdx.x; idx < MP * MP; idx += kWG) {
+            const int r = idx / MP, c = idx - r * MP;
+            double v;
+            if (r == k) v = (c == k) ? pinv : rowk[c] * pinv;
+            else if (c == k) v = -colk[r] * pinv;
+            else v = a[r * LD + c] - colk[r] * rowk[c] * pinv;
+            a[r * LD + c] = v;
+        }
+        __syncthreads();
+    }
+    double *W = blk + ((size_t)i * NB + B) * MP * MP;
+    for (int idx = threadIdx.x; idx < MP * MP; idx += kWG) {
+        const int r = idx / MP, c = idx - r * MP;
+        W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
+    }
+    if (threadIdx.x == 0 && bad) atomicAdd(&st->bad_blocks, 1);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+int supported_mp(int m) {
+    if (m < 1 || m > 128) return 0;
+    int mp = 8;
+    while (mp < m) mp <<= 1;
+    return mp;
+}
+
+template <typename T>
+static int lpw_of(int MP) {
+    switch (MP) {
+        case 8: return Tile<T, 8>::LPW;
+        case 16: return Tile<T, 16>::LPW;
+        case 32: return Tile<T, 32>::LPW;
+        case 64: return Tile<T, 64>::LPW;
+        case 128: return Tile<T, 128>::LPW;
+    }
+    return 1;
+}
+
+int phase_groups(int precision_bytes, int MP, int L, int parity) {
+    const int levels = (L - parity + 1) / 2;
+    const int lpw = precision_bytes == 8 ? lpw_of<double>(MP) : lpw_of<float>(MP);
+    return (levels + lpw - 1) / lpw;
+}
+
+int reduce_groups(int MP, int L) {
+    const int lpw = lpw_of<double>(MP);
+    return (L + lpw - 1) / lpw;
+}
+
+template <typename T, int MP, int B>
+static hipError_t sweep_mpb(bool phase_b, const SweepLaunch &a, hipStream_t s) {
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity);
+    if (groups <= 0) return hipSuccess;
+    if (phase_b)
+        hipLaunchKernelGGL((k_sweep<T, MP, B, true>), dim3(groups), dim3(kWG), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sweep<T, MP, B, false>), dim3(groups), dim3(kWG), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+static hipError_t sweep_b(int MP, bool phase_b, const SweepLaunch &a, hipStream_t s) {
+    switch (MP) {
+        case 8: return sweep_mpb<T, 8, B>(phase_b, a, s);
+        case 16: return sweep_mpb<T, 16, B>(phase_b, a, s);
+        case 32: return sweep_mpb<T, 32, B>(phase_b, a, s);
+        case 64: return sweep_mpb<T, 64, B>(phase_b, a, s);
+        case 128: return sweep_mpb<T, 128, B>(phase_b, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b,
+                              const SweepLaunch &a, hipStream_t stream) {
+    if (precision_bytes == 8)
+        return b == 1 ? sweep_b<double, 1>(MP, phase_b, a, stream)
+                      : sweep_b<double, 2>(MP, phase_b, a, stream);
+    return b == 1 ? sweep_b<float, 1>(MP, phase_b, a, stream)
+                  : sweep_b<float, 2>(MP, phase_b, a, stream);
+}
+
+template <int MP>
+static hipError_t invert_mp(int b, const double *diag, const int *sizes, double *blk, int L,
+                            DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL((k_invert<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk, 2 * b + 1, b,
+                       st);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, double *blk, int L,
+                         DevState *st, hipStream_t stream) {
+    switch (MP) {
+        case 8: return invert_mp<8>(b, diag, sizes, blk, L, st, stream);
+        case 16: return invert_mp<16>(b, diag, sizes, blk, L, st, stream);
+        case 32: return invert_mp<32>(b, diag, sizes, blk, L, st, stream);
+        case 64: return invert_mp<64>(b, diag, sizes, blk, L, st, stream);
+        case 128: return invert_mp<128>(b, diag, sizes, blk, L, st, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int elementwise_groups(size_t n) {
+    size_t g = (n + kWG - 1) / kWG;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_cast_blocks(const double *src, float *dst, size_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_cast, dim3(elementwise_groups(n)), dim3(kWG), 0, stream, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_widen, dim3(elementwise_groups(n)), dim3(kWG), 0, stream, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_state(DevState *st, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
+                                 DevState *st, long long s, double tol, hipStream_t stream) {
+    hipLaunchKernelGGL(k_finalize_sweep, dim3(1), dim3(kWG), 0, stream, part_sum, part_diff,
+                       nslots, st, s, tol);
+    return hipGetLastError();
+}
+
+static hipError_t reduce(const double *part, int n, int mode, DevState *st, long long slot,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, stream, part, n, mode, st, slot);
+    return hipGetLastError();
+}
+
+// load/diff use at most this many groups, so their partial arrays stay small
+constexpr int kAuxGroups = 1024;
+
+hipError_t launch_load(int precision_bytes, int MP, const double *x, const long long *off,
+                       const int *sizes, int L, void *w0, double *part, int nparts,
+                       DevState *st, int state_slot, hipStream_t stream) {
+    int groups = elementwise_groups((size_t)L * MP);
+    if (groups > kAuxGroups) groups = kAuxGroups;
+    if (2 * groups > nparts) groups = nparts / 2;
+    if (precision_bytes == 8)
+        hipLaunchKernelGGL(k_load<double>, dim3(groups), dim3(kWG), 0, stream, x, off, sizes, L,
+                           MP, (double *)w0, part, state_slot);
+    else
+        hipLaunchKernelGGL(k_load<float>, dim3(groups), dim3(kWG), 0, stream, x, off, sizes, L,
+                           MP, (float *)w0, part, state_slot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce(part, groups, kReduceLoad, st, state_slot, stream);
+}
+
+hipError_t launch_store(int precision_bytes, int MP, const void *w, const long long *off,
+                        const int *sizes, int L, DevState *st, long long slot, double *x,
+                        hipStream_t stream) {
+    const int groups = elementwise_groups((size_t)L * MP);
+    if (precision_bytes == 8)
+        hipLaunchKernelGGL(k_store<double>, dim3(groups), dim3(kWG), 0, stream,
+                           (const double *)w, off, sizes, L, MP, st, slot, x);
+    else
+        hipLaunchKernelGGL(k_store<float>, dim3(groups), dim3(kWG), 0, stream, (const float *)w,
+                           off, sizes, L, MP, st, slot, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff(int precision_bytes, int MP, const void *w, const void *w_prev, int L,
+                       DevState *st, long long s, double *part, hipStream_t stream) {
+    const size_t n = (size_t)L * MP;
+    int groups = elementwise_groups(n);
+    if (groups > kAuxGroups) groups = kAuxGroups;
+    if (precision_bytes == 8)
+        hipLaunchKernelGGL(k_diff<double>, dim3(groups), dim3(kWG), 0, stream,
+                           (const double *)w, (const double *)w_prev, n, st, s, part);
+    else
+        hipLaunchKernelGGL(k_diff<float>, dim3(groups), dim3(kWG), 0, stream, (const float *)w,
+                           (const float *)w_prev, n, st, s, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce(part, groups, kReduceDiff, st, s, stream);
+}
+
+template <typename T, int B>
+static hipError_t residual_b(int MP, const double *blk, const double *diag, const void *w,
+                             int L, DevState *st, long long slot, double *part, hipStream_t s) {
+    const int groups = reduce_groups(MP, L);
+    const T *wt = (const T *)w;
+    switch (MP) {
+        case 8:
+            hipLaunchKernelGGL((k_residual<T, 8, B>), dim3(groups), dim3(kWG), 0, s, blk, diag,
+                               wt, L, st, slot, part);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_residual<T, 16, B>), dim3(groups), dim3(kWG), 0, s, blk, diag,
+                               wt, L, st, slot, part);
+            break;
+        case 32:
+            hipLaunchKernelGGL((k_residual<T, 32, B>), dim3(groups), dim3(kWG), 0, s, blk, diag,
+                               wt, L, st, slot, part);
+            break;
+        case 64:
+            hipLaunchKernelGGL((k_residual<T, 64, B>), dim3(groups), dim3(kWG), 0, s, blk, diag,
+                               wt, L, st, slot, part);
+            break;
+        case 128:
+            hipLaunchKernelGGL((k_residual<T, 128, B>), dim3(groups), dim3(kWG), 0, s, blk, diag,
+                               wt, L, st, slot, part);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce(part, groups, kReduceResidual, st, 0, s);
+}
+
+hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
+                           const double *diag64, const void *w, int L, DevState *st,
+                           long long slot, double *part, hipStream_t stream) {
+    if (precision_bytes == 8)
+        return b == 1 ? residual_b<double, 1>(MP, blk64, diag64, w, L, st, slot, part, stream)
+                      : residual_b<double, 2>(MP, blk64, diag64, w, L, st, slot, part, stream);
+    return b == 1 ? residual_b<float, 1>(MP, blk64, diag64, w, L, st, slot, part, stream)
+                  : residual_b<float, 2>(MP, blk64, diag64, w, L, st, slot, part, stream);
+}
+
+}  // namespace stc

@@ -1,0 +1,690 @@
+// Host runtime of the staircase solver: validation and packing of the block
+// generator, arena layout, the solve loop with its stopping tests, and the
+// C ABI declared in include/stc.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/stc.h"
+#include "stc_internal.h"
+
+using namespace stc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+stc_status fail(stc_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(STC_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Sub-allocation plan of one chain inside its arena.
+struct Layout {
+    int MP = 0, NB = 0;
+    bool fp32 = false;          // FP32 copies of blocks and iterates
+    size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
+    size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0;
+    size_t nparts = 0, naux = 0;
+    size_t total = 0;
+};
+
+bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
+    *why = 0;
+    if (!g || !o) return false;
+    if (g->L < 2) { *why = 1; return false; }
+    if (g->b != 1 && g->b != 2) { *why = 2; return false; }
+    const int MP = supported_mp(g->m);
+    if (!MP) { *why = 3; return false; }
+    if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
+    Layout l;
+    l.MP = MP;
+    l.NB = 2 * g->b + 1;
+    l.fp32 = o->precision != STC_FP64;
+    const size_t L = (size_t)g->L, bs = (size_t)MP * MP, vec = L * MP;
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t p = at; at = align_up(at + bytes); return p; };
+    l.blk64 = take(L * l.NB * bs * 8);
+    l.diag64 = take(L * bs * 8);
+    if (l.fp32) l.blk32 = take(L * l.NB * bs * 4);
+    l.w64 = take(3 * vec * 8);
+    if (l.fp32) l.w32 = take(3 * vec * 4);
+    l.wres = take(vec * 8);
+    l.io = take(vec * 8);
+    l.nparts = L + 8;
+    l.part_sum = take(l.nparts * 8);
+    l.part_diff = take(l.nparts * 8);
+    l.naux = std::max<size_t>(2 * 1024 + 8, L + 8);
+    l.part_aux = take(l.naux * 8);
+    l.off = take((L + 1) * 8);
+    l.sizes = take(L * 4);
+    l.state = take(sizeof(DevState));
+    l.total = at;
+    *lay = l;
+    return true;
+}
+
+}  // namespace
+
+struct stc_handle {
+    int L = 0, m = 0, b = 0, MP = 0, NB = 0;
+    int precision = STC_FP64, stair_type = 1, stop = STC_STOP_DIFF, check_every = 1;
+    double switch_tol = 1e-6;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Layout lay;
+    char *base = nullptr;
+    // device views
+    double *blk64 = nullptr, *diag64 = nullptr, *w64 = nullptr, *wres = nullptr, *io = nullptr;
+    float *blk32 = nullptr, *w32 = nullptr;
+    double *part_sum = nullptr, *part_diff = nullptr, *part_aux = nullptr;
+    long long *off = nullptr;
+    int *sizes_d = nullptr;
+    DevState *st = nullptr;
+    std::vector<int> sizes;
+    long long N = 0;
+    // iteration state
+    long long s = 0;        // sweeps done since the last load
+    bool stage32 = false;   // current iterate lives in the FP32 rotation
+    long long iters32 = 0;  // sweeps done in FP32 since the last load
+};
+
+namespace {
+
+void *wbuf(stc_handle *h, bool fp32, long long s) {
+    const size_t vec = (size_t)h->L * h->MP;
+    const int k = (int)(((s % 3) + 3) % 3);
+    if (fp32) return h->w32 + k * vec;
+    return h->w64 + k * vec;
+}
+
+stc_status launch_one_sweep(stc_handle *h, long long s, double tol) {
+    const bool f32 = h->stage32;
+    SweepLaunch a;
+    a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
+    a.w_old = wbuf(h, f32, s - 1);
+    a.w_older = wbuf(h, f32, s - 2);
+    a.w_new = wbuf(h, f32, s);
+    a.part_sum = h->part_sum;
+    a.part_diff = h->part_diff;
+    a.st = h->st;
+    a.L = h->L;
+    a.s = s;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    const int pB = 1 - pA;
+    const int bytes = f32 ? 4 : 8;
+    const int gA = phase_groups(bytes, h->MP, h->L, pA);
+    const int gB = phase_groups(bytes, h->MP, h->L, pB);
+    a.nslots = gA + gB;
+    a.parity = pA;
+    a.slot0 = 0;
+    HIP_TRY(launch_sweep_phase(bytes, h->MP, h->b, false, a, h->stream));
+    a.parity = pB;
+    a.slot0 = gA;
+    HIP_TRY(launch_sweep_phase(bytes, h->MP, h->b, true, a, h->stream));
+    HIP_TRY(launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, tol, h->stream));
+    return STC_OK;
+}
+
+struct HostState {
+    int stop_flag, status;
+    long long stop_sweep, last_sweep;
+    double residual, x_sum;
+    int bad_blocks;
+};
+
+stc_status read_state(stc_handle *h, HostState *hs) {
+    DevState tmp;
+    // only the scalar tail is needed; copy from residual onwards
+    const size_t off = offsetof(DevState, residual);
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char *>(&tmp) + off,
+                           reinterpret_cast<char *>(h->st) + off, sizeof(DevState) - off,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    hs->stop_flag = tmp.stop_flag;
+    hs->status = tmp.status;
+    hs->stop_sweep = tmp.stop_sweep;
+    hs->last_sweep = tmp.last_sweep;
+    hs->residual = tmp.residual;
+    hs->x_sum = tmp.x_sum;
+    hs->bad_blocks = tmp.bad_blocks;
+    return STC_OK;
+}
+
+stc_status read_ring(stc_handle *h, const double *ring_dev, long long s, double *out) {
+    HIP_TRY(hipMemcpyAsync(out, ring_dev + (s & kRingMask), sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return STC_OK;
+}
+
+// Load x (compact, N) as W_0 of the current stage; resets the sweep counter.
+stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
+    const double *src = x;
+    if (x && where == STC_MEM_HOST) {
+        HIP_TRY(hipMemcpyAsync(h->io, x, sizeof(double) * h->N, hipMemcpyHostToDevice, h->stream));
+        src = h->io;
+    } else if (!x) {
+        std::vector<double> e(h->N, 1.0 / (double)h->N);
+        HIP_TRY(hipMemcpyAsync(h->io, e.data(), sizeof(double) * h->N, hipMemcpyHostToDevice,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        src = h->io;
+    }
+    h->stage32 = (h->precision != STC_FP64);
+    h->s = 0;
+    h->iters32 = 0;
+    HIP_TRY(launch_reset_state(h->st, h->stream));
+    HIP_TRY(launch_load(h->stage32 ? 4 : 8, h->MP, src, h->off, h->sizes_d, h->L,
+                        wbuf(h, h->stage32, 0), h->part_aux, (int)h->lay.naux, h->st, 0,
+                        h->stream));
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    if (hs.status == kDevBadStart)
+        return fail(STC_EINVAL, "start vector must be >= 0, finite, with a positive sum "
+                                "(sum = %g)", hs.x_sum);
+    return STC_OK;
+}
+
+stc_status residual_of(stc_handle *h, bool f32, long long s, double *out) {
+    HIP_TRY(launch_residual(f32 ? 4 : 8, h->MP, h->b, h->blk64, h->diag64, wbuf(h, f32, s), h->L,
+                            h->st, s, h->part_aux, h->stream));
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    *out = hs.residual;
+    return STC_OK;
+}
+
+stc_status store_vector(stc_handle *h, bool f32, long long s, double *pi, int32_t where) {
+    double *dst = (where == STC_MEM_DEVICE) ? pi : h->io;
+    HIP_TRY(launch_store(f32 ? 4 : 8, h->MP, wbuf(h, f32, s), h->off, h->sizes_d, h->L, h->st, s,
+                         dst, h->stream));
+    if (where == STC_MEM_HOST)
+        HIP_TRY(hipMemcpyAsync(pi, h->io, sizeof(double) * h->N, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return STC_OK;
+}
+
+// Switch the current iterate from the FP32 rotation to the FP64 one at sweep
+// k: W_k and W_{k-1} are widened exactly, so the scale factors stay valid.
+stc_status widen_at(stc_handle *h, long long k) {
+    const size_t vec = (size_t)h->L * h->MP;
+    HIP_TRY(launch_widen((const float *)wbuf(h, true, k), (double *)wbuf(h, false, k), vec,
+                         h->stream));
+    if (k >= 1)
+        HIP_TRY(launch_widen((const float *)wbuf(h, true, k - 1), (double *)wbuf(h, false, k - 1),
+                             vec, h->stream));
+    h->stage32 = false;
+    return STC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *stc_status_string(stc_status s) {
+    switch (s) {
+        case STC_OK: return "STC_OK";
+        case STC_EINVAL: return "STC_EINVAL: invalid argument";
+        case STC_ENOTGEN: return "STC_ENOTGEN: input is not a generator";
+        case STC_ESINGULAR: return "STC_ESINGULAR: singular diagonal block";
+        case STC_EDEGENERATE: return "STC_EDEGENERATE: sweep produced no positive mass";
+        case STC_EMAXIT: return "STC_EMAXIT: maxit reached before tol";
+        case STC_ENOMEM: return "STC_ENOMEM: arena too small";
+        case STC_EDEVICE: return "STC_EDEVICE: HIP error";
+    }
+    return "unknown status";
+}
+
+const char *stc_last_error(void) { return g_err; }
+
+size_t stc_footprint_bytes(const stc_generator *gen, const stc_options *opt) {
+    Layout l;
+    int why;
+    if (!plan(gen, opt, &l, &why)) return 0;
+    return l.total;
+}
+
+stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **out) {
+    if (!g || !o || !out) return fail(STC_EINVAL, "null argument");
+    *out = nullptr;
+    Layout lay;
+    int why = 0;
+    if (!plan(g, o, &lay, &why)) {
+        static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be 1 or 2",
+                                    "m must be in 1..128", "unknown precision"};
+        return fail(STC_EINVAL, "%s", msg[why < 5 ? why : 0]);
+    }
+    if (!g->blocks) return fail(STC_EINVAL, "blocks is NULL");
+    if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
+    if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
+    if (!o->arena) return fail(STC_EINVAL, "arena is NULL");
+    if ((uintptr_t)o->arena % kAlign) return fail(STC_EINVAL, "arena must be 256-byte aligned");
+    if (o->arena_bytes < lay.total)
+        return fail(STC_ENOMEM, "arena holds %zu bytes, %zu needed", o->arena_bytes, lay.total);
+
+    const int L = g->L, m = g->m, b = g->b, MP = lay.MP, NB = lay.NB;
+    std::vector<int> sizes(L, m);
+    if (g->sizes) {
+        for (int i = 0; i < L; ++i) {
+            if (g->sizes[i] < 1 || g->sizes[i] > m)
+                return fail(STC_EINVAL, "sizes[%d] = %d outside 1..%d", i, g->sizes[i], m);
+            sizes[i] = g->sizes[i];
+        }
+    }
+
+    stc_handle *h = new stc_handle();
+    h->L = L; h->m = m; h->b = b; h->MP = MP; h->NB = NB;
+    h->precision = o->precision;
+    h->stair_type = o->stair_type;
+    h->stop = o->stop;
+    h->check_every = o->check_every > 0 ? o->check_every : 1;
+    h->switch_tol = o->switch_tol > 0 ? o->switch_tol : 1e-6;
+    h->stream = (hipStream_t)o->stream;
+    h->lay = lay;
+    h->base = (char *)o->arena;
+    h->sizes = sizes;
+    (void)hipGetDevice(&h->device);
+    h->blk64 = (double *)(h->base + lay.blk64);
+    h->diag64 = (double *)(h->base + lay.diag64);
+    h->blk32 = lay.fp32 ? (float *)(h->base + lay.blk32) : nullptr;
+    h->w64 = (double *)(h->base + lay.w64);
+    h->w32 = lay.fp32 ? (float *)(h->base + lay.w32) : nullptr;
+    h->wres = (double *)(h->base + lay.wres);
+    h->io = (double *)(h->base + lay.io);
+    h->part_sum = (double *)(h->base + lay.part_sum);
+    h->part_diff = (double *)(h->base + lay.part_diff);
+    h->part_aux = (double *)(h->base + lay.part_aux);
+    h->off = (long long *)(h->base + lay.off);
+    h->sizes_d = (int *)(h->base + lay.sizes);
+    h->st = (DevState *)(h->base + lay.state);
+
+    std::vector<long long> off(L + 1, 0);
+    for (int i = 0; i < L; ++i) off[i + 1] = off[i] + sizes[i];
+    h->N = off[L];
+
+    auto cleanup = [&](stc_status s) { delete h; return s; };
+    auto dev = [&](hipError_t e, const char *what) -> stc_status {
+        if (e == hipSuccess) return STC_OK;
+        return fail(STC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+
+    // validate, then pack in the sweep's layout, a chunk of levels at a time
+    const size_t bs = (size_t)MP * MP, ms = (size_t)m * m;
+    const int chunk = std::max(1, (int)std::min<size_t>(L, (64u << 20) / (NB * bs * 8)));
+    std::vector<double> stage_blk((size_t)chunk * NB * bs), stage_diag((size_t)chunk * bs);
+    const double *Qb = g->blocks;
+    auto q_at = [&](int lev, int slot) { return Qb + ((size_t)lev * NB + slot) * ms; };
+    for (int l0 = 0; l0 < L; l0 += chunk) {
+        const int l1 = std::min(L, l0 + chunk);
+        std::fill(stage_blk.begin(), stage_blk.end(), 0.0);
+        std::fill(stage_diag.begin(), stage_diag.end(), 0.0);
+        for (int i = l0; i < l1; ++i) {
+            const int ni = sizes[i];
+            // generator checks on block row i
+            for (int r = 0; r < ni; ++r) {
+                double out = 0.0;
+                for (int d = -b; d <= b; ++d) {
+                    const int k = i + d;
+                    if (k < 0 || k >= L) continue;
+                    const double *row = q_at(i, d + b) + (size_t)r * m;
+                    for (int c = 0; c < sizes[k]; ++c) {
+                        if (d == 0 && c == r) continue;
+                        const double v = row[c];
+                        if (!(v >= 0.0) || !isfinite(v))
+                            return cleanup(fail(STC_ENOTGEN,
+                                                "Q[level %d row %d][level %d col %d] = %g is not a rate",
+                                                i, r, k, c, v));
+                        out += v;
+                    }
+                }
+                const double dg = q_at(i, b)[(size_t)r * m + r];
+                double *D = stage_diag.data() + (size_t)(i - l0) * bs;
+                for (int c = 0; c < ni; ++c) D[(size_t)r * MP + c] = q_at(i, b)[(size_t)r * m + c];
+                if (g->recompute_diagonal) {
+                    D[(size_t)r * MP + r] = -out;
+                } else {
+                    if (!isfinite(dg) || fabs(dg + out) > 1e-10 * std::max(out, 1e-300))
+                        return cleanup(fail(STC_ENOTGEN,
+                                            "row %d of level %d sums to %g, not 0 (diagonal %g)",
+                                            r, i, dg + out, dg));
+                }
+            }
+            // gather-oriented off-diagonal blocks: slot d+b of level i <- Q_{i+d,i}
+            for (int d = -b; d <= b; ++d) {
+                if (d == 0) continue;
+                const int k = i + d;
+                if (k < 0 || k >= L) continue;
+                const double *src = q_at(k, -d + b);
+                double *dst = stage_blk.data() + ((size_t)(i - l0) * NB + (d + b)) * bs;
+                for (int r = 0; r < sizes[k]; ++r)
+                    memcpy(dst + (size_t)r * MP, src + (size_t)r * m, sizeof(double) * sizes[i]);
+            }
+        }
+        stc_status rc;
+        if ((rc = dev(hipMemcpyAsync(h->blk64 + (size_t)l0 * NB * bs, stage_blk.data(),
+                                     sizeof(double) * (size_t)(l1 - l0) * NB * bs,
+                                     hipMemcpyHostToDevice, h->stream), "copy blocks")) != STC_OK)
+            return cleanup(rc);
+        if ((rc = dev(hipMemcpyAsync(h->diag64 + (size_t)l0 * bs, stage_diag.data(),
+                                     sizeof(double) * (size_t)(l1 - l0) * bs,
+                                     hipMemcpyHostToDevice, h->stream), "copy diagonal blocks")) != STC_OK)
+            return cleanup(rc);
+        if ((rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK) return cleanup(rc);
+    }
+    stc_status rc;
+    if ((rc = dev(hipMemcpyAsync(h->off, off.data(), sizeof(long long) * (L + 1),
+                                 hipMemcpyHostToDevice, h->stream), "copy offsets")) != STC_OK)
+        return cleanup(rc);
+    if ((rc = dev(hipMemcpyAsync(h->sizes_d, sizes.data(), sizeof(int) * L, hipMemcpyHostToDevice,
+                                 h->stream), "copy sizes")) != STC_OK)
+        return cleanup(rc);
+    // zero the whole state once (ring included), then the inverse
+    if ((rc = dev(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream), "clear state")) != STC_OK)
+        return cleanup(rc);
+    if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return cleanup(rc);
+    if ((rc = dev(launch_invert(MP, b, h->diag64, h->sizes_d, h->blk64, L, h->st, h->stream),
+                  "invert")) != STC_OK)
+        return cleanup(rc);
+    if (lay.fp32 &&
+        (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * bs, h->stream), "cast")) !=
+            STC_OK)
+        return cleanup(rc);
+    HostState hs;
+    if ((rc = read_state(h, &hs)) != STC_OK) return cleanup(rc);
+    if (hs.bad_blocks)
+        return cleanup(fail(STC_ESINGULAR,
+                            "%d diagonal block(s) are singular: some level has states that "
+                            "never leave it", hs.bad_blocks));
+    *out = h;
+    return STC_OK;
+}
+
+void stc_destroy(stc_handle *h) { delete h; }
+
+stc_status stc_load(stc_handle *h, const double *x, int32_t where) {
+    if (!h) return fail(STC_EINVAL, "null handle");
+    return load_vector(h, x, where);
+}
+
+stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
+    if (!h || nsweeps < 0) return fail(STC_EINVAL, "bad argument");
+    const long long s0 = h->s;
+    for (int64_t j = 1; j <= nsweeps; ++j) {
+        stc_status rc = launch_one_sweep(h, s0 + j, 0.0);
+        if (rc != STC_OK) return rc;
+    }
+    h->s = s0 + nsweeps;
+    if (h->stage32) h->iters32 += nsweeps;
+    if (diffs && nsweeps > 1) {
+        std::vector<double> ring(kRing);
+        HIP_TRY(hipMemcpyAsync(ring.data(), h->st->diff, sizeof(double) * kRing,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (int64_t j = 1; j < nsweeps; ++j) diffs[j - 1] = ring[(s0 + j) & kRingMask];
+    }
+    return STC_OK;
+}
+
+stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, double *ms_b,
+                              double *ms_sweep) {
+    if (!h || nsweeps < 1) return fail(STC_EINVAL, "bad argument");
+    std::vector<hipEvent_t> ev(2 * nsweeps + 1);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    auto destroy = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
+    const bool f32 = h->stage32;
+    const int bytes = f32 ? 4 : 8;
+    const int pA = (h->stair_type == 1) ? 0 : 1, pB = 1 - pA;
+    const int gA = phase_groups(bytes, h->MP, h->L, pA);
+    const int gB = phase_groups(bytes, h->MP, h->L, pB);
+    const long long s0 = h->s;
+    hipError_t err = hipEventRecord(ev[0], h->stream);
+    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j) {
+        const long long s = s0 + j;
+        SweepLaunch a;
+        a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
+        a.w_old = wbuf(h, f32, s - 1);
+        a.w_older = wbuf(h, f32, s - 2);
+        a.w_new = wbuf(h, f32, s);
+        a.part_sum = h->part_sum;
+        a.part_diff = h->part_diff;
+        a.st = h->st;
+        a.L = h->L;
+        a.s = s;
+        a.nslots = gA + gB;
+        a.parity = pA;
+        a.slot0 = 0;
+        err = launch_sweep_phase(bytes, h->MP, h->b, false, a, h->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[2 * j - 1], h->stream);
+        a.parity = pB;
+        a.slot0 = gA;
+        if (err == hipSuccess) err = launch_sweep_phase(bytes, h->MP, h->b, true, a, h->stream);
+        if (err == hipSuccess)
+            err = launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, 0.0,
+                                        h->stream);
+        if (err == hipSuccess) err = hipEventRecord(ev[2 * j], h->stream);
+    }
+    if (err == hipSuccess) err = hipEventSynchronize(ev[2 * nsweeps]);
+    if (err != hipSuccess) {
+        destroy();
+        return fail(STC_EDEVICE, "profiled sweeps: %s", hipGetErrorString(err));
+    }
+    double ta = 0.0, tb = 0.0;
+    for (int64_t j = 1; j <= nsweeps; ++j) {
+        float x = 0.f, y = 0.f;
+        (void)hipEventElapsedTime(&x, ev[2 * j - 2], ev[2 * j - 1]);
+        (void)hipEventElapsedTime(&y, ev[2 * j - 1], ev[2 * j]);
+        ta += x;
+        tb += y;
+    }
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, ev[0], ev[2 * nsweeps]);
+    destroy();
+    h->s = s0 + nsweeps;
+    if (f32) h->iters32 += nsweeps;
+    if (ms_a) *ms_a = ta / nsweeps;
+    if (ms_b) *ms_b = tb / nsweeps;
+    if (ms_sweep) *ms_sweep = (double)tot / nsweeps;
+    return STC_OK;
+}
+
+stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {
+    if (!h) return fail(STC_EINVAL, "null handle");
+    const double sb = h->stage32 ? 4.0 : 8.0;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    double out[2] = {0.0, 0.0};
+    for (int ph = 0; ph < 2; ++ph) {
+        const int par = ph == 0 ? pA : 1 - pA;
+        double blocks = 0.0, vin = 0.0, vout = 0.0;
+        std::vector<char> seen(h->L, 0);
+        for (int i = par; i < h->L; i += 2) {
+            vout += h->sizes[i];
+            for (int d = -h->b; d <= h->b; ++d) {
+                const int k = i + d;
+                if (k < 0 || k >= h->L) continue;
+                // stored block: rows of level k (or i for the inverse) x columns of level i
+                blocks += (double)h->sizes[k] * h->sizes[i];
+                if (d != 0 && !seen[k]) {
+                    seen[k] = 1;
+                    vin += h->sizes[k];
+                }
+            }
+        }
+        out[ph] = sb * (blocks + vin + vout);
+    }
+    if (bytes_a) *bytes_a = out[0];
+    if (bytes_b) *bytes_b = out[1];
+    return STC_OK;
+}
+
+stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *diff_1) {
+    if (!h) return fail(STC_EINVAL, "null handle");
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    const long long cur = hs.stop_flag ? hs.stop_sweep : h->s;
+    if (sweeps) *sweeps = cur;
+    if (stopped) *stopped = hs.stop_flag;
+    if (diff_1) {
+        *diff_1 = INFINITY;
+        if (cur >= 1 && cur < h->s) {
+            rc = read_ring(h, h->st->diff, cur, diff_1);
+            if (rc != STC_OK) return rc;
+        }
+    }
+    if (hs.status == kDevDegenerate) return fail(STC_EDEGENERATE, "e^T z <= 0 after sweep %lld", hs.stop_sweep + 1);
+    return STC_OK;
+}
+
+stc_status stc_store(stc_handle *h, double *pi, int32_t where) {
+    if (!h || !pi) return fail(STC_EINVAL, "null argument");
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    const long long cur = hs.stop_flag ? hs.stop_sweep : h->s;
+    return store_vector(h, h->stage32, cur, pi, where);
+}
+
+stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t where) {
+    if (!h || !x || !res_1) return fail(STC_EINVAL, "null argument");
+    const double *src = x;
+    if (where == STC_MEM_HOST) {
+        HIP_TRY(hipMemcpyAsync(h->io, x, sizeof(double) * h->N, hipMemcpyHostToDevice, h->stream));
+        src = h->io;
+    }
+    // FP64 copy in the padded layout; slot -1 = use x as given
+    HIP_TRY(launch_load(8, h->MP, src, h->off, h->sizes_d, h->L, h->wres, h->part_aux,
+                        (int)h->lay.naux, h->st, -1, h->stream));
+    HIP_TRY(launch_residual(8, h->MP, h->b, h->blk64, h->diag64, h->wres, h->L, h->st, -1,
+                            h->part_aux, h->stream));
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    *res_1 = hs.residual;
+    return STC_OK;
+}
+
+stc_status stc_step(stc_handle *h, const double *x, double *z, double *diff_1, int32_t where) {
+    if (!h || !x || !z) return fail(STC_EINVAL, "null argument");
+    if (x == z) return fail(STC_EINVAL, "z may not alias x");
+    stc_status rc = load_vector(h, x, where);
+    if (rc != STC_OK) return rc;
+    if ((rc = launch_one_sweep(h, 1, 0.0)) != STC_OK) return rc;
+    h->s = 1;
+    if (h->stage32) h->iters32 = 1;
+    HIP_TRY(launch_diff(h->stage32 ? 4 : 8, h->MP, wbuf(h, h->stage32, 1), wbuf(h, h->stage32, 0),
+                        h->L, h->st, 1, h->part_aux, h->stream));
+    HostState hs;
+    if ((rc = read_state(h, &hs)) != STC_OK) return rc;
+    if (hs.status == kDevDegenerate) return fail(STC_EDEGENERATE, "e^T z <= 0");
+    if (diff_1 && (rc = read_ring(h, h->st->diff, 1, diff_1)) != STC_OK) return rc;
+    return store_vector(h, h->stage32, 1, z, where);
+}
+
+stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit, double *pi,
+                     stc_result *res, int32_t where) {
+    if (!h || !pi) return fail(STC_EINVAL, "null argument");
+    if (maxit < 0 || !(tol >= 0.0)) return fail(STC_EINVAL, "need maxit >= 0 and tol >= 0");
+    stc_status rc = load_vector(h, x0, where);
+    if (rc != STC_OK) return rc;
+    const bool mixed = h->precision == STC_MIXED;
+    auto device_tol = [&]() {
+        if (mixed && h->stage32) return h->switch_tol;
+        return h->stop == STC_STOP_DIFF ? tol : 0.0;
+    };
+    long long s = 0, final_k = -1;
+    bool converged = false;
+    HostState hs;
+    while (s < maxit) {
+        const long long n = std::min<long long>(h->check_every, maxit - s);
+        const double dt = device_tol();
+        for (long long j = 1; j <= n; ++j)
+            if ((rc = launch_one_sweep(h, s + j, dt)) != STC_OK) return rc;
+        s += n;
+        h->s = s;
+        if ((rc = read_state(h, &hs)) != STC_OK) return rc;
+        if (hs.status == kDevDegenerate) {
+            final_k = hs.stop_sweep;
+            rc = fail(STC_EDEGENERATE, "e^T z <= 0 after sweep %lld", hs.stop_sweep + 1);
+            store_vector(h, h->stage32, final_k, pi, where);
+            if (res) { res->iters = final_k; res->status = rc; }
+            return rc;
+        }
+        if (hs.stop_flag) {
+            const long long k = hs.stop_sweep;
+            if (mixed && h->stage32) {
+                // FP32 stage done: continue in FP64 from sweep k
+                h->iters32 = k;
+                if ((rc = widen_at(h, k)) != STC_OK) return rc;
+                HIP_TRY(launch_reset_state(h->st, h->stream));
+                s = k;
+                h->s = k;
+                continue;
+            }
+            final_k = k;
+            converged = true;
+            break;
+        }
+        if (h->stop == STC_STOP_RESIDUAL && !(mixed && h->stage32)) {
+            double r;
+            if ((rc = residual_of(h, h->stage32, s, &r)) != STC_OK) return rc;
+            if (r <= tol) {
+                final_k = s;
+                converged = true;
+                break;
+            }
+        }
+    }
+    if (h->stage32 && !mixed) h->iters32 = s;
+    if (final_k < 0) final_k = s;   // maxit reached
+    h->s = final_k;
+    double diff = INFINITY;
+    if (final_k >= 1) {
+        if (!converged || h->stop != STC_STOP_DIFF) {
+            HIP_TRY(launch_diff(h->stage32 ? 4 : 8, h->MP, wbuf(h, h->stage32, final_k),
+                                wbuf(h, h->stage32, final_k - 1), h->L, h->st, final_k,
+                                h->part_aux, h->stream));
+        }
+        if ((rc = read_ring(h, h->st->diff, final_k, &diff)) != STC_OK) return rc;
+    }
+    double r;
+    if ((rc = residual_of(h, h->stage32, final_k, &r)) != STC_OK) return rc;
+    if (!converged) converged = (h->stop == STC_STOP_DIFF) ? (diff <= tol) : (r <= tol);
+    if ((rc = store_vector(h, h->stage32, final_k, pi, where)) != STC_OK) return rc;
+    const stc_status out = converged ? STC_OK : fail(STC_EMAXIT, "maxit = %lld sweeps done, "
+                                                     "stop quantity above tol", (long long)maxit);
+    if (res) {
+        res->residual_1 = r;
+        res->diff_1 = diff;
+        res->iters = final_k;
+        res->iters_fp32 = mixed ? h->iters32 : (h->precision == STC_FP32 ? final_k : 0);
+        res->status = out;
+    }
+    return out;
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+"""Python binding of the staircase solver's C ABI (include/stc.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+libstc.so.  PyTorch provides the device arena (a uint8 tensor sized by
+stc_footprint_bytes) and the stream.  If the library is not built, or no GPU
+is visible, the calls raise; there is no fallback implementation.
+
+The functions keep the C names (stc_setup, stc_solve, ...); ``Solver`` wraps
+them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstc.so")
+
+STC_OK, STC_EINVAL, STC_ENOTGEN, STC_ESINGULAR, STC_EDEGENERATE, STC_EMAXIT, STC_ENOMEM, \
+    STC_EDEVICE = range(8)
+STC_FP64, STC_FP32, STC_MIXED = 0, 1, 2
+STC_STOP_DIFF, STC_STOP_RESIDUAL = 0, 1
+STC_MEM_HOST, STC_MEM_DEVICE = 0, 1
+
+PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
+STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
+
+# every symbol include/stc.h declares
+EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_residual",
+           "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_load", "stc_query",
+           "stc_store", "stc_destroy",
+           "stc_status_string", "stc_last_error")
+
+
+class stc_generator(ctypes.Structure):
+    _fields_ = [("L", c_int32), ("m", c_int32), ("b", c_int32), ("sizes", POINTER(c_int32)),
+                ("blocks", POINTER(c_double)), ("recompute_diagonal", c_int32)]
+
+
+class stc_options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("stair_type", c_int32), ("stop", c_int32),
+                ("check_every", c_int32), ("switch_tol", c_double), ("stream", c_void_p),
+                ("arena", c_void_p), ("arena_bytes", c_size_t)]
+
+
+class stc_result(ctypes.Structure):
+    _fields_ = [("residual_1", c_double), ("diff_1", c_double), ("iters", c_int64),
+                ("iters_fp32", c_int64), ("status", c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libstc.so and declare its signatures; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    H = c_void_p
+    dp = POINTER(c_double)
+    lib.stc_footprint_bytes.argtypes = [POINTER(stc_generator), POINTER(stc_options)]
+    lib.stc_footprint_bytes.restype = c_size_t
+    lib.stc_setup.argtypes = [POINTER(stc_generator), POINTER(stc_options), POINTER(H)]
+    lib.stc_solve.argtypes = [H, c_void_p, c_double, c_int64, c_void_p, POINTER(stc_result),
+                              c_int32]
+    lib.stc_step.argtypes = [H, c_void_p, c_void_p, dp, c_int32]
+    lib.stc_residual.argtypes = [H, c_void_p, dp, c_int32]
+    lib.stc_sweeps.argtypes = [H, c_int64, c_void_p]
+    lib.stc_profile_sweeps.argtypes = [H, c_int64, dp, dp, dp]
+    lib.stc_phase_bytes.argtypes = [H, dp, dp]
+    lib.stc_load.argtypes = [H, c_void_p, c_int32]
+    lib.stc_query.argtypes = [H, POINTER(c_int64), POINTER(c_int32), dp]
+    lib.stc_store.argtypes = [H, c_void_p, c_int32]
+    lib.stc_destroy.argtypes = [H]
+    lib.stc_destroy.restype = None
+    lib.stc_status_string.argtypes = [c_int32]
+    lib.stc_status_string.restype = ctypes.c_char_p
+    lib.stc_last_error.argtypes = []
+    lib.stc_last_error.restype = ctypes.c_char_p
+    for name in ("stc_setup", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
+                 "stc_profile_sweeps", "stc_phase_bytes", "stc_load", "stc_query", "stc_store"):
+        getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(STC_OK,)):
+    if status in allow:
+        return status
+    lib = load_library()
+    raise StcError(status, lib.stc_last_error().decode() or lib.stc_status_string(status).decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_generator(blocks: np.ndarray, sizes, b: int, recompute_diagonal: bool = False):
+    """Marshal [L][2b+1][m][m] blocks (+ sizes) into the C struct; returns
+    (struct, keep-alive tuple)."""
+    blocks = _f64(blocks)
+    L, nb, m, m2 = blocks.shape
+    if nb != 2 * b + 1 or m != m2:
+        raise ValueError("blocks must have shape [L, 2b+1, m, m]")
+    sz = None if sizes is None else np.ascontiguousarray(sizes, dtype=np.int32)
+    g = stc_generator(L, m, b,
+                      sz.ctypes.data_as(POINTER(c_int32)) if sz is not None else None,
+                      blocks.ctypes.data_as(POINTER(c_double)), int(bool(recompute_diagonal)))
+    return g, (blocks, sz)
+
+
+def make_options(precision="fp64", stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
+                 stream=0, arena=0, arena_bytes=0):
+    return stc_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
+                       int(stair_type), STOPS[stop] if isinstance(stop, str) else int(stop),
+                       int(check_every), float(switch_tol), stream or None, arena or None,
+                       int(arena_bytes))
+
+
+def stc_footprint_bytes(gen: stc_generator, opt: stc_options) -> int:
+    return int(load_library().stc_footprint_bytes(byref(gen), byref(opt)))
+
+
+def stc_setup(gen: stc_generator, opt: stc_options) -> c_void_p:
+    h = c_void_p()
+    _check(load_library().stc_setup(byref(gen), byref(opt), byref(h)))
+    return h
+
+
+def _vec_arg(x):
+    """(pointer, where) for a numpy array (host) or a torch CUDA tensor (device)."""
+    if x is None:
+        return None, STC_MEM_HOST
+    if hasattr(x, "data_ptr") and getattr(x, "is_cuda", False):
+        if x.dtype.__repr__() != "torch.float64" or not x.is_contiguous():
+            raise ValueError("device vectors must be contiguous float64 tensors")
+        return c_void_p(x.data_ptr()), STC_MEM_DEVICE
+    if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.flags.c_contiguous):
+        raise ValueError("host vectors must be contiguous float64 numpy arrays")
+    return c_void_p(x.ctypes.data), STC_MEM_HOST
+
+
+def stc_solve(h, x0, tol: float, maxit: int, pi, allow_maxit: bool = True) -> dict:
+    px, w1 = _vec_arg(x0)
+    pp, w2 = _vec_arg(pi)
+    if x0 is not None and w1 != w2:
+        raise ValueError("x0 and pi must both be host or both be device memory")
+    res = stc_result()
+    allow = (STC_OK, STC_EMAXIT) if allow_maxit else (STC_OK,)
+    _check(load_library().stc_solve(h, px, float(tol), int(maxit), pp, byref(res), w2), allow)
+    return res.as_dict()
+
+
+def stc_step(h, x, z) -> float:
+    px, w1 = _vec_arg(x)
+    pz, w2 = _vec_arg(z)
+    if w1 != w2:
+        raise ValueError("x and z must both be host or both be device memory")
+    d = c_double()
+    _check(load_library().stc_step(h, px, pz, byref(d), w1))
+    return d.value
+
+
+def stc_residual(h, x) -> float:
+    px, w = _vec_arg(x)
+    r = c_double()
+    _check(load_library().stc_residual(h, px, byref(r), w))
+    return r.value
+
+
+def stc_sweeps(h, nsweeps: int, diffs: np.ndarray | None = None):
+    p = None if diffs is None else c_void_p(diffs.ctypes.data)
+    _check(load_library().stc_sweeps(h, int(nsweeps), p))
+
+
+def stc_profile_sweeps(h, nsweeps: int):
+    a, b, t = c_double(), c_double(), c_double()
+    _check(load_library().stc_profile_sweeps(h, int(nsweeps), byref(a), byref(b), byref(t)))
+    return a.value, b.value, t.value
+
+
+def stc_phase_bytes(h):
+    a, b = c_double(), c_double()
+    _check(load_library().stc_phase_bytes(h, byref(a), byref(b)))
+    return a.value, b.value
+
+
+def stc_load(h, x):
+    px, w = _vec_arg(x)
+    _check(load_library().stc_load(h, px, w))
+
+
+def stc_query(h):
+    s, f, d = c_int64(), c_int32(), c_double()
+    _check(load_library().stc_query(h, byref(s), byref(f), byref(d)))
+    return s.value, bool(f.value), d.value
+
+
+def stc_store(h, pi):
+    pp, w = _vec_arg(pi)
+    _check(load_library().stc_store(h, pp, w))
+
+
+def stc_destroy(h):
+    if h:
+        load_library().stc_destroy(h)
+
+
+class Solver:
+    """One chain on the current GPU: owns the torch arena and the handle."""
+
+    def __init__(self, blocks: np.ndarray, sizes, b: int, *, precision="fp64", stair_type=1,
+                 stop="diff", check_every=1, switch_tol=0.0, recompute_diagonal=False,
+                 device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the staircase solver needs a GPU")
+        load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
+        self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
+                                stream=self.stream.cuda_stream)
+        need = stc_footprint_bytes(self.gen, self.opt)
+        if need == 0:
+            raise StcError(STC_EINVAL, "unsupported generator shape or options")
+        self.arena = torch.empty(need, dtype=torch.uint8, device=self.device)
+        self.opt.arena = self.arena.data_ptr()
+        self.opt.arena_bytes = need
+        self.footprint = need
+        self.N = int(np.sum(sizes)) if sizes is not None else self.gen.L * self.gen.m
+        with torch.cuda.device(self.device):
+            self.h = stc_setup(self.gen, self.opt)
+        self._keep = None   # host inputs were copied during setup
+
+    def solve(self, x0=None, tol=1e-9, maxit=10_000, allow_maxit=True):
+        pi = np.empty(self.N)
+        x = None if x0 is None else _f64(x0)
+        info = stc_solve(self.h, x, tol, maxit, pi, allow_maxit)
+        return pi, info
+
+    def step(self, x):
+        z = np.empty(self.N)
+        d = stc_step(self.h, _f64(x), z)
+        return z, d
+
+    def residual(self, x) -> float:
+        return stc_residual(self.h, _f64(x))
+
+    def load(self, x):
+        stc_load(self.h, None if x is None else (_f64(x) if isinstance(x, np.ndarray) else x))
+
+    def sweeps(self, n: int, with_diffs: bool = False):
+        if with_diffs:
+            d = np.empty(max(n - 1, 0))
+            stc_sweeps(self.h, n, d)
+            return d
+        stc_sweeps(self.h, n)
+        return None
+
+    def query(self):
+        return stc_query(self.h)
+
+    def store(self):
+        pi = np.empty(self.N)
+        stc_store(self.h, pi)
+        return pi
+
+    def close(self):
+        if getattr(self, "h", None):
+            stc_destroy(self.h)
+            self.h = None
+        self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,98 @@
+"""CPU checks of the boundary: the library loads, exports every symbol the
+header declares, and the host-side validation rejects bad input without a GPU
+(no kernel is launched on these paths)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2302_07551_amd import build as hipbuild
+from paper_2302_07551_amd import stc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(stc.LIB_PATH):
+        hipbuild.build()
+    return stc.load_library()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "stc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(stc.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        assert lib.stc_status_string(code).decode().startswith("STC_")
+
+
+def _gen_opt(g, **kw):
+    gen, keep = stc.make_generator(g.blocks, g.sizes, g.b)
+    opt = stc.make_options(**kw)
+    return gen, opt, keep
+
+
+def test_footprint_formula(lib):
+    g = synth.qbd(10, 12, 1)
+    gen, opt, _ = _gen_opt(g)
+    fp64 = stc.stc_footprint_bytes(gen, opt)
+    MP, NB, L = 16, 3, 10
+    assert fp64 >= L * NB * MP * MP * 8 + L * MP * MP * 8
+    gen, opt, _ = _gen_opt(g, precision="mixed")
+    mixed = stc.stc_footprint_bytes(gen, opt)
+    assert mixed >= fp64 + L * NB * MP * MP * 4
+
+
+def test_footprint_rejects_bad_shapes(lib):
+    g = synth.qbd(4, 4, 2)
+    gen, opt, _ = _gen_opt(g)
+    gen.L = 1
+    assert stc.stc_footprint_bytes(gen, opt) == 0
+    gen.L, gen.m = 4, 200
+    assert stc.stc_footprint_bytes(gen, opt) == 0
+    gen.m, gen.b = 4, 3
+    assert stc.stc_footprint_bytes(gen, opt) == 0
+
+
+def test_setup_rejects_small_arena_before_touching_the_device(lib):
+    g = synth.qbd(4, 4, 3)
+    gen, opt, _ = _gen_opt(g)
+    opt.arena = 4096
+    opt.arena_bytes = 16
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    assert e.value.status == stc.STC_ENOMEM
+
+
+def test_setup_rejects_bad_arguments(lib):
+    g = synth.qbd(4, 4, 3)
+    gen, opt, _ = _gen_opt(g, stair_type=3)
+    opt.arena, opt.arena_bytes = 4096, 1 << 30
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    assert e.value.status == stc.STC_EINVAL
+    gen, opt, _ = _gen_opt(g)
+    opt.arena, opt.arena_bytes = 4096 + 8, 1 << 30
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    assert e.value.status == stc.STC_EINVAL and "aligned" in str(e.value)
+
+
+def test_make_generator_checks_shape():
+    with pytest.raises(ValueError):
+        stc.make_generator(np.zeros((4, 3, 4, 5)), None, 1)

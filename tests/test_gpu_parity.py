@@ -1,0 +1,272 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Tolerances (FP64): one sweep from the same x agrees to 1e-13 in the 1-norm
+(different but exact-in-real-arithmetic ways of applying A_ii^{-1}: explicit
+inverse vs LU solve, and different summation orders); converged vectors agree
+with the direct reference (GTH / level reduction) to 1e-10; iteration counts
+with the oracle's to max(2, 1 %).  FP32 sweeps agree with the FP64 oracle to
+1e-5 per sweep (storage rounding of blocks and vector, ~1e-7 relative).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, gth, level_reduction, staircase
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2302_07551_amd import stc
+    stc.load_library()
+
+
+def _solver(g, **kw):
+    from paper_2302_07551_amd import Solver
+    return Solver(g.blocks, g.sizes, g.b, **kw)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+SHAPES = [
+    # (name, generator factory)
+    ("qbd_L64_m16", lambda: synth.qbd(64, 16, synth.config_seed(0))),
+    ("qbd_L9_m8_ragged", lambda: synth.qbd(9, 8, 5, last=3)),
+    ("qbd_L2_m4", lambda: synth.qbd(2, 4, 6)),
+    ("qbd_L33_m12_pad", lambda: synth.qbd(33, 12, 7, last=7)),
+    ("qbd_L20_m32", lambda: synth.qbd(20, 32, 8)),
+    ("qbd_L13_m64", lambda: synth.qbd(13, 64, 9, last=40)),
+    ("qbd_L7_m128", lambda: synth.qbd(7, 128, 10, last=100)),
+    ("band_L17_m16", lambda: synth.banded(17, 16, 11, b=2, density=0.3)),
+    ("band_L10_m128", lambda: synth.banded(10, 128, 12, b=2, last=77)),
+    ("bd_L50_m1", lambda: synth.birth_death(np.linspace(0.5, 1.0, 50), np.linspace(1.0, 0.8, 50))),
+]
+
+
+@pytest.mark.parametrize("name,make", SHAPES, ids=[s[0] for s in SHAPES])
+@pytest.mark.parametrize("stair_type", [1, 2])
+def test_step_fp64_matches_oracle_sweep(name, make, stair_type):
+    g = make()
+    _say(f"step fp64 {name} type {stair_type}")
+    x = synth.positive_start(g, 123)
+    s = _solver(g, stair_type=stair_type)
+    z, d = s.step(x)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x,
+                                       stair_type)
+    assert np.abs(z - zr).sum() <= 1e-13
+    assert abs(d - dr) <= 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("name,make", SHAPES[:8], ids=[s[0] for s in SHAPES[:8]])
+def test_step_fp32_matches_oracle_sweep(name, make):
+    g = make()
+    _say(f"step fp32 {name}")
+    x = synth.positive_start(g, 321)
+    s = _solver(g, precision="fp32")
+    z, d = s.step(x)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x, 1)
+    assert np.abs(z - zr).sum() <= 1e-5
+    assert abs(d - dr) <= 1e-5
+    s.close()
+
+
+def test_repeated_steps_track_oracle():
+    g = synth.qbd(24, 16, 31, last=9)
+    s = _solver(g)
+    sysb = staircase.BlockSystem(g.blocks, g.sizes, g.b)
+    x = synth.positive_start(g, 5)
+    xr = x.copy()
+    for _ in range(25):
+        x, _ = s.step(x)
+        xr, _ = staircase.staircase_sweep(sysb, xr, 1)
+    assert np.abs(x - xr).sum() <= 1e-12
+    s.close()
+
+
+def test_small_config_converged_parity():
+    """64 levels x m=16, stop ||Q^T x||_1 < 1e-12 (the small QBD workload)."""
+    g = synth.qbd(64, 16, synth.config_seed(0))
+    ref = gth.gth(dense.assemble_Q(g.blocks, g.sizes, g.b))
+    s = _solver(g, stop="residual", check_every=1)
+    pi, info = s.solve(tol=1e-12, maxit=100000, allow_maxit=False)
+    o = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-12, maxit=100000,
+                                  stop=staircase.STOP_RESIDUAL)
+    _say(f"C0: gpu iters {info['iters']} oracle {o.iters} err {np.abs(pi - ref).sum():.2e}")
+    assert np.abs(pi - ref).sum() <= 1e-10
+    assert info["residual_1"] <= 1e-12
+    assert abs(info["iters"] - o.iters) <= max(2, 0.01 * o.iters)
+    assert abs(dense.residual_1(g.blocks, g.sizes, g.b, pi) - info["residual_1"]) <= 1e-14
+
+
+@pytest.mark.parametrize("stair_type", [1, 2])
+def test_diff_stop_iteration_count_exact(stair_type):
+    g = synth.qbd(40, 8, 41, last=5)
+    s = _solver(g, stair_type=stair_type, check_every=7)
+    pi, info = s.solve(tol=1e-11, maxit=20000, allow_maxit=False)
+    o = staircase.staircase_solve(g.blocks, g.sizes, g.b, stair_type=stair_type, tol=1e-11,
+                                  maxit=20000)
+    assert abs(info["iters"] - o.iters) <= 1
+    assert np.abs(pi - o.x).sum() <= 1e-12
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    assert np.abs(pi - ref).sum() <= 1e-9
+
+
+def test_banded_converged_parity():
+    """Block-pentadiagonal chain with a planted stationary vector.  Its rates
+    are large (q = w / pi), so ||Q^T pi*||_1 itself is ~8e-13 and a residual
+    stop below that cannot be met; stop on the change instead."""
+    g, pstar = synth.planted_reversible(24, 16, 51, b=2)
+    s = _solver(g, stop="diff", check_every=5)
+    pi, info = s.solve(tol=1e-15, maxit=200000, allow_maxit=False)
+    o = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-15, maxit=200000)
+    assert np.abs(pi - pstar).sum() <= 1e-10
+    assert abs(info["iters"] - o.iters) <= max(2, 0.01 * o.iters)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_reduced_precision_solve(precision):
+    g = synth.qbd(48, 16, 61)
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    s = _solver(g, precision=precision, stop="residual", check_every=4, switch_tol=1e-6)
+    if precision == "mixed":
+        pi, info = s.solve(tol=1e-12, maxit=50000, allow_maxit=False)
+        _say(f"mixed: iters {info['iters']} fp32 {info['iters_fp32']} err {np.abs(pi - ref).sum():.2e}")
+        assert np.abs(pi - ref).sum() <= 1e-10
+        assert 0 < info["iters_fp32"] < info["iters"]
+    else:
+        pi, info = s.solve(tol=1e-6, maxit=2000)
+        assert np.abs(pi - ref).sum() <= 1e-4
+        assert info["iters_fp32"] == info["iters"]
+
+
+def test_residual_matches_oracle():
+    g = synth.banded(12, 32, 71, b=2, last=20)
+    x = np.random.default_rng(3).standard_normal(g.N)
+    s = _solver(g)
+    r = s.residual(x)
+    assert abs(r - dense.residual_1(g.blocks, g.sizes, g.b, x)) <= 1e-12 * max(1.0, r)
+
+
+def test_large_qbd_step_parity_full_size():
+    """4096 levels x m=64 (the bandwidth workload) in the launch configuration
+    the benchmark times: one full sweep against the oracle sweep."""
+    g = synth.qbd(4096, 64, synth.config_seed(1))
+    x = synth.positive_start(g, 9)
+    s = _solver(g)
+    z, d = s.step(x)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x, 1)
+    _say(f"C1 step: |z-zr|_1 = {np.abs(z - zr).sum():.2e}")
+    assert np.abs(z - zr).sum() <= 1e-13
+    assert abs(d - dr) <= 1e-13
+    # sweeps on the resident iterate continue the same recurrence
+    s.load(x)
+    s.sweeps(3)
+    z3 = s.store()
+    xr = x
+    for _ in range(3):
+        xr, _ = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), xr, 1)
+    assert np.abs(z3 - xr).sum() <= 1e-13
+    s.close()
+
+
+def test_deterministic_bitwise():
+    g = synth.qbd(64, 16, 81)
+    a = _solver(g)
+    p1, i1 = a.solve(tol=1e-12, maxit=10000)
+    p2, i2 = a.solve(tol=1e-12, maxit=10000)
+    assert i1["iters"] == i2["iters"]
+    assert np.array_equal(p1, p2)
+
+
+def test_device_pointers_match_host():
+    g = synth.qbd(16, 16, 91, last=11)
+    from paper_2302_07551_amd import stc
+    s = _solver(g)
+    x = synth.positive_start(g, 2)
+    z_host, d_host = s.step(x)
+    xd = torch.tensor(x, dtype=torch.float64, device="cuda")
+    zd = torch.empty_like(xd)
+    d_dev = stc.stc_step(s.h, xd, zd)
+    assert np.array_equal(zd.cpu().numpy(), z_host) and d_dev == d_host
+    pid = torch.empty_like(xd)
+    info = stc.stc_solve(s.h, xd, 1e-12, 5000, pid)
+    pih, info_h = s.solve(x0=x, tol=1e-12, maxit=5000)
+    assert np.array_equal(pid.cpu().numpy(), pih) and info["iters"] == info_h["iters"]
+
+
+# ---------------------------------------------------------------------------
+# error paths (inputs that the host or the kernels' own checks turn into codes)
+# ---------------------------------------------------------------------------
+def test_not_a_generator():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(6, 4, 101)
+    g.blocks[2, 2, 1, 0] = -0.5
+    with pytest.raises(stc.StcError) as e:
+        _solver(g)
+    assert e.value.status == stc.STC_ENOTGEN
+    g = synth.qbd(6, 4, 102)
+    g.blocks[3, 1, 0, 0] += 0.25
+    with pytest.raises(stc.StcError) as e:
+        _solver(g)
+    assert e.value.status == stc.STC_ENOTGEN
+
+
+def test_singular_diagonal_block():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(6, 4, 103)
+    # level 3 never leaves itself: drop its up and down rates, refix the diagonal
+    g.blocks[3, 0] = 0.0
+    g.blocks[3, 2] = 0.0
+    ar = np.arange(4)
+    g.blocks[3, 1, ar, ar] = 0.0
+    g.blocks[3, 1, ar, ar] = -g.blocks[3, 1].sum(axis=1)
+    with pytest.raises(stc.StcError) as e:
+        _solver(g)
+    assert e.value.status == stc.STC_ESINGULAR
+
+
+def test_bad_start_vector():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(6, 4, 104)
+    s = _solver(g)
+    x = np.full(g.N, 1.0 / g.N)
+    x[3] = -0.1
+    with pytest.raises(stc.StcError) as e:
+        s.solve(x0=x)
+    assert e.value.status == stc.STC_EINVAL
+    x[3] = np.nan
+    with pytest.raises(stc.StcError) as e:
+        s.solve(x0=x)
+    assert e.value.status == stc.STC_EINVAL
+
+
+def test_degenerate_start():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(6, 4, 105)
+    s = _solver(g)
+    x = np.zeros(g.N)
+    x[:4] = 0.25          # level 0 only: a phase-A level of stair type 1
+    with pytest.raises(stc.StcError) as e:
+        s.step(x)
+    assert e.value.status == stc.STC_EDEGENERATE
+
+
+def test_maxit_returns_last_iterate():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(30, 8, 106)
+    s = _solver(g)
+    pi, info = s.solve(tol=1e-30, maxit=37)
+    assert info["status"] == stc.STC_EMAXIT and info["iters"] == 37
+    o = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-30, maxit=37)
+    assert np.abs(pi - o.x).sum() <= 1e-13
+    assert abs(info["diff_1"] - o.err) <= 1e-13
