@@ -103,6 +103,8 @@ def main():
     t_setup = time.perf_counter() - t0
     print(f"# generated in {t_gen:.1f}s, setup in {t_setup:.2f}s, arena "
           f"{solver.footprint / 2**20:.0f} MiB", file=sys.stderr, flush=True)
+    # pick the sweep kernels' launch variant for this chain
+    tuned_ms, _ = stc.stc_autotune(solver.h, 20)
 
     solver.load(None)
     solver.sweeps(args.warmup)
@@ -117,7 +119,7 @@ def main():
 
     # per-launch device times of the two phase kernels (HIP events on the
     # library's stream around every launch)
-    ms_a, ms_b, ms_sw = stc.stc_profile_sweeps(solver.h, args.steps)
+    ms_a, ms_b, ms_fin, ms_sw = stc.stc_profile_sweeps(solver.h, args.steps)
     bytes_a, bytes_b = stc.stc_phase_bytes(solver.h)
     bytes_sweep = bytes_a + bytes_b
     value = bytes_sweep / (ms_per_step * 1e-3) / 1e9
@@ -146,6 +148,9 @@ def main():
                      "bytes_per_launch": bytes_a, "ms_per_launch": round(ms_a, 5)},
         "phase_b": {"ms_per_launch": round(ms_b, 5), "bytes_per_launch": bytes_b,
                     "GB/s": round(bytes_b / (ms_b * 1e-3) / 1e9, 1)},
+        "finalize_ms_per_launch": round(ms_fin, 5),
+        "variant": {"fp64": stc.stc_get_variant(solver.h, stc.STC_FP64),
+                    "autotune_ms_per_sweep": round(tuned_ms, 5)},
         "sweeps_per_s": round(1e3 / ms_per_step, 1),
     }
 

@@ -148,11 +148,28 @@ stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t w
 stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs);
 
 /* Measurement form of stc_sweeps: the same sweeps, with a HIP event recorded
- * on the handle's stream before and after every phase launch.  Returns the
- * mean device time per launch of phase A and of phase B and the mean time of
- * a whole sweep, in milliseconds (any pointer may be NULL). */
+ * on the handle's stream after every launch.  Returns the mean device time
+ * of the phase-A launch, the phase-B launch and the finalize launch, and of a
+ * whole sweep, in milliseconds (any pointer may be NULL). */
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_phase_a,
-                              double *ms_phase_b, double *ms_sweep);
+                              double *ms_phase_b, double *ms_finalize, double *ms_sweep);
+
+/* Launch variants of the sweep kernels.  A variant fixes the thread shape of
+ * a level (8 or 4 row groups per block) and whether block streams use
+ * non-temporal loads; the result of a sweep does not depend on it beyond
+ * rounding order.  stage is STC_FP64 or STC_FP32 (the precision of the
+ * sweeps the variant applies to).  setup picks a default from the block
+ * size and the bytes of the blocks. */
+int32_t stc_variant_count(void);
+stc_status stc_set_variant(stc_handle *h, int32_t stage, int32_t variant);
+stc_status stc_get_variant(stc_handle *h, int32_t stage, int32_t *variant);
+
+/* Autotuner: for each precision stage the handle sweeps in, time every
+ * variant over trial_sweeps sweeps of this chain (after 3 warm-up sweeps,
+ * from e/N) and keep the fastest.  Returns the best mean sweep times (ms, may
+ * be NULL).  It moves the handle's iterate: the handle is left loaded with
+ * e/N, so call it before stc_load / stc_sweeps (stc_solve reloads anyway). */
+stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, double *ms_fp32);
 
 /* Algorithmic HBM bytes of one launch of phase A and of phase B for this
  * handle's current precision: every stored block the phase reads once, the

@@ -49,8 +49,9 @@ struct SweepLaunch {
 
 // Host-visible launchers (stc_kernels.hip).  Each returns a hipError_t.
 int supported_mp(int m);   // padded block size for m, or 0
-int phase_groups(int precision_bytes, int MP, int L, int parity);
-hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b,
+int variant_count();
+int phase_groups(int precision_bytes, int MP, int L, int parity, int variant);
+hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, int variant,
                               const SweepLaunch &a, hipStream_t stream);
 hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
                                  DevState *st, long long s, double tol, hipStream_t stream);

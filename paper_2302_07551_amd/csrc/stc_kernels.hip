@@ -49,17 +49,34 @@ struct Vec16<float> {
 };
 
 // Thread geometry of one level ("team"): CT lanes span a block row with
-// 16-byte loads, R row groups split the rows, LPW levels share a workgroup.
-template <typename T, int MP>
+// 16-byte loads, R row groups (RG requested) split the rows, LPW levels share
+// a workgroup.
+template <typename T, int MP, int RG = 8>
 struct Tile {
     static constexpr int VEC = 16 / (int)sizeof(T);
     static constexpr int CT = MP / VEC;
-    static constexpr int TS = (CT * 8 <= kWG) ? CT * 8 : kWG;
+    static constexpr int TS = (CT * RG <= kWG) ? CT * RG : kWG;
     static constexpr int R = TS / CT;
     static constexpr int RPT = MP / R;
     static constexpr int LPW = kWG / TS;
     static constexpr int PF = RPT < 8 ? RPT : 8;   // W_i rows prefetched per thread
 };
+
+// Launch variants of the sweep kernels (picked per chain by the autotuner):
+//   bit 0: 4 row groups per level instead of 8 (more levels per workgroup,
+//          longer per-thread row streams)
+//   bit 1: non-temporal block loads (streamed blocks bypass cache allocation,
+//          so the iterate vectors stay cached; best once the blocks exceed
+//          the last-level cache)
+constexpr int kVariants = 4;
+__host__ __device__ constexpr int variant_rg(int v) { return (v & 1) ? 4 : 8; }
+__host__ __device__ constexpr bool variant_nt(int v) { return (v & 2) != 0; }
+
+template <typename VT, bool NT>
+__device__ inline VT stream_load(const VT *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -96,9 +113,9 @@ __device__ inline double block_max(double v, double *sh) {
 // ---------------------------------------------------------------------------
 // half-sweep
 // ---------------------------------------------------------------------------
-template <typename T, int MP, int B, bool PHB>
+template <typename T, int MP, int B, bool PHB, int RG, bool NT>
 __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
-    using TL = Tile<T, MP>;
+    using TL = Tile<T, MP, RG>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
     constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
@@ -137,7 +154,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int row = g + R * q;
-            const VT blkv = *(const VT *)(gb + (size_t)row * MP);
+            const VT blkv = stream_load<VT, NT>((const VT *)(gb + (size_t)row * MP));
             acc += blkv * (v[row] * vs);
         }
     }
@@ -145,7 +162,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     VT vpre[PF];
     const T *wb = base + (size_t)B * BS + c * VEC;
 #pragma unroll
-    for (int q = 0; q < PF; ++q) vpre[q] = *(const VT *)(wb + (size_t)(g + R * q) * MP);
+    for (int q = 0; q < PF; ++q)
+        vpre[q] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * q) * MP));
 
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc[e];
@@ -163,7 +181,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int row = g + R * q;
-        const VT wv = (q < PF) ? vpre[q < PF ? q : 0] : *(const VT *)(wb + (size_t)row * MP);
+        const VT wv = (q < PF) ? vpre[q < PF ? q : 0]
+                               : stream_load<VT, NT>((const VT *)(wb + (size_t)row * MP));
         acc2 += wv * rv[team][row];
     }
 #pragma unroll
@@ -200,7 +219,9 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
                                                          const double *part_diff, int nslots,
                                                          DevState *st, long long s, double tol) {
     __shared__ double sh[kWG / 64];
-    if (st->stop_flag) return;
+    // the flag is read alongside the partials (not before them); after a stop
+    // the partials are stale and nothing is written
+    const int stopped = st->stop_flag;
     double s1 = 0.0, s2 = 0.0;
     for (int j = threadIdx.x; j < nslots; j += kWG) {
         s1 += part_sum[j];
@@ -208,7 +229,7 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
     }
     s1 = block_sum(s1, sh);
     s2 = block_sum(s2, sh);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && !stopped) {
         st->last_sweep = s;
         if (!(s1 > 0.0) || !isfinite(s1)) {
             st->status = kDevDegenerate;
@@ -268,7 +289,7 @@ template <typename T, int MP, int B>
 __global__ __launch_bounds__(kWG) void k_residual(const double *blk, const double *diag,
                                                    const T *w, int L, const DevState *st,
                                                    long long slot, double *part) {
-    using TL = Tile<double, MP>;
+    using TL = Tile<double, MP, 8>;
     using VT = typename Vec16<double>::type;
     constexpr int NB = 2 * B + 1;
     constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
@@ -296,7 +317,7 @@ __global__ __launch_bounds__(kWG) void k_residual(const double *blk, const doubl
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 const int row = g + R * q;
-                const VT bv = *(const VT *)(gb + (size_t)row * MP);
+                const VT bv = stream_load<VT, true>((const VT *)(gb + (size_t)row * MP));
                 acc += bv * ((double)v[row] * inv);
             }
         }
@@ -465,59 +486,77 @@ int supported_mp(int m) {
     return mp;
 }
 
-template <typename T>
+template <typename T, int RG>
 static int lpw_of(int MP) {
     switch (MP) {
-        case 8: return Tile<T, 8>::LPW;
-        case 16: return Tile<T, 16>::LPW;
-        case 32: return Tile<T, 32>::LPW;
-        case 64: return Tile<T, 64>::LPW;
-        case 128: return Tile<T, 128>::LPW;
+        case 8: return Tile<T, 8, RG>::LPW;
+        case 16: return Tile<T, 16, RG>::LPW;
+        case 32: return Tile<T, 32, RG>::LPW;
+        case 64: return Tile<T, 64, RG>::LPW;
+        case 128: return Tile<T, 128, RG>::LPW;
     }
     return 1;
 }
 
-int phase_groups(int precision_bytes, int MP, int L, int parity) {
+int variant_count() { return kVariants; }
+
+int phase_groups(int precision_bytes, int MP, int L, int parity, int variant) {
     const int levels = (L - parity + 1) / 2;
-    const int lpw = precision_bytes == 8 ? lpw_of<double>(MP) : lpw_of<float>(MP);
+    const bool rg4 = variant_rg(variant) == 4;
+    int lpw;
+    if (precision_bytes == 8) lpw = rg4 ? lpw_of<double, 4>(MP) : lpw_of<double, 8>(MP);
+    else lpw = rg4 ? lpw_of<float, 4>(MP) : lpw_of<float, 8>(MP);
     return (levels + lpw - 1) / lpw;
 }
 
 int reduce_groups(int MP, int L) {
-    const int lpw = lpw_of<double>(MP);
+    const int lpw = lpw_of<double, 8>(MP);
     return (L + lpw - 1) / lpw;
 }
 
-template <typename T, int MP, int B>
-static hipError_t sweep_mpb(bool phase_b, const SweepLaunch &a, hipStream_t s) {
-    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity);
+template <typename T, int MP, int B, int RG, bool NT>
+static hipError_t sweep_v(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s) {
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, variant);
     if (groups <= 0) return hipSuccess;
     if (phase_b)
-        hipLaunchKernelGGL((k_sweep<T, MP, B, true>), dim3(groups), dim3(kWG), 0, s, a);
+        hipLaunchKernelGGL((k_sweep<T, MP, B, true, RG, NT>), dim3(groups), dim3(kWG), 0, s, a);
     else
-        hipLaunchKernelGGL((k_sweep<T, MP, B, false>), dim3(groups), dim3(kWG), 0, s, a);
+        hipLaunchKernelGGL((k_sweep<T, MP, B, false, RG, NT>), dim3(groups), dim3(kWG), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int B>
-static hipError_t sweep_b(int MP, bool phase_b, const SweepLaunch &a, hipStream_t s) {
-    switch (MP) {
-        case 8: return sweep_mpb<T, 8, B>(phase_b, a, s);
-        case 16: return sweep_mpb<T, 16, B>(phase_b, a, s);
-        case 32: return sweep_mpb<T, 32, B>(phase_b, a, s);
-        case 64: return sweep_mpb<T, 64, B>(phase_b, a, s);
-        case 128: return sweep_mpb<T, 128, B>(phase_b, a, s);
+template <typename T, int MP, int B>
+static hipError_t sweep_mpb(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s) {
+    switch (variant) {
+        case 0: return sweep_v<T, MP, B, variant_rg(0), variant_nt(0)>(phase_b, 0, a, s);
+        case 1: return sweep_v<T, MP, B, variant_rg(1), variant_nt(1)>(phase_b, 1, a, s);
+        case 2: return sweep_v<T, MP, B, variant_rg(2), variant_nt(2)>(phase_b, 2, a, s);
+        case 3: return sweep_v<T, MP, B, variant_rg(3), variant_nt(3)>(phase_b, 3, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b,
+template <typename T, int B>
+static hipError_t sweep_b(int MP, bool phase_b, int variant, const SweepLaunch &a,
+                          hipStream_t s) {
+    switch (MP) {
+        case 8: return sweep_mpb<T, 8, B>(phase_b, variant, a, s);
+        case 16: return sweep_mpb<T, 16, B>(phase_b, variant, a, s);
+        case 32: return sweep_mpb<T, 32, B>(phase_b, variant, a, s);
+        case 64: return sweep_mpb<T, 64, B>(phase_b, variant, a, s);
+        case 128: return sweep_mpb<T, 128, B>(phase_b, variant, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, int variant,
                               const SweepLaunch &a, hipStream_t stream) {
+    if (variant < 0 || variant >= kVariants) return hipErrorInvalidValue;
     if (precision_bytes == 8)
-        return b == 1 ? sweep_b<double, 1>(MP, phase_b, a, stream)
-                      : sweep_b<double, 2>(MP, phase_b, a, stream);
-    return b == 1 ? sweep_b<float, 1>(MP, phase_b, a, stream)
-                  : sweep_b<float, 2>(MP, phase_b, a, stream);
+        return b == 1 ? sweep_b<double, 1>(MP, phase_b, variant, a, stream)
+                      : sweep_b<double, 2>(MP, phase_b, variant, a, stream);
+    return b == 1 ? sweep_b<float, 1>(MP, phase_b, variant, a, stream)
+                  : sweep_b<float, 2>(MP, phase_b, variant, a, stream);
 }
 
 template <int MP>

@@ -102,6 +102,7 @@ struct stc_handle {
     DevState *st = nullptr;
     std::vector<int> sizes;
     long long N = 0;
+    int variant[2] = {0, 0};   // sweep-kernel launch variant for FP64 [0] / FP32 [1] stages
     // iteration state
     long long s = 0;        // sweeps done since the last load
     bool stage32 = false;   // current iterate lives in the FP32 rotation
@@ -117,8 +118,11 @@ void *wbuf(stc_handle *h, bool fp32, long long s) {
     return h->w64 + k * vec;
 }
 
-stc_status launch_one_sweep(stc_handle *h, long long s, double tol) {
+// Enqueue sweep s (phase A, phase B, finalize).  With ev != nullptr an event
+// is recorded after each of the three launches (ev[0..2]).
+hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev) {
     const bool f32 = h->stage32;
+    const int v = h->variant[f32 ? 1 : 0];
     SweepLaunch a;
     a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
     a.w_old = wbuf(h, f32, s - 1);
@@ -132,17 +136,36 @@ stc_status launch_one_sweep(stc_handle *h, long long s, double tol) {
     const int pA = (h->stair_type == 1) ? 0 : 1;
     const int pB = 1 - pA;
     const int bytes = f32 ? 4 : 8;
-    const int gA = phase_groups(bytes, h->MP, h->L, pA);
-    const int gB = phase_groups(bytes, h->MP, h->L, pB);
+    const int gA = phase_groups(bytes, h->MP, h->L, pA, v);
+    const int gB = phase_groups(bytes, h->MP, h->L, pB, v);
     a.nslots = gA + gB;
     a.parity = pA;
     a.slot0 = 0;
-    HIP_TRY(launch_sweep_phase(bytes, h->MP, h->b, false, a, h->stream));
+    hipError_t e = launch_sweep_phase(bytes, h->MP, h->b, false, v, a, h->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[0], h->stream);
     a.parity = pB;
     a.slot0 = gA;
-    HIP_TRY(launch_sweep_phase(bytes, h->MP, h->b, true, a, h->stream));
-    HIP_TRY(launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, tol, h->stream));
+    if (e == hipSuccess) e = launch_sweep_phase(bytes, h->MP, h->b, true, v, a, h->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], h->stream);
+    if (e == hipSuccess)
+        e = launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, tol, h->stream);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], h->stream);
+    return e;
+}
+
+stc_status launch_one_sweep(stc_handle *h, long long s, double tol) {
+    HIP_TRY(enqueue_sweep(h, s, tol, nullptr));
     return STC_OK;
+}
+
+// Default launch variant before any tuning: non-temporal block streams once
+// the blocks of a stage exceed the 256 MB last-level cache, four row groups
+// per level for blocks of 64 and more.
+int default_variant(int MP, double block_bytes) {
+    int v = 0;
+    if (MP >= 64) v |= 1;
+    if (block_bytes > 256.0 * (1 << 20)) v |= 2;
+    return v;
 }
 
 struct HostState {
@@ -177,8 +200,9 @@ stc_status read_ring(stc_handle *h, const double *ring_dev, long long s, double 
     return STC_OK;
 }
 
-// Load x (compact, N) as W_0 of the current stage; resets the sweep counter.
-stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
+// Load x (compact, N; NULL = e/N) as W_0 of the given precision stage and
+// reset the sweep counter.
+stc_status load_vector_stage(stc_handle *h, const double *x, int32_t where, bool fp32) {
     const double *src = x;
     if (x && where == STC_MEM_HOST) {
         HIP_TRY(hipMemcpyAsync(h->io, x, sizeof(double) * h->N, hipMemcpyHostToDevice, h->stream));
@@ -190,7 +214,7 @@ stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
         HIP_TRY(hipStreamSynchronize(h->stream));
         src = h->io;
     }
-    h->stage32 = (h->precision != STC_FP64);
+    h->stage32 = fp32;
     h->s = 0;
     h->iters32 = 0;
     HIP_TRY(launch_reset_state(h->st, h->stream));
@@ -204,6 +228,11 @@ stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
         return fail(STC_EINVAL, "start vector must be >= 0, finite, with a positive sum "
                                 "(sum = %g)", hs.x_sum);
     return STC_OK;
+}
+
+// Load into the first stage of the handle's precision schedule.
+stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
+    return load_vector_stage(h, x, where, h->precision != STC_FP64);
 }
 
 stc_status residual_of(stc_handle *h, bool f32, long long s, double *out) {
@@ -326,6 +355,11 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     std::vector<long long> off(L + 1, 0);
     for (int i = 0; i < L; ++i) off[i + 1] = off[i] + sizes[i];
     h->N = off[L];
+    {
+        const double nblk = (double)L * NB * MP * MP;
+        h->variant[0] = default_variant(MP, nblk * 8.0);
+        h->variant[1] = default_variant(MP, nblk * 4.0);
+    }
 
     auto cleanup = [&](stc_status s) { delete h; return s; };
     auto dev = [&](hipError_t e, const char *what) -> stc_status {
@@ -451,65 +485,100 @@ stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
 }
 
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, double *ms_b,
-                              double *ms_sweep) {
+                              double *ms_fin, double *ms_sweep) {
     if (!h || nsweeps < 1) return fail(STC_EINVAL, "bad argument");
-    std::vector<hipEvent_t> ev(2 * nsweeps + 1);
+    std::vector<hipEvent_t> ev(3 * nsweeps + 1);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     auto destroy = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
-    const bool f32 = h->stage32;
-    const int bytes = f32 ? 4 : 8;
-    const int pA = (h->stair_type == 1) ? 0 : 1, pB = 1 - pA;
-    const int gA = phase_groups(bytes, h->MP, h->L, pA);
-    const int gB = phase_groups(bytes, h->MP, h->L, pB);
     const long long s0 = h->s;
     hipError_t err = hipEventRecord(ev[0], h->stream);
-    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j) {
-        const long long s = s0 + j;
-        SweepLaunch a;
-        a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
-        a.w_old = wbuf(h, f32, s - 1);
-        a.w_older = wbuf(h, f32, s - 2);
-        a.w_new = wbuf(h, f32, s);
-        a.part_sum = h->part_sum;
-        a.part_diff = h->part_diff;
-        a.st = h->st;
-        a.L = h->L;
-        a.s = s;
-        a.nslots = gA + gB;
-        a.parity = pA;
-        a.slot0 = 0;
-        err = launch_sweep_phase(bytes, h->MP, h->b, false, a, h->stream);
-        if (err == hipSuccess) err = hipEventRecord(ev[2 * j - 1], h->stream);
-        a.parity = pB;
-        a.slot0 = gA;
-        if (err == hipSuccess) err = launch_sweep_phase(bytes, h->MP, h->b, true, a, h->stream);
-        if (err == hipSuccess)
-            err = launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, 0.0,
-                                        h->stream);
-        if (err == hipSuccess) err = hipEventRecord(ev[2 * j], h->stream);
-    }
-    if (err == hipSuccess) err = hipEventSynchronize(ev[2 * nsweeps]);
+    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j)
+        err = enqueue_sweep(h, s0 + j, 0.0, &ev[3 * (j - 1) + 1]);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[3 * nsweeps]);
     if (err != hipSuccess) {
         destroy();
         return fail(STC_EDEVICE, "profiled sweeps: %s", hipGetErrorString(err));
     }
-    double ta = 0.0, tb = 0.0;
-    for (int64_t j = 1; j <= nsweeps; ++j) {
-        float x = 0.f, y = 0.f;
-        (void)hipEventElapsedTime(&x, ev[2 * j - 2], ev[2 * j - 1]);
-        (void)hipEventElapsedTime(&y, ev[2 * j - 1], ev[2 * j]);
-        ta += x;
-        tb += y;
-    }
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int64_t j = 0; j < nsweeps; ++j)
+        for (int k = 0; k < 3; ++k) {
+            float x = 0.f;
+            (void)hipEventElapsedTime(&x, ev[3 * j + k], ev[3 * j + k + 1]);
+            t[k] += x;
+        }
     float tot = 0.f;
-    (void)hipEventElapsedTime(&tot, ev[0], ev[2 * nsweeps]);
+    (void)hipEventElapsedTime(&tot, ev[0], ev[3 * nsweeps]);
     destroy();
     h->s = s0 + nsweeps;
-    if (f32) h->iters32 += nsweeps;
-    if (ms_a) *ms_a = ta / nsweeps;
-    if (ms_b) *ms_b = tb / nsweeps;
+    if (h->stage32) h->iters32 += nsweeps;
+    if (ms_a) *ms_a = t[0] / nsweeps;
+    if (ms_b) *ms_b = t[1] / nsweeps;
+    if (ms_fin) *ms_fin = t[2] / nsweeps;
     if (ms_sweep) *ms_sweep = (double)tot / nsweeps;
     return STC_OK;
+}
+
+int32_t stc_variant_count(void) { return variant_count(); }
+
+stc_status stc_set_variant(stc_handle *h, int32_t stage, int32_t variant) {
+    if (!h) return fail(STC_EINVAL, "null handle");
+    if (stage != STC_FP64 && stage != STC_FP32) return fail(STC_EINVAL, "stage must be FP64 or FP32");
+    if (variant < 0 || variant >= variant_count()) return fail(STC_EINVAL, "no variant %d", variant);
+    h->variant[stage == STC_FP32 ? 1 : 0] = variant;
+    return STC_OK;
+}
+
+stc_status stc_get_variant(stc_handle *h, int32_t stage, int32_t *variant) {
+    if (!h || !variant) return fail(STC_EINVAL, "null argument");
+    if (stage != STC_FP64 && stage != STC_FP32) return fail(STC_EINVAL, "stage must be FP64 or FP32");
+    *variant = h->variant[stage == STC_FP32 ? 1 : 0];
+    return STC_OK;
+}
+
+stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, double *ms_fp32) {
+    if (!h || trial_sweeps < 1) return fail(STC_EINVAL, "bad argument");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    stc_status rc = STC_OK;
+    const int nv = variant_count();
+    for (int stage = 0; stage < 2 && rc == STC_OK; ++stage) {
+        const bool f32 = stage == 1;
+        if (f32 && h->precision == STC_FP64) continue;
+        if (!f32 && h->precision == STC_FP32) continue;
+        // time every variant from the uniform start in this stage's precision
+        double best = 1e300;
+        int best_v = h->variant[stage];
+        for (int v = 0; v < nv && rc == STC_OK; ++v) {
+            if ((rc = load_vector_stage(h, nullptr, STC_MEM_HOST, f32)) != STC_OK) break;
+            h->variant[stage] = v;
+            hipError_t e = hipSuccess;
+            for (long long j = 1; j <= 3 && e == hipSuccess; ++j) e = enqueue_sweep(h, j, 0.0, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            for (long long j = 4; j < 4 + trial_sweeps && e == hipSuccess; ++j)
+                e = enqueue_sweep(h, j, 0.0, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(STC_EDEVICE, "autotune: %s", hipGetErrorString(e));
+                break;
+            }
+            const double per = (double)ms / trial_sweeps;
+            if (per < best) {
+                best = per;
+                best_v = v;
+            }
+        }
+        h->variant[stage] = best_v;
+        if (f32 && ms_fp32) *ms_fp32 = best;
+        if (!f32 && ms_fp64) *ms_fp64 = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == STC_OK) rc = load_vector(h, nullptr, STC_MEM_HOST);
+    return rc;
 }
 
 stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {

@@ -30,7 +30,8 @@ STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
 
 # every symbol include/stc.h declares
 EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_residual",
-           "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_load", "stc_query",
+           "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
+           "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
            "stc_store", "stc_destroy",
            "stc_status_string", "stc_last_error")
 
@@ -81,7 +82,12 @@ def load_library(path: str = LIB_PATH):
     lib.stc_step.argtypes = [H, c_void_p, c_void_p, dp, c_int32]
     lib.stc_residual.argtypes = [H, c_void_p, dp, c_int32]
     lib.stc_sweeps.argtypes = [H, c_int64, c_void_p]
-    lib.stc_profile_sweeps.argtypes = [H, c_int64, dp, dp, dp]
+    lib.stc_profile_sweeps.argtypes = [H, c_int64, dp, dp, dp, dp]
+    lib.stc_variant_count.argtypes = []
+    lib.stc_variant_count.restype = c_int32
+    lib.stc_set_variant.argtypes = [H, c_int32, c_int32]
+    lib.stc_get_variant.argtypes = [H, c_int32, POINTER(c_int32)]
+    lib.stc_autotune.argtypes = [H, c_int32, dp, dp]
     lib.stc_phase_bytes.argtypes = [H, dp, dp]
     lib.stc_load.argtypes = [H, c_void_p, c_int32]
     lib.stc_query.argtypes = [H, POINTER(c_int64), POINTER(c_int32), dp]
@@ -93,7 +99,8 @@ def load_library(path: str = LIB_PATH):
     lib.stc_last_error.argtypes = []
     lib.stc_last_error.restype = ctypes.c_char_p
     for name in ("stc_setup", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
-                 "stc_profile_sweeps", "stc_phase_bytes", "stc_load", "stc_query", "stc_store"):
+                 "stc_profile_sweeps", "stc_phase_bytes", "stc_set_variant", "stc_get_variant",
+                 "stc_autotune", "stc_load", "stc_query", "stc_store"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -189,9 +196,33 @@ def stc_sweeps(h, nsweeps: int, diffs: np.ndarray | None = None):
 
 
 def stc_profile_sweeps(h, nsweeps: int):
-    a, b, t = c_double(), c_double(), c_double()
-    _check(load_library().stc_profile_sweeps(h, int(nsweeps), byref(a), byref(b), byref(t)))
-    return a.value, b.value, t.value
+    """(ms phase A, ms phase B, ms finalize, ms whole sweep), means per sweep."""
+    a, b, f, t = c_double(), c_double(), c_double(), c_double()
+    _check(load_library().stc_profile_sweeps(h, int(nsweeps), byref(a), byref(b), byref(f),
+                                             byref(t)))
+    return a.value, b.value, f.value, t.value
+
+
+def stc_variant_count() -> int:
+    return int(load_library().stc_variant_count())
+
+
+def stc_set_variant(h, stage: int, variant: int):
+    _check(load_library().stc_set_variant(h, int(stage), int(variant)))
+
+
+def stc_get_variant(h, stage: int) -> int:
+    v = c_int32()
+    _check(load_library().stc_get_variant(h, int(stage), byref(v)))
+    return v.value
+
+
+def stc_autotune(h, trial_sweeps: int = 20):
+    """Returns (best ms per FP64 sweep, best ms per FP32 sweep); NaN for a
+    stage the handle does not sweep in."""
+    a, b = c_double(float("nan")), c_double(float("nan"))
+    _check(load_library().stc_autotune(h, int(trial_sweeps), byref(a), byref(b)))
+    return a.value, b.value
 
 
 def stc_phase_bytes(h):

@@ -80,6 +80,39 @@ def test_step_fp32_matches_oracle_sweep(name, make):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,make", [SHAPES[0], SHAPES[5], SHAPES[6], SHAPES[8]],
+                         ids=[SHAPES[k][0] for k in (0, 5, 6, 8)])
+def test_every_launch_variant_matches_oracle(name, make, precision):
+    from paper_2302_07551_amd import stc
+    g = make()
+    x = synth.positive_start(g, 77)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x, 1)
+    s = _solver(g, precision=precision)
+    stage = stc.STC_FP64 if precision == "fp64" else stc.STC_FP32
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    for v in range(stc.stc_variant_count()):
+        _say(f"variant {v} {name} {precision}")
+        stc.stc_set_variant(s.h, stage, v)
+        z, d = s.step(x)
+        assert np.abs(z - zr).sum() <= tol, v
+        assert abs(d - dr) <= tol, v
+    s.close()
+
+
+def test_autotune_keeps_results():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(64, 16, synth.config_seed(0))
+    s = _solver(g, precision="mixed", stop="residual", check_every=4)
+    ms64, ms32 = stc.stc_autotune(s.h, 5)
+    assert ms64 > 0 and ms32 > 0
+    for stage in (stc.STC_FP64, stc.STC_FP32):
+        assert 0 <= stc.stc_get_variant(s.h, stage) < stc.stc_variant_count()
+    ref = gth.gth(dense.assemble_Q(g.blocks, g.sizes, g.b))
+    pi, info = s.solve(tol=1e-12, maxit=100000, allow_maxit=False)
+    assert np.abs(pi - ref).sum() <= 1e-10
+
+
 def test_repeated_steps_track_oracle():
     g = synth.qbd(24, 16, 31, last=9)
     s = _solver(g)
