@@ -179,12 +179,64 @@ stc_status stc_phase_bytes(stc_handle *h, double *bytes_phase_a, double *bytes_p
 /* Set the handle's current iterate to x / e^T x (host or device memory). */
 stc_status stc_load(stc_handle *h, const double *x, int32_t where);
 
-/* Per-handle figures after stc_sweeps: sweeps done since
- * the last load, whether the device stop test fired, the last known change. */
+/* Per-handle figures after stc_sweeps or batched sweeps: the sweep of the
+ * current iterate (the stopped sweep if the device test fired), whether it
+ * fired, and the latest known change (at the stopped sweep, else of the
+ * sweep before the last; +inf if none yet).  STC_EDEGENERATE if a sweep
+ * produced no positive mass. */
 stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *diff_1);
 
 /* Copy the handle's current (or stopped) iterate, normalised, to pi. */
 stc_status stc_store(stc_handle *h, double *pi, int32_t where);
+
+/* Precision switch of the mixed schedule (a6): continue the handle's
+ * iteration in FP64 from its current FP32 iterate (the stopped sweep if the
+ * device test fired).  The last two FP32 iterates are widened exactly, so the
+ * next FP64 sweep continues the same recurrence.  STC_EINVAL if the handle
+ * does not sweep in FP32. */
+stc_status stc_promote(stc_handle *h);
+
+/* ---- many chains ------------------------------------------------------
+ * A batch sweeps many independent chains (one handle each, of any L and m)
+ * with one persistent launch per half-sweep and precision stage: a work list
+ * of (chain, group of levels) items, heaviest first, strided over a fixed
+ * grid, plus one finalize workgroup per chain.  Each chain keeps its own
+ * sweep number, scale ring and device stopping test, so chains admitted at
+ * different times advance independently and a stopped chain stays put.  The
+ * chain table and work lists live at fixed device addresses, so the
+ * hipGraph that stc_batch_sweeps captures stays valid when stc_batch_set
+ * changes the membership.  Per-chain results equal those of the same chain
+ * swept alone with launch variant 0 (same per-level arithmetic, same
+ * fixed-order reductions). */
+typedef struct stc_batch stc_batch;
+
+/* Device bytes of a batch's tables. */
+size_t stc_batch_footprint(int32_t max_chains, int64_t max_items);
+
+/* Create a batch whose tables live in arena (caller-owned, 256-byte
+ * aligned, >= stc_batch_footprint).  All its chains must have block
+ * bandwidth b.  stream: the hipStream_t the batch launches on; NULL makes the
+ * batch create (and later destroy) a non-blocking stream of its own, since a
+ * graph cannot be captured on the null stream.  Work enqueued by
+ * stc_batch_sweeps is ordered only on that stream: call stc_batch_sync
+ * before reading a chain through its handle. */
+stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, void *stream,
+                            void *arena, size_t arena_bytes, stc_batch **out);
+
+/* Set the batch's chains (their current iterates and precision stages) and
+ * the change tolerance of the device stopping test: chains sweeping in FP32
+ * under STC_MIXED stop at their switch_tol, all others at tol.  nontemporal
+ * selects non-temporal block loads.  Synchronous. */
+stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, double tol,
+                         int32_t nontemporal);
+
+/* Enqueue nsweeps sweeps of every chain of the batch on its stream, as a
+ * replay of a captured hipGraph (use_graph != 0; captured on first use and
+ * again when nsweeps or the set of precision stages changes) or as plain
+ * launches.  Asynchronous: use stc_batch_sync / stc_query afterwards. */
+stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph);
+stc_status stc_batch_sync(stc_batch *bt);
+void stc_batch_destroy(stc_batch *bt);
 
 /* Release the handle (the arena stays with the caller). */
 void stc_destroy(stc_handle *h);

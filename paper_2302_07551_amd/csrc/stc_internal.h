@@ -47,6 +47,26 @@ struct SweepLaunch {
     long long s;          // sweep being produced (>= 1)
 };
 
+// One chain of a batched (multi-chain) launch, as the device reads it.  The
+// blocks and iterate buffers are those of the chain's current precision
+// stage; its sweep number is DevState::last_sweep + 1.
+struct ChainDesc {
+    const void *blk;
+    void *w[3];           // rotation: W_s lives in w[s % 3]
+    double *part_sum;
+    double *part_diff;
+    DevState *st;
+    int L, MP, parity_a;  // levels, padded block size, first phase-A level
+    int groups_a, groups_b;
+    double tol;           // device change test for this chain (<= 0: off)
+};
+
+// One workgroup's work in a batched half-sweep: group q of chain c.
+struct WorkItem {
+    int chain;
+    int group;
+};
+
 // Host-visible launchers (stc_kernels.hip).  Each returns a hipError_t.
 int supported_mp(int m);   // padded block size for m, or 0
 int variant_count();
@@ -71,6 +91,13 @@ hipError_t launch_diff(int precision_bytes, int MP, const void *w, const void *w
                        int L, DevState *st, long long s, double *part, hipStream_t stream);
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t stream);
 hipError_t launch_reset_state(DevState *st, hipStream_t stream);
+hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);
+int batch_lpw(int precision_bytes, int MP);
+hipError_t launch_batch_phase(int precision_bytes, int b, bool phase_b, bool nt, int grid,
+                              const ChainDesc *chains, const WorkItem *items, const int *nitems,
+                              hipStream_t stream);
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
+                                 hipStream_t stream);
 int reduce_groups(int MP, int L);
 
 }  // namespace stc

@@ -113,28 +113,43 @@ __device__ inline double block_max(double v, double *sh) {
 // ---------------------------------------------------------------------------
 // half-sweep
 // ---------------------------------------------------------------------------
+// The work of one workgroup in a half-sweep: LPW levels of one chain
+// (team t of group q owns level parity + 2 (q LPW + t)), then the group's
+// partial sums into slot slot0 + q.  Used by the single-chain launch and by
+// the persistent multi-chain launch.
+template <typename T>
+struct ChainView {
+    const T *blk;
+    const T *w_old, *w_older;
+    T *w_new;
+    double *part_sum, *part_diff;
+    const DevState *st;
+    int L, parity, slot0;
+    long long s;
+};
+
 template <typename T, int MP, int B, bool PHB, int RG, bool NT>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
+__device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *red_base,
+                                   T *rv_base, double *sh) {
     using TL = Tile<T, MP, RG>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
     constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
                   LPW = TL::LPW, PF = TL::PF;
     constexpr size_t BS = (size_t)MP * MP;
-    __shared__ T red[LPW][R][MP];
-    __shared__ T rv[LPW][MP];
-    __shared__ double sh[kWG / 64];
 
     const DevState *st = a.st;
     const int tid = threadIdx.x;
     const int team = tid / TS, tt = tid - team * TS;
     const int c = tt % CT, g = tt / CT;
-    const int i = a.parity + 2 * (blockIdx.x * LPW + team);
+    T *red = red_base + team * (R * MP);     // [R][MP] of this team
+    T *rv = rv_base + team * MP;             // [MP]
+    const int i = a.parity + 2 * (q * LPW + team);
     const bool active = i < a.L;
     const int ic = active ? i : a.parity;   // a valid level for idle teams
-    const T *w_old = (const T *)a.w_old;
-    T *w_new = (T *)a.w_new;
-    const T *base = (const T *)a.blk + (size_t)ic * NB * BS;
+    const T *w_old = a.w_old;
+    T *w_new = a.w_new;
+    const T *base = a.blk + (size_t)ic * NB * BS;
     const double inv_old = st->inv_sigma[(a.s - 1) & kRingMask];
     const T sc = (T)inv_old;
 
@@ -152,8 +167,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
         const T vs = in ? (fresh ? (T)1 : sc) : (T)0;
         const T *gb = base + (size_t)(d + B) * BS + c * VEC;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int row = g + R * q;
+        for (int qq = 0; qq < RPT; ++qq) {
+            const int row = g + R * qq;
             const VT blkv = stream_load<VT, NT>((const VT *)(gb + (size_t)row * MP));
             acc += blkv * (v[row] * vs);
         }
@@ -162,63 +177,125 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     VT vpre[PF];
     const T *wb = base + (size_t)B * BS + c * VEC;
 #pragma unroll
-    for (int q = 0; q < PF; ++q)
-        vpre[q] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * q) * MP));
+    for (int qq = 0; qq < PF; ++qq)
+        vpre[qq] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * qq) * MP));
 
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc[e];
+    for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc[e];
     __syncthreads();
     if (tt < MP) {
         T r = 0;
 #pragma unroll
-        for (int gg = 0; gg < R; ++gg) r += red[team][gg][tt];
-        rv[team][tt] = r;
+        for (int gg = 0; gg < R; ++gg) r += red[gg * MP + tt];
+        rv[tt] = r;
     }
     __syncthreads();
 
     // z_i = W_i r_i
     VT acc2 = (VT)(T)0;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        const int row = g + R * q;
-        const VT wv = (q < PF) ? vpre[q < PF ? q : 0]
-                               : stream_load<VT, NT>((const VT *)(wb + (size_t)row * MP));
-        acc2 += wv * rv[team][row];
+    for (int qq = 0; qq < RPT; ++qq) {
+        const int row = g + R * qq;
+        const VT wv = (qq < PF) ? vpre[qq < PF ? qq : 0]
+                                : stream_load<VT, NT>((const VT *)(wb + (size_t)row * MP));
+        acc2 += wv * rv[row];
     }
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc2[e];
+    for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
     __syncthreads();
 
-    // a sweep queued after the device stopping test fired changes nothing
-    const bool live = st->stop_flag == 0;
     double zs = 0.0, dd = 0.0;
     if (live && active && tt < MP) {
         T z = 0;
 #pragma unroll
-        for (int gg = 0; gg < R; ++gg) z += red[team][gg][tt];
+        for (int gg = 0; gg < R; ++gg) z += red[gg * MP + tt];
         w_new[(size_t)i * MP + tt] = z;
         zs = (double)z;
         if (a.s >= 2) {
             const double inv_older = st->inv_sigma[(a.s - 2) & kRingMask];
-            const T *w_older = (const T *)a.w_older;
             dd = fabs((double)w_old[(size_t)i * MP + tt] * inv_old -
-                      (double)w_older[(size_t)i * MP + tt] * inv_older);
+                      (double)a.w_older[(size_t)i * MP + tt] * inv_older);
         }
     }
     const double S = block_sum(zs, sh);
     const double D = block_sum(dd, sh);
     if (live && tid == 0) {
-        a.part_sum[a.slot0 + blockIdx.x] = S;
-        a.part_diff[a.slot0 + blockIdx.x] = D;
+        a.part_sum[a.slot0 + q] = S;
+        a.part_diff[a.slot0 + q] = D;
+    }
+    __syncthreads();   // the LDS may be reused by the next group
+}
+
+template <typename T, int MP, int B, bool PHB, int RG, bool NT>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
+    using TL = Tile<T, MP, RG>;
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
+    __shared__ double sh[kWG / 64];
+    ChainView<T> v;
+    v.blk = (const T *)a.blk;
+    v.w_old = (const T *)a.w_old;
+    v.w_older = (const T *)a.w_older;
+    v.w_new = (T *)a.w_new;
+    v.part_sum = a.part_sum;
+    v.part_diff = a.part_diff;
+    v.st = a.st;
+    v.L = a.L;
+    v.parity = a.parity;
+    v.slot0 = a.slot0;
+    v.s = a.s;
+    // a sweep queued after the device stopping test fired changes nothing
+    const bool live = a.st->stop_flag == 0;
+    sweep_group<T, MP, B, PHB, RG, NT>(v, blockIdx.x, live, red, rv, sh);
+}
+
+// ---------------------------------------------------------------------------
+// many chains: one persistent launch per half-sweep over a work list of
+// (chain, group) items; each chain's sweep number comes from its own state
+// ---------------------------------------------------------------------------
+template <typename T, int B, bool PHB, bool NT>
+__global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
+                                                      const WorkItem *items,
+                                                      const int *nitems) {
+    // LPW * R * MP = kWG * VEC elements for every block size
+    constexpr int VEC = 16 / (int)sizeof(T);
+    __shared__ T red[kWG * VEC];
+    __shared__ T rv[kWG * VEC];
+    __shared__ double sh[kWG / 64];
+    const int n = *nitems;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const WorkItem w = items[it];
+        const ChainDesc &d = chains[w.chain];
+        const DevState *st = d.st;
+        const long long s = st->last_sweep + 1;
+        const bool live = st->stop_flag == 0;
+        ChainView<T> v;
+        v.blk = (const T *)d.blk;
+        v.w_old = (const T *)d.w[(s - 1) % 3];
+        v.w_older = (const T *)d.w[(s + 1) % 3];   // (s - 2) mod 3
+        v.w_new = (T *)d.w[s % 3];
+        v.part_sum = d.part_sum;
+        v.part_diff = d.part_diff;
+        v.st = st;
+        v.L = d.L;
+        v.parity = PHB ? 1 - d.parity_a : d.parity_a;
+        v.slot0 = PHB ? d.groups_a : 0;
+        v.s = s;
+        switch (d.MP) {
+            case 8: sweep_group<T, 8, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+            case 16: sweep_group<T, 16, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+            case 32: sweep_group<T, 32, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+            case 64: sweep_group<T, 64, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+            case 128: sweep_group<T, 128, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+        }
     }
 }
 
-// One workgroup: e^T W_s and the change of sweep s-1 from the partials of
-// both phases (fixed order), then the device stopping test.
-__global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
-                                                         const double *part_diff, int nslots,
-                                                         DevState *st, long long s, double tol) {
-    __shared__ double sh[kWG / 64];
+// e^T W_s and the change of sweep s-1 from the partials of both phases
+// (fixed order), then the device stopping test.  One workgroup per chain.
+__device__ inline void finalize_chain(const double *part_sum, const double *part_diff,
+                                      int nslots, DevState *st, long long s, double tol,
+                                      double *sh) {
     // the flag is read alongside the partials (not before them); after a stop
     // the partials are stale and nothing is written
     const int stopped = st->stop_flag;
@@ -245,6 +322,33 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
                 st->stop_sweep = s - 1;
             }
         }
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
+                                                         const double *part_diff, int nslots,
+                                                         DevState *st, long long s, double tol) {
+    __shared__ double sh[kWG / 64];
+    finalize_chain(part_sum, part_diff, nslots, st, s, tol, sh);
+}
+
+__global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
+                                                         const int *nchains) {
+    __shared__ double sh[kWG / 64];
+    if ((int)blockIdx.x >= *nchains) return;
+    const ChainDesc &d = chains[blockIdx.x];
+    DevState *st = d.st;
+    finalize_chain(d.part_sum, d.part_diff, d.groups_a + d.groups_b, st, st->last_sweep + 1,
+                   d.tol, sh);
+}
+
+// Continue from sweep k after a precision switch: clear the stop state.
+__global__ void k_rearm(DevState *st, long long k) {
+    if (threadIdx.x == 0) {
+        st->stop_flag = 0;
+        st->status = kDevOk;
+        st->stop_sweep = -1;
+        st->last_sweep = k;
     }
 }
 
@@ -598,6 +702,52 @@ hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t str
 
 hipError_t launch_reset_state(DevState *st, hipStream_t stream) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, stream, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream) {
+    hipLaunchKernelGGL(k_rearm, dim3(1), dim3(64), 0, stream, st, k);
+    return hipGetLastError();
+}
+
+int batch_lpw(int precision_bytes, int MP) {
+    return precision_bytes == 8 ? lpw_of<double, 8>(MP) : lpw_of<float, 8>(MP);
+}
+
+template <typename T, int B>
+static hipError_t batch_tb(bool phase_b, bool nt, int grid, const ChainDesc *chains,
+                           const WorkItem *items, const int *nitems, hipStream_t s) {
+    if (phase_b) {
+        if (nt)
+            hipLaunchKernelGGL((k_batch_sweep<T, B, true, true>), dim3(grid), dim3(kWG), 0, s,
+                               chains, items, nitems);
+        else
+            hipLaunchKernelGGL((k_batch_sweep<T, B, true, false>), dim3(grid), dim3(kWG), 0, s,
+                               chains, items, nitems);
+    } else {
+        if (nt)
+            hipLaunchKernelGGL((k_batch_sweep<T, B, false, true>), dim3(grid), dim3(kWG), 0, s,
+                               chains, items, nitems);
+        else
+            hipLaunchKernelGGL((k_batch_sweep<T, B, false, false>), dim3(grid), dim3(kWG), 0, s,
+                               chains, items, nitems);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(int precision_bytes, int b, bool phase_b, bool nt, int grid,
+                              const ChainDesc *chains, const WorkItem *items, const int *nitems,
+                              hipStream_t stream) {
+    if (precision_bytes == 8)
+        return b == 1 ? batch_tb<double, 1>(phase_b, nt, grid, chains, items, nitems, stream)
+                      : batch_tb<double, 2>(phase_b, nt, grid, chains, items, nitems, stream);
+    return b == 1 ? batch_tb<float, 1>(phase_b, nt, grid, chains, items, nitems, stream)
+                  : batch_tb<float, 2>(phase_b, nt, grid, chains, items, nitems, stream);
+}
+
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, nchains);
     return hipGetLastError();
 }
 

@@ -615,15 +615,15 @@ stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *d
     HostState hs;
     stc_status rc = read_state(h, &hs);
     if (rc != STC_OK) return rc;
-    const long long cur = hs.stop_flag ? hs.stop_sweep : h->s;
+    const long long cur = hs.stop_flag ? hs.stop_sweep : hs.last_sweep;
+    h->s = hs.last_sweep;
     if (sweeps) *sweeps = cur;
     if (stopped) *stopped = hs.stop_flag;
     if (diff_1) {
+        // latest known change: at the stopped sweep, else of the sweep before last
+        const long long k = hs.stop_flag ? hs.stop_sweep : hs.last_sweep - 1;
         *diff_1 = INFINITY;
-        if (cur >= 1 && cur < h->s) {
-            rc = read_ring(h, h->st->diff, cur, diff_1);
-            if (rc != STC_OK) return rc;
-        }
+        if (k >= 1 && (rc = read_ring(h, h->st->diff, k, diff_1)) != STC_OK) return rc;
     }
     if (hs.status == kDevDegenerate) return fail(STC_EDEGENERATE, "e^T z <= 0 after sweep %lld", hs.stop_sweep + 1);
     return STC_OK;
@@ -634,8 +634,25 @@ stc_status stc_store(stc_handle *h, double *pi, int32_t where) {
     HostState hs;
     stc_status rc = read_state(h, &hs);
     if (rc != STC_OK) return rc;
-    const long long cur = hs.stop_flag ? hs.stop_sweep : h->s;
+    const long long cur = hs.stop_flag ? hs.stop_sweep : hs.last_sweep;
     return store_vector(h, h->stage32, cur, pi, where);
+}
+
+stc_status stc_promote(stc_handle *h) {
+    if (!h) return fail(STC_EINVAL, "null handle");
+    if (!h->stage32 || h->precision == STC_FP64)
+        return fail(STC_EINVAL, "the handle does not sweep in FP32");
+    HostState hs;
+    stc_status rc = read_state(h, &hs);
+    if (rc != STC_OK) return rc;
+    if (hs.status == kDevDegenerate) return fail(STC_EDEGENERATE, "e^T z <= 0");
+    const long long k = hs.stop_flag ? hs.stop_sweep : hs.last_sweep;
+    h->iters32 = k;
+    if ((rc = widen_at(h, k)) != STC_OK) return rc;
+    HIP_TRY(launch_rearm(h->st, k, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->s = k;
+    return STC_OK;
 }
 
 stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t where) {
@@ -709,7 +726,7 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
                 // FP32 stage done: continue in FP64 from sweep k
                 h->iters32 = k;
                 if ((rc = widen_at(h, k)) != STC_OK) return rc;
-                HIP_TRY(launch_reset_state(h->st, h->stream));
+                HIP_TRY(launch_rearm(h->st, k, h->stream));
                 s = k;
                 h->s = k;
                 continue;
@@ -754,6 +771,249 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
         res->status = out;
     }
     return out;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched sweeps over many chains
+// ---------------------------------------------------------------------------
+
+struct stc_batch {
+    int max_chains = 0;
+    long long max_items = 0;
+    int b = 1;
+    bool nt = false;
+    int grid = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;   // created here: graph capture needs a non-null stream
+    char *base = nullptr;
+    ChainDesc *d_chains[2] = {nullptr, nullptr};   // [0] FP64 stage, [1] FP32 stage
+    WorkItem *d_items_a[2] = {nullptr, nullptr};
+    WorkItem *d_items_b[2] = {nullptr, nullptr};
+    int *d_counts = nullptr;                        // per group: chains, items A, items B
+    int counts[6] = {0, 0, 0, 0, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long long graph_n = -1;
+    int graph_groups = -1;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t chains = 0, items_a = 0, items_b = 0, counts = 0, total = 0;
+};
+
+BatchLayout batch_layout(int max_chains, long long max_items) {
+    BatchLayout l;
+    size_t at = 0;
+    auto take = [&](size_t bytes) { size_t p = at; at = align_up(at + bytes); return p; };
+    l.chains = take(2 * (size_t)max_chains * sizeof(ChainDesc));
+    l.items_a = take(2 * (size_t)max_items * sizeof(WorkItem));
+    l.items_b = take(2 * (size_t)max_items * sizeof(WorkItem));
+    l.counts = take(6 * sizeof(int));
+    l.total = at;
+    return l;
+}
+
+void drop_graph(stc_batch *bt) {
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    bt->graph_n = -1;
+    bt->graph_groups = -1;
+}
+
+// Enqueue n sweeps of every non-empty stage group (FP32 group first).
+hipError_t enqueue_batch(stc_batch *bt, long long n) {
+    hipError_t e = hipSuccess;
+    for (long long j = 0; j < n && e == hipSuccess; ++j) {
+        for (int g = 1; g >= 0 && e == hipSuccess; --g) {
+            if (bt->counts[3 * g] == 0) continue;
+            const int bytes = g == 1 ? 4 : 8;
+            e = launch_batch_phase(bytes, bt->b, false, bt->nt, bt->grid, bt->d_chains[g],
+                                   bt->d_items_a[g], bt->d_counts + 3 * g + 1, bt->stream);
+            if (e == hipSuccess)
+                e = launch_batch_phase(bytes, bt->b, true, bt->nt, bt->grid, bt->d_chains[g],
+                                       bt->d_items_b[g], bt->d_counts + 3 * g + 2, bt->stream);
+            if (e == hipSuccess)
+                e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], bt->d_counts + 3 * g,
+                                          bt->stream);
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stc_batch_footprint(int32_t max_chains, int64_t max_items) {
+    if (max_chains < 1 || max_items < 1) return 0;
+    return batch_layout(max_chains, max_items).total;
+}
+
+stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, void *stream,
+                            void *arena, size_t arena_bytes, stc_batch **out) {
+    if (!out) return fail(STC_EINVAL, "null argument");
+    *out = nullptr;
+    if (max_chains < 1 || max_items < 1 || (b != 1 && b != 2))
+        return fail(STC_EINVAL, "need max_chains >= 1, max_items >= 1, b in {1, 2}");
+    if (!arena || (uintptr_t)arena % kAlign) return fail(STC_EINVAL, "arena must be 256-byte aligned");
+    const BatchLayout l = batch_layout(max_chains, max_items);
+    if (arena_bytes < l.total)
+        return fail(STC_ENOMEM, "batch arena holds %zu bytes, %zu needed", arena_bytes, l.total);
+    stc_batch *bt = new stc_batch();
+    bt->max_chains = max_chains;
+    bt->max_items = max_items;
+    bt->b = b;
+    bt->stream = (hipStream_t)stream;
+    if (!bt->stream) {
+        if (hipStreamCreateWithFlags(&bt->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete bt;
+            return fail(STC_EDEVICE, "could not create the batch stream");
+        }
+        bt->own_stream = true;
+    }
+    bt->base = (char *)arena;
+    for (int g = 0; g < 2; ++g) {
+        bt->d_chains[g] = (ChainDesc *)(bt->base + l.chains) + (size_t)g * max_chains;
+        bt->d_items_a[g] = (WorkItem *)(bt->base + l.items_a) + (size_t)g * max_items;
+        bt->d_items_b[g] = (WorkItem *)(bt->base + l.items_b) + (size_t)g * max_items;
+    }
+    bt->d_counts = (int *)(bt->base + l.counts);
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    bt->grid = cus * 8;   // persistent grid; groups without work exit at once
+    hipError_t e = hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts),
+                                  hipMemcpyHostToDevice, bt->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
+    if (e != hipSuccess) {
+        if (bt->own_stream) (void)hipStreamDestroy(bt->stream);
+        delete bt;
+        return fail(STC_EDEVICE, "batch create: %s", hipGetErrorString(e));
+    }
+    *out = bt;
+    return STC_OK;
+}
+
+stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, double tol,
+                         int32_t nontemporal) {
+    if (!bt || (count > 0 && !hs) || count < 0) return fail(STC_EINVAL, "bad argument");
+    if (count > bt->max_chains) return fail(STC_EINVAL, "%d chains > max_chains %d", count, bt->max_chains);
+    std::vector<ChainDesc> chains[2];
+    std::vector<WorkItem> ia[2], ib[2];
+    std::vector<double> cost_a[2], cost_b[2];
+    for (int c = 0; c < count; ++c) {
+        stc_handle *h = hs[c];
+        if (!h) return fail(STC_EINVAL, "handle %d is NULL", c);
+        if (h->b != bt->b) return fail(STC_EINVAL, "handle %d has bandwidth %d, batch %d", c, h->b, bt->b);
+        const int g = h->stage32 ? 1 : 0;
+        const int bytes = g == 1 ? 4 : 8;
+        const int lpw = batch_lpw(bytes, h->MP);
+        const int pA = (h->stair_type == 1) ? 0 : 1;
+        ChainDesc d;
+        d.blk = g == 1 ? (const void *)h->blk32 : (const void *)h->blk64;
+        for (int k = 0; k < 3; ++k) d.w[k] = wbuf(h, g == 1, k);
+        d.part_sum = h->part_sum;
+        d.part_diff = h->part_diff;
+        d.st = h->st;
+        d.L = h->L;
+        d.MP = h->MP;
+        d.parity_a = pA;
+        d.groups_a = ((h->L - pA + 1) / 2 + lpw - 1) / lpw;
+        d.groups_b = ((h->L - (1 - pA) + 1) / 2 + lpw - 1) / lpw;
+        d.tol = (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
+        const int ci = (int)chains[g].size();
+        chains[g].push_back(d);
+        const double per = (double)lpw * h->MP * h->MP * bytes;
+        for (int q = 0; q < d.groups_a; ++q) { ia[g].push_back({ci, q}); cost_a[g].push_back(per); }
+        for (int q = 0; q < d.groups_b; ++q) { ib[g].push_back({ci, q}); cost_b[g].push_back(per); }
+    }
+    for (int g = 0; g < 2; ++g) {
+        if ((long long)ia[g].size() > bt->max_items || (long long)ib[g].size() > bt->max_items)
+            return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld",
+                        std::max(ia[g].size(), ib[g].size()), bt->max_items);
+        // heaviest items first, so the strided persistent assignment ends level
+        for (int ph = 0; ph < 2; ++ph) {
+            std::vector<WorkItem> &items = ph == 0 ? ia[g] : ib[g];
+            std::vector<double> &cost = ph == 0 ? cost_a[g] : cost_b[g];
+            std::vector<size_t> ord(items.size());
+            for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+            std::vector<WorkItem> sorted(items.size());
+            for (size_t k = 0; k < ord.size(); ++k) sorted[k] = items[ord[k]];
+            items.swap(sorted);
+        }
+        if (!chains[g].empty())
+            HIP_TRY(hipMemcpyAsync(bt->d_chains[g], chains[g].data(), chains[g].size() * sizeof(ChainDesc),
+                                   hipMemcpyHostToDevice, bt->stream));
+        if (!ia[g].empty())
+            HIP_TRY(hipMemcpyAsync(bt->d_items_a[g], ia[g].data(), ia[g].size() * sizeof(WorkItem),
+                                   hipMemcpyHostToDevice, bt->stream));
+        if (!ib[g].empty())
+            HIP_TRY(hipMemcpyAsync(bt->d_items_b[g], ib[g].data(), ib[g].size() * sizeof(WorkItem),
+                                   hipMemcpyHostToDevice, bt->stream));
+        bt->counts[3 * g] = (int)chains[g].size();
+        bt->counts[3 * g + 1] = (int)ia[g].size();
+        bt->counts[3 * g + 2] = (int)ib[g].size();
+    }
+    HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
+                           bt->stream));
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    const bool nt = nontemporal != 0;
+    if (nt != bt->nt) drop_graph(bt);
+    bt->nt = nt;
+    return STC_OK;
+}
+
+stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph) {
+    if (!bt || nsweeps < 0) return fail(STC_EINVAL, "bad argument");
+    if (nsweeps == 0) return STC_OK;
+    if (!use_graph) {
+        HIP_TRY(enqueue_batch(bt, nsweeps));
+        return STC_OK;
+    }
+    const int groups = (bt->counts[0] > 0 ? 1 : 0) | (bt->counts[3] > 0 ? 2 : 0);
+    if (!bt->exec || bt->graph_n != nsweeps || bt->graph_groups != groups) {
+        drop_graph(bt);
+        HIP_TRY(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_batch(bt, nsweeps);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(bt->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(STC_EDEVICE, "graph capture: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        bt->graph = g;
+        HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+        bt->graph_n = nsweeps;
+        bt->graph_groups = groups;
+    }
+    HIP_TRY(hipGraphLaunch(bt->exec, bt->stream));
+    return STC_OK;
+}
+
+stc_status stc_batch_sync(stc_batch *bt) {
+    if (!bt) return fail(STC_EINVAL, "null batch");
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    return STC_OK;
+}
+
+void stc_batch_destroy(stc_batch *bt) {
+    if (!bt) return;
+    drop_graph(bt);
+    if (bt->own_stream) {
+        (void)hipStreamSynchronize(bt->stream);
+        (void)hipStreamDestroy(bt->stream);
+    }
+    delete bt;
 }
 
 }  // extern "C"

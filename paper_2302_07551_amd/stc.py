@@ -32,7 +32,9 @@ STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
 EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_residual",
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
-           "stc_store", "stc_destroy",
+           "stc_store", "stc_promote", "stc_batch_footprint", "stc_batch_create",
+           "stc_batch_set", "stc_batch_sweeps", "stc_batch_sync", "stc_batch_destroy",
+           "stc_destroy",
            "stc_status_string", "stc_last_error")
 
 
@@ -92,6 +94,16 @@ def load_library(path: str = LIB_PATH):
     lib.stc_load.argtypes = [H, c_void_p, c_int32]
     lib.stc_query.argtypes = [H, POINTER(c_int64), POINTER(c_int32), dp]
     lib.stc_store.argtypes = [H, c_void_p, c_int32]
+    lib.stc_promote.argtypes = [H]
+    lib.stc_batch_footprint.argtypes = [c_int32, c_int64]
+    lib.stc_batch_footprint.restype = c_size_t
+    lib.stc_batch_create.argtypes = [c_int32, c_int64, c_int32, c_void_p, c_void_p, c_size_t,
+                                     POINTER(H)]
+    lib.stc_batch_set.argtypes = [H, POINTER(H), c_int32, c_double, c_int32]
+    lib.stc_batch_sweeps.argtypes = [H, c_int64, c_int32]
+    lib.stc_batch_sync.argtypes = [H]
+    lib.stc_batch_destroy.argtypes = [H]
+    lib.stc_batch_destroy.restype = None
     lib.stc_destroy.argtypes = [H]
     lib.stc_destroy.restype = None
     lib.stc_status_string.argtypes = [c_int32]
@@ -100,7 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.stc_last_error.restype = ctypes.c_char_p
     for name in ("stc_setup", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
                  "stc_profile_sweeps", "stc_phase_bytes", "stc_set_variant", "stc_get_variant",
-                 "stc_autotune", "stc_load", "stc_query", "stc_store"):
+                 "stc_autotune", "stc_load", "stc_query", "stc_store", "stc_promote",
+                 "stc_batch_create", "stc_batch_set", "stc_batch_sweeps", "stc_batch_sync"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -247,6 +260,83 @@ def stc_store(h, pi):
     _check(load_library().stc_store(h, pp, w))
 
 
+def stc_promote(h):
+    _check(load_library().stc_promote(h))
+
+
+def stc_batch_footprint(max_chains: int, max_items: int) -> int:
+    return int(load_library().stc_batch_footprint(int(max_chains), int(max_items)))
+
+
+def stc_batch_create(max_chains: int, max_items: int, b: int, stream: int, arena: int,
+                     arena_bytes: int):
+    bt = c_void_p()
+    _check(load_library().stc_batch_create(int(max_chains), int(max_items), int(b),
+                                           stream or None, arena or None, int(arena_bytes),
+                                           byref(bt)))
+    return bt
+
+
+def stc_batch_set(bt, handles, tol: float, nontemporal: bool = False):
+    arr = (c_void_p * max(len(handles), 1))(*[h.value if isinstance(h, c_void_p) else h
+                                             for h in handles])
+    _check(load_library().stc_batch_set(bt, arr, len(handles), float(tol), int(bool(nontemporal))))
+
+
+def stc_batch_sweeps(bt, nsweeps: int, use_graph: bool = True):
+    _check(load_library().stc_batch_sweeps(bt, int(nsweeps), int(bool(use_graph))))
+
+
+def stc_batch_sync(bt):
+    _check(load_library().stc_batch_sync(bt))
+
+
+def stc_batch_destroy(bt):
+    if bt:
+        load_library().stc_batch_destroy(bt)
+
+
+class Batch:
+    """Many chains swept together (owns the batch tables' torch arena)."""
+
+    def __init__(self, max_chains: int, max_items: int, b: int = 1, device=None, stream=None):
+        """stream: a torch stream to launch on, or None for a stream the
+        library creates (graphs cannot be captured on the null stream)."""
+        import torch
+        load_library()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream
+        need = stc_batch_footprint(max_chains, max_items)
+        self.arena = torch.empty(need, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)   # the arena is ready before other streams use it
+        self.bt = stc_batch_create(max_chains, max_items, b,
+                                   stream.cuda_stream if stream is not None else 0,
+                                   self.arena.data_ptr(), need)
+        self.members = []
+
+    def set(self, solvers, tol: float, nontemporal: bool = False):
+        self.members = list(solvers)
+        stc_batch_set(self.bt, [s.h for s in self.members], tol, nontemporal)
+
+    def sweeps(self, n: int, use_graph: bool = True):
+        stc_batch_sweeps(self.bt, n, use_graph)
+
+    def sync(self):
+        stc_batch_sync(self.bt)
+
+    def close(self):
+        if getattr(self, "bt", None):
+            stc_batch_destroy(self.bt)
+            self.bt = None
+        self.arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def stc_destroy(h):
     if h:
         load_library().stc_destroy(h)
@@ -311,6 +401,9 @@ class Solver:
         pi = np.empty(self.N)
         stc_store(self.h, pi)
         return pi
+
+    def promote(self):
+        stc_promote(self.h)
 
     def close(self):
         if getattr(self, "h", None):

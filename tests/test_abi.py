@@ -96,3 +96,12 @@ def test_setup_rejects_bad_arguments(lib):
 def test_make_generator_checks_shape():
     with pytest.raises(ValueError):
         stc.make_generator(np.zeros((4, 3, 4, 5)), None, 1)
+
+
+def test_package_public_names_import():
+    import paper_2302_07551_amd as p
+    for name in ("Batch", "Solver", "StcError", "load_library"):
+        assert hasattr(p, name), name
+    for name in stc.EXPORTS:
+        assert callable(getattr(stc, name, None)) or name in ("stc_status_string",
+                                                              "stc_last_error"), name

@@ -1,0 +1,218 @@
+"""Batched sweeps over many chains against the same chains swept alone.
+
+The batched kernel runs the same per-level code as launch variant 0 of the
+single-chain kernel and the same fixed-order reductions, so every chain's
+iterate must be bitwise equal to the chain swept alone with variant 0.
+Graph replays are checked against plain launches, replay after replay, with
+host work and synchronisations in between.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import level_reduction
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _chains(specs, seed0=500):
+    return [synth.qbd(L, m, seed0 + k, last=last) for k, (L, m, last) in enumerate(specs)]
+
+
+SPECS = [(32, 8, None), (77, 16, 5), (130, 32, None), (45, 64, 33), (300, 8, 3), (19, 128, 100),
+         (64, 12, 7)]
+
+
+def _solvers(gens, precision="fp64", **kw):
+    from paper_2302_07551_amd import Solver, stc
+    out = []
+    for g in gens:
+        s = Solver(g.blocks, g.sizes, g.b, precision=precision, **kw)
+        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
+        out.append(s)
+    return out
+
+
+def _starts(gens, seed=7):
+    return [synth.positive_start(g, seed + k) for k, g in enumerate(gens)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_alone_bitwise(precision):
+    from paper_2302_07551_amd import Batch
+    gens = _chains(SPECS)
+    xs = _starts(gens)
+    nsw = 23
+    alone = []
+    for s, x in zip(_solvers(gens, precision), xs):
+        s.load(x)
+        s.sweeps(nsw)
+        alone.append(s.store())
+        s.close()
+    solvers = _solvers(gens, precision)
+    for s, x in zip(solvers, xs):
+        s.load(x)
+    b = Batch(16, 4096)
+    b.set(solvers, tol=0.0)
+    b.sweeps(nsw)
+    b.sync()
+    for k, s in enumerate(solvers):
+        _say(f"chain {k} L={gens[k].L} m={gens[k].m} {precision}")
+        it, stopped, _ = s.query()
+        assert it == nsw and not stopped
+        assert np.array_equal(s.store(), alone[k]), k
+    b.close()
+
+
+def test_graph_replays_match_plain_launches():
+    from paper_2302_07551_amd import Batch
+    gens = _chains(SPECS[:5], 600)
+    xs = _starts(gens, 3)
+    runs = {}
+    for use_graph in (True, False):
+        solvers = _solvers(gens)
+        for s, x in zip(solvers, xs):
+            s.load(x)
+        b = Batch(8, 2048)
+        b.set(solvers, tol=0.0)
+        snaps = []
+        for rep in range(4):
+            b.sweeps(6, use_graph=use_graph)
+            b.sync()
+            # eager work between replays: read every iterate back
+            snaps.append([s.store() for s in solvers])
+            _ = torch.ones(1000, device="cuda").sum().item()
+        runs[use_graph] = snaps
+        b.close()
+    for rep in range(4):
+        for k in range(len(gens)):
+            assert np.array_equal(runs[True][rep][k], runs[False][rep][k]), (rep, k)
+
+
+def test_device_stop_and_membership_changes():
+    from paper_2302_07551_amd import Batch
+    gens = _chains(SPECS, 700)
+    tol = 1e-12
+    # reference: each chain alone, change-based stop of section 3
+    ref_pi, ref_it = [], []
+    for s in _solvers(gens, check_every=10):
+        pi, info = s.solve(tol=tol, maxit=50000, allow_maxit=False)
+        ref_pi.append(pi)
+        ref_it.append(info["iters"])
+        s.close()
+    solvers = _solvers(gens)
+    for s in solvers:
+        s.load(None)
+    b = Batch(16, 4096)
+    first, rest = solvers[:4], solvers[4:]
+    b.set(first, tol=tol)
+    done = {}
+    active = list(first)
+    pending = list(rest)
+    rounds = 0
+    while active and rounds < 2000:
+        b.sweeps(25)
+        b.sync()
+        rounds += 1
+        keep = []
+        for s in active:
+            it, stopped, _ = s.query()
+            if stopped:
+                done[solvers.index(s)] = (s.store(), it)
+            else:
+                keep.append(s)
+        if len(keep) != len(active) or pending:
+            # retire stopped chains, admit waiting ones (same tables, same graph)
+            keep += pending[:2]
+            pending = pending[2:]
+            b.set(keep, tol=tol)
+        active = keep
+    assert len(done) == len(gens)
+    for k in range(len(gens)):
+        pi, it = done[k]
+        _say(f"chain {k}: batch stop {it} alone {ref_it[k]}")
+        assert it == ref_it[k]
+        assert np.array_equal(pi, ref_pi[k])
+    b.close()
+
+
+def test_mixed_precision_promote_in_batch():
+    from paper_2302_07551_amd import Batch
+    gens = _chains(SPECS[:4], 800)
+    tol = 1e-13
+    ref = []
+    for s in _solvers(gens, precision="mixed", switch_tol=1e-6, check_every=10):
+        pi, info = s.solve(tol=tol, maxit=50000, allow_maxit=False)
+        ref.append((pi, info["iters"], info["iters_fp32"]))
+        s.close()
+    solvers = _solvers(gens, precision="mixed", switch_tol=1e-6)
+    for s in solvers:
+        s.load(None)
+    b = Batch(8, 4096)
+    b.set(solvers, tol=tol)
+    stage = {k: 32 for k in range(len(gens))}
+    fp32_it, done = {}, {}
+    for _ in range(3000):
+        b.sweeps(20)
+        b.sync()
+        changed = False
+        for k, s in enumerate(solvers):
+            if k in done:
+                continue
+            it, stopped, _ = s.query()
+            if stopped and stage[k] == 32:
+                fp32_it[k] = it
+                s.promote()
+                stage[k] = 64
+                changed = True
+            elif stopped:
+                done[k] = (s.store(), it)
+        if len(done) == len(gens):
+            break
+        if changed:
+            b.set([s for k, s in enumerate(solvers) if k not in done], tol=tol)
+    assert len(done) == len(gens)
+    for k in range(len(gens)):
+        pi, it = done[k]
+        rpi, rit, rit32 = ref[k]
+        assert fp32_it[k] == rit32 and it == rit
+        assert np.array_equal(pi, rpi)
+        direct = level_reduction.level_reduction(gens[k].blocks, gens[k].sizes, gens[k].b)
+        assert np.abs(pi - direct).sum() <= 1e-10
+    b.close()
+
+
+def test_served_mix_shapes():
+    """A served-stream-like mix (L in [32, 2048], m in {8, 16, 32, 64})."""
+    from paper_2302_07551_amd import Batch
+    reqs = synth.served_stream(24, 42, rate=100.0)
+    gens = [synth.qbd(r["L"], r["m"], r["seed"]) for r in reqs]
+    xs = _starts(gens, 11)
+    alone = []
+    for s, x in zip(_solvers(gens, "fp32"), xs):
+        s.load(x)
+        s.sweeps(9)
+        alone.append(s.store())
+        s.close()
+    solvers = _solvers(gens, "fp32")
+    for s, x in zip(solvers, xs):
+        s.load(x)
+    b = Batch(32, 1 << 16)
+    b.set(solvers, tol=0.0, nontemporal=False)
+    b.sweeps(9)
+    b.sync()
+    for k, s in enumerate(solvers):
+        assert np.array_equal(s.store(), alone[k]), k
+    b.close()
