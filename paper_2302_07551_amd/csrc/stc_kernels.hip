@@ -155,7 +155,10 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *r
 
     // r_i: gather of the off-diagonal blocks of block row i of A.  The loop
     // has no branches, so all block loads of the level are in flight at once;
-    // a neighbour outside [0, L) has an all-zero stored block and weight 0.
+    // a neighbour outside [0, L) has an all-zero stored block and weight 0,
+    // and reads the old iterate at level ic instead (always written and
+    // finite, so 0 * value stays 0; the fresh buffer may still hold stale or
+    // uninitialised values there).
     VT acc = (VT)(T)0;
 #pragma unroll
     for (int d = -B; d <= B; ++d) {
@@ -163,7 +166,8 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *r
         const int k = ic + d;
         const bool in = (k >= 0) && (k < a.L);
         const bool fresh = PHB && (d == 1 || d == -1);
-        const T *v = (fresh ? (const T *)w_new : w_old) + (size_t)(in ? k : ic) * MP;
+        const T *v = in ? (fresh ? (const T *)w_new : w_old) + (size_t)k * MP
+                        : w_old + (size_t)ic * MP;
         const T vs = in ? (fresh ? (T)1 : sc) : (T)0;
         const T *gb = base + (size_t)(d + B) * BS + c * VEC;
 #pragma unroll

@@ -1,0 +1,193 @@
+"""Continuous-batching service of stationary-vector solves.
+
+Requests (independent block generators) arrive over time.  The service
+admits them in arrival order while the HBM footprint of the admitted chains
+stays under a budget and a batch slot is free, keeps every admitted chain's
+factored blocks and iterate resident on the device, and sweeps all admitted
+chains together with the batched (multi-chain, graph-replayed) launch.  A
+chain in its FP32 stage that meets the switch tolerance is promoted to FP64
+(stc_promote); a chain whose FP64 change meets the tolerance is retired: its
+vector is copied out, its memory freed, and waiting requests are admitted.
+Setup of new chains (host validation and packing, upload, inverse of the
+diagonal blocks) runs on a side stream while the batch sweeps on its own
+stream, so arrivals overlap with the work already on the GPU.
+
+Every step of the method runs in libstc.so; this module schedules calls.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import stc
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the run
+    blocks: np.ndarray        # [L][2b+1][m][m] generator blocks
+    sizes: np.ndarray | None
+    b: int = 1
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    done: float
+    pi: np.ndarray
+    sweeps: int
+    sweeps_fp32: int
+    footprint: int
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class ServeStats:
+    results: list = field(default_factory=list)
+    wall: float = 0.0
+    peak_chains: int = 0
+    peak_bytes: int = 0
+    rounds: int = 0
+    rejected: list = field(default_factory=list)
+
+    def summary(self) -> dict:
+        lat = np.array([r.latency for r in self.results]) if self.results else np.zeros(1)
+        first = min((r.arrival for r in self.results), default=0.0)
+        last = max((r.done for r in self.results), default=0.0)
+        return {
+            "completed": len(self.results),
+            "rejected": len(self.rejected),
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()),
+            "solves_per_s": len(self.results) / max(last - first, 1e-9),
+            "wall_s": self.wall,
+            "peak_chains": self.peak_chains,
+            "peak_bytes": self.peak_bytes,
+            "batch_rounds": self.rounds,
+        }
+
+
+class Server:
+    """Admission by footprint, continuous batching, FP32 -> FP64 promotion."""
+
+    def __init__(self, budget_bytes: int, *, max_chains: int = 64, max_items: int = 1 << 17,
+                 sweeps_per_round: int = 20, tol: float = 1e-13, switch_tol: float = 1e-6,
+                 precision: str = "mixed", nontemporal: bool = False, device=None,
+                 b: int = 1, use_graph: bool = True):
+        import torch
+        self.torch = torch
+        self.budget = int(budget_bytes)
+        self.max_chains = int(max_chains)
+        self.K = int(sweeps_per_round)
+        self.tol = float(tol)
+        self.switch_tol = float(switch_tol)
+        self.precision = precision
+        self.nontemporal = bool(nontemporal)
+        self.use_graph = use_graph
+        self.device = torch.device(device if device is not None else "cuda")
+        self.setup_stream = torch.cuda.Stream(device=self.device)
+        self.batch = stc.Batch(self.max_chains, max_items, b=b, device=self.device)
+
+    def footprint(self, req: Request) -> int:
+        gen, _keep = stc.make_generator(req.blocks, req.sizes, req.b)
+        opt = stc.make_options(self.precision, 1, "diff", 1, self.switch_tol)
+        return stc.stc_footprint_bytes(gen, opt)
+
+    def _admit(self, req: Request) -> stc.Solver:
+        s = stc.Solver(req.blocks, req.sizes, req.b, precision=self.precision,
+                       switch_tol=self.switch_tol, device=self.device,
+                       stream=self.setup_stream)
+        # the batched kernel is launch variant 0 of the single-chain kernel
+        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
+        s.load(None)
+        return s
+
+    def run(self, requests, clock=time.perf_counter) -> ServeStats:
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = deque(reqs)
+        waiting: deque = deque()
+        active = []          # (request, solver, footprint, admitted_at, stage)
+        used = 0
+        stats = ServeStats()
+        t0 = clock()
+        dirty = False
+        while pending or waiting or active:
+            now = clock() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission in arrival order: budget and free slots
+            while waiting and len(active) < self.max_chains:
+                req = waiting[0]
+                fp = self.footprint(req)
+                if fp > self.budget:
+                    waiting.popleft()
+                    stats.rejected.append(req.rid)
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                s = self._admit(req)
+                active.append([req, s, fp, clock() - t0, 32 if self.precision != "fp64" else 64])
+                used += fp
+                dirty = True
+            stats.peak_chains = max(stats.peak_chains, len(active))
+            stats.peak_bytes = max(stats.peak_bytes, used)
+            if not active:
+                if pending:
+                    delay = pending[0].arrival - (clock() - t0)
+                    if delay > 0:
+                        time.sleep(min(delay, 0.05))
+                continue
+            if dirty:
+                self.setup_stream.synchronize()
+                self.batch.set([a[1] for a in active], self.tol, self.nontemporal)
+                dirty = False
+            self.batch.sweeps(self.K, self.use_graph)
+            self.batch.sync()
+            stats.rounds += 1
+            keep = []
+            for entry in active:
+                req, s, fp, t_adm, stage = entry[:5]
+                try:
+                    it, stopped, _ = s.query()
+                except stc.StcError:
+                    # a sweep produced no positive mass: drop the request
+                    stats.rejected.append(req.rid)
+                    s.close()
+                    used -= fp
+                    dirty = True
+                    continue
+                if not stopped:
+                    keep.append(entry)
+                    continue
+                if stage == 32 and self.precision == "mixed":
+                    s.promote()
+                    entry[4] = 64
+                    entry.append(it)          # sweeps in FP32
+                    keep.append(entry)
+                    dirty = True
+                    continue
+                pi = s.store()
+                it32 = entry[5] if len(entry) > 5 else (it if self.precision == "fp32" else 0)
+                stats.results.append(Result(req.rid, req.arrival, t_adm, clock() - t0, pi, it,
+                                            it32, fp))
+                s.close()
+                used -= fp
+                dirty = True
+            active = keep
+        stats.wall = clock() - t0
+        return stats
+
+    def close(self):
+        self.batch.close()

@@ -347,7 +347,10 @@ class Solver:
 
     def __init__(self, blocks: np.ndarray, sizes, b: int, *, precision="fp64", stair_type=1,
                  stop="diff", check_every=1, switch_tol=0.0, recompute_diagonal=False,
-                 device=None, stream=None):
+                 device=None, stream=None, poison=False):
+        """poison: fill the arena with 0xFF bytes (a NaN in FP32 and FP64)
+        before setup, so that any read of memory the library did not write
+        first shows up as NaN in the results (a test aid)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the staircase solver needs a GPU")
@@ -361,6 +364,9 @@ class Solver:
         if need == 0:
             raise StcError(STC_EINVAL, "unsupported generator shape or options")
         self.arena = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if poison:
+            self.arena.fill_(0xFF)
+            torch.cuda.synchronize(self.device)
         self.opt.arena = self.arena.data_ptr()
         self.opt.arena_bytes = need
         self.footprint = need

@@ -113,6 +113,31 @@ def test_autotune_keeps_results():
     assert np.abs(pi - ref).sum() <= 1e-10
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("name,make", [SHAPES[0], SHAPES[1], SHAPES[2], SHAPES[5],
+                                       SHAPES[7], SHAPES[8]],
+                         ids=[SHAPES[k][0] for k in (0, 1, 2, 5, 7, 8)])
+def test_poisoned_arena(name, make, precision):
+    """Every byte of the arena starts as NaN; nothing the library reads before
+    writing may leak into a result (both even and odd level counts, so the
+    last level is a phase-A level in one case and a phase-B level in the
+    other)."""
+    from paper_2302_07551_amd import stc
+    for g in (make(), synth.qbd(60, 64, 323523084)):
+        x = synth.positive_start(g, 13)
+        zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x, 1)
+        stage = stc.STC_FP64 if precision == "fp64" else stc.STC_FP32
+        for v in range(stc.stc_variant_count()):
+            s = _solver(g, precision=precision, poison=True)
+            stc.stc_set_variant(s.h, stage, v)
+            z, d = s.step(x)
+            tol = 1e-13 if precision == "fp64" else 1e-5
+            assert np.all(np.isfinite(z)), (name, v)
+            assert np.abs(z - zr).sum() <= tol and abs(d - dr) <= tol, (name, v)
+            assert np.isfinite(s.residual(x))
+            s.close()
+
+
 def test_repeated_steps_track_oracle():
     g = synth.qbd(24, 16, 31, last=9)
     s = _solver(g)

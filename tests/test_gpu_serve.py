@@ -1,0 +1,68 @@
+"""The continuous-batching service: every served result equals the same chain
+solved alone (same schedule, same device stopping tests, launch variant 0),
+admission never exceeds the memory budget, and requests overlap on the GPU."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import level_reduction
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _requests(count, seed, rate, L_range=(32, 400), m_choices=(8, 16, 32, 64)):
+    from paper_2302_07551_amd.serve import Request
+    specs = synth.served_stream(count, seed, L_range=L_range, m_choices=m_choices, rate=rate)
+    reqs, gens = [], []
+    for k, sp in enumerate(specs):
+        g = synth.qbd(sp["L"], sp["m"], sp["seed"])
+        gens.append(g)
+        reqs.append(Request(k, sp["arrival"], g.blocks, g.sizes, g.b))
+    return reqs, gens
+
+
+def test_served_equals_alone_and_budget_holds():
+    from paper_2302_07551_amd import Solver, stc
+    from paper_2302_07551_amd.serve import Server
+    reqs, gens = _requests(12, 2024, rate=40.0)
+    tol, sw = 1e-13, 1e-6
+    srv = Server(budget_bytes=1, max_chains=8, sweeps_per_round=15, tol=tol, switch_tol=sw)
+    fps = [srv.footprint(r) for r in reqs]
+    srv.budget = int(sum(sorted(fps)[-4:]))      # binds: at most a few chains at once
+    stats = srv.run(reqs)
+    srv.close()
+    summ = stats.summary()
+    print(summ, flush=True)
+    assert summ["completed"] == len(reqs) and not stats.rejected
+    assert stats.peak_bytes <= srv.budget
+    assert stats.peak_chains >= 2                 # requests overlapped on the GPU
+    by_id = {r.rid: r for r in stats.results}
+    for k, g in enumerate(gens):
+        s = Solver(g.blocks, g.sizes, g.b, precision="mixed", switch_tol=sw, check_every=10)
+        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
+        pi, info = s.solve(tol=tol, maxit=100000, allow_maxit=False)
+        s.close()
+        r = by_id[k]
+        assert r.sweeps == info["iters"] and r.sweeps_fp32 == info["iters_fp32"], k
+        assert np.array_equal(r.pi, pi), k
+        ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+        assert np.abs(r.pi - ref).sum() <= 1e-10, k
+
+
+def test_oversized_request_is_rejected():
+    from paper_2302_07551_amd.serve import Server
+    reqs, _ = _requests(3, 7, rate=1000.0, L_range=(40, 60), m_choices=(16,))
+    srv = Server(budget_bytes=1, max_chains=4, sweeps_per_round=10)
+    fps = [srv.footprint(r) for r in reqs]
+    srv.budget = min(fps) - 1                      # nothing fits
+    stats = srv.run(reqs)
+    srv.close()
+    assert sorted(stats.rejected) == [0, 1, 2] and not stats.results
