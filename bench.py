@@ -20,6 +20,10 @@ Other workloads (each prints its own JSON line instead):
   --serve N       served stream of N QBD requests (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
+  --pmc-probe     a short run for hardware counters: 10 autotuned sweeps of the
+                  default workload, then a 1 GiB device-to-device copy (the
+                  calibration kernel of known traffic), run under
+                  rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)
 """
 from __future__ import annotations
 
@@ -90,6 +94,7 @@ def main():
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--serve", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=4.0)
+    ap.add_argument("--pmc-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -99,6 +104,8 @@ def main():
         return large_mode(args)
     if args.serve:
         return serve_mode(args)
+    if args.pmc_probe:
+        return pmc_probe()
 
     import numpy as np
     import torch
@@ -272,6 +279,29 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
             "speedup_mixed_vs_fp64": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3),
             "runs": runs, "sweep_rates": rates}
     print(json.dumps(line), flush=True)
+
+
+def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30):
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    gen = synth.qbd(L, m, synth.config_seed(1))
+    s = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64")
+    stc.stc_autotune(s.h, 10)
+    s.load(None)
+    s.sweeps(sweeps)
+    torch.cuda.synchronize()
+    ba, bb = stc.stc_phase_bytes(s.h)
+    x = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": f"qbd_L{L}_m{m}_fp64", "variant": stc.stc_get_variant(s.h, 0),
+                      "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
+                      "source_hash": kernel_source_hash()}), flush=True)
+    s.close()
 
 
 def args_tol(err_target):
