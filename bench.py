@@ -20,6 +20,9 @@ Other workloads (each prints its own JSON line instead):
   --serve N       served stream of N QBD requests (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
+  --setup L M     time setup (validation and packing on the host, upload, the
+                  batched inverse of the diagonal blocks) for a QBD of L levels
+                  and block size M, FP64 and mixed
   --pmc-probe     a short run for hardware counters: 10 autotuned sweeps of the
                   default workload, then a 1 GiB device-to-device copy (the
                   calibration kernel of known traffic), run under
@@ -95,6 +98,7 @@ def main():
     ap.add_argument("--serve", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--pmc-probe", action="store_true")
+    ap.add_argument("--setup", type=int, nargs=2, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -106,6 +110,8 @@ def main():
         return serve_mode(args)
     if args.pmc_probe:
         return pmc_probe()
+    if args.setup:
+        return setup_mode(*args.setup)
 
     import numpy as np
     import torch
@@ -279,6 +285,25 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
             "speedup_mixed_vs_fp64": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3),
             "runs": runs, "sweep_rates": rates}
     print(json.dumps(line), flush=True)
+
+
+def setup_mode(L, m):
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver
+    torch.cuda.set_device(0)
+    gen = synth.qbd(L, m, synth.config_seed(1))
+    out = {}
+    for prec in ("fp64", "mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec)
+        torch.cuda.synchronize()
+        out[prec] = round(time.perf_counter() - t0, 4)
+        s.close()
+    flops = 2.0 * L * m ** 3
+    print(json.dumps({"setup_seconds": out, "workload": f"qbd_L{L}_m{m}",
+                      "inverse_flops": flops}), flush=True)
 
 
 def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30):

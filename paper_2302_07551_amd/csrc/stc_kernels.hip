@@ -585,6 +585,138 @@ __global__ __launch_bounds__(kWG) void k_invert(const double *diag, const int *s
 }
 
 // ---------------------------------------------------------------------------
+// W_i = (-Q_ii)^{-1} by blocked Gauss-Jordan elimination with FP64 MFMA, one
+// level per workgroup, the whole block in LDS.  For each 16-wide panel k:
+//   D^{-1}     inverse of the 16x16 diagonal tile (one wave, VALU)
+//   R          = D^{-1} A[k, j]              row panel, j != k      (MFMA)
+//   A[i, j]   -= A[i, k] R[k, j]             trailing update, i, j != k (MFMA)
+//   A[i, k]    = -A[i, k] D^{-1},  A[k, k] = D^{-1}   column panel  (MFMA)
+// which is the unblocked elimination of k_invert regrouped by panels, so it
+// needs no pivoting for the same reason; a diagonal-tile pivot that is not
+// clearly positive relative to the original diagonal marks the block singular.
+// v_mfma_f64_16x16x4f64 lane layout: A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, D[i][j] in register i / 4 of lane j + 16 (i % 4).
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const int *sizes,
+                                                      double *blk, int NB, int B, DevState *st) {
+    constexpr int LD = MP + 2;      // row stride in LDS (doubles)
+    constexpr int NT = MP / 16;     // panels
+    constexpr int DL = 17;          // stride of the 16x16 tile
+    __shared__ double a[MP * LD];
+    __shared__ double dinv[16 * DL];
+    __shared__ double dorig[MP];
+    __shared__ int bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;   // lane's row/column in a 16-wide tile, quarter
+    const int i = blockIdx.x;
+    const int n = sizes[i];
+    const double *Q = diag + (size_t)i * MP * MP;
+    if (tid == 0) bad = 0;
+    for (int idx = tid; idx < MP * MP; idx += kWG) {
+        const int r = idx / MP, c = idx - r * MP;
+        double v;
+        if (r < n && c < n) v = -Q[idx];
+        else v = (r == c) ? 1.0 : 0.0;
+        a[r * LD + c] = v;
+        if (r == c) dorig[r] = v;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < NT; ++kb) {
+        const int k0 = 16 * kb;
+        if (wave == 0) {
+            // inverse of the diagonal tile, in place: lanes own 4 of its 256 entries
+            for (int t = 0; t < 4; ++t) {
+                const int e = lane + 64 * t, r = e >> 4, c = e & 15;
+                dinv[r * DL + c] = a[(k0 + r) * LD + k0 + c];
+            }
+            for (int k = 0; k < 16; ++k) {
+                const double p = dinv[k * DL + k];
+                double nv[4];
+                for (int t = 0; t < 4; ++t) {
+                    const int e = lane + 64 * t, r = e >> 4, c = e & 15;
+                    const double col = dinv[r * DL + k], row = dinv[k * DL + c];
+                    const double cur = dinv[r * DL + c];
+                    if (r == k) nv[t] = (c == k) ? 1.0 / p : row / p;
+                    else if (c == k) nv[t] = -col / p;
+                    else nv[t] = cur - col * row / p;
+                }
+                if (lane == 0 && (!(p > 1e-13 * dorig[k0 + k]) || !isfinite(p))) bad = 1;
+                for (int t = 0; t < 4; ++t) {
+                    const int e = lane + 64 * t, r = e >> 4, c = e & 15;
+                    dinv[r * DL + c] = nv[t];
+                }
+            }
+        }
+        __syncthreads();
+        // row panel: R = D^{-1} A[k, j]
+        for (int jb = wave; jb < NT; jb += 4) {
+            if (jb == kb) continue;
+            const int j0 = 16 * jb;
+            d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double av = dinv[lr * DL + 4 * s4 + lq];
+                const double bv = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
+                acc = mfma16x16x4(av, bv, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[(k0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
+        }
+        __syncthreads();
+        // trailing update: A[i, j] += (-A[i, k]) R[k, j]
+        for (int t = wave; t < NT * NT; t += 4) {
+            const int ib = t / NT, jb = t - ib * NT;
+            if (ib == kb || jb == kb) continue;
+            const int i0 = 16 * ib, j0 = 16 * jb;
+            d4_t acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = a[(i0 + lq + 4 * v) * LD + j0 + lr];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double av = -a[(i0 + lr) * LD + k0 + 4 * s4 + lq];
+                const double bv = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
+                acc = mfma16x16x4(av, bv, acc);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[(i0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
+        }
+        __syncthreads();
+        // column panel: A[i, k] = -A[i, k] D^{-1};  A[k, k] = D^{-1}
+        for (int ib = wave; ib < NT; ib += 4) {
+            const int i0 = 16 * ib;
+            d4_t acc = {0.0, 0.0, 0.0, 0.0};
+            if (ib == kb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = dinv[(lq + 4 * v) * DL + lr];
+            } else {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const double av = -a[(i0 + lr) * LD + k0 + 4 * s4 + lq];
+                    const double bv = dinv[(4 * s4 + lq) * DL + lr];
+                    acc = mfma16x16x4(av, bv, acc);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) a[(i0 + lq + 4 * v) * LD + k0 + lr] = acc[v];
+        }
+        __syncthreads();
+    }
+    double *W = blk + ((size_t)i * NB + B) * MP * MP;
+    for (int idx = tid; idx < MP * MP; idx += kWG) {
+        const int r = idx / MP, c = idx - r * MP;
+        W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
+    }
+    if (tid == 0 && bad) atomicAdd(&st->bad_blocks, 1);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 int supported_mp(int m) {
@@ -670,8 +802,12 @@ hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, 
 template <int MP>
 static hipError_t invert_mp(int b, const double *diag, const int *sizes, double *blk, int L,
                             DevState *st, hipStream_t s) {
-    hipLaunchKernelGGL((k_invert<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk, 2 * b + 1, b,
-                       st);
+    if constexpr (MP >= 32)
+        hipLaunchKernelGGL((k_invert_mfma<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk,
+                           2 * b + 1, b, st);
+    else
+        hipLaunchKernelGGL((k_invert<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk, 2 * b + 1,
+                           b, st);
     return hipGetLastError();
 }
 

@@ -279,13 +279,16 @@ def test_not_a_generator():
     assert e.value.status == stc.STC_ENOTGEN
 
 
-def test_singular_diagonal_block():
+@pytest.mark.parametrize("m", [4, 64, 128])
+def test_singular_diagonal_block(m):
+    """A level that never leaves itself: caught by the pivot test of the
+    VALU inverse (m <= 16) and of the MFMA blocked inverse (m >= 32)."""
     from paper_2302_07551_amd import stc
-    g = synth.qbd(6, 4, 103)
+    g = synth.qbd(6, m, 103)
     # level 3 never leaves itself: drop its up and down rates, refix the diagonal
     g.blocks[3, 0] = 0.0
     g.blocks[3, 2] = 0.0
-    ar = np.arange(4)
+    ar = np.arange(m)
     g.blocks[3, 1, ar, ar] = 0.0
     g.blocks[3, 1, ar, ar] = -g.blocks[3, 1].sum(axis=1)
     with pytest.raises(stc.StcError) as e:
