@@ -20,6 +20,9 @@ Other workloads (each prints its own JSON line instead):
   --serve N       served stream of N QBD requests (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
+  --banded        2048 levels x m=128 block-pentadiagonal generator with 10 %
+                  dense off-diagonal blocks: sweeps/s and GB/s with dense and
+                  sparse (ELL) off-diagonal storage, FP64 and FP32
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -99,6 +102,7 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--setup", type=int, nargs=2, default=None)
+    ap.add_argument("--banded", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -112,6 +116,8 @@ def main():
         return pmc_probe()
     if args.setup:
         return setup_mode(*args.setup)
+    if args.banded:
+        return banded_mode()
 
     import numpy as np
     import torch
@@ -216,11 +222,11 @@ def time_to_residual(gen, tol=1e-12):
     return out
 
 
-def sweep_rate(gen, precision, steps=50, warmup=5):
+def sweep_rate(gen, precision, steps=50, warmup=5, format="dense"):
     """Autotuned per-sweep time and algorithmic GB/s of one precision."""
     import torch
     from paper_2302_07551_amd import Solver, stc
-    s = Solver(gen.blocks, gen.sizes, gen.b, precision=precision)
+    s = Solver(gen.blocks, gen.sizes, gen.b, precision=precision, format=format)
     stc.stc_autotune(s.h, 5)
     s.load(None)
     s.sweeps(warmup)
@@ -284,6 +290,32 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
                        "seed": synth.config_seed(3)},
             "speedup_mixed_vs_fp64": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3),
             "runs": runs, "sweep_rates": rates}
+    print(json.dumps(line), flush=True)
+
+
+def banded_mode(L=2048, m=128):
+    """Sweep rate on the block-pentadiagonal 10 %-dense generator.  Its
+    symmetric rates give no drift, so a solve from e/N takes on the order of
+    L^2 sweeps; the figure of merit is the sweep rate."""
+    import torch
+    import synth
+    torch.cuda.set_device(0)
+    gen = synth.banded(L, m, synth.config_seed(2), b=2, density=0.1, decay=0.5)
+    runs = {}
+    for fmt in ("dense", "sparse"):
+        for prec in ("fp64", "fp32"):
+            r = sweep_rate(gen, prec, steps=100, format=fmt)
+            r["sweeps_per_s"] = round(1e3 / r["ms_per_sweep"], 1)
+            runs[f"{fmt}_{prec}"] = r
+            print(f"# {fmt} {prec}: {r}", file=sys.stderr, flush=True)
+    line = {"metric": "sweeps/s on the banded generator (dense vs sparse blocks)",
+            "value": runs["sparse_fp64"]["sweeps_per_s"], "unit": "sweeps/s",
+            "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"banded_b2_L{L}_m{m}_d0.1", "levels": L, "block": m,
+                       "N": L * m, "seed": synth.config_seed(2)},
+            "runs": runs,
+            "speedup_sparse_vs_dense_fp64": round(runs["dense_fp64"]["ms_per_sweep"] /
+                                                 runs["sparse_fp64"]["ms_per_sweep"], 3)}
     print(json.dumps(line), flush=True)
 
 

@@ -59,6 +59,7 @@ typedef enum {
 enum { STC_FP64 = 0, STC_FP32 = 1, STC_MIXED = 2 };   /* stc_options.precision */
 enum { STC_STOP_DIFF = 0, STC_STOP_RESIDUAL = 1 };     /* stc_options.stop      */
 enum { STC_MEM_HOST = 0, STC_MEM_DEVICE = 1 };         /* "where" arguments     */
+enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    */
 
 /* The block generator (section 2 block partition).  blocks is a host array
  * [L][2b+1][m][m], row-major: blocks[i][d+b] holds Q_{i,i+d} (rows = states
@@ -96,6 +97,14 @@ typedef struct {
     void *arena;          /* device memory owned by the caller, 256-byte
                              aligned, on the current device                  */
     size_t arena_bytes;   /* its size, >= stc_footprint_bytes()              */
+    int32_t format;       /* device storage of the off-diagonal blocks swept:
+                             STC_DENSE: dense m x m blocks;
+                             STC_SPARSE: per block, its nonzeros grouped by
+                             column and padded to the block's longest column
+                             (values + 8-bit row indices), for sparse
+                             (localized) generators.  The inverse diagonal
+                             blocks are dense in both.  Batches take dense
+                             chains only.                                     */
 } stc_options;
 
 typedef struct {

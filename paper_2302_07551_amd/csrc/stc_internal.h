@@ -47,6 +47,15 @@ struct SweepLaunch {
     long long s;          // sweep being produced (>= 1)
 };
 
+// One sparse off-diagonal block (column-major ELL in slot quads): K slots per
+// column (a multiple of 4); slot k = 4 kq + t of column j sits at
+// off + (kq MP + j) 4 + t in the value and row-index pools.
+struct EllEntry {
+    long long off;
+    int K;
+    int pad_;
+};
+
 // One chain of a batched (multi-chain) launch, as the device reads it.  The
 // blocks and iterate buffers are those of the chain's current precision
 // stage; its sweep number is DevState::last_sweep + 1.
@@ -73,6 +82,9 @@ int variant_count();
 int phase_groups(int precision_bytes, int MP, int L, int parity, int variant);
 hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, int variant,
                               const SweepLaunch &a, hipStream_t stream);
+hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase_b,
+                                  const SweepLaunch &a, const EllEntry *tab, const void *val,
+                                  const unsigned char *idx, hipStream_t stream);
 hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
                                  DevState *st, long long s, double tol, hipStream_t stream);
 hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, double *blk,

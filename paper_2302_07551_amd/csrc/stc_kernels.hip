@@ -254,6 +254,161 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
 }
 
 // ---------------------------------------------------------------------------
+// half-sweep with sparse off-diagonal blocks (column-major ELL per block):
+// the nonzeros of block Q_{i+d,i} are grouped by output column j, padded to
+// 4 Kq slots with Kq = ceil(longest column / 4), and stored by slot quads:
+// slot 4 kq + t of column j at [kq][j][t], a value and the 8-bit row index r
+// of the source vector v_{i+d}.  A lane owns a column and reads a quad with
+// one 16-byte (FP32) or two 16-byte (FP64) value loads and one 4-byte index
+// load; consecutive lanes read consecutive quads, so loads are coalesced.
+// The source vectors are staged in LDS for the row gather; W_i stays dense.
+// The summation order is fixed (deterministic).
+// ---------------------------------------------------------------------------
+template <typename T, int MP, int B, bool PHB>
+__device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *tab,
+                                       const T *ell_val, const unsigned char *ell_idx, int q,
+                                       bool live, T *red_base, T *rv_base, T *src_base,
+                                       double *sh) {
+    using TL = Tile<T, MP, 8>;
+    using VT = typename Vec16<T>::type;
+    constexpr int NB = 2 * B + 1;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
+                  LPW = TL::LPW, PF = TL::PF;
+    constexpr int G = TS / MP;            // groups splitting the ELL slots of a column
+    constexpr size_t BS = (size_t)MP * MP;
+    static_assert(G >= 1, "team narrower than a block");
+
+    const DevState *st = a.st;
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    T *red = red_base + team * (R * MP);
+    T *rv = rv_base + team * MP;
+    T *src = src_base + team * (2 * B * MP);   // [2B][MP] scaled source vectors
+    const int i = a.parity + 2 * (q * LPW + team);
+    const bool active = i < a.L;
+    const int ic = active ? i : a.parity;
+    const T *w_old = a.w_old;
+    T *w_new = a.w_new;
+    const double inv_old = st->inv_sigma[(a.s - 1) & kRingMask];
+    const T sc = (T)inv_old;
+    const T *wb = a.blk + ((size_t)ic * NB + B) * BS + c * VEC;
+
+    // rows of W_i stream while the sparse part runs
+    VT vpre[PF];
+#pragma unroll
+    for (int qq = 0; qq < PF; ++qq)
+        vpre[qq] = stream_load<VT, true>((const VT *)(wb + (size_t)(g + R * qq) * MP));
+
+    // stage the source vectors (scaled; zero outside [0, L))
+    for (int e = tt; e < 2 * B * MP; e += TS) {
+        const int slot = e / MP, r = e - slot * MP;
+        const int d = slot < B ? slot - B : slot - B + 1;   // -B..-1, 1..B
+        const int k = ic + d;
+        T v = 0;
+        if (k >= 0 && k < a.L) {
+            const bool fresh = PHB && (d == 1 || d == -1);
+            v = fresh ? w_new[(size_t)k * MP + r] : w_old[(size_t)k * MP + r] * sc;
+        }
+        src[e] = v;
+    }
+    __syncthreads();
+
+    // r_i[j] = sum_d sum_k val[k][j] * v_{i+d}[idx[k][j]], a quad of slots per load
+    const int j = tt % MP, gg0 = tt / MP;
+    T accs = 0;
+#pragma unroll
+    for (int slot = 0; slot < 2 * B; ++slot) {
+        const int d = slot < B ? slot - B : slot - B + 1;
+        const EllEntry e = tab[(size_t)ic * NB + (d + B)];
+        const T *sv = src + slot * MP;
+        const int Kq = e.K >> 2;
+        for (int kq = gg0; kq < Kq; kq += G) {
+            const size_t o = (size_t)e.off + ((size_t)kq * MP + j) * 4;
+            const unsigned int r4 = __builtin_nontemporal_load((const unsigned int *)(ell_idx + o));
+            if constexpr (sizeof(T) == 8) {
+                const VT v01 = __builtin_nontemporal_load((const VT *)(ell_val + o));
+                const VT v23 = __builtin_nontemporal_load((const VT *)(ell_val + o + 2));
+                accs += v01[0] * sv[r4 & 0xff] + v01[1] * sv[(r4 >> 8) & 0xff] +
+                        v23[0] * sv[(r4 >> 16) & 0xff] + v23[1] * sv[r4 >> 24];
+            } else {
+                const VT v4 = __builtin_nontemporal_load((const VT *)(ell_val + o));
+                accs += v4[0] * sv[r4 & 0xff] + v4[1] * sv[(r4 >> 8) & 0xff] +
+                        v4[2] * sv[(r4 >> 16) & 0xff] + v4[3] * sv[r4 >> 24];
+            }
+        }
+    }
+    red[gg0 * MP + j] = accs;
+    __syncthreads();
+    if (tt < MP) {
+        T r = 0;
+#pragma unroll
+        for (int x = 0; x < G; ++x) r += red[x * MP + tt];
+        rv[tt] = r;
+    }
+    __syncthreads();
+
+    // z_i = W_i r_i (dense)
+    VT acc2 = (VT)(T)0;
+#pragma unroll
+    for (int qq = 0; qq < RPT; ++qq) {
+        const int row = g + R * qq;
+        const VT wv = (qq < PF) ? vpre[qq < PF ? qq : 0]
+                                : stream_load<VT, true>((const VT *)(wb + (size_t)row * MP));
+        acc2 += wv * rv[row];
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
+    __syncthreads();
+
+    double zs = 0.0, dd = 0.0;
+    if (live && active && tt < MP) {
+        T z = 0;
+#pragma unroll
+        for (int x = 0; x < R; ++x) z += red[x * MP + tt];
+        w_new[(size_t)i * MP + tt] = z;
+        zs = (double)z;
+        if (a.s >= 2) {
+            const double inv_older = st->inv_sigma[(a.s - 2) & kRingMask];
+            dd = fabs((double)w_old[(size_t)i * MP + tt] * inv_old -
+                      (double)a.w_older[(size_t)i * MP + tt] * inv_older);
+        }
+    }
+    const double S = block_sum(zs, sh);
+    const double D = block_sum(dd, sh);
+    if (live && tid == 0) {
+        a.part_sum[a.slot0 + q] = S;
+        a.part_diff[a.slot0 + q] = D;
+    }
+}
+
+template <typename T, int MP, int B, bool PHB>
+__global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry *tab,
+                                                    const void *ell_val,
+                                                    const unsigned char *ell_idx) {
+    using TL = Tile<T, MP, 8>;
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
+    __shared__ T src[TL::LPW * 2 * B * MP];
+    __shared__ double sh[kWG / 64];
+    ChainView<T> v;
+    v.blk = (const T *)a.blk;
+    v.w_old = (const T *)a.w_old;
+    v.w_older = (const T *)a.w_older;
+    v.w_new = (T *)a.w_new;
+    v.part_sum = a.part_sum;
+    v.part_diff = a.part_diff;
+    v.st = a.st;
+    v.L = a.L;
+    v.parity = a.parity;
+    v.slot0 = a.slot0;
+    v.s = a.s;
+    const bool live = a.st->stop_flag == 0;
+    sweep_group_ell<T, MP, B, PHB>(v, tab, (const T *)ell_val, ell_idx, blockIdx.x, live, red,
+                                   rv, src, sh);
+}
+
+// ---------------------------------------------------------------------------
 // many chains: one persistent launch per half-sweep over a work list of
 // (chain, group) items; each chain's sweep number comes from its own state
 // ---------------------------------------------------------------------------
@@ -797,6 +952,43 @@ hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, 
                       : sweep_b<double, 2>(MP, phase_b, variant, a, stream);
     return b == 1 ? sweep_b<float, 1>(MP, phase_b, variant, a, stream)
                   : sweep_b<float, 2>(MP, phase_b, variant, a, stream);
+}
+
+template <typename T, int MP, int B>
+static hipError_t ell_mpb(bool phase_b, const SweepLaunch &a, const EllEntry *tab,
+                          const void *val, const unsigned char *idx, hipStream_t s) {
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, 0);
+    if (groups <= 0) return hipSuccess;
+    if (phase_b)
+        hipLaunchKernelGGL((k_sweep_ell<T, MP, B, true>), dim3(groups), dim3(kWG), 0, s, a, tab,
+                           val, idx);
+    else
+        hipLaunchKernelGGL((k_sweep_ell<T, MP, B, false>), dim3(groups), dim3(kWG), 0, s, a, tab,
+                           val, idx);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+static hipError_t ell_b(int MP, bool phase_b, const SweepLaunch &a, const EllEntry *tab,
+                        const void *val, const unsigned char *idx, hipStream_t s) {
+    switch (MP) {
+        case 8: return ell_mpb<T, 8, B>(phase_b, a, tab, val, idx, s);
+        case 16: return ell_mpb<T, 16, B>(phase_b, a, tab, val, idx, s);
+        case 32: return ell_mpb<T, 32, B>(phase_b, a, tab, val, idx, s);
+        case 64: return ell_mpb<T, 64, B>(phase_b, a, tab, val, idx, s);
+        case 128: return ell_mpb<T, 128, B>(phase_b, a, tab, val, idx, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase_b,
+                                  const SweepLaunch &a, const EllEntry *tab, const void *val,
+                                  const unsigned char *idx, hipStream_t stream) {
+    if (precision_bytes == 8)
+        return b == 1 ? ell_b<double, 1>(MP, phase_b, a, tab, val, idx, stream)
+                      : ell_b<double, 2>(MP, phase_b, a, tab, val, idx, stream);
+    return b == 1 ? ell_b<float, 1>(MP, phase_b, a, tab, val, idx, stream)
+                  : ell_b<float, 2>(MP, phase_b, a, tab, val, idx, stream);
 }
 
 template <int MP>

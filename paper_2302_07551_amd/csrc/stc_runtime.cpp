@@ -42,11 +42,39 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     int MP = 0, NB = 0;
     bool fp32 = false;          // FP32 copies of blocks and iterates
+    bool sparse = false;        // off-diagonal blocks swept from ELL storage
+    size_t ell_tab = 0, ell_v64 = 0, ell_v32 = 0, ell_idx = 0;
+    long long ell_slots = 0;    // sum over blocks of K * MP
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0;
     size_t nparts = 0, naux = 0;
     size_t total = 0;
 };
+
+int level_size(const stc_generator *g, int i) { return g->sizes ? g->sizes[i] : g->m; }
+
+// Longest column (number of nonzeros) of the gather-oriented block Q_{k,i},
+// rounded up to a multiple of 4 (the ELL slot count stored per column).
+int ell_K(const stc_generator *g, int i, int d) {
+    const int k = i + d, b = g->b, m = g->m, NB = 2 * b + 1;
+    if (k < 0 || k >= g->L || d == 0) return 0;
+    const double *Q = g->blocks + ((size_t)k * NB + (-d + b)) * (size_t)m * m;
+    const int nk = level_size(g, k), ni = level_size(g, i);
+    int K = 0;
+    for (int j = 0; j < ni; ++j) {
+        int cnt = 0;
+        for (int r = 0; r < nk; ++r) cnt += Q[(size_t)r * m + j] != 0.0;
+        K = std::max(K, cnt);
+    }
+    return (K + 3) / 4 * 4;   // stored in quads of slots
+}
+
+long long ell_slot_count(const stc_generator *g, int MP) {
+    long long tot = 0;
+    for (int i = 0; i < g->L; ++i)
+        for (int d = -g->b; d <= g->b; ++d) tot += (long long)ell_K(g, i, d) * MP;
+    return tot;
+}
 
 bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     *why = 0;
@@ -56,10 +84,14 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     const int MP = supported_mp(g->m);
     if (!MP) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
+    if (o->format != STC_DENSE && o->format != STC_SPARSE) { *why = 5; return false; }
+    if (!g->blocks) { *why = 6; return false; }
     Layout l;
     l.MP = MP;
     l.NB = 2 * g->b + 1;
     l.fp32 = o->precision != STC_FP64;
+    l.sparse = o->format == STC_SPARSE;
+    if (l.sparse) l.ell_slots = ell_slot_count(g, MP);
     const size_t L = (size_t)g->L, bs = (size_t)MP * MP, vec = L * MP;
     size_t at = 0;
     auto take = [&](size_t bytes) { size_t p = at; at = align_up(at + bytes); return p; };
@@ -75,6 +107,12 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.part_diff = take(l.nparts * 8);
     l.naux = std::max<size_t>(2 * 1024 + 8, L + 8);
     l.part_aux = take(l.naux * 8);
+    if (l.sparse) {
+        l.ell_tab = take(L * l.NB * sizeof(EllEntry));
+        l.ell_v64 = take((size_t)l.ell_slots * 8);
+        if (l.fp32) l.ell_v32 = take((size_t)l.ell_slots * 4);
+        l.ell_idx = take((size_t)l.ell_slots);
+    }
     l.off = take((L + 1) * 8);
     l.sizes = take(L * 4);
     l.state = take(sizeof(DevState));
@@ -103,6 +141,12 @@ struct stc_handle {
     std::vector<int> sizes;
     long long N = 0;
     int variant[2] = {0, 0};   // sweep-kernel launch variant for FP64 [0] / FP32 [1] stages
+    bool sparse = false;
+    EllEntry *ell_tab = nullptr;
+    double *ell_v64 = nullptr;
+    float *ell_v32 = nullptr;
+    unsigned char *ell_idx = nullptr;
+    std::vector<int> ell_K;    // [L][NB] longest column per block
     // iteration state
     long long s = 0;        // sweeps done since the last load
     bool stage32 = false;   // current iterate lives in the FP32 rotation
@@ -136,16 +180,24 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev)
     const int pA = (h->stair_type == 1) ? 0 : 1;
     const int pB = 1 - pA;
     const int bytes = f32 ? 4 : 8;
-    const int gA = phase_groups(bytes, h->MP, h->L, pA, v);
-    const int gB = phase_groups(bytes, h->MP, h->L, pB, v);
+    const int vv = h->sparse ? 0 : v;   // the sparse kernel has variant 0's geometry
+    const int gA = phase_groups(bytes, h->MP, h->L, pA, vv);
+    const int gB = phase_groups(bytes, h->MP, h->L, pB, vv);
     a.nslots = gA + gB;
     a.parity = pA;
     a.slot0 = 0;
-    hipError_t e = launch_sweep_phase(bytes, h->MP, h->b, false, v, a, h->stream);
+    const void *ev_val = f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64;
+    auto phase = [&](bool phb) {
+        if (h->sparse)
+            return launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab, ev_val,
+                                          h->ell_idx, h->stream);
+        return launch_sweep_phase(bytes, h->MP, h->b, phb, v, a, h->stream);
+    };
+    hipError_t e = phase(false);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[0], h->stream);
     a.parity = pB;
     a.slot0 = gA;
-    if (e == hipSuccess) e = launch_sweep_phase(bytes, h->MP, h->b, true, v, a, h->stream);
+    if (e == hipSuccess) e = phase(true);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], h->stream);
     if (e == hipSuccess)
         e = launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, tol, h->stream);
@@ -305,8 +357,9 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     int why = 0;
     if (!plan(g, o, &lay, &why)) {
         static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be 1 or 2",
-                                    "m must be in 1..128", "unknown precision"};
-        return fail(STC_EINVAL, "%s", msg[why < 5 ? why : 0]);
+                                    "m must be in 1..128", "unknown precision", "unknown format",
+                                    "blocks is NULL"};
+        return fail(STC_EINVAL, "%s", msg[why < 7 ? why : 0]);
     }
     if (!g->blocks) return fail(STC_EINVAL, "blocks is NULL");
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
@@ -351,6 +404,13 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     h->off = (long long *)(h->base + lay.off);
     h->sizes_d = (int *)(h->base + lay.sizes);
     h->st = (DevState *)(h->base + lay.state);
+    h->sparse = lay.sparse;
+    if (lay.sparse) {
+        h->ell_tab = (EllEntry *)(h->base + lay.ell_tab);
+        h->ell_v64 = (double *)(h->base + lay.ell_v64);
+        h->ell_v32 = lay.fp32 ? (float *)(h->base + lay.ell_v32) : nullptr;
+        h->ell_idx = (unsigned char *)(h->base + lay.ell_idx);
+    }
 
     std::vector<long long> off(L + 1, 0);
     for (int i = 0; i < L; ++i) off[i + 1] = off[i] + sizes[i];
@@ -431,6 +491,61 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         if ((rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK) return cleanup(rc);
     }
     stc_status rc;
+    if (lay.sparse) {
+        // column-major ELL of every off-diagonal block, levels in order
+        h->ell_K.assign((size_t)L * NB, 0);
+        std::vector<EllEntry> tab((size_t)L * NB);
+        long long at = 0;
+        for (int i = 0; i < L; ++i)
+            for (int d = -b; d <= b; ++d) {
+                const int K = ell_K(g, i, d);
+                h->ell_K[(size_t)i * NB + d + b] = K;
+                tab[(size_t)i * NB + d + b] = EllEntry{at, K, 0};
+                at += (long long)K * MP;
+            }
+        if ((rc = dev(hipMemcpyAsync(h->ell_tab, tab.data(), tab.size() * sizeof(EllEntry),
+                                     hipMemcpyHostToDevice, h->stream), "copy ELL table")) != STC_OK)
+            return cleanup(rc);
+        std::vector<double> val;
+        std::vector<unsigned char> idx;
+        for (int l0 = 0; l0 < L; l0 += chunk) {
+            const int l1 = std::min(L, l0 + chunk);
+            const long long s0 = tab[(size_t)l0 * NB].off;
+            const long long s1 = (l1 < L) ? tab[(size_t)l1 * NB].off : at;
+            val.assign((size_t)(s1 - s0), 0.0);
+            idx.assign((size_t)(s1 - s0), 0);
+            for (int i = l0; i < l1; ++i)
+                for (int d = -b; d <= b; ++d) {
+                    const EllEntry e = tab[(size_t)i * NB + d + b];
+                    if (e.K == 0) continue;
+                    const int k = i + d;
+                    const double *Q = q_at(k, -d + b);    // Q_{k,i}: rows level k, cols level i
+                    for (int j = 0; j < sizes[i]; ++j) {
+                        int cnt = 0;
+                        for (int r = 0; r < sizes[k]; ++r) {
+                            const double v = Q[(size_t)r * m + j];
+                            if (v == 0.0) continue;
+                            const size_t o = (size_t)(e.off - s0) +
+                                             ((size_t)(cnt >> 2) * MP + j) * 4 + (cnt & 3);
+                            val[o] = v;
+                            idx[o] = (unsigned char)r;
+                            ++cnt;
+                        }
+                    }
+                }
+            if (s1 > s0) {
+                if ((rc = dev(hipMemcpyAsync(h->ell_v64 + s0, val.data(), sizeof(double) * (s1 - s0),
+                                             hipMemcpyHostToDevice, h->stream), "copy ELL values")) != STC_OK ||
+                    (rc = dev(hipMemcpyAsync(h->ell_idx + s0, idx.data(), (size_t)(s1 - s0),
+                                             hipMemcpyHostToDevice, h->stream), "copy ELL rows")) != STC_OK ||
+                    (rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK)
+                    return cleanup(rc);
+            }
+        }
+        if (lay.fp32 && at > 0 &&
+            (rc = dev(launch_cast_blocks(h->ell_v64, h->ell_v32, (size_t)at, h->stream), "cast ELL")) != STC_OK)
+            return cleanup(rc);
+    }
     if ((rc = dev(hipMemcpyAsync(h->off, off.data(), sizeof(long long) * (L + 1),
                                  hipMemcpyHostToDevice, h->stream), "copy offsets")) != STC_OK)
         return cleanup(rc);
@@ -549,9 +664,10 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
         // time every variant from the uniform start in this stage's precision
         double best = 1e300;
         int best_v = h->variant[stage];
-        for (int v = 0; v < nv && rc == STC_OK; ++v) {
+        const int nvs = h->sparse ? 1 : nv;   // the sparse kernel has no variants
+        for (int v = 0; v < nvs && rc == STC_OK; ++v) {
             if ((rc = load_vector_stage(h, nullptr, STC_MEM_HOST, f32)) != STC_OK) break;
-            h->variant[stage] = v;
+            if (!h->sparse) h->variant[stage] = v;
             hipError_t e = hipSuccess;
             for (long long j = 1; j <= 3 && e == hipSuccess; ++j) e = enqueue_sweep(h, j, 0.0, nullptr);
             if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
@@ -595,8 +711,12 @@ stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {
             for (int d = -h->b; d <= h->b; ++d) {
                 const int k = i + d;
                 if (k < 0 || k >= h->L) continue;
-                // stored block: rows of level k (or i for the inverse) x columns of level i
-                blocks += (double)h->sizes[k] * h->sizes[i];
+                // stored block: rows of level k (or i for the inverse) x columns of level i;
+                // sparse storage: K slots x MP columns of value + 1-byte row index
+                if (h->sparse && d != 0)
+                    blocks += (double)h->ell_K[(size_t)i * h->NB + d + h->b] * h->MP * (1.0 + 1.0 / sb);
+                else
+                    blocks += (double)h->sizes[k] * h->sizes[i];
                 if (d != 0 && !seen[k]) {
                     seen[k] = 1;
                     vin += h->sizes[k];
@@ -913,6 +1033,7 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
         stc_handle *h = hs[c];
         if (!h) return fail(STC_EINVAL, "handle %d is NULL", c);
         if (h->b != bt->b) return fail(STC_EINVAL, "handle %d has bandwidth %d, batch %d", c, h->b, bt->b);
+        if (h->sparse) return fail(STC_EINVAL, "handle %d stores sparse blocks; batches take dense chains", c);
         const int g = h->stage32 ? 1 : 0;
         const int bytes = g == 1 ? 4 : 8;
         const int lpw = batch_lpw(bytes, h->MP);

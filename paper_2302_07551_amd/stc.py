@@ -24,6 +24,7 @@ STC_OK, STC_EINVAL, STC_ENOTGEN, STC_ESINGULAR, STC_EDEGENERATE, STC_EMAXIT, STC
 STC_FP64, STC_FP32, STC_MIXED = 0, 1, 2
 STC_STOP_DIFF, STC_STOP_RESIDUAL = 0, 1
 STC_MEM_HOST, STC_MEM_DEVICE = 0, 1
+STC_DENSE, STC_SPARSE = 0, 1
 
 PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
 STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
@@ -46,7 +47,7 @@ class stc_generator(ctypes.Structure):
 class stc_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("stair_type", c_int32), ("stop", c_int32),
                 ("check_every", c_int32), ("switch_tol", c_double), ("stream", c_void_p),
-                ("arena", c_void_p), ("arena_bytes", c_size_t)]
+                ("arena", c_void_p), ("arena_bytes", c_size_t), ("format", c_int32)]
 
 
 class stc_result(ctypes.Structure):
@@ -144,12 +145,15 @@ def make_generator(blocks: np.ndarray, sizes, b: int, recompute_diagonal: bool =
     return g, (blocks, sz)
 
 
+FORMATS = {"dense": STC_DENSE, "sparse": STC_SPARSE}
+
+
 def make_options(precision="fp64", stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
-                 stream=0, arena=0, arena_bytes=0):
+                 stream=0, arena=0, arena_bytes=0, format="dense"):
     return stc_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                        int(stair_type), STOPS[stop] if isinstance(stop, str) else int(stop),
                        int(check_every), float(switch_tol), stream or None, arena or None,
-                       int(arena_bytes))
+                       int(arena_bytes), FORMATS[format] if isinstance(format, str) else int(format))
 
 
 def stc_footprint_bytes(gen: stc_generator, opt: stc_options) -> int:
@@ -347,7 +351,7 @@ class Solver:
 
     def __init__(self, blocks: np.ndarray, sizes, b: int, *, precision="fp64", stair_type=1,
                  stop="diff", check_every=1, switch_tol=0.0, recompute_diagonal=False,
-                 device=None, stream=None, poison=False):
+                 device=None, stream=None, poison=False, format="dense"):
         """poison: fill the arena with 0xFF bytes (a NaN in FP32 and FP64)
         before setup, so that any read of memory the library did not write
         first shows up as NaN in the results (a test aid)."""
@@ -359,7 +363,7 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
         self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
-                                stream=self.stream.cuda_stream)
+                                stream=self.stream.cuda_stream, format=format)
         need = stc_footprint_bytes(self.gen, self.opt)
         if need == 0:
             raise StcError(STC_EINVAL, "unsupported generator shape or options")

@@ -105,3 +105,15 @@ def test_package_public_names_import():
     for name in stc.EXPORTS:
         assert callable(getattr(stc, name, None)) or name in ("stc_status_string",
                                                               "stc_last_error"), name
+
+
+def test_sparse_footprint_is_smaller(lib):
+    g = synth.banded(12, 64, 5, b=2, density=0.1)
+    gen, keep = stc.make_generator(g.blocks, g.sizes, g.b)
+    dense = stc.stc_footprint_bytes(gen, stc.make_options(format="dense"))
+    sparse = stc.stc_footprint_bytes(gen, stc.make_options(format="sparse"))
+    assert 0 < dense < sparse    # sparse keeps the dense copies for the residual, plus ELL
+    nb, MP = 5, 64
+    ell_upper = 12 * 4 * MP * MP * 9
+    assert sparse - dense <= ell_upper
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format=7)) == 0

@@ -138,6 +138,59 @@ def test_poisoned_arena(name, make, precision):
             s.close()
 
 
+SPARSE = [
+    ("band_L16_m128", lambda: synth.banded(16, 128, 21, b=2)),
+    ("band_L9_m32_ragged", lambda: synth.banded(9, 32, 22, b=2, density=0.2, last=19)),
+    ("band_L12_m8", lambda: synth.banded(12, 8, 23, b=2, density=0.4)),
+    ("qbd_L15_m64", lambda: synth.qbd(15, 64, 24, last=50)),
+    ("qbd_L8_m16", lambda: synth.qbd(8, 16, 25)),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("stair_type", [1, 2])
+@pytest.mark.parametrize("name,make", SPARSE, ids=[s[0] for s in SPARSE])
+def test_sparse_format_step_matches_oracle(name, make, stair_type, precision):
+    g = make()
+    x = synth.positive_start(g, 31)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x,
+                                       stair_type)
+    s = _solver(g, precision=precision, stair_type=stair_type, format="sparse", poison=True)
+    z, d = s.step(x)
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    assert np.all(np.isfinite(z))
+    assert np.abs(z - zr).sum() <= tol and abs(d - dr) <= tol
+    s.close()
+
+
+def test_sparse_format_converged_and_fewer_bytes():
+    from paper_2302_07551_amd import stc
+    g, pstar = synth.planted_reversible(20, 32, 57, b=2, density=0.15)
+    dense = _solver(g)
+    sparse = _solver(g, format="sparse")
+    pi_d, info_d = dense.solve(tol=1e-15, maxit=100000, allow_maxit=False)
+    pi_s, info_s = sparse.solve(tol=1e-15, maxit=100000, allow_maxit=False)
+    assert np.abs(pi_s - pstar).sum() <= 1e-10
+    assert abs(info_s["iters"] - info_d["iters"]) <= 1
+    a_d, b_d = stc.stc_phase_bytes(dense.h)
+    a_s, b_s = stc.stc_phase_bytes(sparse.h)
+    assert a_s + b_s < a_d + b_d
+    dense.close()
+    sparse.close()
+
+
+def test_batch_rejects_sparse_chains():
+    from paper_2302_07551_amd import Batch, stc
+    g = synth.banded(8, 16, 58, b=2)
+    s = _solver(g, format="sparse")
+    b = Batch(4, 256, b=2)
+    with pytest.raises(stc.StcError) as e:
+        b.set([s], tol=0.0)
+    assert e.value.status == stc.STC_EINVAL
+    b.close()
+    s.close()
+
+
 def test_repeated_steps_track_oracle():
     g = synth.qbd(24, 16, 31, last=9)
     s = _solver(g)
