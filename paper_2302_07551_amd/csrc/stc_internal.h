@@ -11,7 +11,8 @@ namespace stc {
 // Device-side solver state of one chain (lives in the arena).
 // Ring slots are indexed by the sweep number s modulo kRing:
 //   inv_sigma[s] = 1 / e^T W_s   (W_s: unnormalised output of sweep s,
-//                                 W_0 = the loaded start vector)
+//                                 W_0 = the loaded start vector; slot -1
+//                                 holds 1 / e^T W_0 too, the scale of sweep 1)
 //   diff[s]      = ||x^(s) - x^(s-1)||_1 with x^(s) = W_s * inv_sigma[s]
 constexpr int kRing = 4096;
 constexpr int kRingMask = kRing - 1;
@@ -35,7 +36,8 @@ enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2 };
 struct SweepLaunch {
     const void *blk;      // T [L][2b+1][MP][MP] gather-oriented blocks
     const void *w_old;    // T [L][MP]  W_{s-1}
-    const void *w_older;  // T [L][MP]  W_{s-2}  (change of sweep s-1)
+    const void *w_d1;     // T [L][MP]  W_{s-2}  (change of sweep s-2)
+    const void *w_d2;     // T [L][MP]  W_{s-3}
     void *w_new;          // T [L][MP]  W_s
     double *part_sum;     // per-workgroup partial e^T W_s
     double *part_diff;    // per-workgroup partial change
@@ -45,6 +47,13 @@ struct SweepLaunch {
     int slot0;            // first partial slot used by this launch
     int nslots;           // total slots of both phases
     long long s;          // sweep being produced (>= 1)
+    // Phase B only: one extra workgroup reduces the partials of sweep s-1 and
+    // records them (instead of a finalize launch between the sweeps).
+    int fold;
+    int prev_nslots;
+    const double *prev_sum;
+    const double *prev_diff;
+    double tol;           // device change test applied when recording
 };
 
 // One sparse off-diagonal block (column-major ELL in slot quads): K slots per
@@ -61,7 +70,7 @@ struct EllEntry {
 // stage; its sweep number is DevState::last_sweep + 1.
 struct ChainDesc {
     const void *blk;
-    void *w[3];           // rotation: W_s lives in w[s % 3]
+    void *w[4];           // rotation: W_s lives in w[s % 4]
     double *part_sum;
     double *part_diff;
     DevState *st;
@@ -75,6 +84,11 @@ struct WorkItem {
     int chain;
     int group;
 };
+
+// Largest number of per-group partial slots of a sweep that the extra
+// workgroup of phase B reduces; above it a finalize launch follows every
+// sweep (the reduction would outlast the streaming workgroups).
+constexpr int kFoldSlots = 8192;
 
 // Host-visible launchers (stc_kernels.hip).  Each returns a hipError_t.
 int supported_mp(int m);   // padded block size for m, or 0
@@ -99,8 +113,9 @@ hipError_t launch_store(int precision_bytes, int MP, const void *w, const long l
 hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
                            const double *diag64, const void *w, int L, DevState *st,
                            long long slot, double *part, hipStream_t stream);
-hipError_t launch_diff(int precision_bytes, int MP, const void *w, const void *w_prev,
-                       int L, DevState *st, long long s, double *part, hipStream_t stream);
+hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
+                       const void *w_prev, int L, int parity_a, DevState *st, long long k,
+                       double *part, hipStream_t stream, double tol);
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t stream);
 hipError_t launch_reset_state(DevState *st, hipStream_t stream);
 hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);

@@ -21,14 +21,18 @@
 //                          load is a contiguous 16-byte piece of one row.
 //   W   [L][MP]            iterates, zero padded.
 //
-// Normalisation is lazy: the sweep producing W_s reads W_{s-1} scaled by
-// 1/e^T W_{s-1} (a device scalar) and writes fixed-order per-workgroup
-// partial sums of its output and of the change of the previous sweep,
-// ||x^(s-1) - x^(s-2)||_1.  A one-workgroup finalize kernel then forms
-// e^T W_s and that change in a fixed order (the result does not depend on
-// scheduling) and applies the device-side stopping test.  No workgroup waits
-// on another and no kernel needs a device-wide fence: the kernel boundaries
-// order the three launches of a sweep.
+// Normalisation is lazy and lagged.  The sweep producing W_s reads W_{s-1}
+// scaled by kappa_s = 1 / e^T W_{s-2}: the sweep map is linear, so
+// x^(s) = W_s / e^T W_s is exactly the normalised iterate of Algorithm 2,
+// while e^T W_s = g_s e^T W_{s-1} / e^T W_{s-2} stays bounded (g_s -> 1 at
+// the fixed point).  Each launch writes fixed-order per-workgroup partial
+// sums of its output and of the change ||x^(s-2) - x^(s-3)||_1; the partials
+// of sweep s-1 are reduced by one extra workgroup of the phase-B launch of
+// sweep s (or by a one-workgroup finalize launch), which records e^T W_{s-1}
+// and applies the device stopping test.  Nothing on the path of a sweep waits
+// for a reduction, no workgroup waits on another, and no kernel needs a
+// device-wide fence.  The change being measured two sweeps late, the iterates
+// rotate through four buffers.
 #include <math.h>
 
 #include "stc_internal.h"
@@ -120,17 +124,52 @@ __device__ inline double block_max(double v, double *sh) {
 template <typename T>
 struct ChainView {
     const T *blk;
-    const T *w_old, *w_older;
-    T *w_new;
+    const T *w_old;          // W_{s-1}
+    const T *w_d1, *w_d2;    // W_{s-2}, W_{s-3}: the change of sweep s-2
+    T *w_new;                // W_s
     double *part_sum, *part_diff;
     const DevState *st;
     int L, parity, slot0;
     long long s;
 };
 
+// Fixed-order sums of per-group partials (same value in every workgroup).
+__device__ inline void partial_sums(const double *ps, const double *pd, int n, bool want_d,
+                                    double *sh, double &S, double &D) {
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = threadIdx.x; j < n; j += kWG) {
+        s1 += ps[j];
+        if (want_d) s2 += pd[j];
+    }
+    S = block_sum(s1, sh);
+    D = want_d ? block_sum(s2, sh) : 0.0;
+}
+
+// Record sweep s in the state: 1 / e^T W_s and the change of sweep s - 2
+// (measured during sweep s), then the device stopping test.  Thread 0 only;
+// nothing after a stop.
+__device__ inline void record_sweep(DevState *st, long long s, double S, double D, double tol) {
+    if (st->stop_flag) return;
+    st->last_sweep = s;
+    if (!(S > 0.0) || !isfinite(S)) {
+        st->status = kDevDegenerate;
+        st->stop_flag = 1;
+        st->stop_sweep = s - 1;
+        return;
+    }
+    st->inv_sigma[s & kRingMask] = 1.0 / S;
+    if (s >= 3) {
+        st->diff[(s - 2) & kRingMask] = D;
+        if (tol > 0.0 && D <= tol) {
+            st->stop_flag = 1;
+            st->stop_sweep = s - 2;
+        }
+    }
+}
+
 template <typename T, int MP, int B, bool PHB, int RG, bool NT>
-__device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *red_base,
-                                   T *rv_base, double *sh) {
+__device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, double inv_old,
+                                   T *red_base, T *rv_base, double *sh) {
     using TL = Tile<T, MP, RG>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
@@ -150,7 +189,6 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *r
     const T *w_old = a.w_old;
     T *w_new = a.w_new;
     const T *base = a.blk + (size_t)ic * NB * BS;
-    const double inv_old = st->inv_sigma[(a.s - 1) & kRingMask];
     const T sc = (T)inv_old;
 
     // r_i: gather of the off-diagonal blocks of block row i of A.  The loop
@@ -215,10 +253,12 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *r
         for (int gg = 0; gg < R; ++gg) z += red[gg * MP + tt];
         w_new[(size_t)i * MP + tt] = z;
         zs = (double)z;
-        if (a.s >= 2) {
-            const double inv_older = st->inv_sigma[(a.s - 2) & kRingMask];
-            dd = fabs((double)w_old[(size_t)i * MP + tt] * inv_old -
-                      (double)a.w_older[(size_t)i * MP + tt] * inv_older);
+        if (a.s >= 3) {
+            // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
+            const double i2 = st->inv_sigma[(a.s - 2) & kRingMask];
+            const double i3 = st->inv_sigma[(a.s - 3) & kRingMask];
+            dd = fabs((double)a.w_d1[(size_t)i * MP + tt] * i2 -
+                      (double)a.w_d2[(size_t)i * MP + tt] * i3);
         }
     }
     const double S = block_sum(zs, sh);
@@ -230,16 +270,21 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, T *r
     __syncthreads();   // the LDS may be reused by the next group
 }
 
-template <typename T, int MP, int B, bool PHB, int RG, bool NT>
-__global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
-    using TL = Tile<T, MP, RG>;
-    __shared__ T red[TL::LPW * TL::R * MP];
-    __shared__ T rv[TL::LPW * MP];
-    __shared__ double sh[kWG / 64];
+// The extra workgroup of a phase-B launch: reduce sweep s-1's partials and
+// record them (it runs beside the streaming workgroups, off their path).
+__device__ inline void fold_previous(const SweepLaunch &a, double *sh) {
+    double S, D;
+    partial_sums(a.prev_sum, a.prev_diff, a.prev_nslots, true, sh, S, D);
+    if (threadIdx.x == 0) record_sweep(a.st, a.s - 1, S, D, a.tol);
+}
+
+template <typename T>
+__device__ inline ChainView<T> view_of(const SweepLaunch &a) {
     ChainView<T> v;
     v.blk = (const T *)a.blk;
     v.w_old = (const T *)a.w_old;
-    v.w_older = (const T *)a.w_older;
+    v.w_d1 = (const T *)a.w_d1;
+    v.w_d2 = (const T *)a.w_d2;
     v.w_new = (T *)a.w_new;
     v.part_sum = a.part_sum;
     v.part_diff = a.part_diff;
@@ -248,9 +293,23 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     v.parity = a.parity;
     v.slot0 = a.slot0;
     v.s = a.s;
+    return v;
+}
+
+template <typename T, int MP, int B, bool PHB, int RG, bool NT>
+__global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
+    using TL = Tile<T, MP, RG>;
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
+    __shared__ double sh[kWG / 64];
+    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
+        fold_previous(a, sh);
+        return;
+    }
     // a sweep queued after the device stopping test fired changes nothing
     const bool live = a.st->stop_flag == 0;
-    sweep_group<T, MP, B, PHB, RG, NT>(v, blockIdx.x, live, red, rv, sh);
+    const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
+    sweep_group<T, MP, B, PHB, RG, NT>(view_of<T>(a), blockIdx.x, live, kappa, red, rv, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,8 +326,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
 template <typename T, int MP, int B, bool PHB>
 __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *tab,
                                        const T *ell_val, const unsigned char *ell_idx, int q,
-                                       bool live, T *red_base, T *rv_base, T *src_base,
-                                       double *sh) {
+                                       bool live, double inv_old, T *red_base, T *rv_base,
+                                       T *src_base, double *sh) {
     using TL = Tile<T, MP, 8>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
@@ -290,7 +349,6 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     const int ic = active ? i : a.parity;
     const T *w_old = a.w_old;
     T *w_new = a.w_new;
-    const double inv_old = st->inv_sigma[(a.s - 1) & kRingMask];
     const T sc = (T)inv_old;
     const T *wb = a.blk + ((size_t)ic * NB + B) * BS + c * VEC;
 
@@ -368,10 +426,11 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
         for (int x = 0; x < R; ++x) z += red[x * MP + tt];
         w_new[(size_t)i * MP + tt] = z;
         zs = (double)z;
-        if (a.s >= 2) {
-            const double inv_older = st->inv_sigma[(a.s - 2) & kRingMask];
-            dd = fabs((double)w_old[(size_t)i * MP + tt] * inv_old -
-                      (double)a.w_older[(size_t)i * MP + tt] * inv_older);
+        if (a.s >= 3) {
+            const double i2 = st->inv_sigma[(a.s - 2) & kRingMask];
+            const double i3 = st->inv_sigma[(a.s - 3) & kRingMask];
+            dd = fabs((double)a.w_d1[(size_t)i * MP + tt] * i2 -
+                      (double)a.w_d2[(size_t)i * MP + tt] * i3);
         }
     }
     const double S = block_sum(zs, sh);
@@ -391,21 +450,14 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
     __shared__ T rv[TL::LPW * MP];
     __shared__ T src[TL::LPW * 2 * B * MP];
     __shared__ double sh[kWG / 64];
-    ChainView<T> v;
-    v.blk = (const T *)a.blk;
-    v.w_old = (const T *)a.w_old;
-    v.w_older = (const T *)a.w_older;
-    v.w_new = (T *)a.w_new;
-    v.part_sum = a.part_sum;
-    v.part_diff = a.part_diff;
-    v.st = a.st;
-    v.L = a.L;
-    v.parity = a.parity;
-    v.slot0 = a.slot0;
-    v.s = a.s;
+    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
+        fold_previous(a, sh);
+        return;
+    }
     const bool live = a.st->stop_flag == 0;
-    sweep_group_ell<T, MP, B, PHB>(v, tab, (const T *)ell_val, ell_idx, blockIdx.x, live, red,
-                                   rv, src, sh);
+    const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
+    sweep_group_ell<T, MP, B, PHB>(view_of<T>(a), tab, (const T *)ell_val, ell_idx, blockIdx.x,
+                                   live, kappa, red, rv, src, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,9 +482,10 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
         const bool live = st->stop_flag == 0;
         ChainView<T> v;
         v.blk = (const T *)d.blk;
-        v.w_old = (const T *)d.w[(s - 1) % 3];
-        v.w_older = (const T *)d.w[(s + 1) % 3];   // (s - 2) mod 3
-        v.w_new = (T *)d.w[s % 3];
+        v.w_old = (const T *)d.w[(s + 3) & 3];   // W_{s-1}
+        v.w_d1 = (const T *)d.w[(s + 2) & 3];    // W_{s-2}
+        v.w_d2 = (const T *)d.w[(s + 1) & 3];    // W_{s-3}
+        v.w_new = (T *)d.w[s & 3];
         v.part_sum = d.part_sum;
         v.part_diff = d.part_diff;
         v.st = st;
@@ -440,12 +493,13 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
         v.parity = PHB ? 1 - d.parity_a : d.parity_a;
         v.slot0 = PHB ? d.groups_a : 0;
         v.s = s;
+        const double inv_old = st->inv_sigma[(s - 2) & kRingMask];   // kappa_s
         switch (d.MP) {
-            case 8: sweep_group<T, 8, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
-            case 16: sweep_group<T, 16, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
-            case 32: sweep_group<T, 32, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
-            case 64: sweep_group<T, 64, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
-            case 128: sweep_group<T, 128, B, PHB, 8, NT>(v, w.group, live, red, rv, sh); break;
+            case 8: sweep_group<T, 8, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
+            case 16: sweep_group<T, 16, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
+            case 32: sweep_group<T, 32, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
+            case 64: sweep_group<T, 64, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
+            case 128: sweep_group<T, 128, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
         }
     }
 }
@@ -455,33 +509,9 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
 __device__ inline void finalize_chain(const double *part_sum, const double *part_diff,
                                       int nslots, DevState *st, long long s, double tol,
                                       double *sh) {
-    // the flag is read alongside the partials (not before them); after a stop
-    // the partials are stale and nothing is written
-    const int stopped = st->stop_flag;
-    double s1 = 0.0, s2 = 0.0;
-    for (int j = threadIdx.x; j < nslots; j += kWG) {
-        s1 += part_sum[j];
-        s2 += part_diff[j];
-    }
-    s1 = block_sum(s1, sh);
-    s2 = block_sum(s2, sh);
-    if (threadIdx.x == 0 && !stopped) {
-        st->last_sweep = s;
-        if (!(s1 > 0.0) || !isfinite(s1)) {
-            st->status = kDevDegenerate;
-            st->stop_flag = 1;
-            st->stop_sweep = s - 1;
-        } else {
-            st->inv_sigma[s & kRingMask] = 1.0 / s1;
-        }
-        if (s >= 2) {
-            st->diff[(s - 1) & kRingMask] = s2;
-            if (tol > 0.0 && s2 <= tol && !st->stop_flag) {
-                st->stop_flag = 1;
-                st->stop_sweep = s - 1;
-            }
-        }
-    }
+    double S, D;
+    partial_sums(part_sum, part_diff, nslots, true, sh, S, D);
+    if (threadIdx.x == 0) record_sweep(st, s, S, D, tol);
 }
 
 __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
@@ -516,7 +546,7 @@ __global__ void k_rearm(DevState *st, long long k) {
 enum ReduceMode { kReduceResidual = 0, kReduceDiff = 1, kReduceLoad = 2 };
 
 __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int mode,
-                                                 DevState *st, long long slot) {
+                                                 DevState *st, long long slot, double tol) {
     __shared__ double sh[kWG / 64];
     const int stride = (mode == kReduceLoad) ? 2 : 1;
     double t = 0.0, b = 0.0;
@@ -530,7 +560,13 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int m
     if (mode == kReduceResidual) {
         st->residual = t;
     } else if (mode == kReduceDiff) {
+        // the change of sweep slot, with the device stopping test
+        if (st->stop_flag) return;
         st->diff[slot & kRingMask] = t;
+        if (tol > 0.0 && t <= tol) {
+            st->stop_flag = 1;
+            st->stop_sweep = slot;
+        }
     } else {
         st->x_sum = t;
         // slot < 0: a raw vector for the residual, no start-vector checks
@@ -540,6 +576,8 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int m
                 st->inv_sigma[slot & kRingMask] = 0.0;
             } else {
                 st->inv_sigma[slot & kRingMask] = 1.0 / t;
+                // the first sweep's input scale kappa_1 = 1 / e^T W_0 as well
+                if (slot == 0) st->inv_sigma[kRingMask] = 1.0 / t;
             }
         }
     }
@@ -600,19 +638,31 @@ __global__ __launch_bounds__(kWG) void k_residual(const double *blk, const doubl
 }
 
 // ---------------------------------------------------------------------------
-// change ||x^(s) - x^(s-1)||_1 of one sweep (used when the run ends at maxit)
+// change ||x^(k) - x^(k-1)||_1 of one sweep, per workgroup of the sweep
+// kernels' geometry (same levels per group, same slots, same fixed-order
+// sums), so it is bitwise the value the partials of sweep k+2 carry.  Used
+// at the end of a burst for the last two sweeps.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, size_t n,
-                                               const DevState *st, long long s, double *part) {
+template <typename T, int MP, int RG>
+__global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, const DevState *st,
+                                               long long k, int L, int parity_a, int groups_a,
+                                               double *part) {
+    using TL = Tile<T, MP, RG>;
     __shared__ double sh[kWG / 64];
-    const double inv = st->inv_sigma[s & kRingMask];
-    const double invp = st->inv_sigma[(s - 1) & kRingMask];
-    double d = 0.0;
-    for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG)
-        d += fabs((double)w[j] * inv - (double)wp[j] * invp);
-    d = block_sum(d, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = d;
+    const int tid = threadIdx.x;
+    const int team = tid / TL::TS, tt = tid - team * TL::TS;
+    const bool in_a = (int)blockIdx.x < groups_a;
+    const int q = in_a ? blockIdx.x : blockIdx.x - groups_a;
+    const int parity = in_a ? parity_a : 1 - parity_a;
+    const int i = parity + 2 * (q * TL::LPW + team);
+    double dd = 0.0;
+    if (i < L && tt < MP) {
+        const double i2 = st->inv_sigma[k & kRingMask];
+        const double i3 = st->inv_sigma[(k - 1) & kRingMask];
+        dd = fabs((double)w[(size_t)i * MP + tt] * i2 - (double)wp[(size_t)i * MP + tt] * i3);
+    }
+    const double D = block_sum(dd, sh);
+    if (tid == 0) part[blockIdx.x] = D;
 }
 
 // ---------------------------------------------------------------------------
@@ -911,7 +961,8 @@ int reduce_groups(int MP, int L) {
 
 template <typename T, int MP, int B, int RG, bool NT>
 static hipError_t sweep_v(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s) {
-    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, variant);
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, variant) +
+                       ((phase_b && a.fold) ? 1 : 0);   // + the reduction workgroup
     if (groups <= 0) return hipSuccess;
     if (phase_b)
         hipLaunchKernelGGL((k_sweep<T, MP, B, true, RG, NT>), dim3(groups), dim3(kWG), 0, s, a);
@@ -957,7 +1008,8 @@ hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, 
 template <typename T, int MP, int B>
 static hipError_t ell_mpb(bool phase_b, const SweepLaunch &a, const EllEntry *tab,
                           const void *val, const unsigned char *idx, hipStream_t s) {
-    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, 0);
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, 0) +
+                       ((phase_b && a.fold) ? 1 : 0);
     if (groups <= 0) return hipSuccess;
     if (phase_b)
         hipLaunchKernelGGL((k_sweep_ell<T, MP, B, true>), dim3(groups), dim3(kWG), 0, s, a, tab,
@@ -1091,8 +1143,8 @@ hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff
 }
 
 static hipError_t reduce(const double *part, int n, int mode, DevState *st, long long slot,
-                         hipStream_t stream) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, stream, part, n, mode, st, slot);
+                         hipStream_t stream, double tol = 0.0) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, stream, part, n, mode, st, slot, tol);
     return hipGetLastError();
 }
 
@@ -1129,20 +1181,44 @@ hipError_t launch_store(int precision_bytes, int MP, const void *w, const long l
     return hipGetLastError();
 }
 
-hipError_t launch_diff(int precision_bytes, int MP, const void *w, const void *w_prev, int L,
-                       DevState *st, long long s, double *part, hipStream_t stream) {
-    const size_t n = (size_t)L * MP;
-    int groups = elementwise_groups(n);
-    if (groups > kAuxGroups) groups = kAuxGroups;
-    if (precision_bytes == 8)
-        hipLaunchKernelGGL(k_diff<double>, dim3(groups), dim3(kWG), 0, stream,
-                           (const double *)w, (const double *)w_prev, n, st, s, part);
+template <typename T, int MP>
+static hipError_t diff_mp(int rg, const void *w, const void *wp, int L, int pA, int gA, int gB,
+                          const DevState *st, long long k, double *part, hipStream_t s) {
+    if (rg == 4)
+        hipLaunchKernelGGL((k_diff<T, MP, 4>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                           (const T *)wp, st, k, L, pA, gA, part);
     else
-        hipLaunchKernelGGL(k_diff<float>, dim3(groups), dim3(kWG), 0, stream, (const float *)w,
-                           (const float *)w_prev, n, st, s, part);
-    hipError_t e = hipGetLastError();
+        hipLaunchKernelGGL((k_diff<T, MP, 8>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                           (const T *)wp, st, k, L, pA, gA, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
+                       const void *w_prev, int L, int parity_a, DevState *st, long long k,
+                       double *part, hipStream_t stream, double tol) {
+    const int gA = phase_groups(precision_bytes, MP, L, parity_a, variant);
+    const int gB = phase_groups(precision_bytes, MP, L, 1 - parity_a, variant);
+    const int rg = variant_rg(variant);
+    hipError_t e = hipErrorInvalidValue;
+    if (precision_bytes == 8) {
+        switch (MP) {
+            case 8: e = diff_mp<double, 8>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 16: e = diff_mp<double, 16>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 32: e = diff_mp<double, 32>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 64: e = diff_mp<double, 64>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 128: e = diff_mp<double, 128>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+        }
+    } else {
+        switch (MP) {
+            case 8: e = diff_mp<float, 8>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 16: e = diff_mp<float, 16>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 32: e = diff_mp<float, 32>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 64: e = diff_mp<float, 64>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 128: e = diff_mp<float, 128>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+        }
+    }
     if (e != hipSuccess) return e;
-    return reduce(part, groups, kReduceDiff, st, s, stream);
+    return reduce(part, gA + gB, kReduceDiff, st, k, stream, tol);
 }
 
 template <typename T, int B>

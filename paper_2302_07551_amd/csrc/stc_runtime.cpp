@@ -98,13 +98,13 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.blk64 = take(L * l.NB * bs * 8);
     l.diag64 = take(L * bs * 8);
     if (l.fp32) l.blk32 = take(L * l.NB * bs * 4);
-    l.w64 = take(3 * vec * 8);
-    if (l.fp32) l.w32 = take(3 * vec * 4);
+    l.w64 = take(4 * vec * 8);              // four iterates in rotation
+    if (l.fp32) l.w32 = take(4 * vec * 4);
     l.wres = take(vec * 8);
     l.io = take(vec * 8);
     l.nparts = L + 8;
-    l.part_sum = take(l.nparts * 8);
-    l.part_diff = take(l.nparts * 8);
+    l.part_sum = take(2 * l.nparts * 8);    // two sweeps: parity of s
+    l.part_diff = take(2 * l.nparts * 8);
     l.naux = std::max<size_t>(2 * 1024 + 8, L + 8);
     l.part_aux = take(l.naux * 8);
     if (l.sparse) {
@@ -157,33 +157,54 @@ namespace {
 
 void *wbuf(stc_handle *h, bool fp32, long long s) {
     const size_t vec = (size_t)h->L * h->MP;
-    const int k = (int)(((s % 3) + 3) % 3);
+    const int k = (int)(((s % 4) + 4) % 4);
     if (fp32) return h->w32 + k * vec;
     return h->w64 + k * vec;
 }
 
-// Enqueue sweep s (phase A, phase B, finalize).  With ev != nullptr an event
-// is recorded after each of the three launches (ev[0..2]).
-hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev) {
+int sweep_slots(stc_handle *h) {
+    const bool f32 = h->stage32;
+    const int vv = h->sparse ? 0 : h->variant[f32 ? 1 : 0];
+    const int bytes = f32 ? 4 : 8;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    return phase_groups(bytes, h->MP, h->L, pA, vv) + phase_groups(bytes, h->MP, h->L, 1 - pA, vv);
+}
+
+bool folds(stc_handle *h) { return sweep_slots(h) <= kFoldSlots; }
+
+// Enqueue sweep s: phase A, phase B and, for chains with more partial slots
+// than the reduction workgroup of phase B takes, a finalize launch.  first:
+// the first sweep of a burst (the previous sweep was recorded by a flush, a
+// load or a batch, so phase B does not reduce it again).  With ev != nullptr
+// an event is recorded after phase A (ev[0]), after phase B (ev[1]) and after
+// a finalize launch (ev[2], only when one is enqueued).
+hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev, bool first) {
     const bool f32 = h->stage32;
     const int v = h->variant[f32 ? 1 : 0];
     SweepLaunch a;
     a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
     a.w_old = wbuf(h, f32, s - 1);
-    a.w_older = wbuf(h, f32, s - 2);
+    a.w_d1 = wbuf(h, f32, s - 2);
+    a.w_d2 = wbuf(h, f32, s - 3);
     a.w_new = wbuf(h, f32, s);
-    a.part_sum = h->part_sum;
-    a.part_diff = h->part_diff;
+    a.part_sum = h->part_sum + (s & 1) * h->lay.nparts;
+    a.part_diff = h->part_diff + (s & 1) * h->lay.nparts;
     a.st = h->st;
     a.L = h->L;
     a.s = s;
+    a.tol = tol;
     const int pA = (h->stair_type == 1) ? 0 : 1;
     const int pB = 1 - pA;
     const int bytes = f32 ? 4 : 8;
     const int vv = h->sparse ? 0 : v;   // the sparse kernel has variant 0's geometry
     const int gA = phase_groups(bytes, h->MP, h->L, pA, vv);
     const int gB = phase_groups(bytes, h->MP, h->L, pB, vv);
+    const bool fold_ok = gA + gB <= kFoldSlots;
     a.nslots = gA + gB;
+    a.fold = 0;
+    a.prev_nslots = gA + gB;
+    a.prev_sum = h->part_sum + ((s - 1) & 1) * h->lay.nparts;
+    a.prev_diff = h->part_diff + ((s - 1) & 1) * h->lay.nparts;
     a.parity = pA;
     a.slot0 = 0;
     const void *ev_val = f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64;
@@ -197,16 +218,45 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev)
     if (e == hipSuccess && ev) e = hipEventRecord(ev[0], h->stream);
     a.parity = pB;
     a.slot0 = gA;
+    // phase B's extra workgroup records sweep s-1 (unless a flush or a batch
+    // already did, i.e. at the start of a burst)
+    a.fold = (fold_ok && !first && s >= 2) ? 1 : 0;
     if (e == hipSuccess) e = phase(true);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], h->stream);
-    if (e == hipSuccess)
-        e = launch_finalize_sweep(h->part_sum, h->part_diff, gA + gB, h->st, s, tol, h->stream);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], h->stream);
+    if (!fold_ok) {
+        if (e == hipSuccess)
+            e = launch_finalize_sweep(a.part_sum, a.part_diff, gA + gB, h->st, s, tol, h->stream);
+        if (e == hipSuccess && ev) e = hipEventRecord(ev[2], h->stream);
+    }
     return e;
 }
 
-stc_status launch_one_sweep(stc_handle *h, long long s, double tol) {
-    HIP_TRY(enqueue_sweep(h, s, tol, nullptr));
+// Finish a burst that ended with sweep n: record sweep n (the reduction the
+// next sweep's phase B would have done) and the changes of sweeps n-1 and n,
+// which the lagged partials have not measured yet, with the device stopping
+// test in sweep order.  After it the state is complete up to sweep n.
+hipError_t end_burst(stc_handle *h, long long n, double tol) {
+    if (n < 1) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (folds(h))
+        e = launch_finalize_sweep(h->part_sum + (n & 1) * h->lay.nparts,
+                                  h->part_diff + (n & 1) * h->lay.nparts, sweep_slots(h), h->st,
+                                  n, tol, h->stream);
+    const bool f32 = h->stage32;
+    const int vv = h->sparse ? 0 : h->variant[f32 ? 1 : 0];
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    for (long long k = n - 1; k <= n && e == hipSuccess; ++k) {
+        if (k < 1) continue;
+        e = launch_diff(f32 ? 4 : 8, h->MP, vv, wbuf(h, f32, k), wbuf(h, f32, k - 1), h->L, pA,
+                        h->st, k, h->part_aux, h->stream, tol);
+    }
+    return e;
+}
+
+// Enqueue sweeps s0+1 .. s0+n as one burst, state recorded at the end.
+stc_status run_burst(stc_handle *h, long long s0, long long n, double tol) {
+    for (long long j = 1; j <= n; ++j) HIP_TRY(enqueue_sweep(h, s0 + j, tol, nullptr, j == 1));
+    HIP_TRY(end_burst(h, s0 + n, tol));
     return STC_OK;
 }
 
@@ -308,14 +358,14 @@ stc_status store_vector(stc_handle *h, bool f32, long long s, double *pi, int32_
 }
 
 // Switch the current iterate from the FP32 rotation to the FP64 one at sweep
-// k: W_k and W_{k-1} are widened exactly, so the scale factors stay valid.
+// k: W_k, W_{k-1} and W_{k-2} (the next sweep's input and the two iterates of
+// the change it measures) are widened exactly, so the recorded scales stay
+// valid and the next FP64 sweep continues the same recurrence.
 stc_status widen_at(stc_handle *h, long long k) {
     const size_t vec = (size_t)h->L * h->MP;
-    HIP_TRY(launch_widen((const float *)wbuf(h, true, k), (double *)wbuf(h, false, k), vec,
-                         h->stream));
-    if (k >= 1)
-        HIP_TRY(launch_widen((const float *)wbuf(h, true, k - 1), (double *)wbuf(h, false, k - 1),
-                             vec, h->stream));
+    for (long long j = k; j >= 0 && j >= k - 2; --j)
+        HIP_TRY(launch_widen((const float *)wbuf(h, true, j), (double *)wbuf(h, false, j), vec,
+                             h->stream));
     h->stage32 = false;
     return STC_OK;
 }
@@ -583,10 +633,8 @@ stc_status stc_load(stc_handle *h, const double *x, int32_t where) {
 stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
     if (!h || nsweeps < 0) return fail(STC_EINVAL, "bad argument");
     const long long s0 = h->s;
-    for (int64_t j = 1; j <= nsweeps; ++j) {
-        stc_status rc = launch_one_sweep(h, s0 + j, 0.0);
-        if (rc != STC_OK) return rc;
-    }
+    stc_status rc = run_burst(h, s0, nsweeps, 0.0);
+    if (rc != STC_OK) return rc;
     h->s = s0 + nsweeps;
     if (h->stage32) h->iters32 += nsweeps;
     if (diffs && nsweeps > 1) {
@@ -602,14 +650,22 @@ stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, double *ms_b,
                               double *ms_fin, double *ms_sweep) {
     if (!h || nsweeps < 1) return fail(STC_EINVAL, "bad argument");
-    std::vector<hipEvent_t> ev(3 * nsweeps + 1);
+    // events: start, then after phase A, phase B and (when not folded) the
+    // finalize of every sweep, then after the flush that ends the burst
+    std::vector<hipEvent_t> ev(3 * nsweeps + 2);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     auto destroy = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
     const long long s0 = h->s;
+    const bool fold = folds(h);
     hipError_t err = hipEventRecord(ev[0], h->stream);
-    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j)
-        err = enqueue_sweep(h, s0 + j, 0.0, &ev[3 * (j - 1) + 1]);
-    if (err == hipSuccess) err = hipEventSynchronize(ev[3 * nsweeps]);
+    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j) {
+        hipEvent_t *e3 = &ev[3 * (j - 1) + 1];
+        err = enqueue_sweep(h, s0 + j, 0.0, e3, j == 1);
+        if (err == hipSuccess && fold) err = hipEventRecord(e3[2], h->stream);   // no finalize
+    }
+    if (err == hipSuccess) err = end_burst(h, s0 + nsweeps, 0.0);
+    if (err == hipSuccess) err = hipEventRecord(ev[3 * nsweeps + 1], h->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[3 * nsweeps + 1]);
     if (err != hipSuccess) {
         destroy();
         return fail(STC_EDEVICE, "profiled sweeps: %s", hipGetErrorString(err));
@@ -621,8 +677,10 @@ stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, doub
             (void)hipEventElapsedTime(&x, ev[3 * j + k], ev[3 * j + k + 1]);
             t[k] += x;
         }
-    float tot = 0.f;
-    (void)hipEventElapsedTime(&tot, ev[0], ev[3 * nsweeps]);
+    float flush = 0.f, tot = 0.f;
+    (void)hipEventElapsedTime(&flush, ev[3 * nsweeps], ev[3 * nsweeps + 1]);
+    (void)hipEventElapsedTime(&tot, ev[0], ev[3 * nsweeps + 1]);
+    t[2] += flush;   // folded: the one flush at the end of the burst
     destroy();
     h->s = s0 + nsweeps;
     if (h->stage32) h->iters32 += nsweeps;
@@ -669,10 +727,13 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
             if ((rc = load_vector_stage(h, nullptr, STC_MEM_HOST, f32)) != STC_OK) break;
             if (!h->sparse) h->variant[stage] = v;
             hipError_t e = hipSuccess;
-            for (long long j = 1; j <= 3 && e == hipSuccess; ++j) e = enqueue_sweep(h, j, 0.0, nullptr);
+            for (long long j = 1; j <= 3 && e == hipSuccess; ++j)
+                e = enqueue_sweep(h, j, 0.0, nullptr, j == 1);
+            if (e == hipSuccess) e = end_burst(h, 3, 0.0);
             if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
             for (long long j = 4; j < 4 + trial_sweeps && e == hipSuccess; ++j)
-                e = enqueue_sweep(h, j, 0.0, nullptr);
+                e = enqueue_sweep(h, j, 0.0, nullptr, j == 4);
+            if (e == hipSuccess) e = end_burst(h, 3 + trial_sweeps, 0.0);
             if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -740,8 +801,9 @@ stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *d
     if (sweeps) *sweeps = cur;
     if (stopped) *stopped = hs.stop_flag;
     if (diff_1) {
-        // latest known change: at the stopped sweep, else of the sweep before last
-        const long long k = hs.stop_flag ? hs.stop_sweep : hs.last_sweep - 1;
+        // latest change known for certain: at the stopped sweep, else two
+        // sweeps back (batched sweeps measure it two sweeps late)
+        const long long k = hs.stop_flag ? hs.stop_sweep : hs.last_sweep - 2;
         *diff_1 = INFINITY;
         if (k >= 1 && (rc = read_ring(h, h->st->diff, k, diff_1)) != STC_OK) return rc;
     }
@@ -799,11 +861,9 @@ stc_status stc_step(stc_handle *h, const double *x, double *z, double *diff_1, i
     if (x == z) return fail(STC_EINVAL, "z may not alias x");
     stc_status rc = load_vector(h, x, where);
     if (rc != STC_OK) return rc;
-    if ((rc = launch_one_sweep(h, 1, 0.0)) != STC_OK) return rc;
+    if ((rc = run_burst(h, 0, 1, 0.0)) != STC_OK) return rc;   // records sweep 1 and its change
     h->s = 1;
     if (h->stage32) h->iters32 = 1;
-    HIP_TRY(launch_diff(h->stage32 ? 4 : 8, h->MP, wbuf(h, h->stage32, 1), wbuf(h, h->stage32, 0),
-                        h->L, h->st, 1, h->part_aux, h->stream));
     HostState hs;
     if ((rc = read_state(h, &hs)) != STC_OK) return rc;
     if (hs.status == kDevDegenerate) return fail(STC_EDEGENERATE, "e^T z <= 0");
@@ -828,8 +888,7 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
     while (s < maxit) {
         const long long n = std::min<long long>(h->check_every, maxit - s);
         const double dt = device_tol();
-        for (long long j = 1; j <= n; ++j)
-            if ((rc = launch_one_sweep(h, s + j, dt)) != STC_OK) return rc;
+        if ((rc = run_burst(h, s, n, dt)) != STC_OK) return rc;
         s += n;
         h->s = s;
         if ((rc = read_state(h, &hs)) != STC_OK) return rc;
@@ -868,15 +927,8 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
     if (h->stage32 && !mixed) h->iters32 = s;
     if (final_k < 0) final_k = s;   // maxit reached
     h->s = final_k;
-    double diff = INFINITY;
-    if (final_k >= 1) {
-        if (!converged || h->stop != STC_STOP_DIFF) {
-            HIP_TRY(launch_diff(h->stage32 ? 4 : 8, h->MP, wbuf(h, h->stage32, final_k),
-                                wbuf(h, h->stage32, final_k - 1), h->L, h->st, final_k,
-                                h->part_aux, h->stream));
-        }
-        if ((rc = read_ring(h, h->st->diff, final_k, &diff)) != STC_OK) return rc;
-    }
+    double diff = INFINITY;   // every burst ends with the changes up to its last sweep
+    if (final_k >= 1 && (rc = read_ring(h, h->st->diff, final_k, &diff)) != STC_OK) return rc;
     double r;
     if ((rc = residual_of(h, h->stage32, final_k, &r)) != STC_OK) return rc;
     if (!converged) converged = (h->stop == STC_STOP_DIFF) ? (diff <= tol) : (r <= tol);
@@ -1040,7 +1092,7 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
         const int pA = (h->stair_type == 1) ? 0 : 1;
         ChainDesc d;
         d.blk = g == 1 ? (const void *)h->blk32 : (const void *)h->blk64;
-        for (int k = 0; k < 3; ++k) d.w[k] = wbuf(h, g == 1, k);
+        for (int k = 0; k < 4; ++k) d.w[k] = wbuf(h, g == 1, k);
         d.part_sum = h->part_sum;
         d.part_diff = h->part_diff;
         d.st = h->st;
