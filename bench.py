@@ -27,9 +27,15 @@ Other workloads (each prints its own JSON line instead):
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
   --pmc-probe     a short run for hardware counters: 10 autotuned sweeps of the
-                  default workload, then a 1 GiB device-to-device copy (the
-                  calibration kernel of known traffic), run under
+                  default workload (--variant V forces launch variant V),
+                  then a 1 GiB device-to-device copy (the calibration kernel
+                  of known traffic), run under
                   rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)
+  --traffic-summary PROBE FETCH_CSV WRITE_CSV
+                  no GPU: read the JSON line --pmc-probe printed (PROBE) and
+                  the two counter_collection.csv files those runs wrote,
+                  scale each counter by what it reads for the copy of known
+                  size, and write profiles/traffic.json
 """
 from __future__ import annotations
 
@@ -54,9 +60,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, variant: int):
     """HBM bytes per phase-A launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources."""
+    summary, if it was taken on the current kernel sources and the same
+    launch variant."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -64,6 +71,8 @@ def measured_traffic(workload: str):
         rec = json.load(f)
     entry = rec.get(workload)
     if not entry or entry.get("source_hash") != kernel_source_hash():
+        return None
+    if entry.get("variant") != variant:
         return None
     return entry.get("bytes_per_launch")
 
@@ -103,7 +112,11 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--setup", type=int, nargs=2, default=None)
     ap.add_argument("--banded", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=3, default=None)
+    ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
+    if args.traffic_summary:
+        return traffic_summary(*args.traffic_summary)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
@@ -113,7 +126,7 @@ def main():
     if args.serve:
         return serve_mode(args)
     if args.pmc_probe:
-        return pmc_probe()
+        return pmc_probe(variant=args.variant)
     if args.setup:
         return setup_mode(*args.setup)
     if args.banded:
@@ -158,7 +171,7 @@ def main():
     bytes_sweep = bytes_a + bytes_b
     value = bytes_sweep / (ms_per_step * 1e-3) / 1e9
     achieved = bytes_a / (ms_a * 1e-3) / 1e9
-    traffic = measured_traffic(workload)
+    traffic = measured_traffic(workload, stc.stc_get_variant(solver.h, stc.STC_FP64))
 
     line = {
         "metric": "HBM GB/s per staircase sweep",
@@ -338,7 +351,7 @@ def setup_mode(L, m):
                       "inverse_flops": flops}), flush=True)
 
 
-def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30):
+def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30, variant=None):
     import torch
     import synth
     from paper_2302_07551_amd import Solver, stc
@@ -346,6 +359,8 @@ def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30):
     gen = synth.qbd(L, m, synth.config_seed(1))
     s = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64")
     stc.stc_autotune(s.h, 10)
+    if variant is not None:
+        stc.stc_set_variant(s.h, stc.STC_FP64, variant)
     s.load(None)
     s.sweeps(sweeps)
     torch.cuda.synchronize()
@@ -359,6 +374,67 @@ def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30):
                       "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
                       "source_hash": kernel_source_hash()}), flush=True)
     s.close()
+
+
+def _counter_rows(path, counter):
+    import csv
+    rows = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            rows[key] = rows.get(key, 0.0) + float(r["Counter_Value"])
+    return [(name, v) for (_, name), v in rows.items()]
+
+
+def _phase_kernel(name, phase_b, variant):
+    """Is this the sweep kernel k_sweep<double, 64, 1, PHB, RG, NT> of the
+    chosen launch variant (RG = 4 if bit 0 else 8, NT = bit 1)?"""
+    rg = 4 if variant & 1 else 8
+    nt = "true" if variant & 2 else "false"
+    want = f"k_sweep<double,64,1,{'true' if phase_b else 'false'},{rg},{nt}>"
+    return want in name.replace(" ", "")
+
+
+def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1 << 30):
+    """HBM bytes per phase launch from the FETCH_SIZE and WRITE_SIZE runs of
+    --pmc-probe.  Each counter (KiB per dispatch) is scaled by what it reads
+    for the 1 GiB device copy, whose true traffic is 1 GiB each way."""
+    with open(probe_json) as f:
+        probe = json.loads(f.read().strip().splitlines()[-1])
+    variant = probe["variant"]
+    out = {}
+    for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
+                                 ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        copies = sorted((v for n, v in rows if "copyBuffer" in n), reverse=True)[:3]
+        scale = (copy_bytes / 1024) / (sum(copies) / len(copies))
+        a = [v for n, v in rows if _phase_kernel(n, False, variant)]
+        b = [v for n, v in rows if _phase_kernel(n, True, variant)]
+        if not a or not b:
+            raise SystemExit(f"no phase kernels of variant {variant} in {path}")
+        out[label] = (sum(a) / len(a), sum(b) / len(b), scale, len(a))
+    fa, fb, fs, n = out["fetch"]
+    wa, wb, ws, _ = out["write"]
+    rec = {
+        "source_hash": probe["source_hash"],
+        "variant": variant,
+        "bytes_per_launch": int(round((fa * fs + wa * ws) * 1024)),
+        "phase_b_bytes_per_launch": int(round((fb * fs + wb * ws) * 1024)),
+        "fetch_kib_per_launch": fa, "write_kib_per_launch": wa,
+        "phase_b_fetch_kib_per_launch": fb, "phase_b_write_kib_per_launch": wb,
+        "fetch_scale": fs, "write_scale": ws, "dispatches": n,
+        "algorithmic_bytes_per_launch": probe["phase_a_bytes"],
+        "phase_b_algorithmic_bytes_per_launch": probe["phase_b_bytes"],
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --pmc-probe --variant {variant}",
+                     f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --pmc-probe --variant {variant}",
+                     "python3 bench.py --traffic-summary PROBE FETCH_CSV WRITE_CSV"],
+    }
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as f:
+        json.dump({f"qbd_L{L}_m{m}_fp64": rec}, f, indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def args_tol(err_target):

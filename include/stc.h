@@ -156,10 +156,14 @@ stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t w
  * implicit synchronisation. */
 stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs);
 
-/* Measurement form of stc_sweeps: the same sweeps, with a HIP event recorded
- * on the handle's stream after every launch.  Returns the mean device time
- * of the phase-A launch, the phase-B launch and the finalize launch, and of a
- * whole sweep, in milliseconds (any pointer may be NULL). */
+/* Measurement form of stc_sweeps: the same sweeps, each phase launched with
+ * a start and a stop event attached to its dispatch (hipExtLaunchKernel), so
+ * the phase times are the kernels' own.  Returns the mean device time of the
+ * phase-A launch, of the phase-B launch, of the finalize work per sweep (the
+ * per-sweep finalize launches of long chains plus the flush that ends the
+ * burst, spread over the sweeps), and the mean wall time of a whole sweep
+ * between events recorded around the burst, in milliseconds (any pointer may
+ * be NULL). */
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_phase_a,
                               double *ms_phase_b, double *ms_finalize, double *ms_sweep);
 

@@ -2,6 +2,7 @@
 // device kernels (stc_kernels.hip) of the staircase solver library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -94,11 +95,19 @@ constexpr int kFoldSlots = 8192;
 int supported_mp(int m);   // padded block size for m, or 0
 int variant_count();
 int phase_groups(int precision_bytes, int MP, int L, int parity, int variant);
+// The sweep launchers take an optional pair of events attached to the
+// dispatch itself (hipExtLaunchKernel): they time the kernel alone, without
+// the markers a separate hipEventRecord adds to the stream.
+struct LaunchTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, int variant,
-                              const SweepLaunch &a, hipStream_t stream);
+                              const SweepLaunch &a, hipStream_t stream,
+                              LaunchTimer t = LaunchTimer());
 hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase_b,
                                   const SweepLaunch &a, const EllEntry *tab, const void *val,
-                                  const unsigned char *idx, hipStream_t stream);
+                                  const unsigned char *idx, hipStream_t stream,
+                                  LaunchTimer t = LaunchTimer());
 hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
                                  DevState *st, long long s, double tol, hipStream_t stream);
 hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, double *blk,

@@ -959,88 +959,100 @@ int reduce_groups(int MP, int L) {
     return (L + lpw - 1) / lpw;
 }
 
+// Launch through hipExtLaunchKernel when the dispatch is timed, so that the
+// events carry the kernel's own start and end.
+template <typename K, typename... Args>
+static void launch_timed(K kernel, int groups, hipStream_t s, LaunchTimer t, Args... args) {
+    if (t.start || t.stop)
+        hipExtLaunchKernelGGL(kernel, dim3(groups), dim3(kWG), 0, s, t.start, t.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, dim3(groups), dim3(kWG), 0, s, args...);
+}
+
 template <typename T, int MP, int B, int RG, bool NT>
-static hipError_t sweep_v(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s) {
+static hipError_t sweep_v(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s,
+                          LaunchTimer t) {
     const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, variant) +
                        ((phase_b && a.fold) ? 1 : 0);   // + the reduction workgroup
     if (groups <= 0) return hipSuccess;
     if (phase_b)
-        hipLaunchKernelGGL((k_sweep<T, MP, B, true, RG, NT>), dim3(groups), dim3(kWG), 0, s, a);
+        launch_timed(k_sweep<T, MP, B, true, RG, NT>, groups, s, t, a);
     else
-        hipLaunchKernelGGL((k_sweep<T, MP, B, false, RG, NT>), dim3(groups), dim3(kWG), 0, s, a);
+        launch_timed(k_sweep<T, MP, B, false, RG, NT>, groups, s, t, a);
     return hipGetLastError();
 }
 
 template <typename T, int MP, int B>
-static hipError_t sweep_mpb(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s) {
+static hipError_t sweep_mpb(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s,
+                            LaunchTimer t) {
     switch (variant) {
-        case 0: return sweep_v<T, MP, B, variant_rg(0), variant_nt(0)>(phase_b, 0, a, s);
-        case 1: return sweep_v<T, MP, B, variant_rg(1), variant_nt(1)>(phase_b, 1, a, s);
-        case 2: return sweep_v<T, MP, B, variant_rg(2), variant_nt(2)>(phase_b, 2, a, s);
-        case 3: return sweep_v<T, MP, B, variant_rg(3), variant_nt(3)>(phase_b, 3, a, s);
+        case 0: return sweep_v<T, MP, B, variant_rg(0), variant_nt(0)>(phase_b, 0, a, s, t);
+        case 1: return sweep_v<T, MP, B, variant_rg(1), variant_nt(1)>(phase_b, 1, a, s, t);
+        case 2: return sweep_v<T, MP, B, variant_rg(2), variant_nt(2)>(phase_b, 2, a, s, t);
+        case 3: return sweep_v<T, MP, B, variant_rg(3), variant_nt(3)>(phase_b, 3, a, s, t);
     }
     return hipErrorInvalidValue;
 }
 
 template <typename T, int B>
 static hipError_t sweep_b(int MP, bool phase_b, int variant, const SweepLaunch &a,
-                          hipStream_t s) {
+                          hipStream_t s, LaunchTimer t) {
     switch (MP) {
-        case 8: return sweep_mpb<T, 8, B>(phase_b, variant, a, s);
-        case 16: return sweep_mpb<T, 16, B>(phase_b, variant, a, s);
-        case 32: return sweep_mpb<T, 32, B>(phase_b, variant, a, s);
-        case 64: return sweep_mpb<T, 64, B>(phase_b, variant, a, s);
-        case 128: return sweep_mpb<T, 128, B>(phase_b, variant, a, s);
+        case 8: return sweep_mpb<T, 8, B>(phase_b, variant, a, s, t);
+        case 16: return sweep_mpb<T, 16, B>(phase_b, variant, a, s, t);
+        case 32: return sweep_mpb<T, 32, B>(phase_b, variant, a, s, t);
+        case 64: return sweep_mpb<T, 64, B>(phase_b, variant, a, s, t);
+        case 128: return sweep_mpb<T, 128, B>(phase_b, variant, a, s, t);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, int variant,
-                              const SweepLaunch &a, hipStream_t stream) {
+                              const SweepLaunch &a, hipStream_t stream, LaunchTimer t) {
     if (variant < 0 || variant >= kVariants) return hipErrorInvalidValue;
     if (precision_bytes == 8)
-        return b == 1 ? sweep_b<double, 1>(MP, phase_b, variant, a, stream)
-                      : sweep_b<double, 2>(MP, phase_b, variant, a, stream);
-    return b == 1 ? sweep_b<float, 1>(MP, phase_b, variant, a, stream)
-                  : sweep_b<float, 2>(MP, phase_b, variant, a, stream);
+        return b == 1 ? sweep_b<double, 1>(MP, phase_b, variant, a, stream, t)
+                      : sweep_b<double, 2>(MP, phase_b, variant, a, stream, t);
+    return b == 1 ? sweep_b<float, 1>(MP, phase_b, variant, a, stream, t)
+                  : sweep_b<float, 2>(MP, phase_b, variant, a, stream, t);
 }
 
 template <typename T, int MP, int B>
 static hipError_t ell_mpb(bool phase_b, const SweepLaunch &a, const EllEntry *tab,
-                          const void *val, const unsigned char *idx, hipStream_t s) {
+                          const void *val, const unsigned char *idx, hipStream_t s,
+                          LaunchTimer t) {
     const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, 0) +
                        ((phase_b && a.fold) ? 1 : 0);
     if (groups <= 0) return hipSuccess;
     if (phase_b)
-        hipLaunchKernelGGL((k_sweep_ell<T, MP, B, true>), dim3(groups), dim3(kWG), 0, s, a, tab,
-                           val, idx);
+        launch_timed(k_sweep_ell<T, MP, B, true>, groups, s, t, a, tab, val, idx);
     else
-        hipLaunchKernelGGL((k_sweep_ell<T, MP, B, false>), dim3(groups), dim3(kWG), 0, s, a, tab,
-                           val, idx);
+        launch_timed(k_sweep_ell<T, MP, B, false>, groups, s, t, a, tab, val, idx);
     return hipGetLastError();
 }
 
 template <typename T, int B>
 static hipError_t ell_b(int MP, bool phase_b, const SweepLaunch &a, const EllEntry *tab,
-                        const void *val, const unsigned char *idx, hipStream_t s) {
+                        const void *val, const unsigned char *idx, hipStream_t s,
+                        LaunchTimer t) {
     switch (MP) {
-        case 8: return ell_mpb<T, 8, B>(phase_b, a, tab, val, idx, s);
-        case 16: return ell_mpb<T, 16, B>(phase_b, a, tab, val, idx, s);
-        case 32: return ell_mpb<T, 32, B>(phase_b, a, tab, val, idx, s);
-        case 64: return ell_mpb<T, 64, B>(phase_b, a, tab, val, idx, s);
-        case 128: return ell_mpb<T, 128, B>(phase_b, a, tab, val, idx, s);
+        case 8: return ell_mpb<T, 8, B>(phase_b, a, tab, val, idx, s, t);
+        case 16: return ell_mpb<T, 16, B>(phase_b, a, tab, val, idx, s, t);
+        case 32: return ell_mpb<T, 32, B>(phase_b, a, tab, val, idx, s, t);
+        case 64: return ell_mpb<T, 64, B>(phase_b, a, tab, val, idx, s, t);
+        case 128: return ell_mpb<T, 128, B>(phase_b, a, tab, val, idx, s, t);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase_b,
                                   const SweepLaunch &a, const EllEntry *tab, const void *val,
-                                  const unsigned char *idx, hipStream_t stream) {
+                                  const unsigned char *idx, hipStream_t stream, LaunchTimer t) {
     if (precision_bytes == 8)
-        return b == 1 ? ell_b<double, 1>(MP, phase_b, a, tab, val, idx, stream)
-                      : ell_b<double, 2>(MP, phase_b, a, tab, val, idx, stream);
-    return b == 1 ? ell_b<float, 1>(MP, phase_b, a, tab, val, idx, stream)
-                  : ell_b<float, 2>(MP, phase_b, a, tab, val, idx, stream);
+        return b == 1 ? ell_b<double, 1>(MP, phase_b, a, tab, val, idx, stream, t)
+                      : ell_b<double, 2>(MP, phase_b, a, tab, val, idx, stream, t);
+    return b == 1 ? ell_b<float, 1>(MP, phase_b, a, tab, val, idx, stream, t)
+                  : ell_b<float, 2>(MP, phase_b, a, tab, val, idx, stream, t);
 }
 
 template <int MP>

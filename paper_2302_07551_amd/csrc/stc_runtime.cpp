@@ -178,7 +178,15 @@ bool folds(stc_handle *h) { return sweep_slots(h) <= kFoldSlots; }
 // load or a batch, so phase B does not reduce it again).  With ev != nullptr
 // an event is recorded after phase A (ev[0]), after phase B (ev[1]) and after
 // a finalize launch (ev[2], only when one is enqueued).
-hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev, bool first) {
+// Events of one profiled sweep: each phase's dispatch, and the per-sweep
+// finalize launch of long chains.
+struct SweepTimers {
+    LaunchTimer a, b;
+    hipEvent_t fin0 = nullptr, fin1 = nullptr;
+};
+
+hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTimers *tm,
+                         bool first) {
     const bool f32 = h->stage32;
     const int v = h->variant[f32 ? 1 : 0];
     SweepLaunch a;
@@ -209,24 +217,24 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, hipEvent_t *ev,
     a.slot0 = 0;
     const void *ev_val = f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64;
     auto phase = [&](bool phb) {
+        const LaunchTimer t = tm ? (phb ? tm->b : tm->a) : LaunchTimer();
         if (h->sparse)
             return launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab, ev_val,
-                                          h->ell_idx, h->stream);
-        return launch_sweep_phase(bytes, h->MP, h->b, phb, v, a, h->stream);
+                                          h->ell_idx, h->stream, t);
+        return launch_sweep_phase(bytes, h->MP, h->b, phb, v, a, h->stream, t);
     };
     hipError_t e = phase(false);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[0], h->stream);
     a.parity = pB;
     a.slot0 = gA;
     // phase B's extra workgroup records sweep s-1 (unless a flush or a batch
     // already did, i.e. at the start of a burst)
     a.fold = (fold_ok && !first && s >= 2) ? 1 : 0;
     if (e == hipSuccess) e = phase(true);
-    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], h->stream);
     if (!fold_ok) {
+        if (e == hipSuccess && tm) e = hipEventRecord(tm->fin0, h->stream);
         if (e == hipSuccess)
             e = launch_finalize_sweep(a.part_sum, a.part_diff, gA + gB, h->st, s, tol, h->stream);
-        if (e == hipSuccess && ev) e = hipEventRecord(ev[2], h->stream);
+        if (e == hipSuccess && tm) e = hipEventRecord(tm->fin1, h->stream);
     }
     return e;
 }
@@ -650,44 +658,62 @@ stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, double *ms_b,
                               double *ms_fin, double *ms_sweep) {
     if (!h || nsweeps < 1) return fail(STC_EINVAL, "bad argument");
-    // events: start, then after phase A, phase B and (when not folded) the
-    // finalize of every sweep, then after the flush that ends the burst
-    std::vector<hipEvent_t> ev(3 * nsweeps + 2);
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    const bool fold = folds(h);
+    // per sweep: start and stop of each phase's dispatch, and around the
+    // finalize launch when it is not folded; then the burst's bounds and its
+    // closing flush
+    std::vector<SweepTimers> tm(nsweeps);
+    std::vector<hipEvent_t> ev;
+    auto make = [&](hipEvent_t *e) {
+        hipError_t r = hipEventCreate(e);
+        if (r == hipSuccess) ev.push_back(*e);
+        return r;
+    };
+    hipEvent_t t0 = nullptr, t1 = nullptr, fl0 = nullptr;
+    hipError_t err = make(&t0);
+    if (err == hipSuccess) err = make(&t1);
+    if (err == hipSuccess) err = make(&fl0);
+    for (auto &t : tm) {
+        if (err == hipSuccess) err = make(&t.a.start);
+        if (err == hipSuccess) err = make(&t.a.stop);
+        if (err == hipSuccess) err = make(&t.b.start);
+        if (err == hipSuccess) err = make(&t.b.stop);
+        if (!fold && err == hipSuccess) err = make(&t.fin0);
+        if (!fold && err == hipSuccess) err = make(&t.fin1);
+    }
     auto destroy = [&]() { for (auto &e : ev) (void)hipEventDestroy(e); };
     const long long s0 = h->s;
-    const bool fold = folds(h);
-    hipError_t err = hipEventRecord(ev[0], h->stream);
-    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j) {
-        hipEvent_t *e3 = &ev[3 * (j - 1) + 1];
-        err = enqueue_sweep(h, s0 + j, 0.0, e3, j == 1);
-        if (err == hipSuccess && fold) err = hipEventRecord(e3[2], h->stream);   // no finalize
-    }
+    if (err == hipSuccess) err = hipEventRecord(t0, h->stream);
+    for (int64_t j = 1; j <= nsweeps && err == hipSuccess; ++j)
+        err = enqueue_sweep(h, s0 + j, 0.0, &tm[j - 1], j == 1);
+    if (err == hipSuccess) err = hipEventRecord(fl0, h->stream);
     if (err == hipSuccess) err = end_burst(h, s0 + nsweeps, 0.0);
-    if (err == hipSuccess) err = hipEventRecord(ev[3 * nsweeps + 1], h->stream);
-    if (err == hipSuccess) err = hipEventSynchronize(ev[3 * nsweeps + 1]);
+    if (err == hipSuccess) err = hipEventRecord(t1, h->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(t1);
     if (err != hipSuccess) {
         destroy();
         return fail(STC_EDEVICE, "profiled sweeps: %s", hipGetErrorString(err));
     }
-    double t[3] = {0.0, 0.0, 0.0};
-    for (int64_t j = 0; j < nsweeps; ++j)
-        for (int k = 0; k < 3; ++k) {
-            float x = 0.f;
-            (void)hipEventElapsedTime(&x, ev[3 * j + k], ev[3 * j + k + 1]);
-            t[k] += x;
-        }
-    float flush = 0.f, tot = 0.f;
-    (void)hipEventElapsedTime(&flush, ev[3 * nsweeps], ev[3 * nsweeps + 1]);
-    (void)hipEventElapsedTime(&tot, ev[0], ev[3 * nsweeps + 1]);
-    t[2] += flush;   // folded: the one flush at the end of the burst
+    auto ms = [](hipEvent_t a, hipEvent_t b) {
+        float x = 0.f;
+        (void)hipEventElapsedTime(&x, a, b);
+        return (double)x;
+    };
+    double ta = 0.0, tb = 0.0, tf = 0.0;
+    for (const auto &t : tm) {
+        ta += ms(t.a.start, t.a.stop);
+        tb += ms(t.b.start, t.b.stop);
+        if (!fold) tf += ms(t.fin0, t.fin1);
+    }
+    tf += ms(fl0, t1);   // the flush that ends the burst
+    const double tot = ms(t0, t1);
     destroy();
     h->s = s0 + nsweeps;
     if (h->stage32) h->iters32 += nsweeps;
-    if (ms_a) *ms_a = t[0] / nsweeps;
-    if (ms_b) *ms_b = t[1] / nsweeps;
-    if (ms_fin) *ms_fin = t[2] / nsweeps;
-    if (ms_sweep) *ms_sweep = (double)tot / nsweeps;
+    if (ms_a) *ms_a = ta / nsweeps;
+    if (ms_b) *ms_b = tb / nsweeps;
+    if (ms_fin) *ms_fin = tf / nsweeps;
+    if (ms_sweep) *ms_sweep = tot / nsweeps;
     return STC_OK;
 }
 

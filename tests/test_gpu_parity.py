@@ -299,6 +299,26 @@ def test_deterministic_bitwise():
     assert np.array_equal(p1, p2)
 
 
+@pytest.mark.parametrize("format", ["dense", "sparse"])
+def test_profiled_sweeps_equal_plain_sweeps(format):
+    """The measurement path (dispatch-attached events) runs the same sweeps:
+    the iterate and the device's sweep count match plain stc_sweeps bitwise,
+    and the phase times are positive and fit inside the sweep time."""
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(40, 32, 83, last=20)
+    a, b = _solver(g, format=format), _solver(g, format=format)
+    a.load(None)
+    b.load(None)
+    a.sweeps(7)
+    ms_a, ms_b, ms_f, ms_s = stc.stc_profile_sweeps(b.h, 7)
+    assert np.array_equal(a.store(), b.store())
+    assert a.query()[0] == b.query()[0] == 7
+    assert ms_a > 0 and ms_b > 0 and ms_f >= 0
+    assert ms_a + ms_b <= ms_s * 1.001 + 1e-3
+    a.close()
+    b.close()
+
+
 def test_device_pointers_match_host():
     g = synth.qbd(16, 16, 91, last=11)
     from paper_2302_07551_amd import stc
