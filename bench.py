@@ -17,7 +17,7 @@ Other workloads (each prints its own JSON line instead):
   --large         16384 levels x m=128 QBD (N = 2,097,152): per-sweep GB/s in
                   FP64 and FP32, and time to ||pi - pi_ref||_1 <= 1e-10,
                   mixed vs FP64
-  --serve N       served stream of N QBD requests (levels U{32..2048}, m in
+  --serve N       served stream of N QBD requests (512 is the served workload) (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
   --banded        2048 levels x m=128 block-pentadiagonal generator with 10 %
@@ -77,11 +77,12 @@ def measured_traffic(workload: str, variant: int):
     return entry.get("bytes_per_launch")
 
 
-def cpu_baseline(gen, budget_s: float = 12.0):
+def cpu_baseline(gen, budget_s: float = 12.0, threads: int | None = None):
     """The oracle's C/OpenMP Algorithm 2 sweep on the host cores (FP64)."""
     import numpy as np
     from oracle import csweep
-    threads = len(os.sched_getaffinity(0))
+    if threads is None:
+        threads = len(os.sched_getaffinity(0))
     cs = csweep.CSweep(gen.blocks, gen.sizes, gen.b, 1, threads=threads)
     x = np.full((gen.L, gen.m), 1.0 / gen.N)
     z = np.empty_like(x)
@@ -97,6 +98,25 @@ def cpu_baseline(gen, budget_s: float = 12.0):
         if el >= budget_s or n >= 2000:
             break
     return el / n, n, cs.threads
+
+
+def device_copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """GB/s of a device-to-device copy of nbytes (bytes read + bytes written
+    per second), timed with torch events."""
+    import torch
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del x, y
+    return 2 * nbytes / sec / 1e9
 
 
 def main():
@@ -204,12 +224,23 @@ def main():
     if not args.no_ttr:
         line["time_to_residual"] = time_to_residual(gen)
 
+    # the device's own copy rate on the same box, as a second yardstick
+    copy_gbs = device_copy_rate()
+    line["device_copy_GBs"] = round(copy_gbs, 1)
+    line["vs_device_copy"] = round(value / copy_gbs, 4)
+
     if not args.no_cpu:
         sec, n, threads = cpu_baseline(gen)
+        sec1, n1, _ = cpu_baseline(gen, budget_s=4.0, threads=1)
         line["cpu_baseline"] = {"value": round(bytes_sweep / sec / 1e9, 2), "unit": "GB/s",
                                 "cores": threads, "kind": "oracle",
                                 "sample": f"{n} FP64 sweeps of the same workload by the C/OpenMP "
-                                          f"oracle sweep ({sec * 1e3:.1f} ms each)"}
+                                          f"oracle sweep ({sec * 1e3:.1f} ms each)",
+                                "one_thread": {"value": round(bytes_sweep / sec1 / 1e9, 2),
+                                               "sample": f"{n1} sweeps at 1 thread "
+                                                         f"({sec1 * 1e3:.1f} ms each)"},
+                                "speedup": round(sec1 / sec, 2),
+                                "efficiency": round(sec1 / sec / threads, 3)}
     solver.close()
     print(json.dumps(line), flush=True)
 
@@ -454,7 +485,11 @@ def serve_mode(args):
     n = args.serve
     specs = synth.served_stream(n, synth.config_seed(4), rate=1.0)
     t0 = time.perf_counter()
-    gens = [synth.qbd(sp["L"], sp["m"], sp["seed"]) for sp in specs]
+    gens = []
+    for k, sp in enumerate(specs):
+        gens.append(synth.qbd(sp["L"], sp["m"], sp["seed"]))
+        if (k + 1) % 64 == 0:
+            print(f"# generated {k + 1} chains", file=sys.stderr, flush=True)
     print(f"# generated {n} chains in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
           flush=True)
     budget = int(args.budget_gb * (1 << 30))

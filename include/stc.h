@@ -248,6 +248,18 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
  * again when nsweeps or the set of precision stages changes) or as plain
  * launches.  Asynchronous: use stc_batch_sync / stc_query afterwards. */
 stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph);
+
+/* The stopping state of every chain of the batch in one device-to-host copy,
+ * after the work enqueued on the batch's stream (synchronises that stream).
+ * Arrays (host, may be NULL) have one entry per chain, in the order of the
+ * last stc_batch_set.  Per chain the values equal what stc_query returns for
+ * its handle: sweeps = the sweep of the current iterate, stopped = the device
+ * stopping test has fired (section 3's test on the change), diff_1 = the
+ * latest change known for certain (+inf before the first), and status =
+ * STC_OK or STC_EDEGENERATE (a sweep gave e^T z <= 0).  The call itself
+ * returns STC_OK unless the device fails. */
+stc_status stc_batch_query(stc_batch *bt, int64_t *sweeps, int32_t *stopped, double *diff_1,
+                           int32_t *status);
 stc_status stc_batch_sync(stc_batch *bt);
 void stc_batch_destroy(stc_batch *bt);
 

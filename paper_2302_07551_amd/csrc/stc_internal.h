@@ -86,6 +86,15 @@ struct WorkItem {
     int group;
 };
 
+// One chain's state as stc_batch_query reports it.
+struct QueryRow {
+    long long sweeps;       // sweep of the current iterate (the stop sweep once stopped)
+    long long last_sweep;   // last sweep whose phase B finished
+    double diff;            // latest change known for certain (+inf if none)
+    int stopped;
+    int status;             // DevStatus
+};
+
 // Largest number of per-group partial slots of a sweep that the extra
 // workgroup of phase B reduces; above it a finalize launch follows every
 // sweep (the reduction would outlast the streaming workgroups).
@@ -108,6 +117,7 @@ hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase
                                   const SweepLaunch &a, const EllEntry *tab, const void *val,
                                   const unsigned char *idx, hipStream_t stream,
                                   LaunchTimer t = LaunchTimer());
+hipError_t launch_batch_query(DevState *const *states, int n, QueryRow *out, hipStream_t stream);
 hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
                                  DevState *st, long long s, double tol, hipStream_t stream);
 hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, double *blk,

@@ -531,6 +531,26 @@ __global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
                    d.tol, sh);
 }
 
+// Gather the stopping state of n chains into one table (one thread per
+// chain).  The change reported is that of the stop sweep once stopped, else
+// of the sweep two back: lagged normalisation measures it two sweeps late.
+__global__ __launch_bounds__(kWG) void k_batch_query(DevState *const *states, int n,
+                                                      QueryRow *out) {
+    const int c = blockIdx.x * kWG + threadIdx.x;
+    if (c >= n) return;
+    const DevState *st = states[c];
+    const int f = st->stop_flag;
+    const long long ls = st->last_sweep;
+    const long long k = f ? st->stop_sweep : ls - 2;
+    QueryRow r;
+    r.sweeps = f ? st->stop_sweep : ls;
+    r.last_sweep = ls;
+    r.diff = k >= 1 ? st->diff[k & kRingMask] : INFINITY;
+    r.stopped = f;
+    r.status = st->status;
+    out[c] = r;
+}
+
 // Continue from sweep k after a precision switch: clear the stop state.
 __global__ void k_rearm(DevState *st, long long k) {
     if (threadIdx.x == 0) {
@@ -1144,6 +1164,13 @@ hipError_t launch_batch_phase(int precision_bytes, int b, bool phase_b, bool nt,
 hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
                                  hipStream_t stream) {
     hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, nchains);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_query(DevState *const *states, int n, QueryRow *out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_query, dim3((n + kWG - 1) / kWG), dim3(kWG), 0, stream, states, n,
+                       out);
     return hipGetLastError();
 }
 

@@ -7,7 +7,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <sched.h>
+
 #include <algorithm>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/stc.h"
@@ -37,6 +41,44 @@ stc_status fail(stc_status s, const char *fmt, ...) {
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Host threads for validation and packing: the CPUs this process may run on,
+// at most 16, and one for inputs too small to pay for starting threads.
+int host_threads(double bytes) {
+    if (bytes < 8.0 * (1 << 20)) return 1;
+    cpu_set_t set;
+    int n = 1;
+    if (sched_getaffinity(0, sizeof(set), &set) == 0) n = CPU_COUNT(&set);
+    return std::max(1, std::min(n, 16));
+}
+
+// Run f(k, i0, i1) over contiguous sub-ranges k = 0.. of the levels
+// [l0, l1) on up to `threads` host threads (the caller's thread takes range
+// 0).  Returns the number of ranges.
+template <typename F>
+int for_level_ranges(int l0, int l1, int threads, F f) {
+    const int n = l1 - l0;
+    const int t = std::max(1, std::min(threads, n));
+    if (t == 1) {
+        f(0, l0, l1);
+        return 1;
+    }
+    std::vector<std::thread> pool;
+    pool.reserve(t - 1);
+    for (int k = 1; k < t; ++k) {
+        const int a = l0 + (int)((long long)n * k / t), e = l0 + (int)((long long)n * (k + 1) / t);
+        pool.emplace_back([=, &f]() { f(k, a, e); });
+    }
+    f(0, l0, l0 + (int)((long long)n / t));
+    for (auto &th : pool) th.join();
+    return t;
+}
+
+// First error found by any packing thread, by lowest level.
+struct LevelError {
+    int level = -1;
+    std::string msg;
+};
 
 // Sub-allocation plan of one chain inside its arena.
 struct Layout {
@@ -485,17 +527,23 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         return fail(STC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     };
 
-    // validate, then pack in the sweep's layout, a chunk of levels at a time
+    // validate, then pack in the sweep's layout, a chunk of levels at a time;
+    // the levels of a chunk are split over host threads
     const size_t bs = (size_t)MP * MP, ms = (size_t)m * m;
     const int chunk = std::max(1, (int)std::min<size_t>(L, (64u << 20) / (NB * bs * 8)));
+    const int threads = host_threads((double)L * NB * ms * 8.0);
     std::vector<double> stage_blk((size_t)chunk * NB * bs), stage_diag((size_t)chunk * bs);
     const double *Qb = g->blocks;
     auto q_at = [&](int lev, int slot) { return Qb + ((size_t)lev * NB + slot) * ms; };
-    for (int l0 = 0; l0 < L; l0 += chunk) {
-        const int l1 = std::min(L, l0 + chunk);
-        std::fill(stage_blk.begin(), stage_blk.end(), 0.0);
-        std::fill(stage_diag.begin(), stage_diag.end(), 0.0);
-        for (int i = l0; i < l1; ++i) {
+    // pack levels [i0, i1) of the chunk starting at l0; on a bad entry return
+    // its level and message
+    auto pack = [&](int l0, int i0, int i1, LevelError *err) {
+        char msg[256];
+        std::fill(stage_blk.begin() + (size_t)(i0 - l0) * NB * bs,
+                  stage_blk.begin() + (size_t)(i1 - l0) * NB * bs, 0.0);
+        std::fill(stage_diag.begin() + (size_t)(i0 - l0) * bs,
+                  stage_diag.begin() + (size_t)(i1 - l0) * bs, 0.0);
+        for (int i = i0; i < i1; ++i) {
             const int ni = sizes[i];
             // generator checks on block row i
             for (int r = 0; r < ni; ++r) {
@@ -507,10 +555,13 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                     for (int c = 0; c < sizes[k]; ++c) {
                         if (d == 0 && c == r) continue;
                         const double v = row[c];
-                        if (!(v >= 0.0) || !isfinite(v))
-                            return cleanup(fail(STC_ENOTGEN,
-                                                "Q[level %d row %d][level %d col %d] = %g is not a rate",
-                                                i, r, k, c, v));
+                        if (!(v >= 0.0) || !isfinite(v)) {
+                            snprintf(msg, sizeof(msg),
+                                     "Q[level %d row %d][level %d col %d] = %g is not a rate", i, r,
+                                     k, c, v);
+                            *err = LevelError{i, msg};
+                            return;
+                        }
                         out += v;
                     }
                 }
@@ -519,11 +570,11 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                 for (int c = 0; c < ni; ++c) D[(size_t)r * MP + c] = q_at(i, b)[(size_t)r * m + c];
                 if (g->recompute_diagonal) {
                     D[(size_t)r * MP + r] = -out;
-                } else {
-                    if (!isfinite(dg) || fabs(dg + out) > 1e-10 * std::max(out, 1e-300))
-                        return cleanup(fail(STC_ENOTGEN,
-                                            "row %d of level %d sums to %g, not 0 (diagonal %g)",
-                                            r, i, dg + out, dg));
+                } else if (!isfinite(dg) || fabs(dg + out) > 1e-10 * std::max(out, 1e-300)) {
+                    snprintf(msg, sizeof(msg), "row %d of level %d sums to %g, not 0 (diagonal %g)",
+                             r, i, dg + out, dg);
+                    *err = LevelError{i, msg};
+                    return;
                 }
             }
             // gather-oriented off-diagonal blocks: slot d+b of level i <- Q_{i+d,i}
@@ -537,6 +588,16 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                     memcpy(dst + (size_t)r * MP, src + (size_t)r * m, sizeof(double) * sizes[i]);
             }
         }
+    };
+    for (int l0 = 0; l0 < L; l0 += chunk) {
+        const int l1 = std::min(L, l0 + chunk);
+        std::vector<LevelError> errs(threads);
+        for_level_ranges(l0, l1, threads,
+                         [&](int k, int i0, int i1) { pack(l0, i0, i1, &errs[k]); });
+        const LevelError *first = nullptr;
+        for (const auto &e : errs)
+            if (e.level >= 0 && (!first || e.level < first->level)) first = &e;
+        if (first) return cleanup(fail(STC_ENOTGEN, "%s", first->msg.c_str()));
         stc_status rc;
         if ((rc = dev(hipMemcpyAsync(h->blk64 + (size_t)l0 * NB * bs, stage_blk.data(),
                                      sizeof(double) * (size_t)(l1 - l0) * NB * bs,
@@ -572,25 +633,28 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
             const long long s1 = (l1 < L) ? tab[(size_t)l1 * NB].off : at;
             val.assign((size_t)(s1 - s0), 0.0);
             idx.assign((size_t)(s1 - s0), 0);
-            for (int i = l0; i < l1; ++i)
-                for (int d = -b; d <= b; ++d) {
-                    const EllEntry e = tab[(size_t)i * NB + d + b];
-                    if (e.K == 0) continue;
-                    const int k = i + d;
-                    const double *Q = q_at(k, -d + b);    // Q_{k,i}: rows level k, cols level i
-                    for (int j = 0; j < sizes[i]; ++j) {
-                        int cnt = 0;
-                        for (int r = 0; r < sizes[k]; ++r) {
-                            const double v = Q[(size_t)r * m + j];
-                            if (v == 0.0) continue;
-                            const size_t o = (size_t)(e.off - s0) +
-                                             ((size_t)(cnt >> 2) * MP + j) * 4 + (cnt & 3);
-                            val[o] = v;
-                            idx[o] = (unsigned char)r;
-                            ++cnt;
+            // each level writes only its own blocks' slots
+            for_level_ranges(l0, l1, threads, [&](int, int i0, int i1) {
+                for (int i = i0; i < i1; ++i)
+                    for (int d = -b; d <= b; ++d) {
+                        const EllEntry e = tab[(size_t)i * NB + d + b];
+                        if (e.K == 0) continue;
+                        const int k = i + d;
+                        const double *Q = q_at(k, -d + b);    // Q_{k,i}: rows level k, cols level i
+                        for (int j = 0; j < sizes[i]; ++j) {
+                            int cnt = 0;
+                            for (int r = 0; r < sizes[k]; ++r) {
+                                const double v = Q[(size_t)r * m + j];
+                                if (v == 0.0) continue;
+                                const size_t o = (size_t)(e.off - s0) +
+                                                 ((size_t)(cnt >> 2) * MP + j) * 4 + (cnt & 3);
+                                val[o] = v;
+                                idx[o] = (unsigned char)r;
+                                ++cnt;
+                            }
                         }
                     }
-                }
+            });
             if (s1 > s0) {
                 if ((rc = dev(hipMemcpyAsync(h->ell_v64 + s0, val.data(), sizeof(double) * (s1 - s0),
                                              hipMemcpyHostToDevice, h->stream), "copy ELL values")) != STC_OK ||
@@ -991,6 +1055,9 @@ struct stc_batch {
     WorkItem *d_items_b[2] = {nullptr, nullptr};
     int *d_counts = nullptr;                        // per group: chains, items A, items B
     int counts[6] = {0, 0, 0, 0, 0, 0};
+    DevState **d_states = nullptr;                  // members' states, in stc_batch_set order
+    QueryRow *d_query = nullptr;
+    std::vector<stc_handle *> members;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     long long graph_n = -1;
@@ -1000,7 +1067,7 @@ struct stc_batch {
 namespace {
 
 struct BatchLayout {
-    size_t chains = 0, items_a = 0, items_b = 0, counts = 0, total = 0;
+    size_t chains = 0, items_a = 0, items_b = 0, counts = 0, states = 0, query = 0, total = 0;
 };
 
 BatchLayout batch_layout(int max_chains, long long max_items) {
@@ -1011,6 +1078,8 @@ BatchLayout batch_layout(int max_chains, long long max_items) {
     l.items_a = take(2 * (size_t)max_items * sizeof(WorkItem));
     l.items_b = take(2 * (size_t)max_items * sizeof(WorkItem));
     l.counts = take(6 * sizeof(int));
+    l.states = take((size_t)max_chains * sizeof(DevState *));
+    l.query = take((size_t)max_chains * sizeof(QueryRow));
     l.total = at;
     return l;
 }
@@ -1082,6 +1151,8 @@ stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, vo
         bt->d_items_b[g] = (WorkItem *)(bt->base + l.items_b) + (size_t)g * max_items;
     }
     bt->d_counts = (int *)(bt->base + l.counts);
+    bt->d_states = (DevState **)(bt->base + l.states);
+    bt->d_query = (QueryRow *)(bt->base + l.query);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1164,7 +1235,13 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
     }
     HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
                            bt->stream));
+    std::vector<DevState *> states(count);
+    for (int c = 0; c < count; ++c) states[c] = hs[c]->st;
+    if (count > 0)
+        HIP_TRY(hipMemcpyAsync(bt->d_states, states.data(), sizeof(DevState *) * count,
+                               hipMemcpyHostToDevice, bt->stream));
     HIP_TRY(hipStreamSynchronize(bt->stream));
+    bt->members.assign(hs, hs + count);
     const bool nt = nontemporal != 0;
     if (nt != bt->nt) drop_graph(bt);
     bt->nt = nt;
@@ -1196,6 +1273,26 @@ stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph) {
         bt->graph_groups = groups;
     }
     HIP_TRY(hipGraphLaunch(bt->exec, bt->stream));
+    return STC_OK;
+}
+
+stc_status stc_batch_query(stc_batch *bt, int64_t *sweeps, int32_t *stopped, double *diff_1,
+                           int32_t *status) {
+    if (!bt) return fail(STC_EINVAL, "null batch");
+    const int n = (int)bt->members.size();
+    if (n == 0) return STC_OK;
+    std::vector<QueryRow> rows(n);
+    HIP_TRY(launch_batch_query(bt->d_states, n, bt->d_query, bt->stream));
+    HIP_TRY(hipMemcpyAsync(rows.data(), bt->d_query, sizeof(QueryRow) * n, hipMemcpyDeviceToHost,
+                           bt->stream));
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    for (int c = 0; c < n; ++c) {
+        bt->members[c]->s = rows[c].last_sweep;
+        if (sweeps) sweeps[c] = rows[c].sweeps;
+        if (stopped) stopped[c] = rows[c].stopped;
+        if (diff_1) diff_1[c] = rows[c].diff;
+        if (status) status[c] = rows[c].status == kDevDegenerate ? STC_EDEGENERATE : STC_OK;
+    }
     return STC_OK;
 }
 

@@ -117,19 +117,36 @@ class Server:
         reqs = sorted(requests, key=lambda r: r.arrival)
         pending = deque(reqs)
         waiting: deque = deque()
-        active = []          # (request, solver, footprint, admitted_at, stage)
+        active = []          # [request, solver, footprint, admitted_at, stage(, fp32 sweeps)]
+        joining = []         # admitted while the batch swept; they join the next round
+        fps = {}
         used = 0
         stats = ServeStats()
         t0 = clock()
         dirty = False
-        while pending or waiting or active:
+        while pending or waiting or active or joining:
             now = clock() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            # admission in arrival order: budget and free slots
-            while waiting and len(active) < self.max_chains:
+            if joining:
+                active.extend(joining)
+                joining = []
+                dirty = True
+            stats.peak_chains = max(stats.peak_chains, len(active))
+            stats.peak_bytes = max(stats.peak_bytes, used)
+            if active:
+                if dirty:
+                    self.setup_stream.synchronize()
+                    self.batch.set([a[1] for a in active], self.tol, self.nontemporal)
+                    dirty = False
+                self.batch.sweeps(self.K, self.use_graph)     # asynchronous
+            # admission in arrival order (budget and free slots), on the host
+            # and the side stream while the batch sweeps
+            while waiting and len(active) + len(joining) < self.max_chains:
                 req = waiting[0]
-                fp = self.footprint(req)
+                fp = fps.get(req.rid)
+                if fp is None:
+                    fp = fps[req.rid] = self.footprint(req)
                 if fp > self.budget:
                     waiting.popleft()
                     stats.rejected.append(req.rid)
@@ -138,47 +155,40 @@ class Server:
                     break
                 waiting.popleft()
                 s = self._admit(req)
-                active.append([req, s, fp, clock() - t0, 32 if self.precision != "fp64" else 64])
+                joining.append([req, s, fp, clock() - t0,
+                                32 if self.precision != "fp64" else 64])
                 used += fp
-                dirty = True
-            stats.peak_chains = max(stats.peak_chains, len(active))
-            stats.peak_bytes = max(stats.peak_bytes, used)
             if not active:
-                if pending:
+                if not joining and pending:
                     delay = pending[0].arrival - (clock() - t0)
                     if delay > 0:
                         time.sleep(min(delay, 0.05))
                 continue
-            if dirty:
-                self.setup_stream.synchronize()
-                self.batch.set([a[1] for a in active], self.tol, self.nontemporal)
-                dirty = False
-            self.batch.sweeps(self.K, self.use_graph)
-            self.batch.sync()
+            # one device-to-host copy for every chain's stopping state
+            _sweeps, stopped, _diffs, status = self.batch.query()
             stats.rounds += 1
             keep = []
-            for entry in active:
+            for k, entry in enumerate(active):
                 req, s, fp, t_adm, stage = entry[:5]
-                try:
-                    it, stopped, _ = s.query()
-                except stc.StcError:
+                if status[k] != stc.STC_OK:
                     # a sweep produced no positive mass: drop the request
                     stats.rejected.append(req.rid)
                     s.close()
                     used -= fp
                     dirty = True
                     continue
-                if not stopped:
+                if not stopped[k]:
                     keep.append(entry)
                     continue
                 if stage == 32 and self.precision == "mixed":
                     s.promote()
                     entry[4] = 64
-                    entry.append(it)          # sweeps in FP32
+                    entry.append(int(_sweeps[k]))          # sweeps in FP32
                     keep.append(entry)
                     dirty = True
                     continue
                 pi = s.store()
+                it = int(_sweeps[k])
                 it32 = entry[5] if len(entry) > 5 else (it if self.precision == "fp32" else 0)
                 stats.results.append(Result(req.rid, req.arrival, t_adm, clock() - t0, pi, it,
                                             it32, fp))

@@ -34,7 +34,8 @@ EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_res
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
            "stc_store", "stc_promote", "stc_batch_footprint", "stc_batch_create",
-           "stc_batch_set", "stc_batch_sweeps", "stc_batch_sync", "stc_batch_destroy",
+           "stc_batch_set", "stc_batch_sweeps", "stc_batch_query", "stc_batch_sync",
+           "stc_batch_destroy",
            "stc_destroy",
            "stc_status_string", "stc_last_error")
 
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
                                      POINTER(H)]
     lib.stc_batch_set.argtypes = [H, POINTER(H), c_int32, c_double, c_int32]
     lib.stc_batch_sweeps.argtypes = [H, c_int64, c_int32]
+    lib.stc_batch_query.argtypes = [H, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.stc_batch_sync.argtypes = [H]
     lib.stc_batch_destroy.argtypes = [H]
     lib.stc_batch_destroy.restype = None
@@ -114,7 +116,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("stc_setup", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
                  "stc_profile_sweeps", "stc_phase_bytes", "stc_set_variant", "stc_get_variant",
                  "stc_autotune", "stc_load", "stc_query", "stc_store", "stc_promote",
-                 "stc_batch_create", "stc_batch_set", "stc_batch_sweeps", "stc_batch_sync"):
+                 "stc_batch_create", "stc_batch_set", "stc_batch_sweeps", "stc_batch_query",
+                 "stc_batch_sync"):
         getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -291,6 +294,18 @@ def stc_batch_sweeps(bt, nsweeps: int, use_graph: bool = True):
     _check(load_library().stc_batch_sweeps(bt, int(nsweeps), int(bool(use_graph))))
 
 
+def stc_batch_query(bt, count: int):
+    """(sweeps, stopped, diff_1, status) arrays over the batch's chains, in
+    the order of the last stc_batch_set."""
+    sweeps = np.zeros(count, dtype=np.int64)
+    stopped = np.zeros(count, dtype=np.int32)
+    diffs = np.zeros(count, dtype=np.float64)
+    status = np.zeros(count, dtype=np.int32)
+    _check(load_library().stc_batch_query(bt, sweeps.ctypes.data, stopped.ctypes.data,
+                                          diffs.ctypes.data, status.ctypes.data))
+    return sweeps, stopped.astype(bool), diffs, status
+
+
 def stc_batch_sync(bt):
     _check(load_library().stc_batch_sync(bt))
 
@@ -324,6 +339,10 @@ class Batch:
 
     def sweeps(self, n: int, use_graph: bool = True):
         stc_batch_sweeps(self.bt, n, use_graph)
+
+    def query(self):
+        """Stopping state of every member: (sweeps, stopped, diff_1, status)."""
+        return stc_batch_query(self.bt, len(self.members))
 
     def sync(self):
         stc_batch_sync(self.bt)

@@ -117,3 +117,28 @@ def test_sparse_footprint_is_smaller(lib):
     ell_upper = 12 * 4 * MP * MP * 9
     assert sparse - dense <= ell_upper
     assert stc.stc_footprint_bytes(gen, stc.make_options(format=7)) == 0
+
+
+def _bad_gen_status(blocks, sizes, b):
+    gen, keep = stc.make_generator(blocks, sizes, b)
+    opt = stc.make_options()
+    opt.arena, opt.arena_bytes = 4096, 1 << 40    # never touched: validation fails first
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    return e.value
+
+
+def test_threaded_validation_reports_the_first_bad_level(lib):
+    """Validation of a large generator is split over host threads; the error
+    reported is still the one at the lowest level, as a serial scan finds."""
+    g = synth.qbd(600, 64, 31)                     # 59 MB of blocks: several threads
+    blocks = g.blocks.copy()
+    blocks[500, 0, 3, 5] = -1.0                    # a negative rate, late level
+    blocks[101, 2, 7, 1] = np.nan                  # earlier level, another range
+    err = _bad_gen_status(blocks, g.sizes, g.b)
+    assert err.status == stc.STC_ENOTGEN and "level 101 row 7" in str(err), str(err)
+    blocks = g.blocks.copy()
+    blocks[450, 1, 9, 9] += 0.5                    # row sum not 0
+    blocks[599, 0, 0, 1] = -2.0
+    err = _bad_gen_status(blocks, g.sizes, g.b)
+    assert err.status == stc.STC_ENOTGEN and "row 9 of level 450" in str(err), str(err)

@@ -124,11 +124,14 @@ def test_device_stop_and_membership_changes():
     rounds = 0
     while active and rounds < 2000:
         b.sweeps(25)
-        b.sync()
+        # the batched query equals every chain's own query, entry by entry
+        bq_it, bq_stop, bq_diff, bq_status = b.query()
         rounds += 1
         keep = []
-        for s in active:
-            it, stopped, _ = s.query()
+        for k, s in enumerate(active):
+            it, stopped, diff = s.query()
+            assert (bq_it[k], bq_stop[k], bq_status[k]) == (it, stopped, 0), k
+            assert bq_diff[k] == diff or (np.isinf(diff) and np.isinf(bq_diff[k])), k
             if stopped:
                 done[solvers.index(s)] = (s.store(), it)
             else:
