@@ -352,15 +352,46 @@ def banded_mode(L=2048, m=128):
             r["sweeps_per_s"] = round(1e3 / r["ms_per_sweep"], 1)
             runs[f"{fmt}_{prec}"] = r
             print(f"# {fmt} {prec}: {r}", file=sys.stderr, flush=True)
+    ingest = banded_ingest(gen)
     line = {"metric": "sweeps/s on the banded generator (dense vs sparse blocks)",
             "value": runs["sparse_fp64"]["sweeps_per_s"], "unit": "sweeps/s",
             "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"banded_b2_L{L}_m{m}_d0.1", "levels": L, "block": m,
                        "N": L * m, "seed": synth.config_seed(2)},
-            "runs": runs,
+            "runs": runs, "ingest": ingest,
             "speedup_sparse_vs_dense_fp64": round(runs["dense_fp64"]["ms_per_sweep"] /
                                                  runs["sparse_fp64"]["ms_per_sweep"], 3)}
     print(json.dumps(line), flush=True)
+
+
+def banded_ingest(gen):
+    """Setup time of the sparse-storage FP64 solver from dense blocks and from
+    the same generator in CSR form, and a check that both sweep alike."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver
+    t0 = time.perf_counter()
+    ip, ix, v = gen.to_csr()
+    t_conv = time.perf_counter() - t0
+    out = {"nnz": int(len(v)), "csr_host_bytes": int(ip.nbytes + ix.nbytes + v.nbytes),
+           "dense_host_bytes": int(gen.blocks.nbytes)}
+    x = synth.positive_start(gen, 1)
+    z = {}
+    for kind in ("dense_input", "csr_input"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "dense_input":
+            s = Solver(gen.blocks, gen.sizes, gen.b, format="sparse")
+        else:
+            s = Solver(None, gen.sizes, gen.b, csr=(ip, ix, v), m=gen.m, format="sparse")
+        torch.cuda.synchronize()
+        out[f"setup_s_{kind}"] = round(time.perf_counter() - t0, 4)
+        z[kind] = s.step(x)[0]
+        s.close()
+    out["same_sweep"] = bool(np.array_equal(z["dense_input"], z["csr_input"]))
+    print(f"# ingest {out} (to_csr {t_conv:.1f}s)", file=sys.stderr, flush=True)
+    return out
 
 
 def setup_mode(L, m):

@@ -61,19 +61,35 @@ enum { STC_STOP_DIFF = 0, STC_STOP_RESIDUAL = 1 };     /* stc_options.stop      
 enum { STC_MEM_HOST = 0, STC_MEM_DEVICE = 1 };         /* "where" arguments     */
 enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    */
 
-/* The block generator (section 2 block partition).  blocks is a host array
- * [L][2b+1][m][m], row-major: blocks[i][d+b] holds Q_{i,i+d} (rows = states
- * of level i, columns = states of level i+d) padded with zeros to m x m.
- * Slots with i+d outside [0, L) are ignored, as is the padding. */
+/* The block generator (section 2 block partition), in one of two host forms.
+ *
+ * Dense blocks: blocks is an array [L][2b+1][m][m], row-major: blocks[i][d+b]
+ * holds Q_{i,i+d} (rows = states of level i, columns = states of level i+d)
+ * padded with zeros to m x m.  Slots with i+d outside [0, L) are ignored, as
+ * is the padding.
+ *
+ * CSR (blocks NULL): the whole N x N generator, N = sum of the level sizes,
+ * states numbered level by level, as compressed sparse rows.  Every entry
+ * must lie in the block band (the levels of its row and column differ by at
+ * most b) and no column may repeat within a row (STC_EINVAL otherwise);
+ * explicit zeros are allowed.  Diagonal entries may be left out when
+ * recompute_diagonal is 1.  Setup scatters the rows into blocks a range of
+ * levels at a time, so it never holds a dense copy of the whole generator.
+ *
+ * Either way the host arrays are only read during stc_footprint_bytes and
+ * stc_setup, and the caller keeps ownership. */
 typedef struct {
     int32_t L;                   /* levels, >= 2                                    */
     int32_t m;                   /* block size: max states per level, 1..128       */
     int32_t b;                   /* block bandwidth, 1 or 2                        */
     const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */
-    const double *blocks;        /* host, see above                                */
+    const double *blocks;        /* dense blocks, see above; NULL = CSR input      */
     int32_t recompute_diagonal;  /* 1: diag(Q_ii) := -(row sum of its off-diagonal
                                     rates); 0: use the given diagonal, which must
                                     make every row sum to 0                        */
+    const int64_t *csr_rowptr;   /* CSR input: [N+1], csr_rowptr[0] = 0, rising    */
+    const int32_t *csr_col;      /* CSR input: [nnz] global column of each entry   */
+    const double *csr_val;       /* CSR input: [nnz] rate of each entry            */
 } stc_generator;
 
 typedef struct {

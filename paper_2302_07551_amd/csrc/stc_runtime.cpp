@@ -111,12 +111,138 @@ int ell_K(const stc_generator *g, int i, int d) {
     return (K + 3) / 4 * 4;   // stored in quads of slots
 }
 
-long long ell_slot_count(const stc_generator *g, int MP) {
-    long long tot = 0;
-    for (int i = 0; i < g->L; ++i)
-        for (int d = -g->b; d <= g->b; ++d) tot += (long long)ell_K(g, i, d) * MP;
-    return tot;
+bool csr_input(const stc_generator *g) { return !g->blocks && g->csr_rowptr; }
+
+// State offsets of the levels (prefix sums of the sizes), and the level of
+// every state.
+void level_offsets(const stc_generator *g, std::vector<long long> *off, std::vector<int> *lev) {
+    off->assign(g->L + 1, 0);
+    for (int i = 0; i < g->L; ++i) (*off)[i + 1] = (*off)[i] + level_size(g, i);
+    if (lev) {
+        lev->resize((*off)[g->L]);
+        for (int i = 0; i < g->L; ++i)
+            std::fill(lev->begin() + (*off)[i], lev->begin() + (*off)[i + 1], i);
+    }
 }
+
+// ell_K of every block [L][2b+1] (0 for the diagonal and absent blocks).
+// For CSR input the nonzeros of each column of each gather-oriented block
+// Q_{i+d,i} are counted from the entries directly; entries outside the band
+// or the matrix are skipped here (setup rejects them).  Returns false if the
+// CSR row pointers are malformed.
+bool ell_K_table(const stc_generator *g, std::vector<int> *Ks) {
+    const int L = g->L, b = g->b, m = g->m, NB = 2 * b + 1;
+    Ks->assign((size_t)L * NB, 0);
+    if (!csr_input(g)) {
+        for (int i = 0; i < L; ++i)
+            for (int d = -b; d <= b; ++d) (*Ks)[(size_t)i * NB + d + b] = ell_K(g, i, d);
+        return true;
+    }
+    std::vector<long long> off;
+    std::vector<int> lev;
+    level_offsets(g, &off, &lev);
+    const long long N = off[L];
+    const int64_t *rp = g->csr_rowptr;
+    if (rp[0] != 0) return false;
+    std::vector<int> cnt((size_t)L * NB * m, 0);
+    for (long long r = 0; r < N; ++r) {
+        if (rp[r + 1] < rp[r]) return false;
+        const int k = lev[r];
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+            const long long c = g->csr_col[p];
+            if (c < 0 || c >= N || g->csr_val[p] == 0.0) continue;
+            const int i = lev[c], d = k - i;
+            if (d == 0 || d < -b || d > b) continue;
+            ++cnt[((size_t)i * NB + d + b) * m + (c - off[i])];
+        }
+    }
+    for (size_t blk = 0; blk < (size_t)L * NB; ++blk) {
+        int K = 0;
+        for (int j = 0; j < m; ++j) K = std::max(K, cnt[blk * m + j]);
+        (*Ks)[blk] = (K + 3) / 4 * 4;
+    }
+    return true;
+}
+
+// Row-block access to the generator's host input during setup.  Dense input
+// is read in place.  CSR input is scattered, a range of block rows at a time
+// (on the packing threads), into a zeroed staging copy of the dense layout
+// [level][2b+1][m][m]; the entries are checked on the way.
+struct BlockSource {
+    const stc_generator *g = nullptr;
+    int L = 0, m = 0, b = 0, NB = 0;
+    std::vector<long long> off;
+    std::vector<int> lev;
+    std::vector<double> buf;
+    int lo = 0, hi = 0;
+
+    explicit BlockSource(const stc_generator *gen) : g(gen), L(gen->L), m(gen->m), b(gen->b) {
+        NB = 2 * b + 1;
+        if (csr_input(g)) level_offsets(g, &off, &lev);
+    }
+    // Q_{lev, lev + slot - b}, m x m row-major
+    const double *at(int level, int slot) const {
+        const size_t ms = (size_t)m * m;
+        if (!csr_input(g)) return g->blocks + ((size_t)level * NB + slot) * ms;
+        return buf.data() + ((size_t)(level - lo) * NB + slot) * ms;
+    }
+    // Make block rows [l0, l1) (clamped to the levels) readable through at().
+    // CSR: on a bad entry, *err names the lowest level that has one.
+    void load(int l0, int l1, int threads, LevelError *err) {
+        if (!csr_input(g)) return;
+        lo = std::max(0, l0);
+        hi = std::min(L, l1);
+        const size_t ms = (size_t)m * m;
+        buf.resize((size_t)(hi - lo) * NB * ms);
+        const long long N = off[L];
+        std::vector<LevelError> errs(threads);
+        for_level_ranges(lo, hi, threads, [&](int t, int i0, int i1) {
+            std::fill(buf.begin() + (size_t)(i0 - lo) * NB * ms,
+                      buf.begin() + (size_t)(i1 - lo) * NB * ms, 0.0);
+            std::vector<long long> cols;
+            char msg[256];
+            for (int i = i0; i < i1; ++i)
+                for (long long r = off[i]; r < off[i + 1]; ++r) {
+                    const int64_t p0 = g->csr_rowptr[r], p1 = g->csr_rowptr[r + 1];
+                    if (p1 < p0 || (r == 0 && p0 != 0)) {
+                        snprintf(msg, sizeof(msg), "CSR row pointers fall at row %lld", r);
+                        errs[t] = LevelError{i, msg};
+                        return;
+                    }
+                    cols.clear();
+                    for (int64_t p = p0; p < p1; ++p) {
+                        const long long c = g->csr_col[p];
+                        if (c < 0 || c >= N) {
+                            snprintf(msg, sizeof(msg), "CSR column %lld of row %lld is outside 0..%lld",
+                                     c, r, N - 1);
+                            errs[t] = LevelError{i, msg};
+                            return;
+                        }
+                        const int k = lev[c];
+                        if (k < i - b || k > i + b) {
+                            snprintf(msg, sizeof(msg),
+                                     "CSR entry (%lld, %lld) joins levels %d and %d: outside the "
+                                     "block band %d", r, c, i, k, b);
+                            errs[t] = LevelError{i, msg};
+                            return;
+                        }
+                        cols.push_back(c);
+                        buf[((size_t)(i - lo) * NB + (k - i + b)) * ms +
+                            (size_t)(r - off[i]) * m + (c - off[k])] = g->csr_val[p];
+                    }
+                    std::sort(cols.begin(), cols.end());
+                    for (size_t q = 1; q < cols.size(); ++q)
+                        if (cols[q] == cols[q - 1]) {
+                            snprintf(msg, sizeof(msg), "CSR row %lld repeats column %lld", r, cols[q]);
+                            errs[t] = LevelError{i, msg};
+                            return;
+                        }
+                }
+        });
+        for (const auto &e : errs)
+            if (e.level >= 0 && (err->level < 0 || e.level < err->level)) *err = e;
+    }
+};
 
 bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     *why = 0;
@@ -127,13 +253,21 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (!MP) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
     if (o->format != STC_DENSE && o->format != STC_SPARSE) { *why = 5; return false; }
-    if (!g->blocks) { *why = 6; return false; }
+    if (!g->blocks && !(g->csr_rowptr && g->csr_col && g->csr_val)) { *why = 6; return false; }
+    if (g->sizes)
+        for (int i = 0; i < g->L; ++i)
+            if (g->sizes[i] < 1 || g->sizes[i] > g->m) { *why = 9; return false; }
+    if (g->blocks && g->csr_rowptr) { *why = 7; return false; }
     Layout l;
     l.MP = MP;
     l.NB = 2 * g->b + 1;
     l.fp32 = o->precision != STC_FP64;
     l.sparse = o->format == STC_SPARSE;
-    if (l.sparse) l.ell_slots = ell_slot_count(g, MP);
+    if (l.sparse) {
+        std::vector<int> Ks;
+        if (!ell_K_table(g, &Ks)) { *why = 8; return false; }
+        for (int K : Ks) l.ell_slots += (long long)K * MP;
+    }
     const size_t L = (size_t)g->L, bs = (size_t)MP * MP, vec = L * MP;
     size_t at = 0;
     auto take = [&](size_t bytes) { size_t p = at; at = align_up(at + bytes); return p; };
@@ -453,15 +587,21 @@ size_t stc_footprint_bytes(const stc_generator *gen, const stc_options *opt) {
 stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **out) {
     if (!g || !o || !out) return fail(STC_EINVAL, "null argument");
     *out = nullptr;
+    if (g->sizes && g->L >= 2 && g->m >= 1)
+        for (int i = 0; i < g->L; ++i)
+            if (g->sizes[i] < 1 || g->sizes[i] > g->m)
+                return fail(STC_EINVAL, "sizes[%d] = %d outside 1..%d", i, g->sizes[i], g->m);
     Layout lay;
     int why = 0;
     if (!plan(g, o, &lay, &why)) {
         static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be 1 or 2",
                                     "m must be in 1..128", "unknown precision", "unknown format",
-                                    "blocks is NULL"};
-        return fail(STC_EINVAL, "%s", msg[why < 7 ? why : 0]);
+                                    "neither blocks nor a complete CSR input given",
+                                    "give blocks or CSR input, not both",
+                                    "CSR row pointers must start at 0 and never fall",
+                                    "a level size is outside 1..m"};
+        return fail(STC_EINVAL, "%s", msg[why < 10 ? why : 0]);
     }
-    if (!g->blocks) return fail(STC_EINVAL, "blocks is NULL");
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
     if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
     if (!o->arena) return fail(STC_EINVAL, "arena is NULL");
@@ -471,13 +611,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
 
     const int L = g->L, m = g->m, b = g->b, MP = lay.MP, NB = lay.NB;
     std::vector<int> sizes(L, m);
-    if (g->sizes) {
-        for (int i = 0; i < L; ++i) {
-            if (g->sizes[i] < 1 || g->sizes[i] > m)
-                return fail(STC_EINVAL, "sizes[%d] = %d outside 1..%d", i, g->sizes[i], m);
-            sizes[i] = g->sizes[i];
-        }
-    }
+    if (g->sizes) std::copy(g->sizes, g->sizes + L, sizes.begin());
 
     stc_handle *h = new stc_handle();
     h->L = L; h->m = m; h->b = b; h->MP = MP; h->NB = NB;
@@ -533,8 +667,15 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     const int chunk = std::max(1, (int)std::min<size_t>(L, (64u << 20) / (NB * bs * 8)));
     const int threads = host_threads((double)L * NB * ms * 8.0);
     std::vector<double> stage_blk((size_t)chunk * NB * bs), stage_diag((size_t)chunk * bs);
-    const double *Qb = g->blocks;
-    auto q_at = [&](int lev, int slot) { return Qb + ((size_t)lev * NB + slot) * ms; };
+    BlockSource src(g);
+    auto q_at = [&](int lev, int slot) { return src.at(lev, slot); };
+    // block rows [l0 - b, l1 + b) are read while packing levels [l0, l1)
+    auto load_rows = [&](int l0, int l1) -> stc_status {
+        LevelError lerr;
+        src.load(l0 - b, l1 + b, threads, &lerr);
+        if (lerr.level >= 0) return fail(STC_EINVAL, "%s", lerr.msg.c_str());
+        return STC_OK;
+    };
     // pack levels [i0, i1) of the chunk starting at l0; on a bad entry return
     // its level and message
     auto pack = [&](int l0, int i0, int i1, LevelError *err) {
@@ -591,6 +732,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     };
     for (int l0 = 0; l0 < L; l0 += chunk) {
         const int l1 = std::min(L, l0 + chunk);
+        if (stc_status rc = load_rows(l0, l1); rc != STC_OK) return cleanup(rc);
         std::vector<LevelError> errs(threads);
         for_level_ranges(l0, l1, threads,
                          [&](int k, int i0, int i1) { pack(l0, i0, i1, &errs[k]); });
@@ -612,16 +754,13 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     stc_status rc;
     if (lay.sparse) {
         // column-major ELL of every off-diagonal block, levels in order
-        h->ell_K.assign((size_t)L * NB, 0);
+        if (!ell_K_table(g, &h->ell_K)) return cleanup(fail(STC_EINVAL, "bad CSR row pointers"));
         std::vector<EllEntry> tab((size_t)L * NB);
         long long at = 0;
-        for (int i = 0; i < L; ++i)
-            for (int d = -b; d <= b; ++d) {
-                const int K = ell_K(g, i, d);
-                h->ell_K[(size_t)i * NB + d + b] = K;
-                tab[(size_t)i * NB + d + b] = EllEntry{at, K, 0};
-                at += (long long)K * MP;
-            }
+        for (size_t q = 0; q < tab.size(); ++q) {
+            tab[q] = EllEntry{at, h->ell_K[q], 0};
+            at += (long long)h->ell_K[q] * MP;
+        }
         if ((rc = dev(hipMemcpyAsync(h->ell_tab, tab.data(), tab.size() * sizeof(EllEntry),
                                      hipMemcpyHostToDevice, h->stream), "copy ELL table")) != STC_OK)
             return cleanup(rc);
@@ -629,6 +768,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         std::vector<unsigned char> idx;
         for (int l0 = 0; l0 < L; l0 += chunk) {
             const int l1 = std::min(L, l0 + chunk);
+            if ((rc = load_rows(l0, l1)) != STC_OK) return cleanup(rc);
             const long long s0 = tab[(size_t)l0 * NB].off;
             const long long s1 = (l1 < L) ? tab[(size_t)l1 * NB].off : at;
             val.assign((size_t)(s1 - s0), 0.0);

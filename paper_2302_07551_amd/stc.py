@@ -42,7 +42,8 @@ EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_res
 
 class stc_generator(ctypes.Structure):
     _fields_ = [("L", c_int32), ("m", c_int32), ("b", c_int32), ("sizes", POINTER(c_int32)),
-                ("blocks", POINTER(c_double)), ("recompute_diagonal", c_int32)]
+                ("blocks", POINTER(c_double)), ("recompute_diagonal", c_int32),
+                ("csr_rowptr", c_void_p), ("csr_col", c_void_p), ("csr_val", c_void_p)]
 
 
 class stc_options(ctypes.Structure):
@@ -146,6 +147,24 @@ def make_generator(blocks: np.ndarray, sizes, b: int, recompute_diagonal: bool =
                       sz.ctypes.data_as(POINTER(c_int32)) if sz is not None else None,
                       blocks.ctypes.data_as(POINTER(c_double)), int(bool(recompute_diagonal)))
     return g, (blocks, sz)
+
+
+def make_generator_csr(indptr, indices, data, sizes, b: int, m: int | None = None,
+                       recompute_diagonal: bool = False):
+    """Marshal an N x N generator in CSR form (states numbered level by level,
+    level sizes `sizes`) into the C struct; returns (struct, keep-alive)."""
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    rp = np.ascontiguousarray(indptr, dtype=np.int64)
+    col = np.ascontiguousarray(indices, dtype=np.int32)
+    val = _f64(data)
+    if rp.shape != (int(sz.sum()) + 1,) or col.shape != val.shape:
+        raise ValueError("need indptr of length N+1 and matching indices and data")
+    L = len(sz)
+    m = int(sz.max()) if m is None else int(m)
+    g = stc_generator(L, m, b, sz.ctypes.data_as(POINTER(c_int32)), None,
+                      int(bool(recompute_diagonal)), rp.ctypes.data, col.ctypes.data,
+                      val.ctypes.data)
+    return g, (sz, rp, col, val)
 
 
 FORMATS = {"dense": STC_DENSE, "sparse": STC_SPARSE}
@@ -368,19 +387,28 @@ def stc_destroy(h):
 class Solver:
     """One chain on the current GPU: owns the torch arena and the handle."""
 
-    def __init__(self, blocks: np.ndarray, sizes, b: int, *, precision="fp64", stair_type=1,
-                 stop="diff", check_every=1, switch_tol=0.0, recompute_diagonal=False,
-                 device=None, stream=None, poison=False, format="dense"):
-        """poison: fill the arena with 0xFF bytes (a NaN in FP32 and FP64)
-        before setup, so that any read of memory the library did not write
-        first shows up as NaN in the results (a test aid)."""
+    def __init__(self, blocks: np.ndarray | None, sizes, b: int, *, precision="fp64",
+                 stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
+                 recompute_diagonal=False, device=None, stream=None, poison=False,
+                 format="dense", csr=None, m=None):
+        """blocks: [L][2b+1][m][m] dense blocks, or None with csr = (indptr,
+        indices, data) of the N x N generator (sizes then required; m
+        defaults to the largest size).  poison: fill the arena with 0xFF
+        bytes (a NaN in FP32 and FP64) before setup, so that any read of
+        memory the library did not write first shows up as NaN in the
+        results (a test aid)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the staircase solver needs a GPU")
         load_library()
         self.device = torch.device(device if device is not None else "cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
+        if blocks is None:
+            if csr is None or sizes is None:
+                raise ValueError("give blocks, or csr with sizes")
+            self.gen, self._keep = make_generator_csr(*csr, sizes, b, m, recompute_diagonal)
+        else:
+            self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
         self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
                                 stream=self.stream.cuda_stream, format=format)
         need = stc_footprint_bytes(self.gen, self.opt)
@@ -397,6 +425,13 @@ class Solver:
         with torch.cuda.device(self.device):
             self.h = stc_setup(self.gen, self.opt)
         self._keep = None   # host inputs were copied during setup
+
+    @classmethod
+    def from_sparse(cls, Q, sizes, b: int, **kw):
+        """A solver for a generator given as a scipy.sparse matrix (N x N,
+        states numbered level by level); the rows go through the CSR input."""
+        Q = Q.tocsr()
+        return cls(None, sizes, b, csr=(Q.indptr, Q.indices, Q.data), **kw)
 
     def solve(self, x0=None, tol=1e-9, maxit=10_000, allow_maxit=True):
         pi = np.empty(self.N)

@@ -71,6 +71,52 @@ class BlockGenerator:
             return np.zeros((self.sizes[i], self.sizes[k]))
         return self.blocks[i, d + self.b, : self.sizes[i], : self.sizes[k]]
 
+    def to_csr(self, drop_diagonal: bool = False, explicit_zeros: int = 0, seed: int = 0):
+        """The same generator as one N x N CSR matrix (indptr int64, indices
+        int32, data float64), states numbered level by level.  Entries are the
+        nonzeros of the blocks; drop_diagonal leaves out Q's diagonal entries;
+        explicit_zeros adds that many stored zeros at random in-band positions
+        that hold no rate (a storage variant, not a different matrix)."""
+        off = self.offsets
+        rows, cols, vals = [], [], []
+        for i in range(self.L):
+            for d in range(-self.b, self.b + 1):
+                k = i + d
+                if not (0 <= k < self.L):
+                    continue
+                B = self.block(i, k)
+                r, c = np.nonzero(B)
+                v = B[r, c]
+                if d == 0 and drop_diagonal:
+                    keep = r != c
+                    r, c, v = r[keep], c[keep], v[keep]
+                rows.append(r + off[i])
+                cols.append(c + off[k])
+                vals.append(v)
+        rows, cols, vals = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+        if explicit_zeros:
+            rng = np.random.default_rng(seed)
+            taken = set(zip(rows.tolist(), cols.tolist()))
+            zr, zc = [], []
+            while len(zr) < explicit_zeros:
+                i = int(rng.integers(self.L))
+                k = int(np.clip(i + rng.integers(-self.b, self.b + 1), 0, self.L - 1))
+                r = int(off[i] + rng.integers(self.sizes[i]))
+                c = int(off[k] + rng.integers(self.sizes[k]))
+                if (r, c) in taken or (drop_diagonal and r == c):
+                    continue
+                taken.add((r, c))
+                zr.append(r)
+                zc.append(c)
+            rows = np.concatenate([rows, np.array(zr, dtype=rows.dtype)])
+            cols = np.concatenate([cols, np.array(zc, dtype=cols.dtype)])
+            vals = np.concatenate([vals, np.zeros(len(zr))])
+        order = np.lexsort((cols, rows))
+        rows, cols, vals = rows[order], cols[order], vals[order]
+        indptr = np.zeros(self.N + 1, dtype=np.int64)
+        np.cumsum(np.bincount(rows, minlength=self.N), out=indptr[1:])
+        return indptr, cols.astype(np.int32), vals.astype(np.float64)
+
     def pack(self, x: np.ndarray) -> np.ndarray:
         """Compact N-vector -> padded [L, m] array (padding = 0)."""
         out = np.zeros((self.L, self.m), dtype=x.dtype)

@@ -142,3 +142,92 @@ def test_threaded_validation_reports_the_first_bad_level(lib):
     blocks[599, 0, 0, 1] = -2.0
     err = _bad_gen_status(blocks, g.sizes, g.b)
     assert err.status == stc.STC_ENOTGEN and "row 9 of level 450" in str(err), str(err)
+
+
+# ---- CSR input -------------------------------------------------------------
+
+def _csr_gen(g, **kw):
+    ip, ix, v = g.to_csr(**{k: kw.pop(k) for k in ("drop_diagonal", "explicit_zeros") if k in kw})
+    gen, keep = stc.make_generator_csr(ip, ix, v, g.sizes, g.b, g.m, **kw)
+    return gen, keep
+
+
+CSR_CASES = [
+    ("qbd_ragged", lambda: synth.qbd(33, 12, 7, last=7)),
+    ("band_b2", lambda: synth.banded(17, 16, 11, b=2, density=0.3, last=9)),
+    ("band_m128", lambda: synth.banded(6, 128, 12, b=2, density=0.1)),
+]
+
+
+@pytest.mark.parametrize("name,make", CSR_CASES, ids=[c[0] for c in CSR_CASES])
+@pytest.mark.parametrize("fmt", ["dense", "sparse"])
+def test_csr_footprint_equals_dense_input(lib, name, make, fmt):
+    """The CSR form of a generator needs the same device bytes as its dense
+    blocks, also with stored zeros (they do not widen the sparse storage)."""
+    g = make()
+    gd, _kd = stc.make_generator(g.blocks, g.sizes, g.b)
+    want = stc.stc_footprint_bytes(gd, stc.make_options(format=fmt))
+    for kw in ({}, {"explicit_zeros": 40}):
+        gc, _kc = _csr_gen(g, **kw)
+        assert stc.stc_footprint_bytes(gc, stc.make_options(format=fmt)) == want, kw
+
+
+def _setup_error(gen):
+    opt = stc.make_options()
+    opt.arena, opt.arena_bytes = 4096, 1 << 40    # never touched: validation fails first
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    return e.value
+
+
+def test_csr_input_rejections(lib):
+    g = synth.qbd(12, 8, 21)
+    ip, ix, v = g.to_csr()
+    # an entry joining levels 0 and 2 of a QBD (b = 1)
+    ix2 = ix.copy()
+    ix2[0] = g.offsets[2] + 1
+    err = _setup_error(stc.make_generator_csr(ip, ix2, v, g.sizes, 1)[0])
+    assert err.status == stc.STC_EINVAL and "outside the block band" in str(err), str(err)
+    # a column out of range
+    ix2 = ix.copy()
+    ix2[5] = g.N + 3
+    err = _setup_error(stc.make_generator_csr(ip, ix2, v, g.sizes, 1)[0])
+    assert err.status == stc.STC_EINVAL and "outside 0.." in str(err), str(err)
+    # a column repeated within a row
+    ix2 = ix.copy()
+    ix2[ip[3] + 1] = ix2[ip[3]]
+    err = _setup_error(stc.make_generator_csr(ip, ix2, v, g.sizes, 1)[0])
+    assert err.status == stc.STC_EINVAL and "repeats column" in str(err), str(err)
+    # falling row pointers: setup rejects, the sparse footprint is 0
+    ip2 = ip.copy()
+    ip2[4] = ip2[3] - 1
+    gen = stc.make_generator_csr(ip2, ix, v, g.sizes, 1)[0]
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
+    err = _setup_error(gen)
+    assert err.status == stc.STC_EINVAL and "row pointers" in str(err), str(err)
+    # both inputs at once
+    gen, _k = stc.make_generator(g.blocks, g.sizes, 1)
+    gen.csr_rowptr, gen.csr_col, gen.csr_val = ip.ctypes.data, ix.ctypes.data, v.ctypes.data
+    assert stc.stc_footprint_bytes(gen, stc.make_options()) == 0
+    assert _setup_error(gen).status == stc.STC_EINVAL
+    # a negative rate still reads as "not a generator"
+    v2 = v.copy()
+    v2[np.flatnonzero(ix != np.repeat(np.arange(g.N), np.diff(ip)))[7]] = -0.5
+    err = _setup_error(stc.make_generator_csr(ip, ix, v2, g.sizes, 1)[0])
+    assert err.status == stc.STC_ENOTGEN, str(err)
+    # without diagonal entries the rows do not sum to 0 unless recomputed
+    ip3, ix3, v3 = g.to_csr(drop_diagonal=True)
+    err = _setup_error(stc.make_generator_csr(ip3, ix3, v3, g.sizes, 1)[0])
+    assert err.status == stc.STC_ENOTGEN and "sums to" in str(err), str(err)
+
+
+def test_sizes_checked_before_any_scan(lib):
+    """A level size above m is an argument error for the footprint and for
+    setup alike (the sparse footprint scans the blocks by level size)."""
+    g = synth.banded(8, 16, 3, b=2, density=0.3)
+    sizes = g.sizes.copy()
+    sizes[3] = 40
+    gen, _k = stc.make_generator(g.blocks, sizes, 2)
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
+    err = _setup_error(gen)
+    assert err.status == stc.STC_EINVAL and "sizes[3] = 40" in str(err), str(err)
