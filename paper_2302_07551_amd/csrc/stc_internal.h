@@ -31,7 +31,7 @@ struct DevState {
     int pad_;
 };
 
-enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2 };
+enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2, kDevTimeout = 3 };
 
 // One launch of a half-sweep (phase A or phase B) of one chain.
 struct SweepLaunch {
@@ -55,6 +55,45 @@ struct SweepLaunch {
     const double *prev_sum;
     const double *prev_diff;
     double tol;           // device change test applied when recording
+};
+
+// Launch variants of the sweep kernels (picked per chain by the autotuner):
+//   bit 0: 4 row groups per level instead of 8 (more levels per workgroup,
+//          longer per-thread row streams)
+//   bit 1: non-temporal block loads (streamed blocks bypass cache allocation,
+//          so the iterate vectors stay cached; best once the blocks exceed
+//          the last-level cache)
+//   bit 2: a burst of sweeps runs as one persistent cooperative launch whose
+//          blocks wait on their neighbours' progress flags instead of on
+//          kernel boundaries (same per-level arithmetic and reductions, so the
+//          same results bit for bit)
+constexpr int kVariants = 8;
+__host__ __device__ constexpr int variant_rg(int v) { return (v & 1) ? 4 : 8; }
+__host__ __device__ constexpr bool variant_nt(int v) { return (v & 2) != 0; }
+__host__ __device__ constexpr bool variant_flow(int v) { return (v & 4) != 0; }
+
+// A burst of n sweeps in one cooperative launch (launch variant bit 2).
+// Blocks 0..G-1 each own a contiguous range of the groups of both phases and
+// run every sweep of the burst, waiting only on the progress flags of the
+// two neighbouring blocks; block G is the folder, which reduces each sweep's
+// partials once all blocks have finished it and records the sweep.
+struct FlowLaunch {
+    const void *blk;
+    void *w[4];               // iterates W_s in rotation: buffer s % 4
+    double *part_sum;         // [2][nparts] partials, by sweep parity
+    double *part_diff;
+    int nparts;
+    DevState *st;
+    int L;
+    int parity_a;             // first level of phase A
+    int groups_a, groups_b;   // groups of each phase
+    int G;                    // streaming blocks (the folder is block G)
+    unsigned *flags;          // [2 G + 2]: phase A done [G], phase B done [G], folded,
+                              // abort
+    long long s0;             // sweeps s0+1 .. s0+n
+    int n;
+    double tol;
+    long long timeout_ticks;  // a wait longer than this (wall clock) aborts
 };
 
 // One sparse off-diagonal block (column-major ELL in slot quads): K slots per
@@ -117,6 +156,11 @@ hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase
                                   const SweepLaunch &a, const EllEntry *tab, const void *val,
                                   const unsigned char *idx, hipStream_t stream,
                                   LaunchTimer t = LaunchTimer());
+// Most blocks of a persistent sweep kernel that can be resident at once
+// (0 if the variant has no persistent form for these sizes).
+int flow_resident_blocks(int precision_bytes, int MP, int b, int variant);
+hipError_t launch_sweep_flow(int precision_bytes, int MP, int b, int variant, const FlowLaunch &f,
+                             hipStream_t stream);
 hipError_t launch_batch_query(DevState *const *states, int n, QueryRow *out, hipStream_t stream);
 hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff, int nslots,
                                  DevState *st, long long s, double tol, hipStream_t stream);

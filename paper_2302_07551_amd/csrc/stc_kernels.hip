@@ -66,20 +66,27 @@ struct Tile {
     static constexpr int PF = RPT < 8 ? RPT : 8;   // W_i rows prefetched per thread
 };
 
-// Launch variants of the sweep kernels (picked per chain by the autotuner):
-//   bit 0: 4 row groups per level instead of 8 (more levels per workgroup,
-//          longer per-thread row streams)
-//   bit 1: non-temporal block loads (streamed blocks bypass cache allocation,
-//          so the iterate vectors stay cached; best once the blocks exceed
-//          the last-level cache)
-constexpr int kVariants = 4;
-__host__ __device__ constexpr int variant_rg(int v) { return (v & 1) ? 4 : 8; }
-__host__ __device__ constexpr bool variant_nt(int v) { return (v & 2) != 0; }
+// Launch variants: see kVariants in stc_internal.h.
 
 template <typename VT, bool NT>
 __device__ inline VT stream_load(const VT *p) {
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
+}
+
+// Device-scope (cross-XCD coherent) relaxed loads and stores, for data that
+// another block of the same persistent launch wrote or will read.  COH =
+// false gives plain accesses (the producer and consumer are separated by a
+// kernel boundary).
+template <bool COH, typename T>
+__device__ inline T cload(const T *p) {
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH, typename T>
+__device__ inline void cstore(T *p, T v) {
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -99,6 +106,28 @@ __device__ inline double block_sum(double v, double *sh) {
 #pragma unroll
     for (int j = 0; j < kWG / 64; ++j) t += sh[j];
     return t;
+}
+
+// Two fixed-order workgroup sums with one pair of barriers (the same
+// arithmetic as two block_sum calls); sh holds 2 * kWG / 64 doubles.
+__device__ inline void block_sum2(double &a, double &b, double *sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[kWG / 64 + w] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWG / 64; ++j) {
+        ta += sh[j];
+        tb += sh[kWG / 64 + j];
+    }
+    a = ta;
+    b = tb;
 }
 
 __device__ inline double block_max(double v, double *sh) {
@@ -134,12 +163,13 @@ struct ChainView {
 };
 
 // Fixed-order sums of per-group partials (same value in every workgroup).
+template <bool COH = false>
 __device__ inline void partial_sums(const double *ps, const double *pd, int n, bool want_d,
                                     double *sh, double &S, double &D) {
     double s1 = 0.0, s2 = 0.0;
     for (int j = threadIdx.x; j < n; j += kWG) {
-        s1 += ps[j];
-        if (want_d) s2 += pd[j];
+        s1 += cload<COH>(ps + j);
+        if (want_d) s2 += cload<COH>(pd + j);
     }
     S = block_sum(s1, sh);
     D = want_d ? block_sum(s2, sh) : 0.0;
@@ -148,28 +178,36 @@ __device__ inline void partial_sums(const double *ps, const double *pd, int n, b
 // Record sweep s in the state: 1 / e^T W_s and the change of sweep s - 2
 // (measured during sweep s), then the device stopping test.  Thread 0 only;
 // nothing after a stop.
+template <bool COH = false>
 __device__ inline void record_sweep(DevState *st, long long s, double S, double D, double tol) {
-    if (st->stop_flag) return;
-    st->last_sweep = s;
+    if (cload<COH>(&st->stop_flag)) return;
+    cstore<COH>(&st->last_sweep, s);
     if (!(S > 0.0) || !isfinite(S)) {
-        st->status = kDevDegenerate;
-        st->stop_flag = 1;
-        st->stop_sweep = s - 1;
+        cstore<COH>(&st->status, (int)kDevDegenerate);
+        cstore<COH>(&st->stop_sweep, s - 1);
+        cstore<COH>(&st->stop_flag, 1);
         return;
     }
-    st->inv_sigma[s & kRingMask] = 1.0 / S;
+    cstore<COH>(&st->inv_sigma[s & kRingMask], 1.0 / S);
     if (s >= 3) {
-        st->diff[(s - 2) & kRingMask] = D;
+        cstore<COH>(&st->diff[(s - 2) & kRingMask], D);
         if (tol > 0.0 && D <= tol) {
-            st->stop_flag = 1;
-            st->stop_sweep = s - 2;
+            cstore<COH>(&st->stop_sweep, s - 2);
+            cstore<COH>(&st->stop_flag, 1);
         }
     }
 }
 
-template <typename T, int MP, int B, bool PHB, int RG, bool NT>
+constexpr bool kFlowStage = false;
+
+template <typename T, int MP, int B, bool PHB, int RG, bool NT, bool COH = false>
 __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, double inv_old,
-                                   T *red_base, T *rv_base, double *sh) {
+                                   T *red_base, T *rv_base, double *sh, T *nb_base = nullptr) {
+    // persistent launch: live is uniform over the block, and a sweep after
+    // the stop changes nothing, so it skips the block streams as well
+    if constexpr (COH) {
+        if (!live) return;
+    }
     using TL = Tile<T, MP, RG>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
@@ -178,7 +216,13 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     constexpr size_t BS = (size_t)MP * MP;
 
     const DevState *st = a.st;
-    const int tid = threadIdx.x;
+    int tid = threadIdx.x;
+    if constexpr (COH) {
+        // opaque to the optimiser: in the persistent loop the per-thread row
+        // offsets would otherwise be hoisted and held across every sweep,
+        // doubling the registers and halving the resident blocks
+        asm volatile("" : "+v"(tid));
+    }
     const int team = tid / TS, tt = tid - team * TS;
     const int c = tt % CT, g = tt / CT;
     T *red = red_base + team * (R * MP);     // [R][MP] of this team
@@ -197,22 +241,44 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     // and reads the old iterate at level ic instead (always written and
     // finite, so 0 * value stays 0; the fresh buffer may still hold stale or
     // uninitialised values there).
+    auto source = [&](int d, const T **v, T *vs) {
+        const int k = ic + d;
+        const bool in = (k >= 0) && (k < a.L);
+        const bool fresh = PHB && (d == 1 || d == -1);
+        *v = in ? (fresh ? (const T *)w_new : w_old) + (size_t)k * MP : w_old + (size_t)ic * MP;
+        *vs = in ? (fresh ? (T)1 : sc) : (T)0;
+    };
+    // persistent launch: the scaled neighbour segments are staged in LDS with
+    // device-scope loads first, so the block stream below is the same plain
+    // load sequence as in the per-phase launch (same products, same order)
+    T *nb = nb_base + team * (2 * B * MP);
+    if constexpr (COH && kFlowStage) {
+#pragma unroll
+        for (int d = -B; d <= B; ++d) {
+            if (d == 0) continue;
+            const T *v;
+            T vs;
+            source(d, &v, &vs);
+            T *dst = nb + (d < 0 ? d + B : d + B - 1) * MP;
+            for (int e = tt; e < MP; e += TS) dst[e] = cload<true>(v + e) * vs;
+        }
+        __syncthreads();
+    }
     VT acc = (VT)(T)0;
 #pragma unroll
     for (int d = -B; d <= B; ++d) {
         if (d == 0) continue;
-        const int k = ic + d;
-        const bool in = (k >= 0) && (k < a.L);
-        const bool fresh = PHB && (d == 1 || d == -1);
-        const T *v = in ? (fresh ? (const T *)w_new : w_old) + (size_t)k * MP
-                        : w_old + (size_t)ic * MP;
-        const T vs = in ? (fresh ? (T)1 : sc) : (T)0;
+        const T *v;
+        T vs;
+        source(d, &v, &vs);
+        const T *nbd = nb + (d < 0 ? d + B : d + B - 1) * MP;
         const T *gb = base + (size_t)(d + B) * BS + c * VEC;
 #pragma unroll
         for (int qq = 0; qq < RPT; ++qq) {
             const int row = g + R * qq;
             const VT blkv = stream_load<VT, NT>((const VT *)(gb + (size_t)row * MP));
-            acc += blkv * (v[row] * vs);
+            if constexpr (COH && kFlowStage) acc += blkv * nbd[row];
+            else acc += blkv * (cload<COH>(v + row) * vs);
         }
     }
     // rows of W_i fetched before the reduction, so they stream meanwhile
@@ -251,21 +317,21 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
         T z = 0;
 #pragma unroll
         for (int gg = 0; gg < R; ++gg) z += red[gg * MP + tt];
-        w_new[(size_t)i * MP + tt] = z;
+        cstore<COH>(w_new + (size_t)i * MP + tt, z);
         zs = (double)z;
         if (a.s >= 3) {
             // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
-            const double i2 = st->inv_sigma[(a.s - 2) & kRingMask];
-            const double i3 = st->inv_sigma[(a.s - 3) & kRingMask];
-            dd = fabs((double)a.w_d1[(size_t)i * MP + tt] * i2 -
-                      (double)a.w_d2[(size_t)i * MP + tt] * i3);
+            const double i2 = cload<COH>(&st->inv_sigma[(a.s - 2) & kRingMask]);
+            const double i3 = cload<COH>(&st->inv_sigma[(a.s - 3) & kRingMask]);
+            dd = fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + tt) * i2 -
+                      (double)cload<COH>(a.w_d2 + (size_t)i * MP + tt) * i3);
         }
     }
-    const double S = block_sum(zs, sh);
-    const double D = block_sum(dd, sh);
+    double S = zs, D = dd;
+    block_sum2(S, D, sh);
     if (live && tid == 0) {
-        a.part_sum[a.slot0 + q] = S;
-        a.part_diff[a.slot0 + q] = D;
+        cstore<COH>(a.part_sum + a.slot0 + q, S);
+        cstore<COH>(a.part_diff + a.slot0 + q, D);
     }
     __syncthreads();   // the LDS may be reused by the next group
 }
@@ -301,7 +367,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
         fold_previous(a, sh);
         return;
@@ -310,6 +376,253 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     const bool live = a.st->stop_flag == 0;
     const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
     sweep_group<T, MP, B, PHB, RG, NT>(view_of<T>(a), blockIdx.x, live, kappa, red, rv, sh);
+}
+
+// ---------------------------------------------------------------------------
+// a burst of sweeps in one persistent cooperative launch
+// ---------------------------------------------------------------------------
+// The dependencies of a sweep are local: a level of phase A reads the levels
+// next to it from the previous sweep, a level of phase B the fresh phase-A
+// levels next to it.  Block g owns a contiguous range of the groups of each
+// phase and publishes "phase A (or B) of sweep j done" in its flags; before
+// the groups that read levels of another block it waits for that block's
+// flag, and it runs the groups that only read its own levels first.  An
+// extra block, the folder, reduces a sweep's partials once every block has
+// published it and records the sweep; the scale 1 / e^T W_{s-2} that sweep s
+// needs is therefore recorded a full sweep before it is read.  Every wait is bounded by wall
+// clock time: past it the launch is marked aborted (status kDevTimeout) and
+// every block returns.  Data that crosses blocks is read and written with
+// device-scope relaxed accesses (coherent across the XCDs' L2 caches), and a
+// block's stores are complete before its flag is set.
+
+// Upper bound on the polls of one wait (each poll sleeps about 128 clocks,
+// so this is several seconds: past the wall clock bound).
+constexpr long long kFlowMaxSpins = 1ll << 26;
+
+// Thread 0 waits until *p >= target; false if the launch aborted.
+__device__ inline bool flow_wait(const unsigned *p, unsigned target, const FlowLaunch &f,
+                                 int *sh_ok) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (cload<true>(p) < target) {
+            unsigned *abort_flag = f.flags + 2 * f.G + 1;
+            const long long t0 = (long long)wall_clock64();
+            long long spins = 0;
+            while (cload<true>(p) < target) {
+                if (cload<true>(abort_flag)) {
+                    ok = 0;
+                    break;
+                }
+                // wall clock bound, and a count bound in case the clock stalls
+                if ((long long)wall_clock64() - t0 > f.timeout_ticks || ++spins > kFlowMaxSpins) {
+                    cstore<true>(&f.st->status, (int)kDevTimeout);
+                    cstore<true>(&f.st->stop_flag, 1);
+                    cstore<true>(abort_flag, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        *sh_ok = ok;
+    }
+    __syncthreads();
+    const bool ok = *sh_ok != 0;
+    __syncthreads();
+    return ok;
+}
+
+// Every wave's stores are complete, then thread 0 sets the flag.
+__device__ inline void flow_publish(unsigned *flag, unsigned v) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) cstore<true>(flag, v);
+}
+
+// Block of group q of a phase with n groups split over G blocks
+// (block g owns groups [g n / G, (g + 1) n / G)).
+__device__ inline int flow_owner(int q, int n, int G) {
+    return (int)(((long long)(q + 1) * G - 1) / n);
+}
+
+// The folder (block G): record each sweep once every block has finished it.
+// It polls the blocks' flags; no atomics (one counter hit by every block of
+// every sweep serialises at the memory side).
+__device__ inline void flow_fold(const FlowLaunch &f, double *sh, int *sh_ok) {
+    const unsigned *fb = f.flags + f.G;
+    unsigned *folded = f.flags + 2 * f.G;
+    const unsigned *abort_flag = f.flags + 2 * f.G + 1;
+    const int nslots = f.groups_a + f.groups_b;
+    for (int j = 1; j <= f.n; ++j) {
+        const long long s = f.s0 + j;
+        long long t0 = 0;
+        for (long long spin = 0;; ++spin) {
+            int mine = 1;
+            for (int g = threadIdx.x; g < f.G; g += kWG)
+                if (cload<true>(fb + g) < (unsigned)j) {
+                    mine = 0;
+                    break;
+                }
+            if (__syncthreads_and(mine)) break;
+            if (threadIdx.x == 0) {
+                int ok = 1;
+                if (spin == 0) t0 = (long long)wall_clock64();
+                if (cload<true>(abort_flag)) {
+                    ok = 0;
+                } else if ((long long)wall_clock64() - t0 > f.timeout_ticks ||
+                           spin > kFlowMaxSpins) {
+                    cstore<true>(&f.st->status, (int)kDevTimeout);
+                    cstore<true>(&f.st->stop_flag, 1);
+                    cstore<true>(f.flags + 2 * f.G + 1, 1u);
+                    ok = 0;
+                }
+                *sh_ok = ok;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __syncthreads();
+            const bool ok = *sh_ok != 0;
+            __syncthreads();
+            if (!ok) return;
+        }
+        double S, D;
+        partial_sums<true>(f.part_sum + (s & 1) * f.nparts, f.part_diff + (s & 1) * f.nparts,
+                           nslots, true, sh, S, D);
+        if (threadIdx.x == 0) {
+            record_sweep<true>(f.st, s, S, D, f.tol);
+            __builtin_amdgcn_s_waitcnt(0);
+            cstore<true>(folded, (unsigned)j);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ inline ChainView<T> flow_view(const FlowLaunch &f, long long s, int parity,
+                                         int slot0) {
+    ChainView<T> v;
+    v.blk = (const T *)f.blk;
+    v.w_old = (const T *)f.w[(s - 1) & 3];
+    v.w_d1 = (const T *)f.w[(s - 2) & 3];
+    v.w_d2 = (const T *)f.w[(s - 3) & 3];
+    v.w_new = (T *)f.w[s & 3];
+    v.part_sum = f.part_sum + (s & 1) * f.nparts;
+    v.part_diff = f.part_diff + (s & 1) * f.nparts;
+    v.st = f.st;
+    v.L = f.L;
+    v.parity = parity;
+    v.slot0 = slot0;
+    v.s = s;
+    return v;
+}
+
+// One phase of sweep j for block g: the groups whose neighbour levels are all
+// this block's first, then (after waiting for the other blocks' flags at
+// `need`) the rest.  PHB: the neighbours of a level are phase-A levels of
+// this sweep (flag fa >= j); else phase-B levels of the previous sweep
+// (flag fb >= j - 1, which also covers that block's phase A).
+template <typename T, int MP, int B, bool PHB, int RG, bool NT>
+__device__ inline bool flow_phase(const FlowLaunch &f, const ChainView<T> &v, int g, int j,
+                                  bool live, double kappa, T *red, T *rv, T *nb, double *sh,
+                                  int *sh_ok) {
+    constexpr int LPW = Tile<T, MP, RG>::LPW;
+    const int G = f.G;
+    const int par = v.parity, opar = 1 - par;
+    const int n = PHB ? f.groups_b : f.groups_a;
+    const int on = PHB ? f.groups_a : f.groups_b;   // groups of the other phase
+    const int lo = (int)((long long)g * n / G), hi = (int)((long long)(g + 1) * n / G);
+    const unsigned *flag = PHB ? f.flags : f.flags + G;
+    const unsigned target = PHB ? (unsigned)j : (unsigned)(j - 1);
+    // owners of the levels within B of group q's levels, other than g
+    auto owner_of_level = [&](int l, int p, int np) {
+        return flow_owner(((l - p) >> 1) / LPW, np, G);
+    };
+    auto external = [&](int q, int *wl, int *wr) {
+        const int first = par + 2 * q * LPW;
+        const int last = min(par + 2 * (q * LPW + LPW - 1), (f.L - 1 - par) / 2 * 2 + par);
+        int l = g, r = g;
+        for (int d = 1; d <= B; ++d) {
+            const int pl = first - d, pr = last + d;
+            const int pp = (d & 1) ? opar : par;
+            const int np = (d & 1) ? on : n;
+            if (pl >= 0) l = min(l, owner_of_level(pl, pp, np));
+            if (pr < f.L) r = max(r, owner_of_level(pr, pp, np));
+        }
+        *wl = l;
+        *wr = r;
+        return l != g || r != g;
+    };
+    // interior groups first (lo+1 .. hi-2), then the two end groups (the
+    // order only matters for overlap: the end groups are the ones that
+    // usually read another block's levels); before the first group that
+    // does, wait for every block that any group of the range reads from
+    const int cnt = hi - lo;
+    bool waited = target == 0;
+    for (int k = 0; k < cnt; ++k) {
+        const int q = cnt <= 2 ? lo + k : (k < cnt - 2 ? lo + 1 + k : (k == cnt - 2 ? lo : hi - 1));
+        int wl, wr;
+        if (!waited && external(q, &wl, &wr)) {
+            int wmin = g, wmax = g;
+            for (int qq = lo; qq < hi; ++qq) {
+                int l2, r2;
+                external(qq, &l2, &r2);
+                wmin = min(wmin, l2);
+                wmax = max(wmax, r2);
+            }
+            for (int w = wmin; w <= wmax; ++w)
+                if (w != g && !flow_wait(flag + w, target, f, sh_ok)) return false;
+            waited = true;
+        }
+        sweep_group<T, MP, B, PHB, RG, NT, true>(v, q, live, kappa, red, rv, sh, nb);
+    }
+    return true;
+}
+
+template <typename T, int MP, int B, int RG, bool NT>
+__global__ __launch_bounds__(kWG) void k_sweep_flow(FlowLaunch f) {
+    using TL = Tile<T, MP, RG>;
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
+    __shared__ T nb[TL::LPW * 2 * B * MP];
+    __shared__ double sh[2 * kWG / 64];
+    __shared__ int sh_ok, sh_live;
+    __shared__ double sh_kappa;
+    if ((int)blockIdx.x == f.G) {
+        flow_fold(f, sh, &sh_ok);
+        return;
+    }
+    // logical block: blocks are handed to the 8 XCDs in turn, so number
+    // them XCD by XCD and neighbouring ranges mostly share an XCD's L2
+    const int b = blockIdx.x, G = f.G, per = G / 8, rem = G % 8, x = b % 8;
+    const int g = x * per + min(x, rem) + b / 8;
+    unsigned *fa = f.flags, *fb = f.flags + f.G;
+    const unsigned *folded = f.flags + 2 * f.G;
+    const int pA = f.parity_a, pB = 1 - pA;
+    for (int j = 1; j <= f.n; ++j) {
+        const long long s = f.s0 + j;
+        // the scale of sweep s (1 / e^T W_{s-2}) is recorded by the folder
+        if (j >= 3 && !flow_wait(folded, (unsigned)(j - 2), f, &sh_ok)) return;
+        if (threadIdx.x == 0) {
+            sh_live = cload<true>(&f.st->stop_flag) == 0;
+            sh_kappa = cload<true>(&f.st->inv_sigma[(s - 2) & kRingMask]);
+        }
+        __syncthreads();
+        const bool live = sh_live != 0;
+        const double kappa = sh_kappa;
+        __syncthreads();
+        if (!flow_phase<T, MP, B, false, RG, NT>(f, flow_view<T>(f, s, pA, 0), g, j, live, kappa,
+                                                 red, rv, nb, sh, &sh_ok))
+            return;
+        flow_publish(fa + g, (unsigned)j);
+        if (!flow_phase<T, MP, B, true, RG, NT>(f, flow_view<T>(f, s, pB, f.groups_a), g, j, live,
+                                                kappa, red, rv, nb, sh, &sh_ok))
+            return;
+        flow_publish(fb + g, (unsigned)j);
+    }
+}
+
+__global__ void k_flow_reset(unsigned *flags, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        flags[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +762,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ T src[TL::LPW * 2 * B * MP];
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
         fold_previous(a, sh);
         return;
@@ -472,7 +785,7 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
     constexpr int VEC = 16 / (int)sizeof(T);
     __shared__ T red[kWG * VEC];
     __shared__ T rv[kWG * VEC];
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     const int n = *nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const WorkItem w = items[it];
@@ -517,13 +830,13 @@ __device__ inline void finalize_chain(const double *part_sum, const double *part
 __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
                                                          const double *part_diff, int nslots,
                                                          DevState *st, long long s, double tol) {
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     finalize_chain(part_sum, part_diff, nslots, st, s, tol, sh);
 }
 
 __global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
                                                          const int *nchains) {
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     if ((int)blockIdx.x >= *nchains) return;
     const ChainDesc &d = chains[blockIdx.x];
     DevState *st = d.st;
@@ -567,7 +880,7 @@ enum ReduceMode { kReduceResidual = 0, kReduceDiff = 1, kReduceLoad = 2 };
 
 __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int mode,
                                                  DevState *st, long long slot, double tol) {
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     const int stride = (mode == kReduceLoad) ? 2 : 1;
     double t = 0.0, b = 0.0;
     for (int j = threadIdx.x; j < n; j += kWG) {
@@ -617,7 +930,7 @@ __global__ __launch_bounds__(kWG) void k_residual(const double *blk, const doubl
                   LPW = TL::LPW;
     constexpr size_t BS = (size_t)MP * MP;
     __shared__ double red[LPW][R][MP];
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
 
     const int tid = threadIdx.x;
     const int team = tid / TS, tt = tid - team * TS;
@@ -668,7 +981,7 @@ __global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, const Dev
                                                long long k, int L, int parity_a, int groups_a,
                                                double *part) {
     using TL = Tile<T, MP, RG>;
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     const int tid = threadIdx.x;
     const int team = tid / TL::TS, tt = tid - team * TL::TS;
     const bool in_a = (int)blockIdx.x < groups_a;
@@ -693,7 +1006,7 @@ template <typename T>
 __global__ __launch_bounds__(kWG) void k_load(const double *x, const long long *off,
                                                const int *sizes, int L, int MP, T *w,
                                                double *part, int slot) {
-    __shared__ double sh[kWG / 64];
+    __shared__ double sh[2 * kWG / 64];
     const size_t n = (size_t)L * MP;
     double s = 0.0, bad = 0.0;
     for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG) {
@@ -1005,7 +1318,7 @@ static hipError_t sweep_v(bool phase_b, int variant, const SweepLaunch &a, hipSt
 template <typename T, int MP, int B>
 static hipError_t sweep_mpb(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s,
                             LaunchTimer t) {
-    switch (variant) {
+    switch (variant & 3) {   // bit 2 (persistent bursts) has the same phases
         case 0: return sweep_v<T, MP, B, variant_rg(0), variant_nt(0)>(phase_b, 0, a, s, t);
         case 1: return sweep_v<T, MP, B, variant_rg(1), variant_nt(1)>(phase_b, 1, a, s, t);
         case 2: return sweep_v<T, MP, B, variant_rg(2), variant_nt(2)>(phase_b, 2, a, s, t);
@@ -1035,6 +1348,87 @@ hipError_t launch_sweep_phase(int precision_bytes, int MP, int b, bool phase_b, 
                       : sweep_b<double, 2>(MP, phase_b, variant, a, stream, t);
     return b == 1 ? sweep_b<float, 1>(MP, phase_b, variant, a, stream, t)
                   : sweep_b<float, 2>(MP, phase_b, variant, a, stream, t);
+}
+
+// persistent launch: one cooperative launch of G + 1 blocks per burst
+template <typename T, int MP, int B, int RG, bool NT>
+static int flow_resident_v() {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_flow<T, MP, B, RG, NT>,
+                                                     kWG, 0) != hipSuccess)
+        return 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+template <typename T, int MP, int B, int RG, bool NT>
+static hipError_t flow_v(const FlowLaunch &f, hipStream_t s) {
+    const int nflags = 2 * f.G + 2;
+    hipLaunchKernelGGL(k_flow_reset, dim3((nflags + kWG - 1) / kWG), dim3(kWG), 0, s, f.flags,
+                       nflags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    FlowLaunch arg = f;
+    void *args[] = {(void *)&arg};
+    return hipLaunchCooperativeKernel((const void *)k_sweep_flow<T, MP, B, RG, NT>,
+                                      dim3(f.G + 1), dim3(kWG), args, 0, s);
+}
+
+template <typename T, int MP, int B>
+static int flow_mpb(bool launch, int variant, const FlowLaunch *f, hipStream_t s,
+                    hipError_t *err) {
+    switch (variant & 3) {
+        case 0:
+            if (launch) *err = flow_v<T, MP, B, variant_rg(0), variant_nt(0)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(0), variant_nt(0)>();
+        case 1:
+            if (launch) *err = flow_v<T, MP, B, variant_rg(1), variant_nt(1)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(1), variant_nt(1)>();
+        case 2:
+            if (launch) *err = flow_v<T, MP, B, variant_rg(2), variant_nt(2)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(2), variant_nt(2)>();
+        default:
+            if (launch) *err = flow_v<T, MP, B, variant_rg(3), variant_nt(3)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(3), variant_nt(3)>();
+    }
+}
+
+template <typename T, int B>
+static int flow_b(int MP, bool launch, int variant, const FlowLaunch *f, hipStream_t s,
+                  hipError_t *err) {
+    switch (MP) {
+        case 8: return flow_mpb<T, 8, B>(launch, variant, f, s, err);
+        case 16: return flow_mpb<T, 16, B>(launch, variant, f, s, err);
+        case 32: return flow_mpb<T, 32, B>(launch, variant, f, s, err);
+        case 64: return flow_mpb<T, 64, B>(launch, variant, f, s, err);
+        case 128: return flow_mpb<T, 128, B>(launch, variant, f, s, err);
+    }
+    *err = hipErrorInvalidValue;
+    return 0;
+}
+
+static int flow_dispatch(int precision_bytes, int MP, int b, bool launch, int variant,
+                         const FlowLaunch *f, hipStream_t s, hipError_t *err) {
+    if (precision_bytes == 8)
+        return b == 1 ? flow_b<double, 1>(MP, launch, variant, f, s, err)
+                      : flow_b<double, 2>(MP, launch, variant, f, s, err);
+    return b == 1 ? flow_b<float, 1>(MP, launch, variant, f, s, err)
+                  : flow_b<float, 2>(MP, launch, variant, f, s, err);
+}
+
+int flow_resident_blocks(int precision_bytes, int MP, int b, int variant) {
+    hipError_t e = hipSuccess;
+    return flow_dispatch(precision_bytes, MP, b, false, variant, nullptr, nullptr, &e);
+}
+
+hipError_t launch_sweep_flow(int precision_bytes, int MP, int b, int variant, const FlowLaunch &f,
+                             hipStream_t stream) {
+    if (f.G < 1 || f.n < 1) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    flow_dispatch(precision_bytes, MP, b, true, variant, &f, stream, &e);
+    return e;
 }
 
 template <typename T, int MP, int B>

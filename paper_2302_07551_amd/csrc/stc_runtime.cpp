@@ -88,7 +88,7 @@ struct Layout {
     size_t ell_tab = 0, ell_v64 = 0, ell_v32 = 0, ell_idx = 0;
     long long ell_slots = 0;    // sum over blocks of K * MP
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
-    size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0;
+    size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
     size_t nparts = 0, naux = 0;
     size_t total = 0;
 };
@@ -292,6 +292,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.off = take((L + 1) * 8);
     l.sizes = take(L * 4);
     l.state = take(sizeof(DevState));
+    l.flow = take((L + 8) * sizeof(unsigned));   // progress flags of a persistent burst
     l.total = at;
     *lay = l;
     return true;
@@ -323,6 +324,9 @@ struct stc_handle {
     float *ell_v32 = nullptr;
     unsigned char *ell_idx = nullptr;
     std::vector<int> ell_K;    // [L][NB] longest column per block
+    unsigned *flow_flags = nullptr;   // progress flags of a persistent burst
+    int flow_res[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};   // resident blocks, cached
+    long long wall_hz = 100000000;    // device wall clock rate
     // iteration state
     long long s = 0;        // sweeps done since the last load
     bool stage32 = false;   // current iterate lives in the FP32 rotation
@@ -419,10 +423,10 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTime
 // next sweep's phase B would have done) and the changes of sweeps n-1 and n,
 // which the lagged partials have not measured yet, with the device stopping
 // test in sweep order.  After it the state is complete up to sweep n.
-hipError_t end_burst(stc_handle *h, long long n, double tol) {
+hipError_t end_burst(stc_handle *h, long long n, double tol, bool recorded = false) {
     if (n < 1) return hipSuccess;
     hipError_t e = hipSuccess;
-    if (folds(h))
+    if (folds(h) && !recorded)
         e = launch_finalize_sweep(h->part_sum + (n & 1) * h->lay.nparts,
                                   h->part_diff + (n & 1) * h->lay.nparts, sweep_slots(h), h->st,
                                   n, tol, h->stream);
@@ -437,8 +441,61 @@ hipError_t end_burst(stc_handle *h, long long n, double tol) {
     return e;
 }
 
+// Streaming blocks of a persistent burst for the handle's current stage: one
+// block per group at most, every block owning at least one group of each
+// phase, all of them and the folder resident at once; 0 when the stage has
+// no persistent form.
+int flow_blocks(stc_handle *h) {
+    const bool f32 = h->stage32;
+    const int v = h->variant[f32 ? 1 : 0];
+    if (h->sparse || !variant_flow(v)) return 0;
+    int &res = h->flow_res[f32 ? 1 : 0][v & 3];
+    if (res < 0) res = flow_resident_blocks(f32 ? 4 : 8, h->MP, h->b, v);
+    const int bytes = f32 ? 4 : 8;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    const int gA = phase_groups(bytes, h->MP, h->L, pA, v);
+    const int gB = phase_groups(bytes, h->MP, h->L, 1 - pA, v);
+    // as many blocks as fit, with the groups spread evenly (k or k-1 each)
+    const int n = std::min(gA, gB);
+    if (res < 2) return 0;
+    const int k = (n + res - 2) / (res - 1);
+    const int G = (n + k - 1) / k;
+    return G >= 1 ? G : 0;
+}
+
+// Sweeps s0+1 .. s0+n as one persistent launch (it records them all).
+hipError_t enqueue_flow(stc_handle *h, long long s0, long long n, double tol) {
+    const bool f32 = h->stage32;
+    const int v = h->variant[f32 ? 1 : 0];
+    const int bytes = f32 ? 4 : 8;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    FlowLaunch f;
+    f.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
+    for (int k = 0; k < 4; ++k) f.w[k] = wbuf(h, f32, k);
+    f.part_sum = h->part_sum;
+    f.part_diff = h->part_diff;
+    f.nparts = (int)h->lay.nparts;
+    f.st = h->st;
+    f.L = h->L;
+    f.parity_a = pA;
+    f.groups_a = phase_groups(bytes, h->MP, h->L, pA, v);
+    f.groups_b = phase_groups(bytes, h->MP, h->L, 1 - pA, v);
+    f.G = flow_blocks(h);
+    f.flags = h->flow_flags;
+    f.s0 = s0;
+    f.n = (int)n;
+    f.tol = tol;
+    f.timeout_ticks = 2 * h->wall_hz;   // no legitimate wait comes near two seconds
+    return launch_sweep_flow(bytes, h->MP, h->b, v, f, h->stream);
+}
+
 // Enqueue sweeps s0+1 .. s0+n as one burst, state recorded at the end.
 stc_status run_burst(stc_handle *h, long long s0, long long n, double tol) {
+    if (n >= 1 && n <= (1ll << 30) && flow_blocks(h) > 0) {
+        HIP_TRY(enqueue_flow(h, s0, n, tol));
+        HIP_TRY(end_burst(h, s0 + n, tol, true));
+        return STC_OK;
+    }
     for (long long j = 1; j <= n; ++j) HIP_TRY(enqueue_sweep(h, s0 + j, tol, nullptr, j == 1));
     HIP_TRY(end_burst(h, s0 + n, tol));
     return STC_OK;
@@ -469,6 +526,8 @@ stc_status read_state(stc_handle *h, HostState *hs) {
                            reinterpret_cast<char *>(h->st) + off, sizeof(DevState) - off,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    if (tmp.status == kDevTimeout)
+        return fail(STC_EDEVICE, "a persistent sweep launch gave up waiting for another block");
     hs->stop_flag = tmp.stop_flag;
     hs->status = tmp.status;
     hs->stop_sweep = tmp.stop_sweep;
@@ -638,6 +697,13 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     h->off = (long long *)(h->base + lay.off);
     h->sizes_d = (int *)(h->base + lay.sizes);
     h->st = (DevState *)(h->base + lay.state);
+    h->flow_flags = (unsigned *)(h->base + lay.flow);
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess &&
+            khz > 0)
+            h->wall_hz = (long long)khz * 1000;
+    }
     h->sparse = lay.sparse;
     if (lay.sparse) {
         h->ell_tab = (EllEntry *)(h->base + lay.ell_tab);
@@ -862,6 +928,31 @@ stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs) {
 stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, double *ms_b,
                               double *ms_fin, double *ms_sweep) {
     if (!h || nsweeps < 1) return fail(STC_EINVAL, "bad argument");
+    if (flow_blocks(h) > 0) {
+        // one persistent launch for the burst: its time is split evenly
+        // between the two phases of each sweep
+        hipEvent_t e[3];
+        for (auto &x : e) HIP_TRY(hipEventCreate(&x));
+        const long long s0 = h->s;
+        hipError_t err = hipEventRecord(e[0], h->stream);
+        if (err == hipSuccess) err = enqueue_flow(h, s0, nsweeps, 0.0);
+        if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
+        if (err == hipSuccess) err = end_burst(h, s0 + nsweeps, 0.0, true);
+        if (err == hipSuccess) err = hipEventRecord(e[2], h->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e[2]);
+        float k = 0.f, fl = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&k, e[0], e[1]);
+        if (err == hipSuccess) err = hipEventElapsedTime(&fl, e[1], e[2]);
+        for (auto &x : e) (void)hipEventDestroy(x);
+        if (err != hipSuccess) return fail(STC_EDEVICE, "profiled sweeps: %s", hipGetErrorString(err));
+        h->s = s0 + nsweeps;
+        if (h->stage32) h->iters32 += nsweeps;
+        if (ms_a) *ms_a = k / 2.0 / nsweeps;
+        if (ms_b) *ms_b = k / 2.0 / nsweeps;
+        if (ms_fin) *ms_fin = (double)fl / nsweeps;
+        if (ms_sweep) *ms_sweep = ((double)k + fl) / nsweeps;
+        return STC_OK;
+    }
     const bool fold = folds(h);
     // per sweep: start and stop of each phase's dispatch, and around the
     // finalize launch when it is not folded; then the burst's bounds and its
@@ -956,14 +1047,17 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
         for (int v = 0; v < nvs && rc == STC_OK; ++v) {
             if ((rc = load_vector_stage(h, nullptr, STC_MEM_HOST, f32)) != STC_OK) break;
             if (!h->sparse) h->variant[stage] = v;
-            hipError_t e = hipSuccess;
-            for (long long j = 1; j <= 3 && e == hipSuccess; ++j)
-                e = enqueue_sweep(h, j, 0.0, nullptr, j == 1);
-            if (e == hipSuccess) e = end_burst(h, 3, 0.0);
-            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            for (long long j = 4; j < 4 + trial_sweeps && e == hipSuccess; ++j)
-                e = enqueue_sweep(h, j, 0.0, nullptr, j == 4);
-            if (e == hipSuccess) e = end_burst(h, 3 + trial_sweeps, 0.0);
+            if (variant_flow(v) && flow_blocks(h) == 0) continue;   // no persistent form here
+            // 3 warm-up sweeps, then the timed burst, each as the solver runs them
+            if ((rc = run_burst(h, 0, 3, 0.0)) != STC_OK) break;
+            hipError_t e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) {
+                stc_status r2 = run_burst(h, 3, trial_sweeps, 0.0);
+                if (r2 != STC_OK) {
+                    rc = r2;
+                    break;
+                }
+            }
             if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -972,6 +1066,8 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
                 rc = fail(STC_EDEVICE, "autotune: %s", hipGetErrorString(e));
                 break;
             }
+            HostState hs;
+            if ((rc = read_state(h, &hs)) != STC_OK) break;   // a timed-out wait is an error
             const double per = (double)ms / trial_sweeps;
             if (per < best) {
                 best = per;
