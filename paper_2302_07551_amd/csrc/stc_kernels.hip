@@ -198,11 +198,9 @@ __device__ inline void record_sweep(DevState *st, long long s, double S, double 
     }
 }
 
-constexpr bool kFlowStage = false;
-
 template <typename T, int MP, int B, bool PHB, int RG, bool NT, bool COH = false>
 __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, double inv_old,
-                                   T *red_base, T *rv_base, double *sh, T *nb_base = nullptr) {
+                                   T *red_base, T *rv_base, double *sh) {
     // persistent launch: live is uniform over the block, and a sweep after
     // the stop changes nothing, so it skips the block streams as well
     if constexpr (COH) {
@@ -241,44 +239,24 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     // and reads the old iterate at level ic instead (always written and
     // finite, so 0 * value stays 0; the fresh buffer may still hold stale or
     // uninitialised values there).
-    auto source = [&](int d, const T **v, T *vs) {
-        const int k = ic + d;
-        const bool in = (k >= 0) && (k < a.L);
-        const bool fresh = PHB && (d == 1 || d == -1);
-        *v = in ? (fresh ? (const T *)w_new : w_old) + (size_t)k * MP : w_old + (size_t)ic * MP;
-        *vs = in ? (fresh ? (T)1 : sc) : (T)0;
-    };
-    // persistent launch: the scaled neighbour segments are staged in LDS with
-    // device-scope loads first, so the block stream below is the same plain
-    // load sequence as in the per-phase launch (same products, same order)
-    T *nb = nb_base + team * (2 * B * MP);
-    if constexpr (COH && kFlowStage) {
-#pragma unroll
-        for (int d = -B; d <= B; ++d) {
-            if (d == 0) continue;
-            const T *v;
-            T vs;
-            source(d, &v, &vs);
-            T *dst = nb + (d < 0 ? d + B : d + B - 1) * MP;
-            for (int e = tt; e < MP; e += TS) dst[e] = cload<true>(v + e) * vs;
-        }
-        __syncthreads();
-    }
+    // (persistent launch: the neighbour values are device-scope loads, since
+    // another block of the same launch may have written them)
     VT acc = (VT)(T)0;
 #pragma unroll
     for (int d = -B; d <= B; ++d) {
         if (d == 0) continue;
-        const T *v;
-        T vs;
-        source(d, &v, &vs);
-        const T *nbd = nb + (d < 0 ? d + B : d + B - 1) * MP;
+        const int k = ic + d;
+        const bool in = (k >= 0) && (k < a.L);
+        const bool fresh = PHB && (d == 1 || d == -1);
+        const T *v = in ? (fresh ? (const T *)w_new : w_old) + (size_t)k * MP
+                        : w_old + (size_t)ic * MP;
+        const T vs = in ? (fresh ? (T)1 : sc) : (T)0;
         const T *gb = base + (size_t)(d + B) * BS + c * VEC;
 #pragma unroll
         for (int qq = 0; qq < RPT; ++qq) {
             const int row = g + R * qq;
             const VT blkv = stream_load<VT, NT>((const VT *)(gb + (size_t)row * MP));
-            if constexpr (COH && kFlowStage) acc += blkv * nbd[row];
-            else acc += blkv * (cload<COH>(v + row) * vs);
+            acc += blkv * (cload<COH>(v + row) * vs);
         }
     }
     // rows of W_i fetched before the reduction, so they stream meanwhile
@@ -522,7 +500,7 @@ __device__ inline ChainView<T> flow_view(const FlowLaunch &f, long long s, int p
 // (flag fb >= j - 1, which also covers that block's phase A).
 template <typename T, int MP, int B, bool PHB, int RG, bool NT>
 __device__ inline bool flow_phase(const FlowLaunch &f, const ChainView<T> &v, int g, int j,
-                                  bool live, double kappa, T *red, T *rv, T *nb, double *sh,
+                                  bool live, double kappa, T *red, T *rv, double *sh,
                                   int *sh_ok) {
     constexpr int LPW = Tile<T, MP, RG>::LPW;
     const int G = f.G;
@@ -572,7 +550,7 @@ __device__ inline bool flow_phase(const FlowLaunch &f, const ChainView<T> &v, in
                 if (w != g && !flow_wait(flag + w, target, f, sh_ok)) return false;
             waited = true;
         }
-        sweep_group<T, MP, B, PHB, RG, NT, true>(v, q, live, kappa, red, rv, sh, nb);
+        sweep_group<T, MP, B, PHB, RG, NT, true>(v, q, live, kappa, red, rv, sh);
     }
     return true;
 }
@@ -582,7 +560,6 @@ __global__ __launch_bounds__(kWG) void k_sweep_flow(FlowLaunch f) {
     using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
-    __shared__ T nb[TL::LPW * 2 * B * MP];
     __shared__ double sh[2 * kWG / 64];
     __shared__ int sh_ok, sh_live;
     __shared__ double sh_kappa;
@@ -610,11 +587,11 @@ __global__ __launch_bounds__(kWG) void k_sweep_flow(FlowLaunch f) {
         const double kappa = sh_kappa;
         __syncthreads();
         if (!flow_phase<T, MP, B, false, RG, NT>(f, flow_view<T>(f, s, pA, 0), g, j, live, kappa,
-                                                 red, rv, nb, sh, &sh_ok))
+                                                 red, rv, sh, &sh_ok))
             return;
         flow_publish(fa + g, (unsigned)j);
         if (!flow_phase<T, MP, B, true, RG, NT>(f, flow_view<T>(f, s, pB, f.groups_a), g, j, live,
-                                                kappa, red, rv, nb, sh, &sh_ok))
+                                                kappa, red, rv, sh, &sh_ok))
             return;
         flow_publish(fb + g, (unsigned)j);
     }
