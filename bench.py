@@ -26,6 +26,9 @@ Other workloads (each prints its own JSON line instead):
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
+  --variant V     use launch variant V instead of autotuning (profiled runs
+                  pass one: the autotuner's persistent trials launch
+                  cooperatively, after which the profiler can fail at exit)
   --pmc-probe     a short run for hardware counters: 10 autotuned sweeps of the
                   default workload (--variant V forces launch variant V),
                   then a 1 GiB device-to-device copy (the calibration kernel
@@ -170,8 +173,14 @@ def main():
     t_setup = time.perf_counter() - t0
     print(f"# generated in {t_gen:.1f}s, setup in {t_setup:.2f}s, arena "
           f"{solver.footprint / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-    # pick the sweep kernels' launch variant for this chain
-    tuned_ms, _ = stc.stc_autotune(solver.h, 20)
+    # pick the sweep kernels' launch variant for this chain (or take the
+    # one given: profiled runs avoid the persistent variants' cooperative
+    # launches, after which the profiler can fail at exit)
+    if args.variant is None:
+        tuned_ms, _ = stc.stc_autotune(solver.h, 20)
+    else:
+        stc.stc_set_variant(solver.h, stc.STC_FP64, args.variant)
+        tuned_ms = float("nan")
 
     solver.load(None)
     solver.sweeps(args.warmup)
@@ -190,8 +199,12 @@ def main():
     bytes_a, bytes_b = stc.stc_phase_bytes(solver.h)
     bytes_sweep = bytes_a + bytes_b
     value = bytes_sweep / (ms_per_step * 1e-3) / 1e9
+    variant = stc.stc_get_variant(solver.h, stc.STC_FP64)
+    persistent = bool(variant & 4)
+    # per-phase launches: the phase-A kernel's own time; a persistent burst:
+    # half of its launch time per sweep
     achieved = bytes_a / (ms_a * 1e-3) / 1e9
-    traffic = measured_traffic(workload, stc.stc_get_variant(solver.h, stc.STC_FP64))
+    traffic = measured_traffic(workload, variant)
 
     line = {
         "metric": "HBM GB/s per staircase sweep",
@@ -209,7 +222,9 @@ def main():
         "config": {"workload": workload, "levels": L, "block": m, "N": L * m,
                    "stair_type": 1, "bytes_per_sweep": bytes_sweep,
                    "seed": synth.config_seed(1)},
-        "roofline": {"bound": "hbm", "kernel": "phase A sweep kernel",
+        "roofline": {"bound": "hbm",
+                     "kernel": ("persistent sweep kernel, per phase" if persistent
+                                else "phase A sweep kernel"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": bytes_a, "ms_per_launch": round(ms_a, 5)},
@@ -217,7 +232,8 @@ def main():
                     "GB/s": round(bytes_b / (ms_b * 1e-3) / 1e9, 1)},
         "finalize_ms_per_launch": round(ms_fin, 5),
         "variant": {"fp64": stc.stc_get_variant(solver.h, stc.STC_FP64),
-                    "autotune_ms_per_sweep": round(tuned_ms, 5)},
+                    "autotune_ms_per_sweep": (round(tuned_ms, 5) if tuned_ms == tuned_ms
+                                              else None)},
         "sweeps_per_s": round(1e3 / ms_per_step, 1),
     }
 
@@ -420,8 +436,9 @@ def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30, variant=None):
     torch.cuda.set_device(0)
     gen = synth.qbd(L, m, synth.config_seed(1))
     s = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64")
-    stc.stc_autotune(s.h, 10)
-    if variant is not None:
+    if variant is None:
+        stc.stc_autotune(s.h, 10)
+    else:
         stc.stc_set_variant(s.h, stc.STC_FP64, variant)
     s.load(None)
     s.sweeps(sweeps)
