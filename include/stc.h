@@ -227,14 +227,15 @@ stc_status stc_promote(stc_handle *h);
 
 /* ---- many chains ------------------------------------------------------
  * A batch sweeps many independent chains (one handle each, of any L and m)
- * with one persistent launch per half-sweep and precision stage: a work list
- * of (chain, group of levels) items, heaviest first, strided over a fixed
- * grid, plus one finalize workgroup per chain.  Each chain keeps its own
+ * with one persistent launch per half-sweep, precision stage and padded
+ * block size present: a work list of (chain, group of levels) items strided
+ * over a fixed grid, plus one finalize workgroup per chain.  Each chain keeps its own
  * sweep number, scale ring and device stopping test, so chains admitted at
  * different times advance independently and a stopped chain stays put.  The
  * chain table and work lists live at fixed device addresses, so the
  * hipGraph that stc_batch_sweeps captures stays valid when stc_batch_set
- * changes the membership.  Per-chain results equal those of the same chain
+ * changes the membership (it is captured again when the set of precision
+ * stages or block sizes present changes).  Per-chain results equal those of the same chain
  * swept alone with launch variant 0 (same per-level arithmetic, same
  * fixed-order reductions). */
 typedef struct stc_batch stc_batch;

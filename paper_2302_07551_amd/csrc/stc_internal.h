@@ -67,8 +67,19 @@ struct SweepLaunch {
 //          blocks wait on their neighbours' progress flags instead of on
 //          kernel boundaries (same per-level arithmetic and reductions, so the
 //          same results bit for bit)
+// The row groups per level follow the block size: blocks of 64 and more take
+// 8 (bit 0 clear) or 4 (bit 0 set); smaller blocks take MP / 8 or MP / 16
+// (at least 1), so that a thread streams 8 or 16 rows of each block between
+// two workgroup barriers instead of 1 to 4.  Bit 3 is internal: the fixed
+// 8-row-group tile of the sparse kernel.
 constexpr int kVariants = 8;
-__host__ __device__ constexpr int variant_rg(int v) { return (v & 1) ? 4 : 8; }
+constexpr int kEllGeometry = 8;
+__host__ __device__ constexpr int variant_rg(int MP, int v) {
+    return (v & kEllGeometry) ? 8
+           : MP >= 64         ? ((v & 1) ? 4 : 8)
+           : (v & 1)          ? (MP >= 32 ? MP / 16 : 1)
+                              : MP / 8;
+}
 __host__ __device__ constexpr bool variant_nt(int v) { return (v & 2) != 0; }
 __host__ __device__ constexpr bool variant_flow(int v) { return (v & 4) != 0; }
 
@@ -183,7 +194,7 @@ hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t str
 hipError_t launch_reset_state(DevState *st, hipStream_t stream);
 hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);
 int batch_lpw(int precision_bytes, int MP);
-hipError_t launch_batch_phase(int precision_bytes, int b, bool phase_b, bool nt, int grid,
+hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, bool nt, int grid,
                               const ChainDesc *chains, const WorkItem *items, const int *nitems,
                               hipStream_t stream);
 hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,

@@ -198,7 +198,10 @@ __device__ inline void record_sweep(DevState *st, long long s, double S, double 
     }
 }
 
-template <typename T, int MP, int B, bool PHB, int RG, bool NT, bool COH = false>
+// COH: persistent launch (device-scope accesses for data other blocks of the
+// launch write).  LOOP: called from a loop over groups or work items.
+template <typename T, int MP, int B, bool PHB, int RG, bool NT, bool COH = false,
+          bool LOOP = COH>
 __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, double inv_old,
                                    T *red_base, T *rv_base, double *sh) {
     // persistent launch: live is uniform over the block, and a sweep after
@@ -215,10 +218,10 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
 
     const DevState *st = a.st;
     int tid = threadIdx.x;
-    if constexpr (COH) {
-        // opaque to the optimiser: in the persistent loop the per-thread row
-        // offsets would otherwise be hoisted and held across every sweep,
-        // doubling the registers and halving the resident blocks
+    if constexpr (LOOP) {
+        // opaque to the optimiser: in the persistent and work-list loops the
+        // per-thread row offsets would otherwise be hoisted and held across
+        // every item, raising the registers and cutting the resident blocks
         asm volatile("" : "+v"(tid));
     }
     const int team = tid / TS, tt = tid - team * TS;
@@ -269,11 +272,13 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc[e];
     __syncthreads();
-    if (tt < MP) {
+    // a team may be narrower than a block row (small blocks): stride by TS
+#pragma unroll
+    for (int e = tt; e < MP; e += TS) {
         T r = 0;
 #pragma unroll
-        for (int gg = 0; gg < R; ++gg) r += red[gg * MP + tt];
-        rv[tt] = r;
+        for (int gg = 0; gg < R; ++gg) r += red[gg * MP + e];
+        rv[e] = r;
     }
     __syncthreads();
 
@@ -291,18 +296,21 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     __syncthreads();
 
     double zs = 0.0, dd = 0.0;
-    if (live && active && tt < MP) {
-        T z = 0;
+    if (live && active) {
 #pragma unroll
-        for (int gg = 0; gg < R; ++gg) z += red[gg * MP + tt];
-        cstore<COH>(w_new + (size_t)i * MP + tt, z);
-        zs = (double)z;
-        if (a.s >= 3) {
-            // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
-            const double i2 = cload<COH>(&st->inv_sigma[(a.s - 2) & kRingMask]);
-            const double i3 = cload<COH>(&st->inv_sigma[(a.s - 3) & kRingMask]);
-            dd = fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + tt) * i2 -
-                      (double)cload<COH>(a.w_d2 + (size_t)i * MP + tt) * i3);
+        for (int e = tt; e < MP; e += TS) {
+            T z = 0;
+#pragma unroll
+            for (int gg = 0; gg < R; ++gg) z += red[gg * MP + e];
+            cstore<COH>(w_new + (size_t)i * MP + e, z);
+            zs += (double)z;
+            if (a.s >= 3) {
+                // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
+                const double i2 = cload<COH>(&st->inv_sigma[(a.s - 2) & kRingMask]);
+                const double i3 = cload<COH>(&st->inv_sigma[(a.s - 3) & kRingMask]);
+                dd += fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + e) * i2 -
+                           (double)cload<COH>(a.w_d2 + (size_t)i * MP + e) * i3);
+            }
         }
     }
     double S = zs, D = dd;
@@ -754,18 +762,20 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
 // many chains: one persistent launch per half-sweep over a work list of
 // (chain, group) items; each chain's sweep number comes from its own state
 // ---------------------------------------------------------------------------
-template <typename T, int B, bool PHB, bool NT>
+// One launch per block size present (a kernel per block size keeps each one
+// at its own register count; one kernel for all sizes took the largest).
+// cls: {offset, count} of this block size's items in the work list (read
+// on the device, so a captured graph stays valid when the lists change).
+template <typename T, int MP, int B, bool PHB, bool NT>
 __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
-                                                      const WorkItem *items,
-                                                      const int *nitems) {
-    // LPW * R * MP = kWG * VEC elements for every block size
-    constexpr int VEC = 16 / (int)sizeof(T);
-    __shared__ T red[kWG * VEC];
-    __shared__ T rv[kWG * VEC];
+                                                      const WorkItem *items, const int *cls) {
+    using TL = Tile<T, MP, variant_rg(MP, 0)>;   // the tile of launch variant 0
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
     __shared__ double sh[2 * kWG / 64];
-    const int n = *nitems;
+    const int off = cls[0], n = cls[1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
-        const WorkItem w = items[it];
+        const WorkItem w = items[off + it];
         const ChainDesc &d = chains[w.chain];
         const DevState *st = d.st;
         const long long s = st->last_sweep + 1;
@@ -784,13 +794,8 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
         v.slot0 = PHB ? d.groups_a : 0;
         v.s = s;
         const double inv_old = st->inv_sigma[(s - 2) & kRingMask];   // kappa_s
-        switch (d.MP) {
-            case 8: sweep_group<T, 8, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
-            case 16: sweep_group<T, 16, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
-            case 32: sweep_group<T, 32, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
-            case 64: sweep_group<T, 64, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
-            case 128: sweep_group<T, 128, B, PHB, 8, NT>(v, w.group, live, inv_old, red, rv, sh); break;
-        }
+        sweep_group<T, MP, B, PHB, variant_rg(MP, 0), NT, false, true>(v, w.group, live, inv_old,
+                                                                        red, rv, sh);
     }
 }
 
@@ -966,10 +971,12 @@ __global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, const Dev
     const int parity = in_a ? parity_a : 1 - parity_a;
     const int i = parity + 2 * (q * TL::LPW + team);
     double dd = 0.0;
-    if (i < L && tt < MP) {
+    if (i < L) {
         const double i2 = st->inv_sigma[k & kRingMask];
         const double i3 = st->inv_sigma[(k - 1) & kRingMask];
-        dd = fabs((double)w[(size_t)i * MP + tt] * i2 - (double)wp[(size_t)i * MP + tt] * i3);
+#pragma unroll
+        for (int e = tt; e < MP; e += TL::TS)
+            dd += fabs((double)w[(size_t)i * MP + e] * i2 - (double)wp[(size_t)i * MP + e] * i3);
     }
     const double D = block_sum(dd, sh);
     if (tid == 0) part[blockIdx.x] = D;
@@ -1241,14 +1248,25 @@ int supported_mp(int m) {
     return mp;
 }
 
-template <typename T, int RG>
-static int lpw_of(int MP) {
+// Levels per workgroup of variant v's tile for block size MP.
+template <typename T, int MP>
+static int lpw_mp(int v) {
+    switch (variant_rg(MP, v)) {
+        case 1: return Tile<T, MP, 1>::LPW;
+        case 2: return Tile<T, MP, 2>::LPW;
+        case 4: return Tile<T, MP, 4>::LPW;
+        default: return Tile<T, MP, 8>::LPW;
+    }
+}
+
+template <typename T>
+static int lpw_of(int MP, int v) {
     switch (MP) {
-        case 8: return Tile<T, 8, RG>::LPW;
-        case 16: return Tile<T, 16, RG>::LPW;
-        case 32: return Tile<T, 32, RG>::LPW;
-        case 64: return Tile<T, 64, RG>::LPW;
-        case 128: return Tile<T, 128, RG>::LPW;
+        case 8: return lpw_mp<T, 8>(v);
+        case 16: return lpw_mp<T, 16>(v);
+        case 32: return lpw_mp<T, 32>(v);
+        case 64: return lpw_mp<T, 64>(v);
+        case 128: return lpw_mp<T, 128>(v);
     }
     return 1;
 }
@@ -1257,15 +1275,12 @@ int variant_count() { return kVariants; }
 
 int phase_groups(int precision_bytes, int MP, int L, int parity, int variant) {
     const int levels = (L - parity + 1) / 2;
-    const bool rg4 = variant_rg(variant) == 4;
-    int lpw;
-    if (precision_bytes == 8) lpw = rg4 ? lpw_of<double, 4>(MP) : lpw_of<double, 8>(MP);
-    else lpw = rg4 ? lpw_of<float, 4>(MP) : lpw_of<float, 8>(MP);
+    const int lpw = precision_bytes == 8 ? lpw_of<double>(MP, variant) : lpw_of<float>(MP, variant);
     return (levels + lpw - 1) / lpw;
 }
 
 int reduce_groups(int MP, int L) {
-    const int lpw = lpw_of<double, 8>(MP);
+    const int lpw = lpw_of<double>(MP, kEllGeometry);   // the residual kernel's 8-row-group tile
     return (L + lpw - 1) / lpw;
 }
 
@@ -1296,10 +1311,10 @@ template <typename T, int MP, int B>
 static hipError_t sweep_mpb(bool phase_b, int variant, const SweepLaunch &a, hipStream_t s,
                             LaunchTimer t) {
     switch (variant & 3) {   // bit 2 (persistent bursts) has the same phases
-        case 0: return sweep_v<T, MP, B, variant_rg(0), variant_nt(0)>(phase_b, 0, a, s, t);
-        case 1: return sweep_v<T, MP, B, variant_rg(1), variant_nt(1)>(phase_b, 1, a, s, t);
-        case 2: return sweep_v<T, MP, B, variant_rg(2), variant_nt(2)>(phase_b, 2, a, s, t);
-        case 3: return sweep_v<T, MP, B, variant_rg(3), variant_nt(3)>(phase_b, 3, a, s, t);
+        case 0: return sweep_v<T, MP, B, variant_rg(MP, 0), variant_nt(0)>(phase_b, 0, a, s, t);
+        case 1: return sweep_v<T, MP, B, variant_rg(MP, 1), variant_nt(1)>(phase_b, 1, a, s, t);
+        case 2: return sweep_v<T, MP, B, variant_rg(MP, 2), variant_nt(2)>(phase_b, 2, a, s, t);
+        case 3: return sweep_v<T, MP, B, variant_rg(MP, 3), variant_nt(3)>(phase_b, 3, a, s, t);
     }
     return hipErrorInvalidValue;
 }
@@ -1358,17 +1373,17 @@ static int flow_mpb(bool launch, int variant, const FlowLaunch *f, hipStream_t s
                     hipError_t *err) {
     switch (variant & 3) {
         case 0:
-            if (launch) *err = flow_v<T, MP, B, variant_rg(0), variant_nt(0)>(*f, s);
-            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(0), variant_nt(0)>();
+            if (launch) *err = flow_v<T, MP, B, variant_rg(MP, 0), variant_nt(0)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(MP, 0), variant_nt(0)>();
         case 1:
-            if (launch) *err = flow_v<T, MP, B, variant_rg(1), variant_nt(1)>(*f, s);
-            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(1), variant_nt(1)>();
+            if (launch) *err = flow_v<T, MP, B, variant_rg(MP, 1), variant_nt(1)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(MP, 1), variant_nt(1)>();
         case 2:
-            if (launch) *err = flow_v<T, MP, B, variant_rg(2), variant_nt(2)>(*f, s);
-            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(2), variant_nt(2)>();
+            if (launch) *err = flow_v<T, MP, B, variant_rg(MP, 2), variant_nt(2)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(MP, 2), variant_nt(2)>();
         default:
-            if (launch) *err = flow_v<T, MP, B, variant_rg(3), variant_nt(3)>(*f, s);
-            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(3), variant_nt(3)>();
+            if (launch) *err = flow_v<T, MP, B, variant_rg(MP, 3), variant_nt(3)>(*f, s);
+            return launch ? 0 : flow_resident_v<T, MP, B, variant_rg(MP, 3), variant_nt(3)>();
     }
 }
 
@@ -1412,7 +1427,7 @@ template <typename T, int MP, int B>
 static hipError_t ell_mpb(bool phase_b, const SweepLaunch &a, const EllEntry *tab,
                           const void *val, const unsigned char *idx, hipStream_t s,
                           LaunchTimer t) {
-    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, 0) +
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, kEllGeometry) +
                        ((phase_b && a.fold) ? 1 : 0);
     if (groups <= 0) return hipSuccess;
     if (phase_b)
@@ -1498,38 +1513,51 @@ hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream) {
 }
 
 int batch_lpw(int precision_bytes, int MP) {
-    return precision_bytes == 8 ? lpw_of<double, 8>(MP) : lpw_of<float, 8>(MP);
+    return precision_bytes == 8 ? lpw_of<double>(MP, 0) : lpw_of<float>(MP, 0);
 }
 
-template <typename T, int B>
-static hipError_t batch_tb(bool phase_b, bool nt, int grid, const ChainDesc *chains,
+template <typename T, int MP, int B>
+static hipError_t batch_mp(bool phase_b, bool nt, int grid, const ChainDesc *chains,
                            const WorkItem *items, const int *nitems, hipStream_t s) {
     if (phase_b) {
         if (nt)
-            hipLaunchKernelGGL((k_batch_sweep<T, B, true, true>), dim3(grid), dim3(kWG), 0, s,
+            hipLaunchKernelGGL((k_batch_sweep<T, MP, B, true, true>), dim3(grid), dim3(kWG), 0, s,
                                chains, items, nitems);
         else
-            hipLaunchKernelGGL((k_batch_sweep<T, B, true, false>), dim3(grid), dim3(kWG), 0, s,
-                               chains, items, nitems);
+            hipLaunchKernelGGL((k_batch_sweep<T, MP, B, true, false>), dim3(grid), dim3(kWG), 0,
+                               s, chains, items, nitems);
     } else {
         if (nt)
-            hipLaunchKernelGGL((k_batch_sweep<T, B, false, true>), dim3(grid), dim3(kWG), 0, s,
-                               chains, items, nitems);
+            hipLaunchKernelGGL((k_batch_sweep<T, MP, B, false, true>), dim3(grid), dim3(kWG), 0,
+                               s, chains, items, nitems);
         else
-            hipLaunchKernelGGL((k_batch_sweep<T, B, false, false>), dim3(grid), dim3(kWG), 0, s,
-                               chains, items, nitems);
+            hipLaunchKernelGGL((k_batch_sweep<T, MP, B, false, false>), dim3(grid), dim3(kWG), 0,
+                               s, chains, items, nitems);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch_phase(int precision_bytes, int b, bool phase_b, bool nt, int grid,
+template <typename T, int B>
+static hipError_t batch_tb(int MP, bool phase_b, bool nt, int grid, const ChainDesc *chains,
+                           const WorkItem *items, const int *nitems, hipStream_t s) {
+    switch (MP) {
+        case 8: return batch_mp<T, 8, B>(phase_b, nt, grid, chains, items, nitems, s);
+        case 16: return batch_mp<T, 16, B>(phase_b, nt, grid, chains, items, nitems, s);
+        case 32: return batch_mp<T, 32, B>(phase_b, nt, grid, chains, items, nitems, s);
+        case 64: return batch_mp<T, 64, B>(phase_b, nt, grid, chains, items, nitems, s);
+        case 128: return batch_mp<T, 128, B>(phase_b, nt, grid, chains, items, nitems, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, bool nt, int grid,
                               const ChainDesc *chains, const WorkItem *items, const int *nitems,
                               hipStream_t stream) {
     if (precision_bytes == 8)
-        return b == 1 ? batch_tb<double, 1>(phase_b, nt, grid, chains, items, nitems, stream)
-                      : batch_tb<double, 2>(phase_b, nt, grid, chains, items, nitems, stream);
-    return b == 1 ? batch_tb<float, 1>(phase_b, nt, grid, chains, items, nitems, stream)
-                  : batch_tb<float, 2>(phase_b, nt, grid, chains, items, nitems, stream);
+        return b == 1 ? batch_tb<double, 1>(MP, phase_b, nt, grid, chains, items, nitems, stream)
+                      : batch_tb<double, 2>(MP, phase_b, nt, grid, chains, items, nitems, stream);
+    return b == 1 ? batch_tb<float, 1>(MP, phase_b, nt, grid, chains, items, nitems, stream)
+                  : batch_tb<float, 2>(MP, phase_b, nt, grid, chains, items, nitems, stream);
 }
 
 hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
@@ -1594,12 +1622,23 @@ hipError_t launch_store(int precision_bytes, int MP, const void *w, const long l
 template <typename T, int MP>
 static hipError_t diff_mp(int rg, const void *w, const void *wp, int L, int pA, int gA, int gB,
                           const DevState *st, long long k, double *part, hipStream_t s) {
-    if (rg == 4)
-        hipLaunchKernelGGL((k_diff<T, MP, 4>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
-                           (const T *)wp, st, k, L, pA, gA, part);
-    else
-        hipLaunchKernelGGL((k_diff<T, MP, 8>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
-                           (const T *)wp, st, k, L, pA, gA, part);
+    switch (rg) {
+        case 1:
+            hipLaunchKernelGGL((k_diff<T, MP, 1>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                               (const T *)wp, st, k, L, pA, gA, part);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_diff<T, MP, 2>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                               (const T *)wp, st, k, L, pA, gA, part);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_diff<T, MP, 4>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                               (const T *)wp, st, k, L, pA, gA, part);
+            break;
+        default:
+            hipLaunchKernelGGL((k_diff<T, MP, 8>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
+                               (const T *)wp, st, k, L, pA, gA, part);
+    }
     return hipGetLastError();
 }
 
@@ -1608,23 +1647,22 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
                        double *part, hipStream_t stream, double tol) {
     const int gA = phase_groups(precision_bytes, MP, L, parity_a, variant);
     const int gB = phase_groups(precision_bytes, MP, L, 1 - parity_a, variant);
-    const int rg = variant_rg(variant);
     hipError_t e = hipErrorInvalidValue;
     if (precision_bytes == 8) {
         switch (MP) {
-            case 8: e = diff_mp<double, 8>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 16: e = diff_mp<double, 16>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 32: e = diff_mp<double, 32>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 64: e = diff_mp<double, 64>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 128: e = diff_mp<double, 128>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 8: e = diff_mp<double, 8>(variant_rg(8, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 16: e = diff_mp<double, 16>(variant_rg(16, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 32: e = diff_mp<double, 32>(variant_rg(32, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 64: e = diff_mp<double, 64>(variant_rg(64, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 128: e = diff_mp<double, 128>(variant_rg(128, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
         }
     } else {
         switch (MP) {
-            case 8: e = diff_mp<float, 8>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 16: e = diff_mp<float, 16>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 32: e = diff_mp<float, 32>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 64: e = diff_mp<float, 64>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
-            case 128: e = diff_mp<float, 128>(rg, w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 8: e = diff_mp<float, 8>(variant_rg(8, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 16: e = diff_mp<float, 16>(variant_rg(16, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 32: e = diff_mp<float, 32>(variant_rg(32, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 64: e = diff_mp<float, 64>(variant_rg(64, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 128: e = diff_mp<float, 128>(variant_rg(128, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
         }
     }
     if (e != hipSuccess) return e;

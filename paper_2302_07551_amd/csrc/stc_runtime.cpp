@@ -344,7 +344,7 @@ void *wbuf(stc_handle *h, bool fp32, long long s) {
 
 int sweep_slots(stc_handle *h) {
     const bool f32 = h->stage32;
-    const int vv = h->sparse ? 0 : h->variant[f32 ? 1 : 0];
+    const int vv = h->sparse ? kEllGeometry : h->variant[f32 ? 1 : 0];
     const int bytes = f32 ? 4 : 8;
     const int pA = (h->stair_type == 1) ? 0 : 1;
     return phase_groups(bytes, h->MP, h->L, pA, vv) + phase_groups(bytes, h->MP, h->L, 1 - pA, vv);
@@ -384,7 +384,7 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTime
     const int pA = (h->stair_type == 1) ? 0 : 1;
     const int pB = 1 - pA;
     const int bytes = f32 ? 4 : 8;
-    const int vv = h->sparse ? 0 : v;   // the sparse kernel has variant 0's geometry
+    const int vv = h->sparse ? kEllGeometry : v;   // the sparse kernel's fixed tile
     const int gA = phase_groups(bytes, h->MP, h->L, pA, vv);
     const int gB = phase_groups(bytes, h->MP, h->L, pB, vv);
     const bool fold_ok = gA + gB <= kFoldSlots;
@@ -431,7 +431,7 @@ hipError_t end_burst(stc_handle *h, long long n, double tol, bool recorded = fal
                                   h->part_diff + (n & 1) * h->lay.nparts, sweep_slots(h), h->st,
                                   n, tol, h->stream);
     const bool f32 = h->stage32;
-    const int vv = h->sparse ? 0 : h->variant[f32 ? 1 : 0];
+    const int vv = h->sparse ? kEllGeometry : h->variant[f32 ? 1 : 0];
     const int pA = (h->stair_type == 1) ? 0 : 1;
     for (long long k = n - 1; k <= n && e == hipSuccess; ++k) {
         if (k < 1) continue;
@@ -1277,6 +1277,9 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
 // batched sweeps over many chains
 // ---------------------------------------------------------------------------
 
+constexpr int kSizeClasses = 5;                       // MP = 8, 16, 32, 64, 128
+constexpr int kCountsPerGroup = 1 + 4 * kSizeClasses;
+
 struct stc_batch {
     int max_chains = 0;
     long long max_items = 0;
@@ -1289,8 +1292,11 @@ struct stc_batch {
     ChainDesc *d_chains[2] = {nullptr, nullptr};   // [0] FP64 stage, [1] FP32 stage
     WorkItem *d_items_a[2] = {nullptr, nullptr};
     WorkItem *d_items_b[2] = {nullptr, nullptr};
-    int *d_counts = nullptr;                        // per group: chains, items A, items B
-    int counts[6] = {0, 0, 0, 0, 0, 0};
+    // per stage group g (kCountsPerGroup ints from g * kCountsPerGroup):
+    // chains, then per block size class c (MP = 8 << c): phase A {offset,
+    // count}, phase B {offset, count} into that group's work lists
+    int *d_counts = nullptr;
+    int counts[2 * kCountsPerGroup] = {};
     DevState **d_states = nullptr;                  // members' states, in stc_batch_set order
     QueryRow *d_query = nullptr;
     std::vector<stc_handle *> members;
@@ -1313,7 +1319,7 @@ BatchLayout batch_layout(int max_chains, long long max_items) {
     l.chains = take(2 * (size_t)max_chains * sizeof(ChainDesc));
     l.items_a = take(2 * (size_t)max_items * sizeof(WorkItem));
     l.items_b = take(2 * (size_t)max_items * sizeof(WorkItem));
-    l.counts = take(6 * sizeof(int));
+    l.counts = take(2 * kCountsPerGroup * sizeof(int));
     l.states = take((size_t)max_chains * sizeof(DevState *));
     l.query = take((size_t)max_chains * sizeof(QueryRow));
     l.total = at;
@@ -1330,23 +1336,44 @@ void drop_graph(stc_batch *bt) {
 }
 
 // Enqueue n sweeps of every non-empty stage group (FP32 group first).
+int class_of(int MP) {
+    int c = 0;
+    while ((8 << c) < MP) ++c;
+    return c;
+}
+
+// Enqueue n sweeps of every non-empty stage group (FP32 group first): per
+// phase one launch per block size present, then the per-chain finalize.
 hipError_t enqueue_batch(stc_batch *bt, long long n) {
     hipError_t e = hipSuccess;
     for (long long j = 0; j < n && e == hipSuccess; ++j) {
         for (int g = 1; g >= 0 && e == hipSuccess; --g) {
-            if (bt->counts[3 * g] == 0) continue;
+            const int *hc = bt->counts + g * kCountsPerGroup;
+            int *dc = bt->d_counts + g * kCountsPerGroup;
+            if (hc[0] == 0) continue;
             const int bytes = g == 1 ? 4 : 8;
-            e = launch_batch_phase(bytes, bt->b, false, bt->nt, bt->grid, bt->d_chains[g],
-                                   bt->d_items_a[g], bt->d_counts + 3 * g + 1, bt->stream);
+            for (int ph = 0; ph < 2 && e == hipSuccess; ++ph)
+                for (int c = 0; c < kSizeClasses && e == hipSuccess; ++c) {
+                    const int k = 1 + 4 * c + 2 * ph;
+                    if (hc[k + 1] == 0) continue;
+                    e = launch_batch_phase(bytes, bt->b, 8 << c, ph == 1, bt->nt, bt->grid,
+                                           bt->d_chains[g], ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g],
+                                           dc + k, bt->stream);
+                }
             if (e == hipSuccess)
-                e = launch_batch_phase(bytes, bt->b, true, bt->nt, bt->grid, bt->d_chains[g],
-                                       bt->d_items_b[g], bt->d_counts + 3 * g + 2, bt->stream);
-            if (e == hipSuccess)
-                e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], bt->d_counts + 3 * g,
-                                          bt->stream);
+                e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], dc, bt->stream);
         }
     }
     return e;
+}
+
+// Which (stage group, block size) launches a captured graph holds.
+int batch_shape(const stc_batch *bt) {
+    int mask = 0;
+    for (int g = 0; g < 2; ++g)
+        for (int c = 0; c < kSizeClasses; ++c)
+            if (bt->counts[g * kCountsPerGroup + 1 + 4 * c + 1] > 0) mask |= 1 << (g * kSizeClasses + c);
+    return mask;
 }
 
 }  // namespace
@@ -1412,8 +1439,8 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
     if (!bt || (count > 0 && !hs) || count < 0) return fail(STC_EINVAL, "bad argument");
     if (count > bt->max_chains) return fail(STC_EINVAL, "%d chains > max_chains %d", count, bt->max_chains);
     std::vector<ChainDesc> chains[2];
-    std::vector<WorkItem> ia[2], ib[2];
-    std::vector<double> cost_a[2], cost_b[2];
+    // work lists per stage group and block size class, in chain order
+    std::vector<WorkItem> ia[2][kSizeClasses], ib[2][kSizeClasses];
     for (int c = 0; c < count; ++c) {
         stc_handle *h = hs[c];
         if (!h) return fail(STC_EINVAL, "handle %d is NULL", c);
@@ -1437,37 +1464,32 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
         d.tol = (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
         const int ci = (int)chains[g].size();
         chains[g].push_back(d);
-        const double per = (double)lpw * h->MP * h->MP * bytes;
-        for (int q = 0; q < d.groups_a; ++q) { ia[g].push_back({ci, q}); cost_a[g].push_back(per); }
-        for (int q = 0; q < d.groups_b; ++q) { ib[g].push_back({ci, q}); cost_b[g].push_back(per); }
+        const int cls = class_of(h->MP);
+        for (int q = 0; q < d.groups_a; ++q) ia[g][cls].push_back({ci, q});
+        for (int q = 0; q < d.groups_b; ++q) ib[g][cls].push_back({ci, q});
     }
     for (int g = 0; g < 2; ++g) {
-        if ((long long)ia[g].size() > bt->max_items || (long long)ib[g].size() > bt->max_items)
-            return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld",
-                        std::max(ia[g].size(), ib[g].size()), bt->max_items);
-        // heaviest items first, so the strided persistent assignment ends level
+        int *hc = bt->counts + g * kCountsPerGroup;
+        hc[0] = (int)chains[g].size();
         for (int ph = 0; ph < 2; ++ph) {
-            std::vector<WorkItem> &items = ph == 0 ? ia[g] : ib[g];
-            std::vector<double> &cost = ph == 0 ? cost_a[g] : cost_b[g];
-            std::vector<size_t> ord(items.size());
-            for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
-            std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-            std::vector<WorkItem> sorted(items.size());
-            for (size_t k = 0; k < ord.size(); ++k) sorted[k] = items[ord[k]];
-            items.swap(sorted);
+            std::vector<WorkItem> all;
+            for (int c = 0; c < kSizeClasses; ++c) {
+                const std::vector<WorkItem> &v = ph == 0 ? ia[g][c] : ib[g][c];
+                hc[1 + 4 * c + 2 * ph] = (int)all.size();       // offset
+                hc[1 + 4 * c + 2 * ph + 1] = (int)v.size();     // count
+                all.insert(all.end(), v.begin(), v.end());
+            }
+            if ((long long)all.size() > bt->max_items)
+                return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld", all.size(),
+                            bt->max_items);
+            if (!all.empty())
+                HIP_TRY(hipMemcpyAsync(ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], all.data(),
+                                       all.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                       bt->stream));
         }
         if (!chains[g].empty())
             HIP_TRY(hipMemcpyAsync(bt->d_chains[g], chains[g].data(), chains[g].size() * sizeof(ChainDesc),
                                    hipMemcpyHostToDevice, bt->stream));
-        if (!ia[g].empty())
-            HIP_TRY(hipMemcpyAsync(bt->d_items_a[g], ia[g].data(), ia[g].size() * sizeof(WorkItem),
-                                   hipMemcpyHostToDevice, bt->stream));
-        if (!ib[g].empty())
-            HIP_TRY(hipMemcpyAsync(bt->d_items_b[g], ib[g].data(), ib[g].size() * sizeof(WorkItem),
-                                   hipMemcpyHostToDevice, bt->stream));
-        bt->counts[3 * g] = (int)chains[g].size();
-        bt->counts[3 * g + 1] = (int)ia[g].size();
-        bt->counts[3 * g + 2] = (int)ib[g].size();
     }
     HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
                            bt->stream));
@@ -1491,7 +1513,7 @@ stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph) {
         HIP_TRY(enqueue_batch(bt, nsweeps));
         return STC_OK;
     }
-    const int groups = (bt->counts[0] > 0 ? 1 : 0) | (bt->counts[3] > 0 ? 2 : 0);
+    const int groups = batch_shape(bt);
     if (!bt->exec || bt->graph_n != nsweeps || bt->graph_groups != groups) {
         drop_graph(bt);
         HIP_TRY(hipStreamBeginCapture(bt->stream, hipStreamCaptureModeThreadLocal));
