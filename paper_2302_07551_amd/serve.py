@@ -9,13 +9,16 @@ chain in its FP32 stage that meets the switch tolerance is promoted to FP64
 (stc_promote); a chain whose FP64 change meets the tolerance is retired: its
 vector is copied out, its memory freed, and waiting requests are admitted.
 Setup of new chains (host validation and packing, upload, inverse of the
-diagonal blocks) runs on a side stream while the batch sweeps on its own
-stream, so arrivals overlap with the work already on the GPU.
+diagonal blocks) runs on a host thread of its own and a side stream while
+the batch sweeps on its own stream, so arrivals overlap with the work
+already on the GPU.
 
 Every step of the method runs in libstc.so; this module schedules calls.
 """
 from __future__ import annotations
 
+import queue
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -78,11 +81,14 @@ class ServeStats:
 
 
 class Server:
-    """Admission by footprint, continuous batching, FP32 -> FP64 promotion."""
+    """Admission by footprint, continuous batching, FP32 -> FP64 promotion.
+
+    nontemporal: stream the blocks with non-temporal loads (the admitted
+    chains together exceed the last-level cache under any useful budget)."""
 
     def __init__(self, budget_bytes: int, *, max_chains: int = 64, max_items: int = 1 << 17,
                  sweeps_per_round: int = 20, tol: float = 1e-13, switch_tol: float = 1e-6,
-                 precision: str = "mixed", nontemporal: bool = False, device=None,
+                 precision: str = "mixed", nontemporal: bool = True, device=None,
                  b: int = 1, use_graph: bool = True):
         import torch
         self.torch = torch
@@ -113,89 +119,128 @@ class Server:
         s.load(None)
         return s
 
+    def _setup_worker(self, todo: "queue.Queue", ready: "queue.Queue"):
+        """Set up admitted requests in order; each ready solver (or the error
+        its setup raised) goes to `ready`."""
+        import torch
+        with torch.cuda.device(self.device):
+            while True:
+                job = todo.get()
+                if job is None:
+                    return
+                req, fp = job
+                try:
+                    s = self._admit(req)
+                    self.setup_stream.synchronize()
+                    ready.put((req, s, fp, None))
+                except Exception as e:          # reported by the serving loop
+                    ready.put((req, None, fp, e))
+
     def run(self, requests, clock=time.perf_counter) -> ServeStats:
         reqs = sorted(requests, key=lambda r: r.arrival)
         pending = deque(reqs)
         waiting: deque = deque()
         active = []          # [request, solver, footprint, admitted_at, stage(, fp32 sweeps)]
-        joining = []         # admitted while the batch swept; they join the next round
         fps = {}
         used = 0
+        in_setup = 0         # admitted, handed to the setup thread, not yet active
         stats = ServeStats()
+        todo: queue.Queue = queue.Queue()
+        ready: queue.Queue = queue.Queue()
+        worker = threading.Thread(target=self._setup_worker, args=(todo, ready), daemon=True)
+        worker.start()
         t0 = clock()
         dirty = False
-        while pending or waiting or active or joining:
-            now = clock() - t0
-            while pending and pending[0].arrival <= now:
-                waiting.append(pending.popleft())
-            if joining:
-                active.extend(joining)
-                joining = []
-                dirty = True
-            stats.peak_chains = max(stats.peak_chains, len(active))
-            stats.peak_bytes = max(stats.peak_bytes, used)
-            if active:
+        try:
+            while pending or waiting or active or in_setup:
+                now = clock() - t0
+                while pending and pending[0].arrival <= now:
+                    waiting.append(pending.popleft())
+                # admission in arrival order (budget and free slots); setup runs
+                # on the setup thread
+                while waiting and len(active) + in_setup < self.max_chains:
+                    req = waiting[0]
+                    fp = fps.get(req.rid)
+                    if fp is None:
+                        fp = fps[req.rid] = self.footprint(req)
+                    if fp > self.budget:
+                        waiting.popleft()
+                        stats.rejected.append(req.rid)
+                        continue
+                    if used + fp > self.budget:
+                        break
+                    waiting.popleft()
+                    used += fp
+                    in_setup += 1
+                    todo.put((req, fp))
+                # chains whose setup finished join this round
+                while True:
+                    try:
+                        req, s, fp, err = ready.get_nowait()
+                    except queue.Empty:
+                        break
+                    in_setup -= 1
+                    if err is not None:
+                        raise err
+                    active.append([req, s, fp, clock() - t0,
+                                   32 if self.precision != "fp64" else 64])
+                    dirty = True
+                stats.peak_chains = max(stats.peak_chains, len(active))
+                stats.peak_bytes = max(stats.peak_bytes, used)
+                if not active:
+                    if in_setup:
+                        # nothing to sweep: wait for the setup thread
+                        req, s, fp, err = ready.get()
+                        in_setup -= 1
+                        if err is not None:
+                            raise err
+                        active.append([req, s, fp, clock() - t0,
+                                       32 if self.precision != "fp64" else 64])
+                        dirty = True
+                    elif pending:
+                        delay = pending[0].arrival - (clock() - t0)
+                        if delay > 0:
+                            time.sleep(min(delay, 0.05))
+                    continue
                 if dirty:
-                    self.setup_stream.synchronize()
                     self.batch.set([a[1] for a in active], self.tol, self.nontemporal)
                     dirty = False
                 self.batch.sweeps(self.K, self.use_graph)     # asynchronous
-            # admission in arrival order (budget and free slots), on the host
-            # and the side stream while the batch sweeps
-            while waiting and len(active) + len(joining) < self.max_chains:
-                req = waiting[0]
-                fp = fps.get(req.rid)
-                if fp is None:
-                    fp = fps[req.rid] = self.footprint(req)
-                if fp > self.budget:
-                    waiting.popleft()
-                    stats.rejected.append(req.rid)
-                    continue
-                if used + fp > self.budget:
-                    break
-                waiting.popleft()
-                s = self._admit(req)
-                joining.append([req, s, fp, clock() - t0,
-                                32 if self.precision != "fp64" else 64])
-                used += fp
-            if not active:
-                if not joining and pending:
-                    delay = pending[0].arrival - (clock() - t0)
-                    if delay > 0:
-                        time.sleep(min(delay, 0.05))
-                continue
-            # one device-to-host copy for every chain's stopping state
-            _sweeps, stopped, _diffs, status = self.batch.query()
-            stats.rounds += 1
-            keep = []
-            for k, entry in enumerate(active):
-                req, s, fp, t_adm, stage = entry[:5]
-                if status[k] != stc.STC_OK:
-                    # a sweep produced no positive mass: drop the request
-                    stats.rejected.append(req.rid)
+                # one device-to-host copy for every chain's stopping state
+                sweeps, stopped, _diffs, status = self.batch.query()
+                stats.rounds += 1
+                keep = []
+                for k, entry in enumerate(active):
+                    req, s, fp, t_adm, stage = entry[:5]
+                    if status[k] != stc.STC_OK:
+                        # a sweep produced no positive mass: drop the request
+                        stats.rejected.append(req.rid)
+                        s.close()
+                        used -= fp
+                        dirty = True
+                        continue
+                    if not stopped[k]:
+                        keep.append(entry)
+                        continue
+                    if stage == 32 and self.precision == "mixed":
+                        s.promote()
+                        entry[4] = 64
+                        entry.append(int(sweeps[k]))          # sweeps in FP32
+                        keep.append(entry)
+                        dirty = True
+                        continue
+                    pi = s.store()
+                    it = int(sweeps[k])
+                    it32 = entry[5] if len(entry) > 5 else (it if self.precision == "fp32" else 0)
+                    stats.results.append(Result(req.rid, req.arrival, t_adm, clock() - t0, pi, it,
+                                                it32, fp))
                     s.close()
                     used -= fp
                     dirty = True
-                    continue
-                if not stopped[k]:
-                    keep.append(entry)
-                    continue
-                if stage == 32 and self.precision == "mixed":
-                    s.promote()
-                    entry[4] = 64
-                    entry.append(int(_sweeps[k]))          # sweeps in FP32
-                    keep.append(entry)
-                    dirty = True
-                    continue
-                pi = s.store()
-                it = int(_sweeps[k])
-                it32 = entry[5] if len(entry) > 5 else (it if self.precision == "fp32" else 0)
-                stats.results.append(Result(req.rid, req.arrival, t_adm, clock() - t0, pi, it,
-                                            it32, fp))
-                s.close()
-                used -= fp
-                dirty = True
-            active = keep
+                active = keep
+        finally:
+            todo.put(None)
+            worker.join()
         stats.wall = clock() - t0
         return stats
 
