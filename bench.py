@@ -56,9 +56,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 
 
 def kernel_source_hash() -> str:
+    """Hash of every library source (the traffic counters are valid for it)."""
+    import glob
     h = hashlib.sha256()
-    for f in ("stc_kernels.hip", "stc_runtime.cpp", "stc_internal.h"):
-        with open(os.path.join(ROOT, "paper_2302_07551_amd", "csrc", f), "rb") as fh:
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2302_07551_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -81,7 +81,7 @@ enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    
 typedef struct {
     int32_t L;                   /* levels, >= 2                                    */
     int32_t m;                   /* block size: max states per level, 1..128       */
-    int32_t b;                   /* block bandwidth, 1 or 2                        */
+    int32_t b;                   /* block bandwidth, 1..4 (1: QBD)                  */
     const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */
     const double *blocks;        /* dense blocks, see above; NULL = CSR input      */
     int32_t recompute_diagonal;  /* 1: diag(Q_ii) := -(row sum of its off-diagonal

@@ -73,6 +73,7 @@ struct SweepLaunch {
 // two workgroup barriers instead of 1 to 4.  Bit 3 is internal: the fixed
 // 8-row-group tile of the sparse kernel.
 constexpr int kVariants = 8;
+constexpr int kMaxBandwidth = 4;   // block bandwidth b of the generators taken
 constexpr int kEllGeometry = 8;
 __host__ __device__ constexpr int variant_rg(int MP, int v) {
     return (v & kEllGeometry) ? 8

@@ -248,7 +248,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     *why = 0;
     if (!g || !o) return false;
     if (g->L < 2) { *why = 1; return false; }
-    if (g->b != 1 && g->b != 2) { *why = 2; return false; }
+    if (g->b < 1 || g->b > kMaxBandwidth) { *why = 2; return false; }
     const int MP = supported_mp(g->m);
     if (!MP) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
@@ -653,7 +653,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     Layout lay;
     int why = 0;
     if (!plan(g, o, &lay, &why)) {
-        static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be 1 or 2",
+        static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be in 1..4",
                                     "m must be in 1..128", "unknown precision", "unknown format",
                                     "neither blocks nor a complete CSR input given",
                                     "give blocks or CSR input, not both",
@@ -1389,8 +1389,8 @@ stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, vo
                             void *arena, size_t arena_bytes, stc_batch **out) {
     if (!out) return fail(STC_EINVAL, "null argument");
     *out = nullptr;
-    if (max_chains < 1 || max_items < 1 || (b != 1 && b != 2))
-        return fail(STC_EINVAL, "need max_chains >= 1, max_items >= 1, b in {1, 2}");
+    if (max_chains < 1 || max_items < 1 || b < 1 || b > kMaxBandwidth)
+        return fail(STC_EINVAL, "need max_chains >= 1, max_items >= 1, b in 1..4");
     if (!arena || (uintptr_t)arena % kAlign) return fail(STC_EINVAL, "arena must be 256-byte aligned");
     const BatchLayout l = batch_layout(max_chains, max_items);
     if (arena_bytes < l.total)

@@ -8,6 +8,7 @@ from .chains import (  # noqa: F401
     BlockGenerator,
     qbd,
     banded,
+    skip_free,
     birth_death,
     planted_reversible,
     served_stream,

@@ -247,6 +247,46 @@ def banded(L: int, m: int, seed: int, *, b: int = 2, density: float = 0.1,
     return BlockGenerator(L, m, b, blocks, sizes, name or f"banded_b{b}_L{L}_m{m}")
 
 
+def skip_free(L: int, m: int, seed: int, *, b: int = 4, up_density: float = 0.3,
+              decay: float = 0.5, down_max: float = 1.0, last: int | None = None,
+              chunk: int = 32, name: str = "") -> BlockGenerator:
+    """Level-dependent generator that is skip-free to the left (M/G/1 type):
+    from level i the chain moves down by one level at most, and up by 1..b
+    levels with rates that decay with the jump.
+
+    Q_{i,i-1}: Bernoulli(0.3) x U[0, down_max]; Q_{i,i+d}, 1 <= d <= b:
+    Bernoulli(up_density) x U[0, decay^(d-1)] / 2; within-level rates dense
+    U[0, 1].  The blocks Q_{i,i-d}, d >= 2, are zero.  Stored in the block
+    band of width b, so half of the stored off-diagonal slots are empty.
+    All-zero blocks at distance 1 are drawn again (irreducibility).
+    """
+    sizes = _sizes(L, m, last)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nb = 2 * b + 1
+    blocks = np.zeros((L, nb, m, m))
+    ar = np.arange(m)
+    for c0 in range(0, L, chunk):
+        c1 = min(L, c0 + chunk)
+        n = c1 - c0
+        inner = rng.random((n, m, m))
+        inner[:, ar, ar] = 0.0
+        blocks[c0:c1, b] = inner
+        blocks[c0:c1, b - 1] = (rng.random((n, m, m)) < 0.3) * rng.random((n, m, m)) * down_max
+        for d in range(1, b + 1):
+            blocks[c0:c1, b + d] = ((rng.random((n, m, m)) < up_density) *
+                                    rng.random((n, m, m)) * 0.5 * decay ** (d - 1))
+    mask = _level_mask(sizes, L, m, b)
+    blocks *= mask
+    for i in range(L):
+        for s_, dens, scale in ((b - 1, 0.3, down_max), (b + 1, up_density, 0.5)):
+            if not mask[i, s_].any():
+                continue
+            while not blocks[i, s_].any():
+                blocks[i, s_] = (rng.random((m, m)) < dens) * rng.random((m, m)) * scale * mask[i, s_]
+    _set_diagonal(blocks, sizes, b)
+    return BlockGenerator(L, m, b, blocks, sizes, name or f"skipfree_b{b}_L{L}_m{m}")
+
+
 def birth_death(lam: np.ndarray, mu: np.ndarray) -> BlockGenerator:
     """Scalar birth-death chain as an m=1 QBD: rate lam[i] from i to i+1,
     rate mu[i] from i to i-1 (lam[L-1] and mu[0] are ignored)."""

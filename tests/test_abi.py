@@ -65,7 +65,9 @@ def test_footprint_rejects_bad_shapes(lib):
     assert stc.stc_footprint_bytes(gen, opt) == 0
     gen.L, gen.m = 4, 200
     assert stc.stc_footprint_bytes(gen, opt) == 0
-    gen.m, gen.b = 4, 3
+    gen.m, gen.b = 4, 5
+    assert stc.stc_footprint_bytes(gen, opt) == 0
+    gen.b = 0
     assert stc.stc_footprint_bytes(gen, opt) == 0
 
 

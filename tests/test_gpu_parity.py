@@ -465,3 +465,81 @@ def test_csr_from_scipy_large_threaded():
     assert np.abs(z_csr[0] - z_ref).sum() <= 1e-13
     s.close()
     d.close()
+
+
+# ---- wide block bands (b = 3, 4): skip-free, banded and planted ----------
+
+WIDE = [
+    ("skipfree_b3_L19_m12", lambda: synth.skip_free(19, 12, 71, b=3, last=5)),
+    ("skipfree_b4_L23_m32", lambda: synth.skip_free(23, 32, 72, b=4)),
+    ("band_b3_L15_m8", lambda: synth.banded(15, 8, 73, b=3, density=0.4, last=3)),
+    ("planted_b4_L18_m6", lambda: synth.planted_reversible(18, 6, 74, b=4)[0]),
+]
+
+
+@pytest.mark.parametrize("name,make", WIDE, ids=[w[0] for w in WIDE])
+@pytest.mark.parametrize("stair_type", [1, 2])
+@pytest.mark.parametrize("format", ["dense", "sparse"])
+def test_wide_band_step_matches_oracle(name, make, stair_type, format):
+    g = make()
+    _say(f"wide step {name} type {stair_type} {format}")
+    x = synth.positive_start(g, 19)
+    zr, dr = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x,
+                                       stair_type)
+    for precision, tol in (("fp64", 1e-13), ("fp32", 1e-5)):
+        s = _solver(g, stair_type=stair_type, format=format, precision=precision)
+        z, d = s.step(x)
+        s.close()
+        assert np.abs(z - zr).sum() <= tol, precision
+        assert abs(d - dr) <= tol, precision
+
+
+@pytest.mark.parametrize("name,make", WIDE, ids=[w[0] for w in WIDE])
+def test_wide_band_converged_and_every_variant(name, make):
+    """Solves to the direct solution in both storages; every launch variant
+    (the persistent ones fall back to per-phase launches for b > 2) gives
+    the same sweep."""
+    from paper_2302_07551_amd import stc
+    g = make()
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    for format in ("dense", "sparse"):
+        s = _solver(g, format=format)
+        pi, info = s.solve(tol=1e-14, maxit=200000, allow_maxit=False)
+        s.close()
+        _say(f"wide solve {name} {format}: {info['iters']} sweeps")
+        assert np.abs(pi - ref).sum() <= 1e-10
+    x = synth.positive_start(g, 23)
+    s = _solver(g)
+    zs = []
+    for v in range(stc.stc_variant_count()):
+        stc.stc_set_variant(s.h, stc.STC_FP64, v)
+        zs.append(s.step(x)[0])
+    s.close()
+    for v in range(4, stc.stc_variant_count()):
+        assert np.array_equal(zs[v], zs[v - 4]), v
+
+
+def test_wide_band_batch_equals_alone():
+    from paper_2302_07551_amd import Batch, stc
+    gens = [synth.skip_free(40 + 9 * k, m, 80 + k, b=4, last=3 if k % 2 else None)
+            for k, m in enumerate((8, 16, 32, 64, 12))]
+    xs = [synth.positive_start(g, 5 + k) for k, g in enumerate(gens)]
+    alone = []
+    for g, x in zip(gens, xs):
+        s = _solver(g)
+        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+        s.load(x)
+        s.sweeps(31)
+        alone.append(s.store())
+        s.close()
+    sol = [_solver(g) for g in gens]
+    for s, x in zip(sol, xs):
+        s.load(x)
+    b = Batch(8, 4096, b=4)
+    b.set(sol, tol=0.0)
+    b.sweeps(31)
+    b.sync()
+    for k, s in enumerate(sol):
+        assert np.array_equal(s.store(), alone[k]), k
+        s.close()
+    b.close()

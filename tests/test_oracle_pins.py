@@ -92,7 +92,8 @@ def test_gth_rejects_reducible():
 # planted stationary vector (detailed balance)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("L,m,b,last,seed", [(10, 4, 1, None, 21), (9, 5, 1, 3, 22),
-                                             (12, 3, 2, None, 23), (11, 4, 2, 1, 24)])
+                                             (12, 3, 2, None, 23), (11, 4, 2, 1, 24),
+                                             (13, 3, 3, 2, 25), (14, 3, 4, None, 26)])
 def test_planted_gth_and_level_reduction(L, m, b, last, seed):
     g, pstar = synth.planted_reversible(L, m, seed, b=b, last=last)
     Q = dense.assemble_Q(g.blocks, g.sizes, g.b)
@@ -101,7 +102,7 @@ def test_planted_gth_and_level_reduction(L, m, b, last, seed):
     assert dense.residual_1(g.blocks, g.sizes, g.b, pstar) < 1e-13
 
 
-@pytest.mark.parametrize("b,stair_type", [(1, 1), (1, 2), (2, 1), (2, 2)])
+@pytest.mark.parametrize("b,stair_type", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (4, 2)])
 def test_planted_staircase_converges(b, stair_type):
     g, pstar = synth.planted_reversible(8, 4, 31 + b, b=b)
     r = staircase.staircase_solve(g.blocks, g.sizes, g.b, stair_type=stair_type,
@@ -223,13 +224,18 @@ def test_jacobi_on_qbd_has_minus_one():
 # --------------------------------------------------------------------------
 # the sweep: dense formula, fixed point, contraction rate
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("b,stair_type,last", [(1, 1, None), (1, 2, 2), (2, 1, None), (2, 2, 1)])
+@pytest.mark.parametrize("b,stair_type,last", [(1, 1, None), (1, 2, 2), (2, 1, None), (2, 2, 1),
+                                               (3, 1, 2), (4, 2, None)])
 def test_sweep_equals_dense_splitting(b, stair_type, last):
-    """One sweep of Algorithm 2 = normalised M^{-1} N x with M the stair matrix."""
+    """One sweep of Algorithm 2 = normalised M^{-1} N x with M the stair matrix
+    (for b >= 2 the first loop gathers old values from every level of the
+    band outside J_i)."""
     if b == 1:
         g = synth.qbd(9, 4, 50 + stair_type, last=last)
-    else:
+    elif b == 2:
         g = synth.banded(9, 4, 52 + stair_type, b=2, density=0.5, last=last)
+    else:
+        g = synth.skip_free(11, 4, 54 + b, b=b, last=last)
     A = dense.assemble_A(g.blocks, g.sizes, g.b)
     T = splittings.iteration_matrix(A, g.sizes, f"stair{stair_type}")
     x = synth.positive_start(g, 7)
@@ -301,3 +307,20 @@ def test_stop_rules_and_maxit():
     r = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-12, maxit=10000,
                                   stop=staircase.STOP_RESIDUAL)
     assert r.converged and r.residual <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# skip-free (M/G/1-type) generators with wide bands
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [3, 4])
+def test_skip_free_direct_solvers_agree_and_staircase_converges(b):
+    """Level reduction (super-levels of b levels) equals dense GTH on a
+    generator whose blocks below the first subdiagonal are zero, and the
+    staircase iteration converges to it."""
+    g = synth.skip_free(17, 4, 60 + b, b=b, last=3)
+    assert not g.blocks[:, : b - 1].any()          # skip-free to the left
+    Q = dense.assemble_Q(g.blocks, g.sizes, g.b)
+    ref = gth.gth(Q)
+    assert np.abs(level_reduction.level_reduction(g.blocks, g.sizes, g.b) - ref).sum() < 1e-13
+    r = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-15, maxit=50000)
+    assert np.abs(r.x - ref).sum() < 1e-12
