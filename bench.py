@@ -23,6 +23,10 @@ Other workloads (each prints its own JSON line instead):
   --banded        2048 levels x m=128 block-pentadiagonal generator with 10 %
                   dense off-diagonal blocks: sweeps/s and GB/s with dense and
                   sparse (ELL) off-diagonal storage, FP64 and FP32
+  --skipfree      2048 levels x m=64 skip-free (M/G/1-type) generator with
+                  block bandwidth 4 (down one level, up to four): sweeps/s
+                  with dense and sparse storage, FP64 and FP32, and the time
+                  to a change of 1e-13 against the direct solution
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -138,6 +142,7 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true")
     ap.add_argument("--setup", type=int, nargs=2, default=None)
     ap.add_argument("--banded", action="store_true")
+    ap.add_argument("--skipfree", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
@@ -157,6 +162,8 @@ def main():
         return setup_mode(*args.setup)
     if args.banded:
         return banded_mode()
+    if args.skipfree:
+        return skipfree_mode()
 
     import numpy as np
     import torch
@@ -380,6 +387,52 @@ def banded_mode(L=2048, m=128):
             "runs": runs, "ingest": ingest,
             "speedup_sparse_vs_dense_fp64": round(runs["dense_fp64"]["ms_per_sweep"] /
                                                  runs["sparse_fp64"]["ms_per_sweep"], 3)}
+    print(json.dumps(line), flush=True)
+
+
+def skipfree_mode(L=2048, m=64, b=4):
+    """Sweep rates and time to solution on a skip-free generator of block
+    bandwidth 4 (half the band's blocks empty)."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import level_reduction
+    from paper_2302_07551_amd import Solver
+    torch.cuda.set_device(0)
+    seed = synth.config_seed(5)
+    gen = synth.skip_free(L, m, seed, b=b)
+    t0 = time.perf_counter()
+    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
+    print(f"# direct reference in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    runs = {}
+    for fmt in ("dense", "sparse"):
+        for prec in ("fp64", "fp32"):
+            r = sweep_rate(gen, prec, steps=100, format=fmt)
+            r["sweeps_per_s"] = round(1e3 / r["ms_per_sweep"], 1)
+            runs[f"{fmt}_{prec}"] = r
+            print(f"# {fmt} {prec}: {r}", file=sys.stderr, flush=True)
+    solves = {}
+    for fmt in ("dense", "sparse"):
+        for prec in ("fp64", "mixed"):
+            s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec, format=fmt,
+                       check_every=100, switch_tol=1e-6)
+            from paper_2302_07551_amd import stc
+            stc.stc_autotune(s.h, 5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pi, info = s.solve(tol=1e-13, maxit=2_000_000)
+            dt = time.perf_counter() - t0
+            s.close()
+            solves[f"{fmt}_{prec}"] = {"seconds": round(dt, 4), "iters": info["iters"],
+                                       "iters_fp32": info["iters_fp32"],
+                                       "err_vs_direct": float(np.abs(pi - ref).sum())}
+            print(f"# solve {fmt} {prec}: {solves[f'{fmt}_{prec}']}", file=sys.stderr, flush=True)
+    line = {"metric": "time to a change of 1e-13 on the skip-free generator", "unit": "s",
+            "value": min(v["seconds"] for v in solves.values()), "higher_is_better": False,
+            "n_gpus": 1, "dtype": "f64 (mixed: f32+f64)", "data": "synthetic",
+            "config": {"workload": f"skipfree_b{b}_L{L}_m{m}", "levels": L, "block": m,
+                       "bandwidth": b, "N": L * m, "seed": seed},
+            "sweep_rates": runs, "solves": solves}
     print(json.dumps(line), flush=True)
 
 
