@@ -648,6 +648,13 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     const T sc = (T)inv_old;
     const T *wb = a.blk + ((size_t)ic * NB + B) * BS + c * VEC;
 
+    // the ELL table entries of the level's off-diagonal blocks
+    EllEntry te[2 * B];
+#pragma unroll
+    for (int slot = 0; slot < 2 * B; ++slot) {
+        const int d = slot < B ? slot - B : slot - B + 1;
+        te[slot] = tab[(size_t)ic * NB + (d + B)];
+    }
     // rows of W_i stream while the sparse part runs
     VT vpre[PF];
 #pragma unroll
@@ -668,28 +675,43 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     }
     __syncthreads();
 
-    // r_i[j] = sum_d sum_k val[k][j] * v_{i+d}[idx[k][j]], a quad of slots per load
+    // r_i[j] = sum_d sum_k val[k][j] * v_{i+d}[idx[k][j]], a quad of slots per load.
+    // The table entries are read before the staging barrier, and each pass
+    // keeps U quads of one block in flight (the gather is otherwise bound by
+    // one load round trip per quad); the sums keep the quad order, so the
+    // result does not depend on U.
     const int j = tt % MP, gg0 = tt / MP;
     T accs = 0;
 #pragma unroll
     for (int slot = 0; slot < 2 * B; ++slot) {
-        const int d = slot < B ? slot - B : slot - B + 1;
-        const EllEntry e = tab[(size_t)ic * NB + (d + B)];
+        const EllEntry e = te[slot];
         const T *sv = src + slot * MP;
         const int Kq = e.K >> 2;
-        for (int kq = gg0; kq < Kq; kq += G) {
-            const size_t o = (size_t)e.off + ((size_t)kq * MP + j) * 4;
-            const unsigned int r4 = __builtin_nontemporal_load((const unsigned int *)(ell_idx + o));
-            if constexpr (sizeof(T) == 8) {
-                const VT v01 = __builtin_nontemporal_load((const VT *)(ell_val + o));
-                const VT v23 = __builtin_nontemporal_load((const VT *)(ell_val + o + 2));
-                accs += v01[0] * sv[r4 & 0xff] + v01[1] * sv[(r4 >> 8) & 0xff] +
-                        v23[0] * sv[(r4 >> 16) & 0xff] + v23[1] * sv[r4 >> 24];
-            } else {
-                const VT v4 = __builtin_nontemporal_load((const VT *)(ell_val + o));
-                accs += v4[0] * sv[r4 & 0xff] + v4[1] * sv[(r4 >> 8) & 0xff] +
-                        v4[2] * sv[(r4 >> 16) & 0xff] + v4[3] * sv[r4 >> 24];
+        constexpr int U = sizeof(T) == 8 ? 2 : 4;   // FP64 quads hold twice the registers
+        for (int kq0 = gg0; kq0 < Kq; kq0 += G * U) {
+            unsigned int r4[U];
+            T v[U][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int kq = kq0 + u * G;
+                if (kq < Kq) {
+                    const size_t o = (size_t)e.off + ((size_t)kq * MP + j) * 4;
+                    r4[u] = __builtin_nontemporal_load((const unsigned int *)(ell_idx + o));
+                    if constexpr (sizeof(T) == 8) {
+                        const VT v01 = __builtin_nontemporal_load((const VT *)(ell_val + o));
+                        const VT v23 = __builtin_nontemporal_load((const VT *)(ell_val + o + 2));
+                        v[u][0] = v01[0], v[u][1] = v01[1], v[u][2] = v23[0], v[u][3] = v23[1];
+                    } else {
+                        const VT v4 = __builtin_nontemporal_load((const VT *)(ell_val + o));
+                        v[u][0] = v4[0], v[u][1] = v4[1], v[u][2] = v4[2], v[u][3] = v4[3];
+                    }
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (kq0 + u * G < Kq)
+                    accs += v[u][0] * sv[r4[u] & 0xff] + v[u][1] * sv[(r4[u] >> 8) & 0xff] +
+                            v[u][2] * sv[(r4[u] >> 16) & 0xff] + v[u][3] * sv[r4[u] >> 24];
         }
     }
     red[gg0 * MP + j] = accs;
