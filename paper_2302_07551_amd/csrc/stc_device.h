@@ -92,45 +92,85 @@ __device__ inline void cstore(T *p, T v) {
     else *p = v;
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Compensated sums (the normalisation e^T z and the change are FP64 sums of
+// up to millions of terms): every addition is an exact TwoSum whose
+// rounding error is carried in a second word, in a fixed order, so the
+// result is deterministic and its error stays at a few units of the last
+// place whatever the number of terms.
+__device__ inline void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
 }
 
-// Fixed-order workgroup sum (every thread gets the same value).
-__device__ inline double block_sum(double v, double *sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double t = 0.0;
-#pragma unroll
-    for (int j = 0; j < kWG / 64; ++j) t += sh[j];
-    return t;
+// (hi, lo) += (h2, l2)
+__device__ inline void dd_add(double &hi, double &lo, double h2, double l2) {
+    double s, e;
+    two_sum(hi, h2, s, e);
+    hi = s;
+    lo = (lo + l2) + e;
 }
 
-// Two fixed-order workgroup sums with one pair of barriers (the same
-// arithmetic as two block_sum calls); sh holds 2 * kWG / 64 doubles.
-__device__ inline void block_sum2(double &a, double &b, double *sh) {
-    a = wave_sum(a);
-    b = wave_sum(b);
+// (hi, lo) += v, for sequential accumulation in a thread
+__device__ inline void dd_acc(double &hi, double &lo, double v) {
+    double s, e;
+    two_sum(hi, v, s, e);
+    hi = s;
+    lo += e;
+}
+
+// Butterfly over the wave: every lane ends with the same pair (TwoSum is
+// symmetric in its arguments: same sum, same exact error).
+__device__ inline void wave_sum_dd(double &hi, double &lo) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dd_add(hi, lo, __shfl_xor(hi, o, 64), __shfl_xor(lo, o, 64));
+}
+
+// Fixed-order compensated workgroup sum of the pairs (hi, lo); every thread
+// gets the same value.  sh holds 4 * kWG / 64 doubles.
+__device__ inline double block_sum_dd(double hi, double lo, double *sh) {
+    wave_sum_dd(hi, lo);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0) {
-        sh[w] = a;
-        sh[kWG / 64 + w] = b;
+        sh[2 * w] = hi;
+        sh[2 * w + 1] = lo;
     }
     __syncthreads();
-    double ta = 0.0, tb = 0.0;
+    double th = sh[0], tl = sh[1];
 #pragma unroll
-    for (int j = 0; j < kWG / 64; ++j) {
-        ta += sh[j];
-        tb += sh[kWG / 64 + j];
+    for (int j = 1; j < kWG / 64; ++j) dd_add(th, tl, sh[2 * j], sh[2 * j + 1]);
+    return th + tl;
+}
+
+__device__ inline double block_sum(double v, double *sh) { return block_sum_dd(v, 0.0, sh); }
+
+// Two compensated workgroup sums with one pair of barriers (the same
+// arithmetic as two block_sum calls).
+__device__ inline void block_sum2_dd(double &ah, double al, double &bh, double bl, double *sh) {
+    wave_sum_dd(ah, al);
+    wave_sum_dd(bh, bl);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[4 * w] = ah;
+        sh[4 * w + 1] = al;
+        sh[4 * w + 2] = bh;
+        sh[4 * w + 3] = bl;
     }
-    a = ta;
-    b = tb;
+    __syncthreads();
+    double th = sh[0], tl = sh[1], uh = sh[2], ul = sh[3];
+#pragma unroll
+    for (int j = 1; j < kWG / 64; ++j) {
+        dd_add(th, tl, sh[4 * j], sh[4 * j + 1]);
+        dd_add(uh, ul, sh[4 * j + 2], sh[4 * j + 3]);
+    }
+    ah = th + tl;
+    bh = uh + ul;
+}
+
+__device__ inline void block_sum2(double &a, double &b, double *sh) {
+    block_sum2_dd(a, 0.0, b, 0.0, sh);
 }
 
 __device__ inline double block_max(double v, double *sh) {
@@ -169,13 +209,14 @@ struct ChainView {
 template <bool COH = false>
 __device__ inline void partial_sums(const double *ps, const double *pd, int n, bool want_d,
                                     double *sh, double &S, double &D) {
-    double s1 = 0.0, s2 = 0.0;
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
     for (int j = threadIdx.x; j < n; j += kWG) {
-        s1 += cload<COH>(ps + j);
-        if (want_d) s2 += cload<COH>(pd + j);
+        dd_acc(s1, c1, cload<COH>(ps + j));
+        if (want_d) dd_acc(s2, c2, cload<COH>(pd + j));
     }
-    S = block_sum(s1, sh);
-    D = want_d ? block_sum(s2, sh) : 0.0;
+    block_sum2_dd(s1, c1, s2, c2, sh);
+    S = s1;
+    D = want_d ? s2 : 0.0;
 }
 
 // Record sweep s in the state: 1 / e^T W_s and the change of sweep s - 2
@@ -298,7 +339,7 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
     __syncthreads();
 
-    double zs = 0.0, dd = 0.0;
+    double zs = 0.0, zc = 0.0, dd = 0.0, dc = 0.0;
     if (live && active) {
 #pragma unroll
         for (int e = tt; e < MP; e += TS) {
@@ -306,18 +347,18 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
 #pragma unroll
             for (int gg = 0; gg < R; ++gg) z += red[gg * MP + e];
             cstore<COH>(w_new + (size_t)i * MP + e, z);
-            zs += (double)z;
+            dd_acc(zs, zc, (double)z);
             if (a.s >= 3) {
                 // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
                 const double i2 = cload<COH>(&st->inv_sigma[(a.s - 2) & kRingMask]);
                 const double i3 = cload<COH>(&st->inv_sigma[(a.s - 3) & kRingMask]);
-                dd += fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + e) * i2 -
-                           (double)cload<COH>(a.w_d2 + (size_t)i * MP + e) * i3);
+                dd_acc(dd, dc, fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + e) * i2 -
+                                    (double)cload<COH>(a.w_d2 + (size_t)i * MP + e) * i3));
             }
         }
     }
     double S = zs, D = dd;
-    block_sum2(S, D, sh);
+    block_sum2_dd(S, zc, D, dc, sh);
     if (live && tid == 0) {
         cstore<COH>(a.part_sum + a.slot0 + q, S);
         cstore<COH>(a.part_diff + a.slot0 + q, D);
@@ -356,7 +397,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
         fold_previous(a, sh);
         return;
@@ -571,7 +612,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_flow(FlowLaunch f) {
     using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     __shared__ int sh_ok, sh_live;
     __shared__ double sh_kappa;
     if ((int)blockIdx.x == f.G) {
@@ -767,7 +808,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ T src[TL::LPW * 2 * B * MP];
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
         fold_previous(a, sh);
         return;
@@ -792,7 +833,7 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
     using TL = Tile<T, MP, variant_rg(MP, 0)>;   // the tile of launch variant 0
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     const int off = cls[0], n = cls[1];
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const WorkItem w = items[off + it];
@@ -847,7 +888,7 @@ __global__ __launch_bounds__(kWG) void k_residual(const double *blk, const doubl
                   LPW = TL::LPW;
     constexpr size_t BS = (size_t)MP * MP;
     __shared__ double red[LPW][R][MP];
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
 
     const int tid = threadIdx.x;
     const int team = tid / TS, tt = tid - team * TS;
@@ -898,22 +939,24 @@ __global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, const Dev
                                                long long k, int L, int parity_a, int groups_a,
                                                double *part) {
     using TL = Tile<T, MP, RG>;
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     const int tid = threadIdx.x;
     const int team = tid / TL::TS, tt = tid - team * TL::TS;
     const bool in_a = (int)blockIdx.x < groups_a;
     const int q = in_a ? blockIdx.x : blockIdx.x - groups_a;
     const int parity = in_a ? parity_a : 1 - parity_a;
     const int i = parity + 2 * (q * TL::LPW + team);
-    double dd = 0.0;
+    // the same terms, order and compensated sums as the sweep kernels' change
+    double dd = 0.0, dc = 0.0;
     if (i < L) {
         const double i2 = st->inv_sigma[k & kRingMask];
         const double i3 = st->inv_sigma[(k - 1) & kRingMask];
 #pragma unroll
         for (int e = tt; e < MP; e += TL::TS)
-            dd += fabs((double)w[(size_t)i * MP + e] * i2 - (double)wp[(size_t)i * MP + e] * i3);
+            dd_acc(dd, dc, fabs((double)w[(size_t)i * MP + e] * i2 -
+                                (double)wp[(size_t)i * MP + e] * i3));
     }
-    const double D = block_sum(dd, sh);
+    const double D = block_sum_dd(dd, dc, sh);
     if (tid == 0) part[blockIdx.x] = D;
 }
 
@@ -925,9 +968,9 @@ template <typename T>
 __global__ __launch_bounds__(kWG) void k_load(const double *x, const long long *off,
                                                const int *sizes, int L, int MP, T *w,
                                                double *part, int slot) {
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     const size_t n = (size_t)L * MP;
-    double s = 0.0, bad = 0.0;
+    double s = 0.0, sc = 0.0, bad = 0.0;
     for (size_t j = blockIdx.x * (size_t)kWG + threadIdx.x; j < n; j += (size_t)gridDim.x * kWG) {
         const int lev = (int)(j / MP), col = (int)(j - (size_t)lev * MP);
         double v = 0.0;
@@ -938,9 +981,9 @@ __global__ __launch_bounds__(kWG) void k_load(const double *x, const long long *
         }
         const T t = (T)v;
         w[j] = t;
-        s += (double)t;
+        dd_acc(s, sc, (double)t);
     }
-    s = block_sum(s, sh);
+    s = block_sum_dd(s, sc, sh);
     bad = block_max(bad, sh);
     if (threadIdx.x == 0) {
         part[2 * blockIdx.x] = s;

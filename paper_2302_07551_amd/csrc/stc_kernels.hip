@@ -16,7 +16,7 @@ __global__ void k_flow_reset(unsigned *flags, int n) {
 __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
                                                          const double *part_diff, int nslots,
                                                          DevState *st, long long s, double tol) {
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     finalize_chain(part_sum, part_diff, nslots, st, s, tol, sh);
 }
 
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
 
 __global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
                                                          const int *nchains) {
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     if ((int)blockIdx.x >= *nchains) return;
     const ChainDesc &d = chains[blockIdx.x];
     DevState *st = d.st;
@@ -70,14 +70,14 @@ __global__ void k_rearm(DevState *st, long long k) {
 
 __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int mode,
                                                  DevState *st, long long slot, double tol) {
-    __shared__ double sh[2 * kWG / 64];
+    __shared__ double sh[4 * kWG / 64];
     const int stride = (mode == kReduceLoad) ? 2 : 1;
-    double t = 0.0, b = 0.0;
+    double t = 0.0, tc = 0.0, b = 0.0;
     for (int j = threadIdx.x; j < n; j += kWG) {
-        t += part[stride * j];
+        dd_acc(t, tc, part[stride * j]);
         if (mode == kReduceLoad) b = fmax(b, part[2 * j + 1]);
     }
-    t = block_sum(t, sh);
+    t = block_sum_dd(t, tc, sh);
     if (mode == kReduceLoad) b = block_max(b, sh);
     if (threadIdx.x != 0) return;
     if (mode == kReduceResidual) {
