@@ -92,11 +92,14 @@ __device__ inline void cstore(T *p, T v) {
     else *p = v;
 }
 
-// Compensated sums (the normalisation e^T z and the change are FP64 sums of
-// up to millions of terms): every addition is an exact TwoSum whose
-// rounding error is carried in a second word, in a fixed order, so the
-// result is deterministic and its error stays at a few units of the last
-// place whatever the number of terms.
+// Sums for the normalisation e^T z and the change.  Each workgroup of a
+// sweep sums the at most LPW * MP terms of its own levels with a plain
+// fixed-order tree (error below log2(LPW * MP) units of the last place,
+// independent of the chain's length).  The fold of the per-group partials,
+// whose count grows with the chain, is compensated: every addition is an
+// exact TwoSum whose rounding error is carried in a second word, in a
+// fixed order, so the total stays deterministic and its error does not
+// grow with the number of groups.
 __device__ inline void two_sum(double a, double b, double &s, double &e) {
     s = a + b;
     const double bp = s - a;
@@ -143,10 +146,8 @@ __device__ inline double block_sum_dd(double hi, double lo, double *sh) {
     return th + tl;
 }
 
-__device__ inline double block_sum(double v, double *sh) { return block_sum_dd(v, 0.0, sh); }
-
 // Two compensated workgroup sums with one pair of barriers (the same
-// arithmetic as two block_sum calls).
+// arithmetic as two block_sum_dd calls).
 __device__ inline void block_sum2_dd(double &ah, double al, double &bh, double bl, double *sh) {
     wave_sum_dd(ah, al);
     wave_sum_dd(bh, bl);
@@ -169,8 +170,46 @@ __device__ inline void block_sum2_dd(double &ah, double al, double &bh, double b
     bh = uh + ul;
 }
 
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Plain fixed-order workgroup sum (every thread gets the same value), for
+// the few hundred terms of one group.
+__device__ inline double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWG / 64; ++j) t += sh[j];
+    return t;
+}
+
+// Two plain fixed-order workgroup sums with one pair of barriers (the same
+// arithmetic as two block_sum calls).
 __device__ inline void block_sum2(double &a, double &b, double *sh) {
-    block_sum2_dd(a, 0.0, b, 0.0, sh);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = a;
+        sh[kWG / 64 + w] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int j = 0; j < kWG / 64; ++j) {
+        ta += sh[j];
+        tb += sh[kWG / 64 + j];
+    }
+    a = ta;
+    b = tb;
 }
 
 __device__ inline double block_max(double v, double *sh) {
@@ -339,7 +378,7 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
     for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
     __syncthreads();
 
-    double zs = 0.0, zc = 0.0, dd = 0.0, dc = 0.0;
+    double zs = 0.0, dd = 0.0;
     if (live && active) {
 #pragma unroll
         for (int e = tt; e < MP; e += TS) {
@@ -347,18 +386,18 @@ __device__ inline void sweep_group(const ChainView<T> &a, int q, bool live, doub
 #pragma unroll
             for (int gg = 0; gg < R; ++gg) z += red[gg * MP + e];
             cstore<COH>(w_new + (size_t)i * MP + e, z);
-            dd_acc(zs, zc, (double)z);
+            zs += (double)z;
             if (a.s >= 3) {
                 // ||x^(s-2) - x^(s-3)||_1 terms: both scales are recorded by now
                 const double i2 = cload<COH>(&st->inv_sigma[(a.s - 2) & kRingMask]);
                 const double i3 = cload<COH>(&st->inv_sigma[(a.s - 3) & kRingMask]);
-                dd_acc(dd, dc, fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + e) * i2 -
-                                    (double)cload<COH>(a.w_d2 + (size_t)i * MP + e) * i3));
+                dd += fabs((double)cload<COH>(a.w_d1 + (size_t)i * MP + e) * i2 -
+                           (double)cload<COH>(a.w_d2 + (size_t)i * MP + e) * i3);
             }
         }
     }
     double S = zs, D = dd;
-    block_sum2_dd(S, zc, D, dc, sh);
+    block_sum2(S, D, sh);
     if (live && tid == 0) {
         cstore<COH>(a.part_sum + a.slot0 + q, S);
         cstore<COH>(a.part_diff + a.slot0 + q, D);
@@ -946,17 +985,16 @@ __global__ __launch_bounds__(kWG) void k_diff(const T *w, const T *wp, const Dev
     const int q = in_a ? blockIdx.x : blockIdx.x - groups_a;
     const int parity = in_a ? parity_a : 1 - parity_a;
     const int i = parity + 2 * (q * TL::LPW + team);
-    // the same terms, order and compensated sums as the sweep kernels' change
-    double dd = 0.0, dc = 0.0;
+    // the same terms, order and sums as the sweep kernels' change
+    double dd = 0.0;
     if (i < L) {
         const double i2 = st->inv_sigma[k & kRingMask];
         const double i3 = st->inv_sigma[(k - 1) & kRingMask];
 #pragma unroll
         for (int e = tt; e < MP; e += TL::TS)
-            dd_acc(dd, dc, fabs((double)w[(size_t)i * MP + e] * i2 -
-                                (double)wp[(size_t)i * MP + e] * i3));
+            dd += fabs((double)w[(size_t)i * MP + e] * i2 - (double)wp[(size_t)i * MP + e] * i3);
     }
-    const double D = block_sum_dd(dd, dc, sh);
+    const double D = block_sum(dd, sh);
     if (tid == 0) part[blockIdx.x] = D;
 }
 
