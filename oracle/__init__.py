@@ -13,7 +13,9 @@ Contents (each function cites the passage it follows):
   level_reduction.py  block (level-by-level) GTH for block-banded Q - the
                       reference pi for large chains.
   staircase.py        Algorithm 2 (STAIR1 / STAIR2) and Algorithm 1 (JGS)
-                      written from section 2, in FP64 with LU block solves.
+                      written from section 2, in FP64 with LU block solves,
+                      on block-banded generators (BlockSystem) and on
+                      generators of any block pattern (SparseBlockSystem).
   splittings.py       the dense regular splittings Q^T = M - N of section 2
                       (block Jacobi, block Gauss-Seidel, the [BB] composite,
                       stair matrices M1 / M2) and their iteration spectra.

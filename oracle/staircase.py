@@ -77,6 +77,56 @@ class BlockSystem:
     def band(self, i: int):
         return range(max(0, i - self.b), min(self.L, i + self.b + 1))
 
+    def residual(self, x: np.ndarray) -> float:
+        return residual_1(self.blocks, self.sizes, self.b, x)
+
+
+class SparseBlockSystem:
+    """Block view of A = Q^T for a generator of any block pattern (the general
+    localized case of section 2: level i may couple to any level k).
+
+    Q is given as an N x N scipy.sparse matrix, states numbered level by level
+    with the given level sizes.  Only the nonzero blocks are kept, densified:
+    band(i) lists the levels k (i included) whose block A_{i,k} is nonzero, so
+    the sweep below visits exactly the blocks the first loop of Algorithm 2
+    sums over."""
+
+    def __init__(self, Q, sizes):
+        import scipy.sparse as sp
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.L = len(self.sizes)
+        self.off = level_offsets(self.sizes)
+        self.N = int(self.off[-1])
+        self.Q = sp.csr_matrix(Q)
+        if self.Q.shape != (self.N, self.N):
+            raise ValueError("Q must be N x N with N = sum of the level sizes")
+        At = self.Q.T.tocsr()   # A = Q^T
+        lev = np.repeat(np.arange(self.L), self.sizes)
+        self.blocks = {}
+        self.nbr = []
+        for i in range(self.L):
+            rows = At[self.off[i]: self.off[i + 1]]
+            ks = sorted(set(lev[rows.indices].tolist()) | {i})
+            for k in ks:
+                self.blocks[(i, k)] = rows[:, self.off[k]: self.off[k + 1]].toarray()
+            self.nbr.append(ks)
+
+    def A(self, i: int, k: int) -> np.ndarray:
+        blk = self.blocks.get((i, k))
+        if blk is None:
+            return np.zeros((self.sizes[i], self.sizes[k]))
+        return blk
+
+    def seg(self, x: np.ndarray, i: int) -> np.ndarray:
+        return x[self.off[i]: self.off[i + 1]]
+
+    def band(self, i: int):
+        return self.nbr[i]
+
+    def residual(self, x: np.ndarray) -> float:
+        """||Q^T x||_1 (eq. (1)), by one sparse product."""
+        return float(np.abs(self.Q.T @ x).sum())
+
 
 def phase_sets(L: int, stair_type: int):
     """(diagonal-only levels, stair levels), 0-based, for stair type 1 or 2."""
@@ -139,18 +189,25 @@ def staircase_solve(blocks: np.ndarray, sizes, b: int, *, stair_type: int = 1,
                     keep_history: bool = False) -> SolveResult:
     """Algorithm 2: repeat sweeps until the stop quantity is <= tol or maxit
     sweeps were done.  Default start e/N; the start is normalised first."""
-    sys = BlockSystem(blocks, sizes, b)
+    return solve_system(BlockSystem(blocks, sizes, b), stair_type=stair_type, x0=x0, tol=tol,
+                        maxit=maxit, stop=stop, keep_history=keep_history)
+
+
+def solve_system(sys, *, stair_type: int = 1, x0: np.ndarray | None = None, tol: float = 1e-9,
+                 maxit: int = 10_000, stop: str = STOP_DIFF,
+                 keep_history: bool = False) -> SolveResult:
+    """Algorithm 2 on a block system (BlockSystem or SparseBlockSystem)."""
     x = np.full(sys.N, 1.0 / sys.N) if x0 is None else np.asarray(x0, float) / np.sum(x0)
     it, err = 0, np.inf
     hist = []
     while err > tol and it < maxit:
         z, diff = staircase_sweep(sys, x, stair_type)
-        err = diff if stop == STOP_DIFF else residual_1(blocks, sys.sizes, b, z)
+        err = diff if stop == STOP_DIFF else sys.residual(z)
         if keep_history:
             hist.append(err)
         x = z
         it += 1
-    res = residual_1(blocks, sys.sizes, b, x)
+    res = sys.residual(x)
     return SolveResult(x, it, float(err), res, bool(err <= tol), hist)
 
 

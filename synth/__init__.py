@@ -1,6 +1,7 @@
 """Seeded synthetic inputs shared by the oracle tests and the GPU path.
 
-This package builds block-banded Markov generators and start vectors.  It holds
+This package builds block-banded Markov generators, generators of any block
+pattern (CSR) and start vectors.  It holds
 none of the staircase method's arithmetic: only random draws, masks, and the
 generator's defining convention that each row of Q sums to zero.
 """
@@ -14,4 +15,11 @@ from .chains import (  # noqa: F401
     served_stream,
     positive_start,
     config_seed,
+)
+from .general import (  # noqa: F401
+    SparseGenerator,
+    equal_levels,
+    mutual_exclusion,
+    mutual_exclusion_states,
+    localized,
 )

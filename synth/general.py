@@ -1,0 +1,203 @@
+"""Seeded generators of any block pattern (input construction only).
+
+These are CSR generators whose nonzero blocks are not confined to a band
+around the diagonal: the general localized case of section 2, where level i
+may exchange probability with any other level.  The states are numbered level
+by level, and the levels are consecutive runs of the state order, of equal size
+with a smaller last one (the block partition used in section 3).
+
+Workload recipes (stand-ins for the paper's Markov models, whose rates are not
+given):
+  * ``mutual_exclusion``  the mutual-exclusion model of the fourth test matrix
+                 of section 3: n distinguishable processes, each sleeping or
+                 using a resource, at most r of them using it at once.  A
+                 sleeping process p asks at rate lam_p and enters if fewer
+                 than r processes hold the resource (otherwise nothing
+                 changes); a user leaves at rate mu_p.  States are ordered by
+                 the number of users, then lexicographically by the set of
+                 users.  n = 16, r = 12 gives N = 64839 as in the paper.  The
+                 rates are seeded draws (the paper does not give them).
+  * ``localized``  random generator with blocks at every level distance up to
+                 `up` above and `down` below the diagonal, rates scaled by
+                 decay^(|d| - 1), a few long jumps to random far levels, and a
+                 nearest-neighbour backbone that makes the chain irreducible;
+                 ragged level sizes on request.  up = L, down = 1 gives a
+                 block upper Hessenberg generator (the shape of the first test
+                 matrix of section 3).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from itertools import combinations
+from math import comb
+
+import numpy as np
+
+
+def equal_levels(N: int, m: int) -> np.ndarray:
+    """Level sizes: m states per level, the remainder in a smaller last level."""
+    L = (N + m - 1) // m
+    sizes = np.full(L, m, dtype=np.int32)
+    sizes[-1] = N - m * (L - 1)
+    return sizes
+
+
+@dataclass
+class SparseGenerator:
+    """An N x N generator in CSR form with a level partition."""
+
+    indptr: np.ndarray      # int64 [N+1]
+    indices: np.ndarray     # int32 [nnz]
+    data: np.ndarray        # float64 [nnz]
+    sizes: np.ndarray       # int32 [L]
+    name: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(self.sizes.sum())
+
+    @property
+    def L(self) -> int:
+        return len(self.sizes)
+
+    @property
+    def m(self) -> int:
+        return int(self.sizes.max())
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indptr[-1])
+
+    @property
+    def offsets(self) -> np.ndarray:
+        off = np.zeros(self.L + 1, dtype=np.int64)
+        np.cumsum(self.sizes, out=off[1:])
+        return off
+
+    @property
+    def csr(self):
+        return self.indptr, self.indices, self.data
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.data, self.indices, self.indptr), shape=(self.N, self.N))
+
+    def level_of(self) -> np.ndarray:
+        return np.repeat(np.arange(self.L), self.sizes)
+
+    def block_reach(self) -> int:
+        """Largest level distance |level(row) - level(col)| of a nonzero rate."""
+        lev = self.level_of()
+        rows = np.repeat(np.arange(self.N), np.diff(self.indptr))
+        nz = self.data != 0.0
+        if not nz.any():
+            return 0
+        return int(np.abs(lev[rows[nz]] - lev[self.indices[nz]]).max())
+
+
+def _from_triplets(rows, cols, vals, N: int, sizes, name: str, extra=None) -> SparseGenerator:
+    """Assemble off-diagonal rates into CSR with the diagonal that makes every
+    row sum to 0 (the generator convention)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    out = np.bincount(rows, weights=vals, minlength=N)
+    rows = np.concatenate([rows, np.arange(N)])
+    cols = np.concatenate([cols, np.arange(N)])
+    vals = np.concatenate([vals, -out])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    # merge repeated (row, col) pairs
+    keep = np.ones(len(rows), dtype=bool)
+    keep[1:] = (rows[1:] != rows[:-1]) | (cols[1:] != cols[:-1])
+    if not keep.all():
+        starts = np.flatnonzero(keep)
+        vals = np.add.reduceat(vals, starts)
+        rows, cols = rows[starts], cols[starts]
+    indptr = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=N), out=indptr[1:])
+    return SparseGenerator(indptr, cols.astype(np.int32), vals, np.asarray(sizes, dtype=np.int32),
+                           name, extra or {})
+
+
+def mutual_exclusion_states(n: int, r: int):
+    """States (sets of users as bit masks) in the model's order: by the number
+    of users, then lexicographically; returns (masks, index of each mask)."""
+    masks = []
+    for k in range(r + 1):
+        for users in combinations(range(n), k):
+            masks.append(sum(1 << p for p in users))
+    masks = np.array(masks, dtype=np.int64)
+    index = {int(s): i for i, s in enumerate(masks)}
+    return masks, index
+
+
+def mutual_exclusion(n: int = 16, r: int = 12, seed: int = 0, *, m: int = 128,
+                     lam_range=(0.2, 1.0), mu_range=(0.5, 1.5)) -> SparseGenerator:
+    """The mutual-exclusion generator (see the module notes).  extra holds
+    the rates lam, mu and the state masks."""
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(*lam_range, size=n)
+    mu = rng.uniform(*mu_range, size=n)
+    masks, index = mutual_exclusion_states(n, r)
+    N = len(masks)
+    assert N == sum(comb(n, k) for k in range(r + 1))
+    rows, cols, vals = [], [], []
+    for s, u in enumerate(masks.tolist()):
+        users = bin(u).count("1")
+        for p in range(n):
+            bit = 1 << p
+            if u & bit:
+                rows.append(s); cols.append(index[u ^ bit]); vals.append(mu[p])
+            elif users < r:
+                rows.append(s); cols.append(index[u | bit]); vals.append(lam[p])
+    return _from_triplets(rows, cols, vals, N, equal_levels(N, m), f"mutex_n{n}_r{r}_m{m}",
+                          {"lam": lam, "mu": mu, "masks": masks, "n": n, "r": r})
+
+
+def localized(L: int, m: int, seed: int, *, up: int = 3, down: int = 3, density: float = 0.2,
+              decay: float = 0.5, jumps: int = 2, ragged: bool = False,
+              backbone: float = 0.05) -> SparseGenerator:
+    """Random generator with nonzero blocks at level distances 1..up above and
+    1..down below the diagonal, `jumps` extra blocks per level at random far
+    levels, and a backbone s <-> s+1 of rate `backbone` (irreducibility)."""
+    rng = np.random.default_rng(seed)
+    if ragged:
+        sizes = rng.integers(max(1, m // 2), m + 1, size=L).astype(np.int32)
+        sizes[0] = m
+    else:
+        sizes = np.full(L, m, dtype=np.int32)
+    off = np.zeros(L + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    N = int(off[-1])
+    rows, cols, vals = [], [], []
+
+    def block(i, k, scale):
+        mask = rng.random((sizes[i], sizes[k])) < density
+        if i == k:
+            np.fill_diagonal(mask, False)
+        r, c = np.nonzero(mask)
+        rows.append(r + off[i])
+        cols.append(c + off[k])
+        vals.append(rng.uniform(0.0, scale, size=len(r)))
+
+    for i in range(L):
+        block(i, i, 1.0)
+        for d in range(1, up + 1):
+            if i + d < L:
+                block(i, i + d, decay ** (d - 1))
+        for d in range(1, down + 1):
+            if i - d >= 0:
+                block(i, i - d, decay ** (d - 1))
+        for _ in range(jumps):
+            k = int(rng.integers(L))
+            if abs(k - i) > max(up, down):
+                block(i, k, decay ** 3)
+    s = np.arange(N - 1)
+    rows += [s, s + 1]
+    cols += [s + 1, s]
+    vals += [np.full(N - 1, backbone), np.full(N - 1, backbone)]
+    return _from_triplets(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), N,
+                          sizes, f"localized_L{L}_m{m}_up{up}_down{down}",
+                          {"up": up, "down": down})

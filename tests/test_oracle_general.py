@@ -1,0 +1,164 @@
+"""Pins of the oracle on generators of any block pattern (CPU only).
+
+The sweep of Algorithm 2 on a SparseBlockSystem is pinned against facts that
+do not come from that code:
+  * the stair-matrix definition of section 2, built densely (splittings.py),
+    gives the same normalised iterate M^{-1} N x;
+  * GTH elimination (a textbook direct solver) gives the fixed point;
+  * the mutual-exclusion model has a closed-form stationary vector: the
+    processes are independent reversible two-state chains, and blocking the
+    requests that would exceed r users truncates the joint chain to a subset
+    of its states, which keeps the product form restricted to that subset
+    (Kelly's truncation theorem for reversible chains).
+Planted mistakes (a far block dropped, far levels read fresh) must fail them.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import gth, splittings, staircase
+
+
+def _dense_step(g, x, stair_type):
+    A = g.to_scipy().T.toarray()
+    M = splittings.splitting_M(A, g.sizes, f"stair{stair_type}")
+    z = np.linalg.solve(M, (M - A) @ x)
+    return z / z.sum()
+
+
+def _start(N, seed):
+    x = np.random.default_rng(seed).uniform(0.5, 1.5, N)
+    return x / x.sum()
+
+
+def mutex_closed_form(g):
+    """pi(S) proportional to prod_{p in S} lam_p / mu_p over the states."""
+    rho = g.extra["lam"] / g.extra["mu"]
+    masks = g.extra["masks"]
+    n = g.extra["n"]
+    logw = np.zeros(len(masks))
+    for p in range(n):
+        logw += np.where((masks >> p) & 1, np.log(rho[p]), 0.0)
+    w = np.exp(logw - logw.max())
+    return w / w.sum()
+
+
+GENERAL = [
+    dict(L=12, m=6, seed=1, up=2, down=2, jumps=2, ragged=True),
+    dict(L=16, m=4, seed=2, up=16, down=1, jumps=0, ragged=False),   # block upper Hessenberg
+    dict(L=10, m=8, seed=3, up=1, down=4, jumps=3, ragged=True),
+    dict(L=2, m=5, seed=4, up=1, down=1, jumps=0, ragged=True),
+    dict(L=9, m=1, seed=5, up=3, down=3, jumps=1, ragged=False),     # scalar levels
+]
+
+
+@pytest.mark.parametrize("cfg", GENERAL, ids=lambda c: f"L{c['L']}_m{c['m']}_s{c['seed']}")
+@pytest.mark.parametrize("stair_type", [1, 2])
+def test_general_sweep_equals_stair_matrix_definition(cfg, stair_type):
+    g = synth.localized(**cfg)
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    x = _start(g.N, 7)
+    z, err = staircase.staircase_sweep(sys, x, stair_type)
+    want = _dense_step(g, x, stair_type)
+    assert np.abs(z - want).sum() < 1e-13
+    assert abs(err - np.abs(want - x).sum()) < 1e-13
+
+
+@pytest.mark.parametrize("cfg", GENERAL[:3], ids=lambda c: f"L{c['L']}_m{c['m']}_s{c['seed']}")
+def test_general_solve_reaches_gth(cfg):
+    g = synth.localized(**cfg)
+    pi = gth.gth(g.to_scipy().toarray())
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    z, _ = staircase.staircase_sweep(sys, pi, 1)
+    assert np.abs(z - pi).sum() < 1e-13           # pi is a fixed point
+    r = staircase.solve_system(sys, tol=1e-14, maxit=50_000, stop=staircase.STOP_RESIDUAL)
+    assert r.converged
+    assert np.abs(r.x - pi).sum() < 1e-9
+
+
+def test_generator_shapes():
+    g = synth.localized(16, 4, 2, up=16, down=1, jumps=0)
+    Q = g.to_scipy().toarray()
+    lev = g.level_of()
+    r, c = np.nonzero(Q)
+    assert (lev[c] - lev[r]).min() == -1          # block upper Hessenberg
+    assert g.block_reach() == 15
+    assert np.abs(Q.sum(axis=1)).max() < 1e-14
+    assert (Q - np.diag(np.diag(Q)) >= 0).all()
+
+
+def test_mutex_state_space_matches_the_model():
+    g = synth.mutual_exclusion(16, 12, 0)
+    assert g.N == 64839
+    # the scalar bandwidth of this state order is the one the paper reports
+    rows = np.repeat(np.arange(g.N), np.diff(g.indptr))
+    assert int(np.abs(rows - g.indices).max()) == 13495
+    assert np.abs(np.add.reduceat(g.data, g.indptr[:-1])).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,r,m", [(6, 3, 8), (8, 5, 16), (7, 7, 16)])
+def test_mutex_closed_form_is_stationary_and_is_the_gth_vector(n, r, m):
+    g = synth.mutual_exclusion(n, r, 11, m=m)
+    pi = mutex_closed_form(g)
+    assert np.abs(g.to_scipy().T @ pi).sum() < 1e-15
+    assert np.abs(gth.gth(g.to_scipy().toarray()) - pi).sum() < 1e-13
+
+
+@pytest.mark.parametrize("stair_type", [1, 2])
+def test_mutex_oracle_solve_reaches_closed_form(stair_type):
+    g = synth.mutual_exclusion(8, 5, 3, m=16)
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    r = staircase.solve_system(sys, stair_type=stair_type, tol=1e-14, maxit=20_000)
+    assert r.converged
+    assert np.abs(r.x - mutex_closed_form(g)).sum() < 1e-11
+
+
+def test_banded_generator_gives_the_same_sweep_both_ways():
+    g = synth.banded(14, 6, 5, b=2, density=0.4, last=4)
+    import scipy.sparse as sp
+    indptr, col, val = g.to_csr()
+    Q = sp.csr_matrix((val, col, indptr), shape=(g.N, g.N))
+    x = synth.positive_start(g, 2)
+    za, _ = staircase.staircase_sweep(staircase.BlockSystem(g.blocks, g.sizes, g.b), x)
+    zb, _ = staircase.staircase_sweep(staircase.SparseBlockSystem(Q, g.sizes), x)
+    assert np.abs(za - zb).sum() < 1e-14
+
+
+def test_general_residual_is_the_matrix_product():
+    g = synth.localized(10, 5, 8, jumps=3, ragged=True)
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    x = _start(g.N, 1)
+    want = np.abs(g.to_scipy().toarray().T @ x).sum()
+    assert abs(sys.residual(x) - want) < 1e-14
+
+
+# --- planted mistakes ------------------------------------------------------
+
+def test_dropped_far_block_is_caught(monkeypatch):
+    g = synth.localized(12, 6, 1, up=2, down=2, jumps=3, ragged=True)
+    orig = staircase.SparseBlockSystem.band
+
+    def near_only(self, i):   # forgets blocks more than one level away
+        return [k for k in orig(self, i) if abs(k - i) <= 1]
+    monkeypatch.setattr(staircase.SparseBlockSystem, "band", near_only)
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    x = _start(g.N, 7)
+    z, _ = staircase.staircase_sweep(sys, x, 1)
+    assert np.abs(z - _dense_step(g, x, 1)).sum() > 1e-6
+
+
+def test_far_levels_read_fresh_is_caught(monkeypatch):
+    """A sweep that also took the far levels from the fresh iterate (a block
+    Gauss-Seidel slip) no longer matches the stair-matrix definition."""
+    g = synth.localized(12, 6, 1, up=2, down=2, jumps=3, ragged=True)
+
+    def fresh_far(i, L, stair_type):
+        diag_only, stair = staircase.phase_sets(L, stair_type)
+        if i in stair:
+            return [k for k in range(L) if k != i and k in diag_only]
+        return [i]
+    monkeypatch.setattr(staircase, "J_set", fresh_far)
+    sys = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    x = _start(g.N, 7)
+    z, _ = staircase.staircase_sweep(sys, x, 1)
+    assert np.abs(z - _dense_step(g, x, 1)).sum() > 1e-6
