@@ -60,6 +60,7 @@ enum { STC_FP64 = 0, STC_FP32 = 1, STC_MIXED = 2 };   /* stc_options.precision *
 enum { STC_STOP_DIFF = 0, STC_STOP_RESIDUAL = 1 };     /* stc_options.stop      */
 enum { STC_MEM_HOST = 0, STC_MEM_DEVICE = 1 };         /* "where" arguments     */
 enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    */
+enum { STC_ANY_PATTERN = -1 };                         /* stc_generator.b       */
 
 /* The block generator (section 2 block partition), in one of two host forms.
  *
@@ -76,12 +77,21 @@ enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    
  * recompute_diagonal is 1.  Setup scatters the rows into blocks a range of
  * levels at a time, so it never holds a dense copy of the whole generator.
  *
+ * Any block pattern (b = STC_ANY_PATTERN; CSR input and STC_SPARSE storage
+ * only): the general localized case of section 2, where a level may couple to
+ * any other level (block upper Hessenberg generators, state spaces ordered so
+ * that transitions reach many levels away).  Every entry may lie anywhere; the
+ * near entries (levels i - 1 and i + 1, the J_i of the stair rows in
+ * Algorithm 2) are read fresh by phase B and all others from the previous
+ * iterate.  L * padded m must stay below 2^31.
+ *
  * Either way the host arrays are only read during stc_footprint_bytes and
  * stc_setup, and the caller keeps ownership. */
 typedef struct {
     int32_t L;                   /* levels, >= 2                                    */
     int32_t m;                   /* block size: max states per level, 1..128       */
-    int32_t b;                   /* block bandwidth, 1..4 (1: QBD)                  */
+    int32_t b;                   /* block bandwidth, 1..4 (1: QBD), or
+                                    STC_ANY_PATTERN                                 */
     const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */
     const double *blocks;        /* dense blocks, see above; NULL = CSR input      */
     int32_t recompute_diagonal;  /* 1: diag(Q_ii) := -(row sum of its off-diagonal
@@ -118,9 +128,10 @@ typedef struct {
                              STC_SPARSE: per block, its nonzeros grouped by
                              column and padded to the block's longest column
                              (values + 8-bit row indices), for sparse
-                             (localized) generators.  The inverse diagonal
-                             blocks are dense in both.  Batches take dense
-                             chains only.                                     */
+                             (localized) generators; with b = STC_ANY_PATTERN
+                             one ELL per level (values + 32-bit indices).
+                             The inverse diagonal blocks are dense in both.
+                             Batches take dense chains only.                  */
 } stc_options;
 
 typedef struct {

@@ -1,0 +1,301 @@
+// Sweep and residual kernels for generators of any block pattern.
+//
+// The levels of such a generator may exchange probability with any other
+// level (the general localized case of section 2), so the off-diagonal part
+// of a level cannot be staged as a fixed set of neighbour blocks.  Each level
+// keeps its off-diagonal entries of A = Q^T as a column-major ELL (GenEntry)
+// with 32-bit indices into the padded iterate, split into the near segment
+// (sources in levels i - 1 and i + 1, the J_i of a stair row) and the far
+// segment (all other levels).  Algorithm 2 then reads, per level i:
+//   phase A (diagonal-only rows): r_i = -sum_{k != i} A_{i,k} x_k, all from the
+//            previous iterate;
+//   phase B (stair rows): the near segment from the fresh phase-A iterate,
+//            the far segment from the previous one;
+// and solves z_i = W_i r_i with the dense inverse W_i = (-A_{i,i})^{-1}.
+// The normalisation, the change and the stopping test are those of the
+// banded kernels (lagged scales, per-group partials, phase B's fold).
+#include "stc_device.h"
+
+namespace stc {
+
+typedef int Int4 __attribute__((ext_vector_type(4)));
+
+// sum over the quads [0, Kq) of column j of one ELL segment of
+// val[slot] * src[idx[slot]]; the lanes gg0, gg0 + G, ... of the column split
+// the quads, U quads of a lane in flight per pass (the gathers depend on the
+// index loads, so one quad at a time would wait two round trips each).
+template <typename T, int MP, int G>
+__device__ inline T gen_gather(const T *val, const int *idx, size_t base, int Kq, int j, int gg0,
+                               const T *src) {
+    using VT = typename Vec16<T>::type;
+    constexpr int U = sizeof(T) == 8 ? 2 : 4;
+    T acc = 0;
+    for (int kq0 = gg0; kq0 < Kq; kq0 += G * U) {
+        Int4 r4[U];
+        T v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kq = kq0 + u * G;
+            r4[u] = (Int4)0;
+            if (kq < Kq) {
+                const size_t o = base + ((size_t)kq * MP + j) * 4;
+                r4[u] = __builtin_nontemporal_load((const Int4 *)(idx + o));
+                if constexpr (sizeof(T) == 8) {
+                    const VT v01 = __builtin_nontemporal_load((const VT *)(val + o));
+                    const VT v23 = __builtin_nontemporal_load((const VT *)(val + o + 2));
+                    v[u][0] = v01[0], v[u][1] = v01[1], v[u][2] = v23[0], v[u][3] = v23[1];
+                } else {
+                    const VT v4 = __builtin_nontemporal_load((const VT *)(val + o));
+                    v[u][0] = v4[0], v[u][1] = v4[1], v[u][2] = v4[2], v[u][3] = v4[3];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (kq0 + u * G < Kq)
+                acc += v[u][0] * src[r4[u][0]] + v[u][1] * src[r4[u][1]] +
+                       v[u][2] * src[r4[u][2]] + v[u][3] * src[r4[u][3]];
+    }
+    return acc;
+}
+
+// One workgroup of a half-sweep: LPW levels (team t of group q owns level
+// parity + 2 (q LPW + t)), then the group's partial sums into slot slot0 + q.
+template <typename T, int MP, bool PHB>
+__device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *tab, const T *val,
+                                       const int *idx, int q, bool live, double inv_old,
+                                       T *red_base, T *rv_base, double *sh) {
+    using TL = Tile<T, MP, 8>;
+    using VT = typename Vec16<T>::type;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
+                  LPW = TL::LPW, PF = TL::PF;
+    constexpr int G = TS / MP;            // lanes splitting the ELL slots of a column
+    constexpr size_t BS = (size_t)MP * MP;
+    static_assert(G >= 1 && G <= R, "team narrower than a block");
+
+    const DevState *st = a.st;
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    T *red = red_base + team * (R * MP);
+    T *rv = rv_base + team * MP;
+    const int i = a.parity + 2 * (q * LPW + team);
+    const bool active = i < a.L;
+    const int ic = active ? i : a.parity;
+    T *w_new = a.w_new;
+    const T *wb = a.blk + (size_t)ic * BS + c * VEC;   // W_ic, the only dense block
+    const GenEntry te = tab[ic];
+
+    // rows of W_i stream while the gathers run
+    VT vpre[PF];
+#pragma unroll
+    for (int qq = 0; qq < PF; ++qq)
+        vpre[qq] = stream_load<VT, true>((const VT *)(wb + (size_t)(g + R * qq) * MP));
+
+    // r_i[j] = sum over the column's slots of val * source; the previous
+    // iterate's terms are scaled by kappa once, after their sum
+    const int j = tt % MP, gg0 = tt / MP;
+    const T near = gen_gather<T, MP, G>(val, idx, (size_t)te.off, te.Kn >> 2, j, gg0,
+                                        PHB ? (const T *)w_new : a.w_old);
+    const T far = gen_gather<T, MP, G>(val, idx, (size_t)te.off + (size_t)te.Kn * MP, te.Kf >> 2,
+                                       j, gg0, a.w_old);
+    const T sc = (T)inv_old;
+    red[gg0 * MP + j] = PHB ? near + sc * far : sc * (near + far);
+    __syncthreads();
+    if (tt < MP) {
+        T r = 0;
+#pragma unroll
+        for (int x = 0; x < G; ++x) r += red[x * MP + tt];
+        rv[tt] = r;
+    }
+    __syncthreads();
+
+    // z_i = W_i r_i (dense)
+    VT acc2 = (VT)(T)0;
+#pragma unroll
+    for (int qq = 0; qq < RPT; ++qq) {
+        const int row = g + R * qq;
+        const VT wv = (qq < PF) ? vpre[qq < PF ? qq : 0]
+                                : stream_load<VT, true>((const VT *)(wb + (size_t)row * MP));
+        acc2 += wv * rv[row];
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
+    __syncthreads();
+
+    double zs = 0.0, dd = 0.0;
+    if (live && active && tt < MP) {
+        T z = 0;
+#pragma unroll
+        for (int x = 0; x < R; ++x) z += red[x * MP + tt];
+        w_new[(size_t)i * MP + tt] = z;
+        zs = (double)z;
+        if (a.s >= 3) {
+            const double i2 = st->inv_sigma[(a.s - 2) & kRingMask];
+            const double i3 = st->inv_sigma[(a.s - 3) & kRingMask];
+            dd = fabs((double)a.w_d1[(size_t)i * MP + tt] * i2 -
+                      (double)a.w_d2[(size_t)i * MP + tt] * i3);
+        }
+    }
+    double S = zs, D = dd;
+    block_sum2(S, D, sh);
+    if (live && tid == 0) {
+        a.part_sum[a.slot0 + q] = S;
+        a.part_diff[a.slot0 + q] = D;
+    }
+}
+
+template <typename T, int MP, bool PHB>
+__global__ __launch_bounds__(kWG) void k_sweep_gen(SweepLaunch a, const GenEntry *tab,
+                                                    const void *val, const int *idx) {
+    using TL = Tile<T, MP, 8>;
+    __shared__ T red[TL::LPW * TL::R * MP];
+    __shared__ T rv[TL::LPW * MP];
+    __shared__ double sh[4 * kWG / 64];
+    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
+        fold_previous(a, sh);
+        return;
+    }
+    const bool live = a.st->stop_flag == 0;
+    const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
+    sweep_group_gen<T, MP, PHB>(view_of<T>(a), tab, (const T *)val, idx, blockIdx.x, live, kappa,
+                                red, rv, sh);
+}
+
+// ||Q^T x||_1 per group of levels, FP64: (Q^T x) restricted to level i is
+// A_{i,i} x_i (dense diagonal block) plus the level's ELL entries applied to
+// x, with x = w * inv_sigma[slot] (slot < 0: w as given).
+template <typename T, int MP>
+__global__ __launch_bounds__(kWG) void k_residual_gen(const double *diag, const GenEntry *tab,
+                                                       const double *val, const int *idx,
+                                                       const T *w, int L, const DevState *st,
+                                                       long long slot, double *part) {
+    using TL = Tile<double, MP, 8>;
+    using VT = typename Vec16<double>::type;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS,
+                  LPW = TL::LPW;
+    constexpr int G = TS / MP;
+    constexpr size_t BS = (size_t)MP * MP;
+    __shared__ double red[LPW][R][MP];
+    __shared__ double red2[LPW][G][MP];
+    __shared__ double sh[4 * kWG / 64];
+
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    const int i = blockIdx.x * LPW + team;
+    const bool active = i < L;
+    const double inv = slot < 0 ? 1.0 : st->inv_sigma[slot & kRingMask];
+
+    VT acc = (VT)0.0;
+    double off_diag = 0.0;
+    if (active) {
+        const double *gb = diag + (size_t)i * BS + c * VEC;
+        const T *v = w + (size_t)i * MP;
+#pragma unroll
+        for (int qq = 0; qq < RPT; ++qq) {
+            const int row = g + R * qq;
+            const VT bv = stream_load<VT, true>((const VT *)(gb + (size_t)row * MP));
+            acc += bv * ((double)v[row] * inv);
+        }
+        const GenEntry te = tab[i];
+        const int j = tt % MP, gg0 = tt / MP;
+        const int Kq = (te.Kn + te.Kf) >> 2;   // both segments, one source
+        for (int kq = gg0; kq < Kq; kq += G) {
+            const size_t o = (size_t)te.off + ((size_t)kq * MP + j) * 4;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) off_diag += val[o + t] * (double)w[idx[o + t]];
+        }
+        off_diag *= inv;
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) red[team][g][c * VEC + e] = acc[e];
+    red2[team][tt / MP][tt % MP] = off_diag;
+    __syncthreads();
+    double r = 0.0;
+    if (active && tt < MP) {
+        double t = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < R; ++gg) t += red[team][gg][tt];
+#pragma unroll
+        for (int x = 0; x < G; ++x) t += red2[team][x][tt];
+        r = fabs(t);
+    }
+    const double S = block_sum(r, sh);
+    if (tid == 0) part[blockIdx.x] = S;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int MP>
+static hipError_t gen_mp(bool phase_b, const SweepLaunch &a, const GenEntry *tab, const void *val,
+                         const int *idx, hipStream_t s, LaunchTimer t) {
+    const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, kEllGeometry) +
+                       ((phase_b && a.fold) ? 1 : 0);   // + the reduction workgroup
+    if (groups <= 0) return hipSuccess;
+    if (phase_b)
+        launch_timed(k_sweep_gen<T, MP, true>, groups, s, t, a, tab, val, idx);
+    else
+        launch_timed(k_sweep_gen<T, MP, false>, groups, s, t, a, tab, val, idx);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t gen_t(int MP, bool phase_b, const SweepLaunch &a, const GenEntry *tab,
+                        const void *val, const int *idx, hipStream_t s, LaunchTimer t) {
+    switch (MP) {
+        case 8: return gen_mp<T, 8>(phase_b, a, tab, val, idx, s, t);
+        case 16: return gen_mp<T, 16>(phase_b, a, tab, val, idx, s, t);
+        case 32: return gen_mp<T, 32>(phase_b, a, tab, val, idx, s, t);
+        case 64: return gen_mp<T, 64>(phase_b, a, tab, val, idx, s, t);
+        case 128: return gen_mp<T, 128>(phase_b, a, tab, val, idx, s, t);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, const SweepLaunch &a,
+                                  const GenEntry *tab, const void *val, const int *idx,
+                                  hipStream_t stream, LaunchTimer t) {
+    return precision_bytes == 8 ? gen_t<double>(MP, phase_b, a, tab, val, idx, stream, t)
+                                : gen_t<float>(MP, phase_b, a, tab, val, idx, stream, t);
+}
+
+template <typename T, int MP>
+static void residual_gen_mp(int groups, const double *diag, const GenEntry *tab, const double *val,
+                            const int *idx, const void *w, int L, const DevState *st,
+                            long long slot, double *part, hipStream_t s) {
+    hipLaunchKernelGGL((k_residual_gen<T, MP>), dim3(groups), dim3(kWG), 0, s, diag, tab, val, idx,
+                       (const T *)w, L, st, slot, part);
+}
+
+template <typename T>
+static hipError_t residual_gen_t(int MP, int groups, const double *diag, const GenEntry *tab,
+                                 const double *val, const int *idx, const void *w, int L,
+                                 const DevState *st, long long slot, double *part,
+                                 hipStream_t s) {
+    switch (MP) {
+        case 8: residual_gen_mp<T, 8>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        case 16: residual_gen_mp<T, 16>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        case 32: residual_gen_mp<T, 32>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        case 64: residual_gen_mp<T, 64>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        case 128: residual_gen_mp<T, 128>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
+                               const GenEntry *tab, const double *val64, const int *idx,
+                               const void *w, int L, DevState *st, long long slot, double *part,
+                               hipStream_t stream) {
+    const int groups = reduce_groups(MP, L);
+    const hipError_t e =
+        precision_bytes == 8
+            ? residual_gen_t<double>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream)
+            : residual_gen_t<float>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream);
+    if (e != hipSuccess) return e;
+    return launch_reduce_residual(part, groups, st, stream);
+}
+
+}  // namespace stc

@@ -117,6 +117,20 @@ struct EllEntry {
     int pad_;
 };
 
+// The off-diagonal entries of one level of a generator of any block pattern
+// (column-major ELL in slot quads, like EllEntry, with 32-bit indices into
+// the padded iterate, level * MP + state).  Column j of the level holds Kn
+// "near" slots, whose sources lie in the adjacent levels i - 1 and i + 1
+// (read fresh by phase B), then Kf "far" slots from every other level (read
+// from the previous iterate by both phases); Kn and Kf are multiples of 4.
+// Near slot k = 4 kq + t of column j sits at off + (kq MP + j) 4 + t, far
+// slot k at off + Kn MP + (kq MP + j) 4 + t.  Padding slots hold the value 0
+// and the index of a state that every read of that slot finds written.
+struct GenEntry {
+    long long off;
+    int Kn, Kf;
+};
+
 // One chain of a batched (multi-chain) launch, as the device reads it.  The
 // blocks and iterate buffers are those of the chain's current precision
 // stage; its sweep number is DevState::last_sweep + 1.
@@ -168,6 +182,16 @@ hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase
                                   const SweepLaunch &a, const EllEntry *tab, const void *val,
                                   const unsigned char *idx, hipStream_t stream,
                                   LaunchTimer t = LaunchTimer());
+// Generators of any block pattern (stc_general.hip): the sweep phases and
+// the residual, over the diagonal blocks (inverse W_i in blk, Q_ii in diag)
+// and the per-level GenEntry table.
+hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, const SweepLaunch &a,
+                                  const GenEntry *tab, const void *val, const int *idx,
+                                  hipStream_t stream, LaunchTimer t = LaunchTimer());
+hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
+                               const GenEntry *tab, const double *val64, const int *idx,
+                               const void *w, int L, DevState *st, long long slot, double *part,
+                               hipStream_t stream);
 // Most blocks of a persistent sweep kernel that can be resident at once
 // (0 if the variant has no persistent form for these sizes).
 int flow_resident_blocks(int precision_bytes, int MP, int b, int variant);
@@ -188,6 +212,8 @@ hipError_t launch_store(int precision_bytes, int MP, const void *w, const long l
 hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
                            const double *diag64, const void *w, int L, DevState *st,
                            long long slot, double *part, hipStream_t stream);
+// Sum the per-group residual partials into DevState::residual.
+hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream);
 hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
                        const void *w_prev, int L, int parity_a, DevState *st, long long k,
                        double *part, hipStream_t stream, double tol);

@@ -312,6 +312,10 @@ static hipError_t reduce(const double *part, int n, int mode, DevState *st, long
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream) {
+    return reduce(part, n, kReduceResidual, st, 0, stream);
+}
+
 // load/diff use at most this many groups, so their partial arrays stay small
 constexpr int kAuxGroups = 1024;
 

@@ -85,8 +85,11 @@ struct Layout {
     int MP = 0, NB = 0;
     bool fp32 = false;          // FP32 copies of blocks and iterates
     bool sparse = false;        // off-diagonal blocks swept from ELL storage
+    bool general = false;       // any block pattern: one near / far ELL per level
     size_t ell_tab = 0, ell_v64 = 0, ell_v32 = 0, ell_idx = 0;
     long long ell_slots = 0;    // sum over blocks of K * MP
+    size_t gen_tab = 0, gen_v64 = 0, gen_v32 = 0, gen_idx = 0;
+    long long gen_slots = 0;    // sum over levels of (Kn + Kf) * MP
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
     size_t nparts = 0, naux = 0;
@@ -160,6 +163,47 @@ bool ell_K_table(const stc_generator *g, std::vector<int> *Ks) {
         int K = 0;
         for (int j = 0; j < m; ++j) K = std::max(K, cnt[blk * m + j]);
         (*Ks)[blk] = (K + 3) / 4 * 4;
+    }
+    return true;
+}
+
+// Near and far ELL widths of every level of a generator of any block pattern
+// (CSR input): per column c of level i, the nonzero off-diagonal entries
+// Q_{r,c} with r in level i - 1 or i + 1 (near) or in any other level except
+// i (far); the widths are the longest column of each kind, rounded up to a
+// multiple of 4.  Entries of level i itself go to the dense diagonal block.
+// Entries outside the matrix are skipped here (setup rejects them).  Returns
+// false if the row pointers are malformed.
+bool gen_K_table(const stc_generator *g, std::vector<int> *Kn, std::vector<int> *Kf) {
+    const int L = g->L;
+    std::vector<long long> off;
+    std::vector<int> lev;
+    level_offsets(g, &off, &lev);
+    const long long N = off[L];
+    const int64_t *rp = g->csr_rowptr;
+    if (rp[0] != 0) return false;
+    std::vector<int> cn(N, 0), cf(N, 0);
+    for (long long r = 0; r < N; ++r) {
+        if (rp[r + 1] < rp[r]) return false;
+        const int k = lev[r];
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+            const long long c = g->csr_col[p];
+            if (c < 0 || c >= N || g->csr_val[p] == 0.0) continue;
+            const int i = lev[c];
+            if (i == k) continue;
+            ++((k == i - 1 || k == i + 1) ? cn : cf)[c];
+        }
+    }
+    Kn->assign(L, 0);
+    Kf->assign(L, 0);
+    for (int i = 0; i < L; ++i) {
+        int a = 0, b = 0;
+        for (long long c = off[i]; c < off[i + 1]; ++c) {
+            a = std::max(a, cn[c]);
+            b = std::max(b, cf[c]);
+        }
+        (*Kn)[i] = (a + 3) / 4 * 4;
+        (*Kf)[i] = (b + 3) / 4 * 4;
     }
     return true;
 }
@@ -248,7 +292,8 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     *why = 0;
     if (!g || !o) return false;
     if (g->L < 2) { *why = 1; return false; }
-    if (g->b < 1 || g->b > kMaxBandwidth) { *why = 2; return false; }
+    const bool general = g->b == STC_ANY_PATTERN;
+    if (!general && (g->b < 1 || g->b > kMaxBandwidth)) { *why = 2; return false; }
     const int MP = supported_mp(g->m);
     if (!MP) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
@@ -258,15 +303,24 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
         for (int i = 0; i < g->L; ++i)
             if (g->sizes[i] < 1 || g->sizes[i] > g->m) { *why = 9; return false; }
     if (g->blocks && g->csr_rowptr) { *why = 7; return false; }
+    if (general && !csr_input(g)) { *why = 10; return false; }
+    if (general && o->format != STC_SPARSE) { *why = 11; return false; }
+    if (general && (long long)g->L * MP >= (1ll << 31)) { *why = 12; return false; }
     Layout l;
     l.MP = MP;
-    l.NB = 2 * g->b + 1;
+    l.NB = general ? 1 : 2 * g->b + 1;   // any pattern: only the diagonal slot is dense
     l.fp32 = o->precision != STC_FP64;
     l.sparse = o->format == STC_SPARSE;
-    if (l.sparse) {
+    l.general = general;
+    if (l.sparse && !general) {
         std::vector<int> Ks;
         if (!ell_K_table(g, &Ks)) { *why = 8; return false; }
         for (int K : Ks) l.ell_slots += (long long)K * MP;
+    }
+    if (general) {
+        std::vector<int> Kn, Kf;
+        if (!gen_K_table(g, &Kn, &Kf)) { *why = 8; return false; }
+        for (int i = 0; i < g->L; ++i) l.gen_slots += (long long)(Kn[i] + Kf[i]) * MP;
     }
     const size_t L = (size_t)g->L, bs = (size_t)MP * MP, vec = L * MP;
     size_t at = 0;
@@ -283,11 +337,17 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.part_diff = take(2 * l.nparts * 8);
     l.naux = std::max<size_t>(2 * 1024 + 8, L + 8);
     l.part_aux = take(l.naux * 8);
-    if (l.sparse) {
+    if (l.sparse && !general) {
         l.ell_tab = take(L * l.NB * sizeof(EllEntry));
         l.ell_v64 = take((size_t)l.ell_slots * 8);
         if (l.fp32) l.ell_v32 = take((size_t)l.ell_slots * 4);
         l.ell_idx = take((size_t)l.ell_slots);
+    }
+    if (general) {
+        l.gen_tab = take(L * sizeof(GenEntry));
+        l.gen_v64 = take((size_t)l.gen_slots * 8);
+        if (l.fp32) l.gen_v32 = take((size_t)l.gen_slots * 4);
+        l.gen_idx = take((size_t)l.gen_slots * 4);
     }
     l.off = take((L + 1) * 8);
     l.sizes = take(L * 4);
@@ -324,6 +384,14 @@ struct stc_handle {
     float *ell_v32 = nullptr;
     unsigned char *ell_idx = nullptr;
     std::vector<int> ell_K;    // [L][NB] longest column per block
+    // any block pattern
+    bool general = false;
+    GenEntry *gen_tab = nullptr;
+    double *gen_v64 = nullptr;
+    float *gen_v32 = nullptr;
+    int *gen_idx = nullptr;
+    std::vector<GenEntry> gen_host;   // the table, for the byte counts
+    double gen_vin[2] = {0.0, 0.0};   // distinct source values read by phase A / B
     unsigned *flow_flags = nullptr;   // progress flags of a persistent burst
     int flow_res[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};   // resident blocks, cached
     long long wall_hz = 100000000;    // device wall clock rate
@@ -398,6 +466,10 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTime
     const void *ev_val = f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64;
     auto phase = [&](bool phb) {
         const LaunchTimer t = tm ? (phb ? tm->b : tm->a) : LaunchTimer();
+        if (h->general)
+            return launch_sweep_phase_gen(bytes, h->MP, phb, a, h->gen_tab,
+                                          f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
+                                          h->gen_idx, h->stream, t);
         if (h->sparse)
             return launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab, ev_val,
                                           h->ell_idx, h->stream, t);
@@ -580,9 +652,18 @@ stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
     return load_vector_stage(h, x, where, h->precision != STC_FP64);
 }
 
+// ||Q^T x||_1 of the padded iterate w (scaled by inv_sigma[slot]; slot < 0:
+// as given) into DevState::residual.
+hipError_t enqueue_residual(stc_handle *h, bool f32, const void *w, long long slot) {
+    if (h->general)
+        return launch_residual_gen(f32 ? 4 : 8, h->MP, h->diag64, h->gen_tab, h->gen_v64,
+                                   h->gen_idx, w, h->L, h->st, slot, h->part_aux, h->stream);
+    return launch_residual(f32 ? 4 : 8, h->MP, h->b, h->blk64, h->diag64, w, h->L, h->st, slot,
+                           h->part_aux, h->stream);
+}
+
 stc_status residual_of(stc_handle *h, bool f32, long long s, double *out) {
-    HIP_TRY(launch_residual(f32 ? 4 : 8, h->MP, h->b, h->blk64, h->diag64, wbuf(h, f32, s), h->L,
-                            h->st, s, h->part_aux, h->stream));
+    HIP_TRY(enqueue_residual(h, f32, wbuf(h, f32, s), s));
     HostState hs;
     stc_status rc = read_state(h, &hs);
     if (rc != STC_OK) return rc;
@@ -610,6 +691,196 @@ stc_status widen_at(stc_handle *h, long long k) {
         HIP_TRY(launch_widen((const float *)wbuf(h, true, j), (double *)wbuf(h, false, j), vec,
                              h->stream));
     h->stage32 = false;
+    return STC_OK;
+}
+
+// Setup of a generator of any block pattern (CSR input): check every row,
+// then pack the dense diagonal blocks Q_ii, the per-level near / far ELL of
+// the off-diagonal entries of A = Q^T (GenEntry), and the FP32 copy of its
+// values.  Levels are packed a chunk at a time, so the host holds the
+// transposed entries plus one chunk of the device layout.
+stc_status pack_general(stc_handle *h, const stc_generator *g) {
+    const int L = h->L, MP = h->MP;
+    const size_t bs = (size_t)MP * MP;
+    std::vector<long long> off;
+    std::vector<int> lev;
+    level_offsets(g, &off, &lev);
+    const long long N = off[L];
+    const int64_t *rp = g->csr_rowptr;
+    const int32_t *col = g->csr_col;
+    const double *val = g->csr_val;
+
+    // every row: columns in range and not repeated, off-diagonal rates >= 0
+    // and finite, the row sum 0 (or the diagonal recomputed)
+    std::vector<double> dg(N);
+    {
+        std::vector<long long> cols;
+        for (long long r = 0; r < N; ++r) {
+            const int i = lev[r];
+            const int64_t p0 = rp[r], p1 = rp[r + 1];
+            if (p1 < p0 || (r == 0 && p0 != 0))
+                return fail(STC_EINVAL, "CSR row pointers fall at row %lld", r);
+            cols.clear();
+            for (int64_t p = p0; p < p1; ++p) {
+                const long long c = col[p];
+                if (c < 0 || c >= N)
+                    return fail(STC_EINVAL, "CSR column %lld of row %lld is outside 0..%lld", c, r,
+                                N - 1);
+                cols.push_back(c);
+            }
+            std::sort(cols.begin(), cols.end());
+            for (size_t q = 1; q < cols.size(); ++q)
+                if (cols[q] == cols[q - 1])
+                    return fail(STC_EINVAL, "CSR row %lld repeats column %lld", r, cols[q]);
+            double out = 0.0, given = 0.0;
+            for (int64_t p = p0; p < p1; ++p) {
+                const long long c = col[p];
+                const double v = val[p];
+                if (c == r) {
+                    given = v;
+                    continue;
+                }
+                if (!(v >= 0.0) || !std::isfinite(v))
+                    return fail(STC_ENOTGEN, "Q[level %d row %lld][level %d col %lld] = %g is not a rate",
+                                i, r - off[i], lev[c], c - off[lev[c]], v);
+                out += v;
+            }
+            if (g->recompute_diagonal) {
+                dg[r] = -out;
+            } else {
+                if (!std::isfinite(given) || fabs(given + out) > 1e-10 * std::max(out, 1e-300))
+                    return fail(STC_ENOTGEN, "row %lld of level %d sums to %g, not 0 (diagonal %g)",
+                                r - off[i], i, given + out, given);
+                dg[r] = given;
+            }
+        }
+    }
+
+    // the off-diagonal nonzeros of other levels by column (gather orientation),
+    // rows ascending within a column
+    std::vector<long long> cptr(N + 1, 0);
+    for (long long r = 0; r < N; ++r)
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+            if (val[p] != 0.0 && lev[col[p]] != lev[r]) ++cptr[col[p] + 1];
+    for (long long c = 0; c < N; ++c) cptr[c + 1] += cptr[c];
+    std::vector<long long> crow(cptr[N]);
+    std::vector<double> cval(cptr[N]);
+    {
+        std::vector<long long> cur(cptr.begin(), cptr.end() - 1);
+        for (long long r = 0; r < N; ++r)
+            for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+                if (val[p] != 0.0 && lev[col[p]] != lev[r]) {
+                    const long long e = cur[col[p]]++;
+                    crow[e] = r;
+                    cval[e] = val[p];
+                }
+    }
+    auto near_of = [&](int k, int i) { return k == i - 1 || k == i + 1; };
+
+    // ELL widths (the same counts as the footprint plan)
+    std::vector<GenEntry> tab(L);
+    long long at = 0;
+    for (int i = 0; i < L; ++i) {
+        int a = 0, b = 0;
+        for (long long c = off[i]; c < off[i + 1]; ++c) {
+            int n = 0, f = 0;
+            for (long long e = cptr[c]; e < cptr[c + 1]; ++e) ++(near_of(lev[crow[e]], i) ? n : f);
+            a = std::max(a, n);
+            b = std::max(b, f);
+        }
+        tab[i] = GenEntry{at, (a + 3) / 4 * 4, (b + 3) / 4 * 4};
+        at += (long long)(tab[i].Kn + tab[i].Kf) * MP;
+    }
+    if (at != h->lay.gen_slots) return fail(STC_EINVAL, "CSR input changed between the plan and setup");
+
+    // values and indices, a range of levels at a time; padding slots read a
+    // state of an adjacent level, which both phases have written
+    const long long chunk_slots = 8ll << 20;
+    std::vector<double> v64;
+    std::vector<int> ix;
+    for (int l0 = 0; l0 < L;) {
+        int l1 = l0 + 1;
+        while (l1 < L && tab[l1].off + (long long)(tab[l1].Kn + tab[l1].Kf) * MP - tab[l0].off <= chunk_slots)
+            ++l1;
+        const long long s0 = tab[l0].off;
+        const long long s1 = l1 < L ? tab[l1].off : at;
+        v64.assign((size_t)(s1 - s0), 0.0);
+        ix.assign((size_t)(s1 - s0), 0);
+        for (int i = l0; i < l1; ++i) {
+            const GenEntry t = tab[i];
+            const int pad = (i > 0 ? i - 1 : i + 1) * MP;
+            std::fill(ix.begin() + (t.off - s0), ix.begin() + (t.off - s0) + (long long)(t.Kn + t.Kf) * MP, pad);
+            for (long long c = off[i]; c < off[i + 1]; ++c) {
+                const int j = (int)(c - off[i]);
+                int n = 0, f = 0;
+                for (long long e = cptr[c]; e < cptr[c + 1]; ++e) {
+                    const long long r = crow[e];
+                    const int k = lev[r];
+                    size_t o = (size_t)(t.off - s0);
+                    if (near_of(k, i)) {
+                        o += ((size_t)(n >> 2) * MP + j) * 4 + (n & 3);
+                        ++n;
+                    } else {
+                        o += (size_t)t.Kn * MP + ((size_t)(f >> 2) * MP + j) * 4 + (f & 3);
+                        ++f;
+                    }
+                    v64[o] = cval[e];
+                    ix[o] = (int)((long long)k * MP + (r - off[k]));
+                }
+            }
+        }
+        if (s1 > s0) {
+            HIP_TRY(hipMemcpyAsync(h->gen_v64 + s0, v64.data(), sizeof(double) * (s1 - s0),
+                                   hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->gen_idx + s0, ix.data(), sizeof(int) * (s1 - s0),
+                                   hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+        }
+        l0 = l1;
+    }
+    HIP_TRY(hipMemcpyAsync(h->gen_tab, tab.data(), sizeof(GenEntry) * L, hipMemcpyHostToDevice,
+                           h->stream));
+    if (h->lay.fp32 && at > 0) HIP_TRY(launch_cast_blocks(h->gen_v64, h->gen_v32, (size_t)at, h->stream));
+
+    // dense diagonal blocks Q_ii (padded, row-major), a chunk of levels at a time
+    const int dchunk = std::max(1, (int)std::min<size_t>(L, (64u << 20) / (bs * 8)));
+    std::vector<double> D((size_t)dchunk * bs);
+    for (int l0 = 0; l0 < L; l0 += dchunk) {
+        const int l1 = std::min(L, l0 + dchunk);
+        std::fill(D.begin(), D.begin() + (size_t)(l1 - l0) * bs, 0.0);
+        for (int i = l0; i < l1; ++i) {
+            double *Di = D.data() + (size_t)(i - l0) * bs;
+            for (long long r = off[i]; r < off[i + 1]; ++r) {
+                for (int64_t p = rp[r]; p < rp[r + 1]; ++p)
+                    if (lev[col[p]] == i && col[p] != r)
+                        Di[(size_t)(r - off[i]) * MP + (col[p] - off[i])] = val[p];
+                Di[(size_t)(r - off[i]) * MP + (r - off[i])] = dg[r];
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(h->diag64 + (size_t)l0 * bs, D.data(), sizeof(double) * (l1 - l0) * bs,
+                               hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+
+    // distinct source values each phase reads (per buffer), for the byte counts
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    for (int ph = 0; ph < 2; ++ph) {
+        const int par = ph == 0 ? pA : 1 - pA;
+        std::vector<char> seen_old(N, 0), seen_new(N, 0);
+        double cnt = 0.0;
+        for (int i = par; i < L; i += 2)
+            for (long long c = off[i]; c < off[i + 1]; ++c)
+                for (long long e = cptr[c]; e < cptr[c + 1]; ++e) {
+                    const long long r = crow[e];
+                    char &seen = (ph == 1 && near_of(lev[r], i)) ? seen_new[r] : seen_old[r];
+                    if (!seen) {
+                        seen = 1;
+                        cnt += 1.0;
+                    }
+                }
+        h->gen_vin[ph] = cnt;
+    }
+    h->gen_host = tab;
     return STC_OK;
 }
 
@@ -653,13 +924,17 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     Layout lay;
     int why = 0;
     if (!plan(g, o, &lay, &why)) {
-        static const char *msg[] = {"bad arguments", "L must be >= 2", "b must be in 1..4",
+        static const char *msg[] = {"bad arguments", "L must be >= 2",
+                                    "b must be in 1..4 or STC_ANY_PATTERN",
                                     "m must be in 1..128", "unknown precision", "unknown format",
                                     "neither blocks nor a complete CSR input given",
                                     "give blocks or CSR input, not both",
                                     "CSR row pointers must start at 0 and never fall",
-                                    "a level size is outside 1..m"};
-        return fail(STC_EINVAL, "%s", msg[why < 10 ? why : 0]);
+                                    "a level size is outside 1..m",
+                                    "a generator of any pattern (STC_ANY_PATTERN) comes as CSR input",
+                                    "a generator of any pattern (STC_ANY_PATTERN) needs STC_SPARSE storage",
+                                    "L * padded m must stay below 2^31"};
+        return fail(STC_EINVAL, "%s", msg[why < 13 ? why : 0]);
     }
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
     if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
@@ -727,6 +1002,15 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         return fail(STC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     };
 
+    stc_status rc = STC_OK;
+    if (lay.general) {
+        h->general = true;
+        h->gen_tab = (GenEntry *)(h->base + lay.gen_tab);
+        h->gen_v64 = (double *)(h->base + lay.gen_v64);
+        h->gen_v32 = lay.fp32 ? (float *)(h->base + lay.gen_v32) : nullptr;
+        h->gen_idx = (int *)(h->base + lay.gen_idx);
+        if ((rc = pack_general(h, g)) != STC_OK) return cleanup(rc);
+    } else {
     // validate, then pack in the sweep's layout, a chunk of levels at a time;
     // the levels of a chunk are split over host threads
     const size_t bs = (size_t)MP * MP, ms = (size_t)m * m;
@@ -806,7 +1090,6 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         for (const auto &e : errs)
             if (e.level >= 0 && (!first || e.level < first->level)) first = &e;
         if (first) return cleanup(fail(STC_ENOTGEN, "%s", first->msg.c_str()));
-        stc_status rc;
         if ((rc = dev(hipMemcpyAsync(h->blk64 + (size_t)l0 * NB * bs, stage_blk.data(),
                                      sizeof(double) * (size_t)(l1 - l0) * NB * bs,
                                      hipMemcpyHostToDevice, h->stream), "copy blocks")) != STC_OK)
@@ -817,7 +1100,6 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
             return cleanup(rc);
         if ((rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK) return cleanup(rc);
     }
-    stc_status rc;
     if (lay.sparse) {
         // column-major ELL of every off-diagonal block, levels in order
         if (!ell_K_table(g, &h->ell_K)) return cleanup(fail(STC_EINVAL, "bad CSR row pointers"));
@@ -874,6 +1156,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
             (rc = dev(launch_cast_blocks(h->ell_v64, h->ell_v32, (size_t)at, h->stream), "cast ELL")) != STC_OK)
             return cleanup(rc);
     }
+    }
     if ((rc = dev(hipMemcpyAsync(h->off, off.data(), sizeof(long long) * (L + 1),
                                  hipMemcpyHostToDevice, h->stream), "copy offsets")) != STC_OK)
         return cleanup(rc);
@@ -884,12 +1167,13 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     if ((rc = dev(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream), "clear state")) != STC_OK)
         return cleanup(rc);
     if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return cleanup(rc);
-    if ((rc = dev(launch_invert(MP, b, h->diag64, h->sizes_d, h->blk64, L, h->st, h->stream),
+    if ((rc = dev(launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
+                                h->stream),
                   "invert")) != STC_OK)
         return cleanup(rc);
     if (lay.fp32 &&
-        (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * bs, h->stream), "cast")) !=
-            STC_OK)
+        (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * MP * MP, h->stream),
+                  "cast")) != STC_OK)
         return cleanup(rc);
     HostState hs;
     if ((rc = read_state(h, &hs)) != STC_OK) return cleanup(rc);
@@ -1089,7 +1373,19 @@ stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {
     const double sb = h->stage32 ? 4.0 : 8.0;
     const int pA = (h->stair_type == 1) ? 0 : 1;
     double out[2] = {0.0, 0.0};
-    for (int ph = 0; ph < 2; ++ph) {
+    for (int ph = 0; ph < 2 && h->general; ++ph) {
+        // W_i, the level's stored ELL slots (value + 4-byte index), the
+        // distinct source values and the level's output
+        const int par = ph == 0 ? pA : 1 - pA;
+        double blocks = 0.0, vout = 0.0;
+        for (int i = par; i < h->L; i += 2) {
+            vout += h->sizes[i];
+            blocks += (double)h->sizes[i] * h->sizes[i];
+            blocks += (double)(h->gen_host[i].Kn + h->gen_host[i].Kf) * h->MP * (1.0 + 4.0 / sb);
+        }
+        out[ph] = sb * (blocks + h->gen_vin[ph] + vout);
+    }
+    for (int ph = 0; ph < 2 && !h->general; ++ph) {
         const int par = ph == 0 ? pA : 1 - pA;
         double blocks = 0.0, vin = 0.0, vout = 0.0;
         std::vector<char> seen(h->L, 0);
@@ -1173,8 +1469,7 @@ stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t w
     // FP64 copy in the padded layout; slot -1 = use x as given
     HIP_TRY(launch_load(8, h->MP, src, h->off, h->sizes_d, h->L, h->wres, h->part_aux,
                         (int)h->lay.naux, h->st, -1, h->stream));
-    HIP_TRY(launch_residual(8, h->MP, h->b, h->blk64, h->diag64, h->wres, h->L, h->st, -1,
-                            h->part_aux, h->stream));
+    HIP_TRY(enqueue_residual(h, false, h->wres, -1));
     HostState hs;
     stc_status rc = read_state(h, &hs);
     if (rc != STC_OK) return rc;

@@ -25,6 +25,7 @@ STC_FP64, STC_FP32, STC_MIXED = 0, 1, 2
 STC_STOP_DIFF, STC_STOP_RESIDUAL = 0, 1
 STC_MEM_HOST, STC_MEM_DEVICE = 0, 1
 STC_DENSE, STC_SPARSE = 0, 1
+STC_ANY_PATTERN = -1          # stc_generator.b: a generator of any block pattern
 
 PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
 STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}

@@ -233,3 +233,87 @@ def test_sizes_checked_before_any_scan(lib):
     assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
     err = _setup_error(gen)
     assert err.status == stc.STC_EINVAL and "sizes[3] = 40" in str(err), str(err)
+
+
+# --- generators of any block pattern ---------------------------------------
+
+def _gen_csr(g, **kw):
+    return stc.make_generator_csr(g.indptr, g.indices, g.data, g.sizes, stc.STC_ANY_PATTERN, **kw)
+
+
+def test_any_pattern_footprint_and_shape_rules(lib):
+    g = synth.localized(20, 16, 4, up=2, down=2, jumps=2, ragged=True)
+    gen, _k = _gen_csr(g)
+    sparse = stc.stc_footprint_bytes(gen, stc.make_options(format="sparse"))
+    assert sparse > 0
+    # the pattern needs the ELL storage, and CSR input
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="dense")) == 0
+    err = _setup_error(gen)
+    assert err.status == stc.STC_EINVAL and "STC_SPARSE" in str(err), str(err)
+    blocks = np.zeros((g.L, 1, g.m, g.m))
+    gb, _kb = stc.make_generator(blocks, g.sizes, 0)
+    gb.b = stc.STC_ANY_PATTERN
+    assert stc.stc_footprint_bytes(gb, stc.make_options(format="sparse")) == 0
+    # FP32 copies add to the footprint; more far entries add slots
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse", precision="mixed")) > sparse
+    g2 = synth.localized(20, 16, 4, up=2, down=2, jumps=6, ragged=True)
+    gen2, _k2 = _gen_csr(g2)
+    assert stc.stc_footprint_bytes(gen2, stc.make_options(format="sparse")) > sparse
+
+
+def test_any_pattern_footprint_counts_the_ell_slots(lib):
+    """The footprint grows by exactly the ELL slots (12 bytes each in FP64)
+    when one column of a level gets one more far entry than any other."""
+    g = synth.localized(6, 8, 1, up=1, down=1, jumps=0, backbone=0.1)
+    gen, _k = _gen_csr(g)
+    base = stc.stc_footprint_bytes(gen, stc.make_options(format="sparse"))
+    # add 5 far rates into column 0 of level 4 (rows of level 0 and 1): the
+    # far width of level 4 becomes 8 (two quads) from 0
+    Q = g.to_scipy().tolil()
+    for r in range(5):
+        Q[r if r < 3 else 8 + r, 4 * 8] = 0.01
+    Q = Q.tocsr()
+    Q.setdiag(0.0)
+    Q.setdiag(-np.asarray(Q.sum(axis=1)).ravel())
+    Q.sort_indices()
+    gen2, _k2 = stc.make_generator_csr(Q.indptr, Q.indices, Q.data, g.sizes, stc.STC_ANY_PATTERN)
+    grown = stc.stc_footprint_bytes(gen2, stc.make_options(format="sparse"))
+    slots = 8 * 8
+    assert 0 < grown - base <= slots * 12 + 3 * 256
+    assert grown - base >= slots * 12
+
+
+def test_any_pattern_csr_rejections(lib):
+    g = synth.localized(10, 8, 2, up=2, down=1, jumps=2)
+    ip, ix, v = g.indptr, g.indices, g.data
+
+    def err_of(ip_, ix_, v_, **kw):
+        gen = stc.make_generator_csr(ip_, ix_, v_, g.sizes, stc.STC_ANY_PATTERN, **kw)[0]
+        e = stc.StcError
+        opt = stc.make_options(format="sparse")
+        opt.arena, opt.arena_bytes = 4096, 1 << 40
+        import pytest as _p
+        with _p.raises(e) as info:
+            stc.stc_setup(gen, opt)
+        return info.value
+
+    ix2 = ix.copy()
+    ix2[5] = g.N + 3
+    err = err_of(ip, ix2, v)
+    assert err.status == stc.STC_EINVAL and "outside 0.." in str(err), str(err)
+    ix2 = ix.copy()
+    ix2[ip[3] + 1] = ix2[ip[3]]
+    err = err_of(ip, ix2, v)
+    assert err.status == stc.STC_EINVAL and "repeats column" in str(err), str(err)
+    v2 = v.copy()
+    v2[np.flatnonzero(ix != np.repeat(np.arange(g.N), np.diff(ip)))[7]] = -0.5
+    err = err_of(ip, ix, v2)
+    assert err.status == stc.STC_ENOTGEN and "is not a rate" in str(err), str(err)
+    v3 = v.copy()
+    v3[np.flatnonzero(ix == np.repeat(np.arange(g.N), np.diff(ip)))[4]] += 1.0
+    err = err_of(ip, ix, v3)
+    assert err.status == stc.STC_ENOTGEN and "sums to" in str(err), str(err)
+    ip2 = ip.copy()
+    ip2[4] = ip2[3] - 1
+    gen = stc.make_generator_csr(ip2, ix, v, g.sizes, stc.STC_ANY_PATTERN)[0]
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
