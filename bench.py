@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--setup", type=int, nargs=2, default=None)
     ap.add_argument("--banded", action="store_true")
     ap.add_argument("--skipfree", action="store_true")
+    ap.add_argument("--mutex", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
@@ -164,6 +165,8 @@ def main():
         return banded_mode()
     if args.skipfree:
         return skipfree_mode()
+    if args.mutex:
+        return mutex_mode(args)
 
     import numpy as np
     import torch
@@ -433,6 +436,124 @@ def skipfree_mode(L=2048, m=64, b=4):
             "config": {"workload": f"skipfree_b{b}_L{L}_m{m}", "levels": L, "block": m,
                        "bandwidth": b, "N": L * m, "seed": seed},
             "sweep_rates": runs, "solves": solves}
+    print(json.dumps(line), flush=True)
+
+
+def general_nnz_bytes(gen, stair_type, value_bytes):
+    """Algorithmic bytes of one sweep of a generator of any block pattern,
+    from its CSR form: per phase, every off-level nonzero once (value + 4-byte
+    index), the n_i x n_i inverse of each level once, each distinct source
+    value once per iterate it is read from, and each output once."""
+    import numpy as np
+    lev = np.repeat(np.arange(gen.L), gen.sizes)
+    rows = np.repeat(np.arange(gen.N), np.diff(gen.indptr))
+    cols = gen.indices.astype(np.int64)
+    off_level = (gen.data != 0.0) & (lev[rows] != lev[cols])
+    r, c = rows[off_level], cols[off_level]
+    tgt = lev[c]
+    pA = 0 if stair_type == 1 else 1
+    total = 0.0
+    for phase_b in (False, True):
+        par = (1 - pA) if phase_b else pA
+        sel = (tgt % 2) == par
+        near = np.abs(lev[r[sel]] - tgt[sel]) == 1
+        fresh = near if phase_b else np.zeros_like(near)
+        src = len(np.unique(r[sel][fresh])) + len(np.unique(r[sel][~fresh]))
+        out = int(gen.sizes[par::2].sum())
+        inv = float((gen.sizes[par::2].astype(np.float64) ** 2).sum())
+        total += sel.sum() * (value_bytes + 4) + value_bytes * (inv + src + out)
+    return total
+
+
+def mutex_mode(args, n=16, r=12):
+    """The mutual-exclusion model at the paper's size (N = 64839, a generator
+    whose nonzero blocks reach ~100 levels from the diagonal at m = 128):
+    sweep rates of the any-pattern kernels for two block sizes, time to the
+    paper's change tolerance and beyond, errors against the closed form, and
+    the oracle's sweep time on the host."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    seed = synth.config_seed(3)
+    rates, solves, shape = {}, {}, {}
+    for m in (128, 64):
+        gen = synth.mutual_exclusion(n, r, seed, m=m)
+        exact = synth.mutual_exclusion_pi(gen)
+        shape[f"m{m}"] = {"L": gen.L, "block_reach": gen.block_reach(), "nnz": gen.nnz}
+        for prec in ("fp64", "fp32"):
+            t0 = time.perf_counter()
+            s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                       precision=prec)
+            t_setup = time.perf_counter() - t0
+            s.load(None)
+            s.sweeps(args.warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.sweeps(args.steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            ms_a, ms_b, _f, _t = stc.stc_profile_sweeps(s.h, args.steps)
+            ba, bb = stc.stc_phase_bytes(s.h)
+            alg = general_nnz_bytes(gen, 1, 8 if prec == "fp64" else 4)
+            rates[f"m{m}_{prec}"] = {
+                "ms_per_sweep": round(ms, 5), "sweeps_per_s": round(1e3 / ms, 1),
+                "ms_phase_a": round(ms_a, 5), "ms_phase_b": round(ms_b, 5),
+                "stored_bytes_per_sweep": ba + bb, "algorithmic_bytes_per_sweep": alg,
+                "GB/s_algorithmic": round(alg / (ms * 1e-3) / 1e9, 1),
+                "GB/s_stored": round((ba + bb) / (ms * 1e-3) / 1e9, 1),
+                "setup_s": round(t_setup, 3), "footprint_MB": round(s.footprint / 1e6, 1)}
+            print(f"# m{m} {prec}: {rates[f'm{m}_{prec}']}", file=sys.stderr, flush=True)
+            s.close()
+        for prec, tol in () if args.no_ttr else (("fp64", 1e-9), ("fp64", 1e-13),
+                                                 ("mixed", 1e-13)):
+            s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                       precision=prec, check_every=100, switch_tol=1e-6)
+            s.solve(tol=tol, maxit=200_000)   # warm (first launches, code objects)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pi, info = s.solve(tol=tol, maxit=200_000)
+            dt = time.perf_counter() - t0
+            s.close()
+            key = f"m{m}_{prec}_tol{tol:g}"
+            solves[key] = {"seconds": round(dt, 4), "iters": info["iters"],
+                           "iters_fp32": info["iters_fp32"], "residual": info["residual_1"],
+                           "err_vs_closed_form": float(np.abs(pi - exact).sum())}
+            print(f"# solve {key}: {solves[key]}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        from oracle import staircase
+        gen = synth.mutual_exclusion(n, r, seed, m=128)
+        sysm = staircase.SparseBlockSystem(gen.to_scipy(), gen.sizes)
+        x = np.full(gen.N, 1.0 / gen.N)
+        staircase.staircase_sweep(sysm, x, 1)
+        k, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 10.0:
+            x, _ = staircase.staircase_sweep(sysm, x, 1)
+            k += 1
+        dt = (time.perf_counter() - t0) / k
+        cpu = {"value": round(1.0 / dt, 2), "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} FP64 sweeps of the m = 128 partition by the numpy oracle "
+                         f"({dt * 1e3:.0f} ms each)"}
+    best = rates["m128_fp64"]
+    # yardstick at this launch size: a device copy moving as many bytes as
+    # one phase launch (half of them read, half written)
+    copy = device_copy_rate(int(best["stored_bytes_per_sweep"] / 4), reps=200)
+    line = {"metric": "sweeps/s on the mutual-exclusion generator (any block pattern)",
+            "value": best["sweeps_per_s"], "unit": "sweeps/s", "higher_is_better": True,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"mutex_n{n}_r{r}", "N": 64839, "processes": n,
+                       "max_users": r, "seed": seed, "partitions": shape},
+            "roofline": {"bound": "hbm", "kernel": "general sweep kernels (both phases)",
+                         "achieved": best["GB/s_algorithmic"], "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(best["GB/s_algorithmic"] / 8000.0, 4), "traffic": None},
+            "sweep_rates": rates, "solves": solves, "cpu_baseline": cpu,
+            "device_copy_GBs_same_launch_bytes": round(copy, 1),
+            "vs_device_copy": round(best["GB/s_algorithmic"] / copy, 4)}
     print(json.dumps(line), flush=True)
 
 

@@ -199,7 +199,11 @@ stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_phase_a
  * non-temporal loads; the result of a sweep does not depend on it beyond
  * rounding order.  stage is STC_FP64 or STC_FP32 (the precision of the
  * sweeps the variant applies to).  setup picks a default from the block
- * size and the bytes of the blocks. */
+ * size and the bytes of the blocks.  For a generator of any pattern
+ * (STC_ANY_PATTERN) only bit 1 applies: non-temporal loads of the inverse
+ * blocks and entries, the default once they exceed the 256 MB last-level
+ * cache (below it they stay cached from sweep to sweep); the banded sparse
+ * kernel has no variants. */
 int32_t stc_variant_count(void);
 stc_status stc_set_variant(stc_handle *h, int32_t stage, int32_t variant);
 stc_status stc_get_variant(stc_handle *h, int32_t stage, int32_t *variant);

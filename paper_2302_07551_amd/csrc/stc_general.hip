@@ -20,48 +20,63 @@ namespace stc {
 
 typedef int Int4 __attribute__((ext_vector_type(4)));
 
-// sum over the quads [0, Kq) of column j of one ELL segment of
-// val[slot] * src[idx[slot]]; the lanes gg0, gg0 + G, ... of the column split
-// the quads, U quads of a lane in flight per pass (the gathers depend on the
-// index loads, so one quad at a time would wait two round trips each).
-template <typename T, int MP, int G>
-__device__ inline T gen_gather(const T *val, const int *idx, size_t base, int Kq, int j, int gg0,
-                               const T *src) {
-    using VT = typename Vec16<T>::type;
-    constexpr int U = sizeof(T) == 8 ? 2 : 4;
-    T acc = 0;
-    for (int kq0 = gg0; kq0 < Kq; kq0 += G * U) {
-        Int4 r4[U];
-        T v[U][4];
+// Quads of column j of a level's ELL, U per pass: the near segment's quads
+// are 0 .. Kqn-1 and the far segment's Kqn .. Kq-1 (the far segment starts
+// right after the near one, so quad kq sits at off + (kq MP + j) 4 in both).
+// The lanes gg0, gg0 + G, ... of the column split the quads.  load() issues
+// a pass's index and value loads; use() gathers the sources and adds near
+// and far terms to their own sums, each in quad order.
+template <typename T, int MP, int G, int U, bool NT>
+struct GenPass {
+    Int4 r4[U];
+    T v[U][4];
+
+    __device__ inline void load(const T *val, const int *idx, size_t base, int Kq, int kq0, int j) {
+        using VT = typename Vec16<T>::type;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kq = kq0 + u * G;
-            r4[u] = (Int4)0;
+            // no default value: use() reads a quad under the same test, and a
+            // merge with a default would make the loads wait right here
             if (kq < Kq) {
                 const size_t o = base + ((size_t)kq * MP + j) * 4;
-                r4[u] = __builtin_nontemporal_load((const Int4 *)(idx + o));
+                r4[u] = stream_load<Int4, NT>((const Int4 *)(idx + o));
                 if constexpr (sizeof(T) == 8) {
-                    const VT v01 = __builtin_nontemporal_load((const VT *)(val + o));
-                    const VT v23 = __builtin_nontemporal_load((const VT *)(val + o + 2));
+                    const VT v01 = stream_load<VT, NT>((const VT *)(val + o));
+                    const VT v23 = stream_load<VT, NT>((const VT *)(val + o + 2));
                     v[u][0] = v01[0], v[u][1] = v01[1], v[u][2] = v23[0], v[u][3] = v23[1];
                 } else {
-                    const VT v4 = __builtin_nontemporal_load((const VT *)(val + o));
+                    const VT v4 = stream_load<VT, NT>((const VT *)(val + o));
                     v[u][0] = v4[0], v[u][1] = v4[1], v[u][2] = v4[2], v[u][3] = v4[3];
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (kq0 + u * G < Kq)
-                acc += v[u][0] * src[r4[u][0]] + v[u][1] * src[r4[u][1]] +
-                       v[u][2] * src[r4[u][2]] + v[u][3] * src[r4[u][3]];
     }
-    return acc;
-}
+
+    __device__ inline void use(int Kq, int Kqn, int kq0, const T *srcN, const T *srcF, T &accN,
+                               T &accF) const {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kq = kq0 + u * G;
+            if (kq < Kq) {
+                const T *src = kq < Kqn ? srcN : srcF;
+                const T t = v[u][0] * src[r4[u][0]] + v[u][1] * src[r4[u][1]] +
+                            v[u][2] * src[r4[u][2]] + v[u][3] * src[r4[u][3]];
+                if (kq < Kqn)
+                    accN += t;
+                else
+                    accF += t;
+            }
+        }
+    }
+};
 
 // One workgroup of a half-sweep: LPW levels (team t of group q owns level
 // parity + 2 (q LPW + t)), then the group's partial sums into slot slot0 + q.
-template <typename T, int MP, bool PHB>
+// NT: non-temporal loads of the stored entries (a stage whose blocks and
+// entries exceed the last-level cache streams them; a smaller one keeps them
+// cached from sweep to sweep).
+template <typename T, int MP, bool PHB, bool NT>
 __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *tab, const T *val,
                                        const int *idx, int q, bool live, double inv_old,
                                        T *red_base, T *rv_base, double *sh) {
@@ -72,6 +87,10 @@ __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *ta
     constexpr int G = TS / MP;            // lanes splitting the ELL slots of a column
     constexpr size_t BS = (size_t)MP * MP;
     static_assert(G >= 1 && G <= R, "team narrower than a block");
+    // With one level per workgroup (the large blocks) a CU holds few waves,
+    // so the waves keep all their W_i rows in flight, not just PF of them:
+    // the registers are there, and the loads in flight set the bandwidth.
+    constexpr int PW = LPW == 1 ? (RPT < 32 ? RPT : 32) : PF;
 
     const DevState *st = a.st;
     const int tid = threadIdx.x;
@@ -81,26 +100,41 @@ __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *ta
     T *rv = rv_base + team * MP;
     const int i = a.parity + 2 * (q * LPW + team);
     const bool active = i < a.L;
-    const int ic = active ? i : a.parity;
+    // a team of whole waves has one level per wave: make it wave-uniform, so
+    // its table entry comes through a scalar load and the first vector loads
+    // need not wait for it behind the vector queue
+    const int ic = TS >= 64 ? __builtin_amdgcn_readfirstlane(active ? i : a.parity)
+                            : (active ? i : a.parity);
     T *w_new = a.w_new;
     const T *wb = a.blk + (size_t)ic * BS + c * VEC;   // W_ic, the only dense block
     const GenEntry te = tab[ic];
 
-    // rows of W_i stream while the gathers run
-    VT vpre[PF];
-#pragma unroll
-    for (int qq = 0; qq < PF; ++qq)
-        vpre[qq] = stream_load<VT, true>((const VT *)(wb + (size_t)(g + R * qq) * MP));
-
-    // r_i[j] = sum over the column's slots of val * source; the previous
-    // iterate's terms are scaled by kappa once, after their sum
+    // r_i[j] = sum over the column's slots of val * source.  The lane's first
+    // pass of ELL loads goes out before the W_i rows: loads return in order,
+    // so behind the rows the gather would wait for the whole block first.
+    constexpr int U = sizeof(T) == 8 ? 2 : 4;   // FP64 quads hold twice the registers
     const int j = tt % MP, gg0 = tt / MP;
-    const T near = gen_gather<T, MP, G>(val, idx, (size_t)te.off, te.Kn >> 2, j, gg0,
-                                        PHB ? (const T *)w_new : a.w_old);
-    const T far = gen_gather<T, MP, G>(val, idx, (size_t)te.off + (size_t)te.Kn * MP, te.Kf >> 2,
-                                       j, gg0, a.w_old);
+    const int Kqn = te.Kn >> 2, Kq = (te.Kn + te.Kf) >> 2;
+    GenPass<T, MP, G, U, NT> pass;
+    pass.load(val, idx, (size_t)te.off, Kq, gg0, j);
+
+    // rows of W_i stream while the gathers run
+    VT vpre[PW];
+#pragma unroll
+    for (int qq = 0; qq < PW; ++qq)
+        vpre[qq] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * qq) * MP));
+
+    // phase B reads the near sources fresh; the previous iterate's terms are
+    // scaled by kappa once, after their sum
+    const T *srcN = PHB ? (const T *)w_new : a.w_old;
+    T accN = 0, accF = 0;
+    pass.use(Kq, Kqn, gg0, srcN, a.w_old, accN, accF);
+    for (int kq0 = gg0 + G * U; kq0 < Kq; kq0 += G * U) {
+        pass.load(val, idx, (size_t)te.off, Kq, kq0, j);
+        pass.use(Kq, Kqn, kq0, srcN, a.w_old, accN, accF);
+    }
     const T sc = (T)inv_old;
-    red[gg0 * MP + j] = PHB ? near + sc * far : sc * (near + far);
+    red[gg0 * MP + j] = PHB ? accN + sc * accF : sc * (accN + accF);
     __syncthreads();
     if (tt < MP) {
         T r = 0;
@@ -115,8 +149,8 @@ __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *ta
 #pragma unroll
     for (int qq = 0; qq < RPT; ++qq) {
         const int row = g + R * qq;
-        const VT wv = (qq < PF) ? vpre[qq < PF ? qq : 0]
-                                : stream_load<VT, true>((const VT *)(wb + (size_t)row * MP));
+        const VT wv = (qq < PW) ? vpre[qq < PW ? qq : 0]
+                                : stream_load<VT, NT>((const VT *)(wb + (size_t)row * MP));
         acc2 += wv * rv[row];
     }
 #pragma unroll
@@ -145,7 +179,7 @@ __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *ta
     }
 }
 
-template <typename T, int MP, bool PHB>
+template <typename T, int MP, bool PHB, bool NT>
 __global__ __launch_bounds__(kWG) void k_sweep_gen(SweepLaunch a, const GenEntry *tab,
                                                     const void *val, const int *idx) {
     using TL = Tile<T, MP, 8>;
@@ -158,7 +192,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_gen(SweepLaunch a, const GenEntry
     }
     const bool live = a.st->stop_flag == 0;
     const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
-    sweep_group_gen<T, MP, PHB>(view_of<T>(a), tab, (const T *)val, idx, blockIdx.x, live, kappa,
+    sweep_group_gen<T, MP, PHB, NT>(view_of<T>(a), tab, (const T *)val, idx, blockIdx.x, live, kappa,
                                 red, rv, sh);
 }
 
@@ -228,37 +262,40 @@ __global__ __launch_bounds__(kWG) void k_residual_gen(const double *diag, const 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T, int MP>
+template <typename T, int MP, bool NT>
 static hipError_t gen_mp(bool phase_b, const SweepLaunch &a, const GenEntry *tab, const void *val,
                          const int *idx, hipStream_t s, LaunchTimer t) {
     const int groups = phase_groups((int)sizeof(T), MP, a.L, a.parity, kEllGeometry) +
                        ((phase_b && a.fold) ? 1 : 0);   // + the reduction workgroup
     if (groups <= 0) return hipSuccess;
     if (phase_b)
-        launch_timed(k_sweep_gen<T, MP, true>, groups, s, t, a, tab, val, idx);
+        launch_timed(k_sweep_gen<T, MP, true, NT>, groups, s, t, a, tab, val, idx);
     else
-        launch_timed(k_sweep_gen<T, MP, false>, groups, s, t, a, tab, val, idx);
+        launch_timed(k_sweep_gen<T, MP, false, NT>, groups, s, t, a, tab, val, idx);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool NT>
 static hipError_t gen_t(int MP, bool phase_b, const SweepLaunch &a, const GenEntry *tab,
                         const void *val, const int *idx, hipStream_t s, LaunchTimer t) {
     switch (MP) {
-        case 8: return gen_mp<T, 8>(phase_b, a, tab, val, idx, s, t);
-        case 16: return gen_mp<T, 16>(phase_b, a, tab, val, idx, s, t);
-        case 32: return gen_mp<T, 32>(phase_b, a, tab, val, idx, s, t);
-        case 64: return gen_mp<T, 64>(phase_b, a, tab, val, idx, s, t);
-        case 128: return gen_mp<T, 128>(phase_b, a, tab, val, idx, s, t);
+        case 8: return gen_mp<T, 8, NT>(phase_b, a, tab, val, idx, s, t);
+        case 16: return gen_mp<T, 16, NT>(phase_b, a, tab, val, idx, s, t);
+        case 32: return gen_mp<T, 32, NT>(phase_b, a, tab, val, idx, s, t);
+        case 64: return gen_mp<T, 64, NT>(phase_b, a, tab, val, idx, s, t);
+        case 128: return gen_mp<T, 128, NT>(phase_b, a, tab, val, idx, s, t);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, const SweepLaunch &a,
-                                  const GenEntry *tab, const void *val, const int *idx,
-                                  hipStream_t stream, LaunchTimer t) {
-    return precision_bytes == 8 ? gen_t<double>(MP, phase_b, a, tab, val, idx, stream, t)
-                                : gen_t<float>(MP, phase_b, a, tab, val, idx, stream, t);
+hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, bool nt,
+                                  const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                  const int *idx, hipStream_t stream, LaunchTimer t) {
+    if (precision_bytes == 8)
+        return nt ? gen_t<double, true>(MP, phase_b, a, tab, val, idx, stream, t)
+                  : gen_t<double, false>(MP, phase_b, a, tab, val, idx, stream, t);
+    return nt ? gen_t<float, true>(MP, phase_b, a, tab, val, idx, stream, t)
+              : gen_t<float, false>(MP, phase_b, a, tab, val, idx, stream, t);
 }
 
 template <typename T, int MP>

@@ -185,9 +185,10 @@ hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase
 // Generators of any block pattern (stc_general.hip): the sweep phases and
 // the residual, over the diagonal blocks (inverse W_i in blk, Q_ii in diag)
 // and the per-level GenEntry table.
-hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, const SweepLaunch &a,
-                                  const GenEntry *tab, const void *val, const int *idx,
-                                  hipStream_t stream, LaunchTimer t = LaunchTimer());
+// nt: non-temporal loads of the stored blocks and entries.
+hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, bool nt,
+                                  const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                  const int *idx, hipStream_t stream, LaunchTimer t = LaunchTimer());
 hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
                                const GenEntry *tab, const double *val64, const int *idx,
                                const void *w, int L, DevState *st, long long slot, double *part,

@@ -467,7 +467,7 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTime
     auto phase = [&](bool phb) {
         const LaunchTimer t = tm ? (phb ? tm->b : tm->a) : LaunchTimer();
         if (h->general)
-            return launch_sweep_phase_gen(bytes, h->MP, phb, a, h->gen_tab,
+            return launch_sweep_phase_gen(bytes, h->MP, phb, (v & 2) != 0, a, h->gen_tab,
                                           f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
                                           h->gen_idx, h->stream, t);
         if (h->sparse)
@@ -881,6 +881,14 @@ stc_status pack_general(stc_handle *h, const stc_generator *g) {
         h->gen_vin[ph] = cnt;
     }
     h->gen_host = tab;
+    // the kernel's one variant bit is the load policy (bit 1, non-temporal):
+    // a stage whose inverse blocks and entries fit the 256 MB last-level cache
+    // keeps them there from sweep to sweep (plain loads); larger ones stream
+    for (int f = 0; f < 2; ++f) {
+        const double sb = f ? 4.0 : 8.0;
+        const double bytes = (double)L * bs * sb + (double)at * (sb + 4.0);
+        h->variant[f] = bytes > 256.0 * (1 << 20) ? 2 : 0;
+    }
     return STC_OK;
 }
 
@@ -1327,10 +1335,19 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
         // time every variant from the uniform start in this stage's precision
         double best = 1e300;
         int best_v = h->variant[stage];
-        const int nvs = h->sparse ? 1 : nv;   // the sparse kernel has no variants
-        for (int v = 0; v < nvs && rc == STC_OK; ++v) {
+        // the banded sparse kernel has no variants; the any-pattern kernel has
+        // its load policy (plain or non-temporal); the dense kernels all
+        std::vector<int> cands;
+        if (h->general)
+            cands = {0, 2};
+        else if (h->sparse)
+            cands = {h->variant[stage]};
+        else
+            for (int v = 0; v < nv; ++v) cands.push_back(v);
+        for (int v : cands) {
+            if (rc != STC_OK) break;
             if ((rc = load_vector_stage(h, nullptr, STC_MEM_HOST, f32)) != STC_OK) break;
-            if (!h->sparse) h->variant[stage] = v;
+            h->variant[stage] = v;
             if (variant_flow(v) && flow_blocks(h) == 0) continue;   // no persistent form here
             // 3 warm-up sweeps, then the timed burst, each as the solver runs them
             if ((rc = run_burst(h, 0, 3, 0.0)) != STC_OK) break;

@@ -20,6 +20,7 @@ from .general import (  # noqa: F401
     SparseGenerator,
     equal_levels,
     mutual_exclusion,
+    mutual_exclusion_pi,
     mutual_exclusion_states,
     localized,
 )

@@ -156,6 +156,21 @@ def mutual_exclusion(n: int = 16, r: int = 12, seed: int = 0, *, m: int = 128,
                           {"lam": lam, "mu": mu, "masks": masks, "n": n, "r": r})
 
 
+def mutual_exclusion_pi(g: SparseGenerator) -> np.ndarray:
+    """The model's known stationary vector: pi(S) proportional to the product
+    of lam_p / mu_p over the users p in S.  Each process alone is a reversible
+    two-state chain; blocking the requests that would exceed r users truncates
+    the product chain to a subset of its states, which keeps the product form
+    restricted to that subset (Kelly's truncation of reversible chains)."""
+    rho = g.extra["lam"] / g.extra["mu"]
+    masks = g.extra["masks"]
+    logw = np.zeros(len(masks))
+    for p in range(g.extra["n"]):
+        logw += np.where((masks >> p) & 1, np.log(rho[p]), 0.0)
+    w = np.exp(logw - logw.max())
+    return w / w.sum()
+
+
 def localized(L: int, m: int, seed: int, *, up: int = 3, down: int = 3, density: float = 0.2,
               decay: float = 0.5, jumps: int = 2, ragged: bool = False,
               backbone: float = 0.05) -> SparseGenerator:

@@ -46,13 +46,7 @@ def _start(g, seed):
 
 
 def mutex_closed_form(g):
-    rho = g.extra["lam"] / g.extra["mu"]
-    masks = g.extra["masks"]
-    logw = np.zeros(len(masks))
-    for p in range(g.extra["n"]):
-        logw += np.where((masks >> p) & 1, np.log(rho[p]), 0.0)
-    w = np.exp(logw - logw.max())
-    return w / w.sum()
+    return synth.mutual_exclusion_pi(g)
 
 
 GENERAL = [
@@ -212,4 +206,37 @@ def test_mutex_full_size_step_and_solve():
     err = np.abs(pi - exact).sum()
     _say(f"mutex full solve 1e-13: iters {info['iters']} err {err:.2e} res {info['residual_1']:.2e}")
     assert info["status"] == 0 and err <= 1e-10
+    s.close()
+
+
+def test_load_policies_agree_and_default_by_size():
+    """The kernel's one variant bit is its load policy (plain or non-temporal):
+    both give bitwise the same sweeps.  Small stages default to plain loads
+    (they stay in the last-level cache); a stage above 256 MB streams."""
+    from paper_2302_07551_amd import stc
+    g = synth.localized(24, 32, 15, up=3, down=2, jumps=2, ragged=True)
+    x = _start(g, 2)
+    a, b = _solver(g), _solver(g)
+    assert stc.stc_get_variant(a.h, stc.STC_FP64) == 0
+    stc.stc_set_variant(b.h, stc.STC_FP64, 2)
+    for s in (a, b):
+        s.load(x)
+        s.sweeps(5)
+    assert np.array_equal(a.store(), b.store())
+    stc.stc_autotune(a.h, 3)
+    assert stc.stc_get_variant(a.h, stc.STC_FP64) in (0, 2)
+    a.close()
+    b.close()
+    big = synth.localized(2200, 128, 16, up=1, down=1, jumps=1, density=0.01)
+    _say("large any-pattern chain: default load policy")
+    s = _solver(big)
+    assert stc.stc_get_variant(s.h, stc.STC_FP64) == 2   # 2200 x 128 KB of inverses
+    x = _start(big, 3)
+    s.load(x)
+    s.sweeps(3)
+    z_nt = s.store()
+    stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+    s.load(x)
+    s.sweeps(3)
+    assert np.array_equal(z_nt, s.store())
     s.close()

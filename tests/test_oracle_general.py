@@ -32,15 +32,7 @@ def _start(N, seed):
 
 
 def mutex_closed_form(g):
-    """pi(S) proportional to prod_{p in S} lam_p / mu_p over the states."""
-    rho = g.extra["lam"] / g.extra["mu"]
-    masks = g.extra["masks"]
-    n = g.extra["n"]
-    logw = np.zeros(len(masks))
-    for p in range(n):
-        logw += np.where((masks >> p) & 1, np.log(rho[p]), 0.0)
-    w = np.exp(logw - logw.max())
-    return w / w.sum()
+    return synth.mutual_exclusion_pi(g)
 
 
 GENERAL = [
