@@ -10,7 +10,9 @@ Prints one JSON line.  Options:
   --gpus N        only 1 is supported (one GPU per run)
   --steps K       timed sweeps (default 200)
   --warmup W      untimed sweeps first (default 20)
-  --no-cpu        skip the CPU oracle baseline
+  --no-cpu        skip the CPU-baseline leg (the oracle's sweep timed on the
+                  host cores, and its direct solve, whose vector is the pi_ref
+                  the GPU errors are reported against)
   --no-ttr        skip the time to ||Q^T pi||_1 <= 1e-12, FP64 vs mixed
 
 Other workloads (each prints its own JSON line instead):
@@ -27,6 +29,10 @@ Other workloads (each prints its own JSON line instead):
                   block bandwidth 4 (down one level, up to four): sweeps/s
                   with dense and sparse storage, FP64 and FP32, and the time
                   to a change of 1e-13 against the direct solution
+  --mutex         the mutual-exclusion model (16 processes, at most 12 users,
+                  N = 64839) as a generator of any block pattern, m = 128 and
+                  64: sweeps/s, time to the change tolerance 1e-9 and 1e-13,
+                  errors against the closed-form stationary vector
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -108,6 +114,17 @@ def cpu_baseline(gen, budget_s: float = 12.0, threads: int | None = None):
         if el >= budget_s or n >= 2000:
             break
     return el / n, n, cs.threads
+
+
+def cpu_reference(gen):
+    """The CPU-baseline leg's direct solve: the oracle's level-by-level GTH
+    elimination on the host, timed as a CPU baseline.  Its vector is the
+    pi_ref that the GPU results are compared with afterwards; the GPU path
+    never reads it.  Returns (pi_ref, seconds)."""
+    from oracle import level_reduction
+    t0 = time.perf_counter()
+    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
+    return ref, time.perf_counter() - t0
 
 
 def device_copy_rate(nbytes: int = 1 << 30, reps: int = 10) -> float:
@@ -251,7 +268,10 @@ def main():
     }
 
     if not args.no_ttr:
-        line["time_to_residual"] = time_to_residual(gen)
+        ref, t_ref = cpu_reference(gen) if not args.no_cpu else (None, None)
+        line["time_to_residual"] = time_to_residual(gen, ref)
+        if t_ref is not None:
+            line["cpu_direct_solve_s"] = round(t_ref, 3)
 
     # the device's own copy rate on the same box, as a second yardstick
     copy_gbs = device_copy_rate()
@@ -274,12 +294,12 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def time_to_residual(gen, tol=1e-12):
+def time_to_residual(gen, ref=None, tol=1e-12):
+    """FP64 and mixed solves to ||Q^T pi||_1 <= tol; with pi_ref from the
+    CPU-baseline leg, the error of each result as well."""
     import numpy as np
     import torch
-    from oracle import level_reduction
     from paper_2302_07551_amd import Solver
-    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
     out = {}
     for prec in ("fp64", "mixed"):
         s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec, stop="residual",
@@ -290,7 +310,8 @@ def time_to_residual(gen, tol=1e-12):
         dt = time.perf_counter() - t0
         out[prec] = {"seconds": round(dt, 4), "iters": info["iters"],
                      "iters_fp32": info["iters_fp32"], "residual": info["residual_1"],
-                     "err_vs_direct": float(np.abs(pi - ref).sum())}
+                     "err_vs_direct": (float(np.abs(pi - ref).sum()) if ref is not None
+                                       else None)}
         s.close()
     return out
 
@@ -327,15 +348,13 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
     import numpy as np
     import torch
     import synth
-    from oracle import level_reduction
     from paper_2302_07551_amd import Solver, stc
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     gen = synth.qbd(L, m, synth.config_seed(3))
     t_gen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
-    t_ref = time.perf_counter() - t0
+    # the error target needs pi_ref, so this mode always runs the CPU leg
+    ref, t_ref = cpu_reference(gen)
     print(f"# generated in {t_gen:.1f}s, direct reference in {t_ref:.1f}s", file=sys.stderr,
           flush=True)
     rates = {p: sweep_rate(gen, p) for p in ("fp64", "fp32")}
@@ -362,7 +381,10 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
             "config": {"workload": f"qbd_L{L}_m{m}", "levels": L, "block": m, "N": L * m,
                        "seed": synth.config_seed(3)},
             "speedup_mixed_vs_fp64": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3),
-            "runs": runs, "sweep_rates": rates}
+            "runs": runs, "sweep_rates": rates,
+            "cpu_baseline": {"kind": "oracle", "direct_solve_s": round(t_ref, 2), "cores": 1,
+                             "sample": "the oracle's level-by-level GTH solve of the whole "
+                                       "chain (also pi_ref)"}}
     print(json.dumps(line), flush=True)
 
 
@@ -399,14 +421,12 @@ def skipfree_mode(L=2048, m=64, b=4):
     import numpy as np
     import torch
     import synth
-    from oracle import level_reduction
     from paper_2302_07551_amd import Solver
     torch.cuda.set_device(0)
     seed = synth.config_seed(5)
     gen = synth.skip_free(L, m, seed, b=b)
-    t0 = time.perf_counter()
-    ref = level_reduction.level_reduction(gen.blocks, gen.sizes, gen.b)
-    print(f"# direct reference in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    ref, t_ref = cpu_reference(gen)
+    print(f"# direct reference in {t_ref:.1f}s", file=sys.stderr, flush=True)
     runs = {}
     for fmt in ("dense", "sparse"):
         for prec in ("fp64", "fp32"):
@@ -435,7 +455,10 @@ def skipfree_mode(L=2048, m=64, b=4):
             "n_gpus": 1, "dtype": "f64 (mixed: f32+f64)", "data": "synthetic",
             "config": {"workload": f"skipfree_b{b}_L{L}_m{m}", "levels": L, "block": m,
                        "bandwidth": b, "N": L * m, "seed": seed},
-            "sweep_rates": runs, "solves": solves}
+            "sweep_rates": runs, "solves": solves,
+            "cpu_baseline": {"kind": "oracle", "direct_solve_s": round(t_ref, 2), "cores": 1,
+                             "sample": "the oracle's level-by-level GTH solve of the whole "
+                                       "chain (also pi_ref)"}}
     print(json.dumps(line), flush=True)
 
 
@@ -704,7 +727,6 @@ def serve_mode(args):
     import numpy as np
     import torch
     import synth
-    from oracle import level_reduction
     from paper_2302_07551_amd.serve import Request, Server
     torch.cuda.set_device(0)
     n = args.serve
@@ -740,12 +762,13 @@ def serve_mode(args):
         _, summ = run("mixed", frac * lam)
         poisson[f"{frac}x"] = summ
     # accuracy of a sample of served results against the direct FP64 solution
+    # of the CPU-baseline leg
     by_id = {r.rid: r for r in sat.results}
     sample = list(range(0, n, max(1, n // 16)))
-    errs = []
+    errs, t_cpu = [], 0.0
     for k in sample:
-        g = gens[k]
-        ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+        ref, t_ref = cpu_reference(gens[k])
+        t_cpu += t_ref
         errs.append(float(np.abs(by_id[k].pi - ref).sum()))
     line = {"metric": "served stationary solves: p99 latency and solves/s",
             "value": poisson["0.8x"]["p99_latency_s"], "unit": "s", "higher_is_better": False,
@@ -756,7 +779,10 @@ def serve_mode(args):
             "saturated_mixed": sat_summ, "saturated_fp64": sat64_summ,
             "speedup_mixed_vs_fp64": round(sat_summ["solves_per_s"] / sat64_summ["solves_per_s"], 3),
             "poisson": poisson,
-            "max_err_vs_direct_sample": max(errs), "sample_size": len(sample)}
+            "max_err_vs_direct_sample": max(errs), "sample_size": len(sample),
+            "cpu_baseline": {"kind": "oracle", "direct_solve_s_sample": round(t_cpu, 2),
+                             "cores": 1, "sample": f"the oracle's direct solve of {len(sample)} "
+                                                   "served chains (also their pi_ref)"}}
     print(json.dumps(line), flush=True)
 
 

@@ -23,4 +23,6 @@ from .general import (  # noqa: F401
     mutual_exclusion_pi,
     mutual_exclusion_states,
     localized,
+    hessenberg_mmatrix,
+    with_levels,
 )

@@ -17,6 +17,9 @@ given):
                  the number of users, then lexicographically by the set of
                  users.  n = 16, r = 12 gives N = 64839 as in the paper.  The
                  rates are seeded draws (the paper does not give them).
+  * ``hessenberg_mmatrix``  random singular M-matrices A = Q^T in banded
+                 block lower Hessenberg form, the matrices of Example 3 of
+                 section 2 (n blocks of size k, scalar lower bandwidth 4k).
   * ``localized``  random generator with blocks at every level distance up to
                  `up` above and `down` below the diagonal, rates scaled by
                  decay^(|d| - 1), a few long jumps to random far levels, and a
@@ -169,6 +172,32 @@ def mutual_exclusion_pi(g: SparseGenerator) -> np.ndarray:
         logw += np.where((masks >> p) & 1, np.log(rho[p]), 0.0)
     w = np.exp(logw - logw.max())
     return w / w.sum()
+
+
+def hessenberg_mmatrix(n: int = 16, k: int = 64, seed: int = 0, *, lower: int = 4,
+                       m: int | None = None) -> SparseGenerator:
+    """A random singular M-matrix A = Q^T of Example 3: n x n blocks of size
+    k, banded block lower Hessenberg.  A_{ij} (i != j) is drawn U[0, 1] inside
+    the profile: j in a block column at most one above i's (block
+    Hessenberg) and i - j <= lower * k (the scalar lower bandwidth); zero
+    outside.  The diagonal makes every column of A, i.e. every row of the
+    generator Q, sum to 0.  Levels: equal runs of m states (default k)."""
+    rng = np.random.default_rng(seed)
+    N = n * k
+    i = np.repeat(np.arange(N), N)
+    j = np.tile(np.arange(N), N)
+    keep = (j // k <= i // k + 1) & (i - j <= lower * k) & (i != j)
+    i, j = i[keep], j[keep]
+    a = rng.random(len(i))
+    # Q_{j,i} = A_{i,j}
+    return _from_triplets(j, i, a, N, equal_levels(N, m or k), f"hessenberg_n{n}_k{k}",
+                          {"n": n, "k": k, "lower": lower})
+
+
+def with_levels(g: SparseGenerator, m: int) -> SparseGenerator:
+    """The same generator partitioned into equal levels of m states."""
+    return SparseGenerator(g.indptr, g.indices, g.data, equal_levels(g.N, m),
+                           f"{g.name}_m{m}", dict(g.extra))
 
 
 def localized(L: int, m: int, seed: int, *, up: int = 3, down: int = 3, density: float = 0.2,

@@ -154,3 +154,47 @@ def test_far_levels_read_fresh_is_caught(monkeypatch):
     x = _start(g.N, 7)
     z, _ = staircase.staircase_sweep(sys, x, 1)
     assert np.abs(z - _dense_step(g, x, 1)).sum() > 1e-6
+
+
+# --- Example 3 / Table 1 ---------------------------------------------------
+
+def test_example3_matrix_profile():
+    """n = 16 blocks of size k: block lower Hessenberg (one block column above
+    the diagonal), scalar lower bandwidth 4k, a singular M-matrix whose
+    columns sum to 0."""
+    g = synth.hessenberg_mmatrix(16, 16, 0)
+    A = g.to_scipy().T.toarray()
+    off = A - np.diag(np.diag(A))
+    i, j = np.nonzero(off)
+    assert (i - j).max() == 64 and (j // 16 - i // 16).max() == 1
+    assert off.min() >= 0.0 and np.abs(A.sum(axis=0)).max() < 1e-13
+
+
+def test_example3_block_tridiagonal_partition_gives_bgs_spectrum():
+    """With kp = 64 and k = 16 the partition makes A block tridiagonal, where
+    section 2 proves block staircase and block Gauss-Seidel share their
+    eigenvalues (Table 1 prints rho_2 = 1.0 there); block Jacobi has a second
+    eigenvalue of modulus 1 (the printed rho_1 = inf)."""
+    from oracle import table1
+    g = synth.hessenberg_mmatrix(16, 16, 2)
+    A = g.to_scipy().T.toarray()
+    sizes = synth.equal_levels(g.N, 64)
+    ev_gs = splittings.spectrum(A, sizes, "gs")
+    ev_bs = splittings.spectrum(A, sizes, "stair1")
+    big = np.abs(ev_gs) > 1e-6
+    assert np.allclose(np.sort(np.abs(ev_gs[big])), np.sort(np.abs(ev_bs[np.abs(ev_bs) > 1e-6])),
+                       atol=1e-10)
+    gm = table1.gammas(A, sizes)
+    r1, r2 = table1.ratios(gm)
+    assert abs(r2 - 1.0) < 1e-8 and r1 == np.inf
+
+
+def test_example3_staircase_close_to_gauss_seidel():
+    """The qualitative claim of Example 3: at k = 64, kp = 16 the staircase
+    spectral gap stays within a factor 2 of block Gauss-Seidel's (rho_2 in
+    [1, 2]), while block Jacobi's is smaller still (rho_1 > 1)."""
+    from oracle import table1
+    g = synth.hessenberg_mmatrix(16, 64, 0)
+    A = g.to_scipy().T.toarray()
+    r1, r2 = table1.ratios(table1.gammas(A, synth.equal_levels(g.N, 16)))
+    assert 1.0 < r1 < 2.0 and 1.0 <= r2 < 2.0
