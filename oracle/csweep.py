@@ -37,6 +37,12 @@ def _load():
     lib.cs_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp, _dp, _ip,
                              ctypes.c_int, _dp, _dp, _dp]
     lib.cs_sweep.restype = ctypes.c_int
+    _lp = ctypes.POINTER(ctypes.c_longlong)
+    lib.cs_gen_factor.argtypes = [ctypes.c_int, ctypes.c_int, _lp, _lp, _ip, _dp, _dp, _ip]
+    lib.cs_gen_factor.restype = ctypes.c_int
+    lib.cs_gen_sweep.argtypes = [ctypes.c_int, ctypes.c_int, _lp, _lp, _ip, _dp, _dp, _ip,
+                                 ctypes.c_int, _dp, _dp, _dp]
+    lib.cs_gen_sweep.restype = ctypes.c_int
     lib.cs_threads.argtypes = [ctypes.c_int]
     lib.cs_threads.restype = ctypes.c_int
     return lib
@@ -70,6 +76,49 @@ class CSweep:
         rc = self.lib.cs_sweep(self.L, self.m, self.b, _p(self.sizes, _ip),
                                _p(self.blocks, _dp), _p(self.lu, _dp), _p(self.piv, _ip),
                                self.stair_type, _p(x, _dp), _p(z, _dp), ctypes.byref(err))
+        if rc != 0:
+            raise ArithmeticError("e^T z <= 0")
+        return err.value
+
+
+class CGenSweep:
+    """The same Algorithm 2 for a generator of any block pattern: A = Q^T as
+    compact CSR (a scipy matrix or Q itself, transposed here), level sizes;
+    vectors are compact, length N."""
+
+    def __init__(self, Q, sizes, stair_type: int = 1, threads: int = 0):
+        import scipy.sparse as sp
+        self.lib = _load()
+        self.threads = self.lib.cs_threads(int(threads))
+        A = sp.csr_matrix(Q).T.tocsr()
+        A.sort_indices()
+        self.rp = np.ascontiguousarray(A.indptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(A.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(A.data, dtype=np.float64)
+        sizes = np.asarray(sizes, dtype=np.int64)
+        self.off = np.zeros(len(sizes) + 1, dtype=np.int64)
+        np.cumsum(sizes, out=self.off[1:])
+        self.L = len(sizes)
+        self.m = int(sizes.max())
+        self.N = int(self.off[-1])
+        self.stair_type = int(stair_type)
+        self.lu = np.zeros((self.L, self.m, self.m))
+        self.piv = np.zeros((self.L, self.m), dtype=np.int32)
+        _lp = ctypes.POINTER(ctypes.c_longlong)
+        self._lp = _lp
+        rc = self.lib.cs_gen_factor(self.L, self.m, _p(self.off, _lp), _p(self.rp, _lp),
+                                    _p(self.col, _ip), _p(self.val, _dp), _p(self.lu, _dp),
+                                    _p(self.piv, _ip))
+        if rc != 0:
+            raise np.linalg.LinAlgError("singular diagonal block")
+
+    def sweep(self, x: np.ndarray, z: np.ndarray) -> float:
+        err = ctypes.c_double(0.0)
+        lp = self._lp
+        rc = self.lib.cs_gen_sweep(self.L, self.m, _p(self.off, lp), _p(self.rp, lp),
+                                   _p(self.col, _ip), _p(self.val, _dp), _p(self.lu, _dp),
+                                   _p(self.piv, _ip), self.stair_type, _p(x, _dp), _p(z, _dp),
+                                   ctypes.byref(err))
         if rc != 0:
             raise ArithmeticError("e^T z <= 0")
         return err.value

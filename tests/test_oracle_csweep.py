@@ -45,3 +45,30 @@ def test_csweep_degenerate_start():
     cs = csweep.CSweep(g.blocks, g.sizes, g.b, 1, threads=1)
     with pytest.raises(ArithmeticError):
         cs.sweep(x, np.zeros_like(x))
+
+
+@pytest.mark.parametrize("stair_type", [1, 2])
+@pytest.mark.parametrize("cfg", [dict(L=12, m=6, seed=1, up=2, down=2, jumps=3, ragged=True),
+                                 dict(L=16, m=4, seed=2, up=16, down=1, jumps=0)],
+                         ids=["ragged_far", "hessenberg"])
+def test_general_c_sweep_equals_stair_matrix_definition(cfg, stair_type):
+    """The C sweep for generators of any block pattern: one sweep is the
+    normalised M^{-1} N x of the dense stair matrix (section 2), and the
+    fixed point is the GTH vector."""
+    from oracle import gth, splittings
+    g = synth.localized(**cfg)
+    A = g.to_scipy().T.toarray()
+    M = splittings.splitting_M(A, g.sizes, f"stair{stair_type}")
+    x = np.random.default_rng(3).uniform(0.5, 1.5, g.N)
+    x /= x.sum()
+    want = np.linalg.solve(M, (M - A) @ x)
+    want /= want.sum()
+    c = csweep.CGenSweep(g.to_scipy(), g.sizes, stair_type=stair_type)
+    z = np.zeros(g.N)
+    err = c.sweep(x, z)
+    assert np.abs(z - want).sum() < 1e-13
+    assert abs(err - np.abs(want - x).sum()) < 1e-13
+    pi = gth.gth(g.to_scipy().toarray())
+    z2 = np.zeros(g.N)
+    c.sweep(pi.copy(), z2)
+    assert np.abs(z2 - pi).sum() < 1e-13
