@@ -155,6 +155,17 @@ def staircase_sweep(sys: BlockSystem, x: np.ndarray, stair_type: int = 1,
     which includes k = i on stair rows); it exists only so that a test can
     show that this reading does not have pi as a fixed point.
     """
+    z = stair_apply(sys, x, stair_type, literal_J)
+    s = z.sum()
+    if not (np.isfinite(s) and s > 0.0):
+        raise DegenerateIterate(f"e^T z = {s}")
+    z /= s
+    return z, float(np.abs(z - x).sum())
+
+
+def stair_apply(sys, x: np.ndarray, stair_type: int = 1, literal_J: bool = False) -> np.ndarray:
+    """z = M^{-1} N x for the stair splitting Q^T = M - N, by the three
+    parallel loops of Algorithm 2 without the normalisation (any real x)."""
     L = sys.L
     diag_only, stair = phase_sets(L, stair_type)
     Js = {i: J_set(i, L, stair_type) for i in range(L)}
@@ -176,11 +187,7 @@ def staircase_sweep(sys: BlockSystem, x: np.ndarray, stair_type: int = 1,
         for k in Js[i]:
             rhs -= sys.A(i, k) @ sys.seg(z, k)
         sys.seg(z, i)[:] = np.linalg.solve(sys.A(i, i), rhs)
-    s = z.sum()
-    if not (np.isfinite(s) and s > 0.0):
-        raise DegenerateIterate(f"e^T z = {s}")
-    z /= s
-    return z, float(np.abs(z - x).sum())
+    return z
 
 
 def staircase_solve(blocks: np.ndarray, sizes, b: int, *, stair_type: int = 1,
