@@ -132,6 +132,9 @@ typedef struct {
                              one ELL per level (values + 32-bit indices).
                              The inverse diagonal blocks are dense in both.
                              Batches take dense chains only.                  */
+    int32_t krylov_restart; /* 0, or the longest restart length r (1..256) that
+                             stc_solve_gmres may use: the footprint then holds
+                             r + 3 FP64 vectors and small buffers for it     */
 } stc_options;
 
 typedef struct {
@@ -166,6 +169,29 @@ stc_status stc_setup(const stc_generator *gen, const stc_options *opt, stc_handl
  * STC_EDEVICE.  res may be NULL. */
 stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
                      double *pi, stc_result *res, int32_t where);
+
+/* Krylov acceleration of the stair splitting: restarted GMRES(restart) on the
+ * left-preconditioned singular system (I - M^{-1} N) x = 0, with M the stair
+ * matrix of section 2, i.e. the splitting used as a preconditioner (the use
+ * the Conclusions leave to future work).  Each cycle starts from the
+ * normalised x, builds an orthonormal Krylov basis of M^{-1} A (M^{-1} N
+ * applied by the sweep kernels without normalisation; classical
+ * Gram-Schmidt, twice), takes the least-squares step and normalises again.
+ * Cycles repeat until ||Q^T x||_1 <= tol or max_applies applications of
+ * M^{-1} N.  Safeguard: on chains with strong drift the operator is far
+ * from normal and short cycles can stall, so a cycle is kept only if it
+ * lowers ||Q^T x||_1 per application by at least the square of the factor
+ * the last block of plain steps achieved (before any plain block: by half
+ * over the cycle); otherwise x stays and k plain normalised applications of
+ * M^{-1} N follow, k = restart at first, doubled after each rejected cycle.
+ * Always FP64.  x0 (NULL: e/N) is checked like stc_solve's;
+ * pi receives the last normalised iterate.  res->iters counts the
+ * applications, res->diff_1 the last cycle's change ||x_new - x||_1.
+ * Needs restart in 1..opt.krylov_restart (STC_EINVAL otherwise).  Returns
+ * STC_OK, STC_EMAXIT, STC_EDEGENERATE (e^T x <= 0 after a cycle),
+ * STC_EINVAL, STC_EDEVICE. */
+stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, double tol,
+                           int64_t max_applies, double *pi, stc_result *res, int32_t where);
 
 /* One sweep of Algorithm 2 from x (normalised first): z = M^{-1} N x,
  * normalised, and *diff_1 = ||z - x/e^T x||_1.  In STC_FP32 / STC_MIXED the

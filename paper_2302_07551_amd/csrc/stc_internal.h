@@ -213,6 +213,23 @@ hipError_t launch_store(int precision_bytes, int MP, const void *w, const long l
 hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
                            const double *diag64, const void *w, int L, DevState *st,
                            long long slot, double *part, hipStream_t stream);
+// Krylov acceleration (stc_krylov.hip): vectors are FP64 padded [L][MP].
+constexpr int kDotGroups = 128;     // chunks of a vector per partial dot
+constexpr int kMaxRestart = 256;    // largest GMRES restart length
+hipError_t launch_kstate_init(DevState *st, hipStream_t s);
+// out[v] = V[v] . w for v < nv (w = nullptr: e^T V[v]; absdiff:
+// ||V[v] - w||_1); norm: out[0] = sqrt(V[0] . w).  part holds G * nv doubles.
+hipError_t launch_kdots(const double *V, size_t ld, int nv, const double *w, size_t n,
+                        double *part, int G, double *out, bool norm, hipStream_t s,
+                        bool absdiff = false);
+// w += sign * sum_v h[v] V[v], h in device memory
+hipError_t launch_kupdate(const double *V, size_t ld, int nv, const double *h, double sign,
+                          double *w, size_t n, hipStream_t s);
+hipError_t launch_kaxpby(double a, const double *x, double b, const double *y, double *out,
+                         size_t n, hipStream_t s);
+// out = x / sdev[0]
+hipError_t launch_kscale(const double *x, const double *sdev, double *out, size_t n,
+                         hipStream_t s);
 // Sum the per-group residual partials into DevState::residual.
 hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream);
 hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,

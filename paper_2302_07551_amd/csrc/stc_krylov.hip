@@ -1,0 +1,121 @@
+// Vector kernels of the staircase-preconditioned GMRES (Krylov acceleration
+// of the stair splitting; its use as a preconditioner is the future work the
+// Conclusions name).  All vectors are FP64 in the padded layout [L][MP] with
+// zero padding, which every kernel here preserves.  Reductions are
+// compensated and in a fixed order, so every cycle is bitwise reproducible.
+#include "stc_device.h"
+
+namespace stc {
+
+// Apply-state of the Krylov operator T = M^{-1} N: every scale 1, never
+// stopped, so a sweep launch on it is the plain linear map.
+__global__ void k_kstate_init(DevState *st) {
+    for (int k = threadIdx.x; k < kRing; k += blockDim.x) {
+        st->inv_sigma[k] = 1.0;
+        st->diff[k] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+        st->stop_flag = 0;
+        st->status = kDevOk;
+        st->stop_sweep = -1;
+        st->last_sweep = 0;
+        st->residual = 0.0;
+        st->x_sum = 0.0;
+    }
+}
+
+// Partial dot products: block (c, v) sums V[v] . w over chunk c of the
+// vector (w = nullptr: the sum of V[v], i.e. e^T V[v]; absdiff: the sum of
+// |V[v] - w|).  part[v * G + c].
+__global__ __launch_bounds__(kWG) void k_kdot(const double *V, size_t ld, const double *w,
+                                               size_t n, double *part, int absdiff) {
+    __shared__ double sh[4 * kWG / 64];
+    const int G = gridDim.x, c = blockIdx.x, v = blockIdx.y;
+    const size_t chunk = (n + G - 1) / G;
+    const size_t e0 = (size_t)c * chunk, e1 = e0 + chunk < n ? e0 + chunk : n;
+    const double *x = V + (size_t)v * ld;
+    double s = 0.0, sc = 0.0;
+    for (size_t e = e0 + threadIdx.x; e < e1; e += kWG)
+        dd_acc(s, sc, !w ? x[e] : (absdiff ? fabs(x[e] - w[e]) : x[e] * w[e]));
+    s = block_sum_dd(s, sc, sh);
+    if (threadIdx.x == 0) part[(size_t)v * G + c] = s;
+}
+
+// out[v] = fixed-order compensated sum of the G partials of vector v;
+// mode 1: out[0] = sqrt of it (a 2-norm from a self dot).
+__global__ __launch_bounds__(kWG) void k_kfold(const double *part, int G, double *out, int mode) {
+    __shared__ double sh[4 * kWG / 64];
+    const int v = blockIdx.x;
+    double s = 0.0, sc = 0.0;
+    for (int c = threadIdx.x; c < G; c += kWG) dd_acc(s, sc, part[(size_t)v * G + c]);
+    s = block_sum_dd(s, sc, sh);
+    if (threadIdx.x == 0) out[v] = mode == 1 ? sqrt(s) : s;
+}
+
+// w += sign * sum_v h[v] V[v]  (h in device memory)
+__global__ __launch_bounds__(kWG) void k_kupdate(const double *V, size_t ld, int nv,
+                                                  const double *h, double sign, double *w,
+                                                  size_t n) {
+    for (size_t e = blockIdx.x * (size_t)kWG + threadIdx.x; e < n; e += (size_t)gridDim.x * kWG) {
+        double t = 0.0;
+        for (int v = 0; v < nv; ++v) t += h[v] * V[(size_t)v * ld + e];
+        w[e] += sign * t;
+    }
+}
+
+// out = a x + b y
+__global__ __launch_bounds__(kWG) void k_kaxpby(double a, const double *x, double b,
+                                                 const double *y, double *out, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)kWG + threadIdx.x; e < n; e += (size_t)gridDim.x * kWG)
+        out[e] = a * x[e] + b * y[e];
+}
+
+// out = x / s[0]  (s in device memory)
+__global__ __launch_bounds__(kWG) void k_kscale(const double *x, const double *s, double *out,
+                                                 size_t n) {
+    const double inv = 1.0 / s[0];
+    for (size_t e = blockIdx.x * (size_t)kWG + threadIdx.x; e < n; e += (size_t)gridDim.x * kWG)
+        out[e] = x[e] * inv;
+}
+
+static int stream_groups(size_t n) {
+    size_t g = (n + kWG - 1) / kWG;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_kstate_init(DevState *st, hipStream_t s) {
+    hipLaunchKernelGGL(k_kstate_init, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_kdots(const double *V, size_t ld, int nv, const double *w, size_t n, double *part,
+                        int G, double *out, bool norm, hipStream_t s, bool absdiff) {
+    if (nv < 1 || G < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kdot, dim3(G, nv), dim3(kWG), 0, s, V, ld, w, n, part, absdiff ? 1 : 0);
+    hipLaunchKernelGGL(k_kfold, dim3(nv), dim3(kWG), 0, s, part, G, out, norm ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_kupdate(const double *V, size_t ld, int nv, const double *h, double sign,
+                          double *w, size_t n, hipStream_t s) {
+    if (nv < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_kupdate, dim3(stream_groups(n)), dim3(kWG), 0, s, V, ld, nv, h, sign, w,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kaxpby(double a, const double *x, double b, const double *y, double *out,
+                         size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_kaxpby, dim3(stream_groups(n)), dim3(kWG), 0, s, a, x, b, y, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kscale(const double *x, const double *sdev, double *out, size_t n,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_kscale, dim3(stream_groups(n)), dim3(kWG), 0, s, x, sdev, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace stc

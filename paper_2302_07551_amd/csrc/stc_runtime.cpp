@@ -90,6 +90,10 @@ struct Layout {
     long long ell_slots = 0;    // sum over blocks of K * MP
     size_t gen_tab = 0, gen_v64 = 0, gen_v32 = 0, gen_idx = 0;
     long long gen_slots = 0;    // sum over levels of (Kn + Kf) * MP
+    // Krylov workspace: r + 3 FP64 vectors (x, w, v_0 .. v_r), the apply
+    // state, scratch partials of its sweeps, dot partials, small scalars
+    int kr = 0;
+    size_t kvec = 0, kst = 0, kpart = 0, kdot = 0, kh = 0;
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
     size_t nparts = 0, naux = 0;
@@ -306,6 +310,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (general && !csr_input(g)) { *why = 10; return false; }
     if (general && o->format != STC_SPARSE) { *why = 11; return false; }
     if (general && (long long)g->L * MP >= (1ll << 31)) { *why = 12; return false; }
+    if (o->krylov_restart < 0 || o->krylov_restart > kMaxRestart) { *why = 13; return false; }
     Layout l;
     l.MP = MP;
     l.NB = general ? 1 : 2 * g->b + 1;   // any pattern: only the diagonal slot is dense
@@ -349,6 +354,14 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
         if (l.fp32) l.gen_v32 = take((size_t)l.gen_slots * 4);
         l.gen_idx = take((size_t)l.gen_slots * 4);
     }
+    if (o->krylov_restart > 0) {
+        l.kr = o->krylov_restart;
+        l.kvec = take((size_t)(l.kr + 3) * vec * 8);
+        l.kst = take(sizeof(DevState));
+        l.kpart = take(2 * l.nparts * 8);
+        l.kdot = take((size_t)kDotGroups * (l.kr + 2) * 8);
+        l.kh = take((size_t)(4 * (l.kr + 2) + 16) * 8);
+    }
     l.off = take((L + 1) * 8);
     l.sizes = take(L * 4);
     l.state = take(sizeof(DevState));
@@ -391,6 +404,11 @@ struct stc_handle {
     float *gen_v32 = nullptr;
     int *gen_idx = nullptr;
     std::vector<GenEntry> gen_host;   // the table, for the byte counts
+    // Krylov workspace (stc_solve_gmres)
+    int kr = 0;
+    double *kX = nullptr, *kW = nullptr, *kV = nullptr, *kpart = nullptr, *kdot = nullptr,
+           *kh = nullptr;
+    DevState *kst = nullptr;
     double gen_vin[2] = {0.0, 0.0};   // distinct source values read by phase A / B
     unsigned *flow_flags = nullptr;   // progress flags of a persistent burst
     int flow_res[2][4] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}};   // resident blocks, cached
@@ -660,6 +678,50 @@ hipError_t enqueue_residual(stc_handle *h, bool f32, const void *w, long long sl
                                    h->gen_idx, w, h->L, h->st, slot, h->part_aux, h->stream);
     return launch_residual(f32 ? 4 : 8, h->MP, h->b, h->blk64, h->diag64, w, h->L, h->st, slot,
                            h->part_aux, h->stream);
+}
+
+// T v = M^{-1} N v in FP64 (the stair splitting's iteration operator, without
+// normalisation): phase A then phase B of the sweep kernels on the Krylov
+// apply-state, whose scales are all 1, from v into out.  v and out are
+// padded [L][MP] with zero padding; the sweeps' partial sums go to scratch.
+hipError_t enqueue_apply(stc_handle *h, const double *v, double *out) {
+    const int var = h->variant[0] & 3;   // the per-phase form of the FP64 variant
+    const int vv = h->sparse ? kEllGeometry : var;
+    const int pA = (h->stair_type == 1) ? 0 : 1;
+    const int gA = phase_groups(8, h->MP, h->L, pA, vv);
+    const int gB = phase_groups(8, h->MP, h->L, 1 - pA, vv);
+    SweepLaunch a;
+    a.blk = h->blk64;
+    a.w_old = v;
+    a.w_d1 = v;
+    a.w_d2 = v;
+    a.w_new = out;
+    a.part_sum = h->kpart;
+    a.part_diff = h->kpart + h->lay.nparts;
+    a.st = h->kst;
+    a.L = h->L;
+    a.s = 2;   // scale slot 0 (= 1); no change term (sweep numbers >= 3 only)
+    a.tol = 0.0;
+    a.nslots = gA + gB;
+    a.fold = 0;
+    a.prev_nslots = gA + gB;
+    a.prev_sum = a.part_sum;
+    a.prev_diff = a.part_diff;
+    hipError_t e = hipSuccess;
+    for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
+        a.parity = ph == 0 ? pA : 1 - pA;
+        a.slot0 = ph == 0 ? 0 : gA;
+        const bool phb = ph == 1;
+        if (h->general)
+            e = launch_sweep_phase_gen(8, h->MP, phb, (h->variant[0] & 2) != 0, a, h->gen_tab,
+                                       h->gen_v64, h->gen_idx, h->stream);
+        else if (h->sparse)
+            e = launch_sweep_phase_ell(8, h->MP, h->b, phb, a, h->ell_tab, h->ell_v64, h->ell_idx,
+                                       h->stream);
+        else
+            e = launch_sweep_phase(8, h->MP, h->b, phb, var, a, h->stream);
+    }
+    return e;
 }
 
 stc_status residual_of(stc_handle *h, bool f32, long long s, double *out) {
@@ -941,8 +1003,9 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                                     "a level size is outside 1..m",
                                     "a generator of any pattern (STC_ANY_PATTERN) comes as CSR input",
                                     "a generator of any pattern (STC_ANY_PATTERN) needs STC_SPARSE storage",
-                                    "L * padded m must stay below 2^31"};
-        return fail(STC_EINVAL, "%s", msg[why < 13 ? why : 0]);
+                                    "L * padded m must stay below 2^31",
+                                    "krylov_restart must be in 0..256"};
+        return fail(STC_EINVAL, "%s", msg[why < 14 ? why : 0]);
     }
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
     if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
@@ -986,6 +1049,17 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess &&
             khz > 0)
             h->wall_hz = (long long)khz * 1000;
+    }
+    if (lay.kr > 0) {
+        const size_t vec = (size_t)L * MP;
+        h->kr = lay.kr;
+        h->kX = (double *)(h->base + lay.kvec);
+        h->kW = h->kX + vec;
+        h->kV = h->kW + vec;
+        h->kst = (DevState *)(h->base + lay.kst);
+        h->kpart = (double *)(h->base + lay.kpart);
+        h->kdot = (double *)(h->base + lay.kdot);
+        h->kh = (double *)(h->base + lay.kh);
     }
     h->sparse = lay.sparse;
     if (lay.sparse) {
@@ -1175,6 +1249,8 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     if ((rc = dev(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream), "clear state")) != STC_OK)
         return cleanup(rc);
     if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return cleanup(rc);
+    if (h->kr > 0 && (rc = dev(launch_kstate_init(h->kst, h->stream), "Krylov state")) != STC_OK)
+        return cleanup(rc);
     if ((rc = dev(launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
                                 h->stream),
                   "invert")) != STC_OK)
@@ -1578,6 +1654,190 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
         res->diff_1 = diff;
         res->iters = final_k;
         res->iters_fp32 = mixed ? h->iters32 : (h->precision == STC_FP32 ? final_k : 0);
+        res->status = out;
+    }
+    return out;
+}
+
+stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, double tol,
+                           int64_t max_applies, double *pi, stc_result *res, int32_t where) {
+    if (!h || !pi) return fail(STC_EINVAL, "null argument");
+    if (h->kr < 1) return fail(STC_EINVAL, "the handle has no Krylov workspace (krylov_restart = 0)");
+    if (restart < 1 || restart > h->kr)
+        return fail(STC_EINVAL, "restart must be in 1..%d (krylov_restart)", h->kr);
+    if (max_applies < 2 || !(tol >= 0.0)) return fail(STC_EINVAL, "need max_applies >= 2 and tol >= 0");
+    const size_t n = (size_t)h->L * h->MP;
+    const int G = kDotGroups;
+    const int r = restart;
+    double *X = h->kX, *W = h->kW, *V = h->kV;
+    double *h1 = h->kh, *h2 = h->kh + (r + 2), *scal = h->kh + 2 * (r + 2),
+           *ydev = h->kh + 2 * (r + 2) + 8;
+    hipStream_t st = h->stream;
+    // x = x0 / e^T x0 (checked like any start vector), in the Krylov x buffer
+    stc_status rc = load_vector_stage(h, x0, where, false);
+    if (rc != STC_OK) return rc;
+    HIP_TRY(launch_kscale((const double *)wbuf(h, false, 0), &h->st->x_sum, X, n, st));
+    auto residual = [&](double *out) -> stc_status {
+        HIP_TRY(enqueue_residual(h, false, X, -1));
+        HostState hs;
+        stc_status r2 = read_state(h, &hs);
+        if (r2 == STC_OK) *out = hs.residual;
+        return r2;
+    };
+    auto fetch = [&](const double *src, double *dst, size_t count) -> stc_status {
+        HIP_TRY(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return STC_OK;
+    };
+    double res1;
+    if ((rc = residual(&res1)) != STC_OK) return rc;
+    long long applies = 0;
+    double diff = INFINITY;
+    bool converged = res1 <= tol;
+    std::vector<double> R((size_t)r * r), cs(r), sn(r), g(r + 1), hv(2 * (r + 2) + 8), y(r);
+    // safeguard: a cycle is kept only if it lowers ||Q^T x||_1 per
+    // application of T by at least the square of the factor of the last
+    // block of plain steps (before any: by half over the cycle); otherwise x
+    // stays and k plain applications of T follow (k = restart at first,
+    // doubled after every rejected cycle)
+    constexpr int kNormEvery = 16;
+    long long k_plain = r;
+    double plain_rate = -1.0;   // none measured yet
+    while (!converged && applies + 2 <= max_applies) {
+        const int rr = (int)std::min<long long>(r, max_applies - applies - 1);
+        // v_0 = (T x - x) / beta
+        HIP_TRY(enqueue_apply(h, X, W));
+        ++applies;
+        HIP_TRY(launch_kaxpby(1.0, W, -1.0, X, V, n, st));
+        HIP_TRY(launch_kdots(V, n, 1, V, n, h->kdot, G, scal, true, st));
+        double beta;
+        if ((rc = fetch(scal, &beta, 1)) != STC_OK) return rc;
+        if (!(beta > 0.0) || !std::isfinite(beta)) {
+            if (beta == 0.0) converged = true;   // x is already a null vector of T - I
+            break;
+        }
+        HIP_TRY(launch_kscale(V, scal, V, n, st));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int used = 0;
+        for (int j = 0; j < rr; ++j) {
+            double *vj = V + (size_t)j * n;
+            // w = v_j - T v_j = B v_j, orthogonalised against v_0 .. v_j twice
+            HIP_TRY(enqueue_apply(h, vj, W));
+            ++applies;
+            HIP_TRY(launch_kaxpby(1.0, vj, -1.0, W, W, n, st));
+            HIP_TRY(launch_kdots(V, n, j + 1, W, n, h->kdot, G, h1, false, st));
+            HIP_TRY(launch_kupdate(V, n, j + 1, h1, -1.0, W, n, st));
+            HIP_TRY(launch_kdots(V, n, j + 1, W, n, h->kdot, G, h2, false, st));
+            HIP_TRY(launch_kupdate(V, n, j + 1, h2, -1.0, W, n, st));
+            HIP_TRY(launch_kdots(W, n, 1, W, n, h->kdot, G, scal, true, st));
+            if ((rc = fetch(h->kh, hv.data(), 2 * (r + 2) + 1)) != STC_OK) return rc;
+            // column j of the Hessenberg matrix, then the earlier rotations
+            std::vector<double> c(j + 2);
+            for (int i = 0; i <= j; ++i) c[i] = hv[i] + hv[(r + 2) + i];
+            c[j + 1] = hv[2 * (r + 2)];
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * c[i] + sn[i] * c[i + 1];
+                c[i + 1] = -sn[i] * c[i] + cs[i] * c[i + 1];
+                c[i] = t;
+            }
+            const double nr = std::hypot(c[j], c[j + 1]);
+            cs[j] = nr > 0.0 ? c[j] / nr : 1.0;
+            sn[j] = nr > 0.0 ? c[j + 1] / nr : 0.0;
+            c[j] = nr;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            for (int i = 0; i <= j; ++i) R[(size_t)i * r + j] = c[i];
+            used = j + 1;
+            const double hn = hv[2 * (r + 2)];
+            // stop the cycle at a breakdown (the Krylov space holds the
+            // solution) or once the estimate reaches the rounding floor
+            if (!(hn > 1e-300) || nr == 0.0 || std::fabs(g[j + 1]) <= 1e-15 * beta) break;
+            HIP_TRY(launch_kscale(W, scal, V + (size_t)(j + 1) * n, n, st));
+        }
+        // R y = g (upper triangular), then x += V y, normalised
+        for (int i = used - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < used; ++k) t -= R[(size_t)i * r + k] * y[k];
+            y[i] = R[(size_t)i * r + i] != 0.0 ? t / R[(size_t)i * r + i] : 0.0;
+        }
+        HIP_TRY(hipMemcpyAsync(ydev, y.data(), sizeof(double) * used, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_kaxpby(1.0, X, 0.0, X, W, n, st));   // the previous x
+        HIP_TRY(launch_kupdate(V, n, used, ydev, 1.0, X, n, st));
+        HIP_TRY(launch_kdots(X, n, 1, nullptr, n, h->kdot, G, scal + 1, false, st));
+        double sum;
+        if ((rc = fetch(scal + 1, &sum, 1)) != STC_OK) return rc;
+        if (!(sum > 0.0) || !std::isfinite(sum)) {
+            rc = fail(STC_EDEGENERATE, "e^T x = %g after a GMRES cycle", sum);
+            if (res) {
+                res->iters = applies;
+                res->status = rc;
+            }
+            return rc;
+        }
+        HIP_TRY(launch_kscale(X, scal + 1, X, n, st));
+        double res_new;
+        if ((rc = residual(&res_new)) != STC_OK) return rc;
+        const int cyc_applies = used + 1;
+        const double need = plain_rate < 0.0 ? std::pow(0.5, 1.0 / cyc_applies)
+                                             : plain_rate * plain_rate;
+        if (res_new < res1 && std::pow(res_new / res1, 1.0 / cyc_applies) <= need) {
+            HIP_TRY(launch_kdots(X, n, 1, W, n, h->kdot, G, scal + 2, false, st, true));
+            if ((rc = fetch(scal + 2, &diff, 1)) != STC_OK) return rc;
+            res1 = res_new;
+        } else {
+            // keep the previous x and take plain steps x <- T x from it
+            HIP_TRY(launch_kaxpby(1.0, W, 0.0, W, X, n, st));
+            const long long steps = std::min<long long>(k_plain, max_applies - applies);
+            if (steps > 0) {
+                HIP_TRY(launch_kaxpby(1.0, X, 0.0, X, V, n, st));   // for the change
+                double *src = X, *dstv = W;
+                for (long long t = 0; t < steps; ++t) {
+                    HIP_TRY(enqueue_apply(h, src, dstv));
+                    ++applies;
+                    std::swap(src, dstv);
+                    if ((t + 1) % kNormEvery == 0) {
+                        HIP_TRY(launch_kdots(src, n, 1, nullptr, n, h->kdot, G, scal + 3, false, st));
+                        HIP_TRY(launch_kscale(src, scal + 3, src, n, st));
+                    }
+                }
+                if (src != X) HIP_TRY(launch_kaxpby(1.0, src, 0.0, src, X, n, st));
+                HIP_TRY(launch_kdots(X, n, 1, nullptr, n, h->kdot, G, scal + 1, false, st));
+                if ((rc = fetch(scal + 1, &sum, 1)) != STC_OK) return rc;
+                if (!(sum > 0.0) || !std::isfinite(sum)) {
+                    rc = fail(STC_EDEGENERATE, "e^T x = %g after plain steps", sum);
+                    if (res) {
+                        res->iters = applies;
+                        res->status = rc;
+                    }
+                    return rc;
+                }
+                HIP_TRY(launch_kscale(X, scal + 1, X, n, st));
+                HIP_TRY(launch_kdots(X, n, 1, V, n, h->kdot, G, scal + 2, false, st, true));
+                if ((rc = fetch(scal + 2, &diff, 1)) != STC_OK) return rc;
+                double res_plain;
+                if ((rc = residual(&res_plain)) != STC_OK) return rc;
+                plain_rate = res1 > 0.0 ? std::pow(res_plain / res1, 1.0 / (double)steps) : 1.0;
+                res1 = res_plain;
+            }
+            k_plain = std::min<long long>(2 * k_plain, max_applies);
+        }
+        converged = res1 <= tol;
+    }
+    // pi = x (the apply-state's scales are 1)
+    double *dst = (where == STC_MEM_DEVICE) ? pi : h->io;
+    HIP_TRY(launch_store(8, h->MP, X, h->off, h->sizes_d, h->L, h->kst, 0, dst, st));
+    if (where == STC_MEM_HOST)
+        HIP_TRY(hipMemcpyAsync(pi, h->io, sizeof(double) * h->N, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const stc_status out = converged ? STC_OK : fail(STC_EMAXIT, "max_applies = %lld reached, "
+                                                     "residual %g above tol", (long long)max_applies,
+                                                     res1);
+    if (res) {
+        res->residual_1 = res1;
+        res->diff_1 = diff;
+        res->iters = applies;
+        res->iters_fp32 = 0;
         res->status = out;
     }
     return out;

@@ -31,7 +31,8 @@ PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
 STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
 
 # every symbol include/stc.h declares
-EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_step", "stc_residual",
+EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_solve_gmres", "stc_step",
+           "stc_residual",
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
            "stc_store", "stc_promote", "stc_batch_footprint", "stc_batch_create",
@@ -50,7 +51,8 @@ class stc_generator(ctypes.Structure):
 class stc_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("stair_type", c_int32), ("stop", c_int32),
                 ("check_every", c_int32), ("switch_tol", c_double), ("stream", c_void_p),
-                ("arena", c_void_p), ("arena_bytes", c_size_t), ("format", c_int32)]
+                ("arena", c_void_p), ("arena_bytes", c_size_t), ("format", c_int32),
+                ("krylov_restart", c_int32)]
 
 
 class stc_result(ctypes.Structure):
@@ -85,6 +87,8 @@ def load_library(path: str = LIB_PATH):
     lib.stc_setup.argtypes = [POINTER(stc_generator), POINTER(stc_options), POINTER(H)]
     lib.stc_solve.argtypes = [H, c_void_p, c_double, c_int64, c_void_p, POINTER(stc_result),
                               c_int32]
+    lib.stc_solve_gmres.argtypes = [H, c_void_p, c_int32, c_double, c_int64, c_void_p,
+                                    POINTER(stc_result), c_int32]
     lib.stc_step.argtypes = [H, c_void_p, c_void_p, dp, c_int32]
     lib.stc_residual.argtypes = [H, c_void_p, dp, c_int32]
     lib.stc_sweeps.argtypes = [H, c_int64, c_void_p]
@@ -172,11 +176,12 @@ FORMATS = {"dense": STC_DENSE, "sparse": STC_SPARSE}
 
 
 def make_options(precision="fp64", stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
-                 stream=0, arena=0, arena_bytes=0, format="dense"):
+                 stream=0, arena=0, arena_bytes=0, format="dense", krylov_restart=0):
     return stc_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                        int(stair_type), STOPS[stop] if isinstance(stop, str) else int(stop),
                        int(check_every), float(switch_tol), stream or None, arena or None,
-                       int(arena_bytes), FORMATS[format] if isinstance(format, str) else int(format))
+                       int(arena_bytes), FORMATS[format] if isinstance(format, str) else int(format),
+                       int(krylov_restart))
 
 
 def stc_footprint_bytes(gen: stc_generator, opt: stc_options) -> int:
@@ -210,6 +215,19 @@ def stc_solve(h, x0, tol: float, maxit: int, pi, allow_maxit: bool = True) -> di
     res = stc_result()
     allow = (STC_OK, STC_EMAXIT) if allow_maxit else (STC_OK,)
     _check(load_library().stc_solve(h, px, float(tol), int(maxit), pp, byref(res), w2), allow)
+    return res.as_dict()
+
+
+def stc_solve_gmres(h, x0, restart: int, tol: float, max_applies: int, pi,
+                    allow_maxit: bool = True) -> dict:
+    px, w1 = _vec_arg(x0)
+    pp, w2 = _vec_arg(pi)
+    if x0 is not None and w1 != w2:
+        raise ValueError("x0 and pi must both be host or both be device memory")
+    res = stc_result()
+    allow = (STC_OK, STC_EMAXIT) if allow_maxit else (STC_OK,)
+    _check(load_library().stc_solve_gmres(h, px, int(restart), float(tol), int(max_applies), pp,
+                                          byref(res), w2), allow)
     return res.as_dict()
 
 
@@ -391,7 +409,7 @@ class Solver:
     def __init__(self, blocks: np.ndarray | None, sizes, b: int, *, precision="fp64",
                  stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
                  recompute_diagonal=False, device=None, stream=None, poison=False,
-                 format="dense", csr=None, m=None):
+                 format="dense", csr=None, m=None, krylov_restart=0):
         """blocks: [L][2b+1][m][m] dense blocks, or None with csr = (indptr,
         indices, data) of the N x N generator (sizes then required; m
         defaults to the largest size).  poison: fill the arena with 0xFF
@@ -411,7 +429,8 @@ class Solver:
         else:
             self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
         self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
-                                stream=self.stream.cuda_stream, format=format)
+                                stream=self.stream.cuda_stream, format=format,
+                                krylov_restart=krylov_restart)
         need = stc_footprint_bytes(self.gen, self.opt)
         if need == 0:
             raise StcError(STC_EINVAL, "unsupported generator shape or options")
@@ -438,6 +457,15 @@ class Solver:
         pi = np.empty(self.N)
         x = None if x0 is None else _f64(x0)
         info = stc_solve(self.h, x, tol, maxit, pi, allow_maxit)
+        return pi, info
+
+    def solve_gmres(self, x0=None, tol=1e-12, restart=30, max_applies=100_000,
+                    allow_maxit=True):
+        """Staircase-preconditioned restarted GMRES to ||Q^T pi||_1 <= tol
+        (needs krylov_restart >= restart at construction)."""
+        pi = np.empty(self.N)
+        x = None if x0 is None else _f64(x0)
+        info = stc_solve_gmres(self.h, x, restart, tol, max_applies, pi, allow_maxit)
         return pi, info
 
     def step(self, x):

@@ -317,3 +317,15 @@ def test_any_pattern_csr_rejections(lib):
     ip2[4] = ip2[3] - 1
     gen = stc.make_generator_csr(ip2, ix, v, g.sizes, stc.STC_ANY_PATTERN)[0]
     assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
+
+
+def test_krylov_workspace_footprint(lib):
+    g = synth.qbd(16, 16, 4)
+    gen, _k = stc.make_generator(g.blocks, g.sizes, 1)
+    base = stc.stc_footprint_bytes(gen, stc.make_options())
+    f10 = stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=10))
+    f20 = stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=20))
+    vec = 16 * 16 * 8
+    assert f10 - base >= 13 * vec and f20 - f10 >= 10 * vec
+    assert stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=257)) == 0
+    assert stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=-1)) == 0

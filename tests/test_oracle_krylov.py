@@ -82,3 +82,32 @@ def test_sign_slip_in_the_first_residual_is_caught(monkeypatch):
     monkeypatch.setattr(krylov, "stair_apply", real)
     good, _, _ = krylov.gmres_cycle(sys, np.full(g.N, 1.0 / g.N), 20)
     assert np.abs(good - pi).sum() < 0.1 * np.abs(x - pi).sum()
+
+
+def test_safeguard_keeps_drifting_chains_at_the_stationary_pace():
+    """On a QBD with drift, short GMRES cycles stall; the safeguard falls back
+    to plain applications of T, so the solve still converges to the direct
+    solution in about as many applications as the stationary iteration."""
+    g = synth.qbd(256, 16, 11)
+    sys = staircase.BlockSystem(g.blocks, g.sizes, g.b)
+    stat = staircase.solve_system(sys, tol=1e-12, maxit=100_000, stop=staircase.STOP_RESIDUAL)
+    r = krylov.gmres_solve(sys, restart=30, tol=1e-12, maxit=20_000)
+    assert r.converged
+    assert r.applies <= 1.5 * stat.iters
+    pi = dense_pi(g)
+    assert np.abs(r.x - pi).sum() < 1e-10
+
+
+def dense_pi(g):
+    from oracle import level_reduction
+    return level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+
+
+def test_safeguard_keeps_gmres_where_it_helps():
+    """On a chain without drift GMRES cycles beat the plain rate and are all
+    kept: far fewer applications than stationary sweeps."""
+    g = _banded()
+    sys = staircase.BlockSystem(g.blocks, g.sizes, g.b)
+    stat = staircase.solve_system(sys, tol=1e-12, maxit=200_000, stop=staircase.STOP_RESIDUAL)
+    r = krylov.gmres_solve(sys, restart=30, tol=1e-12, maxit=20_000)
+    assert r.converged and r.applies * 5 < stat.iters
