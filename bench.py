@@ -37,6 +37,9 @@ Other workloads (each prints its own JSON line instead):
                   Hessenberg form (16 blocks of 64), partitions of 16, 32 and
                   64 states: the contraction the GPU sweeps show, sweeps and
                   time to a change of 1e-12
+  --krylov        staircase-preconditioned GMRES(60) against stationary sweeps,
+                  both to ||Q^T pi||_1 <= 1e-12, on the 4096 x 64 QBD, the
+                  2048 x 128 banded generator and the mutual-exclusion model
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -166,6 +169,7 @@ def main():
     ap.add_argument("--skipfree", action="store_true")
     ap.add_argument("--mutex", action="store_true")
     ap.add_argument("--example3", type=int, default=0)
+    ap.add_argument("--krylov", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
@@ -191,6 +195,8 @@ def main():
         return mutex_mode(args)
     if args.example3:
         return example3_mode(args.example3)
+    if args.krylov:
+        return krylov_mode(args)
 
     import numpy as np
     import torch
@@ -598,6 +604,73 @@ def mutex_mode(args, n=16, r=12):
             "sweep_rates": rates, "solves": solves, "cpu_baseline": cpu,
             "device_copy_GBs_same_launch_bytes": round(copy, 1),
             "vs_device_copy": round(best["GB/s_algorithmic"] / copy, 4)}
+    print(json.dumps(line), flush=True)
+
+
+def krylov_mode(args, restart=60, tol=1e-12):
+    """Staircase-preconditioned GMRES(restart) against the stationary sweeps
+    of Algorithm 2, both to ||Q^T pi||_1 <= 1e-12 in FP64, on three chains:
+    the 4096 x 64 QBD (strong drift), the 2048 x 128 banded generator
+    (symmetric rates, slow mixing; sparse storage) and the mutual-exclusion
+    model (any block pattern).  The stationary solve of the banded chain
+    gets a budget of 200000 sweeps and reports the residual it reached."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    chains = {
+        "qbd_L4096_m64": (lambda: synth.qbd(4096, 64, synth.config_seed(1)), "dense", 400_000),
+        "banded_b2_L2048_m128": (lambda: synth.banded(2048, 128, synth.config_seed(2), b=2,
+                                                      density=0.1, decay=0.5),
+                                 "sparse", 200_000),
+        "mutex_n16_r12": (lambda: synth.mutual_exclusion(16, 12, synth.config_seed(3)), "any",
+                          400_000),
+    }
+    out = {}
+    for name, (make, fmt, budget) in chains.items():
+        gen = make()
+        exact = synth.mutual_exclusion_pi(gen) if fmt == "any" else None
+
+        def solver(**kw):
+            if fmt == "any":
+                return Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                              **kw)
+            return Solver(gen.blocks, gen.sizes, gen.b, format=fmt, **kw)
+        row = {}
+        s = solver(krylov_restart=restart)
+        s.solve_gmres(tol=tol, restart=restart, max_applies=2 * restart)   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pi, info = s.solve_gmres(tol=tol, restart=restart, max_applies=400_000)
+        row["gmres"] = {"seconds": round(time.perf_counter() - t0, 4), "applies": info["iters"],
+                        "residual": info["residual_1"], "status": info["status"]}
+        if exact is not None:
+            row["gmres"]["err_vs_closed_form"] = float(np.abs(pi - exact).sum())
+        s.close()
+        print(f"# {name} gmres({restart}): {row['gmres']}", file=sys.stderr, flush=True)
+        if not args.no_ttr:
+            s = solver(stop="residual", check_every=200)
+            stc.stc_autotune(s.h, 5)
+            s.solve(tol=tol, maxit=50)   # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pi, info = s.solve(tol=tol, maxit=budget)
+            row["stationary"] = {"seconds": round(time.perf_counter() - t0, 4),
+                                 "sweeps": info["iters"], "residual": info["residual_1"],
+                                 "converged": info["status"] == 0}
+            if exact is not None:
+                row["stationary"]["err_vs_closed_form"] = float(np.abs(pi - exact).sum())
+            s.close()
+            print(f"# {name} stationary: {row['stationary']}", file=sys.stderr, flush=True)
+        out[name] = row
+    line = {"metric": "time to ||Q^T pi||_1 <= 1e-12: staircase-preconditioned GMRES vs "
+                      "stationary sweeps",
+            "value": out["banded_b2_L2048_m128"]["gmres"]["seconds"], "unit": "s",
+            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "banded_b2_L2048_m128 (value), qbd_L4096_m64, mutex_n16_r12",
+                       "restart": restart, "tol": tol},
+            "chains": out}
     print(json.dumps(line), flush=True)
 
 
