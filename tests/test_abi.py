@@ -329,3 +329,21 @@ def test_krylov_workspace_footprint(lib):
     assert f10 - base >= 13 * vec and f20 - f10 >= 10 * vec
     assert stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=257)) == 0
     assert stc.stc_footprint_bytes(gen, stc.make_options(krylov_restart=-1)) == 0
+
+
+def test_any_pattern_size_limit_rejected_before_any_scan(lib):
+    """L * padded m must stay below 2^31 (32-bit gather indices): 2^24 levels
+    of one state padded to 128 is refused by the footprint and by setup,
+    before the entries are read."""
+    L = 1 << 24
+    sizes = np.ones(L, dtype=np.int32)
+    indptr = np.zeros(L + 1, dtype=np.int64)
+    empty_i = np.zeros(0, dtype=np.int32)
+    empty_v = np.zeros(0)
+    gen, _k = stc.make_generator_csr(indptr, empty_i, empty_v, sizes, stc.STC_ANY_PATTERN, m=128)
+    assert stc.stc_footprint_bytes(gen, stc.make_options(format="sparse")) == 0
+    opt = stc.make_options(format="sparse")
+    opt.arena, opt.arena_bytes = 4096, 1 << 40
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup(gen, opt)
+    assert e.value.status == stc.STC_EINVAL and "2^31" in str(e.value)

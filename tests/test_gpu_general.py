@@ -240,3 +240,27 @@ def test_load_policies_agree_and_default_by_size():
     s.sweeps(3)
     assert np.array_equal(z_nt, s.store())
     s.close()
+
+
+def test_any_pattern_singular_diagonal_block():
+    """A level whose states can never leave it makes Q_ii singular: setup
+    reports STC_ESINGULAR (the inverse kernel's pivot check)."""
+    from paper_2302_07551_amd import stc
+    g = synth.localized(6, 8, 21, up=1, down=1, jumps=0, backbone=0.0)
+    Q = g.to_scipy().tolil()
+    off = g.offsets
+    lev = 3
+    for r in range(off[lev], off[lev + 1]):
+        for c in list(Q.rows[r]):
+            if not (off[lev] <= c < off[lev + 1]):
+                Q[r, c] = 0.0
+    Q = Q.tocsr()
+    Q.setdiag(0.0)
+    Q.setdiag(-np.asarray(Q.sum(axis=1)).ravel())
+    Q.eliminate_zeros()
+    Q.sort_indices()
+    with pytest.raises(stc.StcError) as e:
+        from paper_2302_07551_amd import Solver
+        Solver(None, g.sizes, stc.STC_ANY_PATTERN, csr=(Q.indptr, Q.indices, Q.data),
+               format="sparse")
+    assert e.value.status == stc.STC_ESINGULAR

@@ -151,3 +151,17 @@ def test_safeguard_on_a_drifting_qbd():
     assert np.abs(pi - _direct(g, "dense")).sum() <= 1e-10
     s.close()
     s2.close()
+
+
+def test_gmres_device_vectors_match_host():
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(24, 16, 31, last=5)
+    s = _solver(g, "dense", krylov_restart=20)
+    x0 = np.random.default_rng(2).uniform(0.5, 1.5, g.N)
+    p_host, i_host = s.solve_gmres(x0, tol=1e-13, restart=20)
+    xd = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    pd = torch.empty(g.N, dtype=torch.float64, device="cuda")
+    info = stc.stc_solve_gmres(s.h, xd, 20, 1e-13, 100_000, pd)
+    assert info["iters"] == i_host["iters"]
+    assert np.array_equal(pd.cpu().numpy(), p_host)
+    s.close()
