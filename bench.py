@@ -40,6 +40,8 @@ Other workloads (each prints its own JSON line instead):
   --krylov        staircase-preconditioned GMRES(60) against stationary sweeps,
                   both to ||Q^T pi||_1 <= 1e-12, on the 4096 x 64 QBD, the
                   2048 x 128 banded generator and the mutual-exclusion model
+  --launch-sizes  the dense sweep kernel's phase-A rate on QBDs with about 41 MB
+                  and 200 MB per launch, at block sizes 128 and 64
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -170,6 +172,7 @@ def main():
     ap.add_argument("--mutex", action="store_true")
     ap.add_argument("--example3", type=int, default=0)
     ap.add_argument("--krylov", action="store_true")
+    ap.add_argument("--launch-sizes", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
@@ -197,6 +200,8 @@ def main():
         return example3_mode(args.example3)
     if args.krylov:
         return krylov_mode(args)
+    if args.launch_sizes:
+        return launch_sizes_mode()
 
     import numpy as np
     import torch
@@ -672,6 +677,37 @@ def krylov_mode(args, restart=60, tol=1e-12):
                        "restart": restart, "tol": tol},
             "chains": out}
     print(json.dumps(line), flush=True)
+
+
+def launch_sizes_mode():
+    """The dense sweep kernel's phase-A rate against the size and shape of
+    its launch: QBDs with about 41 MB and about 200 MB per phase launch, at
+    block sizes 128 (one level per workgroup) and 64 (autotuned variants)."""
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    rows = {}
+    for L, m in ((208, 128), (832, 64), (1024, 128), (4096, 64)):
+        g = synth.qbd(L, m, 5)
+        s = Solver(g.blocks, g.sizes, g.b)
+        stc.stc_autotune(s.h, 10)
+        s.load(None)
+        s.sweeps(20)
+        ms_a, _mb, _mf, _ms = stc.stc_profile_sweeps(s.h, 200)
+        ba, _bb = stc.stc_phase_bytes(s.h)
+        gbs = ba / (ms_a * 1e-3) / 1e9
+        rows[f"qbd_L{L}_m{m}"] = {"MB_per_launch": round(ba / 1e6, 1),
+                                  "us_per_launch": round(ms_a * 1e3, 2),
+                                  "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "variant": stc.stc_get_variant(s.h, stc.STC_FP64)}
+        print(f"# qbd L{L} m{m}: {rows[f'qbd_L{L}_m{m}']}", file=sys.stderr, flush=True)
+        s.close()
+    print(json.dumps({"metric": "phase-A GB/s of the dense sweep kernel by launch size",
+                      "unit": "GB/s", "value": rows["qbd_L208_m128"]["GB/s"],
+                      "higher_is_better": True, "n_gpus": 1, "dtype": "f64",
+                      "data": "synthetic", "config": {"workload": "qbd launch-size series"},
+                      "launches": rows}), flush=True)
 
 
 def observed_contraction(d, lo=1e-13, hi=1e-6):
