@@ -360,7 +360,9 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
         l.kst = take(sizeof(DevState));
         l.kpart = take(2 * l.nparts * 8);
         l.kdot = take((size_t)kDotGroups * (l.kr + 2) * 8);
-        l.kh = take((size_t)(4 * (l.kr + 2) + 16) * 8);
+        // scalars, the cycle's y, and per step the norm and both Gram-Schmidt
+        // passes' coefficients for a whole cycle
+        l.kh = take((size_t)(2 * (size_t)l.kr * (l.kr + 2) + 2 * l.kr + 32) * 8);
     }
     l.off = take((L + 1) * 8);
     l.sizes = take(L * 4);
@@ -1670,8 +1672,11 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     const int G = kDotGroups;
     const int r = restart;
     double *X = h->kX, *W = h->kW, *V = h->kV;
-    double *h1 = h->kh, *h2 = h->kh + (r + 2), *scal = h->kh + 2 * (r + 2),
-           *ydev = h->kh + 2 * (r + 2) + 8;
+    // device scalars, y, then per step j: ||w_j|| and the coefficients of
+    // both passes (columns of r + 2), so a cycle needs no host round trip
+    // until its end
+    double *scal = h->kh, *ydev = h->kh + 8, *knorm = ydev + r, *H1 = knorm + r,
+           *H2 = H1 + (size_t)r * (r + 2);
     hipStream_t st = h->stream;
     // x = x0 / e^T x0 (checked like any start vector), in the Krylov x buffer
     stc_status rc = load_vector_stage(h, x0, where, false);
@@ -1694,7 +1699,8 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     long long applies = 0;
     double diff = INFINITY;
     bool converged = res1 <= tol;
-    std::vector<double> R((size_t)r * r), cs(r), sn(r), g(r + 1), hv(2 * (r + 2) + 8), y(r);
+    std::vector<double> R((size_t)r * r), cs(r), sn(r), g(r + 1), y(r);
+    std::vector<double> hv((size_t)r + 2 * (size_t)r * (r + 2));
     // safeguard: a cycle is kept only if it lowers ||Q^T x||_1 per
     // application of T by at least the square of the factor of the last
     // block of plain steps (before any: by half over the cycle); otherwise x
@@ -1719,9 +1725,10 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         HIP_TRY(launch_kscale(V, scal, V, n, st));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int used = 0;
+        // the Arnoldi steps of the cycle, enqueued without a host round trip
         for (int j = 0; j < rr; ++j) {
             double *vj = V + (size_t)j * n;
+            double *h1 = H1 + (size_t)j * (r + 2), *h2 = H2 + (size_t)j * (r + 2);
             // w = v_j - T v_j = B v_j, orthogonalised against v_0 .. v_j twice
             HIP_TRY(enqueue_apply(h, vj, W));
             ++applies;
@@ -1730,31 +1737,46 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
             HIP_TRY(launch_kupdate(V, n, j + 1, h1, -1.0, W, n, st));
             HIP_TRY(launch_kdots(V, n, j + 1, W, n, h->kdot, G, h2, false, st));
             HIP_TRY(launch_kupdate(V, n, j + 1, h2, -1.0, W, n, st));
-            HIP_TRY(launch_kdots(W, n, 1, W, n, h->kdot, G, scal, true, st));
-            if ((rc = fetch(h->kh, hv.data(), 2 * (r + 2) + 1)) != STC_OK) return rc;
-            // column j of the Hessenberg matrix, then the earlier rotations
+            HIP_TRY(launch_kdots(W, n, 1, W, n, h->kdot, G, knorm + j, true, st));
+            // v_{j+1} = w / ||w||; after a breakdown (||w|| = 0) this and the
+            // later vectors are not finite, and the least-squares step below
+            // stops before them
+            HIP_TRY(launch_kscale(W, knorm + j, V + (size_t)(j + 1) * n, n, st));
+        }
+        // the cycle's Hessenberg columns, rotated on the host
+        if ((rc = fetch(knorm, hv.data(), (size_t)r + (size_t)r * (r + 2) + (size_t)rr * (r + 2))) !=
+            STC_OK)
+            return rc;
+        const double *hn_h = hv.data(), *H1h = hv.data() + r, *H2h = H1h + (size_t)r * (r + 2);
+        int used = 0;
+        for (int j = 0; j < rr; ++j) {
             std::vector<double> c(j + 2);
-            for (int i = 0; i <= j; ++i) c[i] = hv[i] + hv[(r + 2) + i];
-            c[j + 1] = hv[2 * (r + 2)];
+            bool finite = std::isfinite(hn_h[j]);
+            for (int i = 0; i <= j; ++i) {
+                c[i] = H1h[(size_t)j * (r + 2) + i] + H2h[(size_t)j * (r + 2) + i];
+                finite = finite && std::isfinite(c[i]);
+            }
+            if (!finite) break;
+            c[j + 1] = hn_h[j];
             for (int i = 0; i < j; ++i) {
                 const double t = cs[i] * c[i] + sn[i] * c[i + 1];
                 c[i + 1] = -sn[i] * c[i] + cs[i] * c[i + 1];
                 c[i] = t;
             }
             const double nr = std::hypot(c[j], c[j + 1]);
-            cs[j] = nr > 0.0 ? c[j] / nr : 1.0;
-            sn[j] = nr > 0.0 ? c[j + 1] / nr : 0.0;
+            if (nr == 0.0) break;
+            cs[j] = c[j] / nr;
+            sn[j] = c[j + 1] / nr;
             c[j] = nr;
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             for (int i = 0; i <= j; ++i) R[(size_t)i * r + j] = c[i];
             used = j + 1;
-            const double hn = hv[2 * (r + 2)];
-            // stop the cycle at a breakdown (the Krylov space holds the
-            // solution) or once the estimate reaches the rounding floor
-            if (!(hn > 1e-300) || nr == 0.0 || std::fabs(g[j + 1]) <= 1e-15 * beta) break;
-            HIP_TRY(launch_kscale(W, scal, V + (size_t)(j + 1) * n, n, st));
+            // a breakdown (the Krylov space holds the solution), or the
+            // estimate at the rounding floor: the later columns add nothing
+            if (!(hn_h[j] > 1e-300) || std::fabs(g[j + 1]) <= 1e-15 * beta) break;
         }
+        if (used == 0) break;
         // R y = g (upper triangular), then x += V y, normalised
         for (int i = used - 1; i >= 0; --i) {
             double t = g[i];
@@ -1778,7 +1800,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         HIP_TRY(launch_kscale(X, scal + 1, X, n, st));
         double res_new;
         if ((rc = residual(&res_new)) != STC_OK) return rc;
-        const int cyc_applies = used + 1;
+        const int cyc_applies = rr + 1;   // every step of the cycle ran
         const double need = plain_rate < 0.0 ? std::pow(0.5, 1.0 / cyc_applies)
                                              : plain_rate * plain_rate;
         if (res_new < res1 && std::pow(res_new / res1, 1.0 / cyc_applies) <= need) {
