@@ -661,6 +661,21 @@ def krylov_mode(args, restart=60, tol=1e-12):
             row["cpu_direct_solve_s"] = round(t_ref, 2)
         s.close()
         print(f"# {name} gmres({restart}): {row['gmres']}", file=sys.stderr, flush=True)
+        # mixed: FP32 applications of M^{-1} N until the residual reaches 1e-8
+        # or an FP32 cycle stalls, then FP64
+        s = solver(krylov_restart=restart, precision="mixed", switch_tol=1e-8)
+        s.solve_gmres(tol=tol, restart=restart, max_applies=2 * restart)   # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pi, info = s.solve_gmres(tol=tol, restart=restart, max_applies=400_000)
+        row["gmres_mixed"] = {"seconds": round(time.perf_counter() - t0, 4),
+                              "applies": info["iters"], "applies_fp32": info["iters_fp32"],
+                              "residual": info["residual_1"], "status": info["status"]}
+        if exact is not None:
+            key = "err_vs_closed_form" if fmt == "any" else "err_vs_direct"
+            row["gmres_mixed"][key] = float(np.abs(pi - exact).sum())
+        s.close()
+        print(f"# {name} gmres({restart}) mixed: {row['gmres_mixed']}", file=sys.stderr, flush=True)
         if not args.no_ttr:
             s = solver(stop="residual", check_every=200)
             stc.stc_autotune(s.h, 5)

@@ -184,12 +184,18 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
  * the last block of plain steps achieved (before any plain block: by half
  * over the cycle); otherwise x stays and k plain normalised applications of
  * M^{-1} N follow, k = restart at first, doubled after each rejected cycle.
- * Always FP64.  x0 (NULL: e/N) is checked like stc_solve's;
+ * The Krylov vectors and the residual are always FP64.  An STC_FP64 handle
+ * applies M^{-1} N in FP64; STC_FP32 and STC_MIXED handles apply it in FP32
+ * (vectors rounded to FP32 for each application and widened back) until
+ * ||Q^T x||_1 <= switch_tol or an FP32 cycle stalls, then in FP64 to tol;
+ * res->iters_fp32 counts the FP32 applications.  x0 (NULL: e/N) is checked like stc_solve's;
  * pi receives the last normalised iterate.  res->iters counts the
  * applications, res->diff_1 the last cycle's change ||x_new - x||_1.
- * Needs restart in 1..opt.krylov_restart (STC_EINVAL otherwise).  Returns
- * STC_OK, STC_EMAXIT, STC_EDEGENERATE (e^T x <= 0 after a cycle),
- * STC_EINVAL, STC_EDEVICE. */
+ * A cycle's x is normalised by its sum whatever its sign; a zero or
+ * non-finite sum counts as a rejected cycle.  Needs restart in
+ * 1..opt.krylov_restart (STC_EINVAL otherwise).  Returns STC_OK,
+ * STC_EMAXIT, STC_EDEGENERATE (e^T x <= 0 after plain steps), STC_EINVAL,
+ * STC_EDEVICE. */
 stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, double tol,
                            int64_t max_applies, double *pi, stc_result *res, int32_t where);
 

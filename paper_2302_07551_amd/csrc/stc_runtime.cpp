@@ -682,22 +682,33 @@ hipError_t enqueue_residual(stc_handle *h, bool f32, const void *w, long long sl
                            h->part_aux, h->stream);
 }
 
-// T v = M^{-1} N v in FP64 (the stair splitting's iteration operator, without
+// T v = M^{-1} N v (the stair splitting's iteration operator, without
 // normalisation): phase A then phase B of the sweep kernels on the Krylov
-// apply-state, whose scales are all 1, from v into out.  v and out are
+// apply-state, whose scales are all 1, from v into out.  v and out are FP64,
 // padded [L][MP] with zero padding; the sweeps' partial sums go to scratch.
-hipError_t enqueue_apply(stc_handle *h, const double *v, double *out) {
-    const int var = h->variant[0] & 3;   // the per-phase form of the FP64 variant
+// f32: the sweeps run on the FP32 blocks, from v rounded to FP32 (in the
+// first FP32 iterate buffer) into the second, widened exactly into out.
+hipError_t enqueue_apply(stc_handle *h, const double *v, double *out, bool f32 = false) {
+    const int bytes = f32 ? 4 : 8;
+    const int var = h->variant[f32 ? 1 : 0] & 3;   // the per-phase form of the stage's variant
     const int vv = h->sparse ? kEllGeometry : var;
     const int pA = (h->stair_type == 1) ? 0 : 1;
-    const int gA = phase_groups(8, h->MP, h->L, pA, vv);
-    const int gB = phase_groups(8, h->MP, h->L, 1 - pA, vv);
+    const int gA = phase_groups(bytes, h->MP, h->L, pA, vv);
+    const int gB = phase_groups(bytes, h->MP, h->L, 1 - pA, vv);
+    const size_t n = (size_t)h->L * h->MP;
+    void *src = (void *)v, *dst = out;
+    if (f32) {
+        src = wbuf(h, true, 0);
+        dst = wbuf(h, true, 1);
+        hipError_t e = launch_cast_blocks(v, (float *)src, n, h->stream);
+        if (e != hipSuccess) return e;
+    }
     SweepLaunch a;
-    a.blk = h->blk64;
-    a.w_old = v;
-    a.w_d1 = v;
-    a.w_d2 = v;
-    a.w_new = out;
+    a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
+    a.w_old = src;
+    a.w_d1 = src;
+    a.w_d2 = src;
+    a.w_new = dst;
     a.part_sum = h->kpart;
     a.part_diff = h->kpart + h->lay.nparts;
     a.st = h->kst;
@@ -715,14 +726,17 @@ hipError_t enqueue_apply(stc_handle *h, const double *v, double *out) {
         a.slot0 = ph == 0 ? 0 : gA;
         const bool phb = ph == 1;
         if (h->general)
-            e = launch_sweep_phase_gen(8, h->MP, phb, (h->variant[0] & 2) != 0, a, h->gen_tab,
-                                       h->gen_v64, h->gen_idx, h->stream);
+            e = launch_sweep_phase_gen(bytes, h->MP, phb, (var & 2) != 0, a, h->gen_tab,
+                                       f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
+                                       h->gen_idx, h->stream);
         else if (h->sparse)
-            e = launch_sweep_phase_ell(8, h->MP, h->b, phb, a, h->ell_tab, h->ell_v64, h->ell_idx,
-                                       h->stream);
+            e = launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab,
+                                       f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64,
+                                       h->ell_idx, h->stream);
         else
-            e = launch_sweep_phase(8, h->MP, h->b, phb, var, a, h->stream);
+            e = launch_sweep_phase(bytes, h->MP, h->b, phb, var, a, h->stream);
     }
+    if (e == hipSuccess && f32) e = launch_widen((const float *)dst, out, n, h->stream);
     return e;
 }
 
@@ -1696,9 +1710,17 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     };
     double res1;
     if ((rc = residual(&res1)) != STC_OK) return rc;
-    long long applies = 0;
+    long long applies = 0, applies32 = 0;
     double diff = INFINITY;
     bool converged = res1 <= tol;
+    // FP32 and mixed handles apply M^{-1} N in FP32 first (the Krylov vectors
+    // stay FP64), until ||Q^T x||_1 <= switch_tol or an FP32 cycle stalls
+    bool f32 = h->precision != STC_FP64;
+    auto apply = [&](const double *v, double *o) -> hipError_t {
+        ++applies;
+        if (f32) ++applies32;
+        return enqueue_apply(h, v, o, f32);
+    };
     std::vector<double> R((size_t)r * r), cs(r), sn(r), g(r + 1), y(r);
     std::vector<double> hv((size_t)r + 2 * (size_t)r * (r + 2));
     // safeguard: a cycle is kept only if it lowers ||Q^T x||_1 per
@@ -1712,8 +1734,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     while (!converged && applies + 2 <= max_applies) {
         const int rr = (int)std::min<long long>(r, max_applies - applies - 1);
         // v_0 = (T x - x) / beta
-        HIP_TRY(enqueue_apply(h, X, W));
-        ++applies;
+        HIP_TRY(apply(X, W));
         HIP_TRY(launch_kaxpby(1.0, W, -1.0, X, V, n, st));
         HIP_TRY(launch_kdots(V, n, 1, V, n, h->kdot, G, scal, true, st));
         double beta;
@@ -1730,8 +1751,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
             double *vj = V + (size_t)j * n;
             double *h1 = H1 + (size_t)j * (r + 2), *h2 = H2 + (size_t)j * (r + 2);
             // w = v_j - T v_j = B v_j, orthogonalised against v_0 .. v_j twice
-            HIP_TRY(enqueue_apply(h, vj, W));
-            ++applies;
+            HIP_TRY(apply(vj, W));
             HIP_TRY(launch_kaxpby(1.0, vj, -1.0, W, W, n, st));
             HIP_TRY(launch_kdots(V, n, j + 1, W, n, h->kdot, G, h1, false, st));
             HIP_TRY(launch_kupdate(V, n, j + 1, h1, -1.0, W, n, st));
@@ -1789,21 +1809,33 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         HIP_TRY(launch_kdots(X, n, 1, nullptr, n, h->kdot, G, scal + 1, false, st));
         double sum;
         if ((rc = fetch(scal + 1, &sum, 1)) != STC_OK) return rc;
-        if (!(sum > 0.0) || !std::isfinite(sum)) {
-            rc = fail(STC_EDEGENERATE, "e^T x = %g after a GMRES cycle", sum);
-            if (res) {
-                res->iters = applies;
-                res->status = rc;
-            }
-            return rc;
+        // normalise by any finite non-zero sum (a step that flips the sign of
+        // the null-space component still gives the normalised vector); a
+        // zero or non-finite sum makes the cycle a rejected one
+        double res_new = INFINITY;
+        if (sum != 0.0 && std::isfinite(sum)) {
+            HIP_TRY(launch_kscale(X, scal + 1, X, n, st));
+            if ((rc = residual(&res_new)) != STC_OK) return rc;
+        } else {
+            HIP_TRY(launch_kaxpby(1.0, W, 0.0, W, X, n, st));
         }
-        HIP_TRY(launch_kscale(X, scal + 1, X, n, st));
-        double res_new;
-        if ((rc = residual(&res_new)) != STC_OK) return rc;
         const int cyc_applies = rr + 1;   // every step of the cycle ran
         const double need = plain_rate < 0.0 ? std::pow(0.5, 1.0 / cyc_applies)
                                              : plain_rate * plain_rate;
-        if (res_new < res1 && std::pow(res_new / res1, 1.0 / cyc_applies) <= need) {
+        const bool keep = std::isfinite(res_new) && res_new < res1 &&
+                          std::pow(res_new / res1, 1.0 / cyc_applies) <= need;
+        if (f32 && (!keep || res_new <= h->switch_tol)) {
+            // the FP32 stage ends: at its rounding floor, a stalled cycle is
+            // dropped; the FP64 cycles continue from the best x
+            f32 = false;
+            if (keep) {
+                HIP_TRY(launch_kdots(X, n, 1, W, n, h->kdot, G, scal + 2, false, st, true));
+                if ((rc = fetch(scal + 2, &diff, 1)) != STC_OK) return rc;
+                res1 = res_new;
+            } else {
+                HIP_TRY(launch_kaxpby(1.0, W, 0.0, W, X, n, st));
+            }
+        } else if (keep) {
             HIP_TRY(launch_kdots(X, n, 1, W, n, h->kdot, G, scal + 2, false, st, true));
             if ((rc = fetch(scal + 2, &diff, 1)) != STC_OK) return rc;
             res1 = res_new;
@@ -1815,8 +1847,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
                 HIP_TRY(launch_kaxpby(1.0, X, 0.0, X, V, n, st));   // for the change
                 double *src = X, *dstv = W;
                 for (long long t = 0; t < steps; ++t) {
-                    HIP_TRY(enqueue_apply(h, src, dstv));
-                    ++applies;
+                    HIP_TRY(apply(src, dstv));
                     std::swap(src, dstv);
                     if ((t + 1) % kNormEvery == 0) {
                         HIP_TRY(launch_kdots(src, n, 1, nullptr, n, h->kdot, G, scal + 3, false, st));
@@ -1859,7 +1890,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         res->residual_1 = res1;
         res->diff_1 = diff;
         res->iters = applies;
-        res->iters_fp32 = 0;
+        res->iters_fp32 = applies32;
         res->status = out;
     }
     return out;

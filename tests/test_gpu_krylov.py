@@ -165,3 +165,17 @@ def test_gmres_device_vectors_match_host():
     assert info["iters"] == i_host["iters"]
     assert np.array_equal(pd.cpu().numpy(), p_host)
     s.close()
+
+
+@pytest.mark.parametrize("name,make,fmt", [CHAINS[1], CHAINS[2], CHAINS[4]],
+                         ids=[CHAINS[k][0] for k in (1, 2, 4)])
+def test_mixed_gmres_applies_fp32_then_reaches_the_fp64_solution(name, make, fmt):
+    """STC_MIXED handles run the first applications of M^{-1} N in FP32 and
+    finish in FP64: same direct solution to 1e-10."""
+    g = make()
+    s = _solver(g, fmt, precision="mixed", krylov_restart=30, switch_tol=1e-7, poison=True)
+    pi, info = s.solve_gmres(tol=1e-13, restart=30, max_applies=20_000)
+    _say(f"mixed gmres {name}: applies {info['iters']}, fp32 {info['iters_fp32']}")
+    assert info["status"] == 0 and 0 < info["iters_fp32"] < info["iters"]
+    assert np.abs(pi - _direct(g, fmt)).sum() <= 1e-10
+    s.close()
