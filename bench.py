@@ -57,7 +57,8 @@ Other workloads (each prints its own JSON line instead):
                   no GPU: read the JSON line --pmc-probe printed (PROBE) and
                   the two counter_collection.csv files those runs wrote,
                   scale each counter by what it reads for the copy of known
-                  size, and write profiles/traffic.json
+                  size, and store the figures in profiles/traffic.json under
+                  the probe's launch variant
 """
 from __future__ import annotations
 
@@ -94,10 +95,8 @@ def measured_traffic(workload: str, variant: int):
         return None
     with open(path) as f:
         rec = json.load(f)
-    entry = rec.get(workload)
+    entry = rec.get(workload, {}).get(str(variant))
     if not entry or entry.get("source_hash") != kernel_source_hash():
-        return None
-    if entry.get("variant") != variant:
         return None
     return entry.get("bytes_per_launch")
 
@@ -221,11 +220,11 @@ def main():
     t_setup = time.perf_counter() - t0
     print(f"# generated in {t_gen:.1f}s, setup in {t_setup:.2f}s, arena "
           f"{solver.footprint / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-    # pick the sweep kernels' launch variant for this chain (or take the
-    # one given: profiled runs avoid the persistent variants' cooperative
-    # launches, after which the profiler can fail at exit)
+    # pick the sweep kernels' launch variant for this chain, each candidate
+    # timed on a burst as long as the timed one (a persistent variant's fixed
+    # cost per launch is spread over its burst), or take the one given
     if args.variant is None:
-        tuned_ms, _ = stc.stc_autotune(solver.h, 20)
+        tuned_ms, _ = stc.stc_autotune(solver.h, max(20, args.steps))
     else:
         stc.stc_set_variant(solver.h, stc.STC_FP64, args.variant)
         tuned_ms = float("nan")
@@ -858,7 +857,7 @@ def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30, variant=None):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"probe": f"qbd_L{L}_m{m}_fp64", "variant": stc.stc_get_variant(s.h, 0),
-                      "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
+                      "sweeps": sweeps, "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
                       "source_hash": kernel_source_hash()}), flush=True)
     s.close()
 
@@ -876,21 +875,30 @@ def _counter_rows(path, counter):
 
 
 def _phase_kernel(name, phase_b, variant):
-    """Is this the sweep kernel k_sweep<double, 64, 1, PHB, RG, NT> of the
-    chosen launch variant (RG = 4 if bit 0 else 8, NT = bit 1)?"""
+    """Is this the sweep kernel of the chosen launch variant: per phase
+    k_sweep<double, 64, 1, PHB, RG, NT>, or with bit 2 the persistent
+    k_sweep_flow<double, 64, 1, RG, NT> that runs both phases of a burst
+    (RG = 4 if bit 0 else 8, NT = bit 1)?"""
     rg = 4 if variant & 1 else 8
     nt = "true" if variant & 2 else "false"
-    want = f"k_sweep<double,64,1,{'true' if phase_b else 'false'},{rg},{nt}>"
+    if variant & 4:
+        want = f"k_sweep_flow<double,64,1,{rg},{nt}>"
+    else:
+        want = f"k_sweep<double,64,1,{'true' if phase_b else 'false'},{rg},{nt}>"
     return want in name.replace(" ", "")
 
 
 def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1 << 30):
     """HBM bytes per phase launch from the FETCH_SIZE and WRITE_SIZE runs of
     --pmc-probe.  Each counter (KiB per dispatch) is scaled by what it reads
-    for the 1 GiB device copy, whose true traffic is 1 GiB each way."""
+    for the 1 GiB device copy, whose true traffic is 1 GiB each way.  A
+    persistent variant runs the probe's sweeps in one dispatch per burst:
+    its per-phase figure is the dispatches' total over twice the sweeps.
+    The record is stored per launch variant, beside those of the others."""
     with open(probe_json) as f:
         probe = json.loads(f.read().strip().splitlines()[-1])
     variant = probe["variant"]
+    persistent = bool(variant & 4)
     out = {}
     for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
                                  ("write", write_csv, "WRITE_SIZE")):
@@ -901,7 +909,11 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
         b = [v for n, v in rows if _phase_kernel(n, True, variant)]
         if not a or not b:
             raise SystemExit(f"no phase kernels of variant {variant} in {path}")
-        out[label] = (sum(a) / len(a), sum(b) / len(b), scale, len(a))
+        if persistent:
+            per_phase = sum(a) / (2 * probe["sweeps"])
+            out[label] = (per_phase, per_phase, scale, len(a))
+        else:
+            out[label] = (sum(a) / len(a), sum(b) / len(b), scale, len(a))
     fa, fb, fs, n = out["fetch"]
     wa, wb, ws, _ = out["write"]
     rec = {
@@ -918,9 +930,16 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
                      f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --pmc-probe --variant {variant}",
                      "python3 bench.py --traffic-summary PROBE FETCH_CSV WRITE_CSV"],
     }
+    if persistent:
+        rec["sweeps_per_probe"] = probe["sweeps"]
     path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table.setdefault(f"qbd_L{L}_m{m}_fp64", {})[str(variant)] = rec
     with open(path, "w") as f:
-        json.dump({f"qbd_L{L}_m{m}_fp64": rec}, f, indent=1)
+        json.dump(table, f, indent=1)
     print(json.dumps(rec), flush=True)
 
 

@@ -192,10 +192,13 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
  * pi receives the last normalised iterate.  res->iters counts the
  * applications, res->diff_1 the last cycle's change ||x_new - x||_1.
  * A cycle's x is normalised by its sum whatever its sign; a zero or
- * non-finite sum counts as a rejected cycle.  Needs restart in
- * 1..opt.krylov_restart (STC_EINVAL otherwise).  Returns STC_OK,
- * STC_EMAXIT, STC_EDEGENERATE (e^T x <= 0 after plain steps), STC_EINVAL,
- * STC_EDEVICE. */
+ * non-finite sum counts as a rejected cycle.  A cycle whose first Krylov
+ * vector has zero or non-finite norm (T x = x to rounding) ends an FP32
+ * stage, and in FP64 ends the solve with STC_EMAXIT if the residual is still
+ * above tol.  Needs restart in 1..opt.krylov_restart (STC_EINVAL
+ * otherwise).  Returns STC_OK, STC_EMAXIT (budget spent or stalled; pi and
+ * res still filled), STC_EDEGENERATE (e^T x <= 0 after plain steps),
+ * STC_EINVAL, STC_EDEVICE. */
 stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, double tol,
                            int64_t max_applies, double *pi, stc_result *res, int32_t where);
 

@@ -1712,7 +1712,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     if ((rc = residual(&res1)) != STC_OK) return rc;
     long long applies = 0, applies32 = 0;
     double diff = INFINITY;
-    bool converged = res1 <= tol;
+    bool converged = res1 <= tol, stalled = false;
     // FP32 and mixed handles apply M^{-1} N in FP32 first (the Krylov vectors
     // stay FP64), until ||Q^T x||_1 <= switch_tol or an FP32 cycle stalls
     bool f32 = h->precision != STC_FP64;
@@ -1740,7 +1740,15 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         double beta;
         if ((rc = fetch(scal, &beta, 1)) != STC_OK) return rc;
         if (!(beta > 0.0) || !std::isfinite(beta)) {
-            if (beta == 0.0) converged = true;   // x is already a null vector of T - I
+            // T x = x to rounding (or the FP32 apply overflowed): no Krylov
+            // direction is left in this precision.  An FP32 stage ends and the
+            // FP64 cycles take over; in FP64 the solve stops, and the status
+            // below compares the residual with tol.
+            if (f32) {
+                f32 = false;
+                continue;
+            }
+            stalled = true;
             break;
         }
         HIP_TRY(launch_kscale(V, scal, V, n, st));
@@ -1883,9 +1891,11 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
     if (where == STC_MEM_HOST)
         HIP_TRY(hipMemcpyAsync(pi, h->io, sizeof(double) * h->N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    const stc_status out = converged ? STC_OK : fail(STC_EMAXIT, "max_applies = %lld reached, "
-                                                     "residual %g above tol", (long long)max_applies,
-                                                     res1);
+    const stc_status out =
+        converged ? STC_OK
+        : stalled ? fail(STC_EMAXIT, "GMRES stalled: T x = x to rounding at residual %g above tol", res1)
+                  : fail(STC_EMAXIT, "max_applies = %lld reached, residual %g above tol",
+                         (long long)max_applies, res1);
     if (res) {
         res->residual_1 = res1;
         res->diff_1 = diff;

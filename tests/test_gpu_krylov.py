@@ -179,3 +179,23 @@ def test_mixed_gmres_applies_fp32_then_reaches_the_fp64_solution(name, make, fmt
     assert info["status"] == 0 and 0 < info["iters_fp32"] < info["iters"]
     assert np.abs(pi - _direct(g, fmt)).sum() <= 1e-10
     s.close()
+
+
+def test_gmres_from_the_solution_and_with_an_unreachable_tol():
+    """A start that already meets tol returns at once with no application of
+    T; tol = 0 cannot be met, and the solve ends with STC_EMAXIT (a stalled
+    Krylov space or a spent budget) with pi and the residual still filled."""
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(40, 16, 3, last=9)
+    s = _solver(g, "dense", krylov_restart=20)
+    pi, info = s.solve_gmres(tol=1e-13, restart=20)
+    assert info["status"] == 0
+    p2, i2 = s.solve_gmres(pi, tol=1e-12, restart=20)
+    assert i2["status"] == 0 and i2["iters"] == 0 and i2["residual_1"] <= 1e-12
+    assert np.abs(p2 - pi).sum() <= 1e-14
+    p3, i3 = s.solve_gmres(pi, tol=0.0, restart=20, max_applies=400)
+    _say(f"tol 0: status {i3['status']} applies {i3['iters']} residual {i3['residual_1']:.2e}")
+    assert i3["status"] == stc.STC_EMAXIT and 0 < i3["iters"] <= 400
+    assert np.isfinite(i3["residual_1"]) and i3["residual_1"] <= 1e-12
+    assert np.abs(p3 - _direct(g, "dense")).sum() <= 1e-10
+    s.close()
