@@ -18,13 +18,15 @@ Prints one JSON line.  Options:
 Other workloads (each prints its own JSON line instead):
   --large         16384 levels x m=128 QBD (N = 2,097,152): per-sweep GB/s in
                   FP64 and FP32, and time to ||pi - pi_ref||_1 <= 1e-10,
-                  mixed vs FP64
+                  mixed vs FP64; the oracle's CPU sweep per sweep, and the CPU
+                  time of the FP64 run's sweeps as a projection
   --serve N       served stream of N QBD requests (512 is the served workload) (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
   --banded        2048 levels x m=128 block-pentadiagonal generator with 10 %
                   dense off-diagonal blocks: sweeps/s and GB/s with dense and
-                  sparse (ELL) off-diagonal storage, FP64 and FP32
+                  sparse (ELL) off-diagonal storage, FP64 and FP32, and the
+                  oracle's CPU sweep per sweep
   --skipfree      2048 levels x m=64 skip-free (M/G/1-type) generator with
                   block bandwidth 4 (down one level, up to four): sweeps/s
                   with dense and sparse storage, FP64 and FP32, and the time
@@ -190,7 +192,7 @@ def main():
     if args.setup:
         return setup_mode(*args.setup)
     if args.banded:
-        return banded_mode()
+        return banded_mode(no_cpu=args.no_cpu)
     if args.skipfree:
         return skipfree_mode()
     if args.mutex:
@@ -402,10 +404,28 @@ def large_mode(args, L=16384, m=128, err_target=1e-10):
             "cpu_baseline": {"kind": "oracle", "direct_solve_s": round(t_ref, 2), "cores": 1,
                              "sample": "the oracle's level-by-level GTH solve of the whole "
                                        "chain (also pi_ref)"}}
+    if not args.no_cpu:
+        line["cpu_baseline"]["sweep"] = cpu_sweep_figures(
+            gen, rates["fp64"]["bytes_per_sweep"], runs["fp64"]["iters"], 10.0)
     print(json.dumps(line), flush=True)
 
 
-def banded_mode(L=2048, m=128):
+def cpu_sweep_figures(gen, bytes_per_sweep, gpu_sweeps=None, budget_s=10.0):
+    """The oracle's C/OpenMP FP64 sweep on every host core, over a bounded
+    sample: per-sweep time and GB/s, and (given the sweeps a GPU run took) the
+    CPU time those sweeps would take, labelled a projection."""
+    sec, n, threads = cpu_baseline(gen, budget_s=budget_s)
+    out = {"ms_per_sweep": round(sec * 1e3, 3), "GB/s": round(bytes_per_sweep / sec / 1e9, 2),
+           "cores": threads, "kind": "oracle",
+           "sample": f"{n} FP64 sweeps of the same chain by the C/OpenMP oracle sweep"}
+    if gpu_sweeps:
+        out["projection_s"] = round(gpu_sweeps * sec, 1)
+        out["projection"] = ("not measured: the FP64 GPU run's sweep count times the CPU "
+                             "per-sweep time")
+    return out
+
+
+def banded_mode(L=2048, m=128, no_cpu=False):
     """Sweep rate on the block-pentadiagonal 10 %-dense generator.  Its
     symmetric rates give no drift, so a solve from e/N takes on the order of
     L^2 sweeps; the figure of merit is the sweep rate."""
@@ -429,6 +449,11 @@ def banded_mode(L=2048, m=128):
             "runs": runs, "ingest": ingest,
             "speedup_sparse_vs_dense_fp64": round(runs["dense_fp64"]["ms_per_sweep"] /
                                                  runs["sparse_fp64"]["ms_per_sweep"], 3)}
+    if not no_cpu:
+        cpu = cpu_sweep_figures(gen, runs["dense_fp64"]["bytes_per_sweep"])
+        cpu["gpu_sparse_fp64_speedup"] = round(cpu["ms_per_sweep"] /
+                                               runs["sparse_fp64"]["ms_per_sweep"], 1)
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 
