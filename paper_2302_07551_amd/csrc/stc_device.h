@@ -1121,8 +1121,15 @@ __device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int MP>
-__global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const int *sizes,
+// Waves per workgroup of the MFMA inverse.  The block fills the LDS at
+// MP = 128, so one workgroup runs per CU; 16 waves (4 per SIMD) let the MFMA
+// chains of different tiles overlap (1.3x over 4 waves, same arithmetic per
+// tile, so bitwise the same inverse).  At MP = 64 several workgroups share
+// a CU and 8 waves gain 3 %; more waves cost occupancy.
+__host__ __device__ constexpr int inv_waves(int MP) { return MP >= 128 ? 16 : MP >= 64 ? 8 : 4; }
+
+template <int MP, int NW = inv_waves(MP)>   // NW: waves per workgroup
+__global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, const int *sizes,
                                                       double *blk, int NB, int B, DevState *st) {
     constexpr int LD = MP + 2;      // row stride in LDS (doubles)
     constexpr int NT = MP / 16;     // panels
@@ -1137,7 +1144,7 @@ __global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const i
     const int n = sizes[i];
     const double *Q = diag + (size_t)i * MP * MP;
     if (tid == 0) bad = 0;
-    for (int idx = tid; idx < MP * MP; idx += kWG) {
+    for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
         const int r = idx / MP, c = idx - r * MP;
         double v;
         if (r < n && c < n) v = -Q[idx];
@@ -1174,7 +1181,7 @@ __global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const i
         }
         __syncthreads();
         // row panel: R = D^{-1} A[k, j]
-        for (int jb = wave; jb < NT; jb += 4) {
+        for (int jb = wave; jb < NT; jb += NW) {
             if (jb == kb) continue;
             const int j0 = 16 * jb;
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -1189,7 +1196,7 @@ __global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const i
         }
         __syncthreads();
         // trailing update: A[i, j] += (-A[i, k]) R[k, j]
-        for (int t = wave; t < NT * NT; t += 4) {
+        for (int t = wave; t < NT * NT; t += NW) {
             const int ib = t / NT, jb = t - ib * NT;
             if (ib == kb || jb == kb) continue;
             const int i0 = 16 * ib, j0 = 16 * jb;
@@ -1207,7 +1214,7 @@ __global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const i
         }
         __syncthreads();
         // column panel: A[i, k] = -A[i, k] D^{-1};  A[k, k] = D^{-1}
-        for (int ib = wave; ib < NT; ib += 4) {
+        for (int ib = wave; ib < NT; ib += NW) {
             const int i0 = 16 * ib;
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
             if (ib == kb) {
@@ -1227,7 +1234,7 @@ __global__ __launch_bounds__(kWG) void k_invert_mfma(const double *diag, const i
         __syncthreads();
     }
     double *W = blk + ((size_t)i * NB + B) * MP * MP;
-    for (int idx = tid; idx < MP * MP; idx += kWG) {
+    for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
         const int r = idx / MP, c = idx - r * MP;
         W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
     }

@@ -239,8 +239,8 @@ template <int MP>
 static hipError_t invert_mp(int b, const double *diag, const int *sizes, double *blk, int L,
                             DevState *st, hipStream_t s) {
     if constexpr (MP >= 32)
-        hipLaunchKernelGGL((k_invert_mfma<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk,
-                           2 * b + 1, b, st);
+        hipLaunchKernelGGL((k_invert_mfma<MP>), dim3(L), dim3(64 * inv_waves(MP)), 0, s, diag,
+                           sizes, blk, 2 * b + 1, b, st);
     else
         hipLaunchKernelGGL((k_invert<MP>), dim3(L), dim3(kWG), 0, s, diag, sizes, blk, 2 * b + 1,
                            b, st);
