@@ -24,19 +24,41 @@ __global__ void k_kstate_init(DevState *st) {
     }
 }
 
-// Partial dot products: block (c, v) sums V[v] . w over chunk c of the
-// vector (w = nullptr: the sum of V[v], i.e. e^T V[v]; absdiff: the sum of
-// |V[v] - w|).  part[v * G + c].
-__global__ __launch_bounds__(kWG) void k_kdot(const double *V, size_t ld, const double *w,
-                                               size_t n, double *part, int absdiff) {
+// Term e of a dot kernel: MODE 0 x[e] (e^T x), 1 x[e] w[e], 2 |x[e] - w[e]|.
+// The product is rounded on its own: fused into the compensated sum's first
+// add, it would differ from the copy the compensation term uses.
+template <int MODE>
+__device__ inline double dot_term(const double *__restrict__ x, const double *__restrict__ w,
+                                  size_t e) {
+#pragma clang fp contract(off)
+    if constexpr (MODE == 0) return x[e];
+    else if constexpr (MODE == 1) return x[e] * w[e];
+    else return fabs(x[e] - w[e]);
+}
+
+// Partial dot products: block (c, v) sums the terms of V[v] and w over chunk
+// c of the vector into part[v * G + c].  A thread takes the elements
+// e0 + tid, e0 + tid + kWG, ... in that order; four terms are loaded ahead
+// of their compensated adds, so four loads per thread are in flight.
+template <int MODE>
+__global__ __launch_bounds__(kWG) void k_kdot(const double *__restrict__ V, size_t ld,
+                                               const double *__restrict__ w, size_t n,
+                                               double *__restrict__ part) {
     __shared__ double sh[4 * kWG / 64];
     const int G = gridDim.x, c = blockIdx.x, v = blockIdx.y;
     const size_t chunk = (n + G - 1) / G;
     const size_t e0 = (size_t)c * chunk, e1 = e0 + chunk < n ? e0 + chunk : n;
     const double *x = V + (size_t)v * ld;
     double s = 0.0, sc = 0.0;
-    for (size_t e = e0 + threadIdx.x; e < e1; e += kWG)
-        dd_acc(s, sc, !w ? x[e] : (absdiff ? fabs(x[e] - w[e]) : x[e] * w[e]));
+    size_t e = e0 + threadIdx.x;
+    for (; e + 3 * kWG < e1; e += 4 * kWG) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = dot_term<MODE>(x, w, e + u * kWG);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dd_acc(s, sc, t[u]);
+    }
+    for (; e < e1; e += kWG) dd_acc(s, sc, dot_term<MODE>(x, w, e));
     s = block_sum_dd(s, sc, sh);
     if (threadIdx.x == 0) part[(size_t)v * G + c] = s;
 }
@@ -52,13 +74,23 @@ __global__ __launch_bounds__(kWG) void k_kfold(const double *part, int G, double
     if (threadIdx.x == 0) out[v] = mode == 1 ? sqrt(s) : s;
 }
 
-// w += sign * sum_v h[v] V[v]  (h in device memory)
-__global__ __launch_bounds__(kWG) void k_kupdate(const double *V, size_t ld, int nv,
-                                                  const double *h, double sign, double *w,
-                                                  size_t n) {
+// w += sign * sum_v h[v] V[v]  (h in device memory; V, h and w disjoint).
+// The sum runs over v in order; the V entries of four v are loaded ahead of
+// their multiply-adds, so four loads per thread are in flight.
+__global__ __launch_bounds__(kWG) void k_kupdate(const double *__restrict__ V, size_t ld, int nv,
+                                                  const double *__restrict__ h, double sign,
+                                                  double *__restrict__ w, size_t n) {
     for (size_t e = blockIdx.x * (size_t)kWG + threadIdx.x; e < n; e += (size_t)gridDim.x * kWG) {
         double t = 0.0;
-        for (int v = 0; v < nv; ++v) t += h[v] * V[(size_t)v * ld + e];
+        int v = 0;
+        for (; v + 4 <= nv; v += 4) {
+            double a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = V[(size_t)(v + u) * ld + e];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) t += h[v + u] * a[u];
+        }
+        for (; v < nv; ++v) t += h[v] * V[(size_t)v * ld + e];
         w[e] += sign * t;
     }
 }
@@ -93,7 +125,12 @@ hipError_t launch_kstate_init(DevState *st, hipStream_t s) {
 hipError_t launch_kdots(const double *V, size_t ld, int nv, const double *w, size_t n, double *part,
                         int G, double *out, bool norm, hipStream_t s, bool absdiff) {
     if (nv < 1 || G < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_kdot, dim3(G, nv), dim3(kWG), 0, s, V, ld, w, n, part, absdiff ? 1 : 0);
+    if (!w)
+        hipLaunchKernelGGL(k_kdot<0>, dim3(G, nv), dim3(kWG), 0, s, V, ld, w, n, part);
+    else if (absdiff)
+        hipLaunchKernelGGL(k_kdot<2>, dim3(G, nv), dim3(kWG), 0, s, V, ld, w, n, part);
+    else
+        hipLaunchKernelGGL(k_kdot<1>, dim3(G, nv), dim3(kWG), 0, s, V, ld, w, n, part);
     hipLaunchKernelGGL(k_kfold, dim3(nv), dim3(kWG), 0, s, part, G, out, norm ? 1 : 0);
     return hipGetLastError();
 }
