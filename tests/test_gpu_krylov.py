@@ -199,3 +199,22 @@ def test_gmres_from_the_solution_and_with_an_unreachable_tol():
     assert np.isfinite(i3["residual_1"]) and i3["residual_1"] <= 1e-12
     assert np.abs(p3 - _direct(g, "dense")).sum() <= 1e-10
     s.close()
+
+
+def test_one_cycle_with_unrolled_dot_chunks():
+    """A padded vector of 2100 x 64 = 134400 entries gives each of the dot
+    kernel's 128 chunks 1050 entries: four terms per thread through the
+    unrolled loop and a tail of one for the first 26 threads.  One cycle
+    against the oracle's cycle."""
+    from paper_2302_07551_amd import stc
+    g = synth.qbd(2100, 64, 13)
+    r = 8
+    s = _solver(g, "dense", krylov_restart=r)
+    x0 = np.random.default_rng(11).uniform(0.5, 1.5, g.N)
+    pi, info = s.solve_gmres(x0, tol=0.0, restart=r, max_applies=r + 1)
+    assert info["status"] == stc.STC_EMAXIT and info["iters"] == r + 1
+    want = krylov.gmres_solve(_system(g, "dense"), restart=r, tol=0.0, maxit=r + 1, x0=x0)
+    err = np.abs(pi - want.x).sum()
+    _say(f"2100 x 64 cycle: |pi - oracle|_1 = {err:.2e}")
+    assert want.applies == r + 1 and err <= 1e-10
+    s.close()
