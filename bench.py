@@ -1,25 +1,33 @@
-"""Benchmark: HBM GB/s per staircase sweep on one MI355X.
+"""Benchmark: the staircase sweep on one MI355X.
 
-Workload (default): level-dependent QBD generator, 4096 levels x block size 64
-(N = 262144), FP64, stair type 1, synthetic seeded rates.  A step is one
-sweep of Algorithm 2 (phase A + phase B + normalisation and change), run on
-the device-resident iterate.  value = algorithmic bytes of one sweep / mean
-sweep time.
+Workload (default): level-dependent QBD generator, 16384 levels x block size
+128 (N = 2,097,152), FP64, stair type 1, synthetic seeded rates.  A step is
+one sweep of Algorithm 2 (phase A + phase B + normalisation and change), run
+on the device-resident iterate.  value = algorithmic bytes of one sweep / mean
+sweep time over the timed steps.  The same line then carries:
+  time_to_error   mixed vs FP64 solves from e/N to ||pi - pi_ref||_1 <= 1e-10
+                  (pi_ref: the oracle's direct solve in the CPU-baseline leg)
+  cpu_baseline    the oracle's C/OpenMP sweep of the same chain on the host
+                  cores (and on one), with its FTZ/DAZ state
+  served          the served stream of 512 QBD requests (levels U{32..2048},
+                  m in {8,16,32,64}, mixed precision, 4 GiB admission budget):
+                  solves/s saturated, p50/p99 latency of Poisson arrivals at
+                  0.8x that rate, and the largest error over every served
+                  result against its chain's direct FP64 solution
 
 Prints one JSON line.  Options:
   --gpus N        only 1 is supported (one GPU per run)
   --steps K       timed sweeps (default 200)
   --warmup W      untimed sweeps first (default 20)
   --no-cpu        skip the CPU-baseline leg (the oracle's sweep timed on the
-                  host cores, and its direct solve, whose vector is the pi_ref
-                  the GPU errors are reported against)
-  --no-ttr        skip the time to ||Q^T pi||_1 <= 1e-12, FP64 vs mixed
+                  host cores, and the direct solves whose vectors are the
+                  pi_ref the GPU errors are reported against)
+  --no-ttr        skip the time to error, mixed vs FP64
+  --no-serve      skip the served stream
 
 Other workloads (each prints its own JSON line instead):
-  --large         16384 levels x m=128 QBD (N = 2,097,152): per-sweep GB/s in
-                  FP64 and FP32, and time to ||pi - pi_ref||_1 <= 1e-10,
-                  mixed vs FP64; the oracle's CPU sweep per sweep, and the CPU
-                  time of the FP64 run's sweeps as a projection
+  --qbd4096       the 4096 x 64 FP64 QBD (N = 262,144): sweep GB/s, time to
+                  ||Q^T pi||_1 <= 1e-12 (FP64 vs mixed), the oracle's CPU sweep
   --serve N       served stream of N QBD requests (512 is the served workload) (levels U{32..2048}, m in
                   {8,16,32,64}): saturated solves/s, then Poisson arrivals at
                   0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
@@ -163,7 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttr", action="store_true")
-    ap.add_argument("--large", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--qbd4096", action="store_true")
     ap.add_argument("--serve", type=int, default=0)
     ap.add_argument("--budget-gb", type=float, default=4.0)
     ap.add_argument("--pmc-probe", action="store_true")
@@ -183,12 +192,14 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
         sys.exit(2)
-    if args.large:
-        return large_mode(args)
+    if args.pmc_probe:
+        if args.qbd4096:
+            return pmc_probe(4096, 64, variant=args.variant)
+        return pmc_probe(variant=args.variant)
+    if args.qbd4096:
+        return qbd4096_mode(args)
     if args.serve:
         return serve_mode(args)
-    if args.pmc_probe:
-        return pmc_probe(variant=args.variant)
     if args.setup:
         return setup_mode(*args.setup)
     if args.banded:
@@ -204,24 +215,23 @@ def main():
     if args.launch_sizes:
         return launch_sizes_mode()
 
-    import numpy as np
-    import torch
+    return headline_mode(args)
 
-    import synth
+
+def sweep_bandwidth(gen, workload, args, seed):
+    """Autotuned FP64 sweeps of gen on the device-resident iterate: the timed
+    steps, the per-launch phase kernel times and the algorithmic bytes.
+    Returns the bench line's measured part."""
+    import torch
+    import synth  # noqa: F401  (the generator's module; seeds recorded below)
     from paper_2302_07551_amd import Solver, stc
 
-    torch.cuda.set_device(0)
-    L, m = 4096, 64
-    workload = f"qbd_L{L}_m{m}_fp64"
-    t0 = time.perf_counter()
-    gen = synth.qbd(L, m, synth.config_seed(1))
-    t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     solver = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64", stair_type=1)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    print(f"# generated in {t_gen:.1f}s, setup in {t_setup:.2f}s, arena "
-          f"{solver.footprint / 2**20:.0f} MiB", file=sys.stderr, flush=True)
+    print(f"# {workload}: setup in {t_setup:.2f}s, arena {solver.footprint / 2**20:.0f} MiB",
+          file=sys.stderr, flush=True)
     # pick the sweep kernels' launch variant for this chain, each candidate
     # timed on a burst as long as the timed one (a persistent variant's fixed
     # cost per launch is spread over its burst), or take the one given
@@ -242,9 +252,9 @@ def main():
     torch.cuda.synchronize()
     ms_per_step = e0.elapsed_time(e1) / args.steps
 
-    # per-launch device times of the two phase kernels (HIP events on the
-    # library's stream around every launch)
-    ms_a, ms_b, ms_fin, ms_sw = stc.stc_profile_sweeps(solver.h, args.steps)
+    # per-launch device times of the two phase kernels (events attached to
+    # each dispatch on the library's stream)
+    ms_a, ms_b, ms_fin, _ms_sw = stc.stc_profile_sweeps(solver.h, args.steps)
     bytes_a, bytes_b = stc.stc_phase_bytes(solver.h)
     bytes_sweep = bytes_a + bytes_b
     value = bytes_sweep / (ms_per_step * 1e-3) / 1e9
@@ -254,8 +264,8 @@ def main():
     # half of its launch time per sweep
     achieved = bytes_a / (ms_a * 1e-3) / 1e9
     traffic = measured_traffic(workload, variant)
-
-    line = {
+    solver.close()
+    return {
         "metric": "HBM GB/s per staircase sweep",
         "value": round(value, 1),
         "unit": "GB/s",
@@ -268,9 +278,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "levels": L, "block": m, "N": L * m,
-                   "stair_type": 1, "bytes_per_sweep": bytes_sweep,
-                   "seed": synth.config_seed(1)},
+        "config": {"workload": workload, "levels": gen.L, "block": gen.m, "N": gen.N,
+                   "stair_type": 1, "bytes_per_sweep": bytes_sweep, "seed": seed},
         "roofline": {"bound": "hbm",
                      "kernel": ("persistent sweep kernel, per phase" if persistent
                                 else "phase A sweep kernel"),
@@ -280,36 +289,201 @@ def main():
         "phase_b": {"ms_per_launch": round(ms_b, 5), "bytes_per_launch": bytes_b,
                     "GB/s": round(bytes_b / (ms_b * 1e-3) / 1e9, 1)},
         "finalize_ms_per_launch": round(ms_fin, 5),
-        "variant": {"fp64": stc.stc_get_variant(solver.h, stc.STC_FP64),
+        "variant": {"fp64": variant,
                     "autotune_ms_per_sweep": (round(tuned_ms, 5) if tuned_ms == tuned_ms
                                               else None)},
         "sweeps_per_s": round(1e3 / ms_per_step, 1),
     }
 
+
+def cpu_sweep_baseline(gen, bytes_sweep, budget_s=10.0, one_thread_s=4.0):
+    """The cpu_baseline object: the oracle's C/OpenMP FP64 sweep of the same
+    chain on every host core in the affinity mask, and on one."""
+    from oracle import csweep
+    sec, n, threads = cpu_baseline(gen, budget_s=budget_s)
+    sec1, n1, _ = cpu_baseline(gen, budget_s=one_thread_s, threads=1)
+    return {"value": round(bytes_sweep / sec / 1e9, 2), "unit": "GB/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 sweeps of the same workload by the C/OpenMP "
+                      f"oracle sweep ({sec * 1e3:.1f} ms each)",
+            "one_thread": {"value": round(bytes_sweep / sec1 / 1e9, 2),
+                           "sample": f"{n1} sweeps at 1 thread ({sec1 * 1e3:.1f} ms each)"},
+            "speedup": round(sec1 / sec, 2),
+            "efficiency": round(sec1 / sec / threads, 3),
+            "ftz_daz": csweep.ftz_daz(),
+            "ms_per_sweep": round(sec * 1e3, 3)}
+
+
+def qbd4096_mode(args):
+    """The 4096 x 64 FP64 QBD: sweep bandwidth, time to ||Q^T pi||_1 <= 1e-12
+    (FP64 vs mixed) and the C/OpenMP oracle sweep on the host cores."""
+    import torch
+    import synth
+    torch.cuda.set_device(0)
+    L, m = 4096, 64
+    gen = synth.qbd(L, m, synth.config_seed(1))
+    line = sweep_bandwidth(gen, f"qbd_L{L}_m{m}_fp64", args, synth.config_seed(1))
     if not args.no_ttr:
         ref, t_ref = cpu_reference(gen) if not args.no_cpu else (None, None)
         line["time_to_residual"] = time_to_residual(gen, ref)
         if t_ref is not None:
             line["cpu_direct_solve_s"] = round(t_ref, 3)
-
     # the device's own copy rate on the same box, as a second yardstick
     copy_gbs = device_copy_rate()
     line["device_copy_GBs"] = round(copy_gbs, 1)
-    line["vs_device_copy"] = round(value / copy_gbs, 4)
-
+    line["vs_device_copy"] = round(line["value"] / copy_gbs, 4)
     if not args.no_cpu:
-        sec, n, threads = cpu_baseline(gen)
-        sec1, n1, _ = cpu_baseline(gen, budget_s=4.0, threads=1)
-        line["cpu_baseline"] = {"value": round(bytes_sweep / sec / 1e9, 2), "unit": "GB/s",
-                                "cores": threads, "kind": "oracle",
-                                "sample": f"{n} FP64 sweeps of the same workload by the C/OpenMP "
-                                          f"oracle sweep ({sec * 1e3:.1f} ms each)",
-                                "one_thread": {"value": round(bytes_sweep / sec1 / 1e9, 2),
-                                               "sample": f"{n1} sweeps at 1 thread "
-                                                         f"({sec1 * 1e3:.1f} ms each)"},
-                                "speedup": round(sec1 / sec, 2),
-                                "efficiency": round(sec1 / sec / threads, 3)}
-    solver.close()
+        line["cpu_baseline"] = cpu_sweep_baseline(gen, line["config"]["bytes_per_sweep"])
+    print(json.dumps(line), flush=True)
+
+
+def time_to_error(gen, ref, err_target=1e-10):
+    """Mixed and FP64 solves of gen from e/N, each stopped by the change of
+    section 3 at a tolerance small enough for the error target, then checked
+    against pi_ref (the CPU-baseline leg's direct solution).  Wall time of
+    each solve, setup excluded."""
+    import numpy as np
+    import torch
+    from paper_2302_07551_amd import Solver, stc
+    runs = {}
+    for prec in ("mixed", "fp64"):
+        s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec, stop="diff", check_every=200,
+                   switch_tol=1e-6)
+        stc.stc_autotune(s.h, 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pi, info = s.solve(tol=args_tol(err_target), maxit=400000)
+        dt = time.perf_counter() - t0
+        err = None if ref is None else float(np.abs(pi - ref).sum())
+        runs[prec] = {"seconds": round(dt, 3), "sweeps": info["iters"],
+                      "sweeps_fp32": info["iters_fp32"], "err_vs_direct": err,
+                      "residual": info["residual_1"], "diff": info["diff_1"],
+                      "met_target": None if err is None else err <= err_target,
+                      "variant": {"fp64": stc.stc_get_variant(s.h, stc.STC_FP64),
+                                  "fp32": (stc.stc_get_variant(s.h, stc.STC_FP32)
+                                           if prec == "mixed" else None)}}
+        print(f"# {prec}: {runs[prec]}", file=sys.stderr, flush=True)
+        s.close()
+    runs["target"] = err_target
+    runs["speedup_mixed_vs_fp64"] = round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3)
+    return runs
+
+
+def _served_reference(spec):
+    """Worker of the CPU-baseline leg: one served chain's direct solution
+    (generated here from its seed), and the time the solve took."""
+    import synth
+    from oracle import level_reduction
+    g = synth.qbd(spec["L"], spec["m"], spec["seed"])
+    t0 = time.perf_counter()
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    return ref, time.perf_counter() - t0
+
+
+def _one_blas_thread():
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
+def served_stream_figures(n=512, budget_gb=4.0, with_refs=True):
+    """The served stream of n QBD requests (levels U{32..2048}, m in
+    {8, 16, 32, 64}), mixed precision, 4 GiB admission budget: a saturated
+    run (all requests at t = 0) gives solves/s, then Poisson arrivals at 0.8x
+    that rate give p50 / p99 latency.  With with_refs, every result of both
+    runs is checked against its chain's direct FP64 solution, computed by
+    the oracle on the host cores afterwards."""
+    import multiprocessing as mp
+    import numpy as np
+    import synth
+    from paper_2302_07551_amd.serve import Request, Server
+    specs = synth.served_stream(n, synth.config_seed(4), rate=1.0)
+    t0 = time.perf_counter()
+    gens = [synth.qbd(sp["L"], sp["m"], sp["seed"]) for sp in specs]
+    print(f"# served stream: {n} chains generated in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    budget = int(budget_gb * (1 << 30))
+    unit_gaps = np.array([sp["arrival"] for sp in specs])   # Poisson, rate 1
+
+    def run(rate):
+        arr = np.zeros(n) if rate is None else unit_gaps / rate
+        reqs = [Request(k, float(arr[k]), g.blocks, g.sizes, g.b) for k, g in enumerate(gens)]
+        srv = Server(budget, max_chains=256, sweeps_per_round=25, tol=1e-13, switch_tol=1e-6,
+                     precision="mixed")
+        st = srv.run(reqs)
+        srv.close()
+        summ = st.summary()
+        summ["rate_per_s"] = rate
+        print(f"# served rate={rate}: {summ}", file=sys.stderr, flush=True)
+        return st, summ
+
+    sat, sat_summ = run(None)
+    poisson, p_summ = run(0.8 * sat_summ["solves_per_s"])
+    out = {"workload": f"served_qbd_{n}", "requests": n, "precision": "mixed",
+           "budget_bytes": budget, "seed": synth.config_seed(4),
+           "solves_per_s": round(sat_summ["solves_per_s"], 2),
+           "p50_latency_s": round(p_summ["p50_latency_s"], 4),
+           "p99_latency_s": round(p_summ["p99_latency_s"], 4),
+           "arrival_rate_per_s": round(p_summ["rate_per_s"], 2),
+           "saturated": sat_summ, "poisson_0.8x": p_summ}
+    del gens
+    if with_refs:
+        t0 = time.perf_counter()
+        workers = max(1, min(16, len(os.sched_getaffinity(0))) - 1)
+        with mp.get_context("spawn").Pool(workers, initializer=_one_blas_thread) as pool:
+            refs = pool.map(_served_reference, specs, chunksize=4)
+        errs = []
+        for st in (sat, poisson):
+            for r in st.results:
+                errs.append(float(np.abs(r.pi - refs[r.rid][0]).sum()))
+        out["max_err_vs_direct"] = max(errs)
+        out["results_checked"] = len(errs)
+        out["all_completed"] = (sat_summ["completed"] == n and p_summ["completed"] == n
+                                and sat_summ["maxit"] == 0 and p_summ["maxit"] == 0)
+        out["cpu_direct_solves_s"] = round(sum(t for _, t in refs), 2)
+        print(f"# served references on {workers} processes in "
+              f"{time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    return out
+
+
+def headline_mode(args, L=16384, m=128, err_target=1e-10):
+    """The default line: the 16384 x 128 FP64 QBD (N = 2,097,152).  value is
+    the autotuned FP64 sweep's algorithmic GB/s over the timed steps; then
+    the time to ||pi - pi_ref||_1 <= 1e-10, mixed vs FP64; the oracle's
+    C/OpenMP sweep of the same chain on the host cores; and the served
+    stream of 512 requests (p50 / p99 latency, solves/s, the error of every
+    served result)."""
+    import torch
+    import synth
+    torch.cuda.set_device(0)
+    seed = synth.config_seed(3)
+    t0 = time.perf_counter()
+    gen = synth.qbd(L, m, seed)
+    print(f"# qbd_L{L}_m{m}: generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    line = sweep_bandwidth(gen, f"qbd_L{L}_m{m}_fp64", args, seed)
+    line["metric"] = "HBM GB/s per staircase sweep; time-to-residual 1e-10 FP64 vs mixed; p99 latency"
+    if not args.no_ttr:
+        ref, t_ref = (None, None) if args.no_cpu else cpu_reference(gen)
+        if t_ref is not None:
+            print(f"# direct reference in {t_ref:.1f}s", file=sys.stderr, flush=True)
+        line["time_to_error"] = time_to_error(gen, ref, err_target)
+        if t_ref is not None:
+            line["cpu_direct_solve_s"] = round(t_ref, 2)
+        del ref
+    copy_gbs = device_copy_rate()
+    line["device_copy_GBs"] = round(copy_gbs, 1)
+    line["vs_device_copy"] = round(line["value"] / copy_gbs, 4)
+    if not args.no_cpu:
+        cb = cpu_sweep_baseline(gen, line["config"]["bytes_per_sweep"])
+        fp64 = line.get("time_to_error", {}).get("fp64")
+        if fp64:
+            cb["projection_s"] = round(fp64["sweeps"] * cb["ms_per_sweep"] * 1e-3, 1)
+            cb["projection"] = ("not measured: the FP64 GPU run's sweep count times the CPU "
+                                "per-sweep time")
+        line["cpu_baseline"] = cb
+    del gen
+    if not args.no_serve:
+        line["served"] = served_stream_figures(512, args.budget_gb, with_refs=not args.no_cpu)
     print(json.dumps(line), flush=True)
 
 
@@ -356,58 +530,6 @@ def sweep_rate(gen, precision, steps=50, warmup=5, format="dense"):
            "bytes_per_sweep": ba + bb, "variant": stc.stc_get_variant(s.h, stage)}
     s.close()
     return out
-
-
-def large_mode(args, L=16384, m=128, err_target=1e-10):
-    """Time to ||pi - pi_ref||_1 <= 1e-10 on the 16384 x 128 QBD, mixed vs FP64.
-
-    Both runs use the change-based stop of section 3 with a tolerance small
-    enough for the error target (checked afterwards against the direct
-    solution), so they stop on the same criterion."""
-    import numpy as np
-    import torch
-    import synth
-    from paper_2302_07551_amd import Solver, stc
-    torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    gen = synth.qbd(L, m, synth.config_seed(3))
-    t_gen = time.perf_counter() - t0
-    # the error target needs pi_ref, so this mode always runs the CPU leg
-    ref, t_ref = cpu_reference(gen)
-    print(f"# generated in {t_gen:.1f}s, direct reference in {t_ref:.1f}s", file=sys.stderr,
-          flush=True)
-    rates = {p: sweep_rate(gen, p) for p in ("fp64", "fp32")}
-    print(f"# sweep rates {rates}", file=sys.stderr, flush=True)
-    runs = {}
-    for prec in ("mixed", "fp64"):
-        s = Solver(gen.blocks, gen.sizes, gen.b, precision=prec, stop="diff", check_every=200,
-                   switch_tol=1e-6)
-        stc.stc_autotune(s.h, 5)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        pi, info = s.solve(tol=args_tol(err_target), maxit=400000)
-        dt = time.perf_counter() - t0
-        err = float(np.abs(pi - ref).sum())
-        runs[prec] = {"seconds": round(dt, 3), "iters": info["iters"],
-                      "iters_fp32": info["iters_fp32"], "err_vs_direct": err,
-                      "residual": info["residual_1"], "diff": info["diff_1"],
-                      "met_target": err <= err_target}
-        print(f"# {prec}: {runs[prec]}", file=sys.stderr, flush=True)
-        s.close()
-    line = {"metric": "time to ||pi - pi_ref||_1 <= 1e-10, mixed vs FP64",
-            "value": runs["mixed"]["seconds"], "unit": "s", "higher_is_better": False,
-            "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
-            "config": {"workload": f"qbd_L{L}_m{m}", "levels": L, "block": m, "N": L * m,
-                       "seed": synth.config_seed(3)},
-            "speedup_mixed_vs_fp64": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 3),
-            "runs": runs, "sweep_rates": rates,
-            "cpu_baseline": {"kind": "oracle", "direct_solve_s": round(t_ref, 2), "cores": 1,
-                             "sample": "the oracle's level-by-level GTH solve of the whole "
-                                       "chain (also pi_ref)"}}
-    if not args.no_cpu:
-        line["cpu_baseline"]["sweep"] = cpu_sweep_figures(
-            gen, rates["fp64"]["bytes_per_sweep"], runs["fp64"]["iters"], 10.0)
-    print(json.dumps(line), flush=True)
 
 
 def cpu_sweep_figures(gen, bytes_per_sweep, gpu_sweeps=None, budget_s=10.0):
@@ -861,12 +983,12 @@ def setup_mode(L, m):
                       "inverse_flops": flops}), flush=True)
 
 
-def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30, variant=None):
+def pmc_probe(L=16384, m=128, sweeps=10, copy_bytes=1 << 30, variant=None):
     import torch
     import synth
     from paper_2302_07551_amd import Solver, stc
     torch.cuda.set_device(0)
-    gen = synth.qbd(L, m, synth.config_seed(1))
+    gen = synth.qbd(L, m, synth.config_seed(3 if (L, m) == (16384, 128) else 1))
     s = Solver(gen.blocks, gen.sizes, gen.b, precision="fp64")
     if variant is None:
         stc.stc_autotune(s.h, 10)
@@ -882,7 +1004,7 @@ def pmc_probe(L=4096, m=64, sweeps=10, copy_bytes=1 << 30, variant=None):
         y.copy_(x)
     torch.cuda.synchronize()
     print(json.dumps({"probe": f"qbd_L{L}_m{m}_fp64", "variant": stc.stc_get_variant(s.h, 0),
-                      "sweeps": sweeps, "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
+                      "L": L, "m": m, "sweeps": sweeps, "phase_a_bytes": ba, "phase_b_bytes": bb, "copy_bytes_each_way": copy_bytes,
                       "source_hash": kernel_source_hash()}), flush=True)
     s.close()
 
@@ -899,21 +1021,21 @@ def _counter_rows(path, counter):
     return [(name, v) for (_, name), v in rows.items()]
 
 
-def _phase_kernel(name, phase_b, variant):
+def _phase_kernel(name, phase_b, variant, mp):
     """Is this the sweep kernel of the chosen launch variant: per phase
-    k_sweep<double, 64, 1, PHB, RG, NT>, or with bit 2 the persistent
-    k_sweep_flow<double, 64, 1, RG, NT> that runs both phases of a burst
-    (RG = 4 if bit 0 else 8, NT = bit 1)?"""
+    k_sweep<double, MP, 1, PHB, RG, NT>, or with bit 2 the persistent
+    k_sweep_flow<double, MP, 1, RG, NT> that runs both phases of a burst
+    (blocks of 64 and more: RG = 4 if bit 0 else 8; NT = bit 1)?"""
     rg = 4 if variant & 1 else 8
     nt = "true" if variant & 2 else "false"
     if variant & 4:
-        want = f"k_sweep_flow<double,64,1,{rg},{nt}>"
+        want = f"k_sweep_flow<double,{mp},1,{rg},{nt}>"
     else:
-        want = f"k_sweep<double,64,1,{'true' if phase_b else 'false'},{rg},{nt}>"
+        want = f"k_sweep<double,{mp},1,{'true' if phase_b else 'false'},{rg},{nt}>"
     return want in name.replace(" ", "")
 
 
-def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1 << 30):
+def traffic_summary(probe_json, fetch_csv, write_csv, copy_bytes=1 << 30):
     """HBM bytes per phase launch from the FETCH_SIZE and WRITE_SIZE runs of
     --pmc-probe.  Each counter (KiB per dispatch) is scaled by what it reads
     for the 1 GiB device copy, whose true traffic is 1 GiB each way.  A
@@ -923,6 +1045,7 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
     with open(probe_json) as f:
         probe = json.loads(f.read().strip().splitlines()[-1])
     variant = probe["variant"]
+    L, m = probe.get("L", 4096), probe.get("m", 64)
     persistent = bool(variant & 4)
     out = {}
     for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"),
@@ -930,8 +1053,8 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
         rows = _counter_rows(path, counter)
         copies = sorted((v for n, v in rows if "copyBuffer" in n), reverse=True)[:3]
         scale = (copy_bytes / 1024) / (sum(copies) / len(copies))
-        a = [v for n, v in rows if _phase_kernel(n, False, variant)]
-        b = [v for n, v in rows if _phase_kernel(n, True, variant)]
+        a = [v for n, v in rows if _phase_kernel(n, False, variant, m)]
+        b = [v for n, v in rows if _phase_kernel(n, True, variant, m)]
         if not a or not b:
             raise SystemExit(f"no phase kernels of variant {variant} in {path}")
         if persistent:
@@ -940,6 +1063,7 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
         else:
             out[label] = (sum(a) / len(a), sum(b) / len(b), scale, len(a))
     fa, fb, fs, n = out["fetch"]
+    wl = " --qbd4096" if (L, m) == (4096, 64) else ""
     wa, wb, ws, _ = out["write"]
     rec = {
         "source_hash": probe["source_hash"],
@@ -951,8 +1075,8 @@ def traffic_summary(probe_json, fetch_csv, write_csv, L=4096, m=64, copy_bytes=1
         "fetch_scale": fs, "write_scale": ws, "dispatches": n,
         "algorithmic_bytes_per_launch": probe["phase_a_bytes"],
         "phase_b_algorithmic_bytes_per_launch": probe["phase_b_bytes"],
-        "commands": [f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --pmc-probe --variant {variant}",
-                     f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --pmc-probe --variant {variant}",
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --pmc-probe{wl} --variant {variant}",
+                     f"rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --pmc-probe{wl} --variant {variant}",
                      "python3 bench.py --traffic-summary PROBE FETCH_CSV WRITE_CSV"],
     }
     if persistent:

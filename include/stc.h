@@ -135,6 +135,9 @@ typedef struct {
     int32_t krylov_restart; /* 0, or the longest restart length r (1..256) that
                              stc_solve_gmres may use: the footprint then holds
                              r + 3 FP64 vectors and small buffers for it     */
+    int32_t krylov_keep_all; /* 0: stc_solve_gmres applies its safeguard (below);
+                             1: every cycle is kept (textbook restarted GMRES,
+                             no plain steps)                                   */
 } stc_options;
 
 typedef struct {
@@ -184,6 +187,9 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
  * the last block of plain steps achieved (before any plain block: by half
  * over the cycle); otherwise x stays and k plain normalised applications of
  * M^{-1} N follow, k = restart at first, doubled after each rejected cycle.
+ * With opt.krylov_keep_all = 1 there is no safeguard: every cycle is kept,
+ * as in textbook restarted GMRES, and a cycle whose sum is zero or not
+ * finite ends the solve with STC_EDEGENERATE.
  * The Krylov vectors and the residual are always FP64.  An STC_FP64 handle
  * applies M^{-1} N in FP64; STC_FP32 and STC_MIXED handles apply it in FP32
  * (vectors rounded to FP32 for each application and widened back) until
@@ -197,7 +203,8 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
  * stage, and in FP64 ends the solve with STC_EMAXIT if the residual is still
  * above tol.  Needs restart in 1..opt.krylov_restart (STC_EINVAL
  * otherwise).  Returns STC_OK, STC_EMAXIT (budget spent or stalled; pi and
- * res still filled), STC_EDEGENERATE (e^T x <= 0 after plain steps),
+ * res still filled), STC_EDEGENERATE (e^T x <= 0 after plain steps, or a
+ * cycle without a usable sum under krylov_keep_all),
  * STC_EINVAL, STC_EDEVICE. */
 stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, double tol,
                            int64_t max_applies, double *pi, stc_result *res, int32_t where);
@@ -268,11 +275,13 @@ stc_status stc_query(stc_handle *h, int64_t *sweeps, int32_t *stopped, double *d
 /* Copy the handle's current (or stopped) iterate, normalised, to pi. */
 stc_status stc_store(stc_handle *h, double *pi, int32_t where);
 
-/* Precision switch of the mixed schedule (a6): continue the handle's
- * iteration in FP64 from its current FP32 iterate (the stopped sweep if the
- * device test fired).  The last two FP32 iterates are widened exactly, so the
- * next FP64 sweep continues the same recurrence.  STC_EINVAL if the handle
- * does not sweep in FP32. */
+/* Precision switch of the mixed schedule: continue the handle's iteration in
+ * FP64 from its current FP32 iterate k (the stopped sweep if the device test
+ * fired).  The iterate is widened exactly, so the next FP64 sweep continues
+ * the same recurrence.  The changes of sweeps k - 1 and k keep their FP32
+ * values; the FP64 stopping test starts with the change of sweep k + 1, so a
+ * stop after the switch always comes after at least one FP64 sweep.
+ * STC_EINVAL if the handle does not sweep in FP32. */
 stc_status stc_promote(stc_handle *h);
 
 /* ---- many chains ------------------------------------------------------

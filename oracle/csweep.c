@@ -18,6 +18,7 @@
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
+#include <xmmintrin.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -266,6 +267,14 @@ int cs_gen_sweep(int L, int m, const long long *off, const long long *rp, const 
     }
     *err = e;
     return 0;
+}
+
+/* The calling thread's SSE control word (MXCSR): bit 15 flush-to-zero, bit 6
+ * denormals-are-zero.  The sweeps use the compiler's defaults (neither set),
+ * so subnormal iterate entries are computed in full. */
+unsigned cs_mxcsr(void)
+{
+    return _mm_getcsr();
 }
 
 int cs_threads(int nthreads)

@@ -45,6 +45,8 @@ def _load():
     lib.cs_gen_sweep.restype = ctypes.c_int
     lib.cs_threads.argtypes = [ctypes.c_int]
     lib.cs_threads.restype = ctypes.c_int
+    lib.cs_mxcsr.argtypes = []
+    lib.cs_mxcsr.restype = ctypes.c_uint
     return lib
 
 
@@ -122,3 +124,10 @@ class CGenSweep:
         if rc != 0:
             raise ArithmeticError("e^T z <= 0")
         return err.value
+
+
+def ftz_daz() -> dict:
+    """Flush-to-zero and denormals-are-zero state of the C sweeps (MXCSR of
+    the calling thread, whose setting the OpenMP threads start from)."""
+    w = int(_load().cs_mxcsr())
+    return {"ftz": bool(w & (1 << 15)), "daz": bool(w & (1 << 6))}

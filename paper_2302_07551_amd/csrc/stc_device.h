@@ -272,7 +272,7 @@ __device__ inline void record_sweep(DevState *st, long long s, double S, double 
         return;
     }
     cstore<COH>(&st->inv_sigma[s & kRingMask], 1.0 / S);
-    if (s >= 3) {
+    if (s >= 3 && s - 2 > cload<COH>(&st->test_after)) {
         cstore<COH>(&st->diff[(s - 2) & kRingMask], D);
         if (tol > 0.0 && D <= tol) {
             cstore<COH>(&st->stop_sweep, s - 2);

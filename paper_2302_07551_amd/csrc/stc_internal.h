@@ -29,6 +29,9 @@ struct DevState {
     long long last_sweep;     // last sweep whose phase B finished
     int bad_blocks;           // singular diagonal blocks found by the inverse
     int pad_;
+    long long test_after;     // changes of sweeps <= test_after are neither recorded
+                              // nor tested (set at a precision switch: their
+                              // iterates were overwritten after the FP32 stop)
 };
 
 enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2, kDevTimeout = 3 };

@@ -63,6 +63,7 @@ __global__ void k_rearm(DevState *st, long long k) {
         st->status = kDevOk;
         st->stop_sweep = -1;
         st->last_sweep = k;
+        st->test_after = k;
     }
 }
 
@@ -84,7 +85,7 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int m
         st->residual = t;
     } else if (mode == kReduceDiff) {
         // the change of sweep slot, with the device stopping test
-        if (st->stop_flag) return;
+        if (st->stop_flag || slot <= st->test_after) return;
         st->diff[slot & kRingMask] = t;
         if (tol > 0.0 && t <= tol) {
             st->stop_flag = 1;
@@ -129,6 +130,7 @@ __global__ void k_reset(DevState *st) {
         st->stop_sweep = -1;
         st->last_sweep = 0;
         st->residual = 0.0;
+        st->test_after = 0;
     }
 }
 

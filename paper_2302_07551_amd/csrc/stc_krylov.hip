@@ -21,6 +21,7 @@ __global__ void k_kstate_init(DevState *st) {
         st->last_sweep = 0;
         st->residual = 0.0;
         st->x_sum = 0.0;
+        st->test_after = 0;
     }
 }
 

@@ -408,6 +408,7 @@ struct stc_handle {
     std::vector<GenEntry> gen_host;   // the table, for the byte counts
     // Krylov workspace (stc_solve_gmres)
     int kr = 0;
+    bool keep_all = false;   // stc_solve_gmres keeps every cycle (no safeguard)
     double *kX = nullptr, *kW = nullptr, *kV = nullptr, *kpart = nullptr, *kdot = nullptr,
            *kh = nullptr;
     DevState *kst = nullptr;
@@ -760,9 +761,15 @@ stc_status store_vector(stc_handle *h, bool f32, long long s, double *pi, int32_
 }
 
 // Switch the current iterate from the FP32 rotation to the FP64 one at sweep
-// k: W_k, W_{k-1} and W_{k-2} (the next sweep's input and the two iterates of
-// the change it measures) are widened exactly, so the recorded scales stay
-// valid and the next FP64 sweep continues the same recurrence.
+// k: W_k, the next sweep's input, is widened exactly, so the recorded scales
+// stay valid and the next FP64 sweep continues the same recurrence.  The
+// device test fires two sweeps after the change it tests, and the sweeps
+// queued behind it may already have overwritten the FP32 buffers of W_{k-1}
+// and W_{k-2} with later iterates.  Those buffers are widened too, only so
+// that every FP64 buffer the next two sweeps read holds finite values; the
+// rearm that follows (test_after = k) keeps the changes of sweeps k - 1 and
+// k, which would read them, from being recorded or tested again, so the
+// first FP64 stop can come at sweep k + 1.
 stc_status widen_at(stc_handle *h, long long k) {
     const size_t vec = (size_t)h->L * h->MP;
     for (long long j = k; j >= 0 && j >= k - 2; --j)
@@ -1069,6 +1076,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     if (lay.kr > 0) {
         const size_t vec = (size_t)L * MP;
         h->kr = lay.kr;
+        h->keep_all = o->krylov_keep_all != 0;
         h->kX = (double *)(h->base + lay.kvec);
         h->kW = h->kX + vec;
         h->kV = h->kW + vec;
@@ -1654,8 +1662,8 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
             }
         }
     }
-    if (h->stage32 && !mixed) h->iters32 = s;
     if (final_k < 0) final_k = s;   // maxit reached
+    if (h->stage32) h->iters32 = final_k;   // ended in FP32 (also a mixed solve at maxit)
     h->s = final_k;
     double diff = INFINITY;   // every burst ends with the changes up to its last sweep
     if (final_k >= 1 && (rc = read_ring(h, h->st->diff, final_k, &diff)) != STC_OK) return rc;
@@ -1830,8 +1838,17 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
         const int cyc_applies = rr + 1;   // every step of the cycle ran
         const double need = plain_rate < 0.0 ? std::pow(0.5, 1.0 / cyc_applies)
                                              : plain_rate * plain_rate;
-        const bool keep = std::isfinite(res_new) && res_new < res1 &&
-                          std::pow(res_new / res1, 1.0 / cyc_applies) <= need;
+        if (h->keep_all && !std::isfinite(res_new)) {
+            rc = fail(STC_EDEGENERATE, "a GMRES cycle gave e^T x = %g", sum);
+            if (res) {
+                res->iters = applies;
+                res->status = rc;
+            }
+            return rc;
+        }
+        const bool keep = h->keep_all ||
+                          (std::isfinite(res_new) && res_new < res1 &&
+                           std::pow(res_new / res1, 1.0 / cyc_applies) <= need);
         if (f32 && (!keep || res_new <= h->switch_tol)) {
             // the FP32 stage ends: at its rounding floor, a stalled cycle is
             // dropped; the FP64 cycles continue from the best x

@@ -8,6 +8,10 @@ chains together with the batched (multi-chain, graph-replayed) launch.  A
 chain in its FP32 stage that meets the switch tolerance is promoted to FP64
 (stc_promote); a chain whose FP64 change meets the tolerance is retired: its
 vector is copied out, its memory freed, and waiting requests are admitted.
+A chain that reaches the per-request sweep cap is retired the same way with
+status STC_EMAXIT (its last iterate is returned).  A request whose setup
+fails (not a generator, a singular diagonal block, a bad shape) or whose
+sweeps lose all mass is rejected on its own; the service goes on.
 Setup of new chains (host validation and packing, upload, inverse of the
 diagonal blocks) runs on a host thread of its own and a side stream while
 the batch sweeps on its own stream, so arrivals overlap with the work
@@ -47,6 +51,7 @@ class Result:
     sweeps: int
     sweeps_fp32: int
     footprint: int
+    status: int = stc.STC_OK    # STC_OK, or STC_EMAXIT at the sweep cap
 
     @property
     def latency(self) -> float:
@@ -61,6 +66,7 @@ class ServeStats:
     peak_bytes: int = 0
     rounds: int = 0
     rejected: list = field(default_factory=list)
+    errors: dict = field(default_factory=dict)    # rid -> why it was rejected
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.results]) if self.results else np.zeros(1)
@@ -68,6 +74,7 @@ class ServeStats:
         last = max((r.done for r in self.results), default=0.0)
         return {
             "completed": len(self.results),
+            "maxit": sum(1 for r in self.results if r.status != stc.STC_OK),
             "rejected": len(self.rejected),
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
@@ -84,12 +91,14 @@ class Server:
     """Admission by footprint, continuous batching, FP32 -> FP64 promotion.
 
     nontemporal: stream the blocks with non-temporal loads (the admitted
-    chains together exceed the last-level cache under any useful budget)."""
+    chains together exceed the last-level cache under any useful budget).
+    max_sweeps: sweeps (both stages) after which a request that has not met
+    its tolerance is retired with STC_EMAXIT."""
 
     def __init__(self, budget_bytes: int, *, max_chains: int = 64, max_items: int = 1 << 17,
                  sweeps_per_round: int = 20, tol: float = 1e-13, switch_tol: float = 1e-6,
                  precision: str = "mixed", nontemporal: bool = True, device=None,
-                 b: int = 1, use_graph: bool = True):
+                 b: int = 1, use_graph: bool = True, max_sweeps: int = 1_000_000):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -100,6 +109,7 @@ class Server:
         self.precision = precision
         self.nontemporal = bool(nontemporal)
         self.use_graph = use_graph
+        self.max_sweeps = int(max_sweeps)
         self.device = torch.device(device if device is not None else "cuda")
         self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = stc.Batch(self.max_chains, max_items, b=b, device=self.device)
@@ -151,6 +161,21 @@ class Server:
         worker.start()
         t0 = clock()
         dirty = False
+
+        def join(item):
+            """A chain whose setup finished joins the batch; a failed setup
+            rejects its request alone."""
+            nonlocal in_setup, used, dirty
+            req, s, fp, err = item
+            in_setup -= 1
+            if err is not None:
+                stats.rejected.append(req.rid)
+                stats.errors[req.rid] = str(err)
+                used -= fp
+                return
+            active.append([req, s, fp, clock() - t0, 32 if self.precision != "fp64" else 64])
+            dirty = True
+
         try:
             while pending or waiting or active or in_setup:
                 now = clock() - t0
@@ -163,9 +188,12 @@ class Server:
                     fp = fps.get(req.rid)
                     if fp is None:
                         fp = fps[req.rid] = self.footprint(req)
-                    if fp > self.budget:
+                    if fp == 0 or fp > self.budget:
+                        # an unsupported shape, or larger than the whole budget
                         waiting.popleft()
                         stats.rejected.append(req.rid)
+                        stats.errors[req.rid] = ("unsupported generator shape" if fp == 0
+                                                 else f"footprint {fp} B above the budget")
                         continue
                     if used + fp > self.budget:
                         break
@@ -176,27 +204,16 @@ class Server:
                 # chains whose setup finished join this round
                 while True:
                     try:
-                        req, s, fp, err = ready.get_nowait()
+                        item = ready.get_nowait()
                     except queue.Empty:
                         break
-                    in_setup -= 1
-                    if err is not None:
-                        raise err
-                    active.append([req, s, fp, clock() - t0,
-                                   32 if self.precision != "fp64" else 64])
-                    dirty = True
+                    join(item)
                 stats.peak_chains = max(stats.peak_chains, len(active))
                 stats.peak_bytes = max(stats.peak_bytes, used)
                 if not active:
                     if in_setup:
                         # nothing to sweep: wait for the setup thread
-                        req, s, fp, err = ready.get()
-                        in_setup -= 1
-                        if err is not None:
-                            raise err
-                        active.append([req, s, fp, clock() - t0,
-                                       32 if self.precision != "fp64" else 64])
-                        dirty = True
+                        join(ready.get())
                     elif pending:
                         delay = pending[0].arrival - (clock() - t0)
                         if delay > 0:
@@ -215,14 +232,16 @@ class Server:
                     if status[k] != stc.STC_OK:
                         # a sweep produced no positive mass: drop the request
                         stats.rejected.append(req.rid)
+                        stats.errors[req.rid] = "e^T z <= 0 after a sweep"
                         s.close()
                         used -= fp
                         dirty = True
                         continue
-                    if not stopped[k]:
+                    capped = not stopped[k] and int(sweeps[k]) >= self.max_sweeps
+                    if not stopped[k] and not capped:
                         keep.append(entry)
                         continue
-                    if stage == 32 and self.precision == "mixed":
+                    if stage == 32 and self.precision == "mixed" and not capped:
                         s.promote()
                         entry[4] = 64
                         entry.append(int(sweeps[k]))          # sweeps in FP32
@@ -231,9 +250,11 @@ class Server:
                         continue
                     pi = s.store()
                     it = int(sweeps[k])
-                    it32 = entry[5] if len(entry) > 5 else (it if self.precision == "fp32" else 0)
+                    it32 = (entry[5] if len(entry) > 5
+                            else (it if self.precision == "fp32" or stage == 32 else 0))
                     stats.results.append(Result(req.rid, req.arrival, t_adm, clock() - t0, pi, it,
-                                                it32, fp))
+                                                it32, fp,
+                                                stc.STC_EMAXIT if capped else stc.STC_OK))
                     s.close()
                     used -= fp
                     dirty = True
@@ -241,6 +262,16 @@ class Server:
         finally:
             todo.put(None)
             worker.join()
+            # on an early exit, release every chain still held
+            for entry in active:
+                entry[1].close()
+            while True:
+                try:
+                    _req, s, _fp, _err = ready.get_nowait()
+                except queue.Empty:
+                    break
+                if s is not None:
+                    s.close()
         stats.wall = clock() - t0
         return stats
 

@@ -10,8 +10,10 @@ them for convenience.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_size_t, c_void_p
 
 import numpy as np
@@ -52,7 +54,7 @@ class stc_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("stair_type", c_int32), ("stop", c_int32),
                 ("check_every", c_int32), ("switch_tol", c_double), ("stream", c_void_p),
                 ("arena", c_void_p), ("arena_bytes", c_size_t), ("format", c_int32),
-                ("krylov_restart", c_int32)]
+                ("krylov_restart", c_int32), ("krylov_keep_all", c_int32)]
 
 
 class stc_result(ctypes.Structure):
@@ -70,6 +72,22 @@ class StcError(RuntimeError):
 
 
 _lib = None
+
+# Solvers and batches still open when the interpreter exits are closed by an
+# exit handler, in a fixed order (batches, then handles), rather than by
+# whatever order the garbage collector finds them in during teardown.
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
+_live_solvers: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for group in (_live_batches, _live_solvers):
+        for obj in list(group):
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def load_library(path: str = LIB_PATH):
@@ -176,12 +194,13 @@ FORMATS = {"dense": STC_DENSE, "sparse": STC_SPARSE}
 
 
 def make_options(precision="fp64", stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
-                 stream=0, arena=0, arena_bytes=0, format="dense", krylov_restart=0):
+                 stream=0, arena=0, arena_bytes=0, format="dense", krylov_restart=0,
+                 krylov_keep_all=False):
     return stc_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                        int(stair_type), STOPS[stop] if isinstance(stop, str) else int(stop),
                        int(check_every), float(switch_tol), stream or None, arena or None,
                        int(arena_bytes), FORMATS[format] if isinstance(format, str) else int(format),
-                       int(krylov_restart))
+                       int(krylov_restart), int(bool(krylov_keep_all)))
 
 
 def stc_footprint_bytes(gen: stc_generator, opt: stc_options) -> int:
@@ -370,6 +389,7 @@ class Batch:
                                    stream.cuda_stream if stream is not None else 0,
                                    self.arena.data_ptr(), need)
         self.members = []
+        _live_batches.add(self)
 
     def set(self, solvers, tol: float, nontemporal: bool = False):
         self.members = list(solvers)
@@ -409,7 +429,7 @@ class Solver:
     def __init__(self, blocks: np.ndarray | None, sizes, b: int, *, precision="fp64",
                  stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
                  recompute_diagonal=False, device=None, stream=None, poison=False,
-                 format="dense", csr=None, m=None, krylov_restart=0):
+                 format="dense", csr=None, m=None, krylov_restart=0, krylov_keep_all=False):
         """blocks: [L][2b+1][m][m] dense blocks, or None with csr = (indptr,
         indices, data) of the N x N generator (sizes then required; m
         defaults to the largest size).  poison: fill the arena with 0xFF
@@ -430,7 +450,7 @@ class Solver:
             self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
         self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
                                 stream=self.stream.cuda_stream, format=format,
-                                krylov_restart=krylov_restart)
+                                krylov_restart=krylov_restart, krylov_keep_all=krylov_keep_all)
         need = stc_footprint_bytes(self.gen, self.opt)
         if need == 0:
             raise StcError(STC_EINVAL, "unsupported generator shape or options")
@@ -445,6 +465,7 @@ class Solver:
         with torch.cuda.device(self.device):
             self.h = stc_setup(self.gen, self.opt)
         self._keep = None   # host inputs were copied during setup
+        _live_solvers.add(self)
 
     @classmethod
     def from_sparse(cls, Q, sizes, b: int, **kw):

@@ -1,16 +1,16 @@
 """GPU parity at the full sizes of the large workloads, in the launch
 configuration the benchmark times (launch variant picked by stc_autotune).
 
-- 16384 levels x m = 128 QBD (N = 2,097,152), FP64 and FP32 handles.  A
-  whole oracle sweep at this size takes tens of seconds, so outputs are
-  sampled: windows of levels spread along the chain, the two ends included,
-  give exact unnormalised sweep values (window_oracle.py). They are compared
-  with the GPU sweep up to the one normalisation scalar, which e^T z = 1
-  pins.  The change the GPU returns is checked against ||z - x||_1 on the
-  host, and the FP64 residual at full size against the oracle's.  The same
-  sweep as a burst on the resident iterate (the persistent kernel when the
-  tuned variant has one) meets the same samples, and a burst of three
-  sweeps equals three chained steps.
+- 16384 levels x m = 128 QBD (N = 2,097,152), FP64 and FP32 handles:
+  element by element against the oracle's C/OpenMP sweep of the whole chain
+  (pinned against the stair-matrix definition), with no fitted scalar.  One
+  step with the tuned variant; then a burst of three sweeps on the resident
+  iterate with the persistent kernel (the tuned variant with bit 2 set)
+  against three oracle sweeps; the change of each against the oracle's; the
+  FP64 residual at full size against the oracle's.
+- 4096 levels x m = 64 QBD (N = 262,144): converged FP64 and mixed solves
+  (stop ||Q^T pi||_1 <= 1e-12, as the benchmark runs them) within 1e-10 of
+  the oracle's direct solution (level reduction).
 - Banded 2048 x 128, block bandwidth 2, 10 % density (N = 262144), dense and
   sparse storage, FP64 and FP32: element by element against one whole
   oracle sweep.
@@ -19,8 +19,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import dense, staircase
-from window_oracle import sampled_stair_apply
+from oracle import dense, level_reduction, staircase
 
 pytestmark = pytest.mark.gpu
 
@@ -42,56 +41,84 @@ def _say(msg):
 @pytest.fixture(scope="module")
 def large_qbd():
     g = synth.qbd(16384, 128, synth.config_seed(3))
+    assert np.all(g.sizes == g.m)           # the padded layout is the compact one
     yield g
     del g
 
 
+@pytest.fixture(scope="module")
+def large_oracle(large_qbd):
+    from oracle import csweep
+    _say("16384 x 128: factoring the oracle's diagonal blocks")
+    return csweep.CSweep(large_qbd.blocks, large_qbd.sizes, large_qbd.b, 1)
+
+
+def _oracle_sweeps(cs, g, x, n):
+    """n sweeps of the C/OpenMP oracle from x / e^T x: (z, change of the last)."""
+    xr = np.ascontiguousarray((x / x.sum()).reshape(g.L, g.m))
+    z = np.empty_like(xr)
+    d = np.inf
+    for _ in range(n):
+        d = cs.sweep(xr, z)
+        xr, z = z, xr
+    return xr.reshape(-1).copy(), d
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_large_qbd_sampled_step(large_qbd, precision):
+def test_large_qbd_whole_sweep(large_qbd, large_oracle, precision):
     from paper_2302_07551_amd import Solver, stc
     g = large_qbd
     x = synth.positive_start(g, 17)
+    tol = 1e-13 if precision == "fp64" else 1e-5
     _say(f"16384 x 128 {precision}: setup")
     s = Solver(g.blocks, g.sizes, g.b, precision=precision)
     stc.stc_autotune(s.h, 5)
     stage = stc.STC_FP32 if precision == "fp32" else stc.STC_FP64
-    _say(f"16384 x 128 {precision}: variant {stc.stc_get_variant(s.h, stage)}, step")
+    v = stc.stc_get_variant(s.h, stage)
+    _say(f"16384 x 128 {precision}: variant {v}, step")
     z, d = s.step(x)
-    idx, u = sampled_stair_apply(g, x)
-    zs = z[idx]
-    c = u.sum() / zs.sum()          # e^T (M^{-1} N x), the scalar the sweep divided by
-    rel = np.abs(c * zs - u).sum() / np.abs(u).sum()
-    tol = 1e-13 if precision == "fp64" else 1e-5
-    _say(f"16384 x 128 {precision}: {idx.size} sampled states, relative 1-norm {rel:.2e}, "
-         f"|e^T z - 1| {abs(z.sum() - 1.0):.2e}")
-    assert np.isfinite(c) and c > 0.0
-    assert rel <= tol
-    assert abs(z.sum() - 1.0) <= (1e-12 if precision == "fp64" else 1e-6)
-    assert abs(d - np.abs(z - x).sum()) <= (1e-12 if precision == "fp64" else 1e-5)
-    # the same sweep as a burst on the resident iterate (the persistent kernel
-    # when the tuned variant has one, as in the benchmark's solves)
+    zr, dr = _oracle_sweeps(large_oracle, g, x, 1)
+    err = np.abs(z - zr).sum()
+    _say(f"16384 x 128 {precision}: |z - z_oracle|_1 = {err:.2e}, change {d:.6e} vs {dr:.6e}")
+    assert err <= tol and abs(d - dr) <= tol
+    # three sweeps in one burst on the resident iterate, persistent kernel
+    stc.stc_set_variant(s.h, stage, v | 4)
     s.load(x)
-    s.sweeps(1)
-    zb = s.store()
-    zbs = zb[idx]
-    relb = np.abs((u.sum() / zbs.sum()) * zbs - u).sum() / np.abs(u).sum()
-    assert relb <= tol and abs(zb.sum() - 1.0) <= (1e-12 if precision == "fp64" else 1e-6)
-    assert np.abs(zb - z).sum() <= tol
-    # three sweeps in one burst continue the recurrence of three steps
-    s.load(x)
-    s.sweeps(3)
+    diffs = s.sweeps(3, with_diffs=True)
     z3 = s.store()
-    zz = z
-    for _ in range(2):
-        zz, _d = s.step(zz)
-    _say(f"16384 x 128 {precision}: burst vs step {np.abs(zb - z).sum():.2e}, "
-         f"3-sweep burst vs 3 steps {np.abs(z3 - zz).sum():.2e}")
-    assert np.abs(z3 - zz).sum() <= tol
+    _q_sweeps, stopped, d3 = s.query()
+    zr3, dr3 = _oracle_sweeps(large_oracle, g, x, 3)
+    zr2, dr2 = _oracle_sweeps(large_oracle, g, x, 2)
+    err3 = np.abs(z3 - zr3).sum()
+    _say(f"16384 x 128 {precision}: variant {v | 4} burst of 3, |z - z_oracle|_1 = {err3:.2e}")
+    assert err3 <= tol and not stopped
+    # the changes of sweeps 1 and 2 come back with the burst
+    assert abs(diffs[0] - dr) <= tol and abs(diffs[1] - dr2) <= tol
     if precision == "fp64":
         r = s.residual(x)
         rr = dense.residual_1(g.blocks, g.sizes, g.b, x)
         _say(f"16384 x 128 residual {r:.6e} vs oracle {rr:.6e}")
         assert abs(r - rr) <= 1e-12 * max(1.0, rr)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_qbd_4096x64_converged(precision):
+    """The 4096 x 64 QBD solved to ||Q^T pi||_1 <= 1e-12 as the benchmark's
+    time-to-residual runs it, against the oracle's direct solution."""
+    from paper_2302_07551_amd import Solver, stc
+    g = synth.qbd(4096, 64, synth.config_seed(1))
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    s = Solver(g.blocks, g.sizes, g.b, precision=precision, stop="residual", check_every=50,
+               switch_tol=1e-6)
+    stc.stc_autotune(s.h, 5)
+    pi, info = s.solve(tol=1e-12, maxit=200000, allow_maxit=False)
+    err = np.abs(pi - ref).sum()
+    _say(f"4096 x 64 {precision}: sweeps {info['iters']} (fp32 {info['iters_fp32']}), "
+         f"residual {info['residual_1']:.2e}, |pi - pi_ref|_1 = {err:.2e}")
+    assert err <= 1e-10 and info["residual_1"] <= 1e-12
+    if precision == "mixed":
+        assert 0 < info["iters_fp32"] < info["iters"]
     s.close()
 
 

@@ -1,11 +1,14 @@
 """GPU parity of the staircase-preconditioned GMRES (stc_solve_gmres) against
 the oracle's restarted GMRES (oracle/krylov.py) and the direct solvers.
 
-One cycle from the same start gives the same iterate as the oracle's cycle
-to 1e-10 in the 1-norm (the same Krylov step in exact arithmetic; the GPU
-orthogonalises by classical Gram-Schmidt twice, the oracle by modified
+With krylov_keep_all (every cycle kept, no safeguard) one cycle from the
+same start gives the oracle's cycle to 1e-10 in the 1-norm, and three
+cycles the oracle's three (the same Krylov steps in exact arithmetic; the
+GPU orthogonalises by classical Gram-Schmidt twice, the oracle by modified
 Gram-Schmidt).  Converged vectors (||Q^T pi||_1 <= 1e-13) agree with GTH or
-level reduction to 1e-10.
+level reduction to 1e-10.  The safeguard, the product's own rule for
+rejecting stalled cycles, is tested as behaviour: a drifting QBD converges
+at the stationary pace, and a chain without drift keeps every cycle.
 """
 import numpy as np
 import pytest
@@ -73,21 +76,40 @@ def test_gmres_converges_to_the_direct_solution(name, make, fmt, stair_type):
 
 @pytest.mark.parametrize("name,make,fmt", CHAINS, ids=[c[0] for c in CHAINS])
 def test_one_cycle_matches_the_oracle(name, make, fmt):
+    """Every cycle kept: one cycle's iterate and change against the oracle's
+    cycle, element by element."""
     from paper_2302_07551_amd import stc
     g = make()
     r = 12
-    s = _solver(g, fmt, krylov_restart=r)
+    s = _solver(g, fmt, krylov_restart=r, krylov_keep_all=True)
     x0 = np.random.default_rng(7).uniform(0.5, 1.5, g.N)
     pi, info = s.solve_gmres(x0, tol=0.0, restart=r, max_applies=r + 1)
     assert info["status"] == stc.STC_EMAXIT and info["iters"] == r + 1
-    # the oracle's safeguarded solve with the same budget: one cycle, kept if
-    # it halves the residual (no budget is left for plain steps otherwise)
-    want = krylov.gmres_solve(_system(g, fmt), restart=r, tol=0.0, maxit=r + 1, x0=x0)
-    assert want.applies == r + 1
-    assert np.abs(pi - want.x).sum() <= 1e-10
-    cyc, _, _ = krylov.gmres_cycle(_system(g, fmt), x0 / x0.sum(), r)
-    if np.abs(want.x - cyc).sum() <= 1e-10:    # the cycle was kept
-        assert abs(info["diff_1"] - np.abs(cyc - x0 / x0.sum()).sum()) <= 1e-10
+    x0n = x0 / x0.sum()
+    cyc, applies, _ = krylov.gmres_cycle(_system(g, fmt), x0n, r)
+    err = np.abs(pi - cyc).sum()
+    _say(f"one cycle {name}: |pi - oracle cycle|_1 = {err:.2e}")
+    assert applies == r + 1 and err <= 1e-10
+    assert abs(info["diff_1"] - np.abs(cyc - x0n).sum()) <= 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("name,make,fmt", [CHAINS[0], CHAINS[2], CHAINS[4]],
+                         ids=[CHAINS[k][0] for k in (0, 2, 4)])
+def test_three_cycles_match_restarted_gmres(name, make, fmt):
+    """Every cycle kept: three restarted cycles against the oracle's plain
+    restarted GMRES with the same budget."""
+    g = make()
+    r = 10
+    s = _solver(g, fmt, krylov_restart=r, krylov_keep_all=True)
+    x0 = np.random.default_rng(8).uniform(0.5, 1.5, g.N)
+    pi, info = s.solve_gmres(x0, tol=0.0, restart=r, max_applies=3 * (r + 1))
+    want = krylov.gmres_solve(_system(g, fmt), restart=r, tol=0.0, maxit=3 * (r + 1), x0=x0)
+    err = np.abs(pi - want.x).sum()
+    _say(f"three cycles {name}: |pi - oracle|_1 = {err:.2e}, residual {info['residual_1']:.2e}")
+    assert want.cycles == 3 and info["iters"] == want.applies == 3 * (r + 1)
+    assert err <= 1e-10
+    assert abs(info["residual_1"] - want.residual) <= 1e-12 + 1e-8 * want.residual
     s.close()
 
 
@@ -204,17 +226,35 @@ def test_gmres_from_the_solution_and_with_an_unreachable_tol():
 def test_one_cycle_with_unrolled_dot_chunks():
     """A padded vector of 2100 x 64 = 134400 entries gives each of the dot
     kernel's 128 chunks 1050 entries: four terms per thread through the
-    unrolled loop and a tail of one for the first 26 threads.  One cycle
-    against the oracle's cycle."""
+    unrolled loop and a tail of one for the first 26 threads.  One cycle,
+    kept whatever it does, against the oracle's cycle."""
     from paper_2302_07551_amd import stc
     g = synth.qbd(2100, 64, 13)
     r = 8
-    s = _solver(g, "dense", krylov_restart=r)
+    s = _solver(g, "dense", krylov_restart=r, krylov_keep_all=True)
     x0 = np.random.default_rng(11).uniform(0.5, 1.5, g.N)
     pi, info = s.solve_gmres(x0, tol=0.0, restart=r, max_applies=r + 1)
     assert info["status"] == stc.STC_EMAXIT and info["iters"] == r + 1
-    want = krylov.gmres_solve(_system(g, "dense"), restart=r, tol=0.0, maxit=r + 1, x0=x0)
-    err = np.abs(pi - want.x).sum()
-    _say(f"2100 x 64 cycle: |pi - oracle|_1 = {err:.2e}")
-    assert want.applies == r + 1 and err <= 1e-10
+    x0n = x0 / x0.sum()
+    cyc, applies, _ = krylov.gmres_cycle(_system(g, "dense"), x0n, r)
+    err = np.abs(pi - cyc).sum()
+    _say(f"2100 x 64 cycle: |pi - oracle cycle|_1 = {err:.2e}")
+    assert applies == r + 1 and err <= 1e-10
+    assert abs(info["diff_1"] - np.abs(cyc - x0n).sum()) <= 1e-10
     s.close()
+
+
+def test_safeguard_keeps_every_cycle_without_drift():
+    """On a chain without drift every cycle beats the plain rate, so the
+    safeguarded solve takes the same path as the one that keeps every cycle:
+    the same applications and bitwise the same vector."""
+    g = synth.banded(64, 16, 5, b=2, density=0.3)
+    out = []
+    for keep_all in (False, True):
+        s = _solver(g, "dense", krylov_restart=30, krylov_keep_all=keep_all)
+        out.append(s.solve_gmres(tol=1e-12, restart=30))
+        s.close()
+    (p0, i0), (p1, i1) = out
+    _say(f"no drift: applies {i0['iters']} (every cycle kept: {i1['iters']})")
+    assert i0["status"] == 0 and i0["iters"] == i1["iters"]
+    assert np.array_equal(p0, p1)

@@ -260,6 +260,32 @@ def test_reduced_precision_solve(precision):
         assert info["iters_fp32"] == info["iters"]
 
 
+@pytest.mark.parametrize("tol", [1e-5, 1e-6, 1e-9])
+def test_mixed_switch_inside_a_burst_equals_one_sweep_bursts(tol):
+    """The FP32 stage's device test fires two sweeps after the change it
+    tests, and the sweeps queued behind it in a burst overwrite older FP32
+    buffers before the switch.  The FP64 stage must not test changes read
+    from them.  A solve with bursts of 50 sweeps gives bitwise the result of
+    bursts of one sweep (where nothing runs past the stop), with at least one
+    FP64 sweep after the switch, also when tol >= switch_tol."""
+    g = synth.qbd(48, 16, 61)
+    out = []
+    for ce in (1, 50):
+        s = _solver(g, precision="mixed", stop="diff", check_every=ce, switch_tol=1e-6)
+        out.append(s.solve(tol=tol, maxit=50000, allow_maxit=False))
+        s.close()
+    (p1, i1), (p50, i50) = out
+    _say(f"mixed tol {tol}: iters {i50['iters']} fp32 {i50['iters_fp32']} "
+         f"(bursts of one: {i1['iters']} / {i1['iters_fp32']})")
+    assert i50["iters"] > i50["iters_fp32"] > 0
+    assert (i50["iters"], i50["iters_fp32"]) == (i1["iters"], i1["iters_fp32"])
+    assert np.array_equal(p1, p50)
+    assert i50["diff_1"] <= tol
+    # pi is the oracle's iterate of that sweep, up to the FP32 stage's rounding
+    o = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=0.0, maxit=i50["iters"])
+    assert np.abs(p50 - o.x).sum() <= 1e-5
+
+
 def test_residual_matches_oracle():
     g = synth.banded(12, 32, 71, b=2, last=20)
     x = np.random.default_rng(3).standard_normal(g.N)

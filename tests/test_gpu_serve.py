@@ -66,3 +66,33 @@ def test_oversized_request_is_rejected():
     stats = srv.run(reqs)
     srv.close()
     assert sorted(stats.rejected) == [0, 1, 2] and not stats.results
+
+
+def test_failed_setup_and_sweep_cap_retire_only_their_request():
+    """A request that is not a generator is rejected with its setup error,
+    and the others are still served.  Under a sweep cap every unfinished
+    request is retired with STC_EMAXIT and its last iterate, which equals the
+    same chain solved alone with maxit at that sweep."""
+    from paper_2302_07551_amd import Solver, stc
+    from paper_2302_07551_amd.serve import Server
+    reqs, gens = _requests(5, 99, rate=1000.0, L_range=(40, 80), m_choices=(16,))
+    bad = reqs[1].blocks.copy()
+    bad[3, 2, 0, 1] = -1.0            # a negative rate: not a generator
+    reqs[1].blocks = bad
+    cap = 60
+    srv = Server(budget_bytes=1 << 30, max_chains=4, sweeps_per_round=10, max_sweeps=cap)
+    stats = srv.run(reqs)
+    srv.close()
+    print(stats.summary(), stats.errors, flush=True)
+    assert stats.rejected == [1] and f"(status {stc.STC_ENOTGEN})" in stats.errors[1]
+    assert sorted(r.rid for r in stats.results) == [0, 2, 3, 4]
+    for r in stats.results:
+        assert r.status == stc.STC_EMAXIT and cap <= r.sweeps < cap + 10
+        g = gens[r.rid]
+        s = Solver(g.blocks, g.sizes, g.b, precision="mixed", switch_tol=1e-6, check_every=10)
+        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
+        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
+        pi, info = s.solve(tol=1e-13, maxit=r.sweeps)
+        s.close()
+        assert info["status"] == stc.STC_EMAXIT and info["iters"] == r.sweeps
+        assert r.sweeps_fp32 == info["iters_fp32"] and np.array_equal(r.pi, pi), r.rid

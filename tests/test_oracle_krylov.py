@@ -6,7 +6,10 @@
   * GMRES with a restart longer than N reaches the null vector in one cycle
     (the Krylov space is then all of R^N), and its least-squares residual
     estimates never rise inside a cycle (the minimal-residual property);
-  * a planted sign slip in the cycle's first residual makes it fail.
+  * a planted sign slip in the cycle's first residual makes it fail;
+  * without drift it needs far fewer applications than sweeps.
+The oracle is plain restarted GMRES; the product's rule for rejecting
+stalled cycles is tested on the GPU as product behaviour.
 """
 import numpy as np
 import pytest
@@ -84,30 +87,13 @@ def test_sign_slip_in_the_first_residual_is_caught(monkeypatch):
     assert np.abs(good - pi).sum() < 0.1 * np.abs(x - pi).sum()
 
 
-def test_safeguard_keeps_drifting_chains_at_the_stationary_pace():
-    """On a QBD with drift, short GMRES cycles stall; the safeguard falls back
-    to plain applications of T, so the solve still converges to the direct
-    solution in about as many applications as the stationary iteration."""
-    g = synth.qbd(256, 16, 11)
-    sys = staircase.BlockSystem(g.blocks, g.sizes, g.b)
-    stat = staircase.solve_system(sys, tol=1e-12, maxit=100_000, stop=staircase.STOP_RESIDUAL)
-    r = krylov.gmres_solve(sys, restart=30, tol=1e-12, maxit=20_000)
-    assert r.converged
-    assert r.applies <= 1.5 * stat.iters
-    pi = dense_pi(g)
-    assert np.abs(r.x - pi).sum() < 1e-10
-
-
-def dense_pi(g):
-    from oracle import level_reduction
-    return level_reduction.level_reduction(g.blocks, g.sizes, g.b)
-
-
-def test_safeguard_keeps_gmres_where_it_helps():
-    """On a chain without drift GMRES cycles beat the plain rate and are all
-    kept: far fewer applications than stationary sweeps."""
+def test_restarted_gmres_beats_the_stationary_sweeps_without_drift():
+    """On a chain without drift restarted GMRES needs far fewer applications
+    of T than the stationary iteration needs sweeps, and every cycle lowers
+    the residual (the Krylov step of each cycle is the minimal-residual one)."""
     g = _banded()
     sys = staircase.BlockSystem(g.blocks, g.sizes, g.b)
     stat = staircase.solve_system(sys, tol=1e-12, maxit=200_000, stop=staircase.STOP_RESIDUAL)
     r = krylov.gmres_solve(sys, restart=30, tol=1e-12, maxit=20_000)
     assert r.converged and r.applies * 5 < stat.iters
+    assert all(b < a for a, b in zip(r.history, r.history[1:]))

@@ -324,22 +324,3 @@ def test_skip_free_direct_solvers_agree_and_staircase_converges(b):
     assert np.abs(level_reduction.level_reduction(g.blocks, g.sizes, g.b) - ref).sum() < 1e-13
     r = staircase.staircase_solve(g.blocks, g.sizes, g.b, tol=1e-15, maxit=50000)
     assert np.abs(r.x - ref).sum() < 1e-12
-
-
-def test_windowed_stair_apply_equals_the_whole_sweep():
-    """The sampled outputs the full-size GPU tests use: stair_apply over
-    windows of levels equals stair_apply over the whole chain at each
-    window's interior levels (and at the chain's own ends)."""
-    from window_oracle import sampled_stair_apply
-    g = synth.qbd(203, 8, 41, last=5)
-    x = synth.positive_start(g, 3)
-    full = staircase.stair_apply(staircase.BlockSystem(g.blocks, g.sizes, g.b), x, 1)
-    idx, u = sampled_stair_apply(g, x, width=12, count=9)
-    assert idx[0] == 0 and idx[-1] == g.N - 1
-    assert idx.size > 9 * 6 * 8
-    assert np.array_equal(u, full[idx])
-    # a window whose interior reaches the edge level is wrong there
-    sys_w = staircase.BlockSystem(g.blocks[40:52], g.sizes[40:52], g.b)
-    off = np.concatenate([[0], np.cumsum(g.sizes)])
-    uw = staircase.stair_apply(sys_w, x[off[40]:off[52]], 1)
-    assert not np.allclose(uw[:8], full[off[40]:off[41]])
