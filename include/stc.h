@@ -218,6 +218,27 @@ stc_status stc_step(stc_handle *h, const double *x, double *z, double *diff_1, i
 /* ||Q^T x||_1 in FP64 (eq. (1)), x as given (not normalised). */
 stc_status stc_residual(stc_handle *h, const double *x, double *res_1, int32_t where);
 
+/* Bytes of the static staging array of stc_residual_noalloc on each GPU. */
+#define STC_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * residual of stc_residual, with the same value bit for bit, that allocates
+ * nothing.  x: device memory, N FP64 (compact, as given, not normalised);
+ * res_1: device memory, one FP64, written by the last kernel.  The calls are
+ * enqueued on the handle's stream with no synchronisation and no host copy;
+ * the handle's device must be current.  The padded copy of x and the
+ * per-group partial sums are staged in a static device array of
+ * STC_NOALLOC_SCRATCH_BYTES on each GPU (held until the process ends), which
+ * every call on that GPU shares: calls that overlap on one GPU (other streams
+ * or threads) race.  Every staged byte is written before it is read, so
+ * nothing needs clearing between calls.  Also records e^T x in the handle's
+ * state, as stc_residual does.  Returns STC_EINVAL for a null argument, a
+ * device other than the handle's, or a handle whose staging (8 L m_pad bytes
+ * plus its partial sums, m_pad the padded block size) exceeds the array;
+ * STC_EDEVICE if a launch fails. */
+stc_status stc_residual_noalloc(stc_handle *h, const double *x, double *res_1);
+
 /* Device-resident sweeps: run nsweeps sweeps of Algorithm 2 on the handle's
  * current iterate without host synchronisation (the iterate is the one left by
  * the previous stc_solve / stc_step / stc_load on this handle).  diffs (host,

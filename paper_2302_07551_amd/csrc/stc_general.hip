@@ -325,14 +325,14 @@ static hipError_t residual_gen_t(int MP, int groups, const double *diag, const G
 hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
                                const GenEntry *tab, const double *val64, const int *idx,
                                const void *w, int L, DevState *st, long long slot, double *part,
-                               hipStream_t stream) {
+                               hipStream_t stream, double *out) {
     const int groups = reduce_groups(MP, L);
     const hipError_t e =
         precision_bytes == 8
             ? residual_gen_t<double>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream)
             : residual_gen_t<float>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream);
     if (e != hipSuccess) return e;
-    return launch_reduce_residual(part, groups, st, stream);
+    return launch_reduce_residual(part, groups, st, stream, out);
 }
 
 }  // namespace stc

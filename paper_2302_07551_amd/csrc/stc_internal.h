@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/stc.h"
+
 namespace stc {
 
 // Device-side solver state of one chain (lives in the arena).
@@ -195,7 +197,7 @@ hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, boo
 hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
                                const GenEntry *tab, const double *val64, const int *idx,
                                const void *w, int L, DevState *st, long long slot, double *part,
-                               hipStream_t stream);
+                               hipStream_t stream, double *out = nullptr);
 // Most blocks of a persistent sweep kernel that can be resident at once
 // (0 if the variant has no persistent form for these sizes).
 int flow_resident_blocks(int precision_bytes, int MP, int b, int variant);
@@ -213,9 +215,11 @@ hipError_t launch_load(int precision_bytes, int MP, const double *x, const long 
 hipError_t launch_store(int precision_bytes, int MP, const void *w, const long long *off,
                         const int *sizes, int L, DevState *st, long long slot, double *x,
                         hipStream_t stream);
+// ||Q^T w||_1 into DevState::residual, or into *out (device) when out is set.
 hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
                            const double *diag64, const void *w, int L, DevState *st,
-                           long long slot, double *part, hipStream_t stream);
+                           long long slot, double *part, hipStream_t stream,
+                           double *out = nullptr);
 // Krylov acceleration (stc_krylov.hip): vectors are FP64 padded [L][MP].
 constexpr int kDotGroups = 128;     // chunks of a vector per partial dot
 constexpr int kMaxRestart = 256;    // largest GMRES restart length
@@ -233,8 +237,9 @@ hipError_t launch_kaxpby(double a, const double *x, double b, const double *y, d
 // out = x / sdev[0]
 hipError_t launch_kscale(const double *x, const double *sdev, double *out, size_t n,
                          hipStream_t s);
-// Sum the per-group residual partials into DevState::residual.
-hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream);
+// Sum the per-group residual partials into DevState::residual (or *out).
+hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream,
+                                  double *out = nullptr);
 hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
                        const void *w_prev, int L, int parity_a, DevState *st, long long k,
                        double *part, hipStream_t stream, double tol);
@@ -248,5 +253,14 @@ hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, 
 hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
                                  hipStream_t stream);
 int reduce_groups(int MP, int L);
+
+// Residual with caller-given device staging (stc_runtime.cpp), for the
+// allocation-free entry point: bytes of staging the handle needs, the
+// residual of x (device, compact) into out (device) on the handle's stream,
+// and the library's error report (message for stc_last_error).
+size_t residual_staging_bytes(const stc_handle *h);
+stc_status residual_into(stc_handle *h, const double *x, double *out, int device, char *staging,
+                         size_t staging_bytes);
+stc_status report_error(stc_status s, const char *msg);
 
 }  // namespace stc

@@ -69,8 +69,11 @@ __global__ void k_rearm(DevState *st, long long k) {
 
 
 
+// mode kReduceResidual writes the sum to *out, or to DevState::residual when
+// out is null.
 __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int mode,
-                                                 DevState *st, long long slot, double tol) {
+                                                 DevState *st, long long slot, double tol,
+                                                 double *out) {
     __shared__ double sh[4 * kWG / 64];
     const int stride = (mode == kReduceLoad) ? 2 : 1;
     double t = 0.0, tc = 0.0, b = 0.0;
@@ -82,7 +85,10 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double *part, int n, int m
     if (mode == kReduceLoad) b = block_max(b, sh);
     if (threadIdx.x != 0) return;
     if (mode == kReduceResidual) {
-        st->residual = t;
+        if (out)
+            *out = t;
+        else
+            st->residual = t;
     } else if (mode == kReduceDiff) {
         // the change of sweep slot, with the device stopping test
         if (st->stop_flag || slot <= st->test_after) return;
@@ -309,13 +315,15 @@ hipError_t launch_finalize_sweep(const double *part_sum, const double *part_diff
 }
 
 static hipError_t reduce(const double *part, int n, int mode, DevState *st, long long slot,
-                         hipStream_t stream, double tol = 0.0) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, stream, part, n, mode, st, slot, tol);
+                         hipStream_t stream, double tol = 0.0, double *out = nullptr) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kWG), 0, stream, part, n, mode, st, slot, tol,
+                       out);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream) {
-    return reduce(part, n, kReduceResidual, st, 0, stream);
+hipError_t launch_reduce_residual(const double *part, int n, DevState *st, hipStream_t stream,
+                                  double *out) {
+    return reduce(part, n, kReduceResidual, st, 0, stream, 0.0, out);
 }
 
 // load/diff use at most this many groups, so their partial arrays stay small
@@ -403,7 +411,8 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
 
 template <typename T, int B>
 static hipError_t residual_b(int MP, const double *blk, const double *diag, const void *w,
-                             int L, DevState *st, long long slot, double *part, hipStream_t s) {
+                             int L, DevState *st, long long slot, double *part, hipStream_t s,
+                             double *out) {
     const int groups = reduce_groups(MP, L);
     const T *wt = (const T *)w;
     switch (MP) {
@@ -432,22 +441,22 @@ static hipError_t residual_b(int MP, const double *blk, const double *diag, cons
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return reduce(part, groups, kReduceResidual, st, 0, s);
+    return reduce(part, groups, kReduceResidual, st, 0, s, 0.0, out);
 }
 
 hipError_t launch_residual(int precision_bytes, int MP, int b, const double *blk64,
                            const double *diag64, const void *w, int L, DevState *st,
-                           long long slot, double *part, hipStream_t stream) {
+                           long long slot, double *part, hipStream_t stream, double *out) {
     const bool f64 = precision_bytes == 8;
     switch (b) {
-        case 1: return f64 ? residual_b<double, 1>(MP, blk64, diag64, w, L, st, slot, part, stream)
-                           : residual_b<float, 1>(MP, blk64, diag64, w, L, st, slot, part, stream);
-        case 2: return f64 ? residual_b<double, 2>(MP, blk64, diag64, w, L, st, slot, part, stream)
-                           : residual_b<float, 2>(MP, blk64, diag64, w, L, st, slot, part, stream);
-        case 3: return f64 ? residual_b<double, 3>(MP, blk64, diag64, w, L, st, slot, part, stream)
-                           : residual_b<float, 3>(MP, blk64, diag64, w, L, st, slot, part, stream);
-        case 4: return f64 ? residual_b<double, 4>(MP, blk64, diag64, w, L, st, slot, part, stream)
-                           : residual_b<float, 4>(MP, blk64, diag64, w, L, st, slot, part, stream);
+        case 1: return f64 ? residual_b<double, 1>(MP, blk64, diag64, w, L, st, slot, part, stream, out)
+                           : residual_b<float, 1>(MP, blk64, diag64, w, L, st, slot, part, stream, out);
+        case 2: return f64 ? residual_b<double, 2>(MP, blk64, diag64, w, L, st, slot, part, stream, out)
+                           : residual_b<float, 2>(MP, blk64, diag64, w, L, st, slot, part, stream, out);
+        case 3: return f64 ? residual_b<double, 3>(MP, blk64, diag64, w, L, st, slot, part, stream, out)
+                           : residual_b<float, 3>(MP, blk64, diag64, w, L, st, slot, part, stream, out);
+        case 4: return f64 ? residual_b<double, 4>(MP, blk64, diag64, w, L, st, slot, part, stream, out)
+                           : residual_b<float, 4>(MP, blk64, diag64, w, L, st, slot, part, stream, out);
     }
     return hipErrorInvalidValue;
 }

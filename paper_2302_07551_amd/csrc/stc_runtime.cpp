@@ -674,13 +674,16 @@ stc_status load_vector(stc_handle *h, const double *x, int32_t where) {
 }
 
 // ||Q^T x||_1 of the padded iterate w (scaled by inv_sigma[slot]; slot < 0:
-// as given) into DevState::residual.
-hipError_t enqueue_residual(stc_handle *h, bool f32, const void *w, long long slot) {
+// as given) into DevState::residual, or into *out (device) when out is set.
+// The per-group partials go to part (the handle's own by default).
+hipError_t enqueue_residual(stc_handle *h, bool f32, const void *w, long long slot,
+                            double *part = nullptr, double *out = nullptr) {
+    if (!part) part = h->part_aux;
     if (h->general)
         return launch_residual_gen(f32 ? 4 : 8, h->MP, h->diag64, h->gen_tab, h->gen_v64,
-                                   h->gen_idx, w, h->L, h->st, slot, h->part_aux, h->stream);
+                                   h->gen_idx, w, h->L, h->st, slot, part, h->stream, out);
     return launch_residual(f32 ? 4 : 8, h->MP, h->b, h->blk64, h->diag64, w, h->L, h->st, slot,
-                           h->part_aux, h->stream);
+                           part, h->stream, out);
 }
 
 // T v = M^{-1} N v (the stair splitting's iteration operator, without
@@ -978,6 +981,44 @@ stc_status pack_general(stc_handle *h, const stc_generator *g) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// the residual with caller-given staging (the allocation-free entry point in
+// stc_noalloc.hip passes its static array)
+// ---------------------------------------------------------------------------
+namespace stc {
+
+// Padded FP64 copy of x (L x MP) and the partials of the load and residual
+// kernels, as the handle's own residual uses them.
+size_t residual_staging_bytes(const stc_handle *h) {
+    const size_t naux = std::max<size_t>(2 * 1024 + 8, (size_t)h->L + 8);
+    return align_up((size_t)h->L * h->MP * sizeof(double)) + naux * sizeof(double);
+}
+
+stc_status residual_into(stc_handle *h, const double *x, double *out, int device, char *staging,
+                         size_t staging_bytes) {
+    if (!h || !x || !out) return fail(STC_EINVAL, "null argument");
+    if (device != h->device)
+        return fail(STC_EINVAL, "the current device (%d) is not the handle's (%d)", device,
+                    h->device);
+    const size_t need = residual_staging_bytes(h);
+    if (need > staging_bytes)
+        return fail(STC_EINVAL, "this handle's residual stages %zu bytes (its padded vector "
+                                "of %d x %d and the partial sums), above the allocation-free "
+                                "limit of %zu bytes", need, h->L, h->MP, staging_bytes);
+    double *w = reinterpret_cast<double *>(staging);
+    double *aux = reinterpret_cast<double *>(staging + align_up((size_t)h->L * h->MP * sizeof(double)));
+    const int naux = (int)((need - align_up((size_t)h->L * h->MP * sizeof(double))) / sizeof(double));
+    // the same kernels and grids as stc_residual, so the same value bit for bit
+    HIP_TRY(launch_load(8, h->MP, x, h->off, h->sizes_d, h->L, w, aux, naux, h->st, -1,
+                        h->stream));
+    HIP_TRY(enqueue_residual(h, false, w, -1, aux, out));
+    return STC_OK;
+}
+
+stc_status report_error(stc_status s, const char *msg) { return fail(s, "%s", msg); }
+
+}  // namespace stc
 
 // ---------------------------------------------------------------------------
 // C ABI

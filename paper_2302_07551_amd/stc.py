@@ -34,7 +34,7 @@ STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
 
 # every symbol include/stc.h declares
 EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_solve_gmres", "stc_step",
-           "stc_residual",
+           "stc_residual", "stc_residual_noalloc",
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
            "stc_store", "stc_promote", "stc_batch_footprint", "stc_batch_create",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
                                     POINTER(stc_result), c_int32]
     lib.stc_step.argtypes = [H, c_void_p, c_void_p, dp, c_int32]
     lib.stc_residual.argtypes = [H, c_void_p, dp, c_int32]
+    lib.stc_residual_noalloc.argtypes = [H, c_void_p, c_void_p]
     lib.stc_sweeps.argtypes = [H, c_int64, c_void_p]
     lib.stc_profile_sweeps.argtypes = [H, c_int64, dp, dp, dp, dp]
     lib.stc_variant_count.argtypes = []
@@ -265,6 +266,13 @@ def stc_residual(h, x) -> float:
     r = c_double()
     _check(load_library().stc_residual(h, px, byref(r), w))
     return r.value
+
+
+def stc_residual_noalloc(h, x, res):
+    """x: CUDA tensor of N FP64; res: CUDA tensor with room for one FP64
+    (written asynchronously on the handle's stream)."""
+    _check(load_library().stc_residual_noalloc(h, c_void_p(x.data_ptr()),
+                                               c_void_p(res.data_ptr())))
 
 
 def stc_sweeps(h, nsweeps: int, diffs: np.ndarray | None = None):
