@@ -52,6 +52,13 @@ Other workloads (each prints its own JSON line instead):
                   2048 x 128 banded generator and the mutual-exclusion model
   --launch-sizes  the dense sweep kernel's phase-A rate on QBDs with about 41 MB
                   and 200 MB per launch, at block sizes 128 and 64
+  --jgs           the paper's comparison: sweep times of the stair splittings,
+                  block Gauss-Seidel, JGS (Algorithm 1) and block Jacobi on the
+                  4096 x 64 QBD and the banded generator, and their time to
+                  ||Q^T pi||_1 <= 1e-12 on a 1024 x 64 QBD
+  --batch-rates   the batched kernel's GB/s per block size (8, 16, 32, 64; about
+                  1 GB per sweep; FP32 and FP64) and on 60 served requests,
+                  with the untuned launch shape and after stc_batch_autotune
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -183,6 +190,8 @@ def main():
     ap.add_argument("--example3", type=int, default=0)
     ap.add_argument("--krylov", action="store_true")
     ap.add_argument("--launch-sizes", action="store_true")
+    ap.add_argument("--batch-rates", action="store_true")
+    ap.add_argument("--jgs", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
@@ -214,6 +223,10 @@ def main():
         return krylov_mode(args)
     if args.launch_sizes:
         return launch_sizes_mode()
+    if args.batch_rates:
+        return batch_rates_mode()
+    if args.jgs:
+        return jgs_mode()
 
     return headline_mode(args)
 
@@ -385,6 +398,30 @@ def _one_blas_thread():
         os.environ[k] = "1"
 
 
+def _serve_probes(specs, gens, per_size=6):
+    """Probe chains for the batch's launch autotuner: the first requests of
+    each block size in the stream."""
+    from paper_2302_07551_amd.serve import Request
+    probes, per_m = [], {}
+    for k, sp in enumerate(specs):
+        if per_m.get(sp["m"], 0) < per_size:
+            per_m[sp["m"]] = per_m.get(sp["m"], 0) + 1
+            probes.append(Request(k, 0.0, gens[k].blocks, gens[k].sizes, gens[k].b))
+    return probes
+
+
+def _tune_server(srv, probes):
+    """Tune the server's batched launch on the probes (before a run, outside
+    its clock); the shapes it kept, per stage and block size."""
+    t0 = time.perf_counter()
+    ms = srv.autotune(probes, trial_sweeps=10)
+    out = {"probe_ms_per_sweep": round(ms, 4), "tuning_s": round(time.perf_counter() - t0, 2)}
+    for name, stage in (("fp32", 1), ("fp64", 0)):
+        for mp in (8, 16, 32, 64):
+            out[f"{name}_m{mp}"] = srv.batch.tile(stage, mp)
+    return out
+
+
 def served_stream_figures(n=512, budget_gb=4.0, with_refs=True):
     """The served stream of n QBD requests (levels U{32..2048}, m in
     {8, 16, 32, 64}), mixed precision, 4 GiB admission budget: a saturated
@@ -404,11 +441,15 @@ def served_stream_figures(n=512, budget_gb=4.0, with_refs=True):
     budget = int(budget_gb * (1 << 30))
     unit_gaps = np.array([sp["arrival"] for sp in specs])   # Poisson, rate 1
 
+    probes = _serve_probes(specs, gens)
+    tiles = {}
+
     def run(rate):
         arr = np.zeros(n) if rate is None else unit_gaps / rate
         reqs = [Request(k, float(arr[k]), g.blocks, g.sizes, g.b) for k, g in enumerate(gens)]
         srv = Server(budget, max_chains=256, sweeps_per_round=25, tol=1e-13, switch_tol=1e-6,
                      precision="mixed")
+        tiles.update(_tune_server(srv, probes))
         st = srv.run(reqs)
         srv.close()
         summ = st.summary()
@@ -424,13 +465,15 @@ def served_stream_figures(n=512, budget_gb=4.0, with_refs=True):
            "p50_latency_s": round(p_summ["p50_latency_s"], 4),
            "p99_latency_s": round(p_summ["p99_latency_s"], 4),
            "arrival_rate_per_s": round(p_summ["rate_per_s"], 2),
-           "saturated": sat_summ, "poisson_0.8x": p_summ}
-    del gens
+           "saturated": sat_summ, "poisson_0.8x": p_summ, "batch_tiles": tiles}
+    del gens, probes
     if with_refs:
         t0 = time.perf_counter()
         workers = max(1, min(16, len(os.sched_getaffinity(0))) - 1)
-        with mp.get_context("spawn").Pool(workers, initializer=_one_blas_thread) as pool:
-            refs = pool.map(_served_reference, specs, chunksize=4)
+        pool = mp.get_context("spawn").Pool(workers, initializer=_one_blas_thread)
+        refs = pool.map(_served_reference, specs, chunksize=4)
+        pool.close()       # the workers exit on their own (no terminate)
+        pool.join()
         errs = []
         for st in (sat, poisson):
             for r in st.results:
@@ -562,13 +605,35 @@ def banded_mode(L=2048, m=128, no_cpu=False):
             r["sweeps_per_s"] = round(1e3 / r["ms_per_sweep"], 1)
             runs[f"{fmt}_{prec}"] = r
             print(f"# {fmt} {prec}: {r}", file=sys.stderr, flush=True)
+    # the survey's algorithmic bytes of a sweep with the off-diagonal blocks
+    # in CSR (value + 4-byte column index per nonzero, m + 1 row pointers per
+    # block): every inverse block, every nonzero, the vector read and written
+    import numpy as np
+    NB = 2 * gen.b + 1
+    offd = np.ones(NB, dtype=bool)
+    offd[gen.b] = False
+    nnz = int(np.count_nonzero(gen.blocks[:, offd]))
+    nblk = sum(1 for i in range(L) for d in range(-gen.b, gen.b + 1)
+               if d != 0 and 0 <= i + d < L)
+    w = float(np.sum(gen.sizes.astype(np.float64) ** 2))
+    for fmt in ("sparse",):
+        for prec, sv in (("fp64", 8), ("fp32", 4)):
+            r = runs[f"{fmt}_{prec}"]
+            csr = sv * w + (sv + 4) * nnz + 4 * (m + 1) * nblk + 2 * sv * gen.N
+            r["csr_bytes_per_sweep"] = csr
+            r["GB/s_csr"] = round(csr / (r["ms_per_sweep"] * 1e-3) / 1e9, 1)
     ingest = banded_ingest(gen)
+    sp = runs["sparse_fp64"]
     line = {"metric": "sweeps/s on the banded generator (dense vs sparse blocks)",
             "value": runs["sparse_fp64"]["sweeps_per_s"], "unit": "sweeps/s",
             "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"banded_b2_L{L}_m{m}_d0.1", "levels": L, "block": m,
                        "N": L * m, "seed": synth.config_seed(2)},
-            "runs": runs, "ingest": ingest,
+            "runs": runs, "ingest": ingest, "nnz_off_diagonal": nnz,
+            "roofline": {"bound": "hbm", "kernel": "sparse sweep, FP64, on CSR bytes",
+                         "achieved": sp["GB/s_csr"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(sp["GB/s_csr"] / HBM_PEAK_GBS, 4),
+                         "stored_GB/s": sp["GB/s"]},
             "speedup_sparse_vs_dense_fp64": round(runs["dense_fp64"]["ms_per_sweep"] /
                                                  runs["sparse_fp64"]["ms_per_sweep"], 3)}
     if not no_cpu:
@@ -879,6 +944,149 @@ def launch_sizes_mode():
                       "launches": rows}), flush=True)
 
 
+def _batch_rate(batch, solvers, steps=30):
+    """ms per sweep and algorithmic GB/s of the batch over steps graph-replayed
+    sweeps of its chains from e/N (stopping tests off)."""
+    import torch
+    from paper_2302_07551_amd import stc
+    for s in solvers:
+        s.load(None)
+    batch.set(solvers, tol=0.0, nontemporal=True)
+    nbytes = sum(sum(stc.stc_phase_bytes(s.h)) for s in solvers)
+    batch.sweeps(3)
+    batch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.sweeps(steps)
+    batch.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"ms_per_sweep": round(ms, 4), "GB_per_sweep": round(nbytes / 1e9, 3),
+            "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def batch_rates_mode():
+    """The batched (many-chain) kernel's rate per block size, before and after
+    stc_batch_autotune: batches of chains of one block size with about 1 GB
+    of FP32 blocks per sweep (m = 8: 80 chains of 16384 levels; m = 16: 40
+    of 8192; m = 32: 20 of 4096; m = 64: 10 of 2048), FP32 and FP64; then the
+    first 60 requests of the served stream, FP32."""
+    import torch
+    import synth
+    from paper_2302_07551_amd import Batch, Solver, stc
+    torch.cuda.set_device(0)
+    shapes = {8: (16384, 80), 16: (8192, 40), 32: (4096, 20), 64: (2048, 10)}
+    rows = {}
+    for m, (L, count) in shapes.items():
+        g = synth.qbd(L, m, 4000 + m)
+        for prec in ("fp32", "fp64"):
+            solvers = [Solver(g.blocks, g.sizes, g.b, precision=prec) for _ in range(count)]
+            b = Batch(count, 1 << 20)
+            untuned = _batch_rate(b, solvers)
+            b.set(solvers, tol=0.0, nontemporal=True)
+            b.autotune(10)
+            tuned = _batch_rate(b, solvers)
+            stage = stc.STC_FP32 if prec == "fp32" else stc.STC_FP64
+            key = f"m{m}_{prec}"
+            rows[key] = {"chains": count, "levels": L, "untuned": untuned, "tuned": tuned,
+                         "tile": b.tile(stage, m)}
+            print(f"# {key}: {rows[key]}", file=sys.stderr, flush=True)
+            b.close()
+            for s in solvers:
+                s.close()
+    specs = synth.served_stream(60, synth.config_seed(4), rate=1.0)
+    gens = [synth.qbd(sp["L"], sp["m"], sp["seed"]) for sp in specs]
+    solvers = [Solver(g.blocks, g.sizes, g.b, precision="fp32") for g in gens]
+    b = Batch(64, 1 << 20)
+    untuned = _batch_rate(b, solvers)
+    b.set(solvers, tol=0.0, nontemporal=True)
+    b.autotune(10)
+    tuned = _batch_rate(b, solvers)
+    rows["served_mix_60_fp32"] = {"untuned": untuned, "tuned": tuned,
+                                  "tiles": {mp: b.tile(stc.STC_FP32, mp) for mp in (8, 16, 32, 64)}}
+    print(f"# served mix: {rows['served_mix_60_fp32']}", file=sys.stderr, flush=True)
+    b.close()
+    for s in solvers:
+        s.close()
+    mix = rows["served_mix_60_fp32"]["tuned"]["GB/s"]
+    print(json.dumps({"metric": "batched sweep GB/s by block size, untuned vs autotuned",
+                      "value": mix, "unit": "GB/s", "higher_is_better": True, "n_gpus": 1,
+                      "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "batched QBD chains by block size and the "
+                                             "first 60 served requests"},
+                      "roofline": {"bound": "hbm", "achieved": mix, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(mix / HBM_PEAK_GBS, 4)},
+                      "rates": rows}), flush=True)
+
+
+def _method_solver(gen, method, **kw):
+    """A solver for one of the compared methods: "stair1", "stair2", or
+    "jgs<p>" (Algorithm 1 over p chunks; "jgs1" is block Gauss-Seidel)."""
+    from paper_2302_07551_amd import Solver
+    if method.startswith("stair"):
+        return Solver(gen.blocks, gen.sizes, gen.b, stair_type=int(method[5:]), **kw)
+    return Solver(gen.blocks, gen.sizes, gen.b, method="jgs", jgs_chunks=int(method[3:]), **kw)
+
+
+def jgs_mode():
+    """The paper's comparison (Algorithm 1 against Algorithm 2) on one GPU:
+    FP64 sweep times of the stair splittings (types 1 and 2, autotuned), plain
+    block Gauss-Seidel (one chunk), JGS over 16 and 256 chunks and block
+    Jacobi (one chunk per level) on the 4096 x 64 QBD and the 2048 x 128
+    banded generator; then sweeps and time to ||Q^T pi||_1 <= 1e-12 on a
+    1024 x 64 QBD, with the error against the direct solution."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import level_reduction
+    from paper_2302_07551_amd import stc
+    torch.cuda.set_device(0)
+    out = {"sweep_ms": {}, "to_residual": {}}
+    for name, gen, methods in (
+            ("qbd_L4096_m64", synth.qbd(4096, 64, synth.config_seed(1)),
+             ("stair1", "stair2", "jgs1", "jgs16", "jgs256", "jgs4096")),
+            ("banded_b2_L2048_m128", synth.banded(2048, 128, synth.config_seed(2), b=2,
+                                                  density=0.1, decay=0.5),
+             ("stair1", "stair2", "jgs1", "jgs256", "jgs2048"))):
+        rows = {}
+        for meth in methods:
+            s = _method_solver(gen, meth)
+            stc.stc_autotune(s.h, 3 if meth == "jgs1" else 10)
+            n = 5 if meth == "jgs1" else 50
+            s.load(None)
+            s.sweeps(2)
+            ms_a, _mb, _mf, ms = stc.stc_profile_sweeps(s.h, n)
+            ba, bb = stc.stc_phase_bytes(s.h)
+            rows[meth] = {"ms_per_sweep": round(ms, 4),
+                          "GB/s": round((ba + bb) / (ms * 1e-3) / 1e9, 1)}
+            print(f"# {name} {meth}: {rows[meth]}", file=sys.stderr, flush=True)
+            s.close()
+        out["sweep_ms"][name] = rows
+    g = synth.qbd(1024, 64, synth.config_seed(1))
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    for meth in ("stair1", "stair2", "jgs1", "jgs16", "jgs64"):
+        s = _method_solver(g, meth, stop="residual", check_every=50)
+        stc.stc_autotune(s.h, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pi, info = s.solve(tol=1e-12, maxit=100000)
+        dt = time.perf_counter() - t0
+        out["to_residual"][meth] = {"seconds": round(dt, 4), "sweeps": info["iters"],
+                                    "status": info["status"],
+                                    "err_vs_direct": float(np.abs(pi - ref).sum())}
+        print(f"# qbd_L1024_m64 {meth}: {out['to_residual'][meth]}", file=sys.stderr, flush=True)
+        s.close()
+    tr = out["to_residual"]
+    print(json.dumps({"metric": "time to ||Q^T pi||_1 <= 1e-12: stair splitting vs block "
+                                "Gauss-Seidel and JGS (Algorithm 1)",
+                      "value": tr["stair1"]["seconds"], "unit": "s", "higher_is_better": False,
+                      "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "qbd_L1024_m64 (to residual); qbd_L4096_m64 and "
+                                             "banded_b2_L2048_m128 (sweep times)"},
+                      "speedup_stair1_vs_bgs": round(tr["jgs1"]["seconds"] /
+                                                     tr["stair1"]["seconds"], 2),
+                      **out}), flush=True)
+
+
 def observed_contraction(d, lo=1e-13, hi=1e-6):
     """Geometric mean ratio of successive changes while they fall from hi to
     lo: the contraction factor a run of sweeps shows."""
@@ -1118,11 +1326,14 @@ def serve_mode(args):
     budget = int(args.budget_gb * (1 << 30))
     unit_gaps = np.array([sp["arrival"] for sp in specs])   # Poisson, rate 1
 
+    probes = _serve_probes(specs, gens)
+
     def run(precision, rate):
         arr = np.zeros(n) if rate is None else unit_gaps / rate
         reqs = [Request(k, float(arr[k]), g.blocks, g.sizes, g.b) for k, g in enumerate(gens)]
         srv = Server(budget, max_chains=256, sweeps_per_round=25, tol=1e-13, switch_tol=1e-6,
                      precision=precision)
+        _tune_server(srv, probes)
         st = srv.run(reqs)
         srv.close()
         summ = st.summary()

@@ -61,6 +61,7 @@ enum { STC_STOP_DIFF = 0, STC_STOP_RESIDUAL = 1 };     /* stc_options.stop      
 enum { STC_MEM_HOST = 0, STC_MEM_DEVICE = 1 };         /* "where" arguments     */
 enum { STC_DENSE = 0, STC_SPARSE = 1 };                /* stc_options.format    */
 enum { STC_ANY_PATTERN = -1 };                         /* stc_generator.b       */
+enum { STC_STAIRCASE = 0, STC_JGS = 1 };               /* stc_options.method    */
 
 /* The block generator (section 2 block partition), in one of two host forms.
  *
@@ -138,6 +139,21 @@ typedef struct {
     int32_t krylov_keep_all; /* 0: stc_solve_gmres applies its safeguard (below);
                              1: every cycle is kept (textbook restarted GMRES,
                              no plain steps)                                   */
+    int32_t method;       /* STC_STAIRCASE: the stair splitting (Algorithm 2).
+                             STC_JGS: Algorithm 1 (section 2), the method the
+                             paper compares against: the levels are cut into
+                             jgs_chunks chunks of consecutive levels; a sweep
+                             is block Jacobi across the chunks (a level reads
+                             the previous iterate of every other chunk) and
+                             block Gauss-Seidel inside each (the chunk's
+                             levels in order, each reading the fresh values of
+                             the chunk's earlier levels), then the same
+                             normalisation and change.  jgs_chunks = 1 is
+                             plain block Gauss-Seidel, jgs_chunks = L block
+                             Jacobi.  Dense storage only, no Krylov workspace,
+                             not in batches; stair_type is ignored; every
+                             other call works as for the stair splitting.  */
+    int32_t jgs_chunks;   /* STC_JGS: the number of chunks p, 1..L          */
 } stc_options;
 
 typedef struct {
@@ -273,9 +289,11 @@ stc_status stc_get_variant(stc_handle *h, int32_t stage, int32_t *variant);
 
 /* Autotuner: for each precision stage the handle sweeps in, time every
  * variant over trial_sweeps sweeps of this chain (after 3 warm-up sweeps,
- * from e/N) and keep the fastest.  Returns the best mean sweep times (ms, may
- * be NULL).  It moves the handle's iterate: the handle is left loaded with
- * e/N, so call it before stc_load / stc_sweeps (stc_solve reloads anyway). */
+ * from e/N) and keep the fastest; a persistent variant is kept only if it
+ * beats the fastest per-phase variant by more than 2 %.  Returns the mean
+ * sweep times of the kept variants (ms, may be NULL).  It moves the
+ * handle's iterate: the handle is left loaded with e/N, so call it before
+ * stc_load / stc_sweeps (stc_solve reloads anyway). */
 stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, double *ms_fp32);
 
 /* Algorithmic HBM bytes of one launch of phase A and of phase B for this
@@ -309,7 +327,9 @@ stc_status stc_promote(stc_handle *h);
  * A batch sweeps many independent chains (one handle each, of any L and m)
  * with one persistent launch per half-sweep, precision stage and padded
  * block size present: a work list of (chain, group of levels) items strided
- * over a fixed grid, plus one finalize workgroup per chain.  Each chain keeps its own
+ * over a fixed grid, plus one finalize workgroup per chain.  The launches of
+ * different (precision stage, block size) run on side streams of the batch,
+ * forked from its stream and joined back every sweep, so they overlap.  Each chain keeps its own
  * sweep number, scale ring and device stopping test, so chains admitted at
  * different times advance independently and a stopped chain stays put.  The
  * chain table and work lists live at fixed device addresses, so the
@@ -336,7 +356,10 @@ stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, vo
 /* Set the batch's chains (their current iterates and precision stages) and
  * the change tolerance of the device stopping test: chains sweeping in FP32
  * under STC_MIXED stop at their switch_tol, all others at tol.  nontemporal
- * selects non-temporal block loads.  Synchronous. */
+ * selects non-temporal block loads for the block sizes the batch has not
+ * tuned (stc_batch_autotune).  Each chain takes the batch's launch variant for
+ * its block size in both stages (its handle's stc_get_variant reports it), so
+ * the chain swept alone does the same per-level arithmetic.  Synchronous. */
 stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, double tol,
                          int32_t nontemporal);
 
@@ -345,6 +368,28 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
  * again when nsweeps or the set of precision stages changes) or as plain
  * launches.  Asynchronous: use stc_batch_sync / stc_query afterwards. */
 stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph);
+
+/* Autotuner of the batched launch (project-written; the tile and wave shapes
+ * of the many-chain launch).  For each (precision stage, padded block size)
+ * present among the chains set, one at a time, it times trial_sweeps sweeps
+ * of the whole batch (after 2 warm-up sweeps, stopping tests off) for every
+ * launch shape: the tile of launch variants 0 to 3 (row groups per level, so
+ * levels per workgroup, and plain or non-temporal block loads), 1, 2 or 4
+ * groups of levels per work item, and a persistent grid of 2, 4, 8 or 16
+ * workgroups per compute unit; it keeps the fastest.  The tuned shapes stay
+ * with the batch (the next stc_batch_sweeps captures its graph again) and
+ * apply to chains set later.  It moves the chains' iterates: each is left
+ * loaded with e/N in the first stage of its precision schedule, with the
+ * batch's variants.  ms_per_sweep (may be NULL): the batch's sweep time with
+ * the kept shapes.  STC_EINVAL if no chains are set. */
+stc_status stc_batch_autotune(stc_batch *bt, int32_t trial_sweeps, double *ms_per_sweep);
+
+/* The batch's launch shape for stage (STC_FP64 or STC_FP32) and padded block
+ * size mp (8, 16, 32, 64 or 128): the launch variant (bits 0 and 1), the
+ * groups of levels per work item and the workgroups of the persistent grid.
+ * Any pointer may be NULL. */
+stc_status stc_batch_get_tile(const stc_batch *bt, int32_t stage, int32_t mp, int32_t *variant,
+                              int32_t *groups_per_item, int32_t *grid);
 
 /* The stopping state of every chain of the batch in one device-to-host copy,
  * after the work enqueued on the batch's stream (synchronises that stream).

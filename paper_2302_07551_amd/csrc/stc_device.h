@@ -249,7 +249,25 @@ template <bool COH = false>
 __device__ inline void partial_sums(const double *ps, const double *pd, int n, bool want_d,
                                     double *sh, double &S, double &D) {
     double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
-    for (int j = threadIdx.x; j < n; j += kWG) {
+    // each thread takes slots j, j + kWG, j + 2 kWG, ... in that order; the
+    // loads of U of them are issued before their adds, so a long fold waits
+    // for one load round trip per U slots instead of one per slot
+    constexpr int U = 8;
+    int j = threadIdx.x;
+    for (; j + (U - 1) * kWG < n; j += U * kWG) {
+        double a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = cload<COH>(ps + j + u * kWG);
+            b[u] = want_d ? cload<COH>(pd + j + u * kWG) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dd_acc(s1, c1, a[u]);
+            if (want_d) dd_acc(s2, c2, b[u]);
+        }
+    }
+    for (; j < n; j += kWG) {
         dd_acc(s1, c1, cload<COH>(ps + j));
         if (want_d) dd_acc(s2, c2, cload<COH>(pd + j));
     }
@@ -437,14 +455,20 @@ __global__ __launch_bounds__(kWG) void k_sweep(SweepLaunch a) {
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ double sh[4 * kWG / 64];
-    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
-        fold_previous(a, sh);
-        return;
+    int q = blockIdx.x;
+    if (PHB && a.fold) {
+        // the reduction workgroup is dispatched first, so it runs beside the
+        // whole phase instead of after its last wave of groups
+        if (q == 0) {
+            fold_previous(a, sh);
+            return;
+        }
+        --q;
     }
     // a sweep queued after the device stopping test fired changes nothing
     const bool live = a.st->stop_flag == 0;
     const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
-    sweep_group<T, MP, B, PHB, RG, NT>(view_of<T>(a), blockIdx.x, live, kappa, red, rv, sh);
+    sweep_group<T, MP, B, PHB, RG, NT>(view_of<T>(a), q, live, kappa, red, rv, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,7 +727,7 @@ template <typename T, int MP, int B, bool PHB>
 __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *tab,
                                        const T *ell_val, const unsigned char *ell_idx, int q,
                                        bool live, double inv_old, T *red_base, T *rv_base,
-                                       T *src_base, double *sh) {
+                                       T *src_base, unsigned short *base_base, double *sh) {
     using TL = Tile<T, MP, 8>;
     using VT = typename Vec16<T>::type;
     constexpr int NB = 2 * B + 1;
@@ -720,6 +744,8 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     T *red = red_base + team * (R * MP);
     T *rv = rv_base + team * MP;
     T *src = src_base + team * (2 * B * MP);   // [2B][MP] scaled source vectors
+    constexpr int NBASE = MP / 4 + 1;          // round offsets per block, at most
+    unsigned short *base = base_base + team * (2 * B * NBASE);
     const int i = a.parity + 2 * (q * LPW + team);
     const bool active = i < a.L;
     const int ic = active ? i : a.parity;
@@ -728,12 +754,20 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     const T sc = (T)inv_old;
     const T *wb = a.blk + ((size_t)ic * NB + B) * BS + c * VEC;
 
-    // the ELL table entries of the level's off-diagonal blocks
+    // the table entries of the level's off-diagonal blocks, and this lane's
+    // column quad counts (blocks of 128, upper half: also those of column
+    // j - 64, whose ballot counts the lower half's quads of a round)
+    const int j = tt % MP, gg0 = tt / MP;
     EllEntry te[2 * B];
+    int qj[2 * B], qlow[2 * B];
 #pragma unroll
     for (int slot = 0; slot < 2 * B; ++slot) {
         const int d = slot < B ? slot - B : slot - B + 1;
         te[slot] = tab[(size_t)ic * NB + (d + B)];
+        const unsigned char *qc = ell_idx + te[slot].meta;
+        const bool present = te[slot].Kq > 0;
+        qj[slot] = present ? qc[j] : 0;
+        qlow[slot] = (MP > 64 && present && j >= 64) ? qc[j - 64] : 0;
     }
     // rows of W_i stream while the sparse part runs
     VT vpre[PF];
@@ -741,7 +775,8 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
     for (int qq = 0; qq < PF; ++qq)
         vpre[qq] = stream_load<VT, true>((const VT *)(wb + (size_t)(g + R * qq) * MP));
 
-    // stage the source vectors (scaled; zero outside [0, L))
+    // stage the source vectors (scaled; zero outside [0, L)) and the blocks'
+    // round offsets base_t
     for (int e = tt; e < 2 * B * MP; e += TS) {
         const int slot = e / MP, r = e - slot * MP;
         const int d = slot < B ? slot - B : slot - B + 1;   // -B..-1, 1..B
@@ -753,29 +788,46 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
         }
         src[e] = v;
     }
+    for (int e = tt; e < 2 * B * NBASE; e += TS) {
+        const int slot = e / NBASE, t = e - slot * NBASE;
+        const EllEntry te2 = tab[(size_t)ic * NB + (slot < B ? slot : slot + 1)];
+        if (te2.Kq > 0 && t <= te2.Kq)
+            base[e] = ((const unsigned short *)(ell_idx + te2.meta + MP))[t];
+    }
     __syncthreads();
 
     // r_i[j] = sum_d sum_k val[k][j] * v_{i+d}[idx[k][j]], a quad of slots per load.
-    // The table entries are read before the staging barrier, and each pass
+    // Round t of a block holds quad t of the columns that still have one; a
+    // lane finds its quad's place from ballots of the lanes of its segment
+    // (the MP lanes, at most one wave, that share its rounds).  Each pass
     // keeps U quads of one block in flight (the gather is otherwise bound by
     // one load round trip per quad); the sums keep the quad order, so the
     // result does not depend on U.
-    const int j = tt % MP, gg0 = tt / MP;
+    constexpr int SEG = MP < 64 ? MP : 64;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long seg =
+        SEG == 64 ? ~0ull : (((1ull << (SEG & 63)) - 1ull) << (lane & ~(SEG - 1)));
+    const unsigned long long below = (1ull << lane) - 1ull;
     T accs = 0;
 #pragma unroll
     for (int slot = 0; slot < 2 * B; ++slot) {
         const EllEntry e = te[slot];
         const T *sv = src + slot * MP;
-        const int Kq = e.K >> 2;
+        const unsigned short *bt = base + slot * NBASE;
         constexpr int U = sizeof(T) == 8 ? 2 : 4;   // FP64 quads hold twice the registers
-        for (int kq0 = gg0; kq0 < Kq; kq0 += G * U) {
+        // the loop bound is uniform over a segment, so each ballot sees all of it
+        for (int kq0 = gg0; kq0 < e.Kq; kq0 += G * U) {
             unsigned int r4[U];
             T v[U][4];
+            bool on[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int kq = kq0 + u * G;
-                if (kq < Kq) {
-                    const size_t o = (size_t)e.off + ((size_t)kq * MP + j) * 4;
+                on[u] = kq < qj[slot];
+                int rank = __popcll(__ballot(on[u]) & seg & below);
+                if constexpr (MP > 64) rank += __popcll(__ballot(kq < qlow[slot]) & seg);
+                if (on[u]) {
+                    const size_t o = (size_t)e.off + ((size_t)bt[kq] + rank) * 4;
                     r4[u] = __builtin_nontemporal_load((const unsigned int *)(ell_idx + o));
                     if constexpr (sizeof(T) == 8) {
                         const VT v01 = __builtin_nontemporal_load((const VT *)(ell_val + o));
@@ -789,7 +841,7 @@ __device__ inline void sweep_group_ell(const ChainView<T> &a, const EllEntry *ta
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (kq0 + u * G < Kq)
+                if (on[u])
                     accs += v[u][0] * sv[r4[u] & 0xff] + v[u][1] * sv[(r4[u] >> 8) & 0xff] +
                             v[u][2] * sv[(r4[u] >> 16) & 0xff] + v[u][3] * sv[r4[u] >> 24];
         }
@@ -847,15 +899,20 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ T src[TL::LPW * 2 * B * MP];
+    __shared__ unsigned short base[TL::LPW * 2 * B * (MP / 4 + 1)];
     __shared__ double sh[4 * kWG / 64];
-    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
-        fold_previous(a, sh);
-        return;
+    int q = blockIdx.x;
+    if (PHB && a.fold) {   // the reduction workgroup first (see k_sweep)
+        if (q == 0) {
+            fold_previous(a, sh);
+            return;
+        }
+        --q;
     }
     const bool live = a.st->stop_flag == 0;
     const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
-    sweep_group_ell<T, MP, B, PHB>(view_of<T>(a), tab, (const T *)ell_val, ell_idx, blockIdx.x,
-                                   live, kappa, red, rv, src, sh);
+    sweep_group_ell<T, MP, B, PHB>(view_of<T>(a), tab, (const T *)ell_val, ell_idx, q, live,
+                                   kappa, red, rv, src, base, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -866,10 +923,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
 // at its own register count; one kernel for all sizes took the largest).
 // cls: {offset, count} of this block size's items in the work list (read
 // on the device, so a captured graph stays valid when the lists change).
-template <typename T, int MP, int B, bool PHB, bool NT>
+template <typename T, int MP, int B, bool PHB, int RG, bool NT>
 __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
                                                       const WorkItem *items, const int *cls) {
-    using TL = Tile<T, MP, variant_rg(MP, 0)>;   // the tile of launch variant 0
+    using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ double sh[4 * kWG / 64];
@@ -894,8 +951,8 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
         v.slot0 = PHB ? d.groups_a : 0;
         v.s = s;
         const double inv_old = st->inv_sigma[(s - 2) & kRingMask];   // kappa_s
-        sweep_group<T, MP, B, PHB, variant_rg(MP, 0), NT, false, true>(v, w.group, live, inv_old,
-                                                                        red, rv, sh);
+        for (int q = w.group; q < w.group + w.count; ++q)
+            sweep_group<T, MP, B, PHB, RG, NT, false, true>(v, q, live, inv_old, red, rv, sh);
     }
 }
 
@@ -1144,40 +1201,54 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
     const int n = sizes[i];
     const double *Q = diag + (size_t)i * MP * MP;
     if (tid == 0) bad = 0;
-    for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
-        const int r = idx / MP, c = idx - r * MP;
-        double v;
-        if (r < n && c < n) v = -Q[idx];
-        else v = (r == c) ? 1.0 : 0.0;
-        a[r * LD + c] = v;
-        if (r == c) dorig[r] = v;
+    {
+        // every load of the thread's share issued before the first LDS store
+        // (the block is stored padded to MP x MP, so all of it is readable)
+        constexpr int PER = MP * MP / (64 * NW);
+        double q[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) q[u] = Q[tid + u * 64 * NW];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = tid + u * 64 * NW;
+            const int r = idx / MP, c = idx - r * MP;
+            double v;
+            if (r < n && c < n) v = -q[u];
+            else v = (r == c) ? 1.0 : 0.0;
+            a[r * LD + c] = v;
+            if (r == c) dorig[r] = v;
+        }
     }
     __syncthreads();
     for (int kb = 0; kb < NT; ++kb) {
         const int k0 = 16 * kb;
         if (wave == 0) {
-            // inverse of the diagonal tile, in place: lanes own 4 of its 256 entries
-            for (int t = 0; t < 4; ++t) {
-                const int e = lane + 64 * t, r = e >> 4, c = e & 15;
-                dinv[r * DL + c] = a[(k0 + r) * LD + k0 + c];
-            }
+            // inverse of the diagonal tile in registers: lane (g, c) holds
+            // column c = lane % 16 of rows g + 4 v, g = lane / 16; each step
+            // gathers its pivot row, column and pivot with lane shuffles
+            const int c = lane & 15, g = lane >> 4;
+            double t[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) t[v] = a[(k0 + g + 4 * v) * LD + k0 + c];
+#pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const double p = dinv[k * DL + k];
-                double nv[4];
-                for (int t = 0; t < 4; ++t) {
-                    const int e = lane + 64 * t, r = e >> 4, c = e & 15;
-                    const double col = dinv[r * DL + k], row = dinv[k * DL + c];
-                    const double cur = dinv[r * DL + c];
-                    if (r == k) nv[t] = (c == k) ? 1.0 / p : row / p;
-                    else if (c == k) nv[t] = -col / p;
-                    else nv[t] = cur - col * row / p;
+                const int kg = k & 3, kv = k >> 2;    // row k: lanes of group kg, register kv
+                const double row = __shfl(t[kv], 16 * kg + c, 64);   // (k, c)
+                const double p = __shfl(t[kv], 16 * kg + k, 64);     // (k, k)
+                double col[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) col[v] = __shfl(t[v], 16 * g + k, 64);   // (r, k)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = g + 4 * v;
+                    if (r == k) t[v] = (c == k) ? 1.0 / p : row / p;
+                    else if (c == k) t[v] = -col[v] / p;
+                    else t[v] = t[v] - col[v] * row / p;
                 }
                 if (lane == 0 && (!(p > 1e-13 * dorig[k0 + k]) || !isfinite(p))) bad = 1;
-                for (int t = 0; t < 4; ++t) {
-                    const int e = lane + 64 * t, r = e >> 4, c = e & 15;
-                    dinv[r * DL + c] = nv[t];
-                }
             }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dinv[(g + 4 * v) * DL + c] = t[v];
         }
         __syncthreads();
         // row panel: R = D^{-1} A[k, j]
@@ -1195,22 +1266,58 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
             for (int v = 0; v < 4; ++v) a[(k0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
         }
         __syncthreads();
-        // trailing update: A[i, j] += (-A[i, k]) R[k, j]
-        for (int t = wave; t < NT * NT; t += NW) {
-            const int ib = t / NT, jb = t - ib * NT;
-            if (ib == kb || jb == kb) continue;
-            const int i0 = 16 * ib, j0 = 16 * jb;
+        // trailing update: A[i, j] += (-A[i, k]) R[k, j] over the tiles
+        // outside row and column kb, tile t of them on wave t % NW; the next
+        // tile's operands are read from LDS before the current tile's MFMAs
+        // (tiles are disjoint and panel kb is not written here)
+        {
+            constexpr int NTR = (NT - 1) * (NT - 1);
+            auto tile_at = [&](int t, int &i0, int &j0) {
+                int ib = t / (NT - 1), jb = t - ib * (NT - 1);
+                ib += ib >= kb;
+                jb += jb >= kb;
+                i0 = 16 * ib;
+                j0 = 16 * jb;
+            };
+            auto fetch = [&](int i0, int j0, d4_t &acc, double *av, double *bv) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = a[(i0 + lq + 4 * v) * LD + j0 + lr];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    av[s4] = -a[(i0 + lr) * LD + k0 + 4 * s4 + lq];
+                    bv[s4] = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
+                }
+            };
+            int t = wave, i0 = 0, j0 = 0;
             d4_t acc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = a[(i0 + lq + 4 * v) * LD + j0 + lr];
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const double av = -a[(i0 + lr) * LD + k0 + 4 * s4 + lq];
-                const double bv = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
-                acc = mfma16x16x4(av, bv, acc);
+            double av[4], bv[4];
+            if (t < NTR) {
+                tile_at(t, i0, j0);
+                fetch(i0, j0, acc, av, bv);
             }
+            while (t < NTR) {
+                const int tn = t + NW;
+                int i0n = 0, j0n = 0;
+                d4_t accn;
+                double avn[4], bvn[4];
+                if (tn < NTR) {
+                    tile_at(tn, i0n, j0n);
+                    fetch(i0n, j0n, accn, avn, bvn);
+                }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) a[(i0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
+                for (int s4 = 0; s4 < 4; ++s4) acc = mfma16x16x4(av[s4], bv[s4], acc);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) a[(i0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
+                t = tn;
+                i0 = i0n;
+                j0 = j0n;
+                acc = accn;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    av[s4] = avn[s4];
+                    bv[s4] = bvn[s4];
+                }
+            }
         }
         __syncthreads();
         // column panel: A[i, k] = -A[i, k] D^{-1};  A[k, k] = D^{-1}
@@ -1234,7 +1341,9 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
         __syncthreads();
     }
     double *W = blk + ((size_t)i * NB + B) * MP * MP;
-    for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
+#pragma unroll
+    for (int u = 0; u < MP * MP / (64 * NW); ++u) {
+        const int idx = tid + u * 64 * NW;
         const int r = idx / MP, c = idx - r * MP;
         W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
     }

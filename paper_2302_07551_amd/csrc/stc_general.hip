@@ -186,14 +186,18 @@ __global__ __launch_bounds__(kWG) void k_sweep_gen(SweepLaunch a, const GenEntry
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
     __shared__ double sh[4 * kWG / 64];
-    if (PHB && a.fold && blockIdx.x == gridDim.x - 1) {
-        fold_previous(a, sh);
-        return;
+    int q = blockIdx.x;
+    if (PHB && a.fold) {   // the reduction workgroup first (see k_sweep)
+        if (q == 0) {
+            fold_previous(a, sh);
+            return;
+        }
+        --q;
     }
     const bool live = a.st->stop_flag == 0;
     const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
-    sweep_group_gen<T, MP, PHB, NT>(view_of<T>(a), tab, (const T *)val, idx, blockIdx.x, live, kappa,
-                                red, rv, sh);
+    sweep_group_gen<T, MP, PHB, NT>(view_of<T>(a), tab, (const T *)val, idx, q, live, kappa, red,
+                                    rv, sh);
 }
 
 // ||Q^T x||_1 per group of levels, FP64: (Q^T x) restricted to level i is

@@ -113,13 +113,19 @@ struct FlowLaunch {
     long long timeout_ticks;  // a wait longer than this (wall clock) aborts
 };
 
-// One sparse off-diagonal block (column-major ELL in slot quads): K slots per
-// column (a multiple of 4); slot k = 4 kq + t of column j sits at
-// off + (kq MP + j) 4 + t in the value and row-index pools.
+// One sparse off-diagonal block, stored by rounds of slot quads.  Column j
+// holds its nonzeros in row order, in q_j = ceil(nnz_j / 4) quads (the last
+// one padded with value 0, row 0).  Round t holds quad t of every column with
+// q_j > t, in column order and with no gaps: the quad of column j sits at
+// quad position base_t + rank_t(j), rank_t(j) = #{j' < j : q_j' > t}, that
+// is at slot off + 4 (base_t + rank_t(j)) in the value and row-index pools.
+// The row-index pool also holds, from byte meta (a multiple of 4), the
+// block's q_j (MP bytes) and then base_0 .. base_Kq (Kq + 1 unsigned
+// shorts, base_0 = 0).  Kq = max q_j rounds; 4 base_Kq slots in all.
 struct EllEntry {
     long long off;
-    int K;
-    int pad_;
+    int Kq;
+    int meta;
 };
 
 // The off-diagonal entries of one level of a generator of any block pattern
@@ -150,10 +156,13 @@ struct ChainDesc {
     double tol;           // device change test for this chain (<= 0: off)
 };
 
-// One workgroup's work in a batched half-sweep: group q of chain c.
+// One workgroup's work in a batched half-sweep: groups group .. group +
+// count - 1 of chain c, one after the other (each still writes its own
+// partial slot, so the number of groups per item does not change results).
 struct WorkItem {
     int chain;
     int group;
+    int count;
 };
 
 // One chain's state as stc_batch_query reports it.
@@ -167,8 +176,9 @@ struct QueryRow {
 
 // Largest number of per-group partial slots of a sweep that the extra
 // workgroup of phase B reduces; above it a finalize launch follows every
-// sweep (the reduction would outlast the streaming workgroups).
-constexpr int kFoldSlots = 8192;
+// sweep.  The fold's loads run U slots ahead, so 65536 slots take a few
+// microseconds, while a phase of that many groups streams for hundreds.
+constexpr int kFoldSlots = 65536;
 
 // Host-visible launchers (stc_kernels.hip).  Each returns a hipError_t.
 int supported_mp(int m);   // padded block size for m, or 0
@@ -246,13 +256,26 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
 hipError_t launch_widen(const float *src, double *dst, size_t n, hipStream_t stream);
 hipError_t launch_reset_state(DevState *st, hipStream_t stream);
 hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);
-int batch_lpw(int precision_bytes, int MP);
-hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, bool nt, int grid,
-                              const ChainDesc *chains, const WorkItem *items, const int *nitems,
-                              hipStream_t stream);
+// One batched half-sweep launch of the chains of one padded block size:
+// variant bits 0 (row groups) and 1 (non-temporal loads) as for one chain.
+hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, int variant,
+                              int grid, const ChainDesc *chains, const WorkItem *items,
+                              const int *nitems, hipStream_t stream);
 hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
                                  hipStream_t stream);
 int reduce_groups(int MP, int L);
+
+// Algorithm 1 (stc_jgs.hip): one sweep over `chunks` chunks of levels (the
+// workgroups; plus the reduction workgroup of sweep s - 1 when a.fold), and
+// the change of sweep k in its geometry, with the device stopping test.
+hipError_t launch_sweep_jgs(int precision_bytes, int MP, int b, bool nt, int chunks,
+                            const SweepLaunch &a, hipStream_t stream, LaunchTimer t);
+hipError_t launch_diff_jgs_partials(int precision_bytes, int MP, const void *w, const void *w_prev,
+                                    int L, int chunks, const DevState *st, long long k,
+                                    double *part, hipStream_t stream);
+hipError_t launch_diff_jgs(int precision_bytes, int MP, const void *w, const void *w_prev, int L,
+                           int chunks, DevState *st, long long k, double *part,
+                           hipStream_t stream, double tol);
 
 // Residual with caller-given device staging (stc_runtime.cpp), for the
 // allocation-free entry point: bytes of staging the handle needs, the

@@ -409,6 +409,15 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
     return reduce(part, gA + gB, kReduceDiff, st, k, stream, tol);
 }
 
+hipError_t launch_diff_jgs(int precision_bytes, int MP, const void *w, const void *w_prev, int L,
+                           int chunks, DevState *st, long long k, double *part,
+                           hipStream_t stream, double tol) {
+    hipError_t e = launch_diff_jgs_partials(precision_bytes, MP, w, w_prev, L, chunks, st, k, part,
+                                            stream);
+    if (e != hipSuccess) return e;
+    return reduce(part, chunks, kReduceDiff, st, k, stream, tol);
+}
+
 template <typename T, int B>
 static hipError_t residual_b(int MP, const double *blk, const double *diag, const void *w,
                              int L, DevState *st, long long slot, double *part, hipStream_t s,

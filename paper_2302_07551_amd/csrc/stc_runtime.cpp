@@ -87,7 +87,8 @@ struct Layout {
     bool sparse = false;        // off-diagonal blocks swept from ELL storage
     bool general = false;       // any block pattern: one near / far ELL per level
     size_t ell_tab = 0, ell_v64 = 0, ell_v32 = 0, ell_idx = 0;
-    long long ell_slots = 0;    // sum over blocks of K * MP
+    long long ell_slots = 0;    // sum over blocks of 4 x quads (value slots)
+    size_t ell_meta = 0;        // bytes of the blocks' q_j and round offsets
     size_t gen_tab = 0, gen_v64 = 0, gen_v32 = 0, gen_idx = 0;
     long long gen_slots = 0;    // sum over levels of (Kn + Kf) * MP
     // Krylov workspace: r + 3 FP64 vectors (x, w, v_0 .. v_r), the apply
@@ -102,21 +103,39 @@ struct Layout {
 
 int level_size(const stc_generator *g, int i) { return g->sizes ? g->sizes[i] : g->m; }
 
-// Longest column (number of nonzeros) of the gather-oriented block Q_{k,i},
-// rounded up to a multiple of 4 (the ELL slot count stored per column).
-int ell_K(const stc_generator *g, int i, int d) {
+// Nonzeros of each column of the gather-oriented block Q_{k,i}, k = i + d
+// (cnt[0..m), zero beyond the level's size; nothing for d = 0 or an absent
+// neighbour).  Returns false if there is no such block.
+bool ell_column_counts(const stc_generator *g, int i, int d, int *cnt) {
     const int k = i + d, b = g->b, m = g->m, NB = 2 * b + 1;
-    if (k < 0 || k >= g->L || d == 0) return 0;
+    std::fill(cnt, cnt + m, 0);
+    if (k < 0 || k >= g->L || d == 0) return false;
     const double *Q = g->blocks + ((size_t)k * NB + (-d + b)) * (size_t)m * m;
     const int nk = level_size(g, k), ni = level_size(g, i);
-    int K = 0;
-    for (int j = 0; j < ni; ++j) {
-        int cnt = 0;
-        for (int r = 0; r < nk; ++r) cnt += Q[(size_t)r * m + j] != 0.0;
-        K = std::max(K, cnt);
-    }
-    return (K + 3) / 4 * 4;   // stored in quads of slots
+    for (int j = 0; j < ni; ++j)
+        for (int r = 0; r < nk; ++r) cnt[j] += Q[(size_t)r * m + j] != 0.0;
+    return true;
 }
+
+// Storage shape of one sparse off-diagonal block (see EllEntry): Kq rounds,
+// quads = sum of q_j over the columns.
+struct EllShape {
+    int Kq = 0;
+    long long quads = 0;
+};
+
+EllShape ell_shape_of(const int *cnt, int m) {
+    EllShape e;
+    for (int j = 0; j < m; ++j) {
+        const int qj = (cnt[j] + 3) / 4;
+        e.Kq = std::max(e.Kq, qj);
+        e.quads += qj;
+    }
+    return e;
+}
+
+// Bytes of a block's q_j and round offsets, rounded up to 4.
+size_t ell_meta_bytes(int MP, int Kq) { return ((size_t)MP + 2 * ((size_t)Kq + 1) + 3) / 4 * 4; }
 
 bool csr_input(const stc_generator *g) { return !g->blocks && g->csr_rowptr; }
 
@@ -132,17 +151,20 @@ void level_offsets(const stc_generator *g, std::vector<long long> *off, std::vec
     }
 }
 
-// ell_K of every block [L][2b+1] (0 for the diagonal and absent blocks).
-// For CSR input the nonzeros of each column of each gather-oriented block
-// Q_{i+d,i} are counted from the entries directly; entries outside the band
-// or the matrix are skipped here (setup rejects them).  Returns false if the
-// CSR row pointers are malformed.
-bool ell_K_table(const stc_generator *g, std::vector<int> *Ks) {
+// EllShape of every block [L][2b+1] (empty for the diagonal and absent
+// blocks).  For CSR input the nonzeros of each column of each
+// gather-oriented block Q_{i+d,i} are counted from the entries directly;
+// entries outside the band or the matrix are skipped here (setup rejects
+// them).  Returns false if the CSR row pointers are malformed.
+bool ell_shape_table(const stc_generator *g, std::vector<EllShape> *shapes) {
     const int L = g->L, b = g->b, m = g->m, NB = 2 * b + 1;
-    Ks->assign((size_t)L * NB, 0);
+    shapes->assign((size_t)L * NB, EllShape());
     if (!csr_input(g)) {
+        std::vector<int> cnt(m);
         for (int i = 0; i < L; ++i)
-            for (int d = -b; d <= b; ++d) (*Ks)[(size_t)i * NB + d + b] = ell_K(g, i, d);
+            for (int d = -b; d <= b; ++d)
+                if (ell_column_counts(g, i, d, cnt.data()))
+                    (*shapes)[(size_t)i * NB + d + b] = ell_shape_of(cnt.data(), m);
         return true;
     }
     std::vector<long long> off;
@@ -163,11 +185,8 @@ bool ell_K_table(const stc_generator *g, std::vector<int> *Ks) {
             ++cnt[((size_t)i * NB + d + b) * m + (c - off[i])];
         }
     }
-    for (size_t blk = 0; blk < (size_t)L * NB; ++blk) {
-        int K = 0;
-        for (int j = 0; j < m; ++j) K = std::max(K, cnt[blk * m + j]);
-        (*Ks)[blk] = (K + 3) / 4 * 4;
-    }
+    for (size_t blk = 0; blk < (size_t)L * NB; ++blk)
+        (*shapes)[blk] = ell_shape_of(cnt.data() + blk * m, m);
     return true;
 }
 
@@ -311,6 +330,10 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (general && o->format != STC_SPARSE) { *why = 11; return false; }
     if (general && (long long)g->L * MP >= (1ll << 31)) { *why = 12; return false; }
     if (o->krylov_restart < 0 || o->krylov_restart > kMaxRestart) { *why = 13; return false; }
+    if (o->method != STC_STAIRCASE && o->method != STC_JGS) { *why = 15; return false; }
+    if (o->method == STC_JGS &&
+        (o->format != STC_DENSE || general || o->krylov_restart != 0 || o->jgs_chunks < 1 ||
+         o->jgs_chunks > g->L)) { *why = 16; return false; }
     Layout l;
     l.MP = MP;
     l.NB = general ? 1 : 2 * g->b + 1;   // any pattern: only the diagonal slot is dense
@@ -318,9 +341,15 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.sparse = o->format == STC_SPARSE;
     l.general = general;
     if (l.sparse && !general) {
-        std::vector<int> Ks;
-        if (!ell_K_table(g, &Ks)) { *why = 8; return false; }
-        for (int K : Ks) l.ell_slots += (long long)K * MP;
+        std::vector<EllShape> shapes;
+        if (!ell_shape_table(g, &shapes)) { *why = 8; return false; }
+        for (const EllShape &e : shapes) {
+            l.ell_slots += 4 * e.quads;
+            if (e.Kq > 0) l.ell_meta += ell_meta_bytes(MP, e.Kq);
+        }
+        // the row-index pool (slots, then the blocks' q_j and round offsets)
+        // is addressed with 32-bit offsets
+        if (l.ell_slots + (long long)l.ell_meta >= (1ll << 31)) { *why = 14; return false; }
     }
     if (general) {
         std::vector<int> Kn, Kf;
@@ -346,7 +375,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
         l.ell_tab = take(L * l.NB * sizeof(EllEntry));
         l.ell_v64 = take((size_t)l.ell_slots * 8);
         if (l.fp32) l.ell_v32 = take((size_t)l.ell_slots * 4);
-        l.ell_idx = take((size_t)l.ell_slots);
+        l.ell_idx = take((size_t)l.ell_slots + l.ell_meta);
     }
     if (general) {
         l.gen_tab = take(L * sizeof(GenEntry));
@@ -393,12 +422,14 @@ struct stc_handle {
     std::vector<int> sizes;
     long long N = 0;
     int variant[2] = {0, 0};   // sweep-kernel launch variant for FP64 [0] / FP32 [1] stages
+    int method = STC_STAIRCASE;
+    int chunks = 0;            // STC_JGS: chunks of levels (workgroups of a sweep)
     bool sparse = false;
     EllEntry *ell_tab = nullptr;
     double *ell_v64 = nullptr;
     float *ell_v32 = nullptr;
     unsigned char *ell_idx = nullptr;
-    std::vector<int> ell_K;    // [L][NB] longest column per block
+    std::vector<EllShape> ell_shape;   // [L][NB] storage shape per block
     // any block pattern
     bool general = false;
     GenEntry *gen_tab = nullptr;
@@ -432,6 +463,7 @@ void *wbuf(stc_handle *h, bool fp32, long long s) {
 }
 
 int sweep_slots(stc_handle *h) {
+    if (h->method == STC_JGS) return h->chunks;
     const bool f32 = h->stage32;
     const int vv = h->sparse ? kEllGeometry : h->variant[f32 ? 1 : 0];
     const int bytes = f32 ? 4 : 8;
@@ -454,8 +486,47 @@ struct SweepTimers {
     hipEvent_t fin0 = nullptr, fin1 = nullptr;
 };
 
+// One sweep of Algorithm 1 (STC_JGS): a single launch whose extra workgroup
+// records sweep s - 1, then a finalize launch if the chunks' partials are too
+// many to fold.
+hipError_t enqueue_sweep_jgs(stc_handle *h, long long s, double tol, const SweepTimers *tm,
+                             bool first) {
+    const bool f32 = h->stage32;
+    SweepLaunch a;
+    a.blk = f32 ? (const void *)h->blk32 : (const void *)h->blk64;
+    a.w_old = wbuf(h, f32, s - 1);
+    a.w_d1 = wbuf(h, f32, s - 2);
+    a.w_d2 = wbuf(h, f32, s - 3);
+    a.w_new = wbuf(h, f32, s);
+    a.part_sum = h->part_sum + (s & 1) * h->lay.nparts;
+    a.part_diff = h->part_diff + (s & 1) * h->lay.nparts;
+    a.st = h->st;
+    a.L = h->L;
+    a.s = s;
+    a.tol = tol;
+    a.parity = 0;
+    a.slot0 = 0;
+    a.nslots = h->chunks;
+    const bool fold_ok = h->chunks <= kFoldSlots;
+    a.fold = (fold_ok && !first && s >= 2) ? 1 : 0;
+    a.prev_nslots = h->chunks;
+    a.prev_sum = h->part_sum + ((s - 1) & 1) * h->lay.nparts;
+    a.prev_diff = h->part_diff + ((s - 1) & 1) * h->lay.nparts;
+    const bool nt = variant_nt(h->variant[f32 ? 1 : 0]);
+    hipError_t e = launch_sweep_jgs(f32 ? 4 : 8, h->MP, h->b, nt, h->chunks, a, h->stream,
+                                    tm ? tm->a : LaunchTimer());
+    if (!fold_ok) {
+        if (e == hipSuccess && tm) e = hipEventRecord(tm->fin0, h->stream);
+        if (e == hipSuccess)
+            e = launch_finalize_sweep(a.part_sum, a.part_diff, h->chunks, h->st, s, tol, h->stream);
+        if (e == hipSuccess && tm) e = hipEventRecord(tm->fin1, h->stream);
+    }
+    return e;
+}
+
 hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTimers *tm,
                          bool first) {
+    if (h->method == STC_JGS) return enqueue_sweep_jgs(h, s, tol, tm, first);
     const bool f32 = h->stage32;
     const int v = h->variant[f32 ? 1 : 0];
     SweepLaunch a;
@@ -528,8 +599,12 @@ hipError_t end_burst(stc_handle *h, long long n, double tol, bool recorded = fal
     const int pA = (h->stair_type == 1) ? 0 : 1;
     for (long long k = n - 1; k <= n && e == hipSuccess; ++k) {
         if (k < 1) continue;
-        e = launch_diff(f32 ? 4 : 8, h->MP, vv, wbuf(h, f32, k), wbuf(h, f32, k - 1), h->L, pA,
-                        h->st, k, h->part_aux, h->stream, tol);
+        if (h->method == STC_JGS)
+            e = launch_diff_jgs(f32 ? 4 : 8, h->MP, wbuf(h, f32, k), wbuf(h, f32, k - 1), h->L,
+                                h->chunks, h->st, k, h->part_aux, h->stream, tol);
+        else
+            e = launch_diff(f32 ? 4 : 8, h->MP, vv, wbuf(h, f32, k), wbuf(h, f32, k - 1), h->L,
+                            pA, h->st, k, h->part_aux, h->stream, tol);
     }
     return e;
 }
@@ -541,7 +616,7 @@ hipError_t end_burst(stc_handle *h, long long n, double tol, bool recorded = fal
 int flow_blocks(stc_handle *h) {
     const bool f32 = h->stage32;
     const int v = h->variant[f32 ? 1 : 0];
-    if (h->sparse || !variant_flow(v)) return 0;
+    if (h->sparse || h->method == STC_JGS || !variant_flow(v)) return 0;
     int &res = h->flow_res[f32 ? 1 : 0][v & 3];
     if (res < 0) res = flow_resident_blocks(f32 ? 4 : 8, h->MP, h->b, v);
     const int bytes = f32 ? 4 : 8;
@@ -1068,8 +1143,12 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                                     "a generator of any pattern (STC_ANY_PATTERN) comes as CSR input",
                                     "a generator of any pattern (STC_ANY_PATTERN) needs STC_SPARSE storage",
                                     "L * padded m must stay below 2^31",
-                                    "krylov_restart must be in 0..256"};
-        return fail(STC_EINVAL, "%s", msg[why < 14 ? why : 0]);
+                                    "krylov_restart must be in 0..256",
+                                    "the sparse storage of the blocks exceeds 2^31 slots",
+                                    "unknown method",
+                                    "STC_JGS takes dense storage, no Krylov workspace and "
+                                    "jgs_chunks in 1..L"};
+        return fail(STC_EINVAL, "%s", msg[why < 17 ? why : 0]);
     }
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
     if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
@@ -1086,6 +1165,8 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     h->L = L; h->m = m; h->b = b; h->MP = MP; h->NB = NB;
     h->precision = o->precision;
     h->stair_type = o->stair_type;
+    h->method = o->method;
+    h->chunks = o->method == STC_JGS ? o->jgs_chunks : 0;
     h->stop = o->stop;
     h->check_every = o->check_every > 0 ? o->check_every : 1;
     h->switch_tol = o->switch_tol > 0 ? o->switch_tol : 1e-6;
@@ -1248,13 +1329,24 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         if ((rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK) return cleanup(rc);
     }
     if (lay.sparse) {
-        // column-major ELL of every off-diagonal block, levels in order
-        if (!ell_K_table(g, &h->ell_K)) return cleanup(fail(STC_EINVAL, "bad CSR row pointers"));
+        // every off-diagonal block by rounds of slot quads (EllEntry), levels
+        // in order; the blocks' q_j and round offsets follow the slots in the
+        // row-index pool
+        if (!ell_shape_table(g, &h->ell_shape)) return cleanup(fail(STC_EINVAL, "bad CSR row pointers"));
         std::vector<EllEntry> tab((size_t)L * NB);
         long long at = 0;
         for (size_t q = 0; q < tab.size(); ++q) {
-            tab[q] = EllEntry{at, h->ell_K[q], 0};
-            at += (long long)h->ell_K[q] * MP;
+            tab[q] = EllEntry{at, h->ell_shape[q].Kq, 0};
+            at += 4 * h->ell_shape[q].quads;
+        }
+        std::vector<unsigned char> meta(lay.ell_meta, 0);
+        {
+            size_t mo = 0;
+            for (size_t q = 0; q < tab.size(); ++q) {
+                if (tab[q].Kq == 0) continue;
+                tab[q].meta = (int)((size_t)at + mo);
+                mo += ell_meta_bytes(MP, tab[q].Kq);
+            }
         }
         if ((rc = dev(hipMemcpyAsync(h->ell_tab, tab.data(), tab.size() * sizeof(EllEntry),
                                      hipMemcpyHostToDevice, h->stream), "copy ELL table")) != STC_OK)
@@ -1268,25 +1360,44 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
             const long long s1 = (l1 < L) ? tab[(size_t)l1 * NB].off : at;
             val.assign((size_t)(s1 - s0), 0.0);
             idx.assign((size_t)(s1 - s0), 0);
-            // each level writes only its own blocks' slots
+            // each level writes only its own blocks' slots and metadata
             for_level_ranges(l0, l1, threads, [&](int, int i0, int i1) {
+                std::vector<int> cnt(MP), done(MP);
                 for (int i = i0; i < i1; ++i)
                     for (int d = -b; d <= b; ++d) {
                         const EllEntry e = tab[(size_t)i * NB + d + b];
-                        if (e.K == 0) continue;
+                        if (e.Kq == 0) continue;
                         const int k = i + d;
                         const double *Q = q_at(k, -d + b);    // Q_{k,i}: rows level k, cols level i
-                        for (int j = 0; j < sizes[i]; ++j) {
-                            int cnt = 0;
-                            for (int r = 0; r < sizes[k]; ++r) {
+                        std::fill(cnt.begin(), cnt.end(), 0);
+                        for (int j = 0; j < sizes[i]; ++j)
+                            for (int r = 0; r < sizes[k]; ++r) cnt[j] += Q[(size_t)r * m + j] != 0.0;
+                        // round offsets: base_t = quads of the rounds before t
+                        unsigned char *qc = meta.data() + ((size_t)e.meta - (size_t)at);
+                        unsigned short *base = (unsigned short *)(qc + MP);
+                        base[0] = 0;
+                        for (int t = 0; t < e.Kq; ++t) {
+                            int n = 0;
+                            for (int j = 0; j < MP; ++j) n += (cnt[j] + 3) / 4 > t;
+                            base[t + 1] = (unsigned short)(base[t] + n);
+                        }
+                        // done[t]: columns before j with a quad in round t (rank_t)
+                        std::fill(done.begin(), done.end(), 0);
+                        for (int j = 0; j < MP; ++j) {
+                            const int qj = (cnt[j] + 3) / 4;
+                            qc[j] = (unsigned char)qj;
+                            int e2 = 0;
+                            for (int r = 0; r < sizes[k] && qj > 0; ++r) {
                                 const double v = Q[(size_t)r * m + j];
                                 if (v == 0.0) continue;
+                                const int t = e2 >> 2;
                                 const size_t o = (size_t)(e.off - s0) +
-                                                 ((size_t)(cnt >> 2) * MP + j) * 4 + (cnt & 3);
+                                                 ((size_t)base[t] + done[t]) * 4 + (e2 & 3);
                                 val[o] = v;
                                 idx[o] = (unsigned char)r;
-                                ++cnt;
+                                ++e2;
                             }
+                            for (int t = 0; t < qj; ++t) ++done[t];
                         }
                     }
             });
@@ -1299,6 +1410,11 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
                     return cleanup(rc);
             }
         }
+        if (!meta.empty() &&
+            ((rc = dev(hipMemcpyAsync(h->ell_idx + at, meta.data(), meta.size(),
+                                      hipMemcpyHostToDevice, h->stream), "copy ELL rounds")) != STC_OK ||
+             (rc = dev(hipStreamSynchronize(h->stream), "sync")) != STC_OK))
+            return cleanup(rc);
         if (lay.fp32 && at > 0 &&
             (rc = dev(launch_cast_blocks(h->ell_v64, h->ell_v32, (size_t)at, h->stream), "cast ELL")) != STC_OK)
             return cleanup(rc);
@@ -1427,10 +1543,13 @@ stc_status stc_profile_sweeps(stc_handle *h, int64_t nsweeps, double *ms_a, doub
         (void)hipEventElapsedTime(&x, a, b);
         return (double)x;
     };
+    // Algorithm 1 sweeps in one launch: its time is phase A's, phase B's
+    // events are never recorded (and not read)
+    const bool two_launches = h->method == STC_STAIRCASE;
     double ta = 0.0, tb = 0.0, tf = 0.0;
     for (const auto &t : tm) {
         ta += ms(t.a.start, t.a.stop);
-        tb += ms(t.b.start, t.b.stop);
+        if (two_launches) tb += ms(t.b.start, t.b.stop);
         if (!fold) tf += ms(t.fin0, t.fin1);
     }
     tf += ms(fl0, t1);   // the flush that ends the burst
@@ -1473,13 +1592,14 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
         const bool f32 = stage == 1;
         if (f32 && h->precision == STC_FP64) continue;
         if (!f32 && h->precision == STC_FP32) continue;
-        // time every variant from the uniform start in this stage's precision
-        double best = 1e300;
-        int best_v = h->variant[stage];
+        // time every variant from the uniform start in this stage's precision;
+        // the best per-phase variant and the best persistent one separately
+        double best[2] = {1e300, 1e300};
+        int best_v[2] = {-1, -1};
         // the banded sparse kernel has no variants; the any-pattern kernel has
         // its load policy (plain or non-temporal); the dense kernels all
         std::vector<int> cands;
-        if (h->general)
+        if (h->general || h->method == STC_JGS)
             cands = {0, 2};
         else if (h->sparse)
             cands = {h->variant[stage]};
@@ -1511,14 +1631,24 @@ stc_status stc_autotune(stc_handle *h, int32_t trial_sweeps, double *ms_fp64, do
             HostState hs;
             if ((rc = read_state(h, &hs)) != STC_OK) break;   // a timed-out wait is an error
             const double per = (double)ms / trial_sweeps;
-            if (per < best) {
-                best = per;
-                best_v = v;
+            const int kind = variant_flow(v) ? 1 : 0;
+            if (per < best[kind]) {
+                best[kind] = per;
+                best_v[kind] = v;
             }
         }
-        h->variant[stage] = best_v;
-        if (f32 && ms_fp32) *ms_fp32 = best;
-        if (!f32 && ms_fp64) *ms_fp64 = best;
+        if (rc != STC_OK) break;
+        // a persistent (cooperative) burst must beat the best per-phase
+        // launches by more than kFlowMargin to be chosen: within that margin
+        // the two are run-to-run noise, and plain launches ask less of the
+        // device (no co-residency of the whole grid)
+        constexpr double kFlowMargin = 0.02;
+        const bool flow = best_v[1] >= 0 &&
+                          (best_v[0] < 0 || best[1] < best[0] * (1.0 - kFlowMargin));
+        h->variant[stage] = flow ? best_v[1] : (best_v[0] >= 0 ? best_v[0] : h->variant[stage]);
+        const double best_ms = flow ? best[1] : best[0];
+        if (f32 && ms_fp32) *ms_fp32 = best_ms;
+        if (!f32 && ms_fp64) *ms_fp64 = best_ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1553,10 +1683,13 @@ stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {
                 const int k = i + d;
                 if (k < 0 || k >= h->L) continue;
                 // stored block: rows of level k (or i for the inverse) x columns of level i;
-                // sparse storage: K slots x MP columns of value + 1-byte row index
-                if (h->sparse && d != 0)
-                    blocks += (double)h->ell_K[(size_t)i * h->NB + d + h->b] * h->MP * (1.0 + 1.0 / sb);
-                else
+                // sparse storage: its slots (value + 1-byte row index) and its q_j and
+                // round offsets
+                if (h->sparse && d != 0) {
+                    const EllShape &e = h->ell_shape[(size_t)i * h->NB + d + h->b];
+                    blocks += 4.0 * (double)e.quads * (1.0 + 1.0 / sb) +
+                              (e.Kq > 0 ? (double)ell_meta_bytes(h->MP, e.Kq) / sb : 0.0);
+                } else
                     blocks += (double)h->sizes[k] * h->sizes[i];
                 if (d != 0 && !seen[k]) {
                     seen[k] = 1;
@@ -1565,6 +1698,10 @@ stc_status stc_phase_bytes(stc_handle *h, double *bytes_a, double *bytes_b) {
             }
         }
         out[ph] = sb * (blocks + vin + vout);
+    }
+    if (h->method == STC_JGS) {   // one launch per sweep
+        out[0] += out[1];
+        out[1] = 0.0;
     }
     if (bytes_a) *bytes_a = out[0];
     if (bytes_b) *bytes_b = out[1];
@@ -1728,6 +1865,7 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
                            int64_t max_applies, double *pi, stc_result *res, int32_t where) {
     if (!h || !pi) return fail(STC_EINVAL, "null argument");
     if (h->kr < 1) return fail(STC_EINVAL, "the handle has no Krylov workspace (krylov_restart = 0)");
+    if (h->method != STC_STAIRCASE) return fail(STC_EINVAL, "GMRES takes the stair splitting");
     if (restart < 1 || restart > h->kr)
         return fail(STC_EINVAL, "restart must be in 1..%d (krylov_restart)", h->kr);
     if (max_applies < 2 || !(tol >= 0.0)) return fail(STC_EINVAL, "need max_applies >= 2 and tol >= 0");
@@ -1973,14 +2111,34 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
 constexpr int kSizeClasses = 5;                       // MP = 8, 16, 32, 64, 128
 constexpr int kCountsPerGroup = 1 + 4 * kSizeClasses;
 
+// Launch shape of the batched kernel for one (precision stage, padded block
+// size): the tile (launch variant bits 0 and 1: row groups per level,
+// non-temporal loads), the groups of levels per work item and the
+// persistent grid in workgroups per compute unit.  Untuned: variant 0 with
+// the batch's load policy, one group per item, 8 workgroups per CU.
+struct BatchTile {
+    bool tuned = false;
+    int variant = 0;
+    int per_item = 1;
+    int grid_per_cu = 8;
+};
+
 struct stc_batch {
     int max_chains = 0;
     long long max_items = 0;
     int b = 1;
     bool nt = false;
-    int grid = 0;
+    double tol = 0.0;    // change tolerance of the last stc_batch_set
+    int cus = 256;       // compute units of the device
+    BatchTile tile[2][kSizeClasses];   // [stage: 0 FP64, 1 FP32][size class: MP = 8 << c]
     hipStream_t stream = nullptr;
     bool own_stream = false;   // created here: graph capture needs a non-null stream
+    // each (stage group, block size) present runs its two phases on a side
+    // stream of its own, forked from the batch's stream and joined back, so
+    // the launches of different block sizes overlap
+    hipStream_t side[2 * kSizeClasses] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[2 * kSizeClasses] = {};
     char *base = nullptr;
     ChainDesc *d_chains[2] = {nullptr, nullptr};   // [0] FP64 stage, [1] FP32 stage
     WorkItem *d_items_a[2] = {nullptr, nullptr};
@@ -2028,36 +2186,154 @@ void drop_graph(stc_batch *bt) {
     bt->graph_groups = -1;
 }
 
-// Enqueue n sweeps of every non-empty stage group (FP32 group first).
 int class_of(int MP) {
     int c = 0;
     while ((8 << c) < MP) ++c;
     return c;
 }
 
-// Enqueue n sweeps of every non-empty stage group (FP32 group first): per
-// phase one launch per block size present, then the per-chain finalize.
+// Launch variant of the batched kernel for stage group g and size class c.
+int tile_variant(const stc_batch *bt, int g, int c) {
+    const BatchTile &t = bt->tile[g][c];
+    return t.tuned ? t.variant : (bt->nt ? 2 : 0);
+}
+
+// Build the chain table and the work lists of the batch's members on the
+// device, with change tolerance tol (timing: every stopping test off), and
+// give each member the batch's launch variant for its block size in both
+// stages (so the chain swept alone takes the same per-level arithmetic).
+stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
+    const int count = (int)bt->members.size();
+    std::vector<ChainDesc> chains[2];
+    // work lists per stage group and block size class, in chain order
+    std::vector<WorkItem> ia[2][kSizeClasses], ib[2][kSizeClasses];
+    for (int c = 0; c < count; ++c) {
+        stc_handle *h = bt->members[c];
+        const int g = h->stage32 ? 1 : 0;
+        const int bytes = g == 1 ? 4 : 8;
+        const int cls = class_of(h->MP);
+        const int v = tile_variant(bt, g, cls);
+        h->variant[0] = tile_variant(bt, 0, cls);
+        h->variant[1] = tile_variant(bt, 1, cls);
+        const int pA = (h->stair_type == 1) ? 0 : 1;
+        ChainDesc d;
+        d.blk = g == 1 ? (const void *)h->blk32 : (const void *)h->blk64;
+        for (int k = 0; k < 4; ++k) d.w[k] = wbuf(h, g == 1, k);
+        d.part_sum = h->part_sum;
+        d.part_diff = h->part_diff;
+        d.st = h->st;
+        d.L = h->L;
+        d.MP = h->MP;
+        d.parity_a = pA;
+        d.groups_a = phase_groups(bytes, h->MP, h->L, pA, v);
+        d.groups_b = phase_groups(bytes, h->MP, h->L, 1 - pA, v);
+        d.tol = timing ? 0.0 : (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
+        const int ci = (int)chains[g].size();
+        chains[g].push_back(d);
+        const int per = bt->tile[g][cls].per_item;
+        for (int q = 0; q < d.groups_a; q += per)
+            ia[g][cls].push_back({ci, q, std::min(per, d.groups_a - q)});
+        for (int q = 0; q < d.groups_b; q += per)
+            ib[g][cls].push_back({ci, q, std::min(per, d.groups_b - q)});
+    }
+    for (int g = 0; g < 2; ++g) {
+        int *hc = bt->counts + g * kCountsPerGroup;
+        hc[0] = (int)chains[g].size();
+        for (int ph = 0; ph < 2; ++ph) {
+            std::vector<WorkItem> all;
+            for (int c = 0; c < kSizeClasses; ++c) {
+                const std::vector<WorkItem> &v = ph == 0 ? ia[g][c] : ib[g][c];
+                hc[1 + 4 * c + 2 * ph] = (int)all.size();       // offset
+                hc[1 + 4 * c + 2 * ph + 1] = (int)v.size();     // count
+                all.insert(all.end(), v.begin(), v.end());
+            }
+            if ((long long)all.size() > bt->max_items)
+                return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld", all.size(),
+                            bt->max_items);
+            if (!all.empty())
+                HIP_TRY(hipMemcpyAsync(ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], all.data(),
+                                       all.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                                       bt->stream));
+        }
+        if (!chains[g].empty())
+            HIP_TRY(hipMemcpyAsync(bt->d_chains[g], chains[g].data(), chains[g].size() * sizeof(ChainDesc),
+                                   hipMemcpyHostToDevice, bt->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
+                           bt->stream));
+    std::vector<DevState *> states(count);
+    for (int c = 0; c < count; ++c) states[c] = bt->members[c]->st;
+    if (count > 0)
+        HIP_TRY(hipMemcpyAsync(bt->d_states, states.data(), sizeof(DevState *) * count,
+                               hipMemcpyHostToDevice, bt->stream));
+    HIP_TRY(hipStreamSynchronize(bt->stream));
+    return STC_OK;
+}
+
+// Enqueue n sweeps of every non-empty stage group.  Per sweep, each (stage
+// group, block size) present runs phase A then phase B on its side stream,
+// forked from the batch's stream; the batch's stream joins them all and runs
+// the per-chain finalize of each group.  Captured, the sweep is a graph with
+// one branch per block size; the per-chain arithmetic does not depend on
+// how the branches interleave.
 hipError_t enqueue_batch(stc_batch *bt, long long n) {
     hipError_t e = hipSuccess;
     for (long long j = 0; j < n && e == hipSuccess; ++j) {
+        e = hipEventRecord(bt->fork, bt->stream);
         for (int g = 1; g >= 0 && e == hipSuccess; --g) {
             const int *hc = bt->counts + g * kCountsPerGroup;
             int *dc = bt->d_counts + g * kCountsPerGroup;
             if (hc[0] == 0) continue;
             const int bytes = g == 1 ? 4 : 8;
-            for (int ph = 0; ph < 2 && e == hipSuccess; ++ph)
-                for (int c = 0; c < kSizeClasses && e == hipSuccess; ++c) {
+            for (int c = 0; c < kSizeClasses && e == hipSuccess; ++c) {
+                if (hc[1 + 4 * c + 1] == 0 && hc[1 + 4 * c + 3] == 0) continue;   // absent
+                const int br = g * kSizeClasses + c;
+                hipStream_t sc = bt->side[br];
+                e = hipStreamWaitEvent(sc, bt->fork, 0);
+                const BatchTile &t = bt->tile[g][c];
+                for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
                     const int k = 1 + 4 * c + 2 * ph;
                     if (hc[k + 1] == 0) continue;
-                    e = launch_batch_phase(bytes, bt->b, 8 << c, ph == 1, bt->nt, bt->grid,
-                                           bt->d_chains[g], ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g],
-                                           dc + k, bt->stream);
+                    e = launch_batch_phase(bytes, bt->b, 8 << c, ph == 1, tile_variant(bt, g, c),
+                                           t.grid_per_cu * bt->cus, bt->d_chains[g],
+                                           ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], dc + k,
+                                           sc);
                 }
-            if (e == hipSuccess)
-                e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], dc, bt->stream);
+                if (e == hipSuccess) e = hipEventRecord(bt->join[br], sc);
+                if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->join[br], 0);
+            }
+        }
+        for (int g = 1; g >= 0 && e == hipSuccess; --g) {
+            const int *hc = bt->counts + g * kCountsPerGroup;
+            if (hc[0] == 0) continue;
+            e = launch_batch_finalize(bt->max_chains, bt->d_chains[g],
+                                      bt->d_counts + g * kCountsPerGroup, bt->stream);
         }
     }
     return e;
+}
+
+// Side streams and events of a batch; false (all released) on failure.
+bool make_branches(stc_batch *bt) {
+    bool ok = hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 2 * kSizeClasses && ok; ++k)
+        ok = hipStreamCreateWithFlags(&bt->side[k], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&bt->join[k], hipEventDisableTiming) == hipSuccess;
+    return ok;
+}
+
+void free_branches(stc_batch *bt) {
+    for (int k = 0; k < 2 * kSizeClasses; ++k) {
+        if (bt->side[k]) {
+            (void)hipStreamSynchronize(bt->side[k]);
+            (void)hipStreamDestroy(bt->side[k]);
+        }
+        if (bt->join[k]) (void)hipEventDestroy(bt->join[k]);
+        bt->side[k] = nullptr;
+        bt->join[k] = nullptr;
+    }
+    if (bt->fork) (void)hipEventDestroy(bt->fork);
+    bt->fork = nullptr;
 }
 
 // Which (stage group, block size) launches a captured graph holds.
@@ -2114,11 +2390,18 @@ stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, vo
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
         cus = 256;
-    bt->grid = cus * 8;   // persistent grid; groups without work exit at once
+    bt->cus = cus;   // persistent grids are multiples of it; workgroups without work exit
+    if (!make_branches(bt)) {
+        free_branches(bt);
+        if (bt->own_stream) (void)hipStreamDestroy(bt->stream);
+        delete bt;
+        return fail(STC_EDEVICE, "could not create the batch's side streams");
+    }
     hipError_t e = hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts),
                                   hipMemcpyHostToDevice, bt->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(bt->stream);
     if (e != hipSuccess) {
+        free_branches(bt);
         if (bt->own_stream) (void)hipStreamDestroy(bt->stream);
         delete bt;
         return fail(STC_EDEVICE, "batch create: %s", hipGetErrorString(e));
@@ -2131,71 +2414,98 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
                          int32_t nontemporal) {
     if (!bt || (count > 0 && !hs) || count < 0) return fail(STC_EINVAL, "bad argument");
     if (count > bt->max_chains) return fail(STC_EINVAL, "%d chains > max_chains %d", count, bt->max_chains);
-    std::vector<ChainDesc> chains[2];
-    // work lists per stage group and block size class, in chain order
-    std::vector<WorkItem> ia[2][kSizeClasses], ib[2][kSizeClasses];
     for (int c = 0; c < count; ++c) {
         stc_handle *h = hs[c];
         if (!h) return fail(STC_EINVAL, "handle %d is NULL", c);
         if (h->b != bt->b) return fail(STC_EINVAL, "handle %d has bandwidth %d, batch %d", c, h->b, bt->b);
         if (h->sparse) return fail(STC_EINVAL, "handle %d stores sparse blocks; batches take dense chains", c);
-        const int g = h->stage32 ? 1 : 0;
-        const int bytes = g == 1 ? 4 : 8;
-        const int lpw = batch_lpw(bytes, h->MP);
-        const int pA = (h->stair_type == 1) ? 0 : 1;
-        ChainDesc d;
-        d.blk = g == 1 ? (const void *)h->blk32 : (const void *)h->blk64;
-        for (int k = 0; k < 4; ++k) d.w[k] = wbuf(h, g == 1, k);
-        d.part_sum = h->part_sum;
-        d.part_diff = h->part_diff;
-        d.st = h->st;
-        d.L = h->L;
-        d.MP = h->MP;
-        d.parity_a = pA;
-        d.groups_a = ((h->L - pA + 1) / 2 + lpw - 1) / lpw;
-        d.groups_b = ((h->L - (1 - pA) + 1) / 2 + lpw - 1) / lpw;
-        d.tol = (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
-        const int ci = (int)chains[g].size();
-        chains[g].push_back(d);
-        const int cls = class_of(h->MP);
-        for (int q = 0; q < d.groups_a; ++q) ia[g][cls].push_back({ci, q});
-        for (int q = 0; q < d.groups_b; ++q) ib[g][cls].push_back({ci, q});
+        if (h->method != STC_STAIRCASE)
+            return fail(STC_EINVAL, "handle %d sweeps Algorithm 1; batches take the stair splitting", c);
     }
-    for (int g = 0; g < 2; ++g) {
-        int *hc = bt->counts + g * kCountsPerGroup;
-        hc[0] = (int)chains[g].size();
-        for (int ph = 0; ph < 2; ++ph) {
-            std::vector<WorkItem> all;
-            for (int c = 0; c < kSizeClasses; ++c) {
-                const std::vector<WorkItem> &v = ph == 0 ? ia[g][c] : ib[g][c];
-                hc[1 + 4 * c + 2 * ph] = (int)all.size();       // offset
-                hc[1 + 4 * c + 2 * ph + 1] = (int)v.size();     // count
-                all.insert(all.end(), v.begin(), v.end());
-            }
-            if ((long long)all.size() > bt->max_items)
-                return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld", all.size(),
-                            bt->max_items);
-            if (!all.empty())
-                HIP_TRY(hipMemcpyAsync(ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], all.data(),
-                                       all.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                                       bt->stream));
-        }
-        if (!chains[g].empty())
-            HIP_TRY(hipMemcpyAsync(bt->d_chains[g], chains[g].data(), chains[g].size() * sizeof(ChainDesc),
-                                   hipMemcpyHostToDevice, bt->stream));
-    }
-    HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
-                           bt->stream));
-    std::vector<DevState *> states(count);
-    for (int c = 0; c < count; ++c) states[c] = hs[c]->st;
-    if (count > 0)
-        HIP_TRY(hipMemcpyAsync(bt->d_states, states.data(), sizeof(DevState *) * count,
-                               hipMemcpyHostToDevice, bt->stream));
-    HIP_TRY(hipStreamSynchronize(bt->stream));
-    bt->members.assign(hs, hs + count);
     const bool nt = nontemporal != 0;
     if (nt != bt->nt) drop_graph(bt);
     bt->nt = nt;
+    bt->tol = tol;
+    bt->members.assign(hs, hs + count);
+    return upload_lists(bt, tol);
+}
+
+stc_status stc_batch_autotune(stc_batch *bt, int32_t trial_sweeps, double *ms_per_sweep) {
+    if (!bt || trial_sweeps < 1) return fail(STC_EINVAL, "bad argument");
+    if (bt->members.empty()) return fail(STC_EINVAL, "the batch has no chains to tune on");
+    drop_graph(bt);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    // time the whole batch (stopping tests off) with the current tiles
+    auto timed = [&](double *ms) -> stc_status {
+        stc_status r = upload_lists(bt, 0.0, true);
+        if (r != STC_OK) return r;
+        HIP_TRY(enqueue_batch(bt, 2));
+        HIP_TRY(hipEventRecord(e0, bt->stream));
+        HIP_TRY(enqueue_batch(bt, trial_sweeps));
+        HIP_TRY(hipEventRecord(e1, bt->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        *ms = (double)t / trial_sweeps;
+        return STC_OK;
+    };
+    stc_status rc = upload_lists(bt, 0.0, true);
+    double best_ms = INFINITY;
+    // one (stage, block size) at a time, the others at their current shape:
+    // the launches of different sizes follow each other, so their times add
+    for (int g = 0; g < 2 && rc == STC_OK; ++g)
+        for (int c = 0; c < kSizeClasses && rc == STC_OK; ++c) {
+            if (bt->counts[g * kCountsPerGroup + 1 + 4 * c + 1] == 0) continue;   // absent
+            const int MP = 8 << c;
+            BatchTile best = bt->tile[g][c];
+            best.variant = tile_variant(bt, g, c);
+            best.tuned = true;
+            double best_c = INFINITY;
+            for (int v = 0; v < 4 && rc == STC_OK; ++v) {
+                // variants that differ only in row groups the block size ignores
+                if ((v & 1) && variant_rg(MP, v) == variant_rg(MP, v & 2)) continue;
+                for (int per : {1, 2, 4})
+                    for (int gpc : {2, 4, 8, 16}) {
+                        if (rc != STC_OK) break;
+                        bt->tile[g][c] = BatchTile{true, v, per, gpc};
+                        double ms = INFINITY;
+                        rc = timed(&ms);
+                        if (rc == STC_OK && ms < best_c) {
+                            best_c = ms;
+                            best = bt->tile[g][c];
+                        }
+                    }
+            }
+            bt->tile[g][c] = best;
+            best_ms = best_c;
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != STC_OK) return rc;
+    // the members start again from e/N in their first stage, with the tuned
+    // variants, under the caller's tolerance
+    for (stc_handle *h : bt->members) {
+        const int v0 = h->variant[0], v1 = h->variant[1];
+        if ((rc = load_vector(h, nullptr, STC_MEM_HOST)) != STC_OK) return rc;
+        h->variant[0] = v0;
+        h->variant[1] = v1;
+    }
+    if ((rc = upload_lists(bt, bt->tol)) != STC_OK) return rc;
+    if (ms_per_sweep) *ms_per_sweep = best_ms;
+    return STC_OK;
+}
+
+stc_status stc_batch_get_tile(const stc_batch *bt, int32_t stage, int32_t mp, int32_t *variant,
+                              int32_t *groups_per_item, int32_t *grid) {
+    if (!bt || (stage != STC_FP64 && stage != STC_FP32) || supported_mp(mp) != mp)
+        return fail(STC_EINVAL, "need a batch, stage STC_FP64 or STC_FP32 and mp in 8, 16, 32, "
+                                "64, 128");
+    const int g = stage == STC_FP32 ? 1 : 0, c = class_of(mp);
+    if (variant) *variant = tile_variant(bt, g, c);
+    if (groups_per_item) *groups_per_item = bt->tile[g][c].per_item;
+    if (grid) *grid = bt->tile[g][c].grid_per_cu * bt->cus;
     return STC_OK;
 }
 
@@ -2256,6 +2566,7 @@ stc_status stc_batch_sync(stc_batch *bt) {
 void stc_batch_destroy(stc_batch *bt) {
     if (!bt) return;
     drop_graph(bt);
+    free_branches(bt);
     if (bt->own_stream) {
         (void)hipStreamSynchronize(bt->stream);
         (void)hipStreamDestroy(bt->stream);

@@ -119,13 +119,38 @@ class Server:
         opt = stc.make_options(self.precision, 1, "diff", 1, self.switch_tol)
         return stc.stc_footprint_bytes(gen, opt)
 
+    def autotune(self, probes, trial_sweeps: int = 10) -> float:
+        """Tune the batch's launch shapes (stc_batch_autotune) before serving,
+        on probe chains (Requests) standing in for the stream.  Under mixed
+        precision each probe is set up twice, sweeping in FP32 and in FP64,
+        so that both stages are tuned; probes beyond the batch's slots are
+        left out.  The probes are released afterwards; the shapes stay with
+        the batch and apply to every chain admitted later.  Returns the
+        probes' batched sweep time in ms."""
+        precs = ("fp32", "fp64") if self.precision == "mixed" else (self.precision,)
+        probes = list(probes)[: max(1, self.max_chains // len(precs))]
+        solvers = []
+        try:
+            for req in probes:
+                for prec in precs:
+                    s = stc.Solver(req.blocks, req.sizes, req.b, precision=prec,
+                                   device=self.device, stream=self.setup_stream)
+                    s.load(None)
+                    solvers.append(s)
+            self.setup_stream.synchronize()
+            self.batch.set(solvers, self.tol, self.nontemporal)
+            ms = self.batch.autotune(trial_sweeps)
+            self.batch.set([], self.tol, self.nontemporal)
+        finally:
+            for s in solvers:
+                s.close()
+        return ms
+
     def _admit(self, req: Request) -> stc.Solver:
+        # the batch gives the chain its launch variants when it joins
         s = stc.Solver(req.blocks, req.sizes, req.b, precision=self.precision,
                        switch_tol=self.switch_tol, device=self.device,
                        stream=self.setup_stream)
-        # the batched kernel is launch variant 0 of the single-chain kernel
-        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
-        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
         s.load(None)
         return s
 

@@ -28,6 +28,8 @@ STC_STOP_DIFF, STC_STOP_RESIDUAL = 0, 1
 STC_MEM_HOST, STC_MEM_DEVICE = 0, 1
 STC_DENSE, STC_SPARSE = 0, 1
 STC_ANY_PATTERN = -1          # stc_generator.b: a generator of any block pattern
+STC_STAIRCASE, STC_JGS = 0, 1   # stc_options.method
+METHODS = {"staircase": STC_STAIRCASE, "jgs": STC_JGS}
 
 PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
 STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
@@ -38,7 +40,8 @@ EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_solve_gmres", "
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
            "stc_store", "stc_promote", "stc_batch_footprint", "stc_batch_create",
-           "stc_batch_set", "stc_batch_sweeps", "stc_batch_query", "stc_batch_sync",
+           "stc_batch_set", "stc_batch_autotune", "stc_batch_get_tile", "stc_batch_sweeps",
+           "stc_batch_query", "stc_batch_sync",
            "stc_batch_destroy",
            "stc_destroy",
            "stc_status_string", "stc_last_error")
@@ -54,7 +57,8 @@ class stc_options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("stair_type", c_int32), ("stop", c_int32),
                 ("check_every", c_int32), ("switch_tol", c_double), ("stream", c_void_p),
                 ("arena", c_void_p), ("arena_bytes", c_size_t), ("format", c_int32),
-                ("krylov_restart", c_int32), ("krylov_keep_all", c_int32)]
+                ("krylov_restart", c_int32), ("krylov_keep_all", c_int32),
+                ("method", c_int32), ("jgs_chunks", c_int32)]
 
 
 class stc_result(ctypes.Structure):
@@ -127,6 +131,9 @@ def load_library(path: str = LIB_PATH):
     lib.stc_batch_create.argtypes = [c_int32, c_int64, c_int32, c_void_p, c_void_p, c_size_t,
                                      POINTER(H)]
     lib.stc_batch_set.argtypes = [H, POINTER(H), c_int32, c_double, c_int32]
+    lib.stc_batch_autotune.argtypes = [H, c_int32, dp]
+    lib.stc_batch_get_tile.argtypes = [H, c_int32, c_int32, POINTER(c_int32), POINTER(c_int32),
+                                       POINTER(c_int32)]
     lib.stc_batch_sweeps.argtypes = [H, c_int64, c_int32]
     lib.stc_batch_query.argtypes = [H, c_void_p, c_void_p, c_void_p, c_void_p]
     lib.stc_batch_sync.argtypes = [H]
@@ -196,12 +203,14 @@ FORMATS = {"dense": STC_DENSE, "sparse": STC_SPARSE}
 
 def make_options(precision="fp64", stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
                  stream=0, arena=0, arena_bytes=0, format="dense", krylov_restart=0,
-                 krylov_keep_all=False):
+                 krylov_keep_all=False, method="staircase", jgs_chunks=0):
     return stc_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision),
                        int(stair_type), STOPS[stop] if isinstance(stop, str) else int(stop),
                        int(check_every), float(switch_tol), stream or None, arena or None,
                        int(arena_bytes), FORMATS[format] if isinstance(format, str) else int(format),
-                       int(krylov_restart), int(bool(krylov_keep_all)))
+                       int(krylov_restart), int(bool(krylov_keep_all)),
+                       METHODS[method] if isinstance(method, str) else int(method),
+                       int(jgs_chunks))
 
 
 def stc_footprint_bytes(gen: stc_generator, opt: stc_options) -> int:
@@ -355,6 +364,20 @@ def stc_batch_set(bt, handles, tol: float, nontemporal: bool = False):
     _check(load_library().stc_batch_set(bt, arr, len(handles), float(tol), int(bool(nontemporal))))
 
 
+def stc_batch_autotune(bt, trial_sweeps: int = 20) -> float:
+    """Tune the batch's launch shapes on its chains; ms per sweep with them."""
+    ms = c_double(float("nan"))
+    _check(load_library().stc_batch_autotune(bt, int(trial_sweeps), byref(ms)))
+    return ms.value
+
+
+def stc_batch_get_tile(bt, stage: int, mp: int) -> dict:
+    v, per, grid = c_int32(), c_int32(), c_int32()
+    _check(load_library().stc_batch_get_tile(bt, int(stage), int(mp), byref(v), byref(per),
+                                             byref(grid)))
+    return {"variant": v.value, "groups_per_item": per.value, "grid": grid.value}
+
+
 def stc_batch_sweeps(bt, nsweeps: int, use_graph: bool = True):
     _check(load_library().stc_batch_sweeps(bt, int(nsweeps), int(bool(use_graph))))
 
@@ -406,6 +429,14 @@ class Batch:
     def sweeps(self, n: int, use_graph: bool = True):
         stc_batch_sweeps(self.bt, n, use_graph)
 
+    def autotune(self, trial_sweeps: int = 20) -> float:
+        """Tune the launch shapes on the chains set (their iterates restart
+        from e/N); returns ms per sweep of the batch."""
+        return stc_batch_autotune(self.bt, trial_sweeps)
+
+    def tile(self, stage: int, mp: int) -> dict:
+        return stc_batch_get_tile(self.bt, stage, mp)
+
     def query(self):
         """Stopping state of every member: (sweeps, stopped, diff_1, status)."""
         return stc_batch_query(self.bt, len(self.members))
@@ -437,8 +468,11 @@ class Solver:
     def __init__(self, blocks: np.ndarray | None, sizes, b: int, *, precision="fp64",
                  stair_type=1, stop="diff", check_every=1, switch_tol=0.0,
                  recompute_diagonal=False, device=None, stream=None, poison=False,
-                 format="dense", csr=None, m=None, krylov_restart=0, krylov_keep_all=False):
-        """blocks: [L][2b+1][m][m] dense blocks, or None with csr = (indptr,
+                 format="dense", csr=None, m=None, krylov_restart=0, krylov_keep_all=False,
+                 method="staircase", jgs_chunks=0):
+        """method "jgs" sweeps Algorithm 1 over jgs_chunks chunks of levels
+        instead of the stair splitting.
+        blocks: [L][2b+1][m][m] dense blocks, or None with csr = (indptr,
         indices, data) of the N x N generator (sizes then required; m
         defaults to the largest size).  poison: fill the arena with 0xFF
         bytes (a NaN in FP32 and FP64) before setup, so that any read of
@@ -458,7 +492,8 @@ class Solver:
             self.gen, self._keep = make_generator(blocks, sizes, b, recompute_diagonal)
         self.opt = make_options(precision, stair_type, stop, check_every, switch_tol,
                                 stream=self.stream.cuda_stream, format=format,
-                                krylov_restart=krylov_restart, krylov_keep_all=krylov_keep_all)
+                                krylov_restart=krylov_restart, krylov_keep_all=krylov_keep_all,
+                                method=method, jgs_chunks=jgs_chunks)
         need = stc_footprint_bytes(self.gen, self.opt)
         if need == 0:
             raise StcError(STC_EINVAL, "unsupported generator shape or options")

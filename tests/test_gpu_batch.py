@@ -1,8 +1,10 @@
 """Batched sweeps over many chains against the same chains swept alone.
 
-The batched kernel runs the same per-level code as launch variant 0 of the
-single-chain kernel and the same fixed-order reductions, so every chain's
-iterate must be bitwise equal to the chain swept alone with variant 0.
+The batched kernel runs the same per-level code as the single-chain kernel
+with the launch variant the batch gives the chain's block size (variant 0
+until stc_batch_autotune picks another), and the same fixed-order
+reductions, so every chain's iterate must be bitwise equal to the chain
+swept alone with that variant.
 Graph replays are checked against plain launches, replay after replay, with
 host work and synchronisations in between.
 """
@@ -218,4 +220,59 @@ def test_served_mix_shapes():
     b.sync()
     for k, s in enumerate(solvers):
         assert np.array_equal(s.store(), alone[k]), k
+    b.close()
+
+
+def _mp(m):
+    mp = 8
+    while mp < m:
+        mp *= 2
+    return mp
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuned_batch_equals_alone_bitwise(precision):
+    """After stc_batch_autotune each chain takes the batch's launch variant for
+    its block size; the tuned batch (graph replays, tuned groups per item and
+    grid) gives every chain bitwise the iterate of the chain swept alone with
+    that variant."""
+    from paper_2302_07551_amd import Batch, Solver, stc
+    gens = _chains(SPECS, 900)
+    xs = _starts(gens, 5)
+    solvers = _solvers(gens, precision)
+    b = Batch(16, 4096)
+    b.set(solvers, tol=0.0)
+    ms = b.autotune(3)
+    stage = stc.STC_FP32 if precision == "fp32" else stc.STC_FP64
+    tiles = {mp: b.tile(stage, mp) for mp in (8, 16, 32, 64, 128)}
+    _say(f"tuned {precision}: {ms:.4f} ms per sweep, {tiles}")
+    for s, x in zip(solvers, xs):
+        s.load(x)
+    b.set(solvers, tol=0.0)
+    nsw = 17
+    b.sweeps(nsw)
+    b.sync()
+    got = [s.store() for s in solvers]
+    variants = [stc.stc_get_variant(s.h, stage) for s in solvers]
+    b.close()
+    for s in solvers:
+        s.close()
+    for k, (g, x) in enumerate(zip(gens, xs)):
+        assert variants[k] == tiles[_mp(g.m)]["variant"], k
+        s = Solver(g.blocks, g.sizes, g.b, precision=precision)
+        stc.stc_set_variant(s.h, stage, variants[k])
+        s.load(x)
+        s.sweeps(nsw)
+        assert np.array_equal(s.store(), got[k]), k
+        s.close()
+
+
+def test_batch_autotune_needs_chains():
+    from paper_2302_07551_amd import Batch, stc
+    b = Batch(4, 64)
+    with pytest.raises(stc.StcError) as e:
+        b.autotune(2)
+    assert e.value.status == stc.STC_EINVAL
+    t = b.tile(stc.STC_FP32, 16)
+    assert t["variant"] == 0 and t["groups_per_item"] == 1 and t["grid"] > 0
     b.close()

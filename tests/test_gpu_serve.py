@@ -1,5 +1,6 @@
 """The continuous-batching service: every served result equals the same chain
-solved alone (same schedule, same device stopping tests, launch variant 0),
+solved alone (same schedule, same device stopping tests, the launch variants
+the batch gives its block size),
 admission never exceeds the memory budget, and requests overlap on the GPU."""
 import numpy as np
 import pytest
@@ -36,6 +37,11 @@ def test_served_equals_alone_and_budget_holds():
     srv = Server(budget_bytes=1, max_chains=8, sweeps_per_round=15, tol=tol, switch_tol=sw)
     fps = [srv.footprint(r) for r in reqs]
     srv.budget = int(sum(sorted(fps)[-4:]))      # binds: at most a few chains at once
+    # launch shapes tuned on probe chains first; served chains take them
+    srv.autotune(reqs[:6], trial_sweeps=2)
+    tiles = {(st, mp): srv.batch.tile(st, mp)["variant"]
+             for st in (stc.STC_FP64, stc.STC_FP32) for mp in (8, 16, 32, 64)}
+    print(tiles, flush=True)
     stats = srv.run(reqs)
     srv.close()
     summ = stats.summary()
@@ -46,8 +52,11 @@ def test_served_equals_alone_and_budget_holds():
     by_id = {r.rid: r for r in stats.results}
     for k, g in enumerate(gens):
         s = Solver(g.blocks, g.sizes, g.b, precision="mixed", switch_tol=sw, check_every=10)
-        stc.stc_set_variant(s.h, stc.STC_FP64, 0)
-        stc.stc_set_variant(s.h, stc.STC_FP32, 0)
+        mp = 8
+        while mp < g.m:
+            mp *= 2
+        stc.stc_set_variant(s.h, stc.STC_FP64, tiles[(stc.STC_FP64, mp)])
+        stc.stc_set_variant(s.h, stc.STC_FP32, tiles[(stc.STC_FP32, mp)])
         pi, info = s.solve(tol=tol, maxit=100000, allow_maxit=False)
         s.close()
         r = by_id[k]
