@@ -1162,7 +1162,8 @@ __global__ __launch_bounds__(kWG) void k_invert(const double *diag, const int *s
 // ---------------------------------------------------------------------------
 // W_i = (-Q_ii)^{-1} by blocked Gauss-Jordan elimination with FP64 MFMA, one
 // level per workgroup, the whole block in LDS.  For each 16-wide panel k:
-//   D^{-1}     inverse of the 16x16 diagonal tile (one wave, VALU)
+//   D^{-1}     inverse of the 16x16 diagonal tile (one wave, VALU, computed
+//              during the previous panel's trailing update)
 //   R          = D^{-1} A[k, j]              row panel, j != k      (MFMA)
 //   A[i, j]   -= A[i, k] R[k, j]             trailing update, i, j != k (MFMA)
 //   A[i, k]    = -A[i, k] D^{-1},  A[k, k] = D^{-1}   column panel  (MFMA)
@@ -1185,14 +1186,83 @@ __device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
 // a CU and 8 waves gain 3 %; more waves cost occupancy.
 __host__ __device__ constexpr int inv_waves(int MP) { return MP >= 128 ? 16 : MP >= 64 ? 8 : 4; }
 
+// Row KG (lanes 16 KG .. 16 KG + 15) of x, copied into every row of 16
+// lanes: a swap of the wave's halves, then of neighbouring rows
+// (v_permlane32_swap, v_permlane16_swap; each returns both swapped operands).
+template <int KG>
+__device__ __forceinline__ unsigned row_bcast(unsigned x) {
+    const auto h = __builtin_amdgcn_permlane32_swap(x, x, false, false);   // rows 0 1 0 1 | 2 3 2 3
+    const unsigned y = h[KG >> 1];
+    const auto r = __builtin_amdgcn_permlane16_swap(y, y, false, false);   // rows a a b b | c c d d
+    return r[KG & 1];
+}
+
+// Gauss-Jordan steps K .. 15 of invert_diag_tile (K a constant: the lane
+// broadcasts take it as an immediate).
+template <int K>
+__device__ __forceinline__ void gj_steps(double (&t)[4], int c, int g, double &piv) {
+    if constexpr (K < 16) {
+        constexpr int kg = K & 3, kv = K >> 2;    // row K: lanes of group kg, register kv
+        // (K, c): row kg of the wave, copied into every row of 16 lanes
+        const double row = __hiloint2double((int)row_bcast<kg>((unsigned)__double2hiint(t[kv])),
+                                            (int)row_bcast<kg>((unsigned)__double2loint(t[kv])));
+        // (r, K): lane K of the lane's own row of 16 (DPP row_newbcast)
+        double col[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            col[v] = __hiloint2double(
+                __builtin_amdgcn_mov_dpp(__double2hiint(t[v]), 0x150 + K, 0xF, 0xF, false),
+                __builtin_amdgcn_mov_dpp(__double2loint(t[v]), 0x150 + K, 0xF, 0xF, false));
+        // (K, K), read from its lane into every lane
+        const double pk = __hiloint2double(
+            __builtin_amdgcn_readlane(__double2hiint(t[kv]), 16 * kg + K),
+            __builtin_amdgcn_readlane(__double2loint(t[kv]), 16 * kg + K));
+        const double pinv = 1.0 / pk;
+        const double rs = (c == K ? 1.0 : row) * pinv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double gen = (c == K ? 0.0 : t[v]) - col[v] * rs;
+            t[v] = (g + 4 * v == K) ? rs : gen;
+        }
+        piv = (c == K) ? pk : piv;   // lane c keeps the pivot of step c
+        gj_steps<K + 1>(t, c, g, piv);
+    }
+}
+
+// Inverse of the 16 x 16 diagonal tile kb of the block a (row stride LD, in
+// LDS) into dst (row stride DL), by one wave, in registers: lane (g, c)
+// holds column c = lane % 16 of rows g + 4 v, g = lane / 16.  Each
+// Gauss-Jordan step copies its pivot row to every row of 16 lanes and its
+// pivot column across each row of 16 lanes (register-to-register lane
+// moves), reads the pivot from its lane, and scales by one reciprocal of it;
+// every lane runs the same instructions (selects, no branches).  A pivot
+// not above 1e-13 times the original diagonal entry, or not finite, sets
+// *bad (lane c checks the pivot of step c).
+template <int LD, int DL>
+__device__ __forceinline__ void invert_diag_tile(const double *a, const double *dorig, int kb,
+                                                 double *dst, int *bad) {
+    const int lane = threadIdx.x & 63;
+    const int k0 = 16 * kb;
+    const int c = lane & 15, g = lane >> 4;
+    double t[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) t[v] = a[(k0 + g + 4 * v) * LD + k0 + c];
+    double piv = 0.0;
+    gj_steps<0>(t, c, g, piv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[(g + 4 * v) * DL + c] = t[v];
+    if (!(piv > 1e-13 * dorig[k0 + c]) || !isfinite(piv)) *bad = 1;
+}
+
 template <int MP, int NW = inv_waves(MP)>   // NW: waves per workgroup
 __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, const int *sizes,
                                                       double *blk, int NB, int B, DevState *st) {
     constexpr int LD = MP + 2;      // row stride in LDS (doubles)
     constexpr int NT = MP / 16;     // panels
     constexpr int DL = 17;          // stride of the 16x16 tile
+    static_assert(NW >= 2, "the lookahead wave needs partners for the trailing update");
     __shared__ double a[MP * LD];
-    __shared__ double dinv[16 * DL];
+    __shared__ double dinv[2][16 * DL];   // D^{-1} of this panel and of the next
     __shared__ double dorig[MP];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1220,37 +1290,11 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
         }
     }
     __syncthreads();
+    if (wave == 0) invert_diag_tile<LD, DL>(a, dorig, 0, dinv[0], &bad);
+    __syncthreads();
     for (int kb = 0; kb < NT; ++kb) {
         const int k0 = 16 * kb;
-        if (wave == 0) {
-            // inverse of the diagonal tile in registers: lane (g, c) holds
-            // column c = lane % 16 of rows g + 4 v, g = lane / 16; each step
-            // gathers its pivot row, column and pivot with lane shuffles
-            const int c = lane & 15, g = lane >> 4;
-            double t[4];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) t[v] = a[(k0 + g + 4 * v) * LD + k0 + c];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int kg = k & 3, kv = k >> 2;    // row k: lanes of group kg, register kv
-                const double row = __shfl(t[kv], 16 * kg + c, 64);   // (k, c)
-                const double p = __shfl(t[kv], 16 * kg + k, 64);     // (k, k)
-                double col[4];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) col[v] = __shfl(t[v], 16 * g + k, 64);   // (r, k)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = g + 4 * v;
-                    if (r == k) t[v] = (c == k) ? 1.0 / p : row / p;
-                    else if (c == k) t[v] = -col[v] / p;
-                    else t[v] = t[v] - col[v] * row / p;
-                }
-                if (lane == 0 && (!(p > 1e-13 * dorig[k0 + k]) || !isfinite(p))) bad = 1;
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dinv[(g + 4 * v) * DL + c] = t[v];
-        }
-        __syncthreads();
+        const double *dcur = dinv[kb & 1];
         // row panel: R = D^{-1} A[k, j]
         for (int jb = wave; jb < NT; jb += NW) {
             if (jb == kb) continue;
@@ -1258,7 +1302,7 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
-                const double av = dinv[lr * DL + 4 * s4 + lq];
+                const double av = dcur[lr * DL + 4 * s4 + lq];
                 const double bv = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
                 acc = mfma16x16x4(av, bv, acc);
             }
@@ -1267,11 +1311,16 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
         }
         __syncthreads();
         // trailing update: A[i, j] += (-A[i, k]) R[k, j] over the tiles
-        // outside row and column kb, tile t of them on wave t % NW; the next
-        // tile's operands are read from LDS before the current tile's MFMAs
-        // (tiles are disjoint and panel kb is not written here)
+        // outside row and column kb.  Lookahead: wave 0 updates the next
+        // panel's diagonal tile and inverts it while the other waves update
+        // the remaining tiles (the column panel below leaves that tile
+        // alone).  Each wave reads its next tile's operands from LDS before
+        // the current tile's MFMAs (tiles are disjoint and panel kb is not
+        // written here).
         {
             constexpr int NTR = (NT - 1) * (NT - 1);
+            const bool ahead = kb + 1 < NT;
+            const int tl = kb * (NT - 1) + kb;   // the next diagonal tile among the NTR
             auto tile_at = [&](int t, int &i0, int &j0) {
                 int ib = t / (NT - 1), jb = t - ib * (NT - 1);
                 ib += ib >= kb;
@@ -1288,34 +1337,52 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
                     bv[s4] = a[(k0 + 4 * s4 + lq) * LD + j0 + lr];
                 }
             };
-            int t = wave, i0 = 0, j0 = 0;
-            d4_t acc;
-            double av[4], bv[4];
-            if (t < NTR) {
-                tile_at(t, i0, j0);
-                fetch(i0, j0, acc, av, bv);
-            }
-            while (t < NTR) {
-                const int tn = t + NW;
-                int i0n = 0, j0n = 0;
-                d4_t accn;
-                double avn[4], bvn[4];
-                if (tn < NTR) {
-                    tile_at(tn, i0n, j0n);
-                    fetch(i0n, j0n, accn, avn, bvn);
-                }
+            auto update = [&](int i0, int j0, d4_t acc, const double *av, const double *bv) {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) acc = mfma16x16x4(av[s4], bv[s4], acc);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) a[(i0 + lq + 4 * v) * LD + j0 + lr] = acc[v];
-                t = tn;
-                i0 = i0n;
-                j0 = j0n;
-                acc = accn;
+            };
+            // the tiles this wave updates: u = u0, u0 + du, ... < nu, which
+            // skip the lookahead tile when there is one
+            const int nu = ahead ? NTR - 1 : NTR;
+            const int u0 = ahead ? wave - 1 : wave, du = ahead ? NW - 1 : NW;
+            auto tile_of = [&](int u) { return (ahead && u >= tl) ? u + 1 : u; };
+            if (ahead && wave == 0) {
+                int i0, j0;
+                d4_t acc;
+                double av[4], bv[4];
+                tile_at(tl, i0, j0);
+                fetch(i0, j0, acc, av, bv);
+                update(i0, j0, acc, av, bv);
+                invert_diag_tile<LD, DL>(a, dorig, kb + 1, dinv[(kb + 1) & 1], &bad);
+            } else {
+                int u = u0, i0 = 0, j0 = 0;
+                d4_t acc;
+                double av[4], bv[4];
+                if (u < nu) {
+                    tile_at(tile_of(u), i0, j0);
+                    fetch(i0, j0, acc, av, bv);
+                }
+                while (u < nu) {
+                    const int un = u + du;
+                    int i0n = 0, j0n = 0;
+                    d4_t accn;
+                    double avn[4], bvn[4];
+                    if (un < nu) {
+                        tile_at(tile_of(un), i0n, j0n);
+                        fetch(i0n, j0n, accn, avn, bvn);
+                    }
+                    update(i0, j0, acc, av, bv);
+                    u = un;
+                    i0 = i0n;
+                    j0 = j0n;
+                    acc = accn;
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    av[s4] = avn[s4];
-                    bv[s4] = bvn[s4];
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        av[s4] = avn[s4];
+                        bv[s4] = bvn[s4];
+                    }
                 }
             }
         }
@@ -1326,12 +1393,12 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
             d4_t acc = {0.0, 0.0, 0.0, 0.0};
             if (ib == kb) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[v] = dinv[(lq + 4 * v) * DL + lr];
+                for (int v = 0; v < 4; ++v) acc[v] = dcur[(lq + 4 * v) * DL + lr];
             } else {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) {
                     const double av = -a[(i0 + lr) * LD + k0 + 4 * s4 + lq];
-                    const double bv = dinv[(4 * s4 + lq) * DL + lr];
+                    const double bv = dcur[(4 * s4 + lq) * DL + lr];
                     acc = mfma16x16x4(av, bv, acc);
                 }
             }
