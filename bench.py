@@ -59,6 +59,14 @@ Other workloads (each prints its own JSON line instead):
   --batch-rates   the batched kernel's GB/s per block size (8, 16, 32, 64; about
                   1 GB per sweep; FP32 and FP64) and on 60 served requests,
                   with the untuned launch shape and after stc_batch_autotune
+  --batch-probe   a short run for hardware counters on the batched kernel:
+                  10 FP32 sweeps of each --batch-rates batch (m = 8, 16, 32,
+                  64; untuned shape with non-temporal loads), then a 1 GiB
+                  device-to-device copy, run under rocprofv3 --pmc FETCH_SIZE
+                  (then WRITE_SIZE)
+  --batch-traffic PROBE FETCH_CSV WRITE_CSV
+                  no GPU: HBM bytes per batched phase launch from those two
+                  runs, scaled by the copy, against the algorithmic bytes
   --setup L M     time setup (validation and packing on the host, upload, the
                   batched inverse of the diagonal blocks) for a QBD of L levels
                   and block size M, FP64 and mixed
@@ -193,10 +201,14 @@ def main():
     ap.add_argument("--batch-rates", action="store_true")
     ap.add_argument("--jgs", action="store_true")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
+    ap.add_argument("--batch-probe", action="store_true")
+    ap.add_argument("--batch-traffic", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary)
+    if args.batch_traffic:
+        return batch_traffic(*args.batch_traffic)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
@@ -225,6 +237,8 @@ def main():
         return launch_sizes_mode()
     if args.batch_rates:
         return batch_rates_mode()
+    if args.batch_probe:
+        return batch_probe()
     if args.jgs:
         return jgs_mode()
 
@@ -964,6 +978,89 @@ def _batch_rate(batch, solvers, steps=30):
             "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+BATCH_SHAPES = {8: (16384, 80), 16: (8192, 40), 32: (4096, 20), 64: (2048, 10)}
+
+
+def batch_probe(sweeps=10, copy_bytes=1 << 30):
+    """Counter run of the batched kernel: per block size, one FP32 batch of
+    the --batch-rates shape (untuned launch shape, non-temporal loads),
+    sweeps plain launches, then three 1 GiB device copies (the calibration
+    kernel).  Prints the algorithmic bytes per phase launch."""
+    import torch
+    import synth
+    from paper_2302_07551_amd import Batch, Solver, stc
+    torch.cuda.set_device(0)
+    out = {"sweeps": sweeps, "copy_bytes_each_way": copy_bytes, "classes": {}}
+    for m, (L, count) in BATCH_SHAPES.items():
+        g = synth.qbd(L, m, 4000 + m)
+        solvers = [Solver(g.blocks, g.sizes, g.b, precision="fp32") for _ in range(count)]
+        b = Batch(count, 1 << 20)
+        for s in solvers:
+            s.load(None)
+        b.set(solvers, tol=0.0, nontemporal=True)
+        b.sweeps(sweeps, use_graph=False)
+        b.sync()
+        ba = sum(stc.stc_phase_bytes(s.h)[0] for s in solvers)
+        bb = sum(stc.stc_phase_bytes(s.h)[1] for s in solvers)
+        t = b.tile(stc.STC_FP32, m)
+        out["classes"][str(m)] = {"chains": count, "levels": L, "phase_a_bytes": ba,
+                                  "phase_b_bytes": bb, "tile": t}
+        b.close()
+        for s in solvers:
+            s.close()
+    torch.cuda.synchronize()
+    x = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+
+
+def batch_traffic(probe_json, fetch_csv, write_csv):
+    """HBM bytes per batched phase launch (k_batch_sweep<float, MP, ...>,
+    phase A and B apart) from the FETCH_SIZE and WRITE_SIZE runs of
+    --batch-probe, each counter scaled by what it reads for the 1 GiB copy."""
+    with open(probe_json) as f:
+        probe = json.loads(f.read().strip().splitlines()[-1])
+    cb = probe["copy_bytes_each_way"]
+
+    def per_kernel(path, counter):
+        sums, copy = {}, []
+        for name, v in _counter_rows(path, counter):
+            n = name.replace(" ", "")
+            if "copyBuffer" in n:
+                copy.append(v)
+                continue
+            if not n.startswith("voidstc::k_batch_sweep<float,"):
+                continue
+            mp = int(n.split(",")[1])
+            phb = n.split(",")[3] == "true"
+            sums.setdefault((mp, phb), []).append(v)
+        copy = sorted(copy, reverse=True)[:3]   # the three 1 GiB copies
+        return sums, (sum(copy) / len(copy) if copy else None)
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    fs = cb / (fcopy * 1024) if fcopy else None
+    ws = cb / (wcopy * 1024) if wcopy else None
+    rows = {}
+    for m, c in probe["classes"].items():
+        for phb in (False, True):
+            key = (int(m), phb)
+            if key not in fetch or key not in write or fs is None or ws is None:
+                continue
+            f = sum(fetch[key]) / len(fetch[key])
+            w = sum(write[key]) / len(write[key])
+            alg = c["phase_b_bytes" if phb else "phase_a_bytes"]
+            hbm = f * 1024 * fs + w * 1024 * ws
+            rows[f"m{m}_{'b' if phb else 'a'}"] = {
+                "dispatches": len(fetch[key]), "fetch_kib": round(f, 1), "write_kib": round(w, 1),
+                "hbm_bytes": int(round(hbm)), "algorithmic_bytes": alg,
+                "ratio": round(hbm / alg, 4)}
+    print(json.dumps({"fetch_scale": fs, "write_scale": ws, "launches": rows}, indent=1))
+
+
 def batch_rates_mode():
     """The batched (many-chain) kernel's rate per block size, before and after
     stc_batch_autotune: batches of chains of one block size with about 1 GB
@@ -974,9 +1071,8 @@ def batch_rates_mode():
     import synth
     from paper_2302_07551_amd import Batch, Solver, stc
     torch.cuda.set_device(0)
-    shapes = {8: (16384, 80), 16: (8192, 40), 32: (4096, 20), 64: (2048, 10)}
     rows = {}
-    for m, (L, count) in shapes.items():
+    for m, (L, count) in BATCH_SHAPES.items():
         g = synth.qbd(L, m, 4000 + m)
         for prec in ("fp32", "fp64"):
             solvers = [Solver(g.blocks, g.sizes, g.b, precision=prec) for _ in range(count)]

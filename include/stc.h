@@ -327,9 +327,12 @@ stc_status stc_promote(stc_handle *h);
  * A batch sweeps many independent chains (one handle each, of any L and m)
  * with one persistent launch per half-sweep, precision stage and padded
  * block size present: a work list of (chain, group of levels) items strided
- * over a fixed grid, plus one finalize workgroup per chain.  The launches of
- * different (precision stage, block size) run on side streams of the batch,
- * forked from its stream and joined back every sweep, so they overlap.  Each chain keeps its own
+ * over a fixed grid, plus one finalize workgroup per chain.  Each (precision
+ * stage, block size) present runs all the sweeps of a stc_batch_sweeps call
+ * (both phases and its chains' finalize, sweep after sweep) on a side stream
+ * of the batch, forked from its stream once and joined back once, so the
+ * launches of different sizes overlap and need not wait for each other
+ * between sweeps.  Each chain keeps its own
  * sweep number, scale ring and device stopping test, so chains admitted at
  * different times advance independently and a stopped chain stays put.  The
  * chain table and work lists live at fixed device addresses, so the

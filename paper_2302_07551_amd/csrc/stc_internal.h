@@ -261,7 +261,9 @@ hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);
 hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, int variant,
                               int grid, const ChainDesc *chains, const WorkItem *items,
                               const int *nitems, hipStream_t stream);
-hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
+// Finalize of chains[range[0] ..][0 .. range[1] - 1] (range on the device);
+// grid: at least the largest range[1] the launch may see.
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range,
                                  hipStream_t stream);
 int reduce_groups(int MP, int L);
 

@@ -20,13 +20,14 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
     finalize_chain(part_sum, part_diff, nslots, st, s, tol, sh);
 }
 
-
-
+// The per-chain finalize of a batch's chains chains[range[0] ..
+// range[0] + range[1] - 1], one workgroup per chain (the range is read on the
+// device, so a captured graph stays valid when the membership changes).
 __global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
-                                                         const int *nchains) {
+                                                         const int *range) {
     __shared__ double sh[4 * kWG / 64];
-    if ((int)blockIdx.x >= *nchains) return;
-    const ChainDesc &d = chains[blockIdx.x];
+    if ((int)blockIdx.x >= range[1]) return;
+    const ChainDesc &d = chains[range[0] + blockIdx.x];
     DevState *st = d.st;
     finalize_chain(d.part_sum, d.part_diff, d.groups_a + d.groups_b, st, st->last_sweep + 1,
                    d.tol, sh);
@@ -294,9 +295,9 @@ hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *nchains,
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range,
                                  hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, nchains);
+    hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, range);
     return hipGetLastError();
 }
 

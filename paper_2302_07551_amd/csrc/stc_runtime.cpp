@@ -2109,7 +2109,11 @@ stc_status stc_solve_gmres(stc_handle *h, const double *x0, int32_t restart, dou
 // ---------------------------------------------------------------------------
 
 constexpr int kSizeClasses = 5;                       // MP = 8, 16, 32, 64, 128
-constexpr int kCountsPerGroup = 1 + 4 * kSizeClasses;
+constexpr int kCountsPerGroup = 1 + 6 * kSizeClasses;
+// Index, within a stage group's counts, of size class c's entry k: 0 and 1
+// phase A {offset, count} into the work list, 2 and 3 phase B's, 4 and 5
+// {offset, count} of the class's chains in the group's chain table.
+constexpr int cnt_at(int c, int k) { return 1 + 6 * c + k; }
 
 // Launch shape of the batched kernel for one (precision stage, padded block
 // size): the tile (launch variant bits 0 and 1: row groups per level,
@@ -2145,7 +2149,8 @@ struct stc_batch {
     WorkItem *d_items_b[2] = {nullptr, nullptr};
     // per stage group g (kCountsPerGroup ints from g * kCountsPerGroup):
     // chains, then per block size class c (MP = 8 << c): phase A {offset,
-    // count}, phase B {offset, count} into that group's work lists
+    // count}, phase B {offset, count} into that group's work lists, and the
+    // class's {offset, count} in the group's chain table (ordered by class)
     int *d_counts = nullptr;
     int counts[2 * kCountsPerGroup] = {};
     DevState **d_states = nullptr;                  // members' states, in stc_batch_set order
@@ -2205,9 +2210,15 @@ int tile_variant(const stc_batch *bt, int g, int c) {
 stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
     const int count = (int)bt->members.size();
     std::vector<ChainDesc> chains[2];
-    // work lists per stage group and block size class, in chain order
+    // work lists per stage group and block size class, in chain order; the
+    // chain table of each group holds the chains class by class
     std::vector<WorkItem> ia[2][kSizeClasses], ib[2][kSizeClasses];
-    for (int c = 0; c < count; ++c) {
+    std::vector<int> order;
+    for (int cls = 0; cls < kSizeClasses; ++cls)
+        for (int c = 0; c < count; ++c)
+            if (class_of(bt->members[c]->MP) == cls) order.push_back(c);
+    int cls_first[2][kSizeClasses], cls_count[2][kSizeClasses] = {};
+    for (int c : order) {
         stc_handle *h = bt->members[c];
         const int g = h->stage32 ? 1 : 0;
         const int bytes = g == 1 ? 4 : 8;
@@ -2229,6 +2240,7 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
         d.groups_b = phase_groups(bytes, h->MP, h->L, 1 - pA, v);
         d.tol = timing ? 0.0 : (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
         const int ci = (int)chains[g].size();
+        if (cls_count[g][cls]++ == 0) cls_first[g][cls] = ci;
         chains[g].push_back(d);
         const int per = bt->tile[g][cls].per_item;
         for (int q = 0; q < d.groups_a; q += per)
@@ -2243,8 +2255,10 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
             std::vector<WorkItem> all;
             for (int c = 0; c < kSizeClasses; ++c) {
                 const std::vector<WorkItem> &v = ph == 0 ? ia[g][c] : ib[g][c];
-                hc[1 + 4 * c + 2 * ph] = (int)all.size();       // offset
-                hc[1 + 4 * c + 2 * ph + 1] = (int)v.size();     // count
+                hc[cnt_at(c, 2 * ph)] = (int)all.size();       // offset
+                hc[cnt_at(c, 2 * ph + 1)] = (int)v.size();     // count
+                hc[cnt_at(c, 4)] = cls_count[g][c] ? cls_first[g][c] : 0;
+                hc[cnt_at(c, 5)] = cls_count[g][c];
                 all.insert(all.end(), v.begin(), v.end());
             }
             if ((long long)all.size() > bt->max_items)
@@ -2270,44 +2284,41 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
     return STC_OK;
 }
 
-// Enqueue n sweeps of every non-empty stage group.  Per sweep, each (stage
-// group, block size) present runs phase A then phase B on its side stream,
-// forked from the batch's stream; the batch's stream joins them all and runs
-// the per-chain finalize of each group.  Captured, the sweep is a graph with
-// one branch per block size; the per-chain arithmetic does not depend on
-// how the branches interleave.
+// Enqueue n sweeps of every non-empty stage group.  Each (stage group,
+// block size) present runs its n sweeps (phase A, phase B, then the
+// per-chain finalize of its own chains) on a side stream of its own, forked
+// from the batch's stream once and joined back once: no chain depends on a
+// chain of another block size, so the branches need not meet between
+// sweeps, and each branch's launch gaps are filled by the others' work.
+// Captured, the burst is a graph with one chain of launches per branch; the
+// per-chain arithmetic does not depend on how the branches interleave.
 hipError_t enqueue_batch(stc_batch *bt, long long n) {
-    hipError_t e = hipSuccess;
-    for (long long j = 0; j < n && e == hipSuccess; ++j) {
-        e = hipEventRecord(bt->fork, bt->stream);
-        for (int g = 1; g >= 0 && e == hipSuccess; --g) {
-            const int *hc = bt->counts + g * kCountsPerGroup;
-            int *dc = bt->d_counts + g * kCountsPerGroup;
-            if (hc[0] == 0) continue;
-            const int bytes = g == 1 ? 4 : 8;
-            for (int c = 0; c < kSizeClasses && e == hipSuccess; ++c) {
-                if (hc[1 + 4 * c + 1] == 0 && hc[1 + 4 * c + 3] == 0) continue;   // absent
-                const int br = g * kSizeClasses + c;
-                hipStream_t sc = bt->side[br];
-                e = hipStreamWaitEvent(sc, bt->fork, 0);
-                const BatchTile &t = bt->tile[g][c];
+    hipError_t e = hipEventRecord(bt->fork, bt->stream);
+    for (int g = 1; g >= 0 && e == hipSuccess; --g) {
+        const int *hc = bt->counts + g * kCountsPerGroup;
+        int *dc = bt->d_counts + g * kCountsPerGroup;
+        if (hc[0] == 0) continue;
+        const int bytes = g == 1 ? 4 : 8;
+        for (int c = 0; c < kSizeClasses && e == hipSuccess; ++c) {
+            if (hc[cnt_at(c, 5)] == 0) continue;   // absent
+            const int br = g * kSizeClasses + c;
+            hipStream_t sc = bt->side[br];
+            e = hipStreamWaitEvent(sc, bt->fork, 0);
+            const BatchTile &t = bt->tile[g][c];
+            for (long long j = 0; j < n && e == hipSuccess; ++j) {
                 for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
-                    const int k = 1 + 4 * c + 2 * ph;
-                    if (hc[k + 1] == 0) continue;
+                    if (hc[cnt_at(c, 2 * ph + 1)] == 0) continue;
                     e = launch_batch_phase(bytes, bt->b, 8 << c, ph == 1, tile_variant(bt, g, c),
                                            t.grid_per_cu * bt->cus, bt->d_chains[g],
-                                           ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], dc + k,
-                                           sc);
+                                           ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g],
+                                           dc + cnt_at(c, 2 * ph), sc);
                 }
-                if (e == hipSuccess) e = hipEventRecord(bt->join[br], sc);
-                if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->join[br], 0);
+                if (e == hipSuccess)
+                    e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], dc + cnt_at(c, 4),
+                                              sc);
             }
-        }
-        for (int g = 1; g >= 0 && e == hipSuccess; --g) {
-            const int *hc = bt->counts + g * kCountsPerGroup;
-            if (hc[0] == 0) continue;
-            e = launch_batch_finalize(bt->max_chains, bt->d_chains[g],
-                                      bt->d_counts + g * kCountsPerGroup, bt->stream);
+            if (e == hipSuccess) e = hipEventRecord(bt->join[br], sc);
+            if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->join[br], 0);
         }
     }
     return e;
@@ -2341,7 +2352,8 @@ int batch_shape(const stc_batch *bt) {
     int mask = 0;
     for (int g = 0; g < 2; ++g)
         for (int c = 0; c < kSizeClasses; ++c)
-            if (bt->counts[g * kCountsPerGroup + 1 + 4 * c + 1] > 0) mask |= 1 << (g * kSizeClasses + c);
+            if (bt->counts[g * kCountsPerGroup + cnt_at(c, 5)] > 0)
+                mask |= 1 << (g * kSizeClasses + c);
     return mask;
 }
 
@@ -2453,11 +2465,11 @@ stc_status stc_batch_autotune(stc_batch *bt, int32_t trial_sweeps, double *ms_pe
     };
     stc_status rc = upload_lists(bt, 0.0, true);
     double best_ms = INFINITY;
-    // one (stage, block size) at a time, the others at their current shape:
-    // the launches of different sizes follow each other, so their times add
+    // one (stage, block size) at a time, the others at their current shape,
+    // on the whole batch's time (the branches of different sizes overlap)
     for (int g = 0; g < 2 && rc == STC_OK; ++g)
         for (int c = 0; c < kSizeClasses && rc == STC_OK; ++c) {
-            if (bt->counts[g * kCountsPerGroup + 1 + 4 * c + 1] == 0) continue;   // absent
+            if (bt->counts[g * kCountsPerGroup + cnt_at(c, 5)] == 0) continue;   // absent
             const int MP = 8 << c;
             BatchTile best = bt->tile[g][c];
             best.variant = tile_variant(bt, g, c);
