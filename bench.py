@@ -983,9 +983,10 @@ BATCH_SHAPES = {8: (16384, 80), 16: (8192, 40), 32: (4096, 20), 64: (2048, 10)}
 
 def batch_probe(sweeps=10, copy_bytes=1 << 30):
     """Counter run of the batched kernel: per block size, one FP32 batch of
-    the --batch-rates shape (untuned launch shape, non-temporal loads),
-    sweeps plain launches, then three 1 GiB device copies (the calibration
-    kernel).  Prints the algorithmic bytes per phase launch."""
+    the --batch-rates shape, tuned by stc_batch_autotune, then `sweeps` plain
+    launches of the tuned shape (the last dispatches of each block size),
+    then three 1 GiB device copies (the calibration kernel).  Prints the
+    algorithmic bytes per phase launch and the tuned shapes."""
     import torch
     import synth
     from paper_2302_07551_amd import Batch, Solver, stc
@@ -998,6 +999,10 @@ def batch_probe(sweeps=10, copy_bytes=1 << 30):
         for s in solvers:
             s.load(None)
         b.set(solvers, tol=0.0, nontemporal=True)
+        b.autotune(10)
+        for s in solvers:
+            s.load(None)
+        b.set(solvers, tol=0.0)
         b.sweeps(sweeps, use_graph=False)
         b.sync()
         ba = sum(stc.stc_phase_bytes(s.h)[0] for s in solvers)
@@ -1019,15 +1024,23 @@ def batch_probe(sweeps=10, copy_bytes=1 << 30):
 
 def batch_traffic(probe_json, fetch_csv, write_csv):
     """HBM bytes per batched phase launch (k_batch_sweep<float, MP, ...>,
-    phase A and B apart) from the FETCH_SIZE and WRITE_SIZE runs of
-    --batch-probe, each counter scaled by what it reads for the 1 GiB copy."""
+    phase A and B apart: the last `sweeps` dispatches of each, the tuned
+    shape) from the FETCH_SIZE and WRITE_SIZE runs of --batch-probe, each
+    counter scaled by what it reads for the 1 GiB copy."""
+    import csv
     with open(probe_json) as f:
         probe = json.loads(f.read().strip().splitlines()[-1])
     cb = probe["copy_bytes_each_way"]
 
     def per_kernel(path, counter):
+        rows = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                    rows[key] = rows.get(key, 0.0) + float(r["Counter_Value"])
         sums, copy = {}, []
-        for name, v in _counter_rows(path, counter):
+        for (_, name), v in sorted(rows.items()):
             n = name.replace(" ", "")
             if "copyBuffer" in n:
                 copy.append(v)
@@ -1036,7 +1049,8 @@ def batch_traffic(probe_json, fetch_csv, write_csv):
                 continue
             mp = int(n.split(",")[1])
             phb = n.split(",")[3] == "true"
-            sums.setdefault((mp, phb), []).append(v)
+            sums.setdefault((mp, phb), []).append((v, n))
+        sums = {k: v[-probe["sweeps"]:] for k, v in sums.items()}
         copy = sorted(copy, reverse=True)[:3]   # the three 1 GiB copies
         return sums, (sum(copy) / len(copy) if copy else None)
 
@@ -1050,12 +1064,13 @@ def batch_traffic(probe_json, fetch_csv, write_csv):
             key = (int(m), phb)
             if key not in fetch or key not in write or fs is None or ws is None:
                 continue
-            f = sum(fetch[key]) / len(fetch[key])
-            w = sum(write[key]) / len(write[key])
+            f = sum(v for v, _ in fetch[key]) / len(fetch[key])
+            w = sum(v for v, _ in write[key]) / len(write[key])
             alg = c["phase_b_bytes" if phb else "phase_a_bytes"]
             hbm = f * 1024 * fs + w * 1024 * ws
             rows[f"m{m}_{'b' if phb else 'a'}"] = {
-                "dispatches": len(fetch[key]), "fetch_kib": round(f, 1), "write_kib": round(w, 1),
+                "kernel": fetch[key][-1][1], "dispatches": len(fetch[key]),
+                "fetch_kib": round(f, 1), "write_kib": round(w, 1),
                 "hbm_bytes": int(round(hbm)), "algorithmic_bytes": alg,
                 "ratio": round(hbm / alg, 4)}
     print(json.dumps({"fetch_scale": fs, "write_scale": ws, "launches": rows}, indent=1))

@@ -327,7 +327,10 @@ stc_status stc_promote(stc_handle *h);
  * A batch sweeps many independent chains (one handle each, of any L and m)
  * with one persistent launch per half-sweep, precision stage and padded
  * block size present: a work list of (chain, group of levels) items strided
- * over a fixed grid, plus one finalize workgroup per chain.  Each (precision
+ * over a fixed grid.  Each chain's sweep is reduced and recorded (scale,
+ * change, device stopping test) by one workgroup of the next sweep's phase-A
+ * launch, and the last sweep of each stc_batch_sweeps call by a finalize
+ * launch.  Each (precision
  * stage, block size) present runs all the sweeps of a stc_batch_sweeps call
  * (both phases and its chains' finalize, sweep after sweep) on a side stream
  * of the batch, forked from its stream once and joined back once, so the
@@ -348,7 +351,10 @@ size_t stc_batch_footprint(int32_t max_chains, int64_t max_items);
 
 /* Create a batch whose tables live in arena (caller-owned, 256-byte
  * aligned, >= stc_batch_footprint).  All its chains must have block
- * bandwidth b.  stream: the hipStream_t the batch launches on; NULL makes the
+ * bandwidth b.  max_items bounds the work items of one half-sweep over all
+ * chains: one per 1, 2 or 4 groups of levels (the tuned groups per item),
+ * plus one reduction item per chain in phase A; stc_batch_set fails with
+ * STC_EINVAL beyond it.  stream: the hipStream_t the batch launches on; NULL makes the
  * batch create (and later destroy) a non-blocking stream of its own, since a
  * graph cannot be captured on the null stream.  Work enqueued by
  * stc_batch_sweeps is ordered only on that stream: call stc_batch_sync

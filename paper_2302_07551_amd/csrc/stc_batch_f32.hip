@@ -3,5 +3,5 @@
 
 namespace stc {
 template hipError_t batch_phase_t<float>(int, int, bool, int, int, const ChainDesc *,
-                                      const WorkItem *, const int *, hipStream_t);
+                                      const WorkItem *, const int *, int, hipStream_t);
 }  // namespace stc

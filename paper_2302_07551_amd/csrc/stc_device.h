@@ -923,9 +923,19 @@ __global__ __launch_bounds__(kWG) void k_sweep_ell(SweepLaunch a, const EllEntry
 // at its own register count; one kernel for all sizes took the largest).
 // cls: {offset, count} of this block size's items in the work list (read
 // on the device, so a captured graph stays valid when the lists change).
+// j: the sweep's index in its burst; each chain produces sweep
+// s = burst_base + j (burst_base is fixed for the burst, so every workgroup
+// agrees on s while the reduction items below update the chain's state).
+// Phase A's first items (group < 0) reduce each chain's sweep s - 1 and
+// record it, beside the streaming items: sweep s reads the scale of sweep
+// s - 2 only, so the record of s - 1 is needed only from sweep s + 1 on.  A
+// stop recorded there (sweep s - 3 met the test) may leave sweep s partly
+// written; its buffer is not the stop sweep's, and sweep s + 1, which would
+// overwrite that, sees the stop flag at its start.
 template <typename T, int MP, int B, bool PHB, int RG, bool NT>
 __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
-                                                      const WorkItem *items, const int *cls) {
+                                                      const WorkItem *items, const int *cls,
+                                                      int j) {
     using TL = Tile<T, MP, RG>;
     __shared__ T red[TL::LPW * TL::R * MP];
     __shared__ T rv[TL::LPW * MP];
@@ -934,8 +944,19 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const WorkItem w = items[off + it];
         const ChainDesc &d = chains[w.chain];
-        const DevState *st = d.st;
-        const long long s = st->last_sweep + 1;
+        DevState *st = d.st;
+        const long long s = st->burst_base + j;
+        if (w.group < 0) {
+            if (!PHB && j > 0) {
+                double S, D;
+                const size_t prev = (size_t)((s - 1) & 1) * d.nparts;
+                partial_sums(d.part_sum + prev, d.part_diff + prev, d.groups_a + d.groups_b, true,
+                             sh, S, D);
+                if (threadIdx.x == 0) record_sweep(st, s - 1, S, D, d.tol);
+                __syncthreads();   // sh is reused by the next item
+            }
+            continue;
+        }
         const bool live = st->stop_flag == 0;
         ChainView<T> v;
         v.blk = (const T *)d.blk;
@@ -943,8 +964,8 @@ __global__ __launch_bounds__(kWG) void k_batch_sweep(const ChainDesc *chains,
         v.w_d1 = (const T *)d.w[(s + 2) & 3];    // W_{s-2}
         v.w_d2 = (const T *)d.w[(s + 1) & 3];    // W_{s-3}
         v.w_new = (T *)d.w[s & 3];
-        v.part_sum = d.part_sum;
-        v.part_diff = d.part_diff;
+        v.part_sum = d.part_sum + (size_t)(s & 1) * d.nparts;
+        v.part_diff = d.part_diff + (size_t)(s & 1) * d.nparts;
         v.st = st;
         v.L = d.L;
         v.parity = PHB ? 1 - d.parity_a : d.parity_a;

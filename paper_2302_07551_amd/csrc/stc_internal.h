@@ -34,6 +34,8 @@ struct DevState {
     long long test_after;     // changes of sweeps <= test_after are neither recorded
                               // nor tested (set at a precision switch: their
                               // iterates were overwritten after the FP32 stop)
+    long long burst_base;     // batched sweeps: the first sweep of the burst in
+                              // progress (sweep j of the burst is burst_base + j)
 };
 
 enum DevStatus { kDevOk = 0, kDevDegenerate = 1, kDevBadStart = 2, kDevTimeout = 3 };
@@ -73,9 +75,12 @@ struct SweepLaunch {
 //          kernel boundaries (same per-level arithmetic and reductions, so the
 //          same results bit for bit)
 // The row groups per level follow the block size: blocks of 64 and more take
-// 8 (bit 0 clear) or 4 (bit 0 set); smaller blocks take MP / 8 or MP / 16
-// (at least 1), so that a thread streams 8 or 16 rows of each block between
-// two workgroup barriers instead of 1 to 4.  Bit 3 is internal: the fixed
+// 8 (bit 0 clear) or 4 (bit 0 set); blocks of 16 and 32 take MP / 8 or
+// MP / 16, so that a thread streams 8 or 16 rows of each block between two
+// workgroup barriers instead of 1 to 4.  Blocks of 8 take 1 row group (bit 0
+// clear: a thread streams all 8 rows) or 4 (bit 0 set: a team's load then
+// covers 4 whole rows, 128 contiguous bytes in FP32, 256 in FP64, instead of
+// 32 or 64 bytes of each of 32 or 16 levels).  Bit 3 is internal: the fixed
 // 8-row-group tile of the sparse kernel.
 constexpr int kVariants = 8;
 constexpr int kMaxBandwidth = 4;   // block bandwidth b of the generators taken
@@ -83,7 +88,8 @@ constexpr int kEllGeometry = 8;
 __host__ __device__ constexpr int variant_rg(int MP, int v) {
     return (v & kEllGeometry) ? 8
            : MP >= 64         ? ((v & 1) ? 4 : 8)
-           : (v & 1)          ? (MP >= 32 ? MP / 16 : 1)
+           : MP == 8          ? ((v & 1) ? 4 : 1)
+           : (v & 1)          ? MP / 16
                               : MP / 8;
 }
 __host__ __device__ constexpr bool variant_nt(int v) { return (v & 2) != 0; }
@@ -153,12 +159,16 @@ struct ChainDesc {
     DevState *st;
     int L, MP, parity_a;  // levels, padded block size, first phase-A level
     int groups_a, groups_b;
+    int nparts;           // partial slots per sweep parity: sweep s uses
+                          // part_sum[(s & 1) * nparts ..]
     double tol;           // device change test for this chain (<= 0: off)
 };
 
 // One workgroup's work in a batched half-sweep: groups group .. group +
 // count - 1 of chain c, one after the other (each still writes its own
 // partial slot, so the number of groups per item does not change results).
+// group < 0 (phase A only, listed first): the reduction of the chain's
+// previous sweep, folded into this launch instead of a launch of its own.
 struct WorkItem {
     int chain;
     int group;
@@ -258,13 +268,18 @@ hipError_t launch_reset_state(DevState *st, hipStream_t stream);
 hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream);
 // One batched half-sweep launch of the chains of one padded block size:
 // variant bits 0 (row groups) and 1 (non-temporal loads) as for one chain.
+// j: the sweep's index in its burst (sweep burst_base + j of each chain).
 hipError_t launch_batch_phase(int precision_bytes, int b, int MP, bool phase_b, int variant,
                               int grid, const ChainDesc *chains, const WorkItem *items,
-                              const int *nitems, hipStream_t stream);
-// Finalize of chains[range[0] ..][0 .. range[1] - 1] (range on the device);
-// grid: at least the largest range[1] the launch may see.
-hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range,
+                              const int *nitems, int j, hipStream_t stream);
+// Finalize of sweep burst_base + j of chains[range[0] ..][0 .. range[1] - 1]
+// (range on the device); grid: at least the largest range[1] the launch may
+// see.
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range, int j,
                                  hipStream_t stream);
+// Start of a burst for the same chains: burst_base = last_sweep + 1.
+hipError_t launch_batch_begin(int grid, const ChainDesc *chains, const int *range,
+                              hipStream_t stream);
 int reduce_groups(int MP, int L);
 
 // Algorithm 1 (stc_jgs.hip): one sweep over `chunks` chunks of levels (the

@@ -20,17 +20,27 @@ __global__ __launch_bounds__(kWG) void k_finalize_sweep(const double *part_sum,
     finalize_chain(part_sum, part_diff, nslots, st, s, tol, sh);
 }
 
-// The per-chain finalize of a batch's chains chains[range[0] ..
-// range[0] + range[1] - 1], one workgroup per chain (the range is read on the
-// device, so a captured graph stays valid when the membership changes).
+// The finalize of sweep burst_base + j of a batch's chains chains[range[0]
+// .. range[0] + range[1] - 1], one workgroup per chain (the range is read on
+// the device, so a captured graph stays valid when the membership changes).
 __global__ __launch_bounds__(kWG) void k_batch_finalize(const ChainDesc *chains,
-                                                         const int *range) {
+                                                         const int *range, int j) {
     __shared__ double sh[4 * kWG / 64];
     if ((int)blockIdx.x >= range[1]) return;
     const ChainDesc &d = chains[range[0] + blockIdx.x];
     DevState *st = d.st;
-    finalize_chain(d.part_sum, d.part_diff, d.groups_a + d.groups_b, st, st->last_sweep + 1,
-                   d.tol, sh);
+    const long long s = st->burst_base + j;
+    const size_t p = (size_t)(s & 1) * d.nparts;
+    finalize_chain(d.part_sum + p, d.part_diff + p, d.groups_a + d.groups_b, st, s, d.tol, sh);
+}
+
+// Start of a burst of batched sweeps: each chain's sweeps are numbered from
+// the one after its last recorded sweep (one thread per chain).
+__global__ __launch_bounds__(kWG) void k_batch_begin(const ChainDesc *chains, const int *range) {
+    const int c = blockIdx.x * kWG + threadIdx.x;
+    if (c >= range[1]) return;
+    DevState *st = chains[range[0] + c].st;
+    st->burst_base = st->last_sweep + 1;
 }
 
 
@@ -138,6 +148,7 @@ __global__ void k_reset(DevState *st) {
         st->last_sweep = 0;
         st->residual = 0.0;
         st->test_after = 0;
+        st->burst_base = 1;
     }
 }
 
@@ -295,9 +306,16 @@ hipError_t launch_rearm(DevState *st, long long k, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range,
+hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *range, int j,
                                  hipStream_t stream) {
-    hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, range);
+    hipLaunchKernelGGL(k_batch_finalize, dim3(grid), dim3(kWG), 0, stream, chains, range, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_begin(int grid, const ChainDesc *chains, const int *range,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_begin, dim3((grid + kWG - 1) / kWG), dim3(kWG), 0, stream, chains,
+                       range);
     return hipGetLastError();
 }
 

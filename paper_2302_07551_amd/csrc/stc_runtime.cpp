@@ -2213,6 +2213,9 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
     // work lists per stage group and block size class, in chain order; the
     // chain table of each group holds the chains class by class
     std::vector<WorkItem> ia[2][kSizeClasses], ib[2][kSizeClasses];
+    // phase A lists start with one reduction item per chain (dispatched
+    // first, so they run beside the streaming items)
+    std::vector<WorkItem> fold_a[2][kSizeClasses];
     std::vector<int> order;
     for (int cls = 0; cls < kSizeClasses; ++cls)
         for (int c = 0; c < count; ++c)
@@ -2238,11 +2241,13 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
         d.parity_a = pA;
         d.groups_a = phase_groups(bytes, h->MP, h->L, pA, v);
         d.groups_b = phase_groups(bytes, h->MP, h->L, 1 - pA, v);
+        d.nparts = (int)h->lay.nparts;
         d.tol = timing ? 0.0 : (g == 1 && h->precision == STC_MIXED) ? h->switch_tol : tol;
         const int ci = (int)chains[g].size();
         if (cls_count[g][cls]++ == 0) cls_first[g][cls] = ci;
         chains[g].push_back(d);
         const int per = bt->tile[g][cls].per_item;
+        fold_a[g][cls].push_back({ci, -1, 0});
         for (int q = 0; q < d.groups_a; q += per)
             ia[g][cls].push_back({ci, q, std::min(per, d.groups_a - q)});
         for (int q = 0; q < d.groups_b; q += per)
@@ -2254,7 +2259,9 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
         for (int ph = 0; ph < 2; ++ph) {
             std::vector<WorkItem> all;
             for (int c = 0; c < kSizeClasses; ++c) {
-                const std::vector<WorkItem> &v = ph == 0 ? ia[g][c] : ib[g][c];
+                std::vector<WorkItem> v = ph == 0 ? fold_a[g][c] : std::vector<WorkItem>();
+                v.insert(v.end(), (ph == 0 ? ia[g][c] : ib[g][c]).begin(),
+                         (ph == 0 ? ia[g][c] : ib[g][c]).end());
                 hc[cnt_at(c, 2 * ph)] = (int)all.size();       // offset
                 hc[cnt_at(c, 2 * ph + 1)] = (int)v.size();     // count
                 hc[cnt_at(c, 4)] = cls_count[g][c] ? cls_first[g][c] : 0;
@@ -2285,11 +2292,13 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
 }
 
 // Enqueue n sweeps of every non-empty stage group.  Each (stage group,
-// block size) present runs its n sweeps (phase A, phase B, then the
-// per-chain finalize of its own chains) on a side stream of its own, forked
+// block size) present runs its n sweeps on a side stream of its own, forked
 // from the batch's stream once and joined back once: no chain depends on a
 // chain of another block size, so the branches need not meet between
-// sweeps, and each branch's launch gaps are filled by the others' work.
+// sweeps, and each branch's launch gaps are filled by the others' work.  A
+// branch numbers its chains' sweeps from their last recorded one, runs phase
+// A (whose reduction items record each chain's previous sweep) and phase B
+// per sweep, and a finalize launch records the burst's last sweep.
 // Captured, the burst is a graph with one chain of launches per branch; the
 // per-chain arithmetic does not depend on how the branches interleave.
 hipError_t enqueue_batch(stc_batch *bt, long long n) {
@@ -2304,6 +2313,8 @@ hipError_t enqueue_batch(stc_batch *bt, long long n) {
             const int br = g * kSizeClasses + c;
             hipStream_t sc = bt->side[br];
             e = hipStreamWaitEvent(sc, bt->fork, 0);
+            if (e == hipSuccess)
+                e = launch_batch_begin(bt->max_chains, bt->d_chains[g], dc + cnt_at(c, 4), sc);
             const BatchTile &t = bt->tile[g][c];
             for (long long j = 0; j < n && e == hipSuccess; ++j) {
                 for (int ph = 0; ph < 2 && e == hipSuccess; ++ph) {
@@ -2311,12 +2322,12 @@ hipError_t enqueue_batch(stc_batch *bt, long long n) {
                     e = launch_batch_phase(bytes, bt->b, 8 << c, ph == 1, tile_variant(bt, g, c),
                                            t.grid_per_cu * bt->cus, bt->d_chains[g],
                                            ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g],
-                                           dc + cnt_at(c, 2 * ph), sc);
+                                           dc + cnt_at(c, 2 * ph), (int)j, sc);
                 }
-                if (e == hipSuccess)
-                    e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], dc + cnt_at(c, 4),
-                                              sc);
             }
+            if (e == hipSuccess)
+                e = launch_batch_finalize(bt->max_chains, bt->d_chains[g], dc + cnt_at(c, 4),
+                                          (int)(n - 1), sc);
             if (e == hipSuccess) e = hipEventRecord(bt->join[br], sc);
             if (e == hipSuccess) e = hipStreamWaitEvent(bt->stream, bt->join[br], 0);
         }
@@ -2522,7 +2533,7 @@ stc_status stc_batch_get_tile(const stc_batch *bt, int32_t stage, int32_t mp, in
 }
 
 stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph) {
-    if (!bt || nsweeps < 0) return fail(STC_EINVAL, "bad argument");
+    if (!bt || nsweeps < 0 || nsweeps > INT32_MAX) return fail(STC_EINVAL, "bad argument");
     if (nsweeps == 0) return STC_OK;
     if (!use_graph) {
         HIP_TRY(enqueue_batch(bt, nsweeps));
