@@ -88,6 +88,7 @@ Other workloads (each prints its own JSON line instead):
 from __future__ import annotations
 
 import argparse
+import faulthandler
 import hashlib
 import json
 import os
@@ -205,6 +206,8 @@ def main():
     ap.add_argument("--batch-traffic", nargs=3, default=None)
     ap.add_argument("--variant", type=int, default=None)
     args = ap.parse_args()
+    # a fatal signal prints every thread's Python stack before the process ends
+    faulthandler.enable()
     if args.traffic_summary:
         return traffic_summary(*args.traffic_summary)
     if args.batch_traffic:

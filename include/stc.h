@@ -368,7 +368,9 @@ stc_status stc_batch_create(int32_t max_chains, int64_t max_items, int32_t b, vo
  * selects non-temporal block loads for the block sizes the batch has not
  * tuned (stc_batch_autotune).  Each chain takes the batch's launch variant for
  * its block size in both stages (its handle's stc_get_variant reports it), so
- * the chain swept alone does the same per-level arithmetic.  Synchronous. */
+ * the chain swept alone does the same per-level arithmetic.  Synchronous.
+ * On failure (STC_EINVAL: a bad handle, too many chains or work items) the
+ * batch is left with no chains. */
 stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, double tol,
                          int32_t nontemporal);
 

@@ -2253,41 +2253,56 @@ stc_status upload_lists(stc_batch *bt, double tol, bool timing = false) {
         for (int q = 0; q < d.groups_b; q += per)
             ib[g][cls].push_back({ci, q, std::min(per, d.groups_b - q)});
     }
+    // every host table is built (and checked) before the first copy, and
+    // lives until the copies are done: hipMemcpyAsync reads its host source
+    // until the copy completes
+    std::vector<WorkItem> lists[2][2];   // [stage group][phase]
+    int counts[2 * kCountsPerGroup] = {};
     for (int g = 0; g < 2; ++g) {
-        int *hc = bt->counts + g * kCountsPerGroup;
+        int *hc = counts + g * kCountsPerGroup;
         hc[0] = (int)chains[g].size();
         for (int ph = 0; ph < 2; ++ph) {
-            std::vector<WorkItem> all;
+            std::vector<WorkItem> &all = lists[g][ph];
             for (int c = 0; c < kSizeClasses; ++c) {
-                std::vector<WorkItem> v = ph == 0 ? fold_a[g][c] : std::vector<WorkItem>();
-                v.insert(v.end(), (ph == 0 ? ia[g][c] : ib[g][c]).begin(),
-                         (ph == 0 ? ia[g][c] : ib[g][c]).end());
+                const std::vector<WorkItem> &items = ph == 0 ? ia[g][c] : ib[g][c];
                 hc[cnt_at(c, 2 * ph)] = (int)all.size();       // offset
-                hc[cnt_at(c, 2 * ph + 1)] = (int)v.size();     // count
+                hc[cnt_at(c, 2 * ph + 1)] =                    // count
+                    (int)((ph == 0 ? fold_a[g][c].size() : 0) + items.size());
                 hc[cnt_at(c, 4)] = cls_count[g][c] ? cls_first[g][c] : 0;
                 hc[cnt_at(c, 5)] = cls_count[g][c];
-                all.insert(all.end(), v.begin(), v.end());
+                if (ph == 0) all.insert(all.end(), fold_a[g][c].begin(), fold_a[g][c].end());
+                all.insert(all.end(), items.begin(), items.end());
             }
             if ((long long)all.size() > bt->max_items)
                 return fail(STC_EINVAL, "work list of %zu items exceeds max_items %lld", all.size(),
                             bt->max_items);
-            if (!all.empty())
-                HIP_TRY(hipMemcpyAsync(ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g], all.data(),
-                                       all.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                                       bt->stream));
         }
-        if (!chains[g].empty())
-            HIP_TRY(hipMemcpyAsync(bt->d_chains[g], chains[g].data(), chains[g].size() * sizeof(ChainDesc),
-                                   hipMemcpyHostToDevice, bt->stream));
     }
-    HIP_TRY(hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
-                           bt->stream));
     std::vector<DevState *> states(count);
     for (int c = 0; c < count; ++c) states[c] = bt->members[c]->st;
-    if (count > 0)
-        HIP_TRY(hipMemcpyAsync(bt->d_states, states.data(), sizeof(DevState *) * count,
-                               hipMemcpyHostToDevice, bt->stream));
-    HIP_TRY(hipStreamSynchronize(bt->stream));
+    std::copy(counts, counts + 2 * kCountsPerGroup, bt->counts);
+    hipError_t e = hipSuccess;
+    for (int g = 0; g < 2 && e == hipSuccess; ++g) {
+        for (int ph = 0; ph < 2 && e == hipSuccess; ++ph)
+            if (!lists[g][ph].empty())
+                e = hipMemcpyAsync(ph == 0 ? bt->d_items_a[g] : bt->d_items_b[g],
+                                   lists[g][ph].data(), lists[g][ph].size() * sizeof(WorkItem),
+                                   hipMemcpyHostToDevice, bt->stream);
+        if (e == hipSuccess && !chains[g].empty())
+            e = hipMemcpyAsync(bt->d_chains[g], chains[g].data(),
+                               chains[g].size() * sizeof(ChainDesc), hipMemcpyHostToDevice,
+                               bt->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_counts, bt->counts, sizeof(bt->counts), hipMemcpyHostToDevice,
+                           bt->stream);
+    if (e == hipSuccess && count > 0)
+        e = hipMemcpyAsync(bt->d_states, states.data(), sizeof(DevState *) * count,
+                           hipMemcpyHostToDevice, bt->stream);
+    // also after a failed enqueue: the copies already queued read the tables
+    const hipError_t es = hipStreamSynchronize(bt->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return fail(STC_EDEVICE, "batch tables: %s", hipGetErrorString(e));
     return STC_OK;
 }
 
@@ -2450,7 +2465,16 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
     bt->nt = nt;
     bt->tol = tol;
     bt->members.assign(hs, hs + count);
-    return upload_lists(bt, tol);
+    const stc_status rc = upload_lists(bt, tol);
+    if (rc != STC_OK) {
+        // leave a consistent, empty batch (the device tables of the earlier
+        // members are not kept beside a member list they do not match)
+        bt->members.clear();
+        std::string why = stc_last_error();
+        (void)upload_lists(bt, tol);
+        return fail(rc, "%s", why.c_str());
+    }
+    return STC_OK;
 }
 
 stc_status stc_batch_autotune(stc_batch *bt, int32_t trial_sweeps, double *ms_per_sweep) {

@@ -13,9 +13,16 @@ status STC_EMAXIT (its last iterate is returned).  A request whose setup
 fails (not a generator, a singular diagonal block, a bad shape) or whose
 sweeps lose all mass is rejected on its own; the service goes on.
 Setup of new chains (host validation and packing, upload, inverse of the
-diagonal blocks) runs on a host thread of its own and a side stream while
-the batch sweeps on its own stream, so arrivals overlap with the work
-already on the GPU.
+diagonal blocks) runs on a side stream while the batch sweeps, so that
+arrivals overlap with the work already on the GPU.  By default
+(setup_thread=False) the serving thread does it itself, right after it has
+enqueued a round of sweeps and before it waits for them; the requests set
+up join the next round.  setup_thread=True moves setup to a host thread of
+its own.  That form is off by default: twice it ended in a segmentation
+fault of the process inside the batch's graph capture and launch
+(stc_batch_sweeps) on the serving thread while the setup thread was inside
+stc_setup, in runs of the 512-request stream with Poisson arrivals.  With
+one thread driving the device, no call into the runtime overlaps another.
 
 Every step of the method runs in libstc.so; this module schedules calls.
 """
@@ -93,12 +100,15 @@ class Server:
     nontemporal: stream the blocks with non-temporal loads (the admitted
     chains together exceed the last-level cache under any useful budget).
     max_sweeps: sweeps (both stages) after which a request that has not met
-    its tolerance is retired with STC_EMAXIT."""
+    its tolerance is retired with STC_EMAXIT.
+    setup_thread: set up admitted requests on a host thread of their own
+    (see the module notes) instead of between rounds."""
 
     def __init__(self, budget_bytes: int, *, max_chains: int = 64, max_items: int = 1 << 17,
                  sweeps_per_round: int = 20, tol: float = 1e-13, switch_tol: float = 1e-6,
                  precision: str = "mixed", nontemporal: bool = True, device=None,
-                 b: int = 1, use_graph: bool = True, max_sweeps: int = 1_000_000):
+                 b: int = 1, use_graph: bool = True, max_sweeps: int = 1_000_000,
+                 setup_thread: bool = False):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -110,6 +120,7 @@ class Server:
         self.nontemporal = bool(nontemporal)
         self.use_graph = use_graph
         self.max_sweeps = int(max_sweeps)
+        self.setup_thread = bool(setup_thread)
         self.device = torch.device(device if device is not None else "cuda")
         self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = stc.Batch(self.max_chains, max_items, b=b, device=self.device)
@@ -178,12 +189,15 @@ class Server:
         active = []          # [request, solver, footprint, admitted_at, stage(, fp32 sweeps)]
         fps = {}
         used = 0
-        in_setup = 0         # admitted, handed to the setup thread, not yet active
+        in_setup = 0         # admitted, not yet set up or not yet active
+        to_setup = []        # inline setup: admitted requests to set up this round
         stats = ServeStats()
         todo: queue.Queue = queue.Queue()
         ready: queue.Queue = queue.Queue()
-        worker = threading.Thread(target=self._setup_worker, args=(todo, ready), daemon=True)
-        worker.start()
+        worker = None
+        if self.setup_thread:
+            worker = threading.Thread(target=self._setup_worker, args=(todo, ready), daemon=True)
+            worker.start()
         t0 = clock()
         dirty = False
 
@@ -201,13 +215,25 @@ class Server:
             active.append([req, s, fp, clock() - t0, 32 if self.precision != "fp64" else 64])
             dirty = True
 
+        def setup_inline():
+            """Set up the requests admitted for inline setup (their solvers, or
+            the errors their setup raised, go to `ready`)."""
+            for req, fp in to_setup:
+                try:
+                    s = self._admit(req)
+                    self.setup_stream.synchronize()
+                    ready.put((req, s, fp, None))
+                except Exception as e:          # reported by the serving loop
+                    ready.put((req, None, fp, e))
+            to_setup.clear()
+
         try:
             while pending or waiting or active or in_setup:
                 now = clock() - t0
                 while pending and pending[0].arrival <= now:
                     waiting.append(pending.popleft())
                 # admission in arrival order (budget and free slots); setup runs
-                # on the setup thread
+                # on the setup thread, or inline while this round sweeps
                 while waiting and len(active) + in_setup < self.max_chains:
                     req = waiting[0]
                     fp = fps.get(req.rid)
@@ -225,7 +251,10 @@ class Server:
                     waiting.popleft()
                     used += fp
                     in_setup += 1
-                    todo.put((req, fp))
+                    if worker is not None:
+                        todo.put((req, fp))
+                    else:
+                        to_setup.append((req, fp))
                 # chains whose setup finished join this round
                 while True:
                     try:
@@ -236,7 +265,10 @@ class Server:
                 stats.peak_chains = max(stats.peak_chains, len(active))
                 stats.peak_bytes = max(stats.peak_bytes, used)
                 if not active:
-                    if in_setup:
+                    if to_setup:
+                        # nothing to sweep: set the admitted requests up now
+                        setup_inline()
+                    elif in_setup:
                         # nothing to sweep: wait for the setup thread
                         join(ready.get())
                     elif pending:
@@ -248,6 +280,10 @@ class Server:
                     self.batch.set([a[1] for a in active], self.tol, self.nontemporal)
                     dirty = False
                 self.batch.sweeps(self.K, self.use_graph)     # asynchronous
+                # the requests admitted this round are set up while the batch
+                # sweeps (same host thread; the GPU runs both); they join the
+                # next round
+                setup_inline()
                 # one device-to-host copy for every chain's stopping state
                 sweeps, stopped, _diffs, status = self.batch.query()
                 stats.rounds += 1
@@ -285,9 +321,11 @@ class Server:
                     dirty = True
                 active = keep
         finally:
-            todo.put(None)
-            worker.join()
+            if worker is not None:
+                todo.put(None)
+                worker.join()
             # on an early exit, release every chain still held
+            to_setup.clear()
             for entry in active:
                 entry[1].close()
             while True:

@@ -423,8 +423,13 @@ class Batch:
         _live_batches.add(self)
 
     def set(self, solvers, tol: float, nontemporal: bool = False):
-        self.members = list(solvers)
-        stc_batch_set(self.bt, [s.h for s in self.members], tol, nontemporal)
+        solvers = list(solvers)
+        try:
+            stc_batch_set(self.bt, [s.h for s in solvers], tol, nontemporal)
+        except StcError:
+            self.members = []      # the library leaves the batch empty
+            raise
+        self.members = solvers
 
     def sweeps(self, n: int, use_graph: bool = True):
         stc_batch_sweeps(self.bt, n, use_graph)

