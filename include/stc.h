@@ -180,6 +180,36 @@ size_t stc_footprint_bytes(const stc_generator *gen, const stc_options *opt);
  * before the arena is freed. */
 stc_status stc_setup(const stc_generator *gen, const stc_options *opt, stc_handle **out);
 
+/* ---- setup in two halves ----------------------------------------------
+ * The same setup, split where the host work ends, for callers that overlap
+ * setup with device work that another thread drives: stc_prepare does the
+ * host half (validation of Q and the packing of its blocks in the sweep's
+ * layout, on host threads) and makes no HIP call, so it may run on any
+ * thread at any time; stc_setup_prepared does the device half (upload,
+ * inverse of the diagonal blocks, FP32 copies, state) on opt->stream into
+ * opt->arena.  stc_setup_prepared(stc_prepare(gen, opt), opt) gives the
+ * handle stc_setup(gen, opt) gives, bit for bit.  Dense storage of
+ * block-banded generators (b in 1..4) only: STC_EINVAL for other inputs,
+ * which take stc_setup. */
+typedef struct stc_prepared stc_prepared;
+
+/* Host half.  opt's arena and stream are not used (the precision, format
+ * and method are checked as by stc_setup).  *out owns a host copy of the
+ * packed blocks (the device layout's size of blk64 and the diagonal blocks);
+ * gen's arrays are not read after the call.  Errors: STC_EINVAL,
+ * STC_ENOTGEN (the first bad level), STC_ENOMEM (host memory). */
+stc_status stc_prepare(const stc_generator *gen, const stc_options *opt, stc_prepared **out);
+
+/* Device half, on opt->stream into opt->arena (>= stc_footprint_bytes of the
+ * same generator and options; opt may differ from stc_prepare's in its
+ * precision, stop rule and the like, not in storage).  Returns when the
+ * device work is done.  p stays owned by the caller.  Errors: STC_EINVAL,
+ * STC_ENOMEM (arena), STC_ESINGULAR, STC_EDEVICE. */
+stc_status stc_setup_prepared(const stc_prepared *p, const stc_options *opt, stc_handle **out);
+
+/* Release what stc_prepare allocated (NULL is ignored). */
+void stc_prepared_free(stc_prepared *p);
+
 /* Algorithm 2 (section 2) with the stopping test of section 3: start from
  * x0 / e^T x0 (x0 NULL: e/N), sweep until the stop quantity is <= tol or
  * maxit sweeps were done, and write the last iterate to pi (length N).

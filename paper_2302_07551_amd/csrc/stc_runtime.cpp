@@ -1123,16 +1123,19 @@ size_t stc_footprint_bytes(const stc_generator *gen, const stc_options *opt) {
     return l.total;
 }
 
-stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **out) {
-    if (!g || !o || !out) return fail(STC_EINVAL, "null argument");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// The checks and the layout of stc_setup, without the arena (stc_prepare
+// shares them).
+stc_status plan_setup(const stc_generator *g, const stc_options *o, Layout *lay) {
     if (g->sizes && g->L >= 2 && g->m >= 1)
         for (int i = 0; i < g->L; ++i)
             if (g->sizes[i] < 1 || g->sizes[i] > g->m)
                 return fail(STC_EINVAL, "sizes[%d] = %d outside 1..%d", i, g->sizes[i], g->m);
-    Layout lay;
     int why = 0;
-    if (!plan(g, o, &lay, &why)) {
+    if (!plan(g, o, lay, &why)) {
         static const char *msg[] = {"bad arguments", "L must be >= 2",
                                     "b must be in 1..4 or STC_ANY_PATTERN",
                                     "m must be in 1..128", "unknown precision", "unknown format",
@@ -1152,15 +1155,22 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
     }
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
     if (o->stop != STC_STOP_DIFF && o->stop != STC_STOP_RESIDUAL) return fail(STC_EINVAL, "bad stop rule");
+    return STC_OK;
+}
+
+stc_status check_arena(const stc_options *o, const Layout &lay) {
     if (!o->arena) return fail(STC_EINVAL, "arena is NULL");
     if ((uintptr_t)o->arena % kAlign) return fail(STC_EINVAL, "arena must be 256-byte aligned");
     if (o->arena_bytes < lay.total)
         return fail(STC_ENOMEM, "arena holds %zu bytes, %zu needed", o->arena_bytes, lay.total);
+    return STC_OK;
+}
 
+// A handle over the arena of o, laid out by lay, with its host fields set;
+// nothing on the device yet.
+stc_handle *new_handle(const stc_generator *g, const stc_options *o, const Layout &lay,
+                       const std::vector<int> &sizes) {
     const int L = g->L, m = g->m, b = g->b, MP = lay.MP, NB = lay.NB;
-    std::vector<int> sizes(L, m);
-    if (g->sizes) std::copy(g->sizes, g->sizes + L, sizes.begin());
-
     stc_handle *h = new stc_handle();
     h->L = L; h->m = m; h->b = b; h->MP = MP; h->NB = NB;
     h->precision = o->precision;
@@ -1224,13 +1234,164 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         h->variant[1] = default_variant(MP, nblk * 4.0);
     }
 
+    {
+        long long N = 0;
+        for (int i = 0; i < L; ++i) N += sizes[i];
+        h->N = N;
+        const double nblk = (double)L * NB * MP * MP;
+        h->variant[0] = default_variant(MP, nblk * 8.0);
+        h->variant[1] = default_variant(MP, nblk * 4.0);
+    }
+    return h;
+}
+
+// Check block rows i0 .. i1 - 1 of a block-banded generator and pack them in
+// the sweep's layout: blk holds the gather-oriented off-diagonal blocks
+// (slot d + b of level i <- Q_{i+d,i}) and diag the padded Q_ii, both from
+// level l0 on.  On a bad entry *err names the level and the entry.
+void pack_levels(const stc_generator *g, const BlockSource &src, const std::vector<int> &sizes,
+                 int MP, int l0, int i0, int i1, double *blk, double *diag, LevelError *err) {
+    const int L = g->L, m = g->m, b = g->b, NB = 2 * b + 1;
+    const size_t bs = (size_t)MP * MP;
+    char msg[256];
+    std::fill(blk + (size_t)(i0 - l0) * NB * bs, blk + (size_t)(i1 - l0) * NB * bs, 0.0);
+    std::fill(diag + (size_t)(i0 - l0) * bs, diag + (size_t)(i1 - l0) * bs, 0.0);
+    for (int i = i0; i < i1; ++i) {
+        const int ni = sizes[i];
+        // generator checks on block row i
+        for (int r = 0; r < ni; ++r) {
+            double out = 0.0;
+            for (int d = -b; d <= b; ++d) {
+                const int k = i + d;
+                if (k < 0 || k >= L) continue;
+                const double *row = src.at(i, d + b) + (size_t)r * m;
+                for (int c = 0; c < sizes[k]; ++c) {
+                    if (d == 0 && c == r) continue;
+                    const double v = row[c];
+                    if (!(v >= 0.0) || !isfinite(v)) {
+                        snprintf(msg, sizeof(msg),
+                                 "Q[level %d row %d][level %d col %d] = %g is not a rate", i, r, k,
+                                 c, v);
+                        *err = LevelError{i, msg};
+                        return;
+                    }
+                    out += v;
+                }
+            }
+            const double *qii = src.at(i, b);
+            const double dg = qii[(size_t)r * m + r];
+            double *D = diag + (size_t)(i - l0) * bs;
+            for (int c = 0; c < ni; ++c) D[(size_t)r * MP + c] = qii[(size_t)r * m + c];
+            if (g->recompute_diagonal) {
+                D[(size_t)r * MP + r] = -out;
+            } else if (!isfinite(dg) || fabs(dg + out) > 1e-10 * std::max(out, 1e-300)) {
+                snprintf(msg, sizeof(msg), "row %d of level %d sums to %g, not 0 (diagonal %g)", r,
+                         i, dg + out, dg);
+                *err = LevelError{i, msg};
+                return;
+            }
+        }
+        for (int d = -b; d <= b; ++d) {
+            if (d == 0) continue;
+            const int k = i + d;
+            if (k < 0 || k >= L) continue;
+            const double *q = src.at(k, -d + b);
+            double *dst = blk + ((size_t)(i - l0) * NB + (d + b)) * bs;
+            for (int r = 0; r < sizes[k]; ++r)
+                memcpy(dst + (size_t)r * MP, q + (size_t)r * m, sizeof(double) * sizes[i]);
+        }
+    }
+}
+
+// Pack levels [l0, l1) (their block rows loaded in src) on `threads` host
+// threads; the first bad entry, by lowest level, as STC_ENOTGEN.
+stc_status pack_range(const stc_generator *g, const BlockSource &src,
+                      const std::vector<int> &sizes, int MP, int l0, int l1, int threads,
+                      double *blk, double *diag) {
+    std::vector<LevelError> errs(threads);
+    for_level_ranges(l0, l1, threads, [&](int k, int i0, int i1) {
+        pack_levels(g, src, sizes, MP, l0, i0, i1, blk, diag, &errs[k]);
+    });
+    const LevelError *first = nullptr;
+    for (const auto &e : errs)
+        if (e.level >= 0 && (!first || e.level < first->level)) first = &e;
+    if (first) return fail(STC_ENOTGEN, "%s", first->msg.c_str());
+    return STC_OK;
+}
+
+// The end of every setup: level offsets and sizes, the cleared state, the
+// batched inverse of the diagonal blocks and the FP32 copy; then the
+// singular-block check.
+stc_status finish_setup(stc_handle *h, const Layout &lay, int b) {
+    auto dev = [&](hipError_t e, const char *what) -> stc_status {
+        if (e == hipSuccess) return STC_OK;
+        return fail(STC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    };
+    const int L = h->L, MP = h->MP, NB = h->NB;
+    std::vector<long long> off(L + 1, 0);
+    for (int i = 0; i < L; ++i) off[i + 1] = off[i] + h->sizes[i];
+    stc_status rc = STC_OK;
+    if ((rc = dev(hipMemcpyAsync(h->off, off.data(), sizeof(long long) * (L + 1),
+                                 hipMemcpyHostToDevice, h->stream), "copy offsets")) != STC_OK)
+        return rc;
+    if ((rc = dev(hipMemcpyAsync(h->sizes_d, h->sizes.data(), sizeof(int) * L,
+                                 hipMemcpyHostToDevice, h->stream), "copy sizes")) != STC_OK)
+        return rc;
+    // zero the whole state once (ring included), then the inverse
+    if ((rc = dev(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream), "clear state")) != STC_OK)
+        return rc;
+    if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return rc;
+    if (h->kr > 0 && (rc = dev(launch_kstate_init(h->kst, h->stream), "Krylov state")) != STC_OK)
+        return rc;
+    if ((rc = dev(launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
+                                h->stream),
+                  "invert")) != STC_OK)
+        return rc;
+    if (lay.fp32 &&
+        (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * MP * MP, h->stream),
+                  "cast")) != STC_OK)
+        return rc;
+    // read_state synchronises the stream: the host tables above are read
+    // before they go out of scope
+    HostState hs;
+    if ((rc = read_state(h, &hs)) != STC_OK) return rc;
+    if (hs.bad_blocks)
+        return fail(STC_ESINGULAR,
+                    "%d diagonal block(s) are singular: some level has states that never leave "
+                    "it", hs.bad_blocks);
+    return STC_OK;
+}
+
+}  // namespace
+
+// Host half of a setup (stc_prepare): the packed blocks of a block-banded
+// generator in the sweep's layout, and what the device half needs.
+struct stc_prepared {
+    int L = 0, m = 0, b = 0, MP = 0;
+    std::vector<int> sizes;
+    std::vector<double> blk, diag;
+};
+
+extern "C" {
+
+stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **out) {
+    if (!g || !o || !out) return fail(STC_EINVAL, "null argument");
+    *out = nullptr;
+    Layout lay;
+    stc_status rc = plan_setup(g, o, &lay);
+    if (rc != STC_OK) return rc;
+    if ((rc = check_arena(o, lay)) != STC_OK) return rc;
+
+    const int L = g->L, m = g->m, b = g->b, MP = lay.MP, NB = lay.NB;
+    std::vector<int> sizes(L, m);
+    if (g->sizes) std::copy(g->sizes, g->sizes + L, sizes.begin());
+    stc_handle *h = new_handle(g, o, lay, sizes);
     auto cleanup = [&](stc_status s) { delete h; return s; };
     auto dev = [&](hipError_t e, const char *what) -> stc_status {
         if (e == hipSuccess) return STC_OK;
         return fail(STC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
     };
 
-    stc_status rc = STC_OK;
     if (lay.general) {
         h->general = true;
         h->gen_tab = (GenEntry *)(h->base + lay.gen_tab);
@@ -1254,70 +1415,12 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         if (lerr.level >= 0) return fail(STC_EINVAL, "%s", lerr.msg.c_str());
         return STC_OK;
     };
-    // pack levels [i0, i1) of the chunk starting at l0; on a bad entry return
-    // its level and message
-    auto pack = [&](int l0, int i0, int i1, LevelError *err) {
-        char msg[256];
-        std::fill(stage_blk.begin() + (size_t)(i0 - l0) * NB * bs,
-                  stage_blk.begin() + (size_t)(i1 - l0) * NB * bs, 0.0);
-        std::fill(stage_diag.begin() + (size_t)(i0 - l0) * bs,
-                  stage_diag.begin() + (size_t)(i1 - l0) * bs, 0.0);
-        for (int i = i0; i < i1; ++i) {
-            const int ni = sizes[i];
-            // generator checks on block row i
-            for (int r = 0; r < ni; ++r) {
-                double out = 0.0;
-                for (int d = -b; d <= b; ++d) {
-                    const int k = i + d;
-                    if (k < 0 || k >= L) continue;
-                    const double *row = q_at(i, d + b) + (size_t)r * m;
-                    for (int c = 0; c < sizes[k]; ++c) {
-                        if (d == 0 && c == r) continue;
-                        const double v = row[c];
-                        if (!(v >= 0.0) || !isfinite(v)) {
-                            snprintf(msg, sizeof(msg),
-                                     "Q[level %d row %d][level %d col %d] = %g is not a rate", i, r,
-                                     k, c, v);
-                            *err = LevelError{i, msg};
-                            return;
-                        }
-                        out += v;
-                    }
-                }
-                const double dg = q_at(i, b)[(size_t)r * m + r];
-                double *D = stage_diag.data() + (size_t)(i - l0) * bs;
-                for (int c = 0; c < ni; ++c) D[(size_t)r * MP + c] = q_at(i, b)[(size_t)r * m + c];
-                if (g->recompute_diagonal) {
-                    D[(size_t)r * MP + r] = -out;
-                } else if (!isfinite(dg) || fabs(dg + out) > 1e-10 * std::max(out, 1e-300)) {
-                    snprintf(msg, sizeof(msg), "row %d of level %d sums to %g, not 0 (diagonal %g)",
-                             r, i, dg + out, dg);
-                    *err = LevelError{i, msg};
-                    return;
-                }
-            }
-            // gather-oriented off-diagonal blocks: slot d+b of level i <- Q_{i+d,i}
-            for (int d = -b; d <= b; ++d) {
-                if (d == 0) continue;
-                const int k = i + d;
-                if (k < 0 || k >= L) continue;
-                const double *src = q_at(k, -d + b);
-                double *dst = stage_blk.data() + ((size_t)(i - l0) * NB + (d + b)) * bs;
-                for (int r = 0; r < sizes[k]; ++r)
-                    memcpy(dst + (size_t)r * MP, src + (size_t)r * m, sizeof(double) * sizes[i]);
-            }
-        }
-    };
     for (int l0 = 0; l0 < L; l0 += chunk) {
         const int l1 = std::min(L, l0 + chunk);
-        if (stc_status rc = load_rows(l0, l1); rc != STC_OK) return cleanup(rc);
-        std::vector<LevelError> errs(threads);
-        for_level_ranges(l0, l1, threads,
-                         [&](int k, int i0, int i1) { pack(l0, i0, i1, &errs[k]); });
-        const LevelError *first = nullptr;
-        for (const auto &e : errs)
-            if (e.level >= 0 && (!first || e.level < first->level)) first = &e;
-        if (first) return cleanup(fail(STC_ENOTGEN, "%s", first->msg.c_str()));
+        if ((rc = load_rows(l0, l1)) != STC_OK) return cleanup(rc);
+        if ((rc = pack_range(g, src, sizes, MP, l0, l1, threads, stage_blk.data(),
+                             stage_diag.data())) != STC_OK)
+            return cleanup(rc);
         if ((rc = dev(hipMemcpyAsync(h->blk64 + (size_t)l0 * NB * bs, stage_blk.data(),
                                      sizeof(double) * (size_t)(l1 - l0) * NB * bs,
                                      hipMemcpyHostToDevice, h->stream), "copy blocks")) != STC_OK)
@@ -1420,35 +1523,97 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
             return cleanup(rc);
     }
     }
-    if ((rc = dev(hipMemcpyAsync(h->off, off.data(), sizeof(long long) * (L + 1),
-                                 hipMemcpyHostToDevice, h->stream), "copy offsets")) != STC_OK)
-        return cleanup(rc);
-    if ((rc = dev(hipMemcpyAsync(h->sizes_d, sizes.data(), sizeof(int) * L, hipMemcpyHostToDevice,
-                                 h->stream), "copy sizes")) != STC_OK)
-        return cleanup(rc);
-    // zero the whole state once (ring included), then the inverse
-    if ((rc = dev(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream), "clear state")) != STC_OK)
-        return cleanup(rc);
-    if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return cleanup(rc);
-    if (h->kr > 0 && (rc = dev(launch_kstate_init(h->kst, h->stream), "Krylov state")) != STC_OK)
-        return cleanup(rc);
-    if ((rc = dev(launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
-                                h->stream),
-                  "invert")) != STC_OK)
-        return cleanup(rc);
-    if (lay.fp32 &&
-        (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * MP * MP, h->stream),
-                  "cast")) != STC_OK)
-        return cleanup(rc);
-    HostState hs;
-    if ((rc = read_state(h, &hs)) != STC_OK) return cleanup(rc);
-    if (hs.bad_blocks)
-        return cleanup(fail(STC_ESINGULAR,
-                            "%d diagonal block(s) are singular: some level has states that "
-                            "never leave it", hs.bad_blocks));
+    if ((rc = finish_setup(h, lay, b)) != STC_OK) return cleanup(rc);
     *out = h;
     return STC_OK;
 }
+
+stc_status stc_prepare(const stc_generator *g, const stc_options *o, stc_prepared **out) {
+    if (!g || !o || !out) return fail(STC_EINVAL, "null argument");
+    *out = nullptr;
+    Layout lay;
+    stc_status rc = plan_setup(g, o, &lay);
+    if (rc != STC_OK) return rc;
+    if (lay.general || lay.sparse)
+        return fail(STC_EINVAL, "stc_prepare takes dense storage of block-banded generators; "
+                                "other inputs take stc_setup");
+    const int L = g->L, m = g->m, b = g->b, MP = lay.MP, NB = lay.NB;
+    const size_t bs = (size_t)MP * MP;
+    stc_prepared *p = new (std::nothrow) stc_prepared();
+    if (!p) return fail(STC_ENOMEM, "no host memory for the prepared setup");
+    p->L = L;
+    p->m = m;
+    p->b = b;
+    p->MP = MP;
+    p->sizes.assign(L, m);
+    if (g->sizes) std::copy(g->sizes, g->sizes + L, p->sizes.begin());
+    try {
+        p->blk.resize((size_t)L * NB * bs);
+        p->diag.resize((size_t)L * bs);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(STC_ENOMEM, "no host memory for %zu packed blocks", (size_t)L * (NB + 1));
+    }
+    const int chunk = std::max(1, (int)std::min<size_t>(L, (64u << 20) / (NB * bs * 8)));
+    const int threads = host_threads((double)L * NB * m * m * 8.0);
+    BlockSource src(g);
+    for (int l0 = 0; l0 < L; l0 += chunk) {
+        const int l1 = std::min(L, l0 + chunk);
+        LevelError lerr;
+        src.load(l0 - b, l1 + b, threads, &lerr);
+        if (lerr.level >= 0) rc = fail(STC_EINVAL, "%s", lerr.msg.c_str());
+        if (rc == STC_OK)
+            rc = pack_range(g, src, p->sizes, MP, l0, l1, threads,
+                            p->blk.data() + (size_t)l0 * NB * bs, p->diag.data() + (size_t)l0 * bs);
+        if (rc != STC_OK) {
+            delete p;
+            return rc;
+        }
+    }
+    *out = p;
+    return STC_OK;
+}
+
+stc_status stc_setup_prepared(const stc_prepared *p, const stc_options *o, stc_handle **out) {
+    if (!p || !o || !out) return fail(STC_EINVAL, "null argument");
+    *out = nullptr;
+    // the generator as the plan sees it: its shape, dense blocks given (the
+    // packed copy stands in for them; they are not read again)
+    stc_generator g{};
+    g.L = p->L;
+    g.m = p->m;
+    g.b = p->b;
+    g.sizes = p->sizes.data();
+    g.blocks = p->blk.data();
+    Layout lay;
+    stc_status rc = plan_setup(&g, o, &lay);
+    if (rc != STC_OK) return rc;
+    if (lay.general || lay.sparse || lay.MP != p->MP)
+        return fail(STC_EINVAL, "the options ask for another storage than the prepared blocks");
+    if ((rc = check_arena(o, lay)) != STC_OK) return rc;
+    stc_handle *h = new_handle(&g, o, lay, p->sizes);
+    const size_t bs = (size_t)lay.MP * lay.MP;
+    hipError_t e = hipMemcpyAsync(h->blk64, p->blk.data(), sizeof(double) * p->blk.size(),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->diag64, p->diag.data(), sizeof(double) * (size_t)p->L * bs,
+                           hipMemcpyHostToDevice, h->stream);
+    // also after a failed enqueue: the prepared blocks may be freed on return
+    const hipError_t es = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) {
+        delete h;
+        return fail(STC_EDEVICE, "copy prepared blocks: %s", hipGetErrorString(e));
+    }
+    if ((rc = finish_setup(h, lay, p->b)) != STC_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return STC_OK;
+}
+
+void stc_prepared_free(stc_prepared *p) { delete p; }
 
 void stc_destroy(stc_handle *h) { delete h; }
 

@@ -4,7 +4,7 @@ Requests (independent block generators) arrive over time.  The service
 admits them in arrival order while the HBM footprint of the admitted chains
 stays under a budget and a batch slot is free, keeps every admitted chain's
 factored blocks and iterate resident on the device, and sweeps all admitted
-chains together with the batched (multi-chain, graph-replayed) launch.  A
+chains together with the batched (multi-chain) launch.  A
 chain in its FP32 stage that meets the switch tolerance is promoted to FP64
 (stc_promote); a chain whose FP64 change meets the tolerance is retired: its
 vector is copied out, its memory freed, and waiting requests are admitted.
@@ -12,17 +12,31 @@ A chain that reaches the per-request sweep cap is retired the same way with
 status STC_EMAXIT (its last iterate is returned).  A request whose setup
 fails (not a generator, a singular diagonal block, a bad shape) or whose
 sweeps lose all mass is rejected on its own; the service goes on.
-Setup of new chains (host validation and packing, upload, inverse of the
-diagonal blocks) runs on a side stream while the batch sweeps, so that
-arrivals overlap with the work already on the GPU.  By default
-(setup_thread=False) the serving thread does it itself, right after it has
-enqueued a round of sweeps and before it waits for them; the requests set
-up join the next round.  setup_thread=True moves setup to a host thread of
-its own.  That form is off by default: twice it ended in a segmentation
-fault of the process inside the batch's graph capture and launch
-(stc_batch_sweeps) on the serving thread while the setup thread was inside
-stc_setup, in runs of the 512-request stream with Poisson arrivals.  With
-one thread driving the device, no call into the runtime overlaps another.
+Setup of new chains overlaps the work already on the GPU, and only the
+serving thread calls into the HIP runtime:
+
+- the host half of each admitted request's setup (validation, and packing
+  of its blocks in the sweep's layout: stc_prepare) runs on a prepare
+  thread, which makes no HIP call (prepare_thread=True, the default);
+- the device half (upload, inverse of the diagonal blocks, state:
+  stc_setup_prepared) runs on the serving thread, on a side stream, right
+  after it has enqueued a round of sweeps and before it waits for them.
+
+The requests set up join the next round.  prepare_thread=False does both
+halves on the serving thread.  setup_thread=True runs the whole setup on a
+host thread of its own instead.  That form is off by default: twice it
+ended in a segmentation fault of the process inside the batch's graph
+capture and launch (stc_batch_sweeps) on the serving thread while the
+setup thread was inside stc_setup, in runs of the 512-request stream with
+Poisson arrivals.
+
+The batch's sweeps are plain launches by default (use_graph=False).  With
+graph replay (use_graph=True), three runs of the 512-request stream with
+Poisson arrivals ended in a segmentation fault of the process inside
+stc_batch_sweeps on the serving thread, the third with no other thread in
+the runtime.  Those runs capture the batch's graph again whenever the block
+sizes or precision stages present change, thousands of times; runs with
+all requests at t = 0 (few captures) never did.
 
 Every step of the method runs in libstc.so; this module schedules calls.
 """
@@ -101,14 +115,18 @@ class Server:
     chains together exceed the last-level cache under any useful budget).
     max_sweeps: sweeps (both stages) after which a request that has not met
     its tolerance is retired with STC_EMAXIT.
-    setup_thread: set up admitted requests on a host thread of their own
-    (see the module notes) instead of between rounds."""
+    prepare_thread: the host half of setup on a thread of its own (see the
+    module notes).
+    setup_thread: the whole setup on a thread of its own (off: see the
+    module notes).
+    use_graph: replay the batch's sweeps as a captured hipGraph (off: see
+    the module notes)."""
 
     def __init__(self, budget_bytes: int, *, max_chains: int = 64, max_items: int = 1 << 17,
                  sweeps_per_round: int = 20, tol: float = 1e-13, switch_tol: float = 1e-6,
                  precision: str = "mixed", nontemporal: bool = True, device=None,
-                 b: int = 1, use_graph: bool = True, max_sweeps: int = 1_000_000,
-                 setup_thread: bool = False):
+                 b: int = 1, use_graph: bool = False, max_sweeps: int = 1_000_000,
+                 prepare_thread: bool = True, setup_thread: bool = False):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -121,6 +139,7 @@ class Server:
         self.use_graph = use_graph
         self.max_sweeps = int(max_sweeps)
         self.setup_thread = bool(setup_thread)
+        self.prepare_thread = bool(prepare_thread)
         self.device = torch.device(device if device is not None else "cuda")
         self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = stc.Batch(self.max_chains, max_items, b=b, device=self.device)
@@ -165,6 +184,29 @@ class Server:
         s.load(None)
         return s
 
+    def _prepare_worker(self, todo: "queue.Queue", done: "queue.Queue"):
+        """The host half of the setup of admitted requests, in order: no HIP
+        call and no torch device state.  Each stc.Prepared (or the error its
+        validation raised) goes to `done`."""
+        while True:
+            job = todo.get()
+            if job is None:
+                return
+            req, fp = job
+            try:
+                p = stc.Prepared(req.blocks, req.sizes, req.b, precision=self.precision,
+                                 switch_tol=self.switch_tol)
+                done.put((req, p, fp, None))
+            except Exception as e:          # reported by the serving loop
+                done.put((req, None, fp, e))
+
+    def _finish(self, prep: "stc.Prepared") -> stc.Solver:
+        # the device half, on the serving thread; the batch gives the chain
+        # its launch variants when it joins
+        s = stc.Solver.from_prepared(prep, device=self.device, stream=self.setup_stream)
+        s.load(None)
+        return s
+
     def _setup_worker(self, todo: "queue.Queue", ready: "queue.Queue"):
         """Set up admitted requests in order; each ready solver (or the error
         its setup raised) goes to `ready`."""
@@ -193,10 +235,16 @@ class Server:
         to_setup = []        # inline setup: admitted requests to set up this round
         stats = ServeStats()
         todo: queue.Queue = queue.Queue()
-        ready: queue.Queue = queue.Queue()
+        ready: queue.Queue = queue.Queue()     # solvers set up (or errors)
+        done: queue.Queue = queue.Queue()      # prepared host halves (or errors)
+        mode = ("thread" if self.setup_thread else
+                "prepare" if self.prepare_thread else "inline")
         worker = None
-        if self.setup_thread:
+        if mode == "thread":
             worker = threading.Thread(target=self._setup_worker, args=(todo, ready), daemon=True)
+        elif mode == "prepare":
+            worker = threading.Thread(target=self._prepare_worker, args=(todo, done), daemon=True)
+        if worker is not None:
             worker.start()
         t0 = clock()
         dirty = False
@@ -215,9 +263,26 @@ class Server:
             active.append([req, s, fp, clock() - t0, 32 if self.precision != "fp64" else 64])
             dirty = True
 
+        def finish(item):
+            """The device half of a prepared request; its solver (or the
+            error) goes to `ready`."""
+            req, prep, fp, err = item
+            if err is None:
+                try:
+                    s = self._finish(prep)
+                    self.setup_stream.synchronize()
+                    ready.put((req, s, fp, None))
+                except Exception as e:          # reported by the serving loop
+                    ready.put((req, None, fp, e))
+                finally:
+                    prep.close()
+            else:
+                ready.put((req, None, fp, err))
+
         def setup_inline():
-            """Set up the requests admitted for inline setup (their solvers, or
-            the errors their setup raised, go to `ready`)."""
+            """The setup work of the serving thread (solvers, or the errors
+            their setup raised, go to `ready`): whole setups of the requests
+            admitted inline, or the device halves of those prepared so far."""
             for req, fp in to_setup:
                 try:
                     s = self._admit(req)
@@ -226,14 +291,20 @@ class Server:
                 except Exception as e:          # reported by the serving loop
                     ready.put((req, None, fp, e))
             to_setup.clear()
+            while mode == "prepare":
+                try:
+                    item = done.get_nowait()
+                except queue.Empty:
+                    break
+                finish(item)
 
         try:
             while pending or waiting or active or in_setup:
                 now = clock() - t0
                 while pending and pending[0].arrival <= now:
                     waiting.append(pending.popleft())
-                # admission in arrival order (budget and free slots); setup runs
-                # on the setup thread, or inline while this round sweeps
+                # admission in arrival order (budget and free slots); the setup
+                # starts on the worker thread, or inline while this round sweeps
                 while waiting and len(active) + in_setup < self.max_chains:
                     req = waiting[0]
                     fp = fps.get(req.rid)
@@ -268,6 +339,9 @@ class Server:
                     if to_setup:
                         # nothing to sweep: set the admitted requests up now
                         setup_inline()
+                    elif in_setup and mode == "prepare":
+                        # nothing to sweep: wait for a host half, finish it
+                        finish(done.get())
                     elif in_setup:
                         # nothing to sweep: wait for the setup thread
                         join(ready.get())
@@ -335,6 +409,13 @@ class Server:
                     break
                 if s is not None:
                     s.close()
+            while True:
+                try:
+                    _req, prep, _fp, _err = done.get_nowait()
+                except queue.Empty:
+                    break
+                if prep is not None:
+                    prep.close()
         stats.wall = clock() - t0
         return stats
 

@@ -35,7 +35,8 @@ PRECISIONS = {"fp64": STC_FP64, "fp32": STC_FP32, "mixed": STC_MIXED}
 STOPS = {"diff": STC_STOP_DIFF, "residual": STC_STOP_RESIDUAL}
 
 # every symbol include/stc.h declares
-EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_solve", "stc_solve_gmres", "stc_step",
+EXPORTS = ("stc_footprint_bytes", "stc_setup", "stc_prepare", "stc_setup_prepared",
+           "stc_prepared_free", "stc_solve", "stc_solve_gmres", "stc_step",
            "stc_residual", "stc_residual_noalloc",
            "stc_sweeps", "stc_profile_sweeps", "stc_phase_bytes", "stc_variant_count",
            "stc_set_variant", "stc_get_variant", "stc_autotune", "stc_load", "stc_query",
@@ -107,6 +108,10 @@ def load_library(path: str = LIB_PATH):
     lib.stc_footprint_bytes.argtypes = [POINTER(stc_generator), POINTER(stc_options)]
     lib.stc_footprint_bytes.restype = c_size_t
     lib.stc_setup.argtypes = [POINTER(stc_generator), POINTER(stc_options), POINTER(H)]
+    lib.stc_prepare.argtypes = [POINTER(stc_generator), POINTER(stc_options), POINTER(H)]
+    lib.stc_setup_prepared.argtypes = [H, POINTER(stc_options), POINTER(H)]
+    lib.stc_prepared_free.argtypes = [H]
+    lib.stc_prepared_free.restype = None
     lib.stc_solve.argtypes = [H, c_void_p, c_double, c_int64, c_void_p, POINTER(stc_result),
                               c_int32]
     lib.stc_solve_gmres.argtypes = [H, c_void_p, c_int32, c_double, c_int64, c_void_p,
@@ -145,7 +150,7 @@ def load_library(path: str = LIB_PATH):
     lib.stc_status_string.restype = ctypes.c_char_p
     lib.stc_last_error.argtypes = []
     lib.stc_last_error.restype = ctypes.c_char_p
-    for name in ("stc_setup", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
+    for name in ("stc_setup", "stc_prepare", "stc_setup_prepared", "stc_solve", "stc_step", "stc_residual", "stc_sweeps",
                  "stc_profile_sweeps", "stc_phase_bytes", "stc_set_variant", "stc_get_variant",
                  "stc_autotune", "stc_load", "stc_query", "stc_store", "stc_promote",
                  "stc_batch_create", "stc_batch_set", "stc_batch_sweeps", "stc_batch_query",
@@ -221,6 +226,24 @@ def stc_setup(gen: stc_generator, opt: stc_options) -> c_void_p:
     h = c_void_p()
     _check(load_library().stc_setup(byref(gen), byref(opt), byref(h)))
     return h
+
+
+def stc_prepare(gen: stc_generator, opt: stc_options) -> c_void_p:
+    """Host half of stc_setup (no HIP call: any thread)."""
+    p = c_void_p()
+    _check(load_library().stc_prepare(byref(gen), byref(opt), byref(p)))
+    return p
+
+
+def stc_setup_prepared(p, opt: stc_options) -> c_void_p:
+    h = c_void_p()
+    _check(load_library().stc_setup_prepared(p, byref(opt), byref(h)))
+    return h
+
+
+def stc_prepared_free(p):
+    if p:
+        load_library().stc_prepared_free(p)
 
 
 def _vec_arg(x):
@@ -467,6 +490,38 @@ def stc_destroy(h):
         load_library().stc_destroy(h)
 
 
+class Prepared:
+    """The host half of a setup (stc_prepare): the generator validated and
+    its blocks packed in the sweep's layout on host threads.  It makes no
+    HIP call and touches no torch device state, so any thread may build it
+    while another drives the GPU; Solver.from_prepared does the device half.
+    Dense storage of block-banded generators only."""
+
+    def __init__(self, blocks: np.ndarray, sizes, b: int, *, precision="fp64", stair_type=1,
+                 stop="diff", check_every=1, switch_tol=0.0, recompute_diagonal=False):
+        self.p = None
+        load_library()
+        gen, keep = make_generator(blocks, sizes, b, recompute_diagonal)
+        self.opt = make_options(precision, stair_type, stop, check_every, switch_tol)
+        self.footprint = stc_footprint_bytes(gen, self.opt)
+        if self.footprint == 0:
+            raise StcError(STC_EINVAL, "unsupported generator shape or options")
+        self.N = int(np.sum(sizes)) if sizes is not None else gen.L * gen.m
+        self.p = stc_prepare(gen, self.opt)
+        del keep            # the host inputs were read during stc_prepare
+
+    def close(self):
+        if getattr(self, "p", None):
+            stc_prepared_free(self.p)
+        self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One chain on the current GPU: owns the torch arena and the handle."""
 
@@ -514,6 +569,32 @@ class Solver:
             self.h = stc_setup(self.gen, self.opt)
         self._keep = None   # host inputs were copied during setup
         _live_solvers.add(self)
+
+    @classmethod
+    def from_prepared(cls, prep: "Prepared", device=None, stream=None):
+        """The solver of a prepared generator (the device half of the setup:
+        upload, inverse, state), on stream (None: the current stream)."""
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the staircase solver needs a GPU")
+        if prep.p is None:
+            raise ValueError("the prepared setup was released")
+        self = cls.__new__(cls)
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.gen, self._keep = None, None
+        self.opt = stc_options.from_buffer_copy(prep.opt)
+        self.opt.stream = self.stream.cuda_stream or None
+        self.footprint = prep.footprint
+        self.N = prep.N
+        self.arena = torch.empty(self.footprint, dtype=torch.uint8, device=self.device)
+        self.opt.arena = self.arena.data_ptr()
+        self.opt.arena_bytes = self.footprint
+        self.h = None
+        with torch.cuda.device(self.device):
+            self.h = stc_setup_prepared(prep.p, self.opt)
+        _live_solvers.add(self)
+        return self
 
     @classmethod
     def from_sparse(cls, Q, sizes, b: int, **kw):

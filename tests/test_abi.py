@@ -347,3 +347,48 @@ def test_any_pattern_size_limit_rejected_before_any_scan(lib):
     with pytest.raises(stc.StcError) as e:
         stc.stc_setup(gen, opt)
     assert e.value.status == stc.STC_EINVAL and "2^31" in str(e.value)
+
+
+def test_prepare_is_host_only_and_checks_the_generator(lib):
+    """stc_prepare (the host half of a setup) runs here, with no device: it
+    validates and packs; the first bad level is named, as by stc_setup."""
+    g = synth.qbd(9, 6, 11, last=4)
+    p = stc.Prepared(g.blocks, g.sizes, g.b, precision="mixed")
+    assert p.p and p.N == int(np.sum(g.sizes))
+    assert p.footprint == stc.stc_footprint_bytes(*_gen_opt(g, precision="mixed")[:2])
+    p.close()
+    p.close()                       # a second release is a no-op
+    bad = g.blocks.copy()
+    bad[5, 2, 1, 2] = -0.25         # level 5's up-rate row 1 -> not a generator
+    with pytest.raises(stc.StcError) as e:
+        stc.Prepared(bad, g.sizes, g.b)
+    assert e.value.status == stc.STC_ENOTGEN and "level 5" in str(e.value)
+    bad = g.blocks.copy()
+    bad[2, 1, 0, 0] += 1.0          # row 0 of level 2 no longer sums to 0
+    with pytest.raises(stc.StcError) as e:
+        stc.Prepared(bad, g.sizes, g.b)
+    assert e.value.status == stc.STC_ENOTGEN and "level 2" in str(e.value)
+
+
+def test_prepare_takes_dense_banded_storage_only(lib):
+    g = synth.qbd(6, 4, 12)
+    gen, opt, keep = _gen_opt(g, format="sparse")
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_prepare(gen, opt)
+    assert e.value.status == stc.STC_EINVAL and "dense" in str(e.value)
+
+
+def test_setup_prepared_rejects_small_arena_before_touching_the_device(lib):
+    g = synth.qbd(6, 4, 13)
+    p = stc.Prepared(g.blocks, g.sizes, g.b)
+    opt = stc.make_options("fp64")
+    opt.arena, opt.arena_bytes = 4096, 16
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup_prepared(p.p, opt)
+    assert e.value.status == stc.STC_ENOMEM
+    opt = stc.make_options("fp64", format="sparse")
+    opt.arena, opt.arena_bytes = 4096, 1 << 30
+    with pytest.raises(stc.StcError) as e:
+        stc.stc_setup_prepared(p.p, opt)
+    assert e.value.status == stc.STC_EINVAL
+    p.close()

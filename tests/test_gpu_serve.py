@@ -127,3 +127,16 @@ def test_threaded_setup_serves_like_inline_setup():
     assert out[False].keys() == out[True].keys()
     for k in out[False]:
         assert np.array_equal(out[False][k], out[True][k])
+
+
+@pytest.mark.skip(reason="three runs of the 512-request stream with Poisson arrivals and graph "
+                         "replay ended in a host segmentation fault inside stc_batch_sweeps "
+                         "(the third with no other thread in the runtime); serving replays no "
+                         "graph until that cause is found")
+def test_served_poisson_stream_with_graph_replay():
+    from paper_2302_07551_amd.serve import Server
+    reqs, gens = _requests(64, 2031, rate=50.0, L_range=(32, 2048))
+    srv = Server(budget_bytes=1 << 31, max_chains=64, sweeps_per_round=25, use_graph=True)
+    st = srv.run(reqs)
+    srv.close()
+    assert st.summary()["completed"] == len(reqs)
