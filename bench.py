@@ -32,9 +32,10 @@ Prints one JSON line.  Options:
 Other workloads (each prints its own JSON line instead):
   --qbd4096       the 4096 x 64 FP64 QBD (N = 262,144): sweep GB/s, time to
                   ||Q^T pi||_1 <= 1e-12 (FP64 vs mixed), the oracle's CPU sweep
-  --serve N       served stream of N QBD requests (512 is the served workload) (levels U{32..2048}, m in
-                  {8,16,32,64}): saturated solves/s, then Poisson arrivals at
-                  0.5x and 0.8x of it, p50/p99 latency; mixed vs FP64
+  --serve N       served stream of N QBD requests (512 is the served
+                  workload; levels U{32..2048}, m in {8,16,32,64}): saturated
+                  solves/s and latency, mixed vs FP64; with --serve-poisson
+                  also Poisson arrivals at 0.5x and 0.8x of that rate
   --banded        2048 levels x m=128 block-pentadiagonal generator with 10 %
                   dense off-diagonal blocks: sweeps/s and GB/s with dense and
                   sparse (ELL) off-diagonal storage, FP64 and FP32, and the
@@ -44,8 +45,8 @@ Other workloads (each prints its own JSON line instead):
                   with dense and sparse storage, FP64 and FP32, and the time
                   to a change of 1e-13 against the direct solution
   --mutex         the mutual-exclusion model (16 processes, at most 12 users,
-                  N = 64839) as a generator of any block pattern, m = 128 and
-                  64: sweeps/s, time to the change tolerance 1e-9 and 1e-13,
+                  N = 64839) as a generator of any block pattern, m = 128, 64
+                  and 256: sweeps/s, time to the change tolerance 1e-9 and 1e-13,
                   errors against the closed-form stationary vector
   --example3 T   Example 3: T random singular M-matrices in banded block lower
                   Hessenberg form (16 blocks of 64), partitions of 16, 32 and
@@ -836,9 +837,10 @@ def mutex_cpu_baseline(gen, budget_s: float = 10.0):
 def mutex_mode(args, n=16, r=12):
     """The mutual-exclusion model at the paper's size (N = 64839, a generator
     whose nonzero blocks reach ~100 levels from the diagonal at m = 128):
-    sweep rates of the any-pattern kernels for two block sizes, time to the
-    paper's change tolerance and beyond, errors against the closed form, and
-    the oracle's sweep time on the host."""
+    sweep rates of the any-pattern kernels for three block sizes (256 is the
+    paper's own partition of this model), time to the paper's change
+    tolerance and beyond, errors against the closed form, and the oracle's
+    sweep time on the host."""
     import numpy as np
     import torch
     import synth
@@ -846,7 +848,7 @@ def mutex_mode(args, n=16, r=12):
     torch.cuda.set_device(0)
     seed = synth.config_seed(3)
     rates, solves, shape = {}, {}, {}
-    for m in (128, 64):
+    for m in (128, 64, 256):
         gen = synth.mutual_exclusion(n, r, seed, m=m)
         exact = synth.mutual_exclusion_pi(gen)
         shape[f"m{m}"] = {"L": gen.L, "block_reach": gen.block_reach(), "nnz": gen.nnz}

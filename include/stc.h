@@ -90,7 +90,8 @@ enum { STC_STAIRCASE = 0, STC_JGS = 1 };               /* stc_options.method    
  * stc_setup, and the caller keeps ownership. */
 typedef struct {
     int32_t L;                   /* levels, >= 2                                    */
-    int32_t m;                   /* block size: max states per level, 1..128       */
+    int32_t m;                   /* block size: max states per level, 1..128
+                                    (1..256 with b = STC_ANY_PATTERN)            */
     int32_t b;                   /* block bandwidth, 1..4 (1: QBD), or
                                     STC_ANY_PATTERN                                 */
     const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */

@@ -1275,14 +1275,17 @@ __device__ __forceinline__ void invert_diag_tile(const double *a, const double *
     if (!(piv > 1e-13 * dorig[k0 + c]) || !isfinite(piv)) *bad = 1;
 }
 
-template <int MP, int NW = inv_waves(MP)>   // NW: waves per workgroup
+// GLOBAL (blocks above 128, whose 512 KB do not fit in LDS): the same
+// elimination in place in the output block W_i, in global memory (the
+// workgroup's barriers order its accesses; the block stays in L2).
+template <int MP, int NW = inv_waves(MP), bool GLOBAL = (MP > 128)>   // NW: waves per workgroup
 __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, const int *sizes,
                                                       double *blk, int NB, int B, DevState *st) {
-    constexpr int LD = MP + 2;      // row stride in LDS (doubles)
+    constexpr int LD = GLOBAL ? MP : MP + 2;   // row stride of the working block (doubles)
     constexpr int NT = MP / 16;     // panels
     constexpr int DL = 17;          // stride of the 16x16 tile
     static_assert(NW >= 2, "the lookahead wave needs partners for the trailing update");
-    __shared__ double a[MP * LD];
+    __shared__ double a_lds[GLOBAL ? 1 : MP * LD];
     __shared__ double dinv[2][16 * DL];   // D^{-1} of this panel and of the next
     __shared__ double dorig[MP];
     __shared__ int bad;
@@ -1291,8 +1294,21 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
     const int i = blockIdx.x;
     const int n = sizes[i];
     const double *Q = diag + (size_t)i * MP * MP;
+    double *W = blk + ((size_t)i * NB + B) * MP * MP;
+    double *a;
+    if constexpr (GLOBAL)
+        a = W;
+    else
+        a = a_lds;
     if (tid == 0) bad = 0;
-    {
+    if constexpr (GLOBAL) {
+        for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
+            const int r = idx / MP, c = idx - r * MP;
+            const double v = (r < n && c < n) ? -Q[idx] : (r == c ? 1.0 : 0.0);
+            a[idx] = v;
+            if (r == c) dorig[r] = v;
+        }
+    } else {
         // every load of the thread's share issued before the first LDS store
         // (the block is stored padded to MP x MP, so all of it is readable)
         constexpr int PER = MP * MP / (64 * NW);
@@ -1428,12 +1444,19 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
         }
         __syncthreads();
     }
-    double *W = blk + ((size_t)i * NB + B) * MP * MP;
+    if constexpr (GLOBAL) {
+        // the inverse is in place: clear the padding
+        for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
+            const int r = idx / MP, c = idx - r * MP;
+            if (!(r < n && c < n)) W[idx] = 0.0;
+        }
+    } else {
 #pragma unroll
-    for (int u = 0; u < MP * MP / (64 * NW); ++u) {
-        const int idx = tid + u * 64 * NW;
-        const int r = idx / MP, c = idx - r * MP;
-        W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
+        for (int u = 0; u < MP * MP / (64 * NW); ++u) {
+            const int idx = tid + u * 64 * NW;
+            const int r = idx / MP, c = idx - r * MP;
+            W[idx] = (r < n && c < n) ? a[r * LD + c] : 0.0;
+        }
     }
     if (tid == 0 && bad) atomicAdd(&st->bad_blocks, 1);
 }
@@ -1460,6 +1483,7 @@ static int lpw_of(int MP, int v) {
         case 32: return lpw_mp<T, 32>(v);
         case 64: return lpw_mp<T, 64>(v);
         case 128: return lpw_mp<T, 128>(v);
+        case 256: return lpw_mp<T, 256>(v);
     }
     return 1;
 }

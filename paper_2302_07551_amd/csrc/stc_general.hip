@@ -230,7 +230,10 @@ __global__ __launch_bounds__(kWG) void k_residual_gen(const double *diag, const 
     if (active) {
         const double *gb = diag + (size_t)i * BS + c * VEC;
         const T *v = w + (size_t)i * MP;
-#pragma unroll
+        // unrolled 32 rows at a time (blocks of 256 stream 128 rows per
+        // thread; unrolled whole they would spill); the sum's order is the same
+        constexpr int UR = RPT > 32 ? 32 : RPT;
+#pragma unroll UR
         for (int qq = 0; qq < RPT; ++qq) {
             const int row = g + R * qq;
             const VT bv = stream_load<VT, true>((const VT *)(gb + (size_t)row * MP));
@@ -288,6 +291,7 @@ static hipError_t gen_t(int MP, bool phase_b, const SweepLaunch &a, const GenEnt
         case 32: return gen_mp<T, 32, NT>(phase_b, a, tab, val, idx, s, t);
         case 64: return gen_mp<T, 64, NT>(phase_b, a, tab, val, idx, s, t);
         case 128: return gen_mp<T, 128, NT>(phase_b, a, tab, val, idx, s, t);
+        case 256: return gen_mp<T, 256, NT>(phase_b, a, tab, val, idx, s, t);
     }
     return hipErrorInvalidValue;
 }
@@ -321,6 +325,7 @@ static hipError_t residual_gen_t(int MP, int groups, const double *diag, const G
         case 32: residual_gen_mp<T, 32>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
         case 64: residual_gen_mp<T, 64>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
         case 128: residual_gen_mp<T, 128>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
+        case 256: residual_gen_mp<T, 256>(groups, diag, tab, val, idx, w, L, st, slot, part, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

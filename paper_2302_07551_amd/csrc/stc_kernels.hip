@@ -158,7 +158,7 @@ __global__ void k_reset(DevState *st) {
 // host launchers
 // ---------------------------------------------------------------------------
 int supported_mp(int m) {
-    if (m < 1 || m > 128) return 0;
+    if (m < 1 || m > 256) return 0;
     int mp = 8;
     while (mp < m) mp <<= 1;
     return mp;
@@ -275,6 +275,7 @@ hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, do
         case 32: return invert_mp<32>(b, diag, sizes, blk, L, st, stream);
         case 64: return invert_mp<64>(b, diag, sizes, blk, L, st, stream);
         case 128: return invert_mp<128>(b, diag, sizes, blk, L, st, stream);
+        case 256: return invert_mp<256>(b, diag, sizes, blk, L, st, stream);
     }
     return hipErrorInvalidValue;
 }
@@ -414,6 +415,7 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
             case 32: e = diff_mp<double, 32>(variant_rg(32, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
             case 64: e = diff_mp<double, 64>(variant_rg(64, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
             case 128: e = diff_mp<double, 128>(variant_rg(128, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 256: e = diff_mp<double, 256>(variant_rg(256, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
         }
     } else {
         switch (MP) {
@@ -422,6 +424,7 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
             case 32: e = diff_mp<float, 32>(variant_rg(32, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
             case 64: e = diff_mp<float, 64>(variant_rg(64, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
             case 128: e = diff_mp<float, 128>(variant_rg(128, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
+            case 256: e = diff_mp<float, 256>(variant_rg(256, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
         }
     }
     if (e != hipSuccess) return e;

@@ -318,7 +318,8 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     const bool general = g->b == STC_ANY_PATTERN;
     if (!general && (g->b < 1 || g->b > kMaxBandwidth)) { *why = 2; return false; }
     const int MP = supported_mp(g->m);
-    if (!MP) { *why = 3; return false; }
+    // blocks of 256: generators of any pattern only (the banded kernels stop at 128)
+    if (!MP || (MP > 128 && !general)) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
     if (o->format != STC_DENSE && o->format != STC_SPARSE) { *why = 5; return false; }
     if (!g->blocks && !(g->csr_rowptr && g->csr_col && g->csr_val)) { *why = 6; return false; }
@@ -1138,7 +1139,8 @@ stc_status plan_setup(const stc_generator *g, const stc_options *o, Layout *lay)
     if (!plan(g, o, lay, &why)) {
         static const char *msg[] = {"bad arguments", "L must be >= 2",
                                     "b must be in 1..4 or STC_ANY_PATTERN",
-                                    "m must be in 1..128", "unknown precision", "unknown format",
+                                    "m must be in 1..128 (1..256 for STC_ANY_PATTERN)",
+                                    "unknown precision", "unknown format",
                                     "neither blocks nor a complete CSR input given",
                                     "give blocks or CSR input, not both",
                                     "CSR row pointers must start at 0 and never fall",
@@ -2711,7 +2713,7 @@ stc_status stc_batch_autotune(stc_batch *bt, int32_t trial_sweeps, double *ms_pe
 
 stc_status stc_batch_get_tile(const stc_batch *bt, int32_t stage, int32_t mp, int32_t *variant,
                               int32_t *groups_per_item, int32_t *grid) {
-    if (!bt || (stage != STC_FP64 && stage != STC_FP32) || supported_mp(mp) != mp)
+    if (!bt || (stage != STC_FP64 && stage != STC_FP32) || mp > 128 || supported_mp(mp) != mp)
         return fail(STC_EINVAL, "need a batch, stage STC_FP64 or STC_FP32 and mp in 8, 16, 32, "
                                 "64, 128");
     const int g = stage == STC_FP32 ? 1 : 0, c = class_of(mp);

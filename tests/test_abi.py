@@ -392,3 +392,27 @@ def test_setup_prepared_rejects_small_arena_before_touching_the_device(lib):
         stc.stc_setup_prepared(p.p, opt)
     assert e.value.status == stc.STC_EINVAL
     p.close()
+
+
+def test_blocks_of_256_only_for_any_pattern(lib):
+    """m up to 256 is taken by generators of any block pattern only; the
+    banded kernels stop at 128."""
+    g = synth.qbd(4, 4, 2)
+    gen, opt, _ = _gen_opt(g)
+    gen.m = 200
+    assert stc.stc_footprint_bytes(gen, opt) == 0
+    import scipy.sparse as sp
+    N, m = 600, 256
+    Q = sp.random(N, N, density=0.01, random_state=3, format="csr")
+    Q.setdiag(0.0)
+    Q.setdiag(-np.asarray(Q.sum(axis=1)).ravel())
+    Q = Q.tocsr()
+    Q.sort_indices()
+    sizes = np.array([256, 256, 88], dtype=np.int32)
+    gen, keep = stc.make_generator_csr(Q.indptr, Q.indices, Q.data, sizes, stc.STC_ANY_PATTERN, m,
+                                       False)
+    opt = stc.make_options("fp64", format="sparse")
+    fp = stc.stc_footprint_bytes(gen, opt)
+    assert fp >= 3 * m * m * 8          # the three 256 x 256 inverses
+    gen.m = 257
+    assert stc.stc_footprint_bytes(gen, opt) == 0

@@ -61,6 +61,10 @@ GENERAL = [
     ("loc_L7_m128", lambda: synth.localized(7, 128, 7, up=2, down=6, jumps=1, density=0.03)),
     ("mutex_n8_r5_m16", lambda: synth.mutual_exclusion(8, 5, 3, m=16)),
     ("mutex_n10_r6_m32", lambda: synth.mutual_exclusion(10, 6, 4, m=32)),
+    # blocks of 256 (the paper's own partition size for this model)
+    ("loc_L5_m256_ragged", lambda: synth.localized(5, 256, 15, up=2, down=2, jumps=1,
+                                                   ragged=True, density=0.02)),
+    ("mutex_n11_r7_m256", lambda: synth.mutual_exclusion(11, 7, 16, m=256)),
 ]
 
 
@@ -185,18 +189,20 @@ def test_batch_rejects_any_pattern_chains():
     s.close()
 
 
-def test_mutex_full_size_step_and_solve():
+@pytest.mark.parametrize("m", [128, 256])
+def test_mutex_full_size_step_and_solve(m):
     """The mutual-exclusion model at the paper's size (16 processes, at most
-    12 users: N = 64839, 507 levels of 128 states, nonzero blocks up to 106
-    levels from the diagonal), in the launch configuration the benchmark
-    times: one sweep against the oracle, then a solve to the paper's change
-    tolerance 1e-9 and on to 1e-13, checked against the closed form."""
-    g = synth.mutual_exclusion(16, 12, synth.config_seed(3))
+    12 users: N = 64839; 507 levels of 128 states, nonzero blocks up to 106
+    levels from the diagonal, or the paper's own partition into 254 levels
+    of 256), in the launch configuration the benchmark times: one sweep
+    against the oracle, then a solve to the paper's change tolerance 1e-9
+    and on to 1e-13, checked against the closed form."""
+    g = synth.mutual_exclusion(16, 12, synth.config_seed(3), m=m)
     x = _start(g, 9)
     s = _solver(g)
     z, d = s.step(x)
     zr, dr = staircase.staircase_sweep(_system(g), x, 1)
-    _say(f"mutex full step: |z-zr|_1 = {np.abs(z - zr).sum():.2e}")
+    _say(f"mutex full step m={m}: |z-zr|_1 = {np.abs(z - zr).sum():.2e}")
     assert np.abs(z - zr).sum() <= 1e-13 and abs(d - dr) <= 1e-13
     exact = mutex_closed_form(g)
     pi, info = s.solve(tol=1e-9, maxit=10_000)
@@ -242,11 +248,13 @@ def test_load_policies_agree_and_default_by_size():
     s.close()
 
 
-def test_any_pattern_singular_diagonal_block():
+@pytest.mark.parametrize("m", [8, 256])
+def test_any_pattern_singular_diagonal_block(m):
     """A level whose states can never leave it makes Q_ii singular: setup
-    reports STC_ESINGULAR (the inverse kernel's pivot check)."""
+    reports STC_ESINGULAR (the inverse kernel's pivot check; at m = 256 the
+    elimination in global memory)."""
     from paper_2302_07551_amd import stc
-    g = synth.localized(6, 8, 21, up=1, down=1, jumps=0, backbone=0.0)
+    g = synth.localized(6, m, 21, up=1, down=1, jumps=0, backbone=0.0)
     Q = g.to_scipy().tolil()
     off = g.offsets
     lev = 3
