@@ -298,7 +298,10 @@ static hipError_t gen_t(int MP, bool phase_b, const SweepLaunch &a, const GenEnt
 
 hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, bool nt,
                                   const SweepLaunch &a, const GenEntry *tab, const void *val,
-                                  const int *idx, hipStream_t stream, LaunchTimer t) {
+                                  const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t) {
+    if (MP > kMaxSmallMP)
+        return launch_sweep_phase_big(precision_bytes, MP, phase_b, nt, a, tab, val, idx, rbuf,
+                                      stream, t);
     if (precision_bytes == 8)
         return nt ? gen_t<double, true>(MP, phase_b, a, tab, val, idx, stream, t)
                   : gen_t<double, false>(MP, phase_b, a, tab, val, idx, stream, t);
@@ -337,7 +340,10 @@ hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64
                                hipStream_t stream, double *out) {
     const int groups = reduce_groups(MP, L);
     const hipError_t e =
-        precision_bytes == 8
+        MP > kMaxSmallMP
+            ? launch_residual_big_partials(precision_bytes, MP, groups, diag64, tab, val64, idx, w,
+                                           st, slot, part, stream)
+        : precision_bytes == 8
             ? residual_gen_t<double>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream)
             : residual_gen_t<float>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream);
     if (e != hipSuccess) return e;

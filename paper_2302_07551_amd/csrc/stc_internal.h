@@ -210,10 +210,13 @@ hipError_t launch_sweep_phase_ell(int precision_bytes, int MP, int b, bool phase
 // Generators of any block pattern (stc_general.hip): the sweep phases and
 // the residual, over the diagonal blocks (inverse W_i in blk, Q_ii in diag)
 // and the per-level GenEntry table.
-// nt: non-temporal loads of the stored blocks and entries.
+// nt: non-temporal loads of the stored blocks and entries.  Blocks above
+// kMaxSmallMP take the large-block kernels, which need rbuf: a scratch
+// vector of L x MP elements of the sweep's type.
 hipError_t launch_sweep_phase_gen(int precision_bytes, int MP, bool phase_b, bool nt,
                                   const SweepLaunch &a, const GenEntry *tab, const void *val,
-                                  const int *idx, hipStream_t stream, LaunchTimer t = LaunchTimer());
+                                  const int *idx, void *rbuf, hipStream_t stream,
+                                  LaunchTimer t = LaunchTimer());
 hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64,
                                const GenEntry *tab, const double *val64, const int *idx,
                                const void *w, int L, DevState *st, long long slot, double *part,
@@ -281,6 +284,32 @@ hipError_t launch_batch_finalize(int grid, const ChainDesc *chains, const int *r
 hipError_t launch_batch_begin(int grid, const ChainDesc *chains, const int *range,
                               hipStream_t stream);
 int reduce_groups(int MP, int L);
+
+// Largest padded block size of the one-workgroup-per-level kernels; the
+// padded sizes 512, 1024 and 2048 (generators of any block pattern only)
+// take the large-block kernels of stc_big.hip.
+constexpr int kMaxSmallMP = 256;
+constexpr int kMaxMP = 2048;
+// Large blocks: column slices per level of a sweep phase (one partial slot
+// each) and of the residual.
+int big_slices(int precision_bytes, int MP);
+int big_residual_slices(int MP);
+// One phase of a large-block sweep: the gather launch, then the apply
+// launch (with phase B's reduction workgroup when a.fold).
+hipError_t launch_sweep_phase_big(int precision_bytes, int MP, bool phase_b, bool nt,
+                                  const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                  const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t);
+// The change of sweep k in the apply kernel's slices, one partial per slice
+// (phase A's gA slices, then phase B's gB).
+hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, const void *w_prev,
+                                    int parity_a, int gA, int gB, const DevState *st, long long k,
+                                    double *part, hipStream_t stream);
+// ||Q^T x||_1 partials per (level, 64-column slice): groups = L x
+// big_residual_slices(MP).
+hipError_t launch_residual_big_partials(int precision_bytes, int MP, int groups,
+                                        const double *diag, const GenEntry *tab, const double *val,
+                                        const int *idx, const void *w, const DevState *st,
+                                        long long slot, double *part, hipStream_t stream);
 
 // Algorithm 1 (stc_jgs.hip): one sweep over `chunks` chunks of levels (the
 // workgroups; plus the reduction workgroup of sweep s - 1 when a.fold), and

@@ -158,7 +158,7 @@ __global__ void k_reset(DevState *st) {
 // host launchers
 // ---------------------------------------------------------------------------
 int supported_mp(int m) {
-    if (m < 1 || m > 256) return 0;
+    if (m < 1 || m > kMaxMP) return 0;
     int mp = 8;
     while (mp < m) mp <<= 1;
     return mp;
@@ -169,11 +169,13 @@ int variant_count() { return kVariants; }
 
 int phase_groups(int precision_bytes, int MP, int L, int parity, int variant) {
     const int levels = (L - parity + 1) / 2;
+    if (MP > kMaxSmallMP) return levels * big_slices(precision_bytes, MP);
     const int lpw = precision_bytes == 8 ? lpw_of<double>(MP, variant) : lpw_of<float>(MP, variant);
     return (levels + lpw - 1) / lpw;
 }
 
 int reduce_groups(int MP, int L) {
+    if (MP > kMaxSmallMP) return L * big_residual_slices(MP);
     const int lpw = lpw_of<double>(MP, kEllGeometry);   // the residual kernel's 8-row-group tile
     return (L + lpw - 1) / lpw;
 }
@@ -276,6 +278,9 @@ hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, do
         case 64: return invert_mp<64>(b, diag, sizes, blk, L, st, stream);
         case 128: return invert_mp<128>(b, diag, sizes, blk, L, st, stream);
         case 256: return invert_mp<256>(b, diag, sizes, blk, L, st, stream);
+        case 512: return invert_mp<512>(b, diag, sizes, blk, L, st, stream);
+        case 1024: return invert_mp<1024>(b, diag, sizes, blk, L, st, stream);
+        case 2048: return invert_mp<2048>(b, diag, sizes, blk, L, st, stream);
     }
     return hipErrorInvalidValue;
 }
@@ -408,7 +413,10 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
     const int gA = phase_groups(precision_bytes, MP, L, parity_a, variant);
     const int gB = phase_groups(precision_bytes, MP, L, 1 - parity_a, variant);
     hipError_t e = hipErrorInvalidValue;
-    if (precision_bytes == 8) {
+    if (MP > kMaxSmallMP) {
+        e = launch_diff_big_partials(precision_bytes, MP, w, w_prev, parity_a, gA, gB, st, k, part,
+                                     stream);
+    } else if (precision_bytes == 8) {
         switch (MP) {
             case 8: e = diff_mp<double, 8>(variant_rg(8, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;
             case 16: e = diff_mp<double, 16>(variant_rg(16, variant), w, w_prev, L, parity_a, gA, gB, st, k, part, stream); break;

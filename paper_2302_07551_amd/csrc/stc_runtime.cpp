@@ -97,6 +97,7 @@ struct Layout {
     size_t kvec = 0, kst = 0, kpart = 0, kdot = 0, kh = 0;
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
+    size_t rbuf = 0;            // large blocks: r_i of the gather launches (L x MP elements)
     size_t nparts = 0, naux = 0;
     size_t total = 0;
 };
@@ -311,6 +312,14 @@ struct BlockSource {
     }
 };
 
+// Partial slots of the residual, change and load kernels (part_aux): the
+// groups of the residual and change kernels, and at least the load kernel's
+// 2 x 1024.
+size_t aux_slots(int L, int MP) {
+    const size_t groups = MP > kMaxSmallMP ? (size_t)L * big_residual_slices(MP) : (size_t)L;
+    return std::max<size_t>(2 * 1024 + 8, groups + 8);
+}
+
 bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     *why = 0;
     if (!g || !o) return false;
@@ -318,7 +327,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     const bool general = g->b == STC_ANY_PATTERN;
     if (!general && (g->b < 1 || g->b > kMaxBandwidth)) { *why = 2; return false; }
     const int MP = supported_mp(g->m);
-    // blocks of 256: generators of any pattern only (the banded kernels stop at 128)
+    // blocks above 128: generators of any pattern only (the banded kernels stop there)
     if (!MP || (MP > 128 && !general)) { *why = 3; return false; }
     if (o->precision < STC_FP64 || o->precision > STC_MIXED) { *why = 4; return false; }
     if (o->format != STC_DENSE && o->format != STC_SPARSE) { *why = 5; return false; }
@@ -367,11 +376,14 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (l.fp32) l.w32 = take(4 * vec * 4);
     l.wres = take(vec * 8);
     l.io = take(vec * 8);
-    l.nparts = L + 8;
+    // partial slots of one sweep: a group of levels each, or for large blocks
+    // a column slice of a level each (at most MP / 64 per level)
+    l.nparts = MP > kMaxSmallMP ? L * (MP / 64) + 8 : L + 8;
     l.part_sum = take(2 * l.nparts * 8);    // two sweeps: parity of s
     l.part_diff = take(2 * l.nparts * 8);
-    l.naux = std::max<size_t>(2 * 1024 + 8, L + 8);
+    l.naux = aux_slots(g->L, MP);
     l.part_aux = take(l.naux * 8);
+    if (MP > kMaxSmallMP) l.rbuf = take(vec * 8);
     if (l.sparse && !general) {
         l.ell_tab = take(L * l.NB * sizeof(EllEntry));
         l.ell_v64 = take((size_t)l.ell_slots * 8);
@@ -437,6 +449,7 @@ struct stc_handle {
     double *gen_v64 = nullptr;
     float *gen_v32 = nullptr;
     int *gen_idx = nullptr;
+    void *rbuf = nullptr;             // large blocks: the gather launches' r_i
     std::vector<GenEntry> gen_host;   // the table, for the byte counts
     // Krylov workspace (stc_solve_gmres)
     int kr = 0;
@@ -562,7 +575,7 @@ hipError_t enqueue_sweep(stc_handle *h, long long s, double tol, const SweepTime
         if (h->general)
             return launch_sweep_phase_gen(bytes, h->MP, phb, (v & 2) != 0, a, h->gen_tab,
                                           f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
-                                          h->gen_idx, h->stream, t);
+                                          h->gen_idx, h->rbuf, h->stream, t);
         if (h->sparse)
             return launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab, ev_val,
                                           h->ell_idx, h->stream, t);
@@ -808,7 +821,7 @@ hipError_t enqueue_apply(stc_handle *h, const double *v, double *out, bool f32 =
         if (h->general)
             e = launch_sweep_phase_gen(bytes, h->MP, phb, (var & 2) != 0, a, h->gen_tab,
                                        f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
-                                       h->gen_idx, h->stream);
+                                       h->gen_idx, h->rbuf, h->stream);
         else if (h->sparse)
             e = launch_sweep_phase_ell(bytes, h->MP, h->b, phb, a, h->ell_tab,
                                        f32 ? (const void *)h->ell_v32 : (const void *)h->ell_v64,
@@ -1067,7 +1080,7 @@ namespace stc {
 // Padded FP64 copy of x (L x MP) and the partials of the load and residual
 // kernels, as the handle's own residual uses them.
 size_t residual_staging_bytes(const stc_handle *h) {
-    const size_t naux = std::max<size_t>(2 * 1024 + 8, (size_t)h->L + 8);
+    const size_t naux = aux_slots(h->L, h->MP);
     return align_up((size_t)h->L * h->MP * sizeof(double)) + naux * sizeof(double);
 }
 
@@ -1139,7 +1152,7 @@ stc_status plan_setup(const stc_generator *g, const stc_options *o, Layout *lay)
     if (!plan(g, o, lay, &why)) {
         static const char *msg[] = {"bad arguments", "L must be >= 2",
                                     "b must be in 1..4 or STC_ANY_PATTERN",
-                                    "m must be in 1..128 (1..256 for STC_ANY_PATTERN)",
+                                    "m must be in 1..128 (1..2048 for STC_ANY_PATTERN)",
                                     "unknown precision", "unknown format",
                                     "neither blocks nor a complete CSR input given",
                                     "give blocks or CSR input, not both",
@@ -1400,6 +1413,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         h->gen_v64 = (double *)(h->base + lay.gen_v64);
         h->gen_v32 = lay.fp32 ? (float *)(h->base + lay.gen_v32) : nullptr;
         h->gen_idx = (int *)(h->base + lay.gen_idx);
+        h->rbuf = lay.rbuf ? (void *)(h->base + lay.rbuf) : nullptr;
         if ((rc = pack_general(h, g)) != STC_OK) return cleanup(rc);
     } else {
     // validate, then pack in the sweep's layout, a chunk of levels at a time;

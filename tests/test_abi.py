@@ -394,9 +394,10 @@ def test_setup_prepared_rejects_small_arena_before_touching_the_device(lib):
     p.close()
 
 
-def test_blocks_of_256_only_for_any_pattern(lib):
-    """m up to 256 is taken by generators of any block pattern only; the
-    banded kernels stop at 128."""
+def test_large_blocks_only_for_any_pattern(lib):
+    """Blocks above 128 (up to 2048) are taken by generators of any block
+    pattern only; the banded kernels stop at 128.  Blocks above 256 pad to
+    512, 1024 or 2048, with one partial slot per column slice of a level."""
     g = synth.qbd(4, 4, 2)
     gen, opt, _ = _gen_opt(g)
     gen.m = 200
@@ -414,5 +415,10 @@ def test_blocks_of_256_only_for_any_pattern(lib):
     opt = stc.make_options("fp64", format="sparse")
     fp = stc.stc_footprint_bytes(gen, opt)
     assert fp >= 3 * m * m * 8          # the three 256 x 256 inverses
-    gen.m = 257
+    for m_big, mp in ((257, 512), (1000, 1024), (2048, 2048)):
+        gen.m = m_big
+        fp_big = stc.stc_footprint_bytes(gen, opt)
+        # inverses and diagonal blocks, FP64, padded to mp
+        assert fp_big >= 2 * 3 * mp * mp * 8, m_big
+    gen.m = 2049
     assert stc.stc_footprint_bytes(gen, opt) == 0
