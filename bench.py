@@ -225,6 +225,8 @@ def main():
     ap.add_argument("--launch-sizes", action="store_true")
     ap.add_argument("--batch-rates", action="store_true")
     ap.add_argument("--jgs", action="store_true")
+    ap.add_argument("--large-blocks", action="store_true")
+    ap.add_argument("--only", type=str, default="")
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--batch-probe", action="store_true")
     ap.add_argument("--print-maps", action="store_true")
@@ -258,6 +260,8 @@ def main():
         return banded_mode(no_cpu=args.no_cpu)
     if args.skipfree:
         return skipfree_mode()
+    if args.large_blocks:
+        return large_blocks_mode(args)
     if args.mutex:
         return mutex_mode(args)
     if args.example3:
@@ -912,6 +916,129 @@ def mutex_mode(args, n=16, r=12):
             "sweep_rates": rates, "solves": solves, "cpu_baseline": cpu,
             "device_copy_GBs_same_launch_bytes": round(copy, 1),
             "vs_device_copy": round(best["GB/s_algorithmic"] / copy, 4)}
+    print(json.dumps(line), flush=True)
+
+
+LARGE_BLOCK_WORKLOADS = (
+    # (name, builder(seed), closed form or None): the paper's partitions into
+    # levels of 512 to 2048 states, on the mutual-exclusion model and on
+    # shape stand-ins for the other three test matrices of section 3
+    ("mutex_n16_r12_m512", lambda sd: __import__("synth").mutual_exclusion(16, 12, sd, m=512),
+     "mutex"),
+    ("mutex_n16_r12_m1024", lambda sd: __import__("synth").mutual_exclusion(16, 12, sd, m=1024),
+     "mutex"),
+    ("mutex_n16_r12_m2048", lambda sd: __import__("synth").mutual_exclusion(16, 12, sd, m=2048),
+     "mutex"),
+    ("uhess_N110400_m512", lambda sd: __import__("synth").upper_hessenberg(110400, 138, sd, m=512),
+     None),
+    ("ncd_N91881_bw1135_m2048",
+     lambda sd: __import__("synth").banded_random(91881, 1135, 1135, sd, symmetric=True, m=2048),
+     "uniform"),
+    ("prio_N79220_m512",
+     lambda sd: __import__("synth").banded_random(79220, 2370, 1585, sd, m=512), None),
+    ("prio_N79220_m1024",
+     lambda sd: __import__("synth").banded_random(79220, 2370, 1585, sd, m=1024), None),
+    ("prio_N79220_m2048",
+     lambda sd: __import__("synth").banded_random(79220, 2370, 1585, sd, m=2048), None),
+)
+
+
+def large_blocks_mode(args):
+    """Generators of any block pattern in the paper's large partitions
+    (levels of 512, 1024 and 2048 states): the mutual-exclusion model (N =
+    64839) and shape stand-ins for the other test matrices of section 3 (a
+    block upper Hessenberg chain, N = 110400, levels of 512; a symmetric
+    chain of bandwidth 1135, N = 91881, levels of 2048, block tridiagonal;
+    a chain of bandwidths 2370 / 1585, N = 79220, levels of 512, 1024 and
+    2048).  Per workload: setup time, sweep rates in FP64 and FP32 with the
+    autotuned load policy, and FP64 and mixed solves to a change of 1e-13
+    from a seeded positive start, with their residual and, where one is
+    known, the error against the closed-form stationary vector.  The CPU leg times the oracle's C/OpenMP
+    sweep on the symmetric chain."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    seed = synth.config_seed(3)
+    only = set(args.only.split(",")) if args.only else None
+    out = {}
+    for name, build, closed in LARGE_BLOCK_WORKLOADS:
+        if only and name not in only:
+            continue
+        gen = build(seed)
+        exact = (synth.mutual_exclusion_pi(gen) if closed == "mutex"
+                 else np.full(gen.N, 1.0 / gen.N) if closed == "uniform" else None)
+        rec = {"N": gen.N, "L": gen.L, "m": gen.m, "nnz": gen.nnz,
+               "block_reach": gen.block_reach()}
+        # solves start from a seeded positive vector (e/N is already the
+        # fixed point of the symmetric chain)
+        x0 = np.random.default_rng(seed).uniform(0.5, 1.5, gen.N)
+        x0 /= x0.sum()
+        for prec in ("fp64", "fp32"):
+            t0 = time.perf_counter()
+            s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                       precision=prec)
+            torch.cuda.synchronize()
+            t_setup = time.perf_counter() - t0
+            stage = stc.STC_FP64 if prec == "fp64" else stc.STC_FP32
+            stc.stc_autotune(s.h, 5)
+            s.load(None)
+            s.sweeps(args.warmup)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            s.sweeps(args.steps)
+            e1.record(s.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            ms_a, ms_b, _f, _t = stc.stc_profile_sweeps(s.h, args.steps)
+            alg = general_nnz_bytes(gen, 1, 8 if prec == "fp64" else 4)
+            rec[prec] = {"setup_s": round(t_setup, 3),
+                         "variant": stc.stc_get_variant(s.h, stage),
+                         "ms_per_sweep": round(ms, 5), "sweeps_per_s": round(1e3 / ms, 1),
+                         "ms_phase_a": round(ms_a, 5), "ms_phase_b": round(ms_b, 5),
+                         "algorithmic_bytes_per_sweep": alg,
+                         "GB/s_algorithmic": round(alg / (ms * 1e-3) / 1e9, 1),
+                         "footprint_MB": round(s.footprint / 1e6, 1)}
+            s.close()
+        for prec in () if args.no_ttr else ("fp64", "mixed"):
+            s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                       precision=prec, check_every=100, switch_tol=1e-6)
+            stc.stc_autotune(s.h, 5)
+            s.solve(x0, tol=1e-13, maxit=200_000)   # warm (first launches, code objects)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pi, info = s.solve(x0, tol=1e-13, maxit=200_000)
+            dt = time.perf_counter() - t0
+            s.close()
+            rec[f"solve_{prec}"] = {
+                "seconds": round(dt, 4), "iters": info["iters"], "iters_fp32": info["iters_fp32"],
+                "status": info["status"], "residual_1": info["residual_1"],
+                "err_vs_closed_form": (None if exact is None
+                                       else float(np.abs(pi - exact).sum()))}
+        print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+        out[name] = rec
+    cpu = None
+    if not args.no_cpu and (not only or "ncd_N91881_bw1135_m2048" in only):
+        g = synth.banded_random(91881, 1135, 1135, seed, symmetric=True, m=2048)
+        cpu = mutex_cpu_baseline(g)
+        cpu["sample"] = cpu["sample"].replace("the m = 128 partition",
+                                              "the symmetric N = 91881 chain in levels of 2048")
+        if "ncd_N91881_bw1135_m2048" in out:
+            cpu["gpu_over_cpu"] = round(out["ncd_N91881_bw1135_m2048"]["fp64"]["sweeps_per_s"]
+                                        / cpu["value"], 1)
+    best_name = max(out, key=lambda k: out[k]["fp64"]["GB/s_algorithmic"]) if out else None
+    best = out[best_name]["fp64"] if best_name else {"GB/s_algorithmic": 0.0, "sweeps_per_s": 0.0}
+    line = {"metric": "sweeps/s of the large-partition workloads (any block pattern, FP64)",
+            "value": best["sweeps_per_s"], "unit": "sweeps/s", "higher_is_better": True,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "large_partitions", "best": best_name, "seed": seed},
+            "roofline": {"bound": "hbm", "kernel": "large-block gather + apply (both phases)",
+                         "achieved": best["GB/s_algorithmic"], "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(best["GB/s_algorithmic"] / 8000.0, 4), "traffic": None},
+            "workloads": out, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 

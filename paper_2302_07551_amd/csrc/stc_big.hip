@@ -11,9 +11,9 @@
 //           column splitting its ELL quads; near sources fresh in phase B,
 //           far sources from the previous iterate scaled by kappa, as in the
 //           smaller kernels);
-//   apply:  z_i = W_i r_i by column slices of W_i (workgroups of 512 bytes of
-//           every row: 64 FP64 or 128 FP32 columns), each writing its slice
-//           of z_i and one partial of e^T z and of the change.
+//   apply:  z_i = W_i r_i by column slices of W_i (workgroups of 64 columns
+//           of every row), each writing its slice of z_i and one partial of
+//           e^T z and of the change.
 // The partials, the lagged normalisation, phase B's fold and the device
 // stopping test are those of the other kernels, with one partial slot per
 // (level, slice).  The change kernel of a burst's flush and the residual
@@ -26,21 +26,23 @@ namespace {
 
 constexpr int kGatherCols = 64;             // columns per gather workgroup
 constexpr int kGatherLanes = kWG / kGatherCols;   // lanes per column
-constexpr int kRowGroups = 8;               // row groups of an apply workgroup
+constexpr int kSliceCols = 64;              // columns per apply workgroup
 
+// Apply geometry: TPR lanes cover a slice's row with 16-byte loads, R row
+// groups split the rows (FP64: 32 lanes, 8 groups; FP32: 16 lanes, 16 groups).
 template <typename T>
 struct BigTile {
-    static constexpr int VEC = 16 / (int)sizeof(T);     // elements per 16-byte load
-    static constexpr int CS = (kWG / kRowGroups) * VEC;  // columns of a slice: 512 bytes
+    static constexpr int VEC = 16 / (int)sizeof(T);   // elements per 16-byte load
+    static constexpr int CS = kSliceCols;
+    static constexpr int TPR = CS / VEC;
+    static constexpr int R = kWG / TPR;
 };
 
 typedef int Int4 __attribute__((ext_vector_type(4)));
 
 }  // namespace
 
-int big_slices(int precision_bytes, int MP) {
-    return precision_bytes == 8 ? MP / BigTile<double>::CS : MP / BigTile<float>::CS;
-}
+int big_slices(int, int MP) { return MP / kSliceCols; }
 
 int big_residual_slices(int MP) { return MP / kGatherCols; }
 
@@ -113,19 +115,20 @@ __global__ __launch_bounds__(kWG) void k_gather_big(SweepLaunch a, const GenEntr
 }
 
 // z_i = W_i r_i on one column slice, and the slice's partial sums.  Thread
-// (g, c) streams rows g, g + 8, ... of the slice's 16-byte column group c
+// (g, c) streams rows g, g + R, ... of the slice's 16-byte column group c
 // (W_i is stored gather-oriented: row `row` holds the weights of r_i[row]
-// in every output column); the 8 row groups are added in order in LDS.
+// in every output column); the R row groups are added in order in LDS.
 // Phase B with a.fold: workgroup 0 reduces and records sweep s - 1 first.
 template <typename T, int MP, bool PHB, bool NT>
 __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf) {
     using VT = typename Vec16<T>::type;
     constexpr int VEC = BigTile<T>::VEC, CS = BigTile<T>::CS, S = MP / CS;
-    constexpr int RPT = MP / kRowGroups;   // rows per thread
-    constexpr int PW = 16;                 // rows in flight before r_i is staged
-    static_assert(RPT % PW == 0, "rows per thread in whole prefetch batches");
+    constexpr int TPR = BigTile<T>::TPR, R = BigTile<T>::R;
+    constexpr int RPT = MP / R;   // rows per thread
+    constexpr int PW = 8;         // rows per batch; two batches in flight
+    static_assert(RPT % PW == 0, "rows per thread in whole batches");
     __shared__ T rv[MP];
-    __shared__ T red[kRowGroups * CS];
+    __shared__ T red[R * CS];
     __shared__ double sh[4 * kWG / 64];
     int q = blockIdx.x;
     if (PHB && a.fold) {
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     const int tid = threadIdx.x;
     const int lev = q / S, sl = q - lev * S;
     const int i = a.parity + 2 * lev;
-    const int c = tid % (CS / VEC), g = tid / (CS / VEC);
+    const int c = tid % TPR, g = tid / TPR;
     const int j0 = sl * CS;
     const T *wb = (const T *)a.blk + (size_t)i * MP * MP + j0 + c * VEC;
 
@@ -147,7 +150,7 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     VT cur[PW];
 #pragma unroll
     for (int u = 0; u < PW; ++u)
-        cur[u] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + kRowGroups * u) * MP));
+        cur[u] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * u) * MP));
     const T *r = rbuf + (size_t)i * MP;
 #pragma unroll
     for (int u = 0; u < MP / kWG; ++u) rv[tid + u * kWG] = r[tid + u * kWG];
@@ -159,11 +162,10 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
         if (q0 + PW < RPT) {
 #pragma unroll
             for (int u = 0; u < PW; ++u)
-                nxt[u] = stream_load<VT, NT>(
-                    (const VT *)(wb + (size_t)(g + kRowGroups * (q0 + PW + u)) * MP));
+                nxt[u] = stream_load<VT, NT>((const VT *)(wb + (size_t)(g + R * (q0 + PW + u)) * MP));
         }
 #pragma unroll
-        for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + kRowGroups * (q0 + u)];
+        for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + R * (q0 + u)];
 #pragma unroll
         for (int u = 0; u < PW; ++u) cur[u] = nxt[u];
     }
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     if (live && tid < CS) {
         T z = 0;
 #pragma unroll
-        for (int x = 0; x < kRowGroups; ++x) z += red[x * CS + tid];
+        for (int x = 0; x < R; ++x) z += red[x * CS + tid];
         const size_t e = (size_t)i * MP + j0 + tid;
         ((T *)a.w_new)[e] = z;
         zs = (double)z;
@@ -272,6 +274,215 @@ __global__ __launch_bounds__(kWG) void k_residual_big(const double *diag, const 
     }
     const double S = block_sum(res, sh);
     if (tid == 0) part[blockIdx.x] = S;
+}
+
+// ---------------------------------------------------------------------------
+// W_i = (-Q_ii)^{-1} for the large blocks: the blocked Gauss-Jordan
+// elimination of k_invert_mfma with 64-wide panels, each step spread over
+// many workgroups per level instead of one.  Per panel k:
+//   panel: D^{-1} = (A[k, k])^{-1}, the 64 x 64 diagonal tile inverted in LDS
+//          by the same elimination (one workgroup per level), into scratch;
+//   row:   A[k, j] = D^{-1} A[k, j]                 for every tile j != k;
+//   trail: A[i, j] -= A[i, k] A[k, j]               for i, j != k;
+//   col:   A[i, k] = -A[i, k] D^{-1}, A[k, k] = D^{-1}.
+// Each launch reads only tiles that it does not write, or its own tile,
+// staged in LDS before it is written back.  Tile products are 64 x 64 x 64
+// on v_mfma_f64_16x16x4f64 (wave w: rows 16 w .. 16 w + 15, four 16-column
+// output tiles).  No pivoting, for the reason given at k_invert; a panel
+// pivot not clearly positive against the original diagonal marks the level.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kPanel = 64;
+constexpr int kPL = kPanel + 2;   // LDS row stride of a staged tile (doubles)
+typedef double D2 __attribute__((ext_vector_type(2)));
+
+// The 64 x 64 tile at g (row stride ld) into LDS t (stride kPL), by the
+// workgroup's NTH threads; all loads of a thread are issued before its stores.
+template <int NTH>
+__device__ inline void stage_tile(const double *g, size_t ld, double *t) {
+    constexpr int PER = kPanel * kPanel / 2 / NTH;
+    D2 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = threadIdx.x + u * NTH;
+        v[u] = *(const D2 *)(g + (size_t)(p >> 5) * ld + (p & 31) * 2);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = threadIdx.x + u * NTH;
+        t[(p >> 5) * kPL + (p & 31) * 2] = v[u][0];
+        t[(p >> 5) * kPL + (p & 31) * 2 + 1] = v[u][1];
+    }
+}
+
+// acc[cb] += (sa A[16 w .. 16 w + 15, :]) B[:, 16 cb .. 16 cb + 15], k = 0 .. 63
+// in order (sa = 1 or -1, an exact sign).
+__device__ inline void tile_mma(const double *A, const double *B, double sa, d4_t (&acc)[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int s4 = 0; s4 < kPanel / 4; ++s4) {
+        const double av = sa * A[(16 * w + lr) * kPL + 4 * s4 + lq];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+            acc[cb] = mfma16x16x4(av, B[(4 * s4 + lq) * kPL + 16 * cb + lr], acc[cb]);
+    }
+}
+
+// acc[cb][v] is element (16 w + lq + 4 v, 16 cb + lr) of a 64 x 64 tile.
+__device__ inline void load_acc(const double *g, size_t ld, d4_t (&acc)[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[cb][v] = g[(size_t)(16 * w + lq + 4 * v) * ld + 16 * cb + lr];
+}
+
+__device__ inline void store_acc(double *g, size_t ld, const d4_t (&acc)[4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[(size_t)(16 * w + lq + 4 * v) * ld + 16 * cb + lr] = acc[cb][v];
+}
+
+}  // namespace
+
+// W_i = -Q_ii on the level's states and the identity on its padding; the
+// original diagonal of W_i into dorig; the level flags cleared.
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_binv_init(const double *diag, const int *sizes,
+                                                    double *W, double *dorig, int *bad, int L) {
+    constexpr size_t BS = (size_t)MP * MP;
+    const size_t n2 = (size_t)L * BS / 2;
+    for (size_t p = blockIdx.x * (size_t)kWG + threadIdx.x; p < n2; p += (size_t)gridDim.x * kWG) {
+        const size_t e = 2 * p;
+        const int i = (int)(e / BS);
+        const int r = (int)((e - (size_t)i * BS) / MP), c = (int)(e - (size_t)i * BS - (size_t)r * MP);
+        const int n = sizes[i];
+        const D2 q = *(const D2 *)(diag + e);
+        D2 v;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int cc = c + t;
+            v[t] = (r < n && cc < n) ? -q[t] : (r == cc ? 1.0 : 0.0);
+            if (r == cc) dorig[(size_t)i * MP + r] = v[t];
+        }
+        *(D2 *)(W + e) = v;
+    }
+    const size_t g = blockIdx.x * (size_t)kWG + threadIdx.x;
+    if (g < (size_t)L) bad[g] = 0;
+}
+
+// The inverse of the diagonal tile (kb, kb) of every level, into dinv.
+template <int MP>
+__global__ __launch_bounds__(64 * inv_waves(kPanel)) void k_binv_panel(const double *W,
+                                                                        const double *dorig,
+                                                                        double *dinv, int *bad,
+                                                                        int kb) {
+    constexpr int NTH = 64 * inv_waves(kPanel);
+    __shared__ double a[kPanel * kPL];
+    __shared__ double dl[2][16 * 17];
+    __shared__ double dor[kPanel];
+    __shared__ int badl;
+    const int i = blockIdx.x;
+    const double *Wi = W + (size_t)i * MP * MP;
+    stage_tile<NTH>(Wi + (size_t)kb * kPanel * MP + kb * kPanel, MP, a);
+    if (threadIdx.x < kPanel) dor[threadIdx.x] = dorig[(size_t)i * MP + kb * kPanel + threadIdx.x];
+    if (threadIdx.x == 0) badl = 0;
+    __syncthreads();
+    gj_blocked<kPanel, inv_waves(kPanel), kPL>(a, dor, dl, &badl);
+    __syncthreads();
+    double *d = dinv + (size_t)i * kPanel * kPanel;
+    for (int e = threadIdx.x; e < kPanel * kPanel; e += NTH) d[e] = a[(e / kPanel) * kPL + e % kPanel];
+    if (threadIdx.x == 0 && badl) bad[i] = 1;
+}
+
+// Row panel: A[kb, jb] = D^{-1} A[kb, jb] for jb != kb.
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_binv_row(double *W, const double *dinv, int kb) {
+    constexpr int NT = MP / kPanel;
+    __shared__ double D[kPanel * kPL];
+    __shared__ double B[kPanel * kPL];
+    const int i = blockIdx.x / (NT - 1), jj = blockIdx.x - i * (NT - 1);
+    const int jb = jj + (jj >= kb);
+    double *t = W + (size_t)i * MP * MP + (size_t)kb * kPanel * MP + jb * kPanel;
+    stage_tile<kWG>(dinv + (size_t)i * kPanel * kPanel, kPanel, D);
+    stage_tile<kWG>(t, MP, B);
+    __syncthreads();
+    d4_t acc[4] = {};
+    tile_mma(D, B, 1.0, acc);
+    store_acc(t, MP, acc);
+}
+
+// Trailing update: A[ib, jb] -= A[ib, kb] A[kb, jb] for ib, jb != kb (the
+// row panel already holds D^{-1} A[kb, jb]).
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_binv_trail(double *W, int kb) {
+    constexpr int NT = MP / kPanel;
+    constexpr int NR = (NT - 1) * (NT - 1);
+    __shared__ double C[kPanel * kPL];
+    __shared__ double R[kPanel * kPL];
+    const int i = blockIdx.x / NR, u = blockIdx.x - i * NR;
+    const int ii = u / (NT - 1), jj = u - ii * (NT - 1);
+    const int ib = ii + (ii >= kb), jb = jj + (jj >= kb);
+    double *Wi = W + (size_t)i * MP * MP;
+    double *t = Wi + (size_t)ib * kPanel * MP + jb * kPanel;
+    d4_t acc[4];
+    load_acc(t, MP, acc);
+    stage_tile<kWG>(Wi + (size_t)ib * kPanel * MP + kb * kPanel, MP, C);
+    stage_tile<kWG>(Wi + (size_t)kb * kPanel * MP + jb * kPanel, MP, R);
+    __syncthreads();
+    tile_mma(C, R, -1.0, acc);
+    store_acc(t, MP, acc);
+}
+
+// Column panel: A[ib, kb] = -A[ib, kb] D^{-1} for ib != kb; A[kb, kb] = D^{-1}.
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_binv_col(double *W, const double *dinv, int kb) {
+    constexpr int NT = MP / kPanel;
+    __shared__ double C[kPanel * kPL];
+    __shared__ double D[kPanel * kPL];
+    const int i = blockIdx.x / NT, ib = blockIdx.x - i * NT;
+    double *t = W + (size_t)i * MP * MP + (size_t)ib * kPanel * MP + kb * kPanel;
+    const double *d = dinv + (size_t)i * kPanel * kPanel;
+    if (ib == kb) {
+        for (int e = threadIdx.x; e < kPanel * kPanel; e += kWG)
+            t[(size_t)(e / kPanel) * MP + e % kPanel] = d[e];
+        return;
+    }
+    stage_tile<kWG>(t, MP, C);
+    stage_tile<kWG>(d, kPanel, D);
+    __syncthreads();
+    d4_t acc[4] = {};
+    tile_mma(C, D, -1.0, acc);
+    store_acc(t, MP, acc);
+}
+
+// Padding rows and columns written as zeros; each marked level counted once.
+template <int MP>
+__global__ __launch_bounds__(kWG) void k_binv_final(double *W, const int *sizes, const int *bad,
+                                                     DevState *st, int L) {
+    constexpr size_t BS = (size_t)MP * MP;
+    const size_t n = (size_t)L * BS;
+    for (size_t e = blockIdx.x * (size_t)kWG + threadIdx.x; e < n; e += (size_t)gridDim.x * kWG) {
+        const int i = (int)(e / BS);
+        const int ni = sizes[i];
+        if (ni == MP) {
+            // a full level has no padding: skip to the next level
+            const size_t next = (size_t)(i + 1) * BS;
+            const size_t stride = (size_t)gridDim.x * kWG;
+            if (next > e) e += (next - e - 1) / stride * stride;
+            continue;
+        }
+        const int r = (int)((e - (size_t)i * BS) / MP), c = (int)(e - (size_t)i * BS - (size_t)r * MP);
+        if (!(r < ni && c < ni)) W[e] = 0.0;
+    }
+    const size_t g = blockIdx.x * (size_t)kWG + threadIdx.x;
+    if (g < (size_t)L && bad[g]) atomicAdd(&st->bad_blocks, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,6 +591,53 @@ hipError_t launch_residual_big_partials(int precision_bytes, int MP, int groups,
     return precision_bytes == 8
                ? residual_big_t<double>(MP, groups, diag, tab, val, idx, w, st, slot, part, stream)
                : residual_big_t<float>(MP, groups, diag, tab, val, idx, w, st, slot, part, stream);
+}
+
+
+size_t big_invert_scratch_bytes(int MP, int L) {
+    return (size_t)L * MP * 8 + (size_t)L * kPanel * kPanel * 8 + (size_t)L * 4;
+}
+
+namespace {
+
+template <int MP>
+hipError_t invert_big(const double *diag, const int *sizes, double *W, int L, DevState *st,
+                      void *scratch, hipStream_t s) {
+    constexpr int NT = MP / kPanel;
+    double *dorig = (double *)scratch;
+    double *dinv = dorig + (size_t)L * MP;
+    int *bad = (int *)(dinv + (size_t)L * kPanel * kPanel);
+    const size_t n2 = (size_t)L * MP * MP / 2;
+    size_t g = (n2 + kWG - 1) / kWG;
+    if (g > 8192) g = 8192;
+    if (g * kWG < (size_t)L) g = ((size_t)L + kWG - 1) / kWG;
+    hipLaunchKernelGGL((k_binv_init<MP>), dim3((unsigned)g), dim3(kWG), 0, s, diag, sizes, W,
+                       dorig, bad, L);
+    for (int kb = 0; kb < NT; ++kb) {
+        hipLaunchKernelGGL((k_binv_panel<MP>), dim3(L), dim3(64 * inv_waves(kPanel)), 0, s, W,
+                           dorig, dinv, bad, kb);
+        hipLaunchKernelGGL((k_binv_row<MP>), dim3(L * (NT - 1)), dim3(kWG), 0, s, W, dinv, kb);
+        hipLaunchKernelGGL((k_binv_trail<MP>), dim3(L * (NT - 1) * (NT - 1)), dim3(kWG), 0, s, W,
+                           kb);
+        hipLaunchKernelGGL((k_binv_col<MP>), dim3(L * NT), dim3(kWG), 0, s, W, dinv, kb);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_binv_final<MP>), dim3((unsigned)g), dim3(kWG), 0, s, W, sizes, bad, st, L);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_invert_big(int MP, const double *diag, const int *sizes, double *blk, int L,
+                             DevState *st, void *scratch, hipStream_t stream) {
+    if (!scratch) return hipErrorInvalidValue;
+    switch (MP) {
+        case 512: return invert_big<512>(diag, sizes, blk, L, st, scratch, stream);
+        case 1024: return invert_big<1024>(diag, sizes, blk, L, st, scratch, stream);
+        case 2048: return invert_big<2048>(diag, sizes, blk, L, st, scratch, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace stc

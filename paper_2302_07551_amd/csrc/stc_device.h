@@ -1275,59 +1275,19 @@ __device__ __forceinline__ void invert_diag_tile(const double *a, const double *
     if (!(piv > 1e-13 * dorig[k0 + c]) || !isfinite(piv)) *bad = 1;
 }
 
-// GLOBAL (blocks above 128, whose 512 KB do not fit in LDS): the same
-// elimination in place in the output block W_i, in global memory (the
-// workgroup's barriers order its accesses; the block stays in L2).
-template <int MP, int NW = inv_waves(MP), bool GLOBAL = (MP > 128)>   // NW: waves per workgroup
-__global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, const int *sizes,
-                                                      double *blk, int NB, int B, DevState *st) {
-    constexpr int LD = GLOBAL ? MP : MP + 2;   // row stride of the working block (doubles)
+// The blocked elimination of k_invert_mfma on a block a (row stride LD, in
+// LDS or, for the large blocks, global memory), in place, by the whole
+// workgroup of NW waves: dorig holds the block's original diagonal (for the
+// pivot checks), dinv two 16 x 16 tiles of LDS, *bad is set on a pivot
+// that is not clearly positive.
+template <int MP, int NW, int LD>
+__device__ __forceinline__ void gj_blocked(double *a, const double *dorig,
+                                           double (*dinv)[16 * 17], int *bad) {
     constexpr int NT = MP / 16;     // panels
     constexpr int DL = 17;          // stride of the 16x16 tile
-    static_assert(NW >= 2, "the lookahead wave needs partners for the trailing update");
-    __shared__ double a_lds[GLOBAL ? 1 : MP * LD];
-    __shared__ double dinv[2][16 * DL];   // D^{-1} of this panel and of the next
-    __shared__ double dorig[MP];
-    __shared__ int bad;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lq = lane >> 4;   // lane's row/column in a 16-wide tile, quarter
-    const int i = blockIdx.x;
-    const int n = sizes[i];
-    const double *Q = diag + (size_t)i * MP * MP;
-    double *W = blk + ((size_t)i * NB + B) * MP * MP;
-    double *a;
-    if constexpr (GLOBAL)
-        a = W;
-    else
-        a = a_lds;
-    if (tid == 0) bad = 0;
-    if constexpr (GLOBAL) {
-        for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
-            const int r = idx / MP, c = idx - r * MP;
-            const double v = (r < n && c < n) ? -Q[idx] : (r == c ? 1.0 : 0.0);
-            a[idx] = v;
-            if (r == c) dorig[r] = v;
-        }
-    } else {
-        // every load of the thread's share issued before the first LDS store
-        // (the block is stored padded to MP x MP, so all of it is readable)
-        constexpr int PER = MP * MP / (64 * NW);
-        double q[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) q[u] = Q[tid + u * 64 * NW];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int idx = tid + u * 64 * NW;
-            const int r = idx / MP, c = idx - r * MP;
-            double v;
-            if (r < n && c < n) v = -q[u];
-            else v = (r == c) ? 1.0 : 0.0;
-            a[r * LD + c] = v;
-            if (r == c) dorig[r] = v;
-        }
-    }
-    __syncthreads();
-    if (wave == 0) invert_diag_tile<LD, DL>(a, dorig, 0, dinv[0], &bad);
+    if (wave == 0) invert_diag_tile<LD, DL>(a, dorig, 0, dinv[0], bad);
     __syncthreads();
     for (int kb = 0; kb < NT; ++kb) {
         const int k0 = 16 * kb;
@@ -1392,7 +1352,7 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
                 tile_at(tl, i0, j0);
                 fetch(i0, j0, acc, av, bv);
                 update(i0, j0, acc, av, bv);
-                invert_diag_tile<LD, DL>(a, dorig, kb + 1, dinv[(kb + 1) & 1], &bad);
+                invert_diag_tile<LD, DL>(a, dorig, kb + 1, dinv[(kb + 1) & 1], bad);
             } else {
                 int u = u0, i0 = 0, j0 = 0;
                 d4_t acc;
@@ -1444,6 +1404,59 @@ __global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, con
         }
         __syncthreads();
     }
+}
+
+// GLOBAL (blocks above 128, whose 512 KB do not fit in LDS): the same
+// elimination in place in the output block W_i, in global memory (the
+// workgroup's barriers order its accesses; the block stays in L2).
+template <int MP, int NW = inv_waves(MP), bool GLOBAL = (MP > 128)>   // NW: waves per workgroup
+__global__ __launch_bounds__(64 * NW) void k_invert_mfma(const double *diag, const int *sizes,
+                                                      double *blk, int NB, int B, DevState *st) {
+    constexpr int LD = GLOBAL ? MP : MP + 2;   // row stride of the working block (doubles)
+    constexpr int DL = 17;          // stride of the 16x16 tile
+    static_assert(NW >= 2, "the lookahead wave needs partners for the trailing update");
+    __shared__ double a_lds[GLOBAL ? 1 : MP * LD];
+    __shared__ double dinv[2][16 * DL];   // D^{-1} of this panel and of the next
+    __shared__ double dorig[MP];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int i = blockIdx.x;
+    const int n = sizes[i];
+    const double *Q = diag + (size_t)i * MP * MP;
+    double *W = blk + ((size_t)i * NB + B) * MP * MP;
+    double *a;
+    if constexpr (GLOBAL)
+        a = W;
+    else
+        a = a_lds;
+    if (tid == 0) bad = 0;
+    if constexpr (GLOBAL) {
+        for (int idx = tid; idx < MP * MP; idx += 64 * NW) {
+            const int r = idx / MP, c = idx - r * MP;
+            const double v = (r < n && c < n) ? -Q[idx] : (r == c ? 1.0 : 0.0);
+            a[idx] = v;
+            if (r == c) dorig[r] = v;
+        }
+    } else {
+        // every load of the thread's share issued before the first LDS store
+        // (the block is stored padded to MP x MP, so all of it is readable)
+        constexpr int PER = MP * MP / (64 * NW);
+        double q[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) q[u] = Q[tid + u * 64 * NW];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = tid + u * 64 * NW;
+            const int r = idx / MP, c = idx - r * MP;
+            double v;
+            if (r < n && c < n) v = -q[u];
+            else v = (r == c) ? 1.0 : 0.0;
+            a[r * LD + c] = v;
+            if (r == c) dorig[r] = v;
+        }
+    }
+    __syncthreads();
+    gj_blocked<MP, NW, LD>(a, dorig, dinv, &bad);
     if constexpr (GLOBAL) {
         // the inverse is in place: clear the padding
         for (int idx = tid; idx < MP * MP; idx += 64 * NW) {

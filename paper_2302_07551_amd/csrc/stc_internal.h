@@ -304,6 +304,13 @@ hipError_t launch_sweep_phase_big(int precision_bytes, int MP, bool phase_b, boo
 hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, const void *w_prev,
                                     int parity_a, int gA, int gB, const DevState *st, long long k,
                                     double *part, hipStream_t stream);
+// W_i = (-Q_ii)^{-1} for the large blocks (blocked Gauss-Jordan over many
+// workgroups per level), in place in blk (one MP x MP block per level), with
+// scratch of big_invert_scratch_bytes(MP, L) bytes; singular levels are
+// counted in st->bad_blocks.
+size_t big_invert_scratch_bytes(int MP, int L);
+hipError_t launch_invert_big(int MP, const double *diag, const int *sizes, double *blk, int L,
+                             DevState *st, void *scratch, hipStream_t stream);
 // ||Q^T x||_1 partials per (level, 64-column slice): groups = L x
 // big_residual_slices(MP).
 hipError_t launch_residual_big_partials(int precision_bytes, int MP, int groups,

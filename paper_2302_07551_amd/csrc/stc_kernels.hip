@@ -278,9 +278,6 @@ hipError_t launch_invert(int MP, int b, const double *diag, const int *sizes, do
         case 64: return invert_mp<64>(b, diag, sizes, blk, L, st, stream);
         case 128: return invert_mp<128>(b, diag, sizes, blk, L, st, stream);
         case 256: return invert_mp<256>(b, diag, sizes, blk, L, st, stream);
-        case 512: return invert_mp<512>(b, diag, sizes, blk, L, st, stream);
-        case 1024: return invert_mp<1024>(b, diag, sizes, blk, L, st, stream);
-        case 2048: return invert_mp<2048>(b, diag, sizes, blk, L, st, stream);
     }
     return hipErrorInvalidValue;
 }

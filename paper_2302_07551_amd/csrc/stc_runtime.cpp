@@ -98,6 +98,7 @@ struct Layout {
     size_t blk64 = 0, diag64 = 0, blk32 = 0, w64 = 0, w32 = 0, wres = 0, io = 0;
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
     size_t rbuf = 0;            // large blocks: r_i of the gather launches (L x MP elements)
+    size_t inv_scr = 0;         // large blocks: the inverse's panel scratch
     size_t nparts = 0, naux = 0;
     size_t total = 0;
 };
@@ -383,7 +384,10 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     l.part_diff = take(2 * l.nparts * 8);
     l.naux = aux_slots(g->L, MP);
     l.part_aux = take(l.naux * 8);
-    if (MP > kMaxSmallMP) l.rbuf = take(vec * 8);
+    if (MP > kMaxSmallMP) {
+        l.rbuf = take(vec * 8);
+        l.inv_scr = take(big_invert_scratch_bytes(MP, g->L));
+    }
     if (l.sparse && !general) {
         l.ell_tab = take(L * l.NB * sizeof(EllEntry));
         l.ell_v64 = take((size_t)l.ell_slots * 8);
@@ -1358,10 +1362,13 @@ stc_status finish_setup(stc_handle *h, const Layout &lay, int b) {
     if ((rc = dev(launch_reset_state(h->st, h->stream), "reset")) != STC_OK) return rc;
     if (h->kr > 0 && (rc = dev(launch_kstate_init(h->kst, h->stream), "Krylov state")) != STC_OK)
         return rc;
-    if ((rc = dev(launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
-                                h->stream),
-                  "invert")) != STC_OK)
-        return rc;
+    const hipError_t inv =
+        MP > kMaxSmallMP
+            ? launch_invert_big(MP, h->diag64, h->sizes_d, h->blk64, L, h->st,
+                                (void *)(h->base + lay.inv_scr), h->stream)
+            : launch_invert(MP, lay.general ? 0 : b, h->diag64, h->sizes_d, h->blk64, L, h->st,
+                            h->stream);
+    if ((rc = dev(inv, "invert")) != STC_OK) return rc;
     if (lay.fp32 &&
         (rc = dev(launch_cast_blocks(h->blk64, h->blk32, (size_t)L * NB * MP * MP, h->stream),
                   "cast")) != STC_OK)

@@ -25,4 +25,6 @@ from .general import (  # noqa: F401
     localized,
     hessenberg_mmatrix,
     with_levels,
+    banded_random,
+    upper_hessenberg,
 )

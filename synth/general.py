@@ -245,3 +245,68 @@ def localized(L: int, m: int, seed: int, *, up: int = 3, down: int = 3, density:
     return _from_triplets(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), N,
                           sizes, f"localized_L{L}_m{m}_up{up}_down{down}",
                           {"up": up, "down": down})
+
+
+def banded_random(N: int, lower: int, upper: int, seed: int, *, per_row: int = 6,
+                  m: int = 2048, symmetric: bool = False, backbone: float = 0.05,
+                  name: str = "banded_random") -> SparseGenerator:
+    """A sparse generator inside a scalar band: each state s gets `per_row`
+    transitions to states drawn uniformly from s - lower .. s + upper (s
+    excluded), rates U[0, 1], and a backbone s <-> s + 1 of rate `backbone`.
+    symmetric: every drawn pair (s, t), t > s, within `upper` (= `lower`)
+    gets the same rate both ways, so Q is symmetric, its columns sum to 0 too,
+    and the stationary vector is uniform.  Levels: equal runs of m states.
+    (Shape stand-ins for the second and third test matrices of section 3: the
+    time-sharing model, symmetric with bandwidth 1135, and the priority model,
+    lower and upper bandwidths 2370 and 1585; their rates are not given.)"""
+    rng = np.random.default_rng(seed)
+    s = np.repeat(np.arange(N, dtype=np.int64), per_row)
+    if symmetric:
+        if lower != upper:
+            raise ValueError("a symmetric band has lower == upper")
+        t = s + rng.integers(1, upper + 1, size=len(s))
+        keep = t < N
+        s, t = s[keep], t[keep]
+        v = rng.uniform(0.0, 1.0, size=len(s))
+        b = np.arange(N - 1)
+        rows = np.concatenate([s, t, b, b + 1])
+        cols = np.concatenate([t, s, b + 1, b])
+        vals = np.concatenate([v, v, np.full(N - 1, backbone), np.full(N - 1, backbone)])
+    else:
+        d = rng.integers(-lower, upper, size=len(s))
+        d = np.where(d >= 0, d + 1, d)            # s itself excluded
+        t = s + d
+        keep = (t >= 0) & (t < N)
+        s, t = s[keep], t[keep]
+        v = rng.uniform(0.0, 1.0, size=len(s))
+        b = np.arange(N - 1)
+        rows = np.concatenate([s, b, b + 1])
+        cols = np.concatenate([t, b + 1, b])
+        vals = np.concatenate([v, np.full(N - 1, backbone), np.full(N - 1, backbone)])
+    return _from_triplets(rows, cols, vals, N, equal_levels(N, m), f"{name}_N{N}_m{m}",
+                          {"lower": lower, "upper": upper, "symmetric": symmetric})
+
+
+def upper_hessenberg(N: int, k: int, seed: int, *, up: int = 4, down: int = 2,
+                     mean_jump: float = 2.0, m: int = 512) -> SparseGenerator:
+    """A generator that is block upper Hessenberg in levels of k states: each
+    state s gets `up` upward transitions, J levels of k states up plus a
+    uniform offset inside that level, with J >= 1 geometric of mean
+    `mean_jump` (batch arrivals: unbounded jumps up, mostly short), and `down`
+    transitions to states at most k below (one level down at a time).  Rates
+    U[0, 1].  Levels of the partition: equal runs of m states.  (A shape
+    stand-in for the first test matrix of section 3, the retrial queue with
+    800 levels of 138 states; its rates are not given.)"""
+    rng = np.random.default_rng(seed)
+    su = np.repeat(np.arange(N, dtype=np.int64), up)
+    J = rng.geometric(1.0 / mean_jump, size=len(su))
+    tu = su + J * k + rng.integers(0, k, size=len(su)) - (su % k)
+    ku = tu < N
+    sd = np.repeat(np.arange(N, dtype=np.int64), down)
+    td = sd - rng.integers(1, k + 1, size=len(sd))
+    kd = td >= 0
+    rows = np.concatenate([su[ku], sd[kd]])
+    cols = np.concatenate([tu[ku], td[kd]])
+    vals = rng.uniform(0.0, 1.0, size=len(rows))
+    return _from_triplets(rows, cols, vals, N, equal_levels(N, m), f"upper_hessenberg_N{N}_m{m}",
+                          {"k": k, "up": up, "down": down})

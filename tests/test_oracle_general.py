@@ -198,3 +198,44 @@ def test_example3_staircase_close_to_gauss_seidel():
     A = g.to_scipy().T.toarray()
     r1, r2 = table1.ratios(table1.gammas(A, synth.equal_levels(g.N, 16)))
     assert 1.0 < r1 < 2.0 and 1.0 <= r2 < 2.0
+
+
+def test_band_stand_ins_have_the_paper_shapes():
+    """The stand-ins for the second and third test matrices of section 3
+    (small copies): generators inside the stated scalar band; the symmetric
+    one has Q = Q^T, so its stationary vector is uniform, which GTH
+    confirms; in levels of the stated size they are block tridiagonal
+    (bandwidth below the level size) or reach two levels below and one above."""
+    g = synth.banded_random(900, 40, 40, 1, symmetric=True, m=64)
+    Q = g.to_scipy()
+    assert abs(Q - Q.T).max() == 0.0
+    assert np.abs(np.asarray(Q.sum(axis=1))).max() <= 1e-13
+    r, c = Q.nonzero()
+    assert np.abs(r - c).max() <= 40 and (Q.data[r != c] >= 0.0).all()
+    assert g.block_reach() == 1
+    pi = gth.gth(Q.toarray())
+    assert np.abs(pi - 1.0 / g.N).max() <= 1e-13
+    h = synth.banded_random(1000, 80, 50, 2, m=64)
+    Q = h.to_scipy()
+    r, c = Q.nonzero()
+    assert (c - r).max() <= 50 and (r - c).max() <= 80
+    lev = h.level_of()
+    assert (lev[c] - lev[r]).max() == 1 and (lev[r] - lev[c]).max() == 2
+
+
+def test_upper_hessenberg_stand_in_shape():
+    """The stand-in for the first test matrix of section 3: in levels of k
+    states, transitions go down at most one level and up any number of
+    levels (block upper Hessenberg), and it is a generator."""
+    k = 10
+    g = synth.upper_hessenberg(600, k, 3, m=k)
+    Q = g.to_scipy()
+    assert np.abs(np.asarray(Q.sum(axis=1))).max() <= 1e-13
+    r, c = Q.nonzero()
+    assert (Q.data[r != c] >= 0.0).all()
+    lr, lc = r // k, c // k
+    assert (lr - lc).max() == 1 and (lc - lr).max() >= 3
+    pi = gth.gth(Q.toarray())
+    sys = staircase.SparseBlockSystem(Q, synth.equal_levels(g.N, 40))
+    res = staircase.solve_system(sys, stair_type=1, tol=1e-13, maxit=50_000)
+    assert np.abs(res.x - pi).sum() <= 1e-10
