@@ -84,14 +84,17 @@ enum { STC_STAIRCASE = 0, STC_JGS = 1 };               /* stc_options.method    
  * that transitions reach many levels away).  Every entry may lie anywhere; the
  * near entries (levels i - 1 and i + 1, the J_i of the stair rows in
  * Algorithm 2) are read fresh by phase B and all others from the previous
- * iterate.  L * padded m must stay below 2^31.
+ * iterate.  L * padded m must stay below 2^31.  The block size may go up to
+ * 2048, which covers the partitions of the experiments in section 3 (levels
+ * of 256 to 2048 states); blocks padded to 512 and more are swept by column
+ * slices of 64 states, one partial sum per slice.
  *
  * Either way the host arrays are only read during stc_footprint_bytes and
  * stc_setup, and the caller keeps ownership. */
 typedef struct {
     int32_t L;                   /* levels, >= 2                                    */
     int32_t m;                   /* block size: max states per level, 1..128
-                                    (1..256 with b = STC_ANY_PATTERN)            */
+                                    (1..2048 with b = STC_ANY_PATTERN)           */
     int32_t b;                   /* block bandwidth, 1..4 (1: QBD), or
                                     STC_ANY_PATTERN                                 */
     const int32_t *sizes;        /* [L] states per level n_i in 1..m; NULL = all m */
