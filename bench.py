@@ -227,6 +227,8 @@ def main():
     ap.add_argument("--jgs", action="store_true")
     ap.add_argument("--large-blocks", action="store_true")
     ap.add_argument("--only", type=str, default="")
+    ap.add_argument("--large-probe", action="store_true")
+    ap.add_argument("--large-traffic", nargs=3, default=None)
     ap.add_argument("--traffic-summary", nargs=3, default=None)
     ap.add_argument("--batch-probe", action="store_true")
     ap.add_argument("--print-maps", action="store_true")
@@ -242,6 +244,8 @@ def main():
         return traffic_summary(*args.traffic_summary)
     if args.batch_traffic:
         return batch_traffic(*args.batch_traffic)
+    if args.large_traffic:
+        return large_traffic(*args.large_traffic)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not a measured path.", file=sys.stderr)
@@ -262,6 +266,8 @@ def main():
         return skipfree_mode()
     if args.large_blocks:
         return large_blocks_mode(args)
+    if args.large_probe:
+        return large_probe()
     if args.mutex:
         return mutex_mode(args)
     if args.example3:
@@ -1037,9 +1043,123 @@ def large_blocks_mode(args):
             "config": {"workload": "large_partitions", "best": best_name, "seed": seed},
             "roofline": {"bound": "hbm", "kernel": "large-block gather + apply (both phases)",
                          "achieved": best["GB/s_algorithmic"], "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(best["GB/s_algorithmic"] / 8000.0, 4), "traffic": None},
+                         "frac": round(best["GB/s_algorithmic"] / 8000.0, 4),
+                         "traffic": large_traffic_record() if best_name == LARGE_PROBE else None},
             "workloads": out, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
+
+
+LARGE_PROBE = "ncd_N91881_bw1135_m2048"
+
+
+def large_traffic_record():
+    """The counter record of the large-block probe's apply launches (HBM
+    bytes over algorithmic, per phase), if it was taken on the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(f"large_{LARGE_PROBE}_fp64")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return {k: {"hbm_bytes": v["hbm_bytes"], "algorithmic_bytes": v.get("algorithmic_bytes"),
+                "ratio": v.get("ratio")} for k, v in rec["launches"].items()}
+
+
+def large_probe(sweeps=10, copy_bytes=1 << 30):
+    """Counter-run workload of the large-block kernels: the symmetric
+    N = 91881 chain in levels of 2048, FP64 with the autotuned load policy,
+    `sweeps` sweeps, then three 1 GiB device copies (the calibration).
+    Prints the apply launches' algorithmic bytes per phase: the inverses
+    of the phase's levels, plus r_i read, z_i written and the two iterates
+    the change reads (8 bytes per state each)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    name, build, _closed = [w for w in LARGE_BLOCK_WORKLOADS if w[0] == LARGE_PROBE][0]
+    gen = build(synth.config_seed(3))
+    s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+               precision="fp64")
+    stc.stc_autotune(s.h, 5)
+    s.load(None)
+    s.sweeps(sweeps)
+    torch.cuda.synchronize()
+    n = gen.sizes.astype(np.float64)
+    apply_bytes = [float(8 * (n[p::2] ** 2).sum() + 4 * 8 * n[p::2].sum()) for p in (0, 1)]
+    x = torch.ones(copy_bytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": name, "variant": stc.stc_get_variant(s.h, stc.STC_FP64),
+                      "sweeps": sweeps, "apply_a_bytes": apply_bytes[0],
+                      "apply_b_bytes": apply_bytes[1], "copy_bytes_each_way": copy_bytes,
+                      "source_hash": kernel_source_hash()}), flush=True)
+    s.close()
+
+
+def large_traffic(probe_json, fetch_csv, write_csv):
+    """HBM bytes per apply launch of the large-block sweep (phase A and B
+    apart, the last `sweeps` dispatches of each) and per gather launch, from
+    the FETCH_SIZE and WRITE_SIZE runs of --large-probe, each counter scaled
+    by what it reads for the 1 GiB copies; stored in profiles/traffic.json
+    with the source hash."""
+    import csv
+    with open(probe_json) as f:
+        probe = json.loads(f.read().strip().splitlines()[-1])
+    cb = probe["copy_bytes_each_way"]
+
+    def per_kernel(path, counter):
+        rows = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                    rows[key] = rows.get(key, 0.0) + float(r["Counter_Value"])
+        sums, copy = {}, []
+        for (_, nm), v in sorted(rows.items()):
+            k = nm.replace(" ", "")
+            if "copyBuffer" in k:
+                copy.append(v)
+                continue
+            for kind in ("k_apply_big<double,2048,", "k_gather_big<double,2048,"):
+                if kind in k:
+                    phb = k.split(kind)[1].startswith("true")
+                    sums.setdefault((kind.split("<")[0][2:], phb), []).append(v)
+        sums = {k: v[-probe["sweeps"]:] for k, v in sums.items()}
+        copy = sorted(copy, reverse=True)[:3]
+        return sums, sum(copy) / len(copy)
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    fs, ws = cb / (fcopy * 1024), cb / (wcopy * 1024)
+    rec = {"source_hash": probe["source_hash"], "variant": probe["variant"],
+           "fetch_scale": fs, "write_scale": ws, "launches": {},
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -- python3 bench.py --large-probe",
+                        "rocprofv3 --pmc WRITE_SIZE -- python3 bench.py --large-probe",
+                        "python3 bench.py --large-traffic PROBE FETCH_CSV WRITE_CSV"]}
+    for (kind, phb) in sorted(fetch):
+        f = sum(fetch[(kind, phb)]) / len(fetch[(kind, phb)])
+        w = sum(write[(kind, phb)]) / len(write[(kind, phb)])
+        hbm = f * 1024 * fs + w * 1024 * ws
+        row = {"dispatches": len(fetch[(kind, phb)]), "fetch_kib": round(f, 1),
+               "write_kib": round(w, 1), "hbm_bytes": int(round(hbm))}
+        if kind == "apply_big":
+            alg = probe["apply_b_bytes" if phb else "apply_a_bytes"]
+            row.update({"algorithmic_bytes": alg, "ratio": round(hbm / alg, 4)})
+        rec["launches"][f"{kind}_{'b' if phb else 'a'}"] = row
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    table = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+    table[f"large_{LARGE_PROBE}_fp64"] = rec
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def krylov_mode(args, restart=60, tol=1e-12):

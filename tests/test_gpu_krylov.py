@@ -40,6 +40,9 @@ CHAINS = [
     ("skipfree_L30_m8", lambda: synth.skip_free(30, 8, 4, b=4), "dense"),
     ("loc_L20_m8_any", lambda: synth.localized(20, 8, 9, up=3, down=2, jumps=2, ragged=True),
      "any"),
+    # levels of up to 512: the large-block sweep (gather and sliced apply) as the operator
+    ("loc_L4_m512_any", lambda: synth.localized(4, 512, 17, up=2, down=1, jumps=1, ragged=True,
+                                                density=0.004), "any"),
 ]
 
 
