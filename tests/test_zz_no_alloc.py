@@ -53,6 +53,23 @@ def test_noalloc_residual_equals_stc_residual():
         s.close()
 
 
+def test_noalloc_residual_on_large_blocks():
+    """The large-block residual kernels (levels of 1000 and 512 states,
+    column slices of 64) through the allocation-free entry point: bitwise
+    stc_residual's value, the second handle smaller than the first."""
+    from paper_2302_07551_amd import Solver, stc
+    rng = np.random.default_rng(6)
+    for m, L, seed in ((1000, 4, 18), (512, 3, 19)):
+        g = synth.localized(L, m, seed, up=1, down=1, jumps=1, ragged=True, density=0.003)
+        s = Solver(None, g.sizes, stc.STC_ANY_PATTERN, csr=g.csr, format="sparse")
+        x = rng.uniform(-0.5, 1.5, g.N)
+        want = s.residual(x)
+        got = _noalloc(s, x)
+        print(f"any pattern {L} x {m}: stc_residual {want!r}, noalloc {got!r}", flush=True)
+        assert got == want
+        s.close()
+
+
 def test_noalloc_rejects_staging_above_the_limit():
     from paper_2302_07551_amd import Solver, stc
     L = 600_000                      # padded vector 600000 x 8 x 8 B = 38.4 MB > 32 MiB
