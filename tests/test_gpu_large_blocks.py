@@ -4,7 +4,8 @@ of the experiments in section 3).
 
 These run the large-block kernels: per phase a gather launch (r_i into a
 scratch vector) and an apply launch over column slices of W_i, one partial
-slot per slice, and the one-workgroup MFMA inverse in global memory.  The
+slot per slice, and the MFMA inverse over many workgroups per level (64-wide
+panels, the inverses stored tile-major).  The
 oracle is the same SparseBlockSystem sweep as for the smaller blocks, on the
 same seeded inputs.  Tolerances as for the other kernels: one FP64 sweep
 agrees to 1e-13 in the 1-norm, one FP32 sweep to 1e-5; a converged FP64
@@ -78,23 +79,24 @@ def test_large_block_step_matches_oracle(name, make, stair_type, precision):
     s.close()
 
 
+@pytest.mark.parametrize("stair_type", [1, 2])
 @pytest.mark.parametrize("name,make", [LARGE[k] for k in (0, 3)],
                          ids=[LARGE[k][0] for k in (0, 3)])
-def test_large_block_sweeps_on_the_resident_iterate(name, make):
+def test_large_block_sweeps_on_the_resident_iterate(name, make, stair_type):
     """Bursts of sweeps (lagged normalisation, phase B's fold over the slice
     partials, the flush in the apply kernel's slices) follow the oracle's
-    recurrence, and the changes are the oracle's."""
+    recurrence, and the changes are the oracle's, for both stair types."""
     g = make()
-    _say(f"large-block sweeps {name}")
+    _say(f"large-block sweeps {name} type {stair_type}")
     x = _start(g, 5)
-    s = _solver(g, poison=True)
+    s = _solver(g, poison=True, stair_type=stair_type)
     s.load(x)
     diffs = s.sweeps(6, with_diffs=True)
     z = s.store()
     sys = _system(g)
     xr, want = x, []
     for _ in range(6):
-        xr, dr = staircase.staircase_sweep(sys, xr, 1)
+        xr, dr = staircase.staircase_sweep(sys, xr, stair_type)
         want.append(dr)
     assert np.abs(z - xr).sum() <= 1e-13
     assert np.abs(np.asarray(diffs) - np.asarray(want[:-1])).max() <= 1e-13
@@ -170,7 +172,7 @@ def test_large_block_mutex_full_size_solve(m):
 @pytest.mark.parametrize("m", [512, 2048])
 def test_large_block_singular_diagonal_block(m):
     """A level whose states can never leave it makes Q_ii singular: setup
-    reports STC_ESINGULAR (the pivot check of the inverse in global memory)."""
+    reports STC_ESINGULAR (the pivot check of the panel inverses)."""
     from paper_2302_07551_amd import Solver, stc
     g = synth.localized(4, m, 24, up=1, down=1, jumps=0, backbone=0.0,
                         density=8.0 / m)
