@@ -112,7 +112,11 @@ __device__ inline void sweep_group_gen(const ChainView<T> &a, const GenEntry *ta
     // r_i[j] = sum over the column's slots of val * source.  The lane's first
     // pass of ELL loads goes out before the W_i rows: loads return in order,
     // so behind the rows the gather would wait for the whole block first.
-    constexpr int U = sizeof(T) == 8 ? 2 : 4;   // FP64 quads hold twice the registers
+    // quads per pass: FP64 quads hold twice the registers, so two, except
+    // with one lane per column (blocks of 256), where four keep a column's
+    // usual four quads in one pass (one round of index loads, one of
+    // gathers); the quads are added in the same order either way
+    constexpr int U = (sizeof(T) == 4 || G == 1) ? 4 : 2;
     const int j = tt % MP, gg0 = tt / MP;
     const int Kqn = te.Kn >> 2, Kq = (te.Kn + te.Kf) >> 2;
     GenPass<T, MP, G, U, NT> pass;
