@@ -298,7 +298,10 @@ stc_status stc_sweeps(stc_handle *h, int64_t nsweeps, double *diffs);
 
 /* Measurement form of stc_sweeps: the same sweeps, each phase launched with
  * a start and a stop event attached to its dispatch (hipExtLaunchKernel), so
- * the phase times are the kernels' own.  Returns the mean device time of the
+ * the phase times are the kernels' own (for blocks padded to 512 and more a
+ * phase is two launches, its gather and its apply: the start event goes with
+ * the first and the stop event with the second, so the time covers both).
+ * Returns the mean device time of the
  * phase-A launch, of the phase-B launch, of the finalize work per sweep (the
  * per-sweep finalize launches of long chains plus the flush that ends the
  * burst, spread over the sweeps), and the mean wall time of a whole sweep
