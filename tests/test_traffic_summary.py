@@ -84,3 +84,43 @@ def test_measured_traffic_needs_the_same_sources_and_variant(tmp_path, monkeypat
     assert bench.measured_traffic("w", 7) is None     # taken on other sources
     assert bench.measured_traffic("w", 1) is None     # never measured
     assert bench.measured_traffic("x", 3) is None
+
+
+def test_large_block_traffic(tmp_path, monkeypatch):
+    """The large-block probe: apply launches per phase (the last `sweeps`
+    dispatches of each), gathers apart, other kernels ignored, both counters
+    calibrated by the copies; the record goes under the probe's key with its
+    source hash, and the line's reader takes it only for the current
+    sources."""
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    with open(tmp_path / "probe.txt", "w") as f:
+        f.write(json.dumps({"probe": bench.LARGE_PROBE, "variant": 2, "sweeps": 2,
+                            "apply_a_bytes": 1000.0 * 1024, "apply_b_bytes": 2000.0 * 1024,
+                            "copy_bytes_each_way": 1 << 30, "source_hash": "abc"}) + "\n")
+    aa = "void stc::k_apply_big<double, 2048, false, true>(stc::SweepLaunch, double const*)"
+    ab = "void stc::k_apply_big<double, 2048, true, true>(stc::SweepLaunch, double const*)"
+    ga = ("void stc::k_gather_big<double, 2048, false, true>(stc::SweepLaunch, "
+          "stc::GenEntry const*, double const*, int const*, double*)")
+    f32 = "void stc::k_apply_big<float, 2048, false, true>(stc::SweepLaunch, float const*)"
+    copy = "__amd_rocclr_copyBuffer"
+    # an autotuner trial first (dropped: only the last two dispatches count)
+    fetch = [(aa, 9999.0), (aa, 500.0), (ab, 1000.0), (ga, 40.0), (aa, 500.0), (ab, 1000.0),
+             (ga, 40.0), (f32, 7777.0)] + [(copy, KIB_GIB / 2)] * 3
+    write = [(aa, 9999.0), (aa, 10.0), (ab, 20.0), (ga, 4.0), (aa, 10.0), (ab, 20.0),
+             (ga, 4.0), (f32, 7777.0)] + [(copy, KIB_GIB)] * 3
+    _write_csv(tmp_path / "f.csv", "FETCH_SIZE", fetch)
+    _write_csv(tmp_path / "w.csv", "WRITE_SIZE", write)
+    bench.large_traffic(str(tmp_path / "probe.txt"), str(tmp_path / "f.csv"),
+                        str(tmp_path / "w.csv"))
+    with open(tmp_path / "profiles" / "traffic.json") as f:
+        rec = json.load(f)[f"large_{bench.LARGE_PROBE}_fp64"]
+    assert rec["source_hash"] == "abc" and rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    a, b, g = (rec["launches"][k] for k in ("apply_big_a", "apply_big_b", "gather_big_a"))
+    assert a["dispatches"] == 2 and a["hbm_bytes"] == (500 * 2 + 10) * 1024
+    assert a["ratio"] == round((500 * 2 + 10) / 1000, 4)
+    assert b["hbm_bytes"] == (1000 * 2 + 20) * 1024 and b["ratio"] == round(2020 / 2000, 4)
+    assert g["hbm_bytes"] == (40 * 2 + 4) * 1024 and "ratio" not in g
+    assert bench.large_traffic_record() is None          # not the current sources
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
+    assert bench.large_traffic_record()["apply_big_a"]["hbm_bytes"] == (500 * 2 + 10) * 1024
