@@ -111,7 +111,10 @@ typedef struct {
     int32_t precision;    /* STC_FP64: FP64 blocks and sweeps.
                              STC_FP32: FP32 blocks and sweeps, FP64 sums.
                              STC_MIXED: FP32 sweeps until the change falls below
-                             switch_tol, then FP64 sweeps to tol.             */
+                             switch_tol, or stops falling (the FP32 rounding
+                             floor: no new low over 4 readings taken every 32
+                             sweeps or every check_every, if longer), then
+                             FP64 sweeps to tol.                              */
     int32_t stair_type;   /* 1: M = M1 (phase A = even 0-based levels);
                              2: M = M2 (phase A = odd 0-based levels)         */
     int32_t stop;         /* STC_STOP_DIFF: ||x^(k) - x^(k-1)||_1 <= tol

@@ -1989,6 +1989,25 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
     long long s = 0, final_k = -1;
     bool converged = false;
     HostState hs;
+    // The FP32 stage also ends at its rounding floor, which may lie above
+    // switch_tol: its change is read every kStallSweeps sweeps (or every
+    // burst, if longer), and after kStallReads readings in a row with no new
+    // low the solve continues in FP64 from the current sweep.  A converging
+    // stage makes a new low at every reading.
+    constexpr long long kStallSweeps = 32;
+    constexpr int kStallReads = 4;
+    long long next_read = 0;
+    double low32 = INFINITY;
+    int stale = 0;
+    auto to_fp64 = [&](long long k) -> stc_status {
+        h->iters32 = k;
+        stc_status r = widen_at(h, k);
+        if (r != STC_OK) return r;
+        HIP_TRY(launch_rearm(h->st, k, h->stream));
+        s = k;
+        h->s = k;
+        return STC_OK;
+    };
     while (s < maxit) {
         const long long n = std::min<long long>(h->check_every, maxit - s);
         const double dt = device_tol();
@@ -2007,16 +2026,25 @@ stc_status stc_solve(stc_handle *h, const double *x0, double tol, int64_t maxit,
             const long long k = hs.stop_sweep;
             if (mixed && h->stage32) {
                 // FP32 stage done: continue in FP64 from sweep k
-                h->iters32 = k;
-                if ((rc = widen_at(h, k)) != STC_OK) return rc;
-                HIP_TRY(launch_rearm(h->st, k, h->stream));
-                s = k;
-                h->s = k;
+                if ((rc = to_fp64(k)) != STC_OK) return rc;
                 continue;
             }
             final_k = k;
             converged = true;
             break;
+        }
+        if (mixed && h->stage32 && s >= next_read && s < maxit) {
+            next_read = s + std::max<long long>(h->check_every, kStallSweeps);
+            double d;
+            if ((rc = read_ring(h, h->st->diff, s, &d)) != STC_OK) return rc;
+            if (d < low32) {
+                low32 = d;
+                stale = 0;
+            } else if (++stale >= kStallReads) {
+                // FP32 rounding floor: continue in FP64 from sweep s
+                if ((rc = to_fp64(s)) != STC_OK) return rc;
+                continue;
+            }
         }
         if (h->stop == STC_STOP_RESIDUAL && !(mixed && h->stage32)) {
             double r;

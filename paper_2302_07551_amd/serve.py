@@ -5,8 +5,10 @@ admits them in arrival order while the HBM footprint of the admitted chains
 stays under a budget and a batch slot is free, keeps every admitted chain's
 factored blocks and iterate resident on the device, and sweeps all admitted
 chains together with the batched (multi-chain) launch.  A
-chain in its FP32 stage that meets the switch tolerance is promoted to FP64
-(stc_promote); a chain whose FP64 change meets the tolerance is retired: its
+chain in its FP32 stage that meets the switch tolerance, or whose FP32
+change has stopped falling (its rounding floor lies above the switch
+tolerance), is promoted to FP64 (stc_promote); a chain whose FP64 change
+meets the tolerance is retired: its
 vector is copied out, its memory freed, and waiting requests are admitted.
 A chain that reaches the per-request sweep cap is retired the same way with
 status STC_EMAXIT (its last iterate is returned).  A request whose setup
@@ -106,6 +108,25 @@ class ServeStats:
             "peak_bytes": self.peak_bytes,
             "batch_rounds": self.rounds,
         }
+
+
+class _Floor32:
+    """The FP32 stage's rounding floor, per request: the change read after
+    each round either makes a new low or not; `rounds` readings in a row with
+    no new low mean the FP32 sweeps have stopped converging (a converging
+    stage makes a new low at every reading), whatever switch_tol asks."""
+
+    def __init__(self, rounds: int):
+        self.rounds = rounds
+        self.state = {}
+
+    def reached(self, rid, diff: float) -> bool:
+        low, stale = self.state.get(rid, (float("inf"), 0))
+        if diff < low:
+            self.state[rid] = (diff, 0)
+            return False
+        self.state[rid] = (low, stale + 1)
+        return stale + 1 >= self.rounds
 
 
 class Server:
@@ -234,6 +255,8 @@ class Server:
         in_setup = 0         # admitted, not yet set up or not yet active
         to_setup = []        # inline setup: admitted requests to set up this round
         stats = ServeStats()
+        # readings spanning at least 4 rounds and 128 sweeps, as stc_solve's
+        floor32 = _Floor32(max(4, -(-128 // self.K)))
         todo: queue.Queue = queue.Queue()
         ready: queue.Queue = queue.Queue()     # solvers set up (or errors)
         done: queue.Queue = queue.Queue()      # prepared host halves (or errors)
@@ -359,7 +382,7 @@ class Server:
                 # next round
                 setup_inline()
                 # one device-to-host copy for every chain's stopping state
-                sweeps, stopped, _diffs, status = self.batch.query()
+                sweeps, stopped, diffs, status = self.batch.query()
                 stats.rounds += 1
                 keep = []
                 for k, entry in enumerate(active):
@@ -374,6 +397,14 @@ class Server:
                         continue
                     capped = not stopped[k] and int(sweeps[k]) >= self.max_sweeps
                     if not stopped[k] and not capped:
+                        if (stage == 32 and self.precision == "mixed"
+                                and floor32.reached(req.rid, float(diffs[k]))):
+                            # the FP32 stage's rounding floor lies above
+                            # switch_tol: continue in FP64
+                            s.promote()
+                            entry[4] = 64
+                            entry.append(int(sweeps[k]))
+                            dirty = True
                         keep.append(entry)
                         continue
                     if stage == 32 and self.precision == "mixed" and not capped:

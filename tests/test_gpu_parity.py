@@ -286,6 +286,23 @@ def test_mixed_switch_inside_a_burst_equals_one_sweep_bursts(tol):
     assert np.abs(p50 - o.x).sum() <= 1e-5
 
 
+@pytest.mark.parametrize("check_every", [1, 50])
+def test_mixed_switch_at_the_fp32_floor(check_every):
+    """A switch tolerance below what FP32 sweeps can reach: the FP32 stage
+    ends at its rounding floor (its change stops making new lows) instead of
+    running to maxit, and the FP64 stage converges to the direct solution."""
+    g = synth.qbd(48, 16, 61)
+    ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+    s = _solver(g, precision="mixed", stop="diff", check_every=check_every, switch_tol=1e-15)
+    pi, info = s.solve(tol=1e-13, maxit=50000, allow_maxit=False)
+    err = np.abs(pi - ref).sum()
+    _say(f"floor switch, bursts of {check_every}: iters {info['iters']} "
+         f"fp32 {info['iters_fp32']} err {err:.2e}")
+    assert info["status"] == 0 and err <= 1e-10
+    assert 0 < info["iters_fp32"] < info["iters"] < 50000
+    s.close()
+
+
 def test_residual_matches_oracle():
     g = synth.banded(12, 32, 71, b=2, last=20)
     x = np.random.default_rng(3).standard_normal(g.N)

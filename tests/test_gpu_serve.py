@@ -66,6 +66,25 @@ def test_served_equals_alone_and_budget_holds():
         assert np.abs(r.pi - ref).sum() <= 1e-10, k
 
 
+def test_fp32_floor_promotes_in_the_served_stream():
+    """With a switch tolerance no FP32 sweep reaches, every request is
+    promoted at its FP32 rounding floor and completes in FP64, within 1e-10
+    of its direct solution."""
+    from paper_2302_07551_amd import stc
+    from paper_2302_07551_amd.serve import Server
+    reqs, gens = _requests(6, 77, rate=1000.0, L_range=(40, 120), m_choices=(8, 16, 32))
+    srv = Server(budget_bytes=1 << 30, max_chains=8, sweeps_per_round=25, tol=1e-13,
+                 switch_tol=1e-15, max_sweeps=200_000)
+    stats = srv.run(reqs)
+    srv.close()
+    assert sorted(r.rid for r in stats.results) == list(range(6)) and not stats.rejected
+    for r in stats.results:
+        assert r.status == stc.STC_OK and 0 < r.sweeps_fp32 < r.sweeps, r.rid
+        g = gens[r.rid]
+        ref = level_reduction.level_reduction(g.blocks, g.sizes, g.b)
+        assert np.abs(r.pi - ref).sum() <= 1e-10, r.rid
+
+
 def test_oversized_request_is_rejected():
     from paper_2302_07551_amd.serve import Server
     reqs, _ = _requests(3, 7, rate=1000.0, L_range=(40, 60), m_choices=(16,))
