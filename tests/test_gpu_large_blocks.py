@@ -209,3 +209,35 @@ def test_large_block_load_policies_agree():
     assert np.array_equal(a.store(), b.store())
     a.close()
     b.close()
+
+
+FULL_SIZE = [
+    ("mutex_n16_r12_m512", lambda sd: synth.mutual_exclusion(16, 12, sd, m=512)),
+    ("prio_N79220_m1024", lambda sd: synth.banded_random(79220, 2370, 1585, sd, m=1024)),
+    ("ncd_N91881_bw1135_m2048",
+     lambda sd: synth.banded_random(91881, 1135, 1135, sd, symmetric=True, m=2048)),
+]
+
+
+@pytest.mark.parametrize("name,make", FULL_SIZE, ids=[f[0] for f in FULL_SIZE])
+def test_large_block_full_size_sweep_matches_c_oracle(name, make):
+    """The large-partition workloads at their full sizes (N = 64839 to
+    91881), as the benchmark builds them: one FP64 sweep under both load
+    policies, element by element against the oracle's C/OpenMP sweep of the
+    whole chain (LU-factored diagonal blocks), with no fitted scalar; and
+    the change."""
+    from oracle import csweep
+    from paper_2302_07551_amd import stc
+    g = make(synth.config_seed(3))
+    x = _start(g, 12)
+    c = csweep.CGenSweep(g.to_scipy(), g.sizes, stair_type=1)
+    zr = np.zeros(g.N)
+    dr = c.sweep(x, zr)
+    s = _solver(g)
+    for variant in (0, 2):
+        stc.stc_set_variant(s.h, stc.STC_FP64, variant)
+        z, d = s.step(x)
+        err = np.abs(z - zr).sum()
+        _say(f"full size {name} variant {variant}: |z - z_oracle|_1 = {err:.2e}")
+        assert err <= 1e-13 and abs(d - dr) <= 1e-13
+    s.close()
