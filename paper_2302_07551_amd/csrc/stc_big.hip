@@ -177,19 +177,20 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     __syncthreads();
 
     VT acc = (VT)(T)0;
-    for (int q0 = 0; q0 < RPT; q0 += PW) {
+    int q0 = 0;
+    for (; q0 + PW < RPT; q0 += PW) {
         VT nxt[PW];
-        if (q0 + PW < RPT) {
 #pragma unroll
-            for (int u = 0; u < PW; ++u)
-                nxt[u] = stream_load<VT, NT>(
-                    (const VT *)(wb + slice_row_off<MP>(g + R * (q0 + PW + u))));
-        }
+        for (int u = 0; u < PW; ++u)
+            nxt[u] = stream_load<VT, NT>(
+                (const VT *)(wb + slice_row_off<MP>(g + R * (q0 + PW + u))));
 #pragma unroll
         for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + R * (q0 + u)];
 #pragma unroll
         for (int u = 0; u < PW; ++u) cur[u] = nxt[u];
     }
+#pragma unroll
+    for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + R * (q0 + u)];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[g * CS + c * VEC + e] = acc[e];
     __syncthreads();

@@ -1364,8 +1364,9 @@ __device__ __forceinline__ void gj_blocked(double *a, const double *dorig,
                 while (u < nu) {
                     const int un = u + du;
                     int i0n = 0, j0n = 0;
-                    d4_t accn;
-                    double avn[4], bvn[4];
+                    // defined also when there is no next tile (then unused)
+                    d4_t accn = {0.0, 0.0, 0.0, 0.0};
+                    double avn[4] = {0.0, 0.0, 0.0, 0.0}, bvn[4] = {0.0, 0.0, 0.0, 0.0};
                     if (un < nu) {
                         tile_at(tile_of(un), i0n, j0n);
                         fetch(i0n, j0n, accn, avn, bvn);
