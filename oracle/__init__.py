@@ -20,8 +20,13 @@ Contents (each function cites the passage it follows):
                       (block Jacobi, block Gauss-Seidel, the [BB] composite,
                       stair matrices M1 / M2) and their iteration spectra.
   csweep.c            the same Algorithm 2 sweep as plain C with OpenMP loops
-                      over levels (mirrors the paper's C++/OpenMP build), used
-                      only to time a CPU baseline.
+                      over levels (mirrors the paper's C++/OpenMP build): the
+                      CPU baseline, and the whole-chain reference of the
+                      full-size parity tests.
+  krylov.py           restarted GMRES on (I - M^{-1} N) x = 0, the splitting
+                      as a preconditioner (the paper's stated future work).
+  table1.py           Example 3 / Table 1: the spectral radii of the block
+                      Jacobi, block Gauss-Seidel and staircase iterations.
 
 Every function here is pinned by tests under tests/ against facts that do not
 come from the oracle itself (closed forms, the paper's worked examples,
