@@ -25,8 +25,10 @@ Contents (each function cites the passage it follows):
                       full-size parity tests.
   krylov.py           restarted GMRES on (I - M^{-1} N) x = 0, the splitting
                       as a preconditioner (the paper's stated future work).
-  table1.py           Example 3 / Table 1: the spectral radii of the block
-                      Jacobi, block Gauss-Seidel and staircase iterations.
+  table1.py           Example 3 / Table 1: the spectral gaps (gamma, the
+                      largest modulus after 1) of the block Jacobi, block
+                      Gauss-Seidel and staircase iterations, and the ratios
+                      rho_1, rho_2 over random trials.
 
 Every function here is pinned by tests under tests/ against facts that do not
 come from the oracle itself (closed forms, the paper's worked examples,
