@@ -239,3 +239,24 @@ def test_upper_hessenberg_stand_in_shape():
     sys = staircase.SparseBlockSystem(Q, synth.equal_levels(g.N, 40))
     res = staircase.solve_system(sys, stair_type=1, tol=1e-13, maxit=50_000)
     assert np.abs(res.x - pi).sum() <= 1e-10
+
+
+def test_large_partition_workloads_have_the_papers_sizes():
+    """The large-partition bench builds its workloads at the sizes and
+    partitions of section 3: N = 64839 (mutual exclusion), 110400 (first
+    matrix, levels of 512), 91881 (second, levels of 2048, block
+    tridiagonal as the paper notes), 79220 (third, levels of 512 to 2048);
+    every one a generator (rows sum to 0, rates >= 0)."""
+    import bench
+    want_N = {"mutex": 64839, "uhess": 110400, "ncd": 91881, "prio": 79220}
+    for name, build, _closed in bench.LARGE_BLOCK_WORKLOADS:
+        g = build(synth.config_seed(3))
+        m = int(name.rsplit("_m", 1)[1])
+        assert g.N == want_N[name.split("_")[0]], name
+        assert g.m == m and g.L == -(-g.N // m), name
+        Q = g.to_scipy()
+        assert np.abs(np.asarray(Q.sum(axis=1))).max() <= 1e-12, name
+        r, c = Q.nonzero()
+        assert (Q.data[r != c] >= 0.0).all(), name
+        if name.startswith("ncd"):
+            assert g.block_reach() == 1
