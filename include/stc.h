@@ -157,9 +157,13 @@ typedef struct {
                              the chunk's earlier levels), then the same
                              normalisation and change.  jgs_chunks = 1 is
                              plain block Gauss-Seidel, jgs_chunks = L block
-                             Jacobi.  Dense storage only, no Krylov workspace,
-                             not in batches; stair_type is ignored; every
-                             other call works as for the stair splitting.  */
+                             Jacobi.  Dense band storage, or STC_ANY_PATTERN
+                             with m up to 256 (each level's off-diagonal
+                             entries read fresh or old by their source
+                             level); no banded sparse storage, no Krylov
+                             workspace, not in batches; stair_type is
+                             ignored; every other call works as for the
+                             stair splitting.  */
     int32_t jgs_chunks;   /* STC_JGS: the number of chunks p, 1..L          */
 } stc_options;
 

@@ -204,6 +204,119 @@ __global__ __launch_bounds__(kWG) void k_sweep_gen(SweepLaunch a, const GenEntry
                                     rv, sh);
 }
 
+// Algorithm 1 (JGS) on a generator of any block pattern: one workgroup per
+// chunk of consecutive levels k0 .. k1 - 1, taken in order (block
+// Gauss-Seidel inside the chunk, block Jacobi across chunks).  Level k's
+// entries read W_s for sources in the chunk's earlier levels (written by
+// this workgroup before a barrier) and the previous iterate, scaled by
+// kappa, everywhere else; z_k = W_k r_k with the dense inverse.  The sums
+// e^T z and the change are accumulated per thread over the chunk's levels
+// in the dense JGS kernel's geometry (team 0, elements tt, tt + TS, ...),
+// so its change kernel gives the flush the same partials.  The extra
+// workgroup of a.fold records sweep s - 1 first.
+template <typename T, int MP, bool NT>
+__global__ __launch_bounds__(kWG) void k_sweep_jgs_gen(SweepLaunch a, int chunks,
+                                                        const GenEntry *tab, const void *valv,
+                                                        const int *idx) {
+    using TL = Tile<T, MP, 8>;
+    using VT = typename Vec16<T>::type;
+    constexpr int VEC = TL::VEC, CT = TL::CT, R = TL::R, RPT = TL::RPT, TS = TL::TS;
+    constexpr int G = TS / MP;            // lanes splitting the ELL slots of a column
+    constexpr size_t BS = (size_t)MP * MP;
+    __shared__ T red[R * MP];
+    __shared__ T rv[MP];
+    __shared__ double sh[4 * kWG / 64];
+    int q = blockIdx.x;
+    if (a.fold) {
+        if (q == 0) {
+            fold_previous(a, sh);
+            return;
+        }
+        --q;
+    }
+    const T *val = (const T *)valv;
+    const DevState *st = a.st;
+    const int tid = threadIdx.x;
+    const int team = tid / TS, tt = tid - team * TS;
+    const int c = tt % CT, g = tt / CT;
+    const int j = tt % MP, gg0 = tt / MP;
+    const bool worker = team == 0;
+    const bool live = st->stop_flag == 0;
+    const T sc = (T)st->inv_sigma[(a.s - 2) & kRingMask];
+    const int k0 = (int)((long long)q * a.L / chunks), k1 = (int)((long long)(q + 1) * a.L / chunks);
+    const T *w_old = (const T *)a.w_old, *w_d1 = (const T *)a.w_d1, *w_d2 = (const T *)a.w_d2;
+    T *w_new = (T *)a.w_new;
+    double i2 = 0.0, i3 = 0.0;
+    if (a.s >= 3) {
+        i2 = st->inv_sigma[(a.s - 2) & kRingMask];
+        i3 = st->inv_sigma[(a.s - 3) & kRingMask];
+    }
+    double zs = 0.0, dd = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        const T *wb = (const T *)a.blk + (size_t)k * BS + c * VEC;
+        if (worker) {
+            // r_k[j]: the column's slots, fresh sources (levels k0 .. k - 1)
+            // and previous-iterate sources summed apart, in slot order
+            const GenEntry te = tab[k];
+            const int Kq = (te.Kn + te.Kf) >> 2;
+            T accF = 0, accO = 0;
+            for (int kq = gg0; kq < Kq; kq += G) {
+                const size_t o = (size_t)te.off + ((size_t)kq * MP + j) * 4;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int si = idx[o + t];
+                    const int lev = si / MP;
+                    if (lev >= k0 && lev < k)
+                        accF += val[o + t] * w_new[si];
+                    else
+                        accO += val[o + t] * w_old[si];
+                }
+            }
+            red[gg0 * MP + j] = accF + sc * accO;
+        }
+        __syncthreads();
+        if (worker && tt < MP) {
+            T r = 0;
+#pragma unroll
+            for (int x = 0; x < G; ++x) r += red[x * MP + tt];
+            rv[tt] = r;
+        }
+        __syncthreads();
+        // z_k = W_k r_k
+        if (worker) {
+            VT acc2 = (VT)(T)0;
+#pragma unroll 8
+            for (int qq = 0; qq < RPT; ++qq) {
+                const int row = g + R * qq;
+                acc2 += stream_load<VT, NT>((const VT *)(wb + (size_t)row * MP)) * rv[row];
+            }
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) red[g * MP + c * VEC + e] = acc2[e];
+        }
+        __syncthreads();
+        if (worker) {
+#pragma unroll
+            for (int e = tt; e < MP; e += TS) {
+                T z = 0;
+#pragma unroll
+                for (int gg = 0; gg < R; ++gg) z += red[gg * MP + e];
+                if (live) w_new[(size_t)k * MP + e] = z;
+                zs += (double)z;
+                if (a.s >= 3)
+                    dd += fabs((double)w_d1[(size_t)k * MP + e] * i2 -
+                               (double)w_d2[(size_t)k * MP + e] * i3);
+            }
+        }
+        __syncthreads();   // W_s of level k is visible to the chunk's next levels
+    }
+    double S = zs, D = dd;
+    block_sum2(S, D, sh);
+    if (live && tid == 0) {
+        a.part_sum[q] = S;
+        a.part_diff[q] = D;
+    }
+}
+
 // ||Q^T x||_1 per group of levels, FP64: (Q^T x) restricted to level i is
 // A_{i,i} x_i (dense diagonal block) plus the level's ELL entries applied to
 // x, with x = w * inv_sigma[slot] (slot < 0: w as given).
@@ -352,6 +465,41 @@ hipError_t launch_residual_gen(int precision_bytes, int MP, const double *diag64
             : residual_gen_t<float>(MP, groups, diag64, tab, val64, idx, w, L, st, slot, part, stream);
     if (e != hipSuccess) return e;
     return launch_reduce_residual(part, groups, st, stream, out);
+}
+
+
+template <typename T, int MP>
+static hipError_t jgs_gen_mp(bool nt, int chunks, const SweepLaunch &a, const GenEntry *tab,
+                             const void *val, const int *idx, hipStream_t s, LaunchTimer t) {
+    const int groups = chunks + (a.fold ? 1 : 0);
+    if (nt)
+        launch_timed(k_sweep_jgs_gen<T, MP, true>, groups, s, t, a, chunks, tab, val, idx);
+    else
+        launch_timed(k_sweep_jgs_gen<T, MP, false>, groups, s, t, a, chunks, tab, val, idx);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t jgs_gen_t(int MP, bool nt, int chunks, const SweepLaunch &a,
+                            const GenEntry *tab, const void *val, const int *idx, hipStream_t s,
+                            LaunchTimer t) {
+    switch (MP) {
+        case 8: return jgs_gen_mp<T, 8>(nt, chunks, a, tab, val, idx, s, t);
+        case 16: return jgs_gen_mp<T, 16>(nt, chunks, a, tab, val, idx, s, t);
+        case 32: return jgs_gen_mp<T, 32>(nt, chunks, a, tab, val, idx, s, t);
+        case 64: return jgs_gen_mp<T, 64>(nt, chunks, a, tab, val, idx, s, t);
+        case 128: return jgs_gen_mp<T, 128>(nt, chunks, a, tab, val, idx, s, t);
+        case 256: return jgs_gen_mp<T, 256>(nt, chunks, a, tab, val, idx, s, t);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sweep_jgs_gen(int precision_bytes, int MP, bool nt, int chunks,
+                                const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                const int *idx, hipStream_t stream, LaunchTimer t) {
+    if (chunks < 1 || chunks > a.L) return hipErrorInvalidValue;
+    return precision_bytes == 8 ? jgs_gen_t<double>(MP, nt, chunks, a, tab, val, idx, stream, t)
+                                : jgs_gen_t<float>(MP, nt, chunks, a, tab, val, idx, stream, t);
 }
 
 }  // namespace stc

@@ -323,6 +323,12 @@ hipError_t launch_residual_big_partials(int precision_bytes, int MP, int groups,
 // the change of sweep k in its geometry, with the device stopping test.
 hipError_t launch_sweep_jgs(int precision_bytes, int MP, int b, bool nt, int chunks,
                             const SweepLaunch &a, hipStream_t stream, LaunchTimer t);
+// The same for a generator of any block pattern (stc_general.hip), padded
+// blocks up to 256, from its per-level ELL; its partials follow the dense
+// kernel's geometry, so launch_diff_jgs serves both.
+hipError_t launch_sweep_jgs_gen(int precision_bytes, int MP, bool nt, int chunks,
+                                const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                const int *idx, hipStream_t stream, LaunchTimer t);
 hipError_t launch_diff_jgs_partials(int precision_bytes, int MP, const void *w, const void *w_prev,
                                     int L, int chunks, const DevState *st, long long k,
                                     double *part, hipStream_t stream);

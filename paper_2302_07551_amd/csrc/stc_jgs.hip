@@ -219,6 +219,7 @@ static hipError_t diff_jgs_t(int MP, const void *w, const void *wp, int L, int c
         case 32: return diff_jgs_mp<T, 32>(w, wp, L, chunks, st, k, part, s);
         case 64: return diff_jgs_mp<T, 64>(w, wp, L, chunks, st, k, part, s);
         case 128: return diff_jgs_mp<T, 128>(w, wp, L, chunks, st, k, part, s);
+        case 256: return diff_jgs_mp<T, 256>(w, wp, L, chunks, st, k, part, s);
     }
     return hipErrorInvalidValue;
 }

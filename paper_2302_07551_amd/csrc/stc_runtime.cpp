@@ -342,9 +342,10 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (general && (long long)g->L * MP >= (1ll << 31)) { *why = 12; return false; }
     if (o->krylov_restart < 0 || o->krylov_restart > kMaxRestart) { *why = 13; return false; }
     if (o->method != STC_STAIRCASE && o->method != STC_JGS) { *why = 15; return false; }
+    // Algorithm 1: dense band storage, or any block pattern in blocks up to 256
     if (o->method == STC_JGS &&
-        (o->format != STC_DENSE || general || o->krylov_restart != 0 || o->jgs_chunks < 1 ||
-         o->jgs_chunks > g->L)) { *why = 16; return false; }
+        ((general ? MP > kMaxSmallMP : o->format != STC_DENSE) || o->krylov_restart != 0 ||
+         o->jgs_chunks < 1 || o->jgs_chunks > g->L)) { *why = 16; return false; }
     Layout l;
     l.MP = MP;
     l.NB = general ? 1 : 2 * g->b + 1;   // any pattern: only the diagonal slot is dense
@@ -531,8 +532,13 @@ hipError_t enqueue_sweep_jgs(stc_handle *h, long long s, double tol, const Sweep
     a.prev_sum = h->part_sum + ((s - 1) & 1) * h->lay.nparts;
     a.prev_diff = h->part_diff + ((s - 1) & 1) * h->lay.nparts;
     const bool nt = variant_nt(h->variant[f32 ? 1 : 0]);
-    hipError_t e = launch_sweep_jgs(f32 ? 4 : 8, h->MP, h->b, nt, h->chunks, a, h->stream,
-                                    tm ? tm->a : LaunchTimer());
+    hipError_t e =
+        h->general
+            ? launch_sweep_jgs_gen(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab,
+                                   f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
+                                   h->gen_idx, h->stream, tm ? tm->a : LaunchTimer())
+            : launch_sweep_jgs(f32 ? 4 : 8, h->MP, h->b, nt, h->chunks, a, h->stream,
+                               tm ? tm->a : LaunchTimer());
     if (!fold_ok) {
         if (e == hipSuccess && tm) e = hipEventRecord(tm->fin0, h->stream);
         if (e == hipSuccess)
@@ -1168,7 +1174,8 @@ stc_status plan_setup(const stc_generator *g, const stc_options *o, Layout *lay)
                                     "krylov_restart must be in 0..256",
                                     "the sparse storage of the blocks exceeds 2^31 slots",
                                     "unknown method",
-                                    "STC_JGS takes dense storage, no Krylov workspace and "
+                                    "STC_JGS takes dense band storage or a pattern of any "
+                                    "shape in blocks up to 256, no Krylov workspace and "
                                     "jgs_chunks in 1..L"};
         return fail(STC_EINVAL, "%s", msg[why < 17 ? why : 0]);
     }

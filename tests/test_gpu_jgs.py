@@ -7,6 +7,13 @@ One sweep from the same x agrees to 1e-13 in the 1-norm (FP64) or 1e-5
 (block Jacobi); a burst's changes agree with the oracle's; converged solves
 of block Gauss-Seidel and JGS reach GTH within 1e-10 with the oracle's sweep
 count (within 1).
+
+Generators of any block pattern (levels up to 256 states, the CSR input)
+run the same algorithm from their per-level entry lists, a source read
+fresh when its level is one of the chunk's earlier levels: one sweep, bursts
+(bit for bit against single sweeps) and converged solves against the same
+oracle sweep on the block view of the sparse matrix, and the
+mutual-exclusion model against its closed form.
 """
 import numpy as np
 import pytest
@@ -170,3 +177,118 @@ def test_profiled_sweeps_then_a_new_setup():
     _z, d = s2.step(synth.positive_start(g, 1))
     assert np.isfinite(d)
     s2.close()
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 on generators of any block pattern (CSR input, per-level ELL)
+# ---------------------------------------------------------------------------
+GENERAL = [
+    ("loc_L12_m6_ragged", lambda: synth.localized(12, 6, 1, up=2, down=2, jumps=2, ragged=True)),
+    ("hess_L16_m8", lambda: synth.localized(16, 8, 2, up=16, down=1, jumps=0)),
+    ("loc_L9_m1", lambda: synth.localized(9, 1, 5, up=3, down=3, jumps=1)),
+    ("mutex_n10_r6_m32", lambda: synth.mutual_exclusion(10, 6, 4, m=32)),
+    ("loc_L7_m128", lambda: synth.localized(7, 128, 7, up=2, down=6, jumps=1, density=0.03)),
+    ("loc_L5_m256_ragged", lambda: synth.localized(5, 256, 15, up=2, down=2, jumps=1,
+                                                   ragged=True, density=0.02)),
+]
+
+
+def _gen_solver(g, p, **kw):
+    from paper_2302_07551_amd import Solver, stc
+    return Solver(None, g.sizes, stc.STC_ANY_PATTERN, csr=g.csr, format="sparse", method="jgs",
+                  jgs_chunks=p, **kw)
+
+
+def _gen_system(g):
+    return staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+
+
+def _gen_start(g, seed):
+    x = np.random.default_rng(seed).uniform(0.5, 1.5, g.N)
+    return x / x.sum()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,make", GENERAL, ids=[s[0] for s in GENERAL])
+def test_any_pattern_one_sweep_matches_the_oracle(name, make, precision):
+    """One sweep of Algorithm 1 on a pattern of any shape for one chunk
+    (block Gauss-Seidel), a few, and one per level (block Jacobi), against
+    the oracle's jgs_sweep on the same system."""
+    g = make()
+    sysg = _gen_system(g)
+    x = _gen_start(g, 21)
+    tol = 1e-13 if precision == "fp64" else 1e-5
+    for p in sorted({1, min(3, g.L), g.L}):
+        zr, dr = staircase.jgs_sweep(sysg, x, _chunks(g.L, p))
+        s = _gen_solver(g, p, precision=precision, poison=True)
+        z, d = s.step(x)
+        err = np.abs(z - zr).sum()
+        _say(f"jgs any pattern {name} {precision} p={p}: |z - z_oracle|_1 = {err:.2e}")
+        assert err <= tol and abs(d - dr) <= tol
+        s.close()
+
+
+@pytest.mark.parametrize("name,make", [GENERAL[k] for k in (0, 3, 5)],
+                         ids=[GENERAL[k][0] for k in (0, 3, 5)])
+def test_any_pattern_bursts_follow_the_oracle(name, make):
+    """Bursts: the iterate and the changes follow the oracle's recurrence,
+    and one burst equals bursts of one sweep bit for bit (the flush's
+    change kernel has the sweep's geometry)."""
+    g = make()
+    sysg = _gen_system(g)
+    x = _gen_start(g, 5)
+    p = min(3, g.L)
+    s = _gen_solver(g, p, poison=True)
+    s.load(x)
+    diffs = s.sweeps(6, with_diffs=True)
+    z6 = s.store()
+    xr, want = x, []
+    for _ in range(6):
+        xr, dr = staircase.jgs_sweep(sysg, xr, _chunks(g.L, p))
+        want.append(dr)
+    assert np.abs(z6 - xr).sum() <= 1e-13
+    assert np.abs(np.asarray(diffs) - np.asarray(want[:-1])).max() <= 1e-13
+    s.load(x)
+    for _ in range(6):
+        s.sweeps(1)
+    assert np.array_equal(s.store(), z6)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("p", [1, 4])
+def test_any_pattern_converged_solve_reaches_gth(p, precision):
+    g = synth.localized(12, 8, 9, up=3, down=2, jumps=2, ragged=True)
+    ref = gth.gth(g.to_scipy().toarray())
+    s = _gen_solver(g, p, precision=precision, check_every=7, switch_tol=1e-6)
+    pi, info = s.solve(tol=1e-13, maxit=100000, allow_maxit=False)
+    err = np.abs(pi - ref).sum()
+    _say(f"jgs any pattern p={p} {precision}: sweeps {info['iters']} "
+         f"(fp32 {info['iters_fp32']}), err {err:.2e}")
+    assert err <= 1e-10
+    if precision == "mixed":
+        assert 0 < info["iters_fp32"] < info["iters"]
+    s.close()
+
+
+def test_any_pattern_mutex_closed_form():
+    """The mutual-exclusion model (the paper's fourth matrix, N = 4017 here)
+    in levels of 256 by block Gauss-Seidel and by JGS over 8 chunks: both
+    reach the closed-form stationary vector."""
+    g = synth.mutual_exclusion(12, 9, 25, m=256)
+    exact = synth.mutual_exclusion_pi(g)
+    for p in (1, 8):
+        s = _gen_solver(g, p, check_every=50)
+        pi, info = s.solve(tol=1e-13, maxit=100000, allow_maxit=False)
+        err = np.abs(pi - exact).sum()
+        _say(f"jgs mutex m256 p={p}: sweeps {info['iters']}, err {err:.2e}")
+        assert err <= 1e-10
+        s.close()
+
+
+def test_any_pattern_jgs_rejects_large_blocks():
+    from paper_2302_07551_amd import stc
+    g = synth.localized(3, 512, 26, up=1, down=1, jumps=0, density=0.01)
+    with pytest.raises(stc.StcError) as e:
+        _gen_solver(g, 2)
+    assert e.value.status == stc.STC_EINVAL
