@@ -61,6 +61,10 @@ Other workloads (each prints its own JSON line instead):
                   block Gauss-Seidel, JGS (Algorithm 1) and block Jacobi on the
                   4096 x 64 QBD and the banded generator, and their time to
                   ||Q^T pi||_1 <= 1e-12 on a 1024 x 64 QBD
+  --section3      section 3's comparison at the paper's partitions: STAIR1,
+                  STAIR2 and JGS over 1, 4, 12 and 24 chunks on the four test
+                  matrices (levels of 512, 2048, 2048 and 256), to a change of
+                  1e-9 or 10^4 sweeps (--only NAME,... picks matrices)
   --batch-rates   the batched kernel's GB/s per block size (8, 16, 32, 64; about
                   1 GB per sweep; FP32 and FP64) and on 60 served requests,
                   with the untuned launch shape and after stc_batch_autotune
@@ -225,6 +229,7 @@ def main():
     ap.add_argument("--launch-sizes", action="store_true")
     ap.add_argument("--batch-rates", action="store_true")
     ap.add_argument("--jgs", action="store_true")
+    ap.add_argument("--section3", action="store_true")
     ap.add_argument("--large-blocks", action="store_true")
     ap.add_argument("--only", type=str, default="")
     ap.add_argument("--large-probe", action="store_true")
@@ -282,6 +287,8 @@ def main():
         return batch_probe()
     if args.jgs:
         return jgs_mode(args)
+    if args.section3:
+        return section3_mode(args)
 
     return headline_mode(args)
 
@@ -1522,6 +1529,84 @@ def jgs_mode(args):
                       "speedup_stair1_vs_bgs": round(tr["jgs1"]["seconds"] /
                                                      tr["stair1"]["seconds"], 2),
                       **out}), flush=True)
+
+
+SECTION3_METHODS = ("stair1", "stair2", "jgs1", "jgs4", "jgs12", "jgs24")
+
+
+def section3_workloads(seed):
+    """The four test matrices of section 3 at the paper's partitions: the
+    block Hessenberg chain (N = 110400, levels of 512), the symmetric chain
+    of bandwidth 1135 (N = 91881, 2048), the chain of bandwidths 2370 / 1585
+    (N = 79220, 2048) and the mutual-exclusion model (N = 64839, 256); the
+    first three are shape stand-ins (see the large-partition workloads)."""
+    import synth
+    return (("uhess_N110400_m512", lambda: synth.upper_hessenberg(110400, 138, seed, m=512),
+             None),
+            ("ncd_N91881_bw1135_m2048",
+             lambda: synth.banded_random(91881, 1135, 1135, seed, symmetric=True, m=2048),
+             "uniform"),
+            ("prio_N79220_m2048", lambda: synth.banded_random(79220, 2370, 1585, seed, m=2048),
+             None),
+            ("mutex_n16_r12_m256", lambda: synth.mutual_exclusion(16, 12, seed, m=256), "mutex"))
+
+
+def section3_mode(args):
+    """Section 3's comparison on one GPU: STAIR1 and STAIR2 (Algorithm 2) and
+    JGS (Algorithm 1) over p = 1, 4, 12 and 24 chunks (the paper's thread
+    counts; p = 1 is block Gauss-Seidel) on the four test matrices at the
+    paper's partitions, with the paper's stopping rule (a change
+    ||x_k - x_k+1||_1 <= 1e-9, or 10^4 sweeps), FP64, from a seeded positive
+    start.  Per method: sweeps, seconds, whether it stopped on the change, the
+    last change, the residual and the error against the closed form where
+    there is one."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2302_07551_amd import Solver, stc
+    torch.cuda.set_device(0)
+    seed = synth.config_seed(3)
+    only = set(filter(None, args.only.split(",")))
+    out = {}
+    for name, build, closed in section3_workloads(seed):
+        if only and name not in only:
+            continue
+        gen = build()
+        exact = (synth.mutual_exclusion_pi(gen) if closed == "mutex"
+                 else np.full(gen.N, 1.0 / gen.N) if closed == "uniform" else None)
+        x0 = np.random.default_rng(seed).uniform(0.5, 1.5, gen.N)
+        x0 /= x0.sum()
+        rec = {"N": gen.N, "L": gen.L, "m": gen.m}
+        for meth in SECTION3_METHODS:
+            kw = ({"stair_type": int(meth[5:])} if meth.startswith("stair")
+                  else {"method": "jgs", "jgs_chunks": int(meth[3:])})
+            s = Solver(None, gen.sizes, stc.STC_ANY_PATTERN, csr=gen.csr, format="sparse",
+                       check_every=10, **kw)
+            stc.stc_autotune(s.h, 2)
+            s.load(x0)
+            s.sweeps(3)   # first launches of this handle's kernels
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pi, info = s.solve(x0, tol=1e-9, maxit=10_000)
+            dt = time.perf_counter() - t0
+            s.close()
+            rec[meth] = {"sweeps": info["iters"], "seconds": round(dt, 4),
+                         "ms_per_sweep": round(1e3 * dt / max(1, info["iters"]), 4),
+                         "converged": info["status"] == 0, "change": info["diff_1"],
+                         "residual_1": info["residual_1"],
+                         "err_vs_closed_form": (None if exact is None
+                                                else float(np.abs(pi - exact).sum()))}
+            print(f"# {name} {meth}: {rec[meth]}", file=sys.stderr, flush=True)
+        out[name] = rec
+    first = next(iter(out.values()), None)
+    print(json.dumps({"metric": "sweeps and time to a change of 1e-9 (section 3's stopping "
+                                "rule): STAIR1 / STAIR2 against JGS over 1 to 24 chunks",
+                      "value": first["stair1"]["seconds"] if first else None, "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": "section 3 matrices at the paper's partitions",
+                                 "first": next(iter(out), None), "seed": seed},
+                      "workloads": out}), flush=True)
 
 
 def observed_contraction(d, lo=1e-13, hi=1e-6):

@@ -138,9 +138,14 @@ __global__ __launch_bounds__(kWG) void k_gather_big(SweepLaunch a, const GenEntr
 // slice's 16-byte column group c (W_i is stored gather-oriented: row `row`
 // holds the weights of r_i[row] in every output column); the R row groups
 // are added in order in LDS.
-// Phase B with a.fold: workgroup 0 reduces and records sweep s - 1 first.
-template <typename T, int MP, bool PHB, bool NT>
-__global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf) {
+// A phase of Algorithm 2 (JGS = false): workgroup q takes level
+// parity + 2 (q / (MP / 64)) and slice q % (MP / 64), slot slot0 + q; phase
+// B with a.fold: workgroup 0 reduces and records sweep s - 1 first.
+// A step of Algorithm 1 (JGS = true, below): level jgs_first(c) + t of chunk
+// c = q / (MP / 64), slot i (MP / 64) + slice; a.fold on the first step.
+template <typename T, int MP, bool PHB, bool NT, bool JGS>
+__global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf, int chunks,
+                                                    int t) {
     using VT = typename Vec16<T>::type;
     constexpr int VEC = BigTile<T>::VEC, CS = BigTile<T>::CS, S = MP / CS;
     constexpr int TPR = BigTile<T>::TPR, R = BigTile<T>::R;
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     __shared__ T red[R * CS];
     __shared__ double sh[4 * kWG / 64];
     int q = blockIdx.x;
-    if (PHB && a.fold) {
+    if ((PHB || JGS) && a.fold) {
         if (q == 0) {
             fold_previous(a, sh);
             return;
@@ -159,8 +164,19 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
         --q;
     }
     const int tid = threadIdx.x;
-    const int lev = q / S, sl = q - lev * S;
-    const int i = a.parity + 2 * lev;
+    int i, sl, slot;
+    if constexpr (JGS) {
+        const int cq = q / S;
+        sl = q - cq * S;
+        i = jgs_first(cq, a.L, chunks) + t;
+        if (i >= jgs_first(cq + 1, a.L, chunks)) return;   // the chunk has no level here
+        slot = i * S + sl;
+    } else {
+        const int lev = q / S;
+        sl = q - lev * S;
+        i = a.parity + 2 * lev;
+        slot = a.slot0 + q;
+    }
     const int c = tid % TPR, g = tid / TPR;
     const int j0 = sl * CS;
     const T *wb = (const T *)a.blk + (size_t)i * MP * MP + tile_off<MP>(0, sl) + c * VEC;
@@ -214,17 +230,97 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf)
     double Ssum = zs, D = dd;
     block_sum2(Ssum, D, sh);
     if (live && tid == 0) {
-        a.part_sum[a.slot0 + q] = Ssum;
-        a.part_diff[a.slot0 + q] = D;
+        a.part_sum[slot] = Ssum;
+        a.part_diff[slot] = D;
+    }
+}
+
+// Algorithm 1 (JGS) on the large blocks: a sweep is ceil(L / chunks) steps,
+// step t taking level jgs_first(c) + t of every chunk c that has one (block
+// Gauss-Seidel inside a chunk needs its levels in order; block Jacobi across
+// the chunks lets a step take one level of each).  Per step a gather launch
+// and an apply launch, as for a phase of Algorithm 2.  A source is fresh
+// (this sweep's W_s) when its level is one of the chunk's earlier levels,
+// which earlier steps wrote, and the previous iterate, scaled by kappa,
+// otherwise; fresh and old terms are summed apart, each in quad order.
+// Level i's slice sl records its partials in slot i (MP / 64) + sl, the
+// order of k_diff_big with lstep = 1.
+template <typename T, int MP, bool NT>
+__global__ __launch_bounds__(kWG) void k_gather_big_jgs(SweepLaunch a, int chunks, int t,
+                                                         const GenEntry *tab, const T *val,
+                                                         const int *idx, T *rbuf) {
+    constexpr int SL = MP / kGatherCols;
+    __shared__ T red[kGatherLanes * kGatherCols];
+    const int tid = threadIdx.x;
+    const int q = blockIdx.x;
+    const int cq = q / SL, sl = q - cq * SL;
+    const int k0 = jgs_first(cq, a.L, chunks), k1 = jgs_first(cq + 1, a.L, chunks);
+    const int i = k0 + t;
+    if (i >= k1) return;   // the chunk has no level at this step
+    const int jl = tid % kGatherCols, gg = tid / kGatherCols;
+    const int j = sl * kGatherCols + jl;
+    const GenEntry te = tab[i];
+    const int Kq = (te.Kn + te.Kf) >> 2;
+    const T *w_old = (const T *)a.w_old;
+    const T *w_new = (const T *)a.w_new;
+    const double kappa = a.st->inv_sigma[(a.s - 2) & kRingMask];
+    using VT = typename Vec16<T>::type;
+    constexpr int U = sizeof(T) == 8 ? 2 : 4;
+    // fresh sources: indices k0 MP .. i MP - 1 of the padded iterate
+    const unsigned lo = (unsigned)k0 * MP, span = (unsigned)(i - k0) * MP;
+    T accF = 0, accO = 0;
+    for (int kq0 = gg; kq0 < Kq; kq0 += kGatherLanes * U) {
+        Int4 r4[U];
+        T v[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kq = kq0 + u * kGatherLanes;
+            if (kq < Kq) {
+                const size_t o = (size_t)te.off + ((size_t)kq * MP + j) * 4;
+                r4[u] = stream_load<Int4, NT>((const Int4 *)(idx + o));
+                if constexpr (sizeof(T) == 8) {
+                    const VT v01 = stream_load<VT, NT>((const VT *)(val + o));
+                    const VT v23 = stream_load<VT, NT>((const VT *)(val + o + 2));
+                    v[u][0] = v01[0], v[u][1] = v01[1], v[u][2] = v23[0], v[u][3] = v23[1];
+                } else {
+                    const VT v4 = stream_load<VT, NT>((const VT *)(val + o));
+                    v[u][0] = v4[0], v[u][1] = v4[1], v[u][2] = v4[2], v[u][3] = v4[3];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int kq = kq0 + u * kGatherLanes;
+            if (kq < Kq) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int si = r4[u][e];
+                    if ((unsigned)si - lo < span)
+                        accF += v[u][e] * w_new[si];
+                    else
+                        accO += v[u][e] * w_old[si];
+                }
+            }
+        }
+    }
+    red[gg * kGatherCols + jl] = accF + (T)kappa * accO;
+    __syncthreads();
+    if (tid < kGatherCols) {
+        T r = 0;
+#pragma unroll
+        for (int x = 0; x < kGatherLanes; ++x) r += red[x * kGatherCols + tid];
+        rbuf[(size_t)i * MP + j] = r;
     }
 }
 
 // The change of sweep k per (level, slice), in the apply kernel's geometry
 // and order (the flush's partials equal the next sweep's bit for bit).
+// lstep = 2: the stair phases' order (phase A's levels, then phase B's);
+// lstep = 1: every level in order, Algorithm 1's slots.
 template <typename T, int MP>
 __global__ __launch_bounds__(kWG) void k_diff_big(const T *w, const T *wp, const DevState *st,
                                                    long long k, int parity_a, int groups_a,
-                                                   double *part) {
+                                                   int lstep, double *part) {
     constexpr int CS = BigTile<T>::CS, S = MP / CS;
     __shared__ double sh[4 * kWG / 64];
     const int tid = threadIdx.x;
@@ -232,7 +328,7 @@ __global__ __launch_bounds__(kWG) void k_diff_big(const T *w, const T *wp, const
     const int q = in_a ? blockIdx.x : blockIdx.x - groups_a;
     const int parity = in_a ? parity_a : 1 - parity_a;
     const int lev = q / S, sl = q - lev * S;
-    const int i = parity + 2 * lev;
+    const int i = parity + lstep * lev;
     double dd = 0.0;
     if (tid < CS) {
         const double i2 = st->inv_sigma[k & kRingMask];
@@ -535,11 +631,12 @@ hipError_t phase_big(bool phase_b, const SweepLaunch &a, const GenEntry *tab, co
     if (phase_b) {
         launch_timed(k_gather_big<T, MP, true, NT>, gg, s, t0, a, tab, (const T *)val, idx,
                      (T *)rbuf);
-        launch_timed(k_apply_big<T, MP, true, NT>, ga, s, t1, a, (const T *)rbuf);
+        launch_timed(k_apply_big<T, MP, true, NT, false>, ga, s, t1, a, (const T *)rbuf, 0, 0);
     } else {
         launch_timed(k_gather_big<T, MP, false, NT>, gg, s, t0, a, tab, (const T *)val, idx,
                      (T *)rbuf);
-        launch_timed(k_apply_big<T, MP, false, NT>, ga, s, t1, a, (const T *)rbuf);
+        launch_timed(k_apply_big<T, MP, false, NT, false>, ga, s, t1, a, (const T *)rbuf, 0,
+                     0);
     }
     return hipGetLastError();
 }
@@ -557,22 +654,54 @@ hipError_t phase_big_t(int MP, bool phase_b, const SweepLaunch &a, const GenEntr
 }
 
 template <typename T, int MP>
-void diff_big(const void *w, const void *wp, int parity_a, int gA, int gB, const DevState *st,
-              long long k, double *part, hipStream_t s) {
+void diff_big(const void *w, const void *wp, int parity_a, int gA, int gB, int lstep,
+              const DevState *st, long long k, double *part, hipStream_t s) {
     hipLaunchKernelGGL((k_diff_big<T, MP>), dim3(gA + gB), dim3(kWG), 0, s, (const T *)w,
-                       (const T *)wp, st, k, parity_a, gA, part);
+                       (const T *)wp, st, k, parity_a, gA, lstep, part);
 }
 
 template <typename T>
 hipError_t diff_big_t(int MP, const void *w, const void *wp, int parity_a, int gA, int gB,
-                      const DevState *st, long long k, double *part, hipStream_t s) {
+                      int lstep, const DevState *st, long long k, double *part, hipStream_t s) {
     switch (MP) {
-        case 512: diff_big<T, 512>(w, wp, parity_a, gA, gB, st, k, part, s); break;
-        case 1024: diff_big<T, 1024>(w, wp, parity_a, gA, gB, st, k, part, s); break;
-        case 2048: diff_big<T, 2048>(w, wp, parity_a, gA, gB, st, k, part, s); break;
+        case 512: diff_big<T, 512>(w, wp, parity_a, gA, gB, lstep, st, k, part, s); break;
+        case 1024: diff_big<T, 1024>(w, wp, parity_a, gA, gB, lstep, st, k, part, s); break;
+        case 2048: diff_big<T, 2048>(w, wp, parity_a, gA, gB, lstep, st, k, part, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename T, int MP, bool NT>
+hipError_t jgs_big(int chunks, const SweepLaunch &a, const GenEntry *tab, const void *val,
+                   const int *idx, void *rbuf, hipStream_t s, LaunchTimer t) {
+    constexpr int SL = MP / kGatherCols, S = MP / BigTile<T>::CS;
+    const int steps = (a.L + chunks - 1) / chunks;
+    SweepLaunch b = a;
+    for (int step = 0; step < steps; ++step) {
+        // the sweep's launches are timed as one span
+        const LaunchTimer t0{step == 0 ? t.start : nullptr, nullptr};
+        const LaunchTimer t1{nullptr, step == steps - 1 ? t.stop : nullptr};
+        b.fold = step == 0 ? a.fold : 0;
+        launch_timed(k_gather_big_jgs<T, MP, NT>, chunks * SL, s, t0, b, chunks, step, tab,
+                     (const T *)val, idx, (T *)rbuf);
+        launch_timed(k_apply_big<T, MP, false, NT, true>, chunks * S + (b.fold ? 1 : 0), s, t1,
+                     b, (const T *)rbuf, chunks, step);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename T, bool NT>
+hipError_t jgs_big_t(int MP, int chunks, const SweepLaunch &a, const GenEntry *tab,
+                     const void *val, const int *idx, void *rbuf, hipStream_t s, LaunchTimer t) {
+    switch (MP) {
+        case 512: return jgs_big<T, 512, NT>(chunks, a, tab, val, idx, rbuf, s, t);
+        case 1024: return jgs_big<T, 1024, NT>(chunks, a, tab, val, idx, rbuf, s, t);
+        case 2048: return jgs_big<T, 2048, NT>(chunks, a, tab, val, idx, rbuf, s, t);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int MP>
@@ -613,8 +742,28 @@ hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, 
                                     int parity_a, int gA, int gB, const DevState *st, long long k,
                                     double *part, hipStream_t stream) {
     return precision_bytes == 8
-               ? diff_big_t<double>(MP, w, w_prev, parity_a, gA, gB, st, k, part, stream)
-               : diff_big_t<float>(MP, w, w_prev, parity_a, gA, gB, st, k, part, stream);
+               ? diff_big_t<double>(MP, w, w_prev, parity_a, gA, gB, 2, st, k, part, stream)
+               : diff_big_t<float>(MP, w, w_prev, parity_a, gA, gB, 2, st, k, part, stream);
+}
+
+hipError_t launch_sweep_jgs_big(int precision_bytes, int MP, bool nt, int chunks,
+                                const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t) {
+    if (!rbuf || chunks < 1 || chunks > a.L) return hipErrorInvalidValue;
+    if (precision_bytes == 8)
+        return nt ? jgs_big_t<double, true>(MP, chunks, a, tab, val, idx, rbuf, stream, t)
+                  : jgs_big_t<double, false>(MP, chunks, a, tab, val, idx, rbuf, stream, t);
+    return nt ? jgs_big_t<float, true>(MP, chunks, a, tab, val, idx, rbuf, stream, t)
+              : jgs_big_t<float, false>(MP, chunks, a, tab, val, idx, rbuf, stream, t);
+}
+
+hipError_t launch_diff_big_levels(int precision_bytes, int MP, const void *w, const void *w_prev,
+                                  int L, const DevState *st, long long k, double *part,
+                                  hipStream_t stream) {
+    const int n = L * (MP / kSliceCols);
+    return precision_bytes == 8
+               ? diff_big_t<double>(MP, w, w_prev, 0, n, 0, 1, st, k, part, stream)
+               : diff_big_t<float>(MP, w, w_prev, 0, n, 0, 1, st, k, part, stream);
 }
 
 hipError_t launch_residual_big_partials(int precision_bytes, int MP, int groups,

@@ -69,6 +69,12 @@ struct Tile {
     static constexpr int PF = RPT < 8 ? RPT : 8;   // W_i rows prefetched per thread
 };
 
+// Algorithm 1's chunks: chunk q of `chunks` holds the levels
+// jgs_first(q) .. jgs_first(q + 1) - 1.
+__device__ inline int jgs_first(int q, int L, int chunks) {
+    return (int)((long long)q * L / chunks);
+}
+
 // Launch variants: see kVariants in stc_internal.h.
 
 template <typename VT, bool NT>

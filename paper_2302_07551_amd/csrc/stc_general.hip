@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_jgs_gen(SweepLaunch a, int chunks
     const bool worker = team == 0;
     const bool live = st->stop_flag == 0;
     const T sc = (T)st->inv_sigma[(a.s - 2) & kRingMask];
-    const int k0 = (int)((long long)q * a.L / chunks), k1 = (int)((long long)(q + 1) * a.L / chunks);
+    const int k0 = jgs_first(q, a.L, chunks), k1 = jgs_first(q + 1, a.L, chunks);
     const T *w_old = (const T *)a.w_old, *w_d1 = (const T *)a.w_d1, *w_d2 = (const T *)a.w_d2;
     T *w_new = (T *)a.w_new;
     double i2 = 0.0, i3 = 0.0;

@@ -304,6 +304,16 @@ hipError_t launch_sweep_phase_big(int precision_bytes, int MP, bool phase_b, boo
 hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, const void *w_prev,
                                     int parity_a, int gA, int gB, const DevState *st, long long k,
                                     double *part, hipStream_t stream);
+// One sweep of Algorithm 1 on the large blocks: ceil(L / chunks) steps of a
+// gather and an apply launch, step t taking the t-th level of every chunk
+// (a.fold on the first step's apply); partials in slot i (MP / 64) + slice.
+hipError_t launch_sweep_jgs_big(int precision_bytes, int MP, bool nt, int chunks,
+                                const SweepLaunch &a, const GenEntry *tab, const void *val,
+                                const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t);
+// The change of sweep k in those slots (L (MP / 64) partials, levels in order).
+hipError_t launch_diff_big_levels(int precision_bytes, int MP, const void *w, const void *w_prev,
+                                  int L, const DevState *st, long long k, double *part,
+                                  hipStream_t stream);
 // W_i = (-Q_ii)^{-1} for the large blocks (blocked Gauss-Jordan over many
 // workgroups per level), in place in blk (one MP x MP block per level), with
 // scratch of big_invert_scratch_bytes(MP, L) bytes; singular levels are
@@ -325,7 +335,8 @@ hipError_t launch_sweep_jgs(int precision_bytes, int MP, int b, bool nt, int chu
                             const SweepLaunch &a, hipStream_t stream, LaunchTimer t);
 // The same for a generator of any block pattern (stc_general.hip), padded
 // blocks up to 256, from its per-level ELL; its partials follow the dense
-// kernel's geometry, so launch_diff_jgs serves both.
+// kernel's geometry, so launch_diff_jgs serves both (larger blocks:
+// launch_sweep_jgs_big).
 hipError_t launch_sweep_jgs_gen(int precision_bytes, int MP, bool nt, int chunks,
                                 const SweepLaunch &a, const GenEntry *tab, const void *val,
                                 const int *idx, hipStream_t stream, LaunchTimer t);

@@ -15,10 +15,6 @@
 
 namespace stc {
 
-__device__ inline int jgs_first(int q, int L, int chunks) {
-    return (int)((long long)q * L / chunks);
-}
-
 template <typename T, int MP, int B, bool NT>
 __global__ __launch_bounds__(kWG) void k_sweep_jgs(SweepLaunch a, int chunks) {
     using TL = Tile<T, MP, 8>;

@@ -439,10 +439,15 @@ hipError_t launch_diff(int precision_bytes, int MP, int variant, const void *w,
 hipError_t launch_diff_jgs(int precision_bytes, int MP, const void *w, const void *w_prev, int L,
                            int chunks, DevState *st, long long k, double *part,
                            hipStream_t stream, double tol) {
-    hipError_t e = launch_diff_jgs_partials(precision_bytes, MP, w, w_prev, L, chunks, st, k, part,
-                                            stream);
+    // the large blocks' sweep records one partial per (level, slice)
+    const bool big = MP > kMaxSmallMP;
+    hipError_t e = big ? launch_diff_big_levels(precision_bytes, MP, w, w_prev, L, st, k, part,
+                                                stream)
+                       : launch_diff_jgs_partials(precision_bytes, MP, w, w_prev, L, chunks, st, k,
+                                                  part, stream);
     if (e != hipSuccess) return e;
-    return reduce(part, chunks, kReduceDiff, st, k, stream, tol);
+    return reduce(part, big ? L * big_slices(precision_bytes, MP) : chunks, kReduceDiff, st, k,
+                  stream, tol);
 }
 
 template <typename T, int B>

@@ -342,10 +342,10 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (general && (long long)g->L * MP >= (1ll << 31)) { *why = 12; return false; }
     if (o->krylov_restart < 0 || o->krylov_restart > kMaxRestart) { *why = 13; return false; }
     if (o->method != STC_STAIRCASE && o->method != STC_JGS) { *why = 15; return false; }
-    // Algorithm 1: dense band storage, or any block pattern in blocks up to 256
+    // Algorithm 1: dense band storage, or any block pattern
     if (o->method == STC_JGS &&
-        ((general ? MP > kMaxSmallMP : o->format != STC_DENSE) || o->krylov_restart != 0 ||
-         o->jgs_chunks < 1 || o->jgs_chunks > g->L)) { *why = 16; return false; }
+        ((!general && o->format != STC_DENSE) || o->krylov_restart != 0 || o->jgs_chunks < 1 ||
+         o->jgs_chunks > g->L)) { *why = 16; return false; }
     Layout l;
     l.MP = MP;
     l.NB = general ? 1 : 2 * g->b + 1;   // any pattern: only the diagonal slot is dense
@@ -482,8 +482,9 @@ void *wbuf(stc_handle *h, bool fp32, long long s) {
 }
 
 int sweep_slots(stc_handle *h) {
-    if (h->method == STC_JGS) return h->chunks;
     const bool f32 = h->stage32;
+    if (h->method == STC_JGS)   // per chunk; per (level, slice) on the large blocks
+        return h->MP > kMaxSmallMP ? h->L * big_slices(f32 ? 4 : 8, h->MP) : h->chunks;
     const int vv = h->sparse ? kEllGeometry : h->variant[f32 ? 1 : 0];
     const int bytes = f32 ? 4 : 8;
     const int pA = (h->stair_type == 1) ? 0 : 1;
@@ -505,9 +506,10 @@ struct SweepTimers {
     hipEvent_t fin0 = nullptr, fin1 = nullptr;
 };
 
-// One sweep of Algorithm 1 (STC_JGS): a single launch whose extra workgroup
-// records sweep s - 1, then a finalize launch if the chunks' partials are too
-// many to fold.
+// One sweep of Algorithm 1 (STC_JGS): a single launch (on the large blocks,
+// a gather and an apply launch per level of a chunk) whose extra workgroup
+// records sweep s - 1, then a finalize launch if the partials are too many
+// to fold.
 hipError_t enqueue_sweep_jgs(stc_handle *h, long long s, double tol, const SweepTimers *tm,
                              bool first) {
     const bool f32 = h->stage32;
@@ -525,24 +527,29 @@ hipError_t enqueue_sweep_jgs(stc_handle *h, long long s, double tol, const Sweep
     a.tol = tol;
     a.parity = 0;
     a.slot0 = 0;
-    a.nslots = h->chunks;
-    const bool fold_ok = h->chunks <= kFoldSlots;
+    const int nslots = sweep_slots(h);
+    a.nslots = nslots;
+    const bool fold_ok = nslots <= kFoldSlots;
     a.fold = (fold_ok && !first && s >= 2) ? 1 : 0;
-    a.prev_nslots = h->chunks;
+    a.prev_nslots = nslots;
     a.prev_sum = h->part_sum + ((s - 1) & 1) * h->lay.nparts;
     a.prev_diff = h->part_diff + ((s - 1) & 1) * h->lay.nparts;
     const bool nt = variant_nt(h->variant[f32 ? 1 : 0]);
-    hipError_t e =
-        h->general
-            ? launch_sweep_jgs_gen(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab,
-                                   f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64,
-                                   h->gen_idx, h->stream, tm ? tm->a : LaunchTimer())
-            : launch_sweep_jgs(f32 ? 4 : 8, h->MP, h->b, nt, h->chunks, a, h->stream,
-                               tm ? tm->a : LaunchTimer());
+    const void *gval = f32 ? (const void *)h->gen_v32 : (const void *)h->gen_v64;
+    const LaunchTimer t = tm ? tm->a : LaunchTimer();
+    hipError_t e;
+    if (h->general && h->MP > kMaxSmallMP)
+        e = launch_sweep_jgs_big(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab, gval,
+                                 h->gen_idx, h->rbuf, h->stream, t);
+    else if (h->general)
+        e = launch_sweep_jgs_gen(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab, gval,
+                                 h->gen_idx, h->stream, t);
+    else
+        e = launch_sweep_jgs(f32 ? 4 : 8, h->MP, h->b, nt, h->chunks, a, h->stream, t);
     if (!fold_ok) {
         if (e == hipSuccess && tm) e = hipEventRecord(tm->fin0, h->stream);
         if (e == hipSuccess)
-            e = launch_finalize_sweep(a.part_sum, a.part_diff, h->chunks, h->st, s, tol, h->stream);
+            e = launch_finalize_sweep(a.part_sum, a.part_diff, nslots, h->st, s, tol, h->stream);
         if (e == hipSuccess && tm) e = hipEventRecord(tm->fin1, h->stream);
     }
     return e;
@@ -1175,8 +1182,7 @@ stc_status plan_setup(const stc_generator *g, const stc_options *o, Layout *lay)
                                     "the sparse storage of the blocks exceeds 2^31 slots",
                                     "unknown method",
                                     "STC_JGS takes dense band storage or a pattern of any "
-                                    "shape in blocks up to 256, no Krylov workspace and "
-                                    "jgs_chunks in 1..L"};
+                                    "shape, no Krylov workspace and jgs_chunks in 1..L"};
         return fail(STC_EINVAL, "%s", msg[why < 17 ? why : 0]);
     }
     if (o->stair_type != 1 && o->stair_type != 2) return fail(STC_EINVAL, "stair_type must be 1 or 2");
