@@ -11,6 +11,10 @@ do not come from that code:
     of its states, which keeps the product form restricted to that subset
     (Kelly's truncation theorem for reversible chains).
 Planted mistakes (a far block dropped, far levels read fresh) must fail them.
+Algorithm 1 (JGS) on the same systems is pinned the same way: one sweep is
+the normalised M^{-1} N x of the JGS splitting, whose M is written in the
+test from the definition (block lower triangular inside each chunk), and the
+GTH vector is its fixed point for every chunking.
 """
 import numpy as np
 import pytest
@@ -125,6 +129,56 @@ def test_general_residual_is_the_matrix_product():
 
 
 # --- planted mistakes ------------------------------------------------------
+
+def _jgs_chunks(L, p):
+    return [(c * L // p, (c + 1) * L // p - c * L // p) for c in range(p)]
+
+
+@pytest.mark.parametrize("cfg", GENERAL, ids=lambda c: f"L{c['L']}_m{c['m']}_s{c['seed']}")
+def test_general_jgs_sweep_equals_dense_splitting(cfg):
+    """Algorithm 1 on a SparseBlockSystem (the oracle of the GPU's
+    any-pattern JGS): one sweep equals the normalised M^{-1} N x of the JGS
+    splitting, with M written here from the method's definition: the blocks
+    A_{i,k} with k <= i and i, k in one chunk (block lower triangular inside
+    each chunk, nothing across).  At p = 1 that is block Gauss-Seidel's M and
+    at p = L block Jacobi's, which the oracle's own splittings also give."""
+    g = synth.localized(**cfg)
+    A = g.to_scipy().T.toarray()
+    lev = np.repeat(np.arange(g.L), g.sizes)
+    sysg = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    x = _start(g.N, 11)
+    for p in sorted({1, min(3, g.L), g.L}):
+        chunks = _jgs_chunks(g.L, p)
+        chunk_of = np.repeat(np.arange(p), [c for _, c in chunks])[lev]
+        M = np.where((chunk_of[:, None] == chunk_of[None, :]) & (lev[:, None] >= lev[None, :]),
+                     A, 0.0)
+        assert np.array_equal(M, splittings.splitting_M(A, g.sizes, "jgs", chunks))
+        if p == 1:
+            assert np.array_equal(M, splittings.splitting_M(A, g.sizes, "gs"))
+        if p == g.L:
+            assert np.array_equal(M, splittings.splitting_M(A, g.sizes, "jacobi"))
+        want = np.linalg.solve(M, (M - A) @ x)
+        want /= want.sum()
+        z, err = staircase.jgs_sweep(sysg, x, chunks)
+        assert np.abs(z - want).sum() < 1e-13, p
+        assert abs(err - np.abs(want - x).sum()) < 1e-13
+
+
+def test_general_jgs_fixed_point_and_fresh_reads():
+    """The GTH vector is a fixed point of every JGS sweep, and the chunks
+    matter: on a generator with far jumps, p = 1 and p = L give different
+    iterates from the same start (fresh against previous-iterate reads)."""
+    g = synth.localized(12, 6, 1, up=2, down=2, jumps=3, ragged=True)
+    pi = gth.gth(g.to_scipy().toarray())
+    sysg = staircase.SparseBlockSystem(g.to_scipy(), g.sizes)
+    for p in (1, 4, 12):
+        z, err = staircase.jgs_sweep(sysg, pi, _jgs_chunks(g.L, p))
+        assert err < 1e-13 and np.abs(z - pi).sum() < 1e-13
+    x = _start(g.N, 3)
+    z1, _ = staircase.jgs_sweep(sysg, x, _jgs_chunks(g.L, 1))
+    zL, _ = staircase.jgs_sweep(sysg, x, _jgs_chunks(g.L, g.L))
+    assert np.abs(z1 - zL).sum() > 1e-3
+
 
 def test_dropped_far_block_is_caught(monkeypatch):
     g = synth.localized(12, 6, 1, up=2, down=2, jumps=3, ragged=True)
