@@ -28,6 +28,8 @@ constexpr int kGatherCols = 64;             // columns per gather workgroup
 constexpr int kGatherLanes = kWG / kGatherCols;   // lanes per column
 constexpr int kTileDim = 64;                // tiles of the stored inverses
 constexpr int kSliceCols = kTileDim;        // columns per apply workgroup
+constexpr int kJgsSplit = 8;                // row ranges of a split Algorithm 1 apply
+constexpr int kJgsSplitBelow = 128;         // split steps with fewer (level, slice) groups
 
 // The inverses W_i of these blocks are stored tile-major: tile (ib, jb)
 // (64 x 64, row-major inside) of a level sits at element offset
@@ -143,13 +145,16 @@ __global__ __launch_bounds__(kWG) void k_gather_big(SweepLaunch a, const GenEntr
 // B with a.fold: workgroup 0 reduces and records sweep s - 1 first.
 // A step of Algorithm 1 (JGS = true, below): level jgs_first(c) + t of chunk
 // c = q / (MP / 64), slot i (MP / 64) + slice; a.fold on the first step.
-template <typename T, int MP, bool PHB, bool NT, bool JGS>
+// With RS > 1 (Algorithm 1 steps with few levels) workgroup q takes row
+// range q % RS of (chunk, slice) q / RS, MP / RS rows, and writes its part
+// of z_i to zpart (RS vectors of L MP); k_combine_big_jgs adds the parts.
+template <typename T, int MP, bool PHB, bool NT, bool JGS, int RS>
 __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf, int chunks,
-                                                    int t) {
+                                                    int t, T *zpart) {
     using VT = typename Vec16<T>::type;
     constexpr int VEC = BigTile<T>::VEC, CS = BigTile<T>::CS, S = MP / CS;
     constexpr int TPR = BigTile<T>::TPR, R = BigTile<T>::R;
-    constexpr int RPT = MP / R;   // rows per thread
+    constexpr int RPT = MP / R / RS;   // rows per thread
     constexpr int PW = 8;         // rows per batch; two batches in flight
     static_assert(RPT % PW == 0, "rows per thread in whole batches");
     __shared__ T rv[MP];
@@ -164,10 +169,12 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf,
         --q;
     }
     const int tid = threadIdx.x;
-    int i, sl, slot;
+    int i, sl, slot, rb = 0;
     if constexpr (JGS) {
-        const int cq = q / S;
-        sl = q - cq * S;
+        const int cs = q / RS;
+        rb = (q - cs * RS) * (MP / RS);   // first row of the range
+        const int cq = cs / S;
+        sl = cs - cq * S;
         i = jgs_first(cq, a.L, chunks) + t;
         if (i >= jgs_first(cq + 1, a.L, chunks)) return;   // the chunk has no level here
         slot = i * S + sl;
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf,
     VT cur[PW];
 #pragma unroll
     for (int u = 0; u < PW; ++u)
-        cur[u] = stream_load<VT, NT>((const VT *)(wb + slice_row_off<MP>(g + R * u)));
+        cur[u] = stream_load<VT, NT>((const VT *)(wb + slice_row_off<MP>(rb + g + R * u)));
     const T *r = rbuf + (size_t)i * MP;
 #pragma unroll
     for (int u = 0; u < MP / kWG; ++u) rv[tid + u * kWG] = r[tid + u * kWG];
@@ -199,17 +206,26 @@ __global__ __launch_bounds__(kWG) void k_apply_big(SweepLaunch a, const T *rbuf,
 #pragma unroll
         for (int u = 0; u < PW; ++u)
             nxt[u] = stream_load<VT, NT>(
-                (const VT *)(wb + slice_row_off<MP>(g + R * (q0 + PW + u))));
+                (const VT *)(wb + slice_row_off<MP>(rb + g + R * (q0 + PW + u))));
 #pragma unroll
-        for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + R * (q0 + u)];
+        for (int u = 0; u < PW; ++u) acc += cur[u] * rv[rb + g + R * (q0 + u)];
 #pragma unroll
         for (int u = 0; u < PW; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
-    for (int u = 0; u < PW; ++u) acc += cur[u] * rv[g + R * (q0 + u)];
+    for (int u = 0; u < PW; ++u) acc += cur[u] * rv[rb + g + R * (q0 + u)];
 #pragma unroll
     for (int e = 0; e < VEC; ++e) red[g * CS + c * VEC + e] = acc[e];
     __syncthreads();
+    if constexpr (RS > 1) {   // this row range's part of z_i
+        if (tid < CS) {
+            T z = 0;
+#pragma unroll
+            for (int x = 0; x < R; ++x) z += red[x * CS + tid];
+            zpart[(size_t)(rb / (MP / RS)) * a.L * MP + (size_t)i * MP + j0 + tid] = z;
+        }
+        return;
+    }
 
     const DevState *st = a.st;
     const bool live = st->stop_flag == 0;
@@ -310,6 +326,51 @@ __global__ __launch_bounds__(kWG) void k_gather_big_jgs(SweepLaunch a, int chunk
 #pragma unroll
         for (int x = 0; x < kGatherLanes; ++x) r += red[x * kGatherCols + tid];
         rbuf[(size_t)i * MP + j] = r;
+    }
+}
+
+// z_i of an Algorithm 1 step split over RS row ranges: the parts added in
+// range order, then the slice's partial sums as k_apply_big writes them
+// (slot i (MP / 64) + slice); with a.fold workgroup 0 first records sweep
+// s - 1.
+template <typename T, int MP, int RS>
+__global__ __launch_bounds__(kWG) void k_combine_big_jgs(SweepLaunch a, int chunks, int t,
+                                                          const T *zpart) {
+    constexpr int CS = BigTile<T>::CS, S = MP / CS;
+    __shared__ double sh[4 * kWG / 64];
+    int q = blockIdx.x;
+    if (a.fold) {
+        if (q == 0) {
+            fold_previous(a, sh);
+            return;
+        }
+        --q;
+    }
+    const int cq = q / S, sl = q - cq * S;
+    const int i = jgs_first(cq, a.L, chunks) + t;
+    if (i >= jgs_first(cq + 1, a.L, chunks)) return;
+    const int tid = threadIdx.x;
+    const DevState *st = a.st;
+    const bool live = st->stop_flag == 0;
+    double zs = 0.0, dd = 0.0;
+    if (live && tid < CS) {
+        const size_t e = (size_t)i * MP + sl * CS + tid;
+        T z = 0;
+#pragma unroll
+        for (int x = 0; x < RS; ++x) z += zpart[(size_t)x * a.L * MP + e];
+        ((T *)a.w_new)[e] = z;
+        zs = (double)z;
+        if (a.s >= 3) {
+            const double i2 = st->inv_sigma[(a.s - 2) & kRingMask];
+            const double i3 = st->inv_sigma[(a.s - 3) & kRingMask];
+            dd = fabs((double)((const T *)a.w_d1)[e] * i2 - (double)((const T *)a.w_d2)[e] * i3);
+        }
+    }
+    double Ssum = zs, D = dd;
+    block_sum2(Ssum, D, sh);
+    if (live && tid == 0) {
+        a.part_sum[i * S + sl] = Ssum;
+        a.part_diff[i * S + sl] = D;
     }
 }
 
@@ -631,12 +692,13 @@ hipError_t phase_big(bool phase_b, const SweepLaunch &a, const GenEntry *tab, co
     if (phase_b) {
         launch_timed(k_gather_big<T, MP, true, NT>, gg, s, t0, a, tab, (const T *)val, idx,
                      (T *)rbuf);
-        launch_timed(k_apply_big<T, MP, true, NT, false>, ga, s, t1, a, (const T *)rbuf, 0, 0);
+        launch_timed(k_apply_big<T, MP, true, NT, false, 1>, ga, s, t1, a, (const T *)rbuf, 0, 0,
+                     (T *)nullptr);
     } else {
         launch_timed(k_gather_big<T, MP, false, NT>, gg, s, t0, a, tab, (const T *)val, idx,
                      (T *)rbuf);
-        launch_timed(k_apply_big<T, MP, false, NT, false>, ga, s, t1, a, (const T *)rbuf, 0,
-                     0);
+        launch_timed(k_apply_big<T, MP, false, NT, false, 1>, ga, s, t1, a, (const T *)rbuf, 0,
+                     0, (T *)nullptr);
     }
     return hipGetLastError();
 }
@@ -672,11 +734,23 @@ hipError_t diff_big_t(int MP, const void *w, const void *wp, int parity_a, int g
     return hipGetLastError();
 }
 
+// Row ranges of a split Algorithm 1 apply: at most 8, each thread keeping
+// whole batches of rows (MP / (R RS) >= 8).
+template <typename T, int MP>
+constexpr int jgs_split() {
+    return MP / (BigTile<T>::R * 8) < kJgsSplit ? MP / (BigTile<T>::R * 8) : kJgsSplit;
+}
+
 template <typename T, int MP, bool NT>
 hipError_t jgs_big(int chunks, const SweepLaunch &a, const GenEntry *tab, const void *val,
-                   const int *idx, void *rbuf, hipStream_t s, LaunchTimer t) {
+                   const int *idx, void *rbuf, void *zpart, hipStream_t s, LaunchTimer t) {
     constexpr int SL = MP / kGatherCols, S = MP / BigTile<T>::CS;
+    constexpr int RS = jgs_split<T, MP>();
     const int steps = (a.L + chunks - 1) / chunks;
+    // few (level, slice) workgroups per step leave most CUs idle: split rows.
+    // Levels of 512 stream 256 KB per workgroup, too little to pay for the
+    // third launch (measured: 6 % faster at one chunk, 19 % slower at 12).
+    const bool split = MP >= 1024 && chunks * S < kJgsSplitBelow && zpart;
     SweepLaunch b = a;
     for (int step = 0; step < steps; ++step) {
         // the sweep's launches are timed as one span
@@ -685,8 +759,17 @@ hipError_t jgs_big(int chunks, const SweepLaunch &a, const GenEntry *tab, const 
         b.fold = step == 0 ? a.fold : 0;
         launch_timed(k_gather_big_jgs<T, MP, NT>, chunks * SL, s, t0, b, chunks, step, tab,
                      (const T *)val, idx, (T *)rbuf);
-        launch_timed(k_apply_big<T, MP, false, NT, true>, chunks * S + (b.fold ? 1 : 0), s, t1,
-                     b, (const T *)rbuf, chunks, step);
+        if (split) {
+            SweepLaunch c = b;
+            c.fold = 0;
+            launch_timed(k_apply_big<T, MP, false, NT, true, RS>, chunks * S * RS, s,
+                         LaunchTimer(), c, (const T *)rbuf, chunks, step, (T *)zpart);
+            launch_timed(k_combine_big_jgs<T, MP, RS>, chunks * S + (b.fold ? 1 : 0), s, t1, b,
+                         chunks, step, (const T *)zpart);
+        } else {
+            launch_timed(k_apply_big<T, MP, false, NT, true, 1>, chunks * S + (b.fold ? 1 : 0), s,
+                         t1, b, (const T *)rbuf, chunks, step, (T *)nullptr);
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -695,11 +778,12 @@ hipError_t jgs_big(int chunks, const SweepLaunch &a, const GenEntry *tab, const 
 
 template <typename T, bool NT>
 hipError_t jgs_big_t(int MP, int chunks, const SweepLaunch &a, const GenEntry *tab,
-                     const void *val, const int *idx, void *rbuf, hipStream_t s, LaunchTimer t) {
+                     const void *val, const int *idx, void *rbuf, void *zpart, hipStream_t s,
+                     LaunchTimer t) {
     switch (MP) {
-        case 512: return jgs_big<T, 512, NT>(chunks, a, tab, val, idx, rbuf, s, t);
-        case 1024: return jgs_big<T, 1024, NT>(chunks, a, tab, val, idx, rbuf, s, t);
-        case 2048: return jgs_big<T, 2048, NT>(chunks, a, tab, val, idx, rbuf, s, t);
+        case 512: return jgs_big<T, 512, NT>(chunks, a, tab, val, idx, rbuf, zpart, s, t);
+        case 1024: return jgs_big<T, 1024, NT>(chunks, a, tab, val, idx, rbuf, zpart, s, t);
+        case 2048: return jgs_big<T, 2048, NT>(chunks, a, tab, val, idx, rbuf, zpart, s, t);
     }
     return hipErrorInvalidValue;
 }
@@ -748,14 +832,18 @@ hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, 
 
 hipError_t launch_sweep_jgs_big(int precision_bytes, int MP, bool nt, int chunks,
                                 const SweepLaunch &a, const GenEntry *tab, const void *val,
-                                const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t) {
+                                const int *idx, void *rbuf, void *zpart, hipStream_t stream,
+                                LaunchTimer t) {
     if (!rbuf || chunks < 1 || chunks > a.L) return hipErrorInvalidValue;
     if (precision_bytes == 8)
-        return nt ? jgs_big_t<double, true>(MP, chunks, a, tab, val, idx, rbuf, stream, t)
-                  : jgs_big_t<double, false>(MP, chunks, a, tab, val, idx, rbuf, stream, t);
-    return nt ? jgs_big_t<float, true>(MP, chunks, a, tab, val, idx, rbuf, stream, t)
-              : jgs_big_t<float, false>(MP, chunks, a, tab, val, idx, rbuf, stream, t);
+        return nt ? jgs_big_t<double, true>(MP, chunks, a, tab, val, idx, rbuf, zpart, stream, t)
+                  : jgs_big_t<double, false>(MP, chunks, a, tab, val, idx, rbuf, zpart, stream,
+                                             t);
+    return nt ? jgs_big_t<float, true>(MP, chunks, a, tab, val, idx, rbuf, zpart, stream, t)
+              : jgs_big_t<float, false>(MP, chunks, a, tab, val, idx, rbuf, zpart, stream, t);
 }
+
+size_t jgs_big_split_bytes(int L, int MP) { return (size_t)kJgsSplit * L * MP * sizeof(double); }
 
 hipError_t launch_diff_big_levels(int precision_bytes, int MP, const void *w, const void *w_prev,
                                   int L, const DevState *st, long long k, double *part,

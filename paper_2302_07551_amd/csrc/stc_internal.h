@@ -307,9 +307,14 @@ hipError_t launch_diff_big_partials(int precision_bytes, int MP, const void *w, 
 // One sweep of Algorithm 1 on the large blocks: ceil(L / chunks) steps of a
 // gather and an apply launch, step t taking the t-th level of every chunk
 // (a.fold on the first step's apply); partials in slot i (MP / 64) + slice.
+// Steps with few (level, slice) groups split each apply over row ranges into
+// zpart (jgs_big_split_bytes(L, MP) bytes; null: never split) and add the
+// ranges in a third launch.
 hipError_t launch_sweep_jgs_big(int precision_bytes, int MP, bool nt, int chunks,
                                 const SweepLaunch &a, const GenEntry *tab, const void *val,
-                                const int *idx, void *rbuf, hipStream_t stream, LaunchTimer t);
+                                const int *idx, void *rbuf, void *zpart, hipStream_t stream,
+                                LaunchTimer t);
+size_t jgs_big_split_bytes(int L, int MP);
 // The change of sweep k in those slots (L (MP / 64) partials, levels in order).
 hipError_t launch_diff_big_levels(int precision_bytes, int MP, const void *w, const void *w_prev,
                                   int L, const DevState *st, long long k, double *part,

@@ -99,6 +99,7 @@ struct Layout {
     size_t part_sum = 0, part_diff = 0, part_aux = 0, off = 0, sizes = 0, state = 0, flow = 0;
     size_t rbuf = 0;            // large blocks: r_i of the gather launches (L x MP elements)
     size_t inv_scr = 0;         // large blocks: the inverse's panel scratch
+    size_t zpart = 0;           // large blocks, STC_JGS: row parts of a split apply
     size_t nparts = 0, naux = 0;
     size_t total = 0;
 };
@@ -388,6 +389,7 @@ bool plan(const stc_generator *g, const stc_options *o, Layout *lay, int *why) {
     if (MP > kMaxSmallMP) {
         l.rbuf = take(vec * 8);
         l.inv_scr = take(big_invert_scratch_bytes(MP, g->L));
+        if (o->method == STC_JGS) l.zpart = take(jgs_big_split_bytes(g->L, MP));
     }
     if (l.sparse && !general) {
         l.ell_tab = take(L * l.NB * sizeof(EllEntry));
@@ -455,6 +457,7 @@ struct stc_handle {
     float *gen_v32 = nullptr;
     int *gen_idx = nullptr;
     void *rbuf = nullptr;             // large blocks: the gather launches' r_i
+    void *zpart = nullptr;            // large blocks, STC_JGS: row parts of a split apply
     std::vector<GenEntry> gen_host;   // the table, for the byte counts
     // Krylov workspace (stc_solve_gmres)
     int kr = 0;
@@ -540,7 +543,7 @@ hipError_t enqueue_sweep_jgs(stc_handle *h, long long s, double tol, const Sweep
     hipError_t e;
     if (h->general && h->MP > kMaxSmallMP)
         e = launch_sweep_jgs_big(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab, gval,
-                                 h->gen_idx, h->rbuf, h->stream, t);
+                                 h->gen_idx, h->rbuf, h->zpart, h->stream, t);
     else if (h->general)
         e = launch_sweep_jgs_gen(f32 ? 4 : 8, h->MP, nt, h->chunks, a, h->gen_tab, gval,
                                  h->gen_idx, h->stream, t);
@@ -1434,6 +1437,7 @@ stc_status stc_setup(const stc_generator *g, const stc_options *o, stc_handle **
         h->gen_v32 = lay.fp32 ? (float *)(h->base + lay.gen_v32) : nullptr;
         h->gen_idx = (int *)(h->base + lay.gen_idx);
         h->rbuf = lay.rbuf ? (void *)(h->base + lay.rbuf) : nullptr;
+        h->zpart = lay.zpart ? (void *)(h->base + lay.zpart) : nullptr;
         if ((rc = pack_general(h, g)) != STC_OK) return cleanup(rc);
     } else {
     // validate, then pack in the sweep's layout, a chunk of levels at a time;

@@ -292,6 +292,7 @@ LARGE = [
     ("loc_L4_m1000_ragged", lambda: synth.localized(4, 1000, 18, up=1, down=2, jumps=1,
                                                     ragged=True, density=0.002)),
     ("mutex_n13_r8_m2048", lambda: synth.mutual_exclusion(13, 8, 20, m=2048)),
+    ("loc_L18_m512", lambda: synth.localized(18, 512, 27, up=1, down=1, jumps=1, density=0.004)),
 ]
 
 
@@ -299,7 +300,10 @@ LARGE = [
 @pytest.mark.parametrize("name,make", LARGE, ids=[s[0] for s in LARGE])
 def test_large_blocks_one_sweep_matches_the_oracle(name, make, precision):
     """Levels of 512 to 2048 states (a gather and a sliced apply launch per
-    level of a chunk): one sweep for p = 1, 2 and L against the oracle."""
+    level of a chunk): one sweep for p = 1, 2 and L against the oracle.  Steps
+    of levels of 1024 or more with under 128 (level, slice) groups split the
+    apply over row ranges and add them in a third launch (the 1000 and 2048
+    cases, except p = L = 4 at 2048); the 512 cases run unsplit."""
     g = make()
     sysg = _gen_system(g)
     x = _gen_start(g, 22)
@@ -316,11 +320,13 @@ def test_large_blocks_one_sweep_matches_the_oracle(name, make, precision):
 
 
 @pytest.mark.parametrize("p", [1, 3])
-def test_large_blocks_bursts_follow_the_oracle(p):
-    """Bursts on the large blocks: the iterate and the changes follow the
+@pytest.mark.parametrize("k", [0, 1])
+def test_large_blocks_bursts_follow_the_oracle(k, p):
+    """Bursts on the large blocks (512: one apply launch per step; 1000: the
+    row-split apply and its combine): the iterate and the changes follow the
     oracle, and one burst equals bursts of one sweep bit for bit (the flush's
     change kernel takes the apply's (level, slice) slots)."""
-    g = LARGE[0][1]()
+    g = LARGE[k][1]()
     sysg = _gen_system(g)
     x = _gen_start(g, 6)
     s = _gen_solver(g, p, poison=True)
