@@ -158,9 +158,12 @@ typedef struct {
                              normalisation and change.  jgs_chunks = 1 is
                              plain block Gauss-Seidel, jgs_chunks = L block
                              Jacobi.  Dense band storage, or STC_ANY_PATTERN
-                             with m up to 256 (each level's off-diagonal
+                             with m up to 2048 (each level's off-diagonal
                              entries read fresh or old by their source
-                             level); no banded sparse storage, no Krylov
+                             level; above 256 a sweep is ceil(L / p) steps
+                             of a few launches each, and the footprint adds
+                             8 L m FP64 of scratch); no banded sparse
+                             storage, no Krylov
                              workspace, not in batches; stair_type is
                              ignored; every other call works as for the
                              stair splitting.  */
