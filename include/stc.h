@@ -388,7 +388,8 @@ stc_status stc_promote(stc_handle *h);
  * chain table and work lists live at fixed device addresses, so the
  * hipGraph that stc_batch_sweeps captures stays valid when stc_batch_set
  * changes the membership (it is captured again when the set of precision
- * stages or block sizes present changes).  Per-chain results equal those of the same chain
+ * stages or block sizes present changes, or nsweeps does; the call then
+ * waits for the stream to drain before it releases the old graph).  Per-chain results equal those of the same chain
  * swept alone with launch variant 0 (same per-level arithmetic, same
  * fixed-order reductions). */
 typedef struct stc_batch stc_batch;

@@ -2415,7 +2415,11 @@ BatchLayout batch_layout(int max_chains, long long max_items) {
     return l;
 }
 
+// Release the captured graph.  Its last launch may still be queued or
+// running on the batch's stream (stc_batch_sweeps returns at once), so the
+// stream drains first.
 void drop_graph(stc_batch *bt) {
+    if (bt->exec) (void)hipStreamSynchronize(bt->stream);
     if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
     if (bt->graph) (void)hipGraphDestroy(bt->graph);
     bt->exec = nullptr;
