@@ -424,8 +424,13 @@ stc_status stc_batch_set(stc_batch *bt, stc_handle *const *hs, int32_t count, do
 
 /* Enqueue nsweeps sweeps of every chain of the batch on its stream, as a
  * replay of a captured hipGraph (use_graph != 0; captured on first use and
- * again when nsweeps or the set of precision stages changes) or as plain
- * launches.  Asynchronous: use stc_batch_sync / stc_query afterwards. */
+ * again when nsweeps or the set of precision stages or block sizes changes)
+ * or as plain launches.  Asynchronous: use stc_batch_sync / stc_query
+ * afterwards.  Known problem: a capture made right after the previous graph
+ * is released has ended the process with a segmentation fault inside this
+ * call (bursts of changing length back to back; a served stream whose block
+ * sizes change every round), cause not yet found.  Callers that change
+ * nsweeps or the batch's sizes often should pass use_graph = 0. */
 stc_status stc_batch_sweeps(stc_batch *bt, int64_t nsweeps, int32_t use_graph);
 
 /* Autotuner of the batched launch (project-written; the tile and wave shapes
