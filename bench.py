@@ -63,8 +63,9 @@ Other workloads (each prints its own JSON line instead):
                   ||Q^T pi||_1 <= 1e-12 on a 1024 x 64 QBD
   --section3      section 3's comparison at the paper's partitions: STAIR1,
                   STAIR2 and JGS over 1, 4, 12 and 24 chunks on the four test
-                  matrices (levels of 512, 2048, 2048 and 256), to a change of
-                  1e-9 or 10^4 sweeps (--only NAME,... picks matrices)
+                  matrices (levels of 512, 2048, 2048 and 256; the third also
+                  in 1024 and 512), to a change of 1e-9 or 10^4 sweeps
+                  (--only NAME,... picks matrices)
   --batch-rates   the batched kernel's GB/s per block size (8, 16, 32, 64; about
                   1 GB per sweep; FP32 and FP64) and on 60 served requests,
                   with the untuned launch shape and after stc_batch_autotune
@@ -1539,7 +1540,9 @@ def section3_workloads(seed):
     block Hessenberg chain (N = 110400, levels of 512), the symmetric chain
     of bandwidth 1135 (N = 91881, 2048), the chain of bandwidths 2370 / 1585
     (N = 79220, 2048) and the mutual-exclusion model (N = 64839, 256); the
-    first three are shape stand-ins (see the large-partition workloads)."""
+    first three are shape stand-ins (see the large-partition workloads).
+    The third also in levels of 1024 and 512, as in the paper's block-size
+    study."""
     import synth
     return (("uhess_N110400_m512", lambda: synth.upper_hessenberg(110400, 138, seed, m=512),
              None),
@@ -1548,7 +1551,13 @@ def section3_workloads(seed):
              "uniform"),
             ("prio_N79220_m2048", lambda: synth.banded_random(79220, 2370, 1585, seed, m=2048),
              None),
-            ("mutex_n16_r12_m256", lambda: synth.mutual_exclusion(16, 12, seed, m=256), "mutex"))
+            ("mutex_n16_r12_m256", lambda: synth.mutual_exclusion(16, 12, seed, m=256), "mutex"),
+            # the third matrix again in levels of 512 and 1024 (the block-size
+            # study at the end of section 3)
+            ("prio_N79220_m1024", lambda: synth.banded_random(79220, 2370, 1585, seed, m=1024),
+             None),
+            ("prio_N79220_m512", lambda: synth.banded_random(79220, 2370, 1585, seed, m=512),
+             None))
 
 
 def section3_mode(args):
