@@ -422,3 +422,34 @@ def test_large_blocks_only_for_any_pattern(lib):
         assert fp_big >= 2 * 3 * mp * mp * 8, m_big
     gen.m = 2049
     assert stc.stc_footprint_bytes(gen, opt) == 0
+
+
+def test_jgs_footprints_on_any_pattern(lib):
+    """Algorithm 1 takes generators of any block pattern at every block size
+    up to 2048.  Up to 256 it needs nothing beyond the stair splitting's
+    footprint; on the large blocks it adds the split apply's row-range parts,
+    8 vectors of L MP FP64 (within the arena's alignment).  jgs_chunks must lie
+    in 1..L, and no Krylov workspace is taken."""
+    import scipy.sparse as sp
+    N = 600
+    Q = sp.random(N, N, density=0.01, random_state=4, format="csr")
+    Q.setdiag(0.0)
+    Q.setdiag(-np.asarray(Q.sum(axis=1)).ravel())
+    Q = Q.tocsr()
+    Q.sort_indices()
+    sizes = np.array([256, 256, 88], dtype=np.int32)
+    gen, keep = stc.make_generator_csr(Q.indptr, Q.indices, Q.data, sizes, stc.STC_ANY_PATTERN, 256,
+                                       False)
+    stair = stc.make_options("fp64", format="sparse")
+    jgs = stc.make_options("fp64", format="sparse", method="jgs", jgs_chunks=2)
+    assert stc.stc_footprint_bytes(gen, jgs) == stc.stc_footprint_bytes(gen, stair) > 0
+    for m_big, mp in ((257, 512), (1000, 1024), (2048, 2048)):
+        gen.m = m_big
+        extra = stc.stc_footprint_bytes(gen, jgs) - stc.stc_footprint_bytes(gen, stair)
+        assert 8 * 3 * mp * 8 <= extra <= 8 * 3 * mp * 8 + 4096, m_big
+    gen.m = 256
+    for bad in (stc.make_options("fp64", format="sparse", method="jgs", jgs_chunks=0),
+                stc.make_options("fp64", format="sparse", method="jgs", jgs_chunks=4),
+                stc.make_options("fp64", format="sparse", method="jgs", jgs_chunks=2,
+                                 krylov_restart=4)):
+        assert stc.stc_footprint_bytes(gen, bad) == 0
