@@ -394,3 +394,23 @@ def test_any_pattern_jgs_argument_errors():
         with pytest.raises(stc.StcError) as e:
             _gen_solver(g, kw.pop("jgs_chunks"), **kw)
         assert e.value.status == stc.STC_EINVAL
+
+
+def test_full_size_jgs_sweep_matches_the_oracle():
+    """The symmetric chain of bandwidth 1135 at its full size (N = 91881, 45
+    levels of 2048, as the section 3 comparison builds it): one FP64 sweep of
+    block Gauss-Seidel (p = 1, the row-split apply) and of JGS over 12
+    chunks (unsplit), element by element against the oracle's sweep of the
+    whole chain (its block view is tridiagonal, about 4 GB of dense blocks)."""
+    g = synth.banded_random(91881, 1135, 1135, synth.config_seed(3), symmetric=True, m=2048)
+    sysg = _gen_system(g)
+    x = _gen_start(g, 12)
+    for p in (1, 12):
+        zr, dr = staircase.jgs_sweep(sysg, x, _chunks(g.L, p))
+        s = _gen_solver(g, p)
+        z, d = s.step(x)
+        err = np.abs(z - zr).sum()
+        _say(f"full-size jgs p={p}: |z - z_oracle|_1 = {err:.2e}, change {d:.6e} "
+             f"(oracle {dr:.6e})")
+        assert err <= 1e-13 and abs(d - dr) <= 1e-13
+        s.close()
