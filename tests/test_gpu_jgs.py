@@ -414,3 +414,23 @@ def test_full_size_jgs_sweep_matches_the_oracle():
              f"(oracle {dr:.6e})")
         assert err <= 1e-13 and abs(d - dr) <= 1e-13
         s.close()
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_large_blocks_profiled_sweeps(p):
+    """Profiled Algorithm 1 sweeps on the large blocks (a timed span from the
+    first step's gather to the last step's apply or combine): the time is
+    reported as phase A's, none for phase B, and the iterate after them is
+    the one plain sweeps give."""
+    from paper_2302_07551_amd import stc
+    g = LARGE[1][1]()
+    x = _gen_start(g, 14)
+    a, b = _gen_solver(g, p), _gen_solver(g, p)
+    a.load(x)
+    ms_a, ms_b, _ms_f, ms = stc.stc_profile_sweeps(a.h, 4)
+    assert ms_a > 0.0 and ms_b == 0.0 and ms >= ms_a
+    b.load(x)
+    b.sweeps(4)
+    assert np.array_equal(a.store(), b.store())
+    a.close()
+    b.close()
